@@ -1,0 +1,285 @@
+"""ctypes binding of the CPU FP64 oracle (oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: the oracle is loaded by the test-suite, by the smoke
+check and by the CPU-baseline leg of the benchmark.  The GPU library never
+imports or links it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (FP64, no fast-math, OpenMP for the LU)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-o", _LIB + ".tmp", _SRC]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P, I, D, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+        sig = {
+            "oracle_philox4x32_10": (None, [P, P, P]),
+            "oracle_gaussian_tv": (None, [I, I, U64, P]),
+            "oracle_wilson_apply": (None, [I, P, D, P, P]),
+            "oracle_wilson_dense": (None, [I, P, D, P]),
+            "oracle_wilson_csr_nnz": (I, [I, P]),
+            "oracle_wilson_csr": (None, [I, P, D, P, P, P]),
+            "oracle_dhat_dense": (None, [I, P, D, P]),
+            "oracle_dhat_apply": (None, [I, P, D, P, P, I]),
+            "oracle_eo_reduce": (None, [I, P, D, P, P, I]),
+            "oracle_eo_reconstruct": (None, [I, P, D, P, P, P, I]),
+            "oracle_kaczmarz_fine": (None, [I, P, D, P, P, I, I]),
+            "oracle_fine_colour": (I, [I, I]),
+            "oracle_coarse_colour": (I, [I, I, I, I]),
+            "oracle_coarse_ncolours": (I, [I, I]),
+            "oracle_setup": (P, [I, P, D, I, I, I, I, I, I, I, I, U64, P]),
+            "oracle_free": (None, [P]),
+            "oracle_n_levels": (I, [P]),
+            "oracle_level_info": (None, [P, I, P]),
+            "oracle_export_op": (None, [P, I, P, P, P]),
+            "oracle_export_P": (None, [P, I, P]),
+            "oracle_export_tv": (None, [P, P]),
+            "oracle_import_P": (None, [P, I, P]),
+            "oracle_level_op": (I, [P, I, I, P, P, I]),
+            "oracle_solve_reduced": (I, [P, P, P, D, I, I, P]),
+            "oracle_solve": (I, [P, P, P, D, I, I, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _c(a: np.ndarray, dtype=np.complex128) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- primitives
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def gaussian_tv(N, k, seed):
+    out = np.zeros((k, N * N), dtype=np.complex128)
+    lib().oracle_gaussian_tv(N, k, seed, _p(out))
+    return out
+
+
+def wilson_apply(U, m, psi):
+    U = _c(U); N = U.shape[-1]
+    x = _c(psi).reshape(-1)
+    y = np.zeros_like(x)
+    lib().oracle_wilson_apply(N, _p(U), m, _p(x), _p(y))
+    return y
+
+
+def wilson_dense(U, m):
+    U = _c(U); N = U.shape[-1]
+    n = 2 * N * N
+    out = np.zeros((n, n), dtype=np.complex128)
+    lib().oracle_wilson_dense(N, _p(U), m, _p(out))
+    return out
+
+
+def wilson_csr(U, m):
+    """(indptr, indices, data) of the full Wilson matrix D."""
+    U = _c(U); N = U.shape[-1]
+    n = 2 * N * N
+    nnz = lib().oracle_wilson_csr_nnz(N, _p(U))
+    ptr = np.zeros(n + 1, dtype=np.int32)
+    col = np.zeros(nnz, dtype=np.int32)
+    val = np.zeros(nnz, dtype=np.complex128)
+    lib().oracle_wilson_csr(N, _p(U), m, _p(ptr), _p(col), _p(val))
+    return ptr, col, val
+
+
+def dhat_dense(U, m):
+    U = _c(U); N = U.shape[-1]
+    n = N * N
+    out = np.zeros((n, n), dtype=np.complex128)
+    lib().oracle_dhat_dense(N, _p(U), m, _p(out))
+    return out
+
+
+def dhat_apply(U, m, x):
+    U = _c(U); N = U.shape[-1]
+    x = _c(x); nrhs = x.size // (N * N)
+    y = np.zeros_like(x)
+    lib().oracle_dhat_apply(N, _p(U), m, _p(x), _p(y), nrhs)
+    return y
+
+
+def eo_reduce(U, m, b):
+    U = _c(U); N = U.shape[-1]
+    b = _c(b); nrhs = b.size // (2 * N * N)
+    out = np.zeros(nrhs * N * N, dtype=np.complex128)
+    lib().oracle_eo_reduce(N, _p(U), m, _p(b), _p(out), nrhs)
+    return out.reshape((nrhs, N * N)) if nrhs > 1 else out
+
+
+def eo_reconstruct(U, m, b, xe):
+    U = _c(U); N = U.shape[-1]
+    b = _c(b); xe = _c(xe); nrhs = b.size // (2 * N * N)
+    out = np.zeros(nrhs * 2 * N * N, dtype=np.complex128)
+    lib().oracle_eo_reconstruct(N, _p(U), m, _p(b), _p(xe), _p(out), nrhs)
+    return out.reshape((nrhs, 2 * N * N)) if nrhs > 1 else out
+
+
+def kaczmarz_fine(U, m, x, b=None, sweeps=1):
+    U = _c(U); N = U.shape[-1]
+    x = _c(x).copy(); nrhs = x.size // (N * N)
+    bb = None if b is None else _c(b)
+    lib().oracle_kaczmarz_fine(N, _p(U), m, _p(x), None if bb is None else _p(bb), sweeps, nrhs)
+    return x
+
+
+def fine_colour(x, y):
+    return lib().oracle_fine_colour(x, y)
+
+
+def coarse_colour(ax, ay, ex, ey):
+    return lib().oracle_coarse_colour(ax, ay, ex, ey)
+
+
+def coarse_ncolours(ex, ey):
+    return lib().oracle_coarse_ncolours(ex, ey)
+
+
+# ---------------------------------------------------------------- hierarchy
+class Hierarchy:
+    """Oracle bootstrap-AMG hierarchy (setup, cycle, FGMRES)."""
+
+    def __init__(self, U, m, *, n_levels=0, max_coarse=2048, n_tv=8, setup_sweeps=20,
+                 setup_adapt=1, pre=4, post=4, cycle=0, seed=0, init_tv=None):
+        U = _c(U)
+        self.N = U.shape[-1]
+        self.U, self.m = U, float(m)
+        self._tv = None if init_tv is None else _c(init_tv)
+        h = lib().oracle_setup(self.N, _p(U), self.m, n_levels, max_coarse, n_tv, setup_sweeps,
+                               setup_adapt, pre, post, cycle, seed,
+                               None if self._tv is None else _p(self._tv))
+        if not h:
+            raise ValueError("oracle_setup rejected the parameters")
+        self.h = h
+        self.n_tv = n_tv
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().oracle_free(h)
+            self.h = None
+
+    @property
+    def n_levels(self):
+        return lib().oracle_n_levels(self.h)
+
+    def level_info(self, l):
+        info = np.zeros(6, dtype=np.int32)
+        lib().oracle_level_info(self.h, l, _p(info))
+        return dict(ex=int(info[0]), ey=int(info[1]), dps=int(info[2]), n=int(info[3]),
+                    nnz=int(info[4]), singular=bool(info[5]))
+
+    def operator(self, l):
+        """Level operator as a scipy CSR matrix."""
+        import scipy.sparse as sp
+        inf = self.level_info(l)
+        ptr = np.zeros(inf["n"] + 1, dtype=np.int32)
+        col = np.zeros(inf["nnz"], dtype=np.int32)
+        val = np.zeros(inf["nnz"], dtype=np.complex128)
+        lib().oracle_export_op(self.h, l, _p(ptr), _p(col), _p(val))
+        return sp.csr_matrix((val, col, ptr), shape=(inf["n"], inf["n"]))
+
+    def P_blocks(self, l):
+        inf, cinf = self.level_info(l), self.level_info(l + 1)
+        rows = 16 if l == 0 else 32
+        out = np.zeros((cinf["ex"] * cinf["ey"], 2, rows, 8), dtype=np.complex128)
+        lib().oracle_export_P(self.h, l, _p(out))
+        return out
+
+    def import_P(self, l, P):
+        P = _c(P)
+        lib().oracle_import_P(self.h, l, _p(P))
+
+    def test_vectors(self):
+        out = np.zeros((self.n_tv, self.N * self.N), dtype=np.complex128)
+        lib().oracle_export_tv(self.h, _p(out))
+        return out
+
+    def level_op(self, l, op, x, out=None, nrhs=1):
+        x = _c(x)
+        n = self.level_info(l)["n"]
+        if op == 2:
+            nout = self.level_info(l + 1)["n"]
+        elif op == 3:
+            nout = n
+        else:
+            nout = n
+        if out is None:
+            out = np.zeros(nrhs * nout, dtype=np.complex128)
+        else:
+            out = _c(out).copy()
+        st = lib().oracle_level_op(self.h, l, op, _p(x), _p(out), nrhs)
+        if st != 0:
+            raise RuntimeError(f"oracle_level_op status {st}")
+        return out
+
+    def apply(self, l, x, nrhs=1):
+        return self.level_op(l, 0, x, nrhs=nrhs)
+
+    def sweep(self, l, x, b, nrhs=1):
+        return self.level_op(l, 1, b, out=x, nrhs=nrhs)
+
+    def restrict(self, l, x, nrhs=1):
+        return self.level_op(l, 2, x, nrhs=nrhs)
+
+    def prolong_add(self, l, xc, y, nrhs=1):
+        return self.level_op(l, 3, xc, out=y, nrhs=nrhs)
+
+    def coarsest_solve(self, x, nrhs=1):
+        return self.level_op(self.n_levels - 1, 4, x, nrhs=nrhs)
+
+    def cycle(self, b, l=0, nrhs=1):
+        return self.level_op(l, 5, b, nrhs=nrhs)
+
+    def solve_reduced(self, bh, tol=1e-10, restart=32, max_iter=1000):
+        bh = _c(bh)
+        x = np.zeros_like(bh)
+        info = np.zeros(5)
+        st = lib().oracle_solve_reduced(self.h, _p(bh), _p(x), tol, restart, max_iter, _p(info))
+        return st, x, dict(iters=int(info[0]), restarts=int(info[1]), relres=float(info[2]),
+                           rho=float(info[4]))
+
+    def solve(self, b, tol=1e-10, restart=32, max_iter=1000):
+        b = _c(b)
+        x = np.zeros_like(b)
+        info = np.zeros(5)
+        st = lib().oracle_solve(self.h, _p(b), _p(x), tol, restart, max_iter, _p(info))
+        return st, x, dict(iters=int(info[0]), restarts=int(info[1]), relres=float(info[2]),
+                           relres_full=float(info[3]), rho=float(info[4]))

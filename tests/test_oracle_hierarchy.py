@@ -1,0 +1,222 @@
+"""Pins of the oracle's setup, cycle and outer Krylov solver.
+
+* P^H P = I and exact representation of the test vectors (Sec. 3.3: with k <= 8
+  test vectors per 16-dof block the least squares fit is exact);
+* Galerkin product P^H A P and gamma5 symmetry on every level (Sec. 3.5,
+  eq. gammaC / eq. bs and Theorem 1: Z_l = Gamma_5 D_l is Hermitian);
+* the coarse stencil keeps a fixed block sparsity (Sec. 3.2, Sec. 4);
+* the two-grid coarse correction is a projector with Galerkin orthogonality
+  (Sec. 1, E_G);
+* full solves against independent solutions: the free-field momentum-space
+  solve (FFT) and a dense LAPACK solve of D built from eq. (bst);
+* gauge covariance of the whole pipeline;
+* FGMRES failure handling.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import inputs
+import oracle
+from tests.test_oracle_operator import _paper_bst_dense
+
+
+@pytest.fixture(scope="module")
+def hier32():
+    N = 32
+    U = inputs.gauge_metropolis(N, 3.0, 50, 1)
+    h = oracle.Hierarchy(U, -0.1, n_levels=3, max_coarse=512, seed=7, setup_sweeps=10)
+    return U, h
+
+
+def _P_csr(h, l, P):
+    """Expand aggregate blocks [agg][s][row][k] to a sparse matrix (fine x coarse)."""
+    fi, ci = h.level_info(l), h.level_info(l + 1)
+    rows, cols, vals = [], [], []
+    if l == 0:
+        ax, ay = 4, 4
+    else:
+        ax, ay = 2, 2
+    for sy in range(fi["ey"]):
+        for sx in range(fi["ex"]):
+            site = sy * fi["ex"] + sx
+            a = (sy // ay) * ci["ex"] + sx // ax
+            loc = (sy % ay) * ax + sx % ax
+            for d in range(fi["dps"]):
+                s = d if l == 0 else d // 8
+                r = loc if l == 0 else 8 * loc + d % 8
+                for k in range(8):
+                    rows.append(site * fi["dps"] + d)
+                    cols.append(16 * a + 8 * s + k)
+                    vals.append(P[a, s, r, k])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(fi["n"], ci["n"]))
+
+
+def test_P_orthonormal_and_test_vectors_exact(hier32):
+    U, h = hier32
+    P = h.P_blocks(0)
+    for a in range(P.shape[0]):
+        for s in range(2):
+            Q = P[a, s]
+            assert np.abs(Q.conj().T @ Q - np.eye(8)).max() < 1e-13
+    Pm = _P_csr(h, 0, P)
+    V = h.test_vectors().T
+    assert np.abs(Pm @ (Pm.conj().T @ V) - V).max() < 1e-12 * np.abs(V).max()
+    # P_{a,s} spans the test vectors on each block in test-vector order (positive R_jj)
+    for a in range(0, P.shape[0], 7):
+        for s in range(2):
+            Q = P[a, s]
+            rows = Pm[:, 16 * a + 8 * s].nonzero()[0]
+            R = Q.conj().T @ V[rows]
+            assert np.abs(np.tril(R, -1)).max() < 1e-12
+            assert (np.diag(R).real > 0).all()
+
+
+def test_galerkin_and_gamma5_on_all_levels(hier32):
+    U, h = hier32
+    for l in range(h.n_levels - 1):
+        A = h.operator(l).toarray()
+        Pm = _P_csr(h, l, h.P_blocks(l)).toarray()
+        Ac = h.operator(l + 1).toarray()
+        assert np.abs(Pm.conj().T @ A @ Pm - Ac).max() < 1e-13 * np.abs(Ac).max()
+        n = Ac.shape[0]
+        g = np.tile(np.r_[np.ones(8), -np.ones(8)], n // 16)
+        Z = g[:, None] * Ac
+        assert np.abs(Z - Z.conj().T).max() < 1e-13 * np.abs(Z).max()
+
+
+def test_coarse_stencil_is_the_seven_block_set(hier32):
+    U, h = hier32
+    inf = h.level_info(1)
+    ex, ey = inf["ex"], inf["ey"]
+    A = h.operator(1).tocoo()
+    offs = set()
+    for r, c, v in zip(A.row, A.col, A.data):
+        if abs(v) == 0:
+            continue
+        a, b = r // 16, c // 16
+        dx = ((b % ex) - (a % ex) + 1) % ex - 1
+        dy = ((b // ex) - (a // ex) + 1) % ey - 1
+        offs.add((dx, dy))
+    assert offs == {(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1)}
+
+
+def test_two_grid_coarse_correction_is_galerkin_projection():
+    N = 16
+    U = inputs.gauge_random(N, 3)
+    h = oracle.Hierarchy(U, 0.2, n_levels=2, seed=4, setup_sweeps=5, pre=0, post=0)
+    A = h.operator(0).toarray()
+    Pm = _P_csr(h, 0, h.P_blocks(0)).toarray()
+    b = inputs.gaussian(N * N, 5)
+    z = h.cycle(b)
+    # z = P Ac^-1 P^H b, hence P^H (b - A z) = 0 and E = I - z-map is a projector
+    assert np.abs(Pm.conj().T @ (b - A @ z)).max() < 1e-11 * np.abs(b).max()
+    Ac = Pm.conj().T @ A @ Pm
+    E = np.eye(A.shape[0]) - Pm @ np.linalg.solve(Ac, Pm.conj().T @ A)
+    assert np.abs(E @ E - E).max() < 1e-10
+
+
+def test_coarsest_solve_matches_dense(hier32):
+    U, h = hier32
+    L = h.n_levels - 1
+    A = h.operator(L).toarray()
+    b = inputs.gaussian(A.shape[0], 9)
+    x = h.coarsest_solve(b)
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) < 1e-12
+
+
+def test_free_field_solve_matches_momentum_space():
+    """U = 1: D is diagonal in momentum space (closed form), solved by FFT."""
+    N, m = 32, 0.05
+    U = inputs.gauge_free(N)
+    h = oracle.Hierarchy(U, m, seed=1)
+    b = inputs.gaussian(2 * N * N, 2)
+    st, x, info = h.solve(b, tol=1e-10)
+    assert st == 0 and info["relres"] <= 1e-10
+    # momentum space: psi(z) = sum_p e^{ipz} psi(p); (H psi)(p) = sum_mu [cos p I - i sin p gamma_mu]
+    bp = np.fft.fft2(b.reshape(N, N, 2), axes=(0, 1))  # axes (y, x)
+    p = 2 * np.pi * np.fft.fftfreq(N)
+    py, px = np.meshgrid(p, p, indexing="ij")
+    g1 = np.array([[0, 1], [1, 0]], complex)
+    g2 = np.array([[0, 1j], [-1j, 0]], complex)
+    Dp = ((m + 2 - np.cos(px) - np.cos(py))[..., None, None] * np.eye(2)
+          + 1j * np.sin(px)[..., None, None] * g1 + 1j * np.sin(py)[..., None, None] * g2)
+    xp = np.linalg.solve(Dp, bp[..., None])[..., 0]
+    xref = np.fft.ifft2(xp, axes=(0, 1)).reshape(-1)
+    kappa = 1.0 / m * 4  # generous condition estimate of D at this mass
+    assert np.linalg.norm(x - xref) / np.linalg.norm(xref) < kappa * 1e-10
+
+
+def test_solve_matches_dense_solve_of_block_form():
+    N, m = 16, -0.15
+    U = inputs.gauge_metropolis(N, 3.0, 100, 2)
+    D = _paper_bst_dense(U, m)
+    b = inputs.gaussian(2 * N * N, 3)
+    xref = np.linalg.solve(D, b)
+    h = oracle.Hierarchy(U, m, seed=3)
+    st, x, info = h.solve(b, tol=1e-10)
+    assert st == 0 and info["relres"] <= 1e-10 and info["relres_full"] < 1e-9
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(x - xref) / np.linalg.norm(xref) < kappa * 1e-10
+
+
+def test_gauge_covariance_of_the_whole_pipeline():
+    """U_mu(z) -> g(z) U_mu(z) conj(g(z+mu)), b -> G b, test vectors -> G v give
+    x -> G x with identical iteration counts (QR commutes with a diagonal unitary)."""
+    N, m = 32, -0.1
+    U = inputs.gauge_metropolis(N, 6.0, 50, 4)
+    rng = np.random.default_rng(5)
+    g = np.exp(1j * rng.uniform(-np.pi, np.pi, size=(N, N)))  # g[y, x]
+    Ug = np.empty_like(U)
+    Ug[0] = g * U[0] * np.conj(np.roll(g, -1, axis=1))
+    Ug[1] = g * U[1] * np.conj(np.roll(g, -1, axis=0))
+    b = inputs.gaussian(2 * N * N, 6)
+    gb = (g.reshape(-1)[:, None] * b.reshape(-1, 2)).reshape(-1)
+    tv = oracle.gaussian_tv(N, 8, 11)
+    ev = np.array([g[y, 2 * xh + (y % 2)] for y in range(N) for xh in range(N // 2)])
+    gtv = (tv.reshape(8, -1, 2) * ev[None, :, None]).reshape(8, -1)
+    h1 = oracle.Hierarchy(U, m, init_tv=tv)
+    h2 = oracle.Hierarchy(Ug, m, init_tv=gtv)
+    s1, x1, i1 = h1.solve(b)
+    s2, x2, i2 = h2.solve(gb)
+    assert s1 == 0 and s2 == 0
+    assert i1["iters"] == i2["iters"]
+    gx1 = (g.reshape(-1)[:, None] * x1.reshape(-1, 2)).reshape(-1)
+    assert np.linalg.norm(gx1 - x2) / np.linalg.norm(x2) < 1e-9
+
+
+def test_fgmres_failure_handling():
+    N = 16
+    U = inputs.gauge_random(N, 1)
+    h = oracle.Hierarchy(U, 0.1, seed=1)
+    b = inputs.gaussian(2 * N * N, 1)
+    st, x, info = h.solve(b, tol=1e-14, max_iter=1)
+    assert st == 1 and info["iters"] == 1 and np.isfinite(x).all()
+    st, x, info = h.solve(np.zeros(2 * N * N, complex))
+    assert st == 0 and info["iters"] == 0 and not x.any()
+    bn = b.copy()
+    bn[3] = np.nan
+    st, x, info = h.solve(bn)
+    assert st == -1
+
+
+def test_test_vector_generator_statistics():
+    tv = oracle.gaussian_tv(32, 8, 123)
+    assert abs(tv.mean()) < 0.02
+    assert abs(np.mean(np.abs(tv) ** 2) - 1.0) < 0.02
+    assert abs(np.var(tv.real) - 0.5) < 0.02 and abs(np.var(tv.imag) - 0.5) < 0.02
+    # Box-Muller on two independent uniforms: |z|^2 is exponential with mean 1
+    assert abs(np.mean(np.abs(tv) ** 4) - 2.0) < 0.1
+
+
+def test_philox_known_answers():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    n = 0
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(t, 16) for t in line.split()]
+        assert oracle.philox4x32_10(w[0:4], w[4:6]).tolist() == w[6:10]
+        n += 1
+    assert n == 3
