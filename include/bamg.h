@@ -1,0 +1,178 @@
+/*
+ * bamg.h -- C ABI of libbamg: bootstrap algebraic multigrid (Brannick & Kahl,
+ * arXiv:1308.5992) for the odd-even reduced 2D Wilson-Dirac system on AMD
+ * MI355X (gfx950), as a preconditioner of a flexible GMRES in FP64.
+ *
+ * The problem (Sec. 1, eq. dirac; Sec. 2, eq. wilson): solve D psi = b on an
+ * N x N periodic lattice with U(1) links, two spin components per site and
+ * D = (m + 2) I - H, where H is the Wilson hopping term of eq. (wilson).
+ * The library solves the odd-even reduced system of Sec. 3.2 / Sec. 4,
+ * Dhat x_e = bhat with c = m + 2,
+ *     Dhat = I - c^-2 H_eo H_oe,  bhat = b_e / c + c^-2 H_eo b_o,
+ * and reconstructs x_o = b_o / c + c^-1 H_oe x_e.
+ *
+ * Layouts (all complex numbers are complex128, interleaved (re, im)):
+ *   gauge    U[mu][y][x]      mu = 0: link (x,y)->(x+1,y), mu = 1: (x,y)->(x,y+1)
+ *                             (the U_mu^z of Sec. 2, Fig. 1)
+ *   spinor   psi[y][x][s]     full lattice, 2 N^2 entries; batched: [nrhs][y][x][s]
+ *   reduced  v[y][xh][s]      even sites only (x + y even), x = 2 xh + (y mod 2),
+ *                             N^2 entries; batched: [nrhs][...]
+ *   level l  v[site][d]       coarse level l >= 1: site = ay * ex + ax on an
+ *                             ex x ey grid, d = 8 s + k (spin s, k < 8), 16 per site
+ *   P_l      [agg][s][row][k] interpolation from level l+1 to level l per aggregate
+ *                             and spin; row < 16 on level 0 (local even site
+ *                             4*(y mod 4) + (xh mod 4)), row < 32 on coarser levels
+ *                             (8 * local site + d mod 8, local site 2*(ay mod 2) + (ax mod 2))
+ *   D_l      [site][o][i][j]  coarse operator (l >= 1) as 16x16 blocks coupling a
+ *                             site to its neighbour at offset o in the order
+ *                             (0,0) (+1,0) (-1,0) (0,+1) (0,-1) (+1,+1) (-1,-1)
+ *
+ * Pointers: unless stated otherwise every array argument is DEVICE memory
+ * (for example torch.Tensor.data_ptr() of a CUDA/HIP tensor) that is valid on
+ * the stream given in bamg_params.stream.  Host pointers are marked _host.
+ * Ownership: the caller owns every array it passes; the library copies the
+ * gauge field at setup and keeps no caller pointer after a call returns.  The
+ * hierarchy is owned by the library until bamg_free.
+ * Errors: every int-returning call returns a bamg_status.  Negative values are
+ * failures (outputs unspecified); BAMG_NOT_CONVERGED leaves the best iterate.
+ * bamg_last_error() returns a thread-local text for the last failure.
+ * Threads and streams: one hierarchy must not be used from two threads at
+ * once; different hierarchies may run concurrently on different streams.
+ */
+#ifndef BAMG_H
+#define BAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bamg_hierarchy bamg_hierarchy;
+
+typedef enum {
+  BAMG_OK = 0,
+  BAMG_NOT_CONVERGED = 1,
+  BAMG_EINVAL = -1,
+  BAMG_ENOMEM = -2,
+  BAMG_EDEVICE = -3,
+  BAMG_ESINGULAR = -4,
+  BAMG_ENOTIMPL = -5
+} bamg_status;
+
+typedef enum { BAMG_CYCLE_V = 0, BAMG_CYCLE_W = 1 } bamg_cycle;
+
+typedef enum {
+  BAMG_FP64 = 0,        /* everything in FP64 */
+  BAMG_MIXED_FP16 = 1,  /* FP64 outer FGMRES + coarsest solve; FP32 cycle; coarse operators stored FP16 */
+  BAMG_MIXED_BF16 = 2,  /* as above with BF16 storage */
+  BAMG_MIXED_FP32 = 3   /* as above with FP32 storage */
+} bamg_precision;
+
+typedef struct {
+  int32_t N;            /* lattice extent, N % 8 == 0, N >= 16 */
+  int32_t n_levels;     /* 0: automatic (coarsen until the level dimension <= max_coarse) */
+  int32_t max_coarse;   /* dimension bound of the directly solved coarsest level (default 2048) */
+  int32_t n_tv;         /* test vectors k (Sec. 4: k_r = 8); must be 8 */
+  int32_t setup_sweeps; /* Kaczmarz sweeps on A_l v = 0 per level and setup pass (default 20) */
+  int32_t setup_adapt;  /* adaptive passes after the first setup pass (default 1) */
+  int32_t pre, post;    /* smoothing sweeps of the solve cycle (default 4, 4; Sec. 4) */
+  int32_t cycle;        /* bamg_cycle (default V) */
+  int32_t precision;    /* bamg_precision (default FP64) */
+  int32_t restart;      /* FGMRES restart length (default 32; Sec. 4) */
+  int32_t max_iter;     /* FGMRES iteration cap (default 1000) */
+  uint64_t seed;        /* Philox4x32-10 key of the random initial test vectors */
+  const double *init_tv_host; /* optional HOST [n_tv][N*N] complex reduced vectors; overrides seed */
+  void *stream;         /* hipStream_t for all work, or NULL for the null stream */
+} bamg_params;
+
+typedef struct {
+  int32_t iters;          /* FGMRES iterations (preconditioner applications) */
+  int32_t restarts;       /* restarts performed */
+  double relres_reduced;  /* ||bhat - Dhat x_e|| / ||bhat|| (true residual) */
+  double relres_full;     /* ||b - D x|| / ||b|| (0 when not computed) */
+  double rho_est;         /* relres_reduced^(1/iters) */
+  double t_solve_ms;      /* host wall time of the call */
+} bamg_solve_info;
+
+/* Fill p with the defaults listed above (N = 0: the caller must set it). */
+int bamg_default_params(bamg_params *p);
+
+/* Build the hierarchy for gauge field `gauge` (device, U[mu][y][x]) and mass m
+ * (Sec. 3.4 bootstrap setup, reading: relax k random test vectors with Kaczmarz
+ * on A_l v = 0, least-squares fit of P per aggregate and spin (Sec. 3.3),
+ * Galerkin coarse operators P^H A_l P (Sec. 3.5), direct coarsest solve,
+ * followed by `setup_adapt` adaptive passes of two cycles per test vector).
+ * Returns BAMG_EINVAL for bad parameters, BAMG_ESINGULAR if the coarsest
+ * operator is singular, BAMG_ENOMEM / BAMG_EDEVICE on allocation or HIP errors. */
+int bamg_setup(const void *gauge, double m, const bamg_params *p, bamg_hierarchy **out);
+
+/* Solve D x = b for one right-hand side (device b and x, full-lattice layout).
+ * tol is the relative residual of the reduced system (Sec. 4: ||r|| / ||bhat||).
+ * info may be NULL.  BAMG_EINVAL if b holds a non-finite value. */
+int bamg_solve(bamg_hierarchy *h, const void *b, void *x, double tol, bamg_solve_info *info);
+
+/* nrhs independent solves with one shared hierarchy: B and X are [nrhs][y][x][s].
+ * infos (host, may be NULL) receives nrhs records.  Each right-hand side
+ * converges on its own; results equal those of bamg_solve up to rounding. */
+int bamg_solve_batch(bamg_hierarchy *h, const void *B, void *X, int32_t nrhs, double tol,
+                     bamg_solve_info *infos);
+
+/* y = Dhat x on nrhs reduced vectors (Sec. 3.2, eq. wilsonSchur). */
+int bamg_apply_dhat(bamg_hierarchy *h, const void *x, void *y, int32_t nrhs);
+
+/* bhat = b_e / c + c^-2 H_eo b_o for nrhs full-lattice b (Sec. 3.2, step 1). */
+int bamg_eo_reduce(bamg_hierarchy *h, const void *b, void *bhat, int32_t nrhs);
+
+/* x (full lattice) from x_e: even sites copied, x_o = b_o / c + c^-1 H_oe x_e
+ * (Sec. 3.2, step 2). */
+int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *x, int32_t nrhs);
+
+/* Level operations on nrhs level-l vectors (test and benchmark hook):
+ *   op 0 BAMG_OP_APPLY:    out = A_l in
+ *   op 1 BAMG_OP_SWEEP:    out <- one multicolour Kaczmarz sweep on A_l out = in (in place on out)
+ *   op 2 BAMG_OP_RESTRICT: out (level l+1) = P_l^H in
+ *   op 3 BAMG_OP_PROLONG:  out (level l) += P_l in (level l+1)
+ *   op 4 BAMG_OP_COARSEST: out = A_L^-1 in  (l must be the coarsest level)
+ *   op 5 BAMG_OP_CYCLE:    out = one multigrid cycle from level l on A_l out = in, zero start
+ *   op 6 BAMG_OP_RESIDUAL: out = in - A_l out  (in: right-hand side; out: iterate, overwritten)
+ * Level 0 is the fine reduced system (A_0 = Dhat). */
+enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLONG = 3,
+       BAMG_OP_COARSEST = 4, BAMG_OP_CYCLE = 5, BAMG_OP_RESIDUAL = 6 };
+int bamg_level_op(bamg_hierarchy *h, int32_t level, int32_t op, const void *in, void *out, int32_t nrhs);
+
+/* Number of levels, or a negative status. */
+int bamg_n_levels(const bamg_hierarchy *h);
+
+/* info_host[0..4] = ex, ey, dofs per site, level dimension, colours of the smoother. */
+int bamg_level_info(const bamg_hierarchy *h, int32_t level, int32_t *info_host);
+
+/* Copy level l to host buffers (any may be NULL): P_host = P_l (l < L-1), Dl_host =
+ * D_l in blocks (l >= 1; the coarsest level too), tv_host = the level-0 test vectors
+ * [n_tv][N*N] after the last setup pass (l == 0 only). */
+int bamg_export_level(const bamg_hierarchy *h, int32_t l, void *P_host, void *Dl_host, void *tv_host);
+
+/* Replace P_l (host, aggregate blocks) and rebuild level l+1 by the Galerkin
+ * product (and its smoother data, or the coarsest inverse).  Dl_host must be
+ * NULL (reserved).  Levels below l+1 keep their old P and are rebuilt by
+ * importing them in order. */
+int bamg_import_level(bamg_hierarchy *h, int32_t l, const void *P_host, const void *Dl_host);
+
+/* Device bytes a hierarchy with parameters p (and one right-hand side) needs. */
+size_t bamg_footprint_bytes(const bamg_params *p);
+
+/* k test vectors from the Philox4x32-10 generator (as used by setup):
+ * out (device) [k][N*N] reduced vectors, entries (re, im) i.i.d. N(0, 1/2). */
+int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void *out, void *stream);
+
+/* Release the hierarchy (NULL is ignored). */
+void bamg_free(bamg_hierarchy *h);
+
+/* Text of the last error on this thread ("" if none). */
+const char *bamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BAMG_H */

@@ -1,0 +1,228 @@
+"""Python binding of libbamg (include/bamg.h): argument marshalling only.
+
+Every function keeps the name of the C entry point it calls.  Arrays are
+torch tensors on the GPU (complex128, contiguous); their data pointers are
+passed to the library together with torch's current HIP stream, so the work
+is ordered with the caller's torch work.  There is no fallback: if the HIP
+library is missing the import of this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbamg.so")
+
+BAMG_OK, BAMG_NOT_CONVERGED = 0, 1
+BAMG_EINVAL, BAMG_ENOMEM, BAMG_EDEVICE, BAMG_ESINGULAR, BAMG_ENOTIMPL = -1, -2, -3, -4, -5
+BAMG_CYCLE_V, BAMG_CYCLE_W = 0, 1
+BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
+OP_APPLY, OP_SWEEP, OP_RESTRICT, OP_PROLONG, OP_COARSEST, OP_CYCLE, OP_RESIDUAL = range(7)
+
+EXPORTED = [
+    "bamg_default_params", "bamg_setup", "bamg_solve", "bamg_solve_batch", "bamg_apply_dhat",
+    "bamg_eo_reduce", "bamg_eo_reconstruct", "bamg_level_op", "bamg_n_levels", "bamg_level_info",
+    "bamg_export_level", "bamg_import_level", "bamg_footprint_bytes", "bamg_gaussian_tv",
+    "bamg_free", "bamg_last_error",
+]
+
+
+class bamg_params(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
+        ("n_tv", ctypes.c_int32), ("setup_sweeps", ctypes.c_int32), ("setup_adapt", ctypes.c_int32),
+        ("pre", ctypes.c_int32), ("post", ctypes.c_int32), ("cycle", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("init_tv_host", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+    ]
+
+
+class bamg_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("relres_reduced", ctypes.c_double),
+        ("relres_full", ctypes.c_double), ("rho_est", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libbamg.so is not built ({LIB_PATH}); run python -m paper_1308_5992_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, D, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_size_t
+    PP = ctypes.POINTER(bamg_params)
+    PI = ctypes.POINTER(bamg_solve_info)
+    sig = {
+        "bamg_default_params": (I32, [PP]),
+        "bamg_setup": (I32, [P, D, PP, ctypes.POINTER(P)]),
+        "bamg_solve": (I32, [P, P, P, D, PI]),
+        "bamg_solve_batch": (I32, [P, P, P, I32, D, PI]),
+        "bamg_apply_dhat": (I32, [P, P, P, I32]),
+        "bamg_eo_reduce": (I32, [P, P, P, I32]),
+        "bamg_eo_reconstruct": (I32, [P, P, P, P, I32]),
+        "bamg_level_op": (I32, [P, I32, I32, P, P, I32]),
+        "bamg_n_levels": (I32, [P]),
+        "bamg_level_info": (I32, [P, I32, P]),
+        "bamg_export_level": (I32, [P, I32, P, P, P]),
+        "bamg_import_level": (I32, [P, I32, P, P]),
+        "bamg_footprint_bytes": (SZ, [PP]),
+        "bamg_gaussian_tv": (I32, [I32, I32, U64, P, P]),
+        "bamg_free": (None, [P]),
+        "bamg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+class BamgError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: status {status}: {bamg_last_error()}")
+        self.status = status
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError("expected a contiguous complex128 GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(st, where, allow_nc=False):
+    if st < 0 or (st == BAMG_NOT_CONVERGED and not allow_nc):
+        raise BamgError(st, where)
+    return st
+
+
+def bamg_last_error() -> str:
+    return lib.bamg_last_error().decode()
+
+
+def bamg_default_params(**kw) -> bamg_params:
+    p = bamg_params()
+    lib.bamg_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "init_tv_host":
+            continue
+        setattr(p, k, v)
+    return p
+
+
+def bamg_footprint_bytes(p: bamg_params) -> int:
+    return int(lib.bamg_footprint_bytes(ctypes.byref(p)))
+
+
+class Hierarchy(ctypes.c_void_p):
+    """Opaque hierarchy handle (freed by bamg_free or when collected)."""
+
+    def __del__(self):
+        if self.value:
+            lib.bamg_free(self)
+            self.value = None
+
+
+def bamg_setup(gauge, m: float, p: bamg_params, init_tv=None) -> Hierarchy:
+    """gauge: complex128 GPU tensor U[mu][y][x]; init_tv: optional host numpy [k][N*N]."""
+    if p.stream is None:
+        p.stream = _stream().value
+    keep = None
+    if init_tv is not None:
+        keep = np.ascontiguousarray(init_tv, dtype=np.complex128)
+        p.init_tv_host = keep.ctypes.data
+    else:
+        p.init_tv_host = None
+    h = Hierarchy()
+    st = lib.bamg_setup(_ptr(gauge), float(m), ctypes.byref(p), ctypes.byref(h))
+    p.init_tv_host = None
+    _check(st, "bamg_setup")
+    return h
+
+
+def bamg_solve(h, b, x, tol: float):
+    info = bamg_solve_info()
+    st = lib.bamg_solve(h, _ptr(b), _ptr(x), float(tol), ctypes.byref(info))
+    _check(st, "bamg_solve", allow_nc=True)
+    return st, info.as_dict()
+
+
+def bamg_solve_batch(h, B, X, nrhs: int, tol: float):
+    infos = (bamg_solve_info * nrhs)()
+    st = lib.bamg_solve_batch(h, _ptr(B), _ptr(X), int(nrhs), float(tol), infos)
+    _check(st, "bamg_solve_batch", allow_nc=True)
+    return st, [i.as_dict() for i in infos]
+
+
+def bamg_apply_dhat(h, x, y, nrhs: int = 1):
+    _check(lib.bamg_apply_dhat(h, _ptr(x), _ptr(y), int(nrhs)), "bamg_apply_dhat")
+
+
+def bamg_eo_reduce(h, b, bhat, nrhs: int = 1):
+    _check(lib.bamg_eo_reduce(h, _ptr(b), _ptr(bhat), int(nrhs)), "bamg_eo_reduce")
+
+
+def bamg_eo_reconstruct(h, b, xe, x, nrhs: int = 1):
+    _check(lib.bamg_eo_reconstruct(h, _ptr(b), _ptr(xe), _ptr(x), int(nrhs)), "bamg_eo_reconstruct")
+
+
+def bamg_level_op(h, level: int, op: int, inp, out, nrhs: int = 1):
+    _check(lib.bamg_level_op(h, int(level), int(op), _ptr(inp), _ptr(out), int(nrhs)), "bamg_level_op")
+
+
+def bamg_n_levels(h) -> int:
+    return _check(lib.bamg_n_levels(h), "bamg_n_levels")
+
+
+def bamg_level_info(h, level: int) -> dict:
+    info = np.zeros(5, dtype=np.int32)
+    _check(lib.bamg_level_info(h, int(level), info.ctypes.data), "bamg_level_info")
+    return dict(ex=int(info[0]), ey=int(info[1]), dps=int(info[2]), n=int(info[3]), colours=int(info[4]))
+
+
+def bamg_export_level(h, level: int, P=True, D=True, tv=False, n_tv=8):
+    """Host copies of P_l [agg][2][rows][8], D_l [site][7][16][16] and the level-0 test vectors."""
+    nl = bamg_n_levels(h)
+    inf = bamg_level_info(h, level)
+    Pa = Da = Ta = None
+    if P and level < nl - 1:
+        cinf = bamg_level_info(h, level + 1)
+        rows = 16 if level == 0 else 32
+        Pa = np.zeros((cinf["ex"] * cinf["ey"], 2, rows, 8), dtype=np.complex128)
+    if D and level >= 1:
+        Da = np.zeros((inf["ex"] * inf["ey"], 7, 16, 16), dtype=np.complex128)
+    if tv and level == 0:
+        Ta = np.zeros((n_tv, inf["n"]), dtype=np.complex128)
+    ptr = lambda a: None if a is None else a.ctypes.data
+    _check(lib.bamg_export_level(h, int(level), ptr(Pa), ptr(Da), ptr(Ta)), "bamg_export_level")
+    return Pa, Da, Ta
+
+
+def bamg_import_level(h, level: int, P):
+    P = np.ascontiguousarray(P, dtype=np.complex128)
+    _check(lib.bamg_import_level(h, int(level), P.ctypes.data, None), "bamg_import_level")
+
+
+def bamg_gaussian_tv(N: int, k: int, seed: int, out):
+    _check(lib.bamg_gaussian_tv(int(N), int(k), int(seed), _ptr(out), _stream()), "bamg_gaussian_tv")
+
+
+def bamg_free(h):
+    if h is not None and h.value:
+        lib.bamg_free(h)
+        h.value = None

@@ -1,0 +1,749 @@
+// libbamg host side: the C ABI of include/bamg.h, the hierarchy, the
+// bootstrap setup, the multigrid cycle and the outer flexible GMRES.
+// Every arithmetic step on vectors and operators runs in the HIP kernels of
+// fine.hip, coarse.hip, dense.hip and blas.hip; the host orders the launches
+// on the hierarchy's stream and performs the O(restart^2) Givens / Hessenberg
+// algebra of the Krylov method.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bamg.h"
+#include "bamg_internal.h"
+
+using namespace bamg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw HipFail(std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+struct HipFail {
+  std::string msg;
+  explicit HipFail(std::string m) : msg(std::move(m)) {}
+};
+struct BadArg {
+  std::string msg;
+  explicit BadArg(std::string m) : msg(std::move(m)) {}
+};
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw HipFail(std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+template <typename T>
+T* dalloc(size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) throw HipFail(std::string("hipMalloc: ") + hipGetErrorString(e));
+  return (T*)p;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int floor_mod(int a, int n) { return ((a % n) + n) % n; }
+
+// ---- multicolour orderings (Sec. 3.1 leaves the colouring open) -------------
+// fine even site (x, y): 4 * (((x+y)/2) mod 4) + (((x-y)/2) mod 4); 16 colours
+int fine_colour_of(int x, int y) { return 4 * floor_mod((x + y) / 2, 4) + floor_mod((x - y) / 2, 4); }
+// coarse site (ax, ay): 8 colours (ax - 3 ay) mod 8 if both extents are
+// multiples of 8, else 16 colours 4 (ay mod 4) + (ax mod 4) if multiples of 4,
+// else one site per colour
+int coarse_ncol(int ex, int ey) {
+  if (ex % 8 == 0 && ey % 8 == 0) return 8;
+  if (ex % 4 == 0 && ey % 4 == 0) return 16;
+  return ex * ey;
+}
+int coarse_colour_of(int ax, int ay, int ex, int ey) {
+  if (ex % 8 == 0 && ey % 8 == 0) return floor_mod(ax - 3 * ay, 8);
+  if (ex % 4 == 0 && ey % 4 == 0) return 4 * (ay % 4) + (ax % 4);
+  return ay * ex + ax;
+}
+
+}  // namespace
+
+struct Level {
+  int ex = 0, ey = 0, dps = 0;
+  size_t n = 0;                 // dofs
+  zd* D = nullptr;              // coarse block stencil (levels >= 1)
+  zd* Kinv = nullptr;           // smoother data (non-coarsest coarse levels)
+  zd* Ainv = nullptr;           // inverse of the coarsest operator
+  std::vector<int> col_off;     // colour c: sites [col_off[c], col_off[c+1]) of col_sites
+  int* col_sites = nullptr;
+  zd* P = nullptr;              // interpolation from level l+1 (non-coarsest levels)
+  int prow = 0;                 // rows of P_{a,s}
+  zd *x = nullptr, *b = nullptr, *r = nullptr;  // work vectors, cap right-hand sides
+  zd* tv = nullptr;             // test vectors on this level [k][n]
+  Coarse coarse() const {
+    Coarse c;
+    c.ex = ex; c.ey = ey; c.D = D; c.Kinv = Kinv;
+    return c;
+  }
+};
+
+struct bamg_hierarchy {
+  bamg_params p{};
+  double m = 0;
+  hipStream_t s = nullptr;
+  Fine f;
+  zd *Ue = nullptr, *Uo = nullptr;
+  std::vector<Level> lv;
+  int cap = 0;  // right-hand sides the work vectors hold
+  // coarsest inversion scratch
+  zd* gjcol = nullptr;
+  int* gjperm = nullptr;
+  int* dflag = nullptr;   // device flag
+  int* hflag = nullptr;   // pinned host mirror
+  // Krylov workspace
+  int kdim = 0;
+  zd *V = nullptr, *Z = nullptr, *w = nullptr, *bh = nullptr, *xe = nullptr, *rr = nullptr;
+  zd *partial = nullptr, *hdev = nullptr;
+  zd* hhost = nullptr;  // pinned
+  zd* tvsave = nullptr; // level-0 test vectors after the last setup pass
+
+  ~bamg_hierarchy() {
+    for (auto& L : lv) {
+      dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.col_sites); dfree(L.P);
+      dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
+    }
+    dfree(Ue); dfree(Uo); dfree(gjcol); dfree(gjperm); dfree(dflag);
+    if (hflag) (void)hipHostFree(hflag);
+    dfree(V); dfree(Z); dfree(w); dfree(bh); dfree(xe); dfree(rr); dfree(partial); dfree(hdev);
+    if (hhost) (void)hipHostFree(hhost);
+    dfree(tvsave);
+  }
+
+  int L() const { return (int)lv.size(); }
+  bool coarsest(int l) const { return l == L() - 1; }
+
+  void ensure_cap(int nrhs) {
+    if (nrhs <= cap) return;
+    for (auto& Lv : lv) {
+      dfree(Lv.x); dfree(Lv.b); dfree(Lv.r);
+      Lv.x = dalloc<zd>(Lv.n * nrhs);
+      Lv.b = dalloc<zd>(Lv.n * nrhs);
+      Lv.r = dalloc<zd>(Lv.n * nrhs);
+    }
+    cap = nrhs;
+  }
+
+  // ---------------------------------------------------------------- level ops
+  void apply(int l, const zd* x, zd* y, const zd* b, int nrhs) {
+    if (l == 0) launch_dhat(f, x, y, b, nrhs, s);
+    else launch_coarse_apply(lv[l].coarse(), x, y, b, nrhs, s);
+    check_launch();
+  }
+  void sweep(int l, zd* x, const zd* b, int nrhs) {
+    Level& Lv = lv[l];
+    const int nc = (int)Lv.col_off.size() - 1;
+    for (int c = 0; c < nc; ++c) {
+      const int lo = Lv.col_off[c], cnt = Lv.col_off[c + 1] - lo;
+      if (cnt == 0) continue;
+      if (l == 0) launch_kaczmarz_fine(f, Lv.col_sites + lo, cnt, x, b, nrhs, s);
+      else launch_kaczmarz_coarse(Lv.coarse(), Lv.col_sites + lo, cnt, x, b, nrhs, s);
+    }
+    check_launch();
+  }
+  void restrict_(int l, const zd* r, zd* rc, int nrhs) {
+    if (l == 0) launch_restrict_fine(f, lv[0].P, r, rc, nrhs, s);
+    else launch_restrict_coarse(lv[l].coarse(), lv[l].P, r, rc, nrhs, s);
+    check_launch();
+  }
+  void prolong(int l, const zd* xc, zd* x, int nrhs) {
+    if (l == 0) launch_prolong_fine(f, lv[0].P, xc, x, nrhs, s);
+    else launch_prolong_coarse(lv[l].coarse(), lv[l].P, xc, x, nrhs, s);
+    check_launch();
+  }
+  void coarsest_solve(const zd* b, zd* x, int nrhs) {
+    Level& Lv = lv.back();
+    launch_dense_mv(Lv.Ainv, (int)Lv.n, b, x, nrhs, s);
+    check_launch();
+  }
+
+  // multigrid cycle on level l for A_l x = b, x holds the initial guess
+  // (pre-smoothing, residual, restriction, coarse correction, prolongation,
+  // post-smoothing; Sec. 1 two-grid scheme applied recursively, Sec. 4)
+  void cycle(int l, const zd* b, zd* x, int nrhs) {
+    if (coarsest(l)) {
+      coarsest_solve(b, x, nrhs);
+      return;
+    }
+    Level& Lv = lv[l];
+    Level& C = lv[l + 1];
+    for (int i = 0; i < p.pre; ++i) sweep(l, x, b, nrhs);
+    apply(l, x, Lv.r, b, nrhs);  // r = b - A x
+    restrict_(l, Lv.r, C.b, nrhs);
+    launch_fill_zero(C.x, C.n * nrhs, s);
+    const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
+    for (int g = 0; g < gamma; ++g) {
+      cycle(l + 1, C.b, C.x, nrhs);
+      if (coarsest(l + 1)) break;
+    }
+    prolong(l, C.x, x, nrhs);
+    for (int i = 0; i < p.post; ++i) sweep(l, x, b, nrhs);
+  }
+
+  // ---------------------------------------------------------------- setup
+  void build_colours(int l) {
+    Level& Lv = lv[l];
+    std::vector<std::vector<int>> bins;
+    if (l == 0) {
+      bins.resize(16);
+      const int N = f.N, NH = f.NH;
+      for (int y = 0; y < N; ++y)
+        for (int xh = 0; xh < NH; ++xh) bins[fine_colour_of(2 * xh + (y & 1), y)].push_back(y * NH + xh);
+    } else {
+      bins.resize(coarse_ncol(Lv.ex, Lv.ey));
+      for (int ay = 0; ay < Lv.ey; ++ay)
+        for (int ax = 0; ax < Lv.ex; ++ax) bins[coarse_colour_of(ax, ay, Lv.ex, Lv.ey)].push_back(ay * Lv.ex + ax);
+    }
+    std::vector<int> flat;
+    Lv.col_off.assign(1, 0);
+    for (auto& b : bins) {
+      flat.insert(flat.end(), b.begin(), b.end());
+      Lv.col_off.push_back((int)flat.size());
+    }
+    Lv.col_sites = dalloc<int>(flat.size());
+    HIPCHK(hipMemcpyAsync(Lv.col_sites, flat.data(), flat.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // D_{l+1} from P_l, then its smoother data or (coarsest) its inverse
+  void build_next(int l) {
+    Level& C = lv[l + 1];
+    if (l == 0) launch_galerkin_fine(f, lv[0].P, C.D, s);
+    else launch_galerkin_coarse(lv[l].coarse(), lv[l].P, C.D, s);
+    check_launch();
+    if (!coarsest(l + 1)) {
+      launch_kaczmarz_prep(C.coarse(), C.Kinv, s);
+      check_launch();
+    } else {
+      invert_coarsest();
+    }
+  }
+
+  void invert_coarsest() {
+    Level& C = lv.back();
+    const int n = (int)C.n;
+    launch_densify(C.coarse(), C.Ainv, s);
+    HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), s));
+    for (int k = 0; k < n; ++k) launch_gj_step(C.Ainv, n, k, gjcol, gjperm, dflag, s);
+    launch_gj_unpermute(C.Ainv, nullptr, n, gjperm, s);
+    check_launch();
+    HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (*hflag) throw BadArg("singular coarsest operator");
+  }
+
+  void fit(int l, const zd* V) {
+    if (l == 0) launch_fit_fine(f, V, p.n_tv, lv[0].P, s);
+    else launch_fit_coarse(lv[l].coarse(), V, p.n_tv, lv[l].P, s);
+    check_launch();
+  }
+
+  // relax -> normalise -> fit -> Galerkin -> restrict, level by level, from
+  // the level-0 test vectors in lv[0].tv
+  void setup_pass() {
+    const int k = p.n_tv;
+    for (int l = 0; l + 1 < L(); ++l) {
+      Level& Lv = lv[l];
+      for (int i = 0; i < p.setup_sweeps; ++i) sweep(l, Lv.tv, nullptr, k);
+      launch_norms(Lv.tv, Lv.n, k, Lv.n, partial, hdev, s);
+      launch_normalize(Lv.tv, Lv.n, k, Lv.n, hdev, s);
+      check_launch();
+      if (l == 0) launch_copy(Lv.tv, tvsave, Lv.n * k, s);
+      fit(l, Lv.tv);
+      build_next(l);
+      restrict_(l, Lv.tv, lv[l + 1].tv, k);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  }
+};
+
+namespace {
+
+struct Shape {
+  std::vector<std::pair<int, int>> ext;
+};
+
+bool level_shapes(const bamg_params* p, Shape& sh, std::string& why) {
+  const int N = p->N;
+  if (N < 16 || N % 8 != 0) { why = "N must be a multiple of 8 and >= 16"; return false; }
+  sh.ext.clear();
+  sh.ext.push_back({N / 2, N});
+  int ex = N / 8, ey = N / 4;
+  sh.ext.push_back({ex, ey});
+  while (true) {
+    const int L = (int)sh.ext.size();
+    if (p->n_levels > 0 && L >= p->n_levels) break;
+    if (p->n_levels <= 0 && ex * ey * 16 <= p->max_coarse) break;
+    if (ex % 2 || ey % 2 || ex < 4 || ey < 4) break;
+    ex /= 2;
+    ey /= 2;
+    sh.ext.push_back({ex, ey});
+  }
+  if (p->n_levels > 0 && (int)sh.ext.size() != p->n_levels) { why = "n_levels not reachable for this N"; return false; }
+  const size_t nL = (size_t)sh.ext.back().first * sh.ext.back().second * 16;
+  if (nL > 8192) { why = "coarsest level dimension exceeds 8192 (dense inverse); raise n_levels"; return false; }
+  return true;
+}
+
+bool valid_params(const bamg_params* p, std::string& why) {
+  if (!p) { why = "params is NULL"; return false; }
+  if (p->n_tv != 8) { why = "n_tv must be 8"; return false; }
+  if (p->setup_sweeps < 0 || p->setup_adapt < 0 || p->pre < 0 || p->post < 0) { why = "negative count"; return false; }
+  if (p->cycle != BAMG_CYCLE_V && p->cycle != BAMG_CYCLE_W) { why = "unknown cycle"; return false; }
+  if (p->precision != BAMG_FP64) { why = "precision not available"; return false; }
+  if (p->restart < 1 || p->restart > 60) { why = "restart must be in [1, 60]"; return false; }
+  if (p->max_iter < 0) { why = "max_iter < 0"; return false; }
+  if (p->max_coarse < 16) { why = "max_coarse < 16"; return false; }
+  return true;
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+const char* bamg_last_error(void) { return g_err.c_str(); }
+
+int bamg_default_params(bamg_params* p) {
+  if (!p) return fail(BAMG_EINVAL, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->N = 0;
+  p->n_levels = 0;
+  p->max_coarse = 2048;
+  p->n_tv = 8;
+  p->setup_sweeps = 20;
+  p->setup_adapt = 1;
+  p->pre = 4;
+  p->post = 4;
+  p->cycle = BAMG_CYCLE_V;
+  p->precision = BAMG_FP64;
+  p->restart = 32;
+  p->max_iter = 1000;
+  p->seed = 0;
+  p->init_tv_host = nullptr;
+  p->stream = nullptr;
+  return BAMG_OK;
+}
+
+size_t bamg_footprint_bytes(const bamg_params* p) {
+  std::string why;
+  Shape sh;
+  if (!valid_params(p, why) || !level_shapes(p, sh, why)) return 0;
+  const size_t N = p->N, k = p->n_tv, z = sizeof(zd);
+  size_t bytes = 2 * N * N * z;  // links
+  const int L = (int)sh.ext.size();
+  for (int l = 0; l < L; ++l) {
+    const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
+    const size_t n = ns * (l == 0 ? 2 : 16);
+    bytes += (3 + k) * n * z;  // work vectors + test vectors
+    if (l >= 1) bytes += ns * NOFF * 256 * z;
+    if (l >= 1 && l < L - 1) bytes += ns * 256 * z;
+    if (l < L - 1) bytes += n * 8 * z;  // P
+    if (l == L - 1) bytes += n * n * z;
+  }
+  const size_t n0 = N * N, kd = p->restart;
+  bytes += (2 * kd + 5) * n0 * z + n0 * k * z;
+  return bytes;
+}
+
+int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy** out) {
+  if (!out) return fail(BAMG_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  Shape sh;
+  if (!gauge) return fail(BAMG_EINVAL, "gauge is NULL");
+  if (!valid_params(p, why) || !level_shapes(p, sh, why)) return fail(BAMG_EINVAL, why);
+  if (!std::isfinite(m) || m + 2.0 == 0.0) return fail(BAMG_EINVAL, "mass gives c = m + 2 = 0 or non-finite");
+  bamg_hierarchy* h = new bamg_hierarchy();
+  try {
+    h->p = *p;
+    h->p.init_tv_host = nullptr;
+    h->m = m;
+    h->s = (hipStream_t)p->stream;
+    const int N = p->N;
+    h->f.N = N;
+    h->f.NH = N / 2;
+    h->f.c = m + 2.0;
+    h->f.kappa = 1.0 / h->f.c;
+    h->f.kappa2 = h->f.kappa * h->f.kappa;
+    h->Ue = dalloc<zd>((size_t)N * N);
+    h->Uo = dalloc<zd>((size_t)N * N);
+    h->f.Ue = h->Ue;
+    h->f.Uo = h->Uo;
+    launch_gauge_pack((const zd*)gauge, h->Ue, h->Uo, N, h->s);
+    check_launch();
+    const int L = (int)sh.ext.size(), k = p->n_tv;
+    h->lv.resize(L);
+    for (int l = 0; l < L; ++l) {
+      Level& Lv = h->lv[l];
+      Lv.ex = sh.ext[l].first;
+      Lv.ey = sh.ext[l].second;
+      Lv.dps = (l == 0) ? 2 : 16;
+      Lv.n = (size_t)Lv.ex * Lv.ey * Lv.dps;
+      Lv.tv = dalloc<zd>(Lv.n * k);
+      if (l >= 1) Lv.D = dalloc<zd>((size_t)Lv.ex * Lv.ey * NOFF * 256);
+      if (l < L - 1) {
+        Lv.prow = (l == 0) ? 16 : 32;
+        Lv.P = dalloc<zd>(Lv.n * 8);
+        h->build_colours(l);
+        if (l >= 1) Lv.Kinv = dalloc<zd>((size_t)Lv.ex * Lv.ey * 256);
+      } else {
+        Lv.Ainv = dalloc<zd>(Lv.n * Lv.n);
+      }
+    }
+    h->ensure_cap(k);
+    const size_t n0 = h->lv[0].n;
+    h->gjcol = dalloc<zd>(h->lv.back().n);
+    h->gjperm = dalloc<int>(h->lv.back().n);
+    h->dflag = dalloc<int>(1);
+    HIPCHK(hipHostMalloc((void**)&h->hflag, sizeof(int)));
+    h->kdim = p->restart;
+    h->V = dalloc<zd>(n0 * (h->kdim + 1));
+    h->Z = dalloc<zd>(n0 * h->kdim);
+    h->w = dalloc<zd>(n0);
+    h->bh = dalloc<zd>(n0);
+    h->xe = dalloc<zd>(n0);
+    h->rr = dalloc<zd>(n0);
+    h->partial = dalloc<zd>((size_t)blas_nblocks(n0) * 64);
+    h->hdev = dalloc<zd>(256);
+    HIPCHK(hipHostMalloc((void**)&h->hhost, 256 * sizeof(zd)));
+    h->tvsave = dalloc<zd>(n0 * k);
+    // initial test vectors (Sec. 4: random, normal, mean 0, variance 1)
+    if (p->init_tv_host) {
+      HIPCHK(hipMemcpyAsync(h->lv[0].tv, p->init_tv_host, n0 * k * sizeof(zd), hipMemcpyHostToDevice, h->s));
+    } else {
+      launch_philox_tv((int)n0, k, p->seed, h->lv[0].tv, h->s);
+      check_launch();
+    }
+    h->setup_pass();
+    // adaptive passes: two cycles of the current hierarchy on Dhat v = 0 for
+    // every saved level-0 test vector, then relax-fit-coarsen again
+    for (int a = 0; a < p->setup_adapt; ++a) {
+      Level& L0 = h->lv[0];
+      launch_copy(h->tvsave, L0.tv, n0 * k, h->s);
+      launch_fill_zero(L0.b, n0 * k, h->s);
+      for (int c = 0; c < 2; ++c) h->cycle(0, L0.b, L0.tv, k);
+      launch_norms(L0.tv, n0, k, n0, h->partial, h->hdev, h->s);
+      launch_normalize(L0.tv, n0, k, n0, h->hdev, h->s);
+      check_launch();
+      h->setup_pass();
+    }
+    HIPCHK(hipStreamSynchronize(h->s));
+  } catch (const HipFail& e) {
+    delete h;
+    return fail(BAMG_EDEVICE, e.msg);
+  } catch (const BadArg& e) {
+    delete h;
+    return fail(BAMG_ESINGULAR, e.msg);
+  }
+  *out = h;
+  return BAMG_OK;
+}
+
+void bamg_free(bamg_hierarchy* h) { delete h; }
+
+int bamg_n_levels(const bamg_hierarchy* h) {
+  if (!h) return fail(BAMG_EINVAL, "hierarchy is NULL");
+  return h->L();
+}
+
+int bamg_level_info(const bamg_hierarchy* h, int32_t l, int32_t* info) {
+  if (!h || !info || l < 0 || l >= h->L()) return fail(BAMG_EINVAL, "bad level");
+  const Level& Lv = h->lv[l];
+  info[0] = Lv.ex;
+  info[1] = Lv.ey;
+  info[2] = Lv.dps;
+  info[3] = (int32_t)Lv.n;
+  info[4] = Lv.col_off.empty() ? 0 : (int32_t)Lv.col_off.size() - 1;
+  return BAMG_OK;
+}
+
+int bamg_apply_dhat(bamg_hierarchy* h, const void* x, void* y, int32_t nrhs) {
+  if (!h || !x || !y || nrhs < 1) return fail(BAMG_EINVAL, "bad arguments");
+  if (x == y) return fail(BAMG_EINVAL, "x and y must not alias");
+  try {
+    h->apply(0, (const zd*)x, (zd*)y, nullptr, nrhs);
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  }
+  return BAMG_OK;
+}
+
+int bamg_eo_reduce(bamg_hierarchy* h, const void* b, void* bhat, int32_t nrhs) {
+  if (!h || !b || !bhat || nrhs < 1) return fail(BAMG_EINVAL, "bad arguments");
+  launch_eo_reduce(h->f, (const zd*)b, (zd*)bhat, nrhs, h->s);
+  if (hipGetLastError() != hipSuccess) return fail(BAMG_EDEVICE, "launch failed");
+  return BAMG_OK;
+}
+
+int bamg_eo_reconstruct(bamg_hierarchy* h, const void* b, const void* xe, void* x, int32_t nrhs) {
+  if (!h || !b || !xe || !x || nrhs < 1) return fail(BAMG_EINVAL, "bad arguments");
+  launch_eo_reconstruct(h->f, (const zd*)b, (const zd*)xe, (zd*)x, nrhs, h->s);
+  if (hipGetLastError() != hipSuccess) return fail(BAMG_EDEVICE, "launch failed");
+  return BAMG_OK;
+}
+
+int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void* out, int32_t nrhs) {
+  if (!h || !in || !out || nrhs < 1 || l < 0 || l >= h->L()) return fail(BAMG_EINVAL, "bad arguments");
+  try {
+    const zd* xi = (const zd*)in;
+    zd* xo = (zd*)out;
+    switch (op) {
+      case BAMG_OP_APPLY:
+        if (in == out) return fail(BAMG_EINVAL, "in and out must not alias");
+        h->apply(l, xi, xo, nullptr, nrhs);
+        break;
+      case BAMG_OP_SWEEP:
+        if (h->coarsest(l)) return fail(BAMG_EINVAL, "no smoother on the coarsest level");
+        h->sweep(l, xo, xi, nrhs);
+        break;
+      case BAMG_OP_RESTRICT:
+        if (h->coarsest(l)) return fail(BAMG_EINVAL, "no restriction from the coarsest level");
+        h->restrict_(l, xi, xo, nrhs);
+        break;
+      case BAMG_OP_PROLONG:
+        if (h->coarsest(l)) return fail(BAMG_EINVAL, "no prolongation to the coarsest level");
+        h->prolong(l, xi, xo, nrhs);
+        break;
+      case BAMG_OP_COARSEST:
+        if (!h->coarsest(l)) return fail(BAMG_EINVAL, "level is not the coarsest");
+        h->coarsest_solve(xi, xo, nrhs);
+        break;
+      case BAMG_OP_CYCLE:
+        h->ensure_cap(nrhs);
+        launch_fill_zero(xo, h->lv[l].n * nrhs, h->s);
+        h->cycle(l, xi, xo, nrhs);
+        break;
+      case BAMG_OP_RESIDUAL: {
+        h->ensure_cap(nrhs);
+        Level& Lv = h->lv[l];
+        h->apply(l, xo, Lv.r, xi, nrhs);
+        launch_copy(Lv.r, xo, Lv.n * nrhs, h->s);
+        check_launch();
+        break;
+      }
+      default:
+        return fail(BAMG_EINVAL, "unknown op");
+    }
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  }
+  return BAMG_OK;
+}
+
+int bamg_export_level(const bamg_hierarchy* hc, int32_t l, void* P_host, void* Dl_host, void* tv_host) {
+  bamg_hierarchy* h = const_cast<bamg_hierarchy*>(hc);
+  if (!h || l < 0 || l >= h->L()) return fail(BAMG_EINVAL, "bad level");
+  const Level& Lv = h->lv[l];
+  try {
+    if (P_host) {
+      if (!Lv.P) return fail(BAMG_EINVAL, "no P on the coarsest level");
+      HIPCHK(hipMemcpyAsync(P_host, Lv.P, Lv.n * 8 * sizeof(zd), hipMemcpyDeviceToHost, h->s));
+    }
+    if (Dl_host) {
+      if (!Lv.D) return fail(BAMG_EINVAL, "level 0 has no block operator");
+      HIPCHK(hipMemcpyAsync(Dl_host, Lv.D, (size_t)Lv.ex * Lv.ey * NOFF * 256 * sizeof(zd), hipMemcpyDeviceToHost, h->s));
+    }
+    if (tv_host) {
+      if (l != 0) return fail(BAMG_EINVAL, "test vectors are exported from level 0");
+      HIPCHK(hipMemcpyAsync(tv_host, h->tvsave, Lv.n * h->p.n_tv * sizeof(zd), hipMemcpyDeviceToHost, h->s));
+    }
+    HIPCHK(hipStreamSynchronize(h->s));
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  }
+  return BAMG_OK;
+}
+
+int bamg_import_level(bamg_hierarchy* h, int32_t l, const void* P_host, const void* Dl_host) {
+  if (!h || l < 0 || l + 1 >= h->L() || !P_host) return fail(BAMG_EINVAL, "bad level or P");
+  if (Dl_host) return fail(BAMG_EINVAL, "Dl_host is reserved and must be NULL");
+  try {
+    Level& Lv = h->lv[l];
+    HIPCHK(hipMemcpyAsync(Lv.P, P_host, Lv.n * 8 * sizeof(zd), hipMemcpyHostToDevice, h->s));
+    h->build_next(l);
+    HIPCHK(hipStreamSynchronize(h->s));
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  } catch (const BadArg& e) {
+    return fail(BAMG_ESINGULAR, e.msg);
+  }
+  return BAMG_OK;
+}
+
+int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void* out, void* stream) {
+  if (N < 2 || k < 1 || !out) return fail(BAMG_EINVAL, "bad arguments");
+  launch_philox_tv(N * N, k, seed, (zd*)out, (hipStream_t)stream);
+  if (hipGetLastError() != hipSuccess) return fail(BAMG_EDEVICE, "launch failed");
+  return BAMG_OK;
+}
+
+// Flexible GMRES(restart), right preconditioned by one cycle (Sec. 4), on the
+// reduced system; classical Gram-Schmidt applied twice; Givens rotations;
+// true residual recomputed at every restart.
+static int fgmres(bamg_hierarchy* h, double tol, bamg_solve_info* info) {
+  const size_t n = h->lv[0].n;
+  const int m = h->kdim;
+  hipStream_t s = h->s;
+  zd* hh = h->hhost;
+  // ||bhat||
+  launch_norms(h->bh, n, 1, n, h->partial, h->hdev, s);
+  HIPCHK(hipMemcpyAsync(hh, h->hdev, sizeof(zd), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double bnorm = std::sqrt(hh[0].x);
+  launch_fill_zero(h->xe, n, s);
+  info->iters = 0;
+  info->restarts = 0;
+  info->relres_reduced = 0;
+  if (bnorm == 0.0) return BAMG_OK;
+  launch_copy(h->bh, h->rr, n, s);
+  int it = 0, cycles = 0;
+  double relres = 1.0;
+  std::vector<std::complex<double>> H((size_t)(m + 1) * m), g(m + 1), sn(m);
+  std::vector<double> cs(m);
+  while (true) {
+    launch_norms(h->rr, n, 1, n, h->partial, h->hdev, s);
+    HIPCHK(hipMemcpyAsync(hh, h->hdev, sizeof(zd), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double beta = std::sqrt(hh[0].x);
+    relres = beta / bnorm;
+    if (!(relres > tol) || it >= h->p.max_iter) break;
+    launch_scale_copy(h->rr, h->V, n, 1.0 / beta, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    std::fill(H.begin(), H.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      zd* vj = h->V + (size_t)j * n;
+      zd* zj = h->Z + (size_t)j * n;
+      launch_fill_zero(zj, n, s);
+      h->cycle(0, vj, zj, 1);
+      h->apply(0, zj, h->w, nullptr, 1);
+      // CGS2: h1 = V^H w; w -= V h1; h2 = V^H w; w -= V h2; ||w||
+      launch_multidot(h->V, n, j + 1, h->w, n, h->partial, h->hdev, s);
+      launch_multiaxpy(h->V, n, j + 1, h->hdev, -1.0, h->w, n, s);
+      launch_multidot(h->V, n, j + 1, h->w, n, h->partial, h->hdev + 64, s);
+      launch_multiaxpy(h->V, n, j + 1, h->hdev + 64, -1.0, h->w, n, s);
+      launch_norms(h->w, n, 1, n, h->partial, h->hdev + 128, s);
+      check_launch();
+      HIPCHK(hipMemcpyAsync(hh, h->hdev, 129 * sizeof(zd), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int q = 0; q <= j; ++q)
+        H[(size_t)q * m + j] = std::complex<double>(hh[q].x, hh[q].y) + std::complex<double>(hh[64 + q].x, hh[64 + q].y);
+      const double hn = std::sqrt(hh[128].x);
+      if (!std::isfinite(hn)) throw HipFail("non-finite Arnoldi vector");
+      for (int q = 0; q < j; ++q) {
+        const std::complex<double> a = H[(size_t)q * m + j], b = H[(size_t)(q + 1) * m + j];
+        H[(size_t)q * m + j] = cs[q] * a + sn[q] * b;
+        H[(size_t)(q + 1) * m + j] = -std::conj(sn[q]) * a + cs[q] * b;
+      }
+      const std::complex<double> a = H[(size_t)j * m + j];
+      const double aa = std::abs(a);
+      double c;
+      std::complex<double> sv;
+      if (hn == 0.0) { c = 1.0; sv = 0.0; }
+      else if (aa == 0.0) { c = 0.0; sv = 1.0; }
+      else {
+        const double t = std::sqrt(aa * aa + hn * hn);
+        c = aa / t;
+        sv = (a / aa) * (hn / t);
+      }
+      cs[j] = c;
+      sn[j] = sv;
+      H[(size_t)j * m + j] = c * a + sv * hn;
+      g[j + 1] = -std::conj(sv) * g[j];
+      g[j] = c * g[j];
+      ++it;
+      jend = j + 1;
+      if (hn != 0.0) launch_scale_copy(h->w, h->V + (size_t)(j + 1) * n, n, 1.0 / hn, s);
+      if (std::abs(g[j + 1]) <= tol * bnorm || it >= h->p.max_iter || hn == 0.0) break;
+    }
+    std::vector<std::complex<double>> y(jend);
+    for (int i = jend - 1; i >= 0; --i) {
+      std::complex<double> sum = g[i];
+      for (int q = i + 1; q < jend; ++q) sum -= H[(size_t)i * m + q] * y[q];
+      y[i] = sum / H[(size_t)i * m + i];
+    }
+    std::vector<double> coef(2 * jend);
+    for (int q = 0; q < jend; ++q) {
+      coef[2 * q] = y[q].real();
+      coef[2 * q + 1] = y[q].imag();
+    }
+    launch_lincomb_host(h->Z, n, jend, coef.data(), h->xe, n, s);
+    h->apply(0, h->xe, h->rr, h->bh, 1);  // true residual
+    ++cycles;
+  }
+  info->iters = it;
+  info->restarts = cycles > 0 ? cycles - 1 : 0;
+  info->relres_reduced = relres;
+  info->rho_est = it > 0 ? std::pow(relres, 1.0 / it) : 0.0;
+  return relres <= tol ? BAMG_OK : BAMG_NOT_CONVERGED;
+}
+
+int bamg_solve(bamg_hierarchy* h, const void* b, void* x, double tol, bamg_solve_info* info) {
+  if (!h || !b || !x) return fail(BAMG_EINVAL, "bad arguments");
+  if (!(tol > 0)) return fail(BAMG_EINVAL, "tol must be > 0");
+  bamg_solve_info tmp{};
+  if (!info) info = &tmp;
+  *info = bamg_solve_info{};
+  const auto t0 = std::chrono::steady_clock::now();
+  int st;
+  try {
+    launch_eo_reduce(h->f, (const zd*)b, h->bh, 1, h->s);
+    HIPCHK(hipMemsetAsync(h->dflag, 0, sizeof(int), h->s));
+    launch_check_finite(h->bh, h->lv[0].n, h->dflag, h->s);
+    check_launch();
+    HIPCHK(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    if (*h->hflag) return fail(BAMG_EINVAL, "right-hand side is not finite");
+    st = fgmres(h, tol, info);
+    launch_eo_reconstruct(h->f, (const zd*)b, h->xe, (zd*)x, 1, h->s);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(h->s));
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  }
+  info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st == BAMG_NOT_CONVERGED) g_err = "not converged within max_iter";
+  return st;
+}
+
+int bamg_solve_batch(bamg_hierarchy* h, const void* B, void* X, int32_t nrhs, double tol, bamg_solve_info* infos) {
+  if (!h || !B || !X || nrhs < 1) return fail(BAMG_EINVAL, "bad arguments");
+  const size_t nf = 2 * h->lv[0].n;
+  int worst = BAMG_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    int st = bamg_solve(h, (const zd*)B + r * nf, (zd*)X + r * nf, tol, infos ? infos + r : nullptr);
+    if (st < 0) return st;
+    if (st > worst) worst = st;
+  }
+  return worst;
+}
+
+}  // extern "C"

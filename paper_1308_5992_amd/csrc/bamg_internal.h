@@ -1,0 +1,138 @@
+// Internal declarations of libbamg: complex arithmetic, device data layouts of
+// the levels and the host-side launch wrappers of every kernel.
+//
+// Device layouts (all FP64 unless a template says otherwise):
+//   links   Ue[(y*NH + xh)*2 + mu], Uo likewise: the two forward links of the
+//           even / odd site with half-x index (xh, y); NH = N/2.  The half-x
+//           index of lattice site (x, y) is y*NH + (x >> 1) for both parities.
+//   level 0 vectors v[rhs][y*NH + xh][s]   (the reduced layout of the ABI)
+//   level l vectors v[rhs][site][16]       (dof 8 s + k)
+//   P_l     [agg][s][row][8]
+//   D_l     [site][7][16][16]   offsets (0,0) (+1,0) (-1,0) (0,+1) (0,-1) (+1,+1) (-1,-1)
+//   Kinv_l  [site][16][16]      inverse of the lower triangle of G = A_a A_a^H
+//                               (the block row A_a of site a), used to run the
+//                               16 sequential row projections of a site at once
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace bamg {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+using zd = cx<double>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmk(T a, T b) { return cx<T>{a, b}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.x, -a.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cjmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+// i * a
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
+template <typename T>
+__host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * a.y; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cdiv_real(cx<T> a, T s) { return {a.x / s, a.y / s}; }
+
+constexpr int NOFF = 7;  // coarse stencil offsets
+constexpr int NC = 16;   // dofs per coarse site
+
+// Fine-level geometry and links
+struct Fine {
+  int N = 0, NH = 0;
+  double c = 0, kappa = 0, kappa2 = 0;  // c = m + 2, kappa = 1/c
+  const zd* Ue = nullptr;
+  const zd* Uo = nullptr;
+};
+
+// ---- fine.hip ---------------------------------------------------------------
+void launch_gauge_pack(const zd* U, zd* Ue, zd* Uo, int N, hipStream_t s);
+void launch_eo_reduce(const Fine& f, const zd* b, zd* bh, int nrhs, hipStream_t s);
+void launch_eo_reconstruct(const Fine& f, const zd* b, const zd* xe, zd* x, int nrhs, hipStream_t s);
+// y = Dhat x, or y = b - Dhat x if b != nullptr
+void launch_dhat(const Fine& f, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s);
+// one colour pass: sites[0..nsites) half-x indices of one colour
+void launch_kaczmarz_fine(const Fine& f, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
+                          hipStream_t s);
+// rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
+void launch_restrict_fine(const Fine& f, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s);
+void launch_prolong_fine(const Fine& f, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s);
+// D_1 = P^H Dhat P in 7-offset blocks
+void launch_galerkin_fine(const Fine& f, const zd* P, zd* D1, hipStream_t s);
+// gather test vectors into aggregate blocks and fit P (level 0)
+void launch_fit_fine(const Fine& f, const zd* V, int k, zd* P, hipStream_t s);
+void launch_philox_tv(int n, int k, uint64_t seed, zd* out, hipStream_t s);
+
+// ---- coarse.hip -------------------------------------------------------------
+struct Coarse {
+  int ex = 0, ey = 0;  // extents in sites
+  const zd* D = nullptr;
+  const zd* Kinv = nullptr;
+};
+void launch_coarse_apply(const Coarse& c, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s);
+void launch_kaczmarz_coarse(const Coarse& c, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
+                            hipStream_t s);
+void launch_kaczmarz_prep(const Coarse& c, zd* Kinv, hipStream_t s);
+// level l (ex x ey) -> l+1 (ex/2 x ey/2)
+void launch_restrict_coarse(const Coarse& c, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s);
+void launch_prolong_coarse(const Coarse& c, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s);
+void launch_galerkin_coarse(const Coarse& c, const zd* P, zd* Dc, hipStream_t s);
+void launch_fit_coarse(const Coarse& c, const zd* V, int k, zd* P, hipStream_t s);
+// expand the block stencil into a dense n x n matrix (coarsest level)
+void launch_densify(const Coarse& c, zd* A, hipStream_t s);
+
+// ---- dense.hip --------------------------------------------------------------
+// In-place Gauss-Jordan inversion with partial pivoting of the n x n matrix A;
+// work: n complex (column buffer) + 2 ints; sets *flag = 1 on a zero pivot.
+void launch_gj_step(zd* A, int n, int k, zd* col, int* perm, int* flag, hipStream_t s);
+void launch_gj_unpermute(zd* A, zd* tmp, int n, const int* perm, hipStream_t s);
+// y = A x for nrhs vectors (A n x n row-major)
+void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, hipStream_t s);
+
+// ---- blas.hip ---------------------------------------------------------------
+// partial[b][v] = sum over block b of conj(X_v) w, X_v = X + v*ldx; then out[v] = sum_b partial[b][v]
+int blas_nblocks(size_t n);
+void launch_multidot(const zd* X, size_t ldx, int nv, const zd* w, size_t n, zd* partial, zd* out,
+                     hipStream_t s);
+// w += sign * sum_v X_v h_v   (h on device)
+void launch_multiaxpy(const zd* X, size_t ldx, int nv, const zd* h, double sign, zd* w, size_t n,
+                      hipStream_t s);
+// per-vector squared norms of nv vectors of length n: out[v] (real part)
+void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s);
+// X_v *= 1/sqrt(nrm[v].x) for nrm > 0
+void launch_normalize(zd* X, size_t ldx, int nv, size_t n, const zd* nrm, hipStream_t s);
+// y = alpha x (alpha real, host scalar)
+void launch_scale_copy(const zd* x, zd* y, size_t n, double alpha, hipStream_t s);
+// y = x / h (h device complex scalar, real part used)
+void launch_div_by_dev(const zd* x, zd* y, size_t n, const zd* h, hipStream_t s);
+// y += sum_v X_v c_v (c host array copied by value, nv <= 64)
+void launch_lincomb_host(const zd* X, size_t ldx, int nv, const double* c_host, zd* y, size_t n,
+                         hipStream_t s);
+void launch_fill_zero(zd* x, size_t n, hipStream_t s);
+void launch_copy(const zd* x, zd* y, size_t n, hipStream_t s);
+// y = a - b
+void launch_sub(const zd* a, const zd* b, zd* y, size_t n, hipStream_t s);
+// flag[0] = 1 if any entry of x is not finite
+void launch_check_finite(const zd* x, size_t n, int* flag, hipStream_t s);
+
+}  // namespace bamg

@@ -1,0 +1,178 @@
+// Vector kernels of the outer flexible GMRES (Sec. 4): batched inner products
+// for classical Gram-Schmidt, the matching multi-axpy, norms, scaling.
+// Reductions are deterministic: a fixed block decomposition of the index
+// range gives per-block partial sums, reduced by one work-group in a fixed
+// tree order (no floating-point atomics), so repeated runs are bitwise equal.
+#include "bamg_internal.h"
+
+namespace bamg {
+
+constexpr int BT = 256;  // threads per reduction block
+
+int blas_nblocks(size_t n) {
+  size_t nb = (n + 2047) / 2048;
+  if (nb < 1) nb = 1;
+  if (nb > 512) nb = 512;
+  return (int)nb;
+}
+
+__device__ __forceinline__ zd block_sum(zd v, zd* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = BT / 2; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] = sh[tid] + sh[tid + off];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// partial[b * nv + v] = sum_{i in chunk b} conj(X_v[i]) w[i]   (w == nullptr: |X_v[i]|^2)
+__global__ __launch_bounds__(BT) void k_dot_partial(const zd* __restrict__ X, size_t ldx, int nv,
+                                                    const zd* __restrict__ w, size_t n, zd* __restrict__ partial) {
+  __shared__ zd sh[BT];
+  const int b = blockIdx.x, v = blockIdx.y, nb = gridDim.x;
+  const size_t chunk = (n + nb - 1) / nb;
+  const size_t lo = (size_t)b * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
+  const zd* xv = X + (size_t)v * ldx;
+  zd acc = {0, 0};
+  if (w) {
+    for (size_t i = lo + threadIdx.x; i < hi; i += BT) acc = acc + cjmul(xv[i], w[i]);
+  } else {
+    for (size_t i = lo + threadIdx.x; i < hi; i += BT) acc.x += norm2(xv[i]);
+  }
+  const zd s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[(size_t)b * nv + v] = s;
+}
+
+__global__ __launch_bounds__(BT) void k_reduce_partial(const zd* __restrict__ partial, int nb, int nv,
+                                                       zd* __restrict__ out) {
+  __shared__ zd sh[BT];
+  const int v = blockIdx.x;
+  zd acc = {0, 0};
+  for (int b = threadIdx.x; b < nb; b += BT) acc = acc + partial[(size_t)b * nv + v];
+  const zd s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[v] = s;
+}
+
+void launch_multidot(const zd* X, size_t ldx, int nv, const zd* w, size_t n, zd* partial, zd* out,
+                     hipStream_t s) {
+  const int nb = blas_nblocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, w, n, partial);
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
+}
+
+void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s) {
+  const int nb = blas_nblocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, (const zd*)nullptr, n, partial);
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
+}
+
+// w[i] += sign * sum_v X_v[i] h[v]
+__global__ void k_multiaxpy(const zd* __restrict__ X, size_t ldx, int nv, const zd* __restrict__ h, double sign,
+                            zd* __restrict__ w, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  zd acc = {0, 0};
+  for (int v = 0; v < nv; ++v) acc = acc + X[(size_t)v * ldx + i] * h[v];
+  w[i] = w[i] + sign * acc;
+}
+
+void launch_multiaxpy(const zd* X, size_t ldx, int nv, const zd* h, double sign, zd* w, size_t n,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_multiaxpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, ldx, nv, h, sign, w, n);
+}
+
+__global__ void k_normalize(zd* __restrict__ X, size_t ldx, size_t n, const zd* __restrict__ nrm) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (i >= n) return;
+  const double q = nrm[v].x;
+  if (q > 0) {
+    const double s = 1.0 / sqrt(q);
+    X[(size_t)v * ldx + i] = s * X[(size_t)v * ldx + i];
+  }
+}
+
+void launch_normalize(zd* X, size_t ldx, int nv, size_t n, const zd* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, dim3((unsigned)((n + 255) / 256), nv), dim3(256), 0, s, X, ldx, n, nrm);
+}
+
+__global__ void k_scale_copy(const zd* __restrict__ x, zd* __restrict__ y, size_t n, double a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+void launch_scale_copy(const zd* x, zd* y, size_t n, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, alpha);
+}
+
+__global__ void k_div_by_dev(const zd* __restrict__ x, zd* __restrict__ y, size_t n, const zd* __restrict__ h) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = cdiv_real(x[i], h[0].x);
+}
+
+void launch_div_by_dev(const zd* x, zd* y, size_t n, const zd* h, hipStream_t s) {
+  hipLaunchKernelGGL(k_div_by_dev, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, h);
+}
+
+struct Coef64 {
+  double c[128];
+};
+
+__global__ void k_lincomb(const zd* __restrict__ X, size_t ldx, int nv, Coef64 c, zd* __restrict__ y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  zd acc = {0, 0};
+  for (int v = 0; v < nv; ++v) acc = acc + X[(size_t)v * ldx + i] * zd{c.c[2 * v], c.c[2 * v + 1]};
+  y[i] = y[i] + acc;
+}
+
+void launch_lincomb_host(const zd* X, size_t ldx, int nv, const double* c_host, zd* y, size_t n, hipStream_t s) {
+  Coef64 c;
+  for (int v = 0; v < 2 * nv && v < 128; ++v) c.c[v] = c_host[v];
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, ldx, nv, c, y, n);
+}
+
+__global__ void k_fill_zero(zd* __restrict__ x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = zd{0, 0};
+}
+
+void launch_fill_zero(zd* x, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+}
+
+__global__ void k_copy(const zd* __restrict__ x, zd* __restrict__ y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+void launch_copy(const zd* x, zd* y, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+}
+
+__global__ void k_sub(const zd* __restrict__ a, const zd* __restrict__ b, zd* __restrict__ y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] - b[i];
+}
+
+void launch_sub(const zd* a, const zd* b, zd* y, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, y, n);
+}
+
+__global__ void k_check_finite(const zd* __restrict__ x, size_t n, int* __restrict__ flag) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const zd v = x[i];
+    if (!isfinite(v.x) || !isfinite(v.y)) flag[0] = 1;
+  }
+}
+
+void launch_check_finite(const zd* x, size_t n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, flag);
+}
+
+}  // namespace bamg

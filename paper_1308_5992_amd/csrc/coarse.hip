@@ -1,0 +1,335 @@
+// Coarse-level kernels: the Galerkin block stencil D_l (16 x 16 complex blocks
+// on the 7 offsets that the 4x4-then-2x2 aggregation of the odd-even reduced
+// operator produces, Sec. 3.2 / 3.5), its multicolour Kaczmarz smoother
+// (Sec. 3.1), the 2x2 aggregate transfers and least-squares fit (Sec. 3.3),
+// the Galerkin product of the next level and the dense expansion of the
+// coarsest operator.
+//
+// A wave (64 lanes) owns one coarse site: lane = 4*i + q holds row i of the
+// site's 16 x 112 block row, columns 4q..4q+3 of each of the 7 blocks.
+#include "bamg_internal.h"
+
+namespace bamg {
+
+__device__ __forceinline__ int cwrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__constant__ int ODX[NOFF] = {0, 1, -1, 0, 0, 1, -1};
+__constant__ int ODY[NOFF] = {0, 0, 0, 1, -1, 1, -1};
+
+__device__ __forceinline__ int coarse_offset_index(int dx, int dy) {
+  for (int o = 0; o < NOFF; ++o)
+    if (ODX[o] == dx && ODY[o] == dy) return o;
+  return -1;
+}
+
+__device__ __forceinline__ int neighbour_site(int site, int o, int ex, int ey) {
+  const int ax = site % ex, ay = site / ex;
+  return cwrap(ay + ODY[o], ey) * ex + cwrap(ax + ODX[o], ex);
+}
+
+__device__ __forceinline__ zd shfl_xor_z(zd v, int m) {
+  return zd{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
+}
+__device__ __forceinline__ zd shfl_z(zd v, int src) { return zd{__shfl(v.x, src, 64), __shfl(v.y, src, 64)}; }
+
+// ---------------------------------------------------------------------------
+// y = D x  (or y = b - D x)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coarse_apply(Coarse c, const zd* __restrict__ x, zd* __restrict__ y,
+                                                      const zd* __restrict__ b, int nrhs) {
+  const int ns = c.ex * c.ey;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int site = blockIdx.x * 4 + wave;
+  if (site >= ns) return;
+  const int i = lane >> 2, q = lane & 3;
+  int nb[NOFF];
+  zd Dv[NOFF][4];
+  for (int o = 0; o < NOFF; ++o) {
+    nb[o] = neighbour_site(site, o, c.ex, c.ey);
+    const zd* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 4 * q;
+    for (int jj = 0; jj < 4; ++jj) Dv[o][jj] = Dr[jj];
+  }
+  const size_t n = (size_t)ns * 16;
+  for (int r = 0; r < nrhs; ++r) {
+    const zd* xv = x + r * n;
+    zd acc = {0, 0};
+    for (int o = 0; o < NOFF; ++o)
+      for (int jj = 0; jj < 4; ++jj) acc = acc + Dv[o][jj] * xv[nb[o] * 16 + 4 * q + jj];
+    acc = acc + shfl_xor_z(acc, 1);
+    acc = acc + shfl_xor_z(acc, 2);
+    if (q == 0) {
+      if (b) acc = b[r * n + site * 16 + i] - acc;
+      y[r * n + site * 16 + i] = acc;
+    }
+  }
+}
+
+void launch_coarse_apply(const Coarse& c, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s) {
+  int ns = c.ex * c.ey;
+  hipLaunchKernelGGL(k_coarse_apply, dim3((ns + 3) / 4), dim3(256), 0, s, c, x, y, b, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// One colour pass of the coarse Kaczmarz smoother.  The 16 rows d_i of a site
+// are projected one after the other (i = 0..15).  With G = A_a A_a^H the
+// sequence is exactly alpha = tril(G)^{-1} (b_a - A_a x), x += A_a^H alpha
+// (row i sees the updates of rows m < i through G_im), so a wave computes the
+// residual block, applies the precomputed Kinv = tril(G)^{-1} and scatters.
+// One wave per block; the scatter sums over rows go through LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_kaczmarz_coarse(Coarse c, const int* __restrict__ sites, int nsites,
+                                                        zd* __restrict__ x, const zd* __restrict__ b) {
+  __shared__ zd part[16][NOFF * 16];
+  const int ns = c.ex * c.ey;
+  const int t = blockIdx.x;
+  if (t >= nsites) return;
+  const int lane = threadIdx.x, i = lane >> 2, q = lane & 3;
+  const int site = sites[t];
+  const size_t n = (size_t)ns * 16;
+  zd* xv = x + blockIdx.y * n;
+  int nb[NOFF];
+  zd Dv[NOFF][4];
+  for (int o = 0; o < NOFF; ++o) {
+    nb[o] = neighbour_site(site, o, c.ex, c.ey);
+    const zd* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 4 * q;
+    for (int jj = 0; jj < 4; ++jj) Dv[o][jj] = Dr[jj];
+  }
+  // residual of the 16 rows
+  zd acc = {0, 0};
+  for (int o = 0; o < NOFF; ++o)
+    for (int jj = 0; jj < 4; ++jj) acc = acc + Dv[o][jj] * xv[nb[o] * 16 + 4 * q + jj];
+  acc = acc + shfl_xor_z(acc, 1);
+  acc = acc + shfl_xor_z(acc, 2);
+  const zd bi = b ? b[blockIdx.y * n + site * 16 + i] : zd{0, 0};
+  const zd res = bi - acc;  // r_i in all four lanes of row i
+  // alpha_i = sum_{j <= i} Kinv[i][j] r_j
+  const zd* K = c.Kinv + ((size_t)site * 16 + i) * 16 + 4 * q;
+  zd al = {0, 0};
+  for (int jj = 0; jj < 4; ++jj) {
+    const zd rj = shfl_z(res, 4 * (4 * q + jj));
+    al = al + K[jj] * rj;
+  }
+  al = al + shfl_xor_z(al, 1);
+  al = al + shfl_xor_z(al, 2);
+  // x_col += sum_i conj(D[i][col]) alpha_i
+  for (int o = 0; o < NOFF; ++o)
+    for (int jj = 0; jj < 4; ++jj) part[i][o * 16 + 4 * q + jj] = cjmul(Dv[o][jj], al);
+  __syncthreads();
+  for (int col = lane; col < NOFF * 16; col += 64) {
+    zd sum = {0, 0};
+    for (int r = 0; r < 16; ++r) sum = sum + part[r][col];
+    const int o = col >> 4, j = col & 15;
+    zd* xp = xv + nb[o] * 16 + j;
+    *xp = *xp + sum;
+  }
+}
+
+void launch_kaczmarz_coarse(const Coarse& c, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_kaczmarz_coarse, dim3(nsites, nrhs), dim3(64), 0, s, c, sites, nsites, x, b);
+}
+
+// ---------------------------------------------------------------------------
+// Kinv = tril(G)^{-1}, G = sum_o D[o] D[o]^H per site (G_ii = ||d_i||^2).
+// A zero row (G_ii = 0) is skipped by the smoother: its row and column of Kinv
+// are zero.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_kaczmarz_prep(Coarse c, zd* __restrict__ Kinv) {
+  __shared__ zd G[16][16];
+  __shared__ zd K[16][16];
+  const int site = blockIdx.x;
+  const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
+  zd g = {0, 0};
+  if (j <= i) {
+    for (int o = 0; o < NOFF; ++o) {
+      const zd* Di = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16;
+      const zd* Dj = c.D + (((size_t)site * NOFF + o) * 16 + j) * 16;
+      for (int m = 0; m < 16; ++m) g = g + cjmul(Dj[m], Di[m]);
+    }
+  }
+  G[i][j] = g;
+  K[i][j] = zd{0, 0};
+  __syncthreads();
+  if (tid < 16) {
+    const int col = tid;
+    if (G[col][col].x > 0) {
+      K[col][col] = zd{1.0 / G[col][col].x, 0};
+      for (int r = col + 1; r < 16; ++r) {
+        if (!(G[r][r].x > 0)) continue;
+        zd s = {0, 0};
+        for (int m = col; m < r; ++m) s = s + G[r][m] * K[m][col];
+        K[r][col] = -(cdiv_real(s, G[r][r].x));
+      }
+    }
+  }
+  __syncthreads();
+  Kinv[((size_t)site * 16 + i) * 16 + j] = K[i][j];
+}
+
+void launch_kaczmarz_prep(const Coarse& c, zd* Kinv, hipStream_t s) {
+  hipLaunchKernelGGL(k_kaczmarz_prep, dim3(c.ex * c.ey), dim3(256), 0, s, c, Kinv);
+}
+
+// ---------------------------------------------------------------------------
+// 2x2 aggregation: coarse site A = AY*(ex/2) + AX holds the sites
+// (2AX + (t&1), 2AY + (t>>1)), local t; P rows 8t + (d mod 8) for spin d/8.
+// ---------------------------------------------------------------------------
+__global__ void k_restrict_coarse(Coarse c, const zd* __restrict__ P, const zd* __restrict__ r, zd* __restrict__ rc) {
+  const int cex = c.ex / 2, cey = c.ey / 2;
+  const int tt = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tt >= cex * cey * 16) return;
+  const int A = tt >> 4, d = tt & 15, s = d >> 3, k = d & 7;
+  const int AX = A % cex, AY = A / cex;
+  const size_t n = (size_t)c.ex * c.ey * 16, nc = (size_t)cex * cey * 16;
+  const zd* rv = r + blockIdx.y * n;
+  const zd* Pa = P + ((size_t)A * 2 + s) * 32 * 8;
+  zd acc = {0, 0};
+  for (int t = 0; t < 4; ++t) {
+    const int site = (2 * AY + (t >> 1)) * c.ex + 2 * AX + (t & 1);
+    for (int j = 0; j < 8; ++j) acc = acc + cjmul(Pa[(8 * t + j) * 8 + k], rv[site * 16 + 8 * s + j]);
+  }
+  rc[blockIdx.y * nc + tt] = acc;
+}
+
+void launch_restrict_coarse(const Coarse& c, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s) {
+  int n = (c.ex / 2) * (c.ey / 2) * 16;
+  hipLaunchKernelGGL(k_restrict_coarse, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, c, P, r, rc);
+}
+
+__global__ void k_prolong_coarse(Coarse c, const zd* __restrict__ P, const zd* __restrict__ xc, zd* __restrict__ x) {
+  const int cex = c.ex / 2, cey = c.ey / 2;
+  const int tt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ns = c.ex * c.ey;
+  if (tt >= ns * 16) return;
+  const int site = tt >> 4, d = tt & 15, s = d >> 3, j = d & 7;
+  const int ax = site % c.ex, ay = site / c.ex;
+  const int A = (ay >> 1) * cex + (ax >> 1), t = 2 * (ay & 1) + (ax & 1);
+  const size_t n = (size_t)ns * 16, nc = (size_t)cex * cey * 16;
+  const zd* Pr = P + (((size_t)A * 2 + s) * 32 + 8 * t + j) * 8;
+  const zd* xcv = xc + blockIdx.y * nc + A * 16 + 8 * s;
+  zd acc = {0, 0};
+  for (int k = 0; k < 8; ++k) acc = acc + Pr[k] * xcv[k];
+  x[blockIdx.y * n + tt] = x[blockIdx.y * n + tt] + acc;
+}
+
+void launch_prolong_coarse(const Coarse& c, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s) {
+  int n = c.ex * c.ey * 16;
+  hipLaunchKernelGGL(k_prolong_coarse, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, c, P, xc, x);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin product of the next level by fine displacement:
+// Dc[A][O][(s1,k1),(s2,k2)] = sum_{t, o: agg(a_t + o) = A + O}
+//     sum_{j1, j2} conj(P[A][s1][8t+j1][k1]) D[a_t][o][8s1+j1][8s2+j2] P[A+O][s2][8t'+j2][k2]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int fdiv2(int a) { return a >= 0 ? a >> 1 : -((-a + 1) >> 1); }
+
+__global__ __launch_bounds__(256) void k_galerkin_coarse(Coarse c, const zd* __restrict__ P, zd* __restrict__ Dc) {
+  const int cex = c.ex / 2, cey = c.ey / 2;
+  const int A = blockIdx.x, AX = A % cex, AY = A / cex;
+  __shared__ int tO[4][NOFF], tT[4][NOFF], tA[4][NOFF], tS[4];
+  const int tid = threadIdx.x;
+  if (tid < 4 * NOFF) {
+    const int t = tid / NOFF, o = tid - t * NOFF;
+    const int ux = 2 * AX + (t & 1), uy = 2 * AY + (t >> 1);
+    const int nx = ux + ODX[o], ny = uy + ODY[o];
+    const int BX = fdiv2(nx), BY = fdiv2(ny);
+    tO[t][o] = coarse_offset_index(BX - AX, BY - AY);
+    tT[t][o] = 2 * (ny - 2 * BY) + (nx - 2 * BX);
+    tA[t][o] = cwrap(BY, cey) * cex + cwrap(BX, cex);
+    if (o == 0) tS[t] = uy * c.ex + ux;
+  }
+  __syncthreads();
+  for (int out = tid; out < NOFF * 256; out += blockDim.x) {
+    const int O = out >> 8, rr = (out >> 4) & 15, cc = out & 15;
+    const int s1 = rr >> 3, k1 = rr & 7, s2 = cc >> 3, k2 = cc & 7;
+    zd acc = {0, 0};
+    for (int t = 0; t < 4; ++t)
+      for (int o = 0; o < NOFF; ++o) {
+        if (tO[t][o] != O) continue;
+        const zd* Dblk = c.D + ((size_t)tS[t] * NOFF + o) * 256;
+        const zd* Pb = P + ((size_t)tA[t][o] * 2 + s2) * 32 * 8;
+        const zd* Pa = P + ((size_t)A * 2 + s1) * 32 * 8;
+        for (int j1 = 0; j1 < 8; ++j1) {
+          zd part = {0, 0};
+          for (int j2 = 0; j2 < 8; ++j2)
+            part = part + Dblk[(8 * s1 + j1) * 16 + 8 * s2 + j2] * Pb[(8 * tT[t][o] + j2) * 8 + k2];
+          acc = acc + cjmul(Pa[(8 * t + j1) * 8 + k1], part);
+        }
+      }
+    Dc[(((size_t)A * NOFF + O) * 16 + rr) * 16 + cc] = acc;
+  }
+}
+
+void launch_galerkin_coarse(const Coarse& c, const zd* P, zd* Dc, hipStream_t s) {
+  int na = (c.ex / 2) * (c.ey / 2);
+  hipLaunchKernelGGL(k_galerkin_coarse, dim3(na), dim3(256), 0, s, c, P, Dc);
+}
+
+// ---------------------------------------------------------------------------
+// Least-squares fit on a coarse level: 32 rows (4 sites x 8 dofs of spin s)
+// per problem, two problems per wave, classical Gram-Schmidt applied twice.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ zd seg_sum_c(zd v) {
+#pragma unroll
+  for (int off = R / 2; off > 0; off >>= 1) v = v + shfl_xor_z(v, off);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_fit_coarse(Coarse c, const zd* __restrict__ V, int k, zd* __restrict__ P) {
+  const int cex = c.ex / 2, cey = c.ey / 2;
+  const int lane = threadIdx.x, grp = lane >> 5, row = lane & 31;
+  const int prob = blockIdx.x * 2 + grp;
+  const int nprob = cex * cey * 2;
+  const bool act = prob < nprob;
+  const int A = act ? prob >> 1 : 0, s = prob & 1;
+  const int AX = A % cex, AY = A / cex;
+  const int t = row >> 3, j = row & 7;
+  const int site = (2 * AY + (t >> 1)) * c.ex + 2 * AX + (t & 1);
+  const size_t n = (size_t)c.ex * c.ey * 16;
+  zd v[8], qv[8];
+  for (int m = 0; m < 8; ++m) v[m] = (act && m < k) ? V[m * n + site * 16 + 8 * s + j] : zd{0, 0};
+  for (int m = 0; m < 8; ++m) qv[m] = zd{0, 0};
+  for (int jj = 0; jj < k && jj < 8; ++jj) {
+    zd w = v[jj];
+    for (int pass = 0; pass < 2; ++pass) {
+      zd h[8];
+      for (int q = 0; q < jj; ++q) h[q] = seg_sum_c<32>(cjmul(qv[q], w));
+      for (int q = 0; q < jj; ++q) w = w - qv[q] * h[q];
+    }
+    const double nrm = sqrt(seg_sum_c<32>(zd{norm2(w), 0.0}).x);
+    qv[jj] = nrm > 0 ? cdiv_real(w, nrm) : zd{0, 0};
+  }
+  if (act)
+    for (int m = 0; m < 8; ++m) P[(((size_t)A * 2 + s) * 32 + row) * 8 + m] = qv[m];
+}
+
+void launch_fit_coarse(const Coarse& c, const zd* V, int k, zd* P, hipStream_t s) {
+  int nprob = (c.ex / 2) * (c.ey / 2) * 2;
+  hipLaunchKernelGGL(k_fit_coarse, dim3((nprob + 1) / 2), dim3(64), 0, s, c, V, k, P);
+}
+
+// ---------------------------------------------------------------------------
+// dense n x n matrix of the block stencil (n = 16 ex ey), aliasing offsets summed
+// ---------------------------------------------------------------------------
+__global__ void k_densify(Coarse c, zd* __restrict__ A) {
+  const int ns = c.ex * c.ey, n = ns * 16;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int site = row >> 4, i = row & 15;
+  zd* Ar = A + (size_t)row * n;
+  for (int col = 0; col < n; ++col) Ar[col] = zd{0, 0};
+  for (int o = 0; o < NOFF; ++o) {
+    const int nb = neighbour_site(site, o, c.ex, c.ey);
+    const zd* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16;
+    for (int j = 0; j < 16; ++j) Ar[nb * 16 + j] = Ar[nb * 16 + j] + Dr[j];
+  }
+}
+
+void launch_densify(const Coarse& c, zd* A, hipStream_t s) {
+  int n = c.ex * c.ey * 16;
+  hipLaunchKernelGGL(k_densify, dim3((n + 63) / 64), dim3(64), 0, s, c, A);
+}
+
+}  // namespace bamg

@@ -1,0 +1,520 @@
+// Fine-level kernels: the odd-even reduced Wilson operator Dhat (Sec. 3.2,
+// eq. wilsonSchur), the reduction of the right-hand side and the odd-site
+// reconstruction, the 16-colour Kaczmarz row projections on Dhat (Sec. 3.1),
+// transfer between the fine grid and the first aggregate grid (Sec. 3.3,
+// eq. bs), the fine Galerkin product (Sec. 3.5) and the test-vector generator.
+//
+// Notation: H is the Wilson hopping term of eq. (wilson),
+//   (H psi)_z = sum_mu [ P_mu^- U_mu(z) psi_{z+mu} + P_mu^+ conj(U_mu(z-mu)) psi_{z-mu} ],
+// P_mu^{+-} = (I +- gamma_mu)/2 with gamma_1 = [[0,1],[1,0]], gamma_2 = [[0,i],[-i,0]]
+// (Sec. 2).  Each projector is rank one, so a hop costs one complex product:
+//   +x: h = u (a - b) -> (h, -h)        -x: h = u (a + b) -> (h,  h)
+//   +y: h = u (a - i b) -> (h, i h)     -y: h = u (a + i b) -> (h, -i h)
+// with a factor 1/2 applied once per hop (exact in binary floating point).
+#include "bamg_internal.h"
+
+namespace bamg {
+
+__device__ __forceinline__ int wrapn(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// half-x index of lattice site (x, y), |displacement| <= N assumed
+__device__ __forceinline__ int hidx(int x, int y, int N, int NH) {
+  return wrapn(y, N) * NH + (wrapn(x, N) >> 1);
+}
+
+// accumulate the hop in direction d (0:+x 1:-x 2:+y 3:-y) of spinor (a, b) with link u
+// (u already conjugated for backward hops) into (o0, o1), without the factor 1/2
+__device__ __forceinline__ void hop_acc(int d, zd u, zd a, zd b, zd& o0, zd& o1) {
+  zd h;
+  switch (d) {
+    case 0: h = u * (a - b); o0 = o0 + h; o1 = o1 - h; break;
+    case 1: h = u * (a + b); o0 = o0 + h; o1 = o1 + h; break;
+    case 2: h = u * (a - mul_i(b)); o0 = o0 + h; o1 = o1 + mul_i(h); break;
+    default: h = u * (a + mul_i(b)); o0 = o0 + h; o1 = o1 - mul_i(h); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gauge layout: U[mu][y][x] -> Ue/Uo[(y*NH + xh)*2 + mu]
+// ---------------------------------------------------------------------------
+__global__ void k_gauge_pack(const zd* __restrict__ U, zd* __restrict__ Ue, zd* __restrict__ Uo, int N) {
+  int NH = N / 2;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * NH) return;
+  int y = i / NH, xh = i - y * NH, p = y & 1;
+  int xe = 2 * xh + p, xo = 2 * xh + 1 - p;
+  for (int mu = 0; mu < 2; ++mu) {
+    Ue[2 * i + mu] = U[((size_t)mu * N + y) * N + xe];
+    Uo[2 * i + mu] = U[((size_t)mu * N + y) * N + xo];
+  }
+}
+
+void launch_gauge_pack(const zd* U, zd* Ue, zd* Uo, int N, hipStream_t s) {
+  int n = N * N / 2;
+  hipLaunchKernelGGL(k_gauge_pack, dim3((n + 255) / 256), dim3(256), 0, s, U, Ue, Uo, N);
+}
+
+// ---------------------------------------------------------------------------
+// bhat = kappa b_e + kappa^2 H_eo b_o   (b in the full-lattice layout)
+// ---------------------------------------------------------------------------
+__global__ void k_eo_reduce(Fine f, const zd* __restrict__ b, zd* __restrict__ bh) {
+  int N = f.N, NH = f.NH;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  if (i >= N * NH) return;
+  const zd* bf = b + (size_t)r * 2 * N * N;
+  int y = i / NH, xh = i - y * NH;
+  int x = 2 * xh + (y & 1);
+  const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+  zd o0 = {0, 0}, o1 = {0, 0};
+  for (int d = 0; d < 4; ++d) {
+    int xn = wrapn(x + dx[d], N), yn = wrapn(y + dy[d], N);
+    size_t q = ((size_t)yn * N + xn) * 2;
+    zd u;
+    if (d == 0) u = f.Ue[2 * i + 0];
+    else if (d == 2) u = f.Ue[2 * i + 1];
+    else u = conj(f.Uo[2 * (yn * NH + (xn >> 1)) + (d == 1 ? 0 : 1)]);
+    hop_acc(d, u, bf[q], bf[q + 1], o0, o1);
+  }
+  size_t qe = ((size_t)y * N + x) * 2;
+  double k = f.kappa, k2h = 0.5 * f.kappa2;
+  zd* out = bh + (size_t)r * N * N;
+  out[2 * i] = k * bf[qe] + k2h * o0;
+  out[2 * i + 1] = k * bf[qe + 1] + k2h * o1;
+}
+
+void launch_eo_reduce(const Fine& f, const zd* b, zd* bh, int nrhs, hipStream_t s) {
+  int n = f.N * f.NH;
+  hipLaunchKernelGGL(k_eo_reduce, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, b, bh);
+}
+
+// ---------------------------------------------------------------------------
+// x_e copied into the full layout, x_o = kappa b_o + kappa H_oe x_e
+// ---------------------------------------------------------------------------
+__global__ void k_eo_reconstruct(Fine f, const zd* __restrict__ b, const zd* __restrict__ xe,
+                                 zd* __restrict__ x) {
+  int N = f.N, NH = f.NH;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  if (i >= N * NH) return;
+  const zd* bf = b + (size_t)r * 2 * N * N;
+  const zd* xr = xe + (size_t)r * N * N;
+  zd* xf = x + (size_t)r * 2 * N * N;
+  int y = i / NH, xh = i - y * NH, p = y & 1;
+  int lxe = 2 * xh + p, lxo = 2 * xh + 1 - p;
+  size_t qe = ((size_t)y * N + lxe) * 2, qo = ((size_t)y * N + lxo) * 2;
+  xf[qe] = xr[2 * i];
+  xf[qe + 1] = xr[2 * i + 1];
+  const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+  zd o0 = {0, 0}, o1 = {0, 0};
+  for (int d = 0; d < 4; ++d) {
+    int xn = wrapn(lxo + dx[d], N), yn = wrapn(y + dy[d], N);
+    int j = yn * NH + (xn >> 1);
+    zd u;
+    if (d == 0) u = f.Uo[2 * i + 0];
+    else if (d == 2) u = f.Uo[2 * i + 1];
+    else u = conj(f.Ue[2 * j + (d == 1 ? 0 : 1)]);
+    hop_acc(d, u, xr[2 * j], xr[2 * j + 1], o0, o1);
+  }
+  double k = f.kappa, kh = 0.5 * f.kappa;
+  xf[qo] = k * bf[qo] + kh * o0;
+  xf[qo + 1] = k * bf[qo + 1] + kh * o1;
+}
+
+void launch_eo_reconstruct(const Fine& f, const zd* b, const zd* xe, zd* x, int nrhs, hipStream_t s) {
+  int n = f.N * f.NH;
+  hipLaunchKernelGGL(k_eo_reconstruct, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, b, xe, x);
+}
+
+// ---------------------------------------------------------------------------
+// Dhat apply: y = x - kappa^2 H_eo (H_oe x), or y = b - Dhat x.
+// One work-group owns a TX x TY tile of even sites (half-x columns x rows).
+// Stage 1 computes t = H_oe x on the odd sites of the tile plus a one-site
+// halo into LDS; stage 2 applies H_eo from LDS.  x and the links are read
+// once from HBM per tile (halo re-reads hit L2).
+// ---------------------------------------------------------------------------
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_dhat(Fine f, const zd* __restrict__ x, zd* __restrict__ y,
+                                                 const zd* __restrict__ b) {
+  constexpr int W = TX + 2, NREG = (TY + 2) * (TX + 2), NT = TX * TY;
+  __shared__ zd t0[NREG], t1[NREG];
+  const int N = f.N, NH = f.NH;
+  const size_t n = (size_t)N * NH * 2;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const zd* __restrict__ xv = x + blockIdx.z * n;
+  const zd* __restrict__ Ue = f.Ue;
+  const zd* __restrict__ Uo = f.Uo;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < NREG; q += NT) {
+    int cy = q / W, cxh = q - cy * W;
+    int yy = wrapn(y0 - 1 + cy, N), xhh = wrapn(x0 - 1 + cxh, NH);
+    int lx = 2 * xhh + 1 - (yy & 1);
+    int w = yy * NH + xhh;
+    int jpx = hidx(lx + 1, yy, N, NH), jmx = hidx(lx - 1, yy, N, NH);
+    int jpy = hidx(lx, yy + 1, N, NH), jmy = hidx(lx, yy - 1, N, NH);
+    zd a0 = {0, 0}, a1 = {0, 0};
+    hop_acc(0, Uo[2 * w], xv[2 * jpx], xv[2 * jpx + 1], a0, a1);
+    hop_acc(1, conj(Ue[2 * jmx]), xv[2 * jmx], xv[2 * jmx + 1], a0, a1);
+    hop_acc(2, Uo[2 * w + 1], xv[2 * jpy], xv[2 * jpy + 1], a0, a1);
+    hop_acc(3, conj(Ue[2 * jmy + 1]), xv[2 * jmy], xv[2 * jmy + 1], a0, a1);
+    t0[q] = a0;
+    t1[q] = a1;
+  }
+  __syncthreads();
+  const int ly = tid / TX, lxh = tid - ly * TX;
+  const int yy = y0 + ly, xhh = x0 + lxh, p = yy & 1;
+  const int e = yy * NH + xhh;
+  const int qpx = (ly + 1) * W + lxh + 1 + p, qmx = (ly + 1) * W + lxh + p;
+  const int qpy = (ly + 2) * W + lxh + 1, qmy = ly * W + lxh + 1;
+  const int omx = yy * NH + wrapn(xhh + p - 1, NH), omy = wrapn(yy - 1, N) * NH + xhh;
+  zd a0 = {0, 0}, a1 = {0, 0};
+  hop_acc(0, Ue[2 * e], t0[qpx], t1[qpx], a0, a1);
+  hop_acc(1, conj(Uo[2 * omx]), t0[qmx], t1[qmx], a0, a1);
+  hop_acc(2, Ue[2 * e + 1], t0[qpy], t1[qpy], a0, a1);
+  hop_acc(3, conj(Uo[2 * omy + 1]), t0[qmy], t1[qmy], a0, a1);
+  const double k2q = 0.25 * f.kappa2;
+  zd r0 = xv[2 * e] - k2q * a0, r1 = xv[2 * e + 1] - k2q * a1;
+  zd* yv = y + blockIdx.z * n;
+  if (b) {
+    const zd* bv = b + blockIdx.z * n;
+    r0 = bv[2 * e] - r0;
+    r1 = bv[2 * e + 1] - r1;
+  }
+  yv[2 * e] = r0;
+  yv[2 * e + 1] = r1;
+}
+
+void launch_dhat(const Fine& f, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s) {
+  const int N = f.N, NH = f.NH;
+  dim3 g;
+#define DHAT_CASE(TX)                                                                     \
+  if (NH % TX == 0) {                                                                     \
+    g = dim3(NH / TX, N / 4, nrhs);                                                       \
+    hipLaunchKernelGGL((k_dhat<TX, 4>), g, dim3(TX * 4), 0, s, f, x, y, b);              \
+    return;                                                                               \
+  }
+  DHAT_CASE(64) DHAT_CASE(32) DHAT_CASE(16) DHAT_CASE(8) DHAT_CASE(4)
+#undef DHAT_CASE
+}
+
+// ---------------------------------------------------------------------------
+// Rows of Dhat at even site (xh, y): e[n][s][t] = Dhat[(i,s), (j_n,t)] for the
+// nine even sites j_n at lattice displacement (SDX[n], SDY[n]).  Built from
+// the two-hop paths i -> w -> j; back-tracking paths vanish exactly
+// (P^- P^+ = 0) and are skipped, so the diagonal block is I.
+// ---------------------------------------------------------------------------
+__constant__ int SDX[9] = {0, 2, -2, 0, 0, 1, 1, -1, -1};
+__constant__ int SDY[9] = {0, 0, 0, 2, -2, 1, -1, 1, -1};
+// slot of the path (d1, d2), -1 for back-tracking
+__constant__ int SLOT[4][4] = {{1, -1, 5, 6}, {-1, 2, 7, 8}, {5, 7, 3, -1}, {6, 8, -1, 4}};
+
+// 2x2 projector (times 2) of the hop in direction d: Pi_d = 2 P^{-+}
+__device__ __forceinline__ void proj2(int d, zd P[2][2]) {
+  const zd one = {1, 0}, mone = {-1, 0}, I = {0, 1}, mI = {0, -1};
+  switch (d) {
+    case 0: P[0][0] = one; P[0][1] = mone; P[1][0] = mone; P[1][1] = one; break;  // I - g1
+    case 1: P[0][0] = one; P[0][1] = one; P[1][0] = one; P[1][1] = one; break;    // I + g1
+    case 2: P[0][0] = one; P[0][1] = mI; P[1][0] = I; P[1][1] = one; break;       // I - g2
+    default: P[0][0] = one; P[0][1] = I; P[1][0] = mI; P[1][1] = one; break;      // I + g2
+  }
+}
+
+__device__ void dhat_rows(const Fine& f, int xh, int y, zd e[9][2][2], int jn[9]) {
+  const int N = f.N, NH = f.NH;
+  const int x = 2 * xh + (y & 1);
+  const int i = y * NH + xh;
+  const int dxs[4] = {1, -1, 0, 0}, dys[4] = {0, 0, 1, -1};
+  for (int n = 0; n < 9; ++n) {
+    jn[n] = hidx(x + SDX[n], y + SDY[n], N, NH);
+    for (int s = 0; s < 2; ++s)
+      for (int t = 0; t < 2; ++t) e[n][s][t] = zd{0, 0};
+  }
+  for (int d1 = 0; d1 < 4; ++d1) {
+    const int wx = x + dxs[d1], wy = y + dys[d1];
+    const int w = hidx(wx, wy, N, NH);
+    zd l1;
+    if (d1 == 0) l1 = f.Ue[2 * i];
+    else if (d1 == 2) l1 = f.Ue[2 * i + 1];
+    else l1 = conj(f.Uo[2 * w + (d1 == 1 ? 0 : 1)]);
+    zd P1[2][2];
+    proj2(d1, P1);
+    for (int d2 = 0; d2 < 4; ++d2) {
+      const int sl = SLOT[d1][d2];
+      if (sl < 0) continue;
+      zd l2;
+      if (d2 == 0) l2 = f.Uo[2 * w];
+      else if (d2 == 2) l2 = f.Uo[2 * w + 1];
+      else l2 = conj(f.Ue[2 * jn[sl] + (d2 == 1 ? 0 : 1)]);
+      zd P2[2][2];
+      proj2(d2, P2);
+      const zd u = l1 * l2;
+      for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) {
+          zd pp = P1[s][0] * P2[0][t] + P1[s][1] * P2[1][t];
+          e[sl][s][t] = e[sl][s][t] + pp * u;
+        }
+    }
+  }
+  // Dhat = I - kappa^2 H_eo H_oe, each hop carrying 1/2
+  const double k2q = 0.25 * f.kappa2;
+  for (int n = 0; n < 9; ++n)
+    for (int s = 0; s < 2; ++s)
+      for (int t = 0; t < 2; ++t) e[n][s][t] = -(k2q * e[n][s][t]);
+  e[0][0][0] = e[0][0][0] + zd{1, 0};
+  e[0][1][1] = e[0][1][1] + zd{1, 0};
+}
+
+// ---------------------------------------------------------------------------
+// One colour pass of the fine Kaczmarz smoother: every site of the colour
+// projects its spin-0 row, then its spin-1 row:
+//   alpha = (b_r - d_r . x) / ||d_r||^2,  x_j += alpha conj(d_rj).
+// Sites of one colour touch disjoint sets of unknowns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_kaczmarz_fine(Fine f, const int* __restrict__ sites, int nsites,
+                                                      zd* __restrict__ x, const zd* __restrict__ b) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsites) return;
+  const size_t n = (size_t)f.N * f.NH * 2;
+  zd* xv = x + blockIdx.y * n;
+  const int i = sites[t];
+  const int y = i / f.NH, xh = i - y * f.NH;
+  zd e[9][2][2];
+  int jn[9];
+  dhat_rows(f, xh, y, e, jn);
+  zd xs[9][2];
+  for (int q = 0; q < 9; ++q) {
+    xs[q][0] = xv[2 * jn[q]];
+    xs[q][1] = xv[2 * jn[q] + 1];
+  }
+  for (int s = 0; s < 2; ++s) {
+    double nu = 0;
+    zd res = b ? b[blockIdx.y * n + 2 * i + s] : zd{0, 0};
+    for (int q = 0; q < 9; ++q)
+      for (int u = 0; u < 2; ++u) {
+        nu += norm2(e[q][s][u]);
+        res = res - e[q][s][u] * xs[q][u];
+      }
+    const zd alpha = cdiv_real(res, nu);
+    for (int q = 0; q < 9; ++q)
+      for (int u = 0; u < 2; ++u) xs[q][u] = xs[q][u] + cjmul(e[q][s][u], alpha);
+  }
+  for (int q = 0; q < 9; ++q) {
+    xv[2 * jn[q]] = xs[q][0];
+    xv[2 * jn[q] + 1] = xs[q][1];
+  }
+}
+
+void launch_kaczmarz_fine(const Fine& f, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_kaczmarz_fine, dim3((nsites + 63) / 64, nrhs), dim3(64), 0, s, f, sites, nsites, x, b);
+}
+
+// ---------------------------------------------------------------------------
+// Transfers between level 0 and the 4x4 aggregates of the half-x grid.
+// Aggregate a = Ay*(NH/4) + Ax holds the even sites xh = 4Ax + lx, y = 4Ay + ly,
+// local row 4*ly + lx.  rc[a][8s + k] = sum_row conj(P[a][s][row][k]) r[site][s].
+// ---------------------------------------------------------------------------
+__global__ void k_restrict_fine(Fine f, const zd* __restrict__ P, const zd* __restrict__ r, zd* __restrict__ rc) {
+  const int cxn = f.NH / 4, cyn = f.N / 4;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cxn * cyn * 16) return;
+  const int a = t >> 4, d = t & 15, s = d >> 3, k = d & 7;
+  const int Ax = a % cxn, Ay = a / cxn;
+  const size_t n = (size_t)f.N * f.NH * 2, nc = (size_t)cxn * cyn * 16;
+  const zd* rv = r + blockIdx.y * n;
+  const zd* Pa = P + ((size_t)a * 2 + s) * 16 * 8;
+  zd acc = {0, 0};
+  for (int row = 0; row < 16; ++row) {
+    int ly = row >> 2, lx = row & 3;
+    int e = (4 * Ay + ly) * f.NH + 4 * Ax + lx;
+    acc = acc + cjmul(Pa[row * 8 + k], rv[2 * e + s]);
+  }
+  rc[blockIdx.y * nc + t] = acc;
+}
+
+void launch_restrict_fine(const Fine& f, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s) {
+  int n = (f.NH / 4) * (f.N / 4) * 16;
+  hipLaunchKernelGGL(k_restrict_fine, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, r, rc);
+}
+
+__global__ void k_prolong_fine(Fine f, const zd* __restrict__ P, const zd* __restrict__ xc, zd* __restrict__ x) {
+  const int cxn = f.NH / 4, cyn = f.N / 4;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= f.N * f.NH * 2) return;
+  const int e = t >> 1, s = t & 1;
+  const int y = e / f.NH, xh = e - y * f.NH;
+  const int a = (y >> 2) * cxn + (xh >> 2), row = 4 * (y & 3) + (xh & 3);
+  const size_t n = (size_t)f.N * f.NH * 2, nc = (size_t)cxn * cyn * 16;
+  const zd* Pr = P + (((size_t)a * 2 + s) * 16 + row) * 8;
+  const zd* xcv = xc + blockIdx.y * nc + a * 16 + 8 * s;
+  zd acc = {0, 0};
+  for (int k = 0; k < 8; ++k) acc = acc + Pr[k] * xcv[k];
+  x[blockIdx.y * n + t] = x[blockIdx.y * n + t] + acc;
+}
+
+void launch_prolong_fine(const Fine& f, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s) {
+  int n = f.N * f.NH * 2;
+  hipLaunchKernelGGL(k_prolong_fine, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, xc, x);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin product D_1 = P^H Dhat P, assembled per aggregate A by fine
+// displacement: for every fine pair (i in A, j = i + disp) the aggregate of j
+// (in unwrapped coordinates) fixes the offset o, so grids of extent < 3 (where
+// offsets alias) are still exact.
+// D_1[A][o][(s1,k1),(s2,k2)] = sum conj(P_A[s1][i][k1]) Dhat[(i,s1),(j,s2)] P_{A+o}[s2][j][k2]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int offset_index(int dx, int dy) {
+  if (dx == 0 && dy == 0) return 0;
+  if (dx == 1 && dy == 0) return 1;
+  if (dx == -1 && dy == 0) return 2;
+  if (dx == 0 && dy == 1) return 3;
+  if (dx == 0 && dy == -1) return 4;
+  if (dx == 1 && dy == 1) return 5;
+  if (dx == -1 && dy == -1) return 6;
+  return -1;
+}
+
+__device__ __forceinline__ int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+__global__ __launch_bounds__(256) void k_galerkin_fine(Fine f, const zd* __restrict__ P, zd* __restrict__ D1) {
+  const int cxn = f.NH / 4, cyn = f.N / 4;
+  const int A = blockIdx.x, Ax = A % cxn, Ay = A / cxn;
+  __shared__ zd rows[16][9][2][2];
+  __shared__ int tgt_o[16][9], tgt_row[16][9], tgt_agg[16][9];
+  const int tid = threadIdx.x;
+  if (tid < 16) {
+    const int ly = tid >> 2, lx = tid & 3;
+    const int y = 4 * Ay + ly, xh = 4 * Ax + lx;
+    zd e[9][2][2];
+    int jn[9];
+    dhat_rows(f, xh, y, e, jn);
+    const int x = 2 * xh + (y & 1);
+    for (int q = 0; q < 9; ++q) {
+      for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) rows[tid][q][s][t] = e[q][s][t];
+      // unwrapped half-x coordinates of the neighbour
+      const int yn = y + SDY[q];
+      const int xn = x + SDX[q];
+      const int xhn = (xn >= 0) ? (xn >> 1) : -((-xn + 1) >> 1);
+      const int Axn = floordiv(xhn, 4), Ayn = floordiv(yn, 4);
+      tgt_o[tid][q] = offset_index(Axn - Ax, Ayn - Ay);
+      tgt_row[tid][q] = 4 * (yn - 4 * Ayn) + (xhn - 4 * Axn);
+      tgt_agg[tid][q] = wrapn(Ayn, cyn) * cxn + wrapn(Axn, cxn);
+    }
+  }
+  __syncthreads();
+  for (int out = tid; out < NOFF * 256; out += blockDim.x) {
+    const int o = out >> 8, rr = (out >> 4) & 15, cc = out & 15;
+    const int s1 = rr >> 3, k1 = rr & 7, s2 = cc >> 3, k2 = cc & 7;
+    zd acc = {0, 0};
+    for (int i = 0; i < 16; ++i) {
+      const zd pa = P[(((size_t)A * 2 + s1) * 16 + i) * 8 + k1];
+      zd part = {0, 0};
+      for (int q = 0; q < 9; ++q) {
+        if (tgt_o[i][q] != o) continue;
+        const zd pb = P[(((size_t)tgt_agg[i][q] * 2 + s2) * 16 + tgt_row[i][q]) * 8 + k2];
+        part = part + rows[i][q][s1][s2] * pb;
+      }
+      acc = acc + cjmul(pa, part);
+    }
+    D1[(((size_t)A * NOFF + o) * 16 + rr) * 16 + cc] = acc;
+  }
+}
+
+void launch_galerkin_fine(const Fine& f, const zd* P, zd* D1, hipStream_t s) {
+  int na = (f.NH / 4) * (f.N / 4);
+  hipLaunchKernelGGL(k_galerkin_fine, dim3(na), dim3(256), 0, s, f, P, D1);
+}
+
+// ---------------------------------------------------------------------------
+// Least-squares fit (Sec. 3.3, eq. LSfuncrowi) per aggregate and spin: with
+// k <= 8 test vectors restricted to a block of R rows the fit is exact and
+// P_{a,s} is the orthonormal basis from classical Gram-Schmidt applied twice
+// (positive R_jj), in test-vector order.  R rows of one problem live in R
+// consecutive lanes; sums are butterfly reductions over those lanes.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ zd seg_sum(zd v) {
+#pragma unroll
+  for (int off = R / 2; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+template <int R>
+__device__ void cgs2_fit(const zd* vrow, int k, zd* qrow) {
+  // vrow[j]: the lane's entry of test vector j; qrow[j]: output
+  for (int j = 0; j < 8; ++j) qrow[j] = zd{0, 0};
+  for (int j = 0; j < k && j < 8; ++j) {
+    zd w = vrow[j];
+    for (int pass = 0; pass < 2; ++pass) {
+      zd h[8];
+      for (int q = 0; q < j; ++q) h[q] = seg_sum<R>(cjmul(qrow[q], w));
+      for (int q = 0; q < j; ++q) w = w - qrow[q] * h[q];
+    }
+    const double nrm = sqrt(seg_sum<R>(zd{norm2(w), 0.0}).x);
+    qrow[j] = nrm > 0 ? cdiv_real(w, nrm) : zd{0, 0};
+  }
+}
+
+__global__ __launch_bounds__(64) void k_fit_fine(Fine f, const zd* __restrict__ V, int k, zd* __restrict__ P) {
+  const int cxn = f.NH / 4, cyn = f.N / 4;
+  const int lane = threadIdx.x, grp = lane >> 4, row = lane & 15;
+  const int prob = blockIdx.x * 4 + grp;  // (aggregate, spin)
+  const int nprob = cxn * cyn * 2;
+  const bool act = prob < nprob;
+  const int a = act ? prob >> 1 : 0, s = prob & 1;
+  const int Ax = a % cxn, Ay = a / cxn;
+  const int e = (4 * Ay + (row >> 2)) * f.NH + 4 * Ax + (row & 3);
+  const size_t n = (size_t)f.N * f.NH * 2;
+  zd v[8], q[8];
+  for (int j = 0; j < 8; ++j) v[j] = (act && j < k) ? V[j * n + 2 * e + s] : zd{0, 0};
+  cgs2_fit<16>(v, k, q);
+  if (act)
+    for (int j = 0; j < 8; ++j) P[(((size_t)a * 2 + s) * 16 + row) * 8 + j] = q[j];
+}
+
+void launch_fit_fine(const Fine& f, const zd* V, int k, zd* P, hipStream_t s) {
+  int nprob = (f.NH / 4) * (f.N / 4) * 2;
+  hipLaunchKernelGGL(k_fit_fine, dim3((nprob + 3) / 4), dim3(64), 0, s, f, V, k, P);
+}
+
+// ---------------------------------------------------------------------------
+// Test vectors: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed with
+// counter (dof, vector, 0, 0); two 53-bit uniforms in (0,1) -> Box-Muller ->
+// one complex Gaussian with Re, Im i.i.d. N(0, 1/2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+}
+
+__global__ void k_philox_tv(int n, int k, uint64_t seed, zd* __restrict__ out) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * k) return;
+  const int j = (int)(t / n), d = (int)(t - (size_t)j * n);
+  uint32_t c[4] = {(uint32_t)d, (uint32_t)j, 0u, 0u};
+  philox10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  const double two53 = 9007199254740992.0;
+  const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) / two53;
+  const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) / two53;
+  const double rho = sqrt(-2.0 * log(u1));
+  const double th = 2.0 * M_PI * u2;
+  const double s2 = sqrt(2.0);
+  out[t] = zd{rho * cos(th) / s2, rho * sin(th) / s2};
+}
+
+void launch_philox_tv(int n, int k, uint64_t seed, zd* out, hipStream_t s) {
+  size_t tot = (size_t)n * k;
+  hipLaunchKernelGGL(k_philox_tv, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, k, seed, out);
+}
+
+}  // namespace bamg

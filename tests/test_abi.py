@@ -1,0 +1,46 @@
+"""The C-ABI library loads on the host and exports every entry point that
+include/bamg.h declares (no GPU work is issued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "bamg.h")
+LIB = os.path.join(ROOT, "paper_1308_5992_amd", "libbamg.so")
+
+
+def declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bamg_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ["bamg_setup", "bamg_solve", "bamg_solve_batch", "bamg_apply_dhat", "bamg_free",
+                 "bamg_export_level", "bamg_import_level", "bamg_footprint_bytes", "bamg_last_error",
+                 "bamg_default_params"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("libbamg.so not built")
+    lib = ctypes.CDLL(LIB)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_host_only_entry_points():
+    """default params and the footprint query run on the host."""
+    if not os.path.exists(LIB):
+        pytest.skip("libbamg.so not built")
+    import paper_1308_5992_amd as b
+    p = b.bamg_default_params(N=256)
+    assert (p.max_coarse, p.n_tv, p.pre, p.post, p.restart) == (2048, 8, 4, 4, 32)
+    fb = b.bamg_footprint_bytes(p)
+    assert 50 * 2 ** 20 < fb < 2 * 2 ** 30
+    assert b.bamg_footprint_bytes(b.bamg_default_params(N=36)) == 0
+    assert b.bamg_footprint_bytes(b.bamg_default_params(N=512)) > fb
