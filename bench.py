@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the BAMG-preconditioned FGMRES solve on one MI355X.
+
+Workload (default): 256 x 256 periodic lattice, quenched U(1) links from 500
+Metropolis sweeps at beta = 10 (seed 3), mass calibrated so that
+min |eig(D)| ~ 1e-4, one complex Gaussian right-hand side (seed 103); 4-level
+hierarchy (4x4 then 2x2 aggregates, 8 test vectors), V(4,4) cycle, FGMRES(32)
+to a relative residual of 1e-10 on the reduced system.  Setup is done once
+and timed separately; every timed step is one full solve (reduction, FGMRES,
+reconstruction) with the right-hand side already in HBM.
+
+Prints one JSON line (rank 0).  Besides solves/s it reports the Dhat
+("D_oe") bandwidth at three sizes, the roofline of the dominant kernel and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s to rel-res 1e-10 @256² (mixed vs FP64); D_oe HBM GB/s; p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3_256_b10")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dhat", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    return ap.parse_args()
+
+
+def time_launches(fn, reps, launches_per_call, torch):
+    """Average duration per kernel launch of fn() (events on the library's stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / (reps * launches_per_call)
+
+
+def dhat_bandwidth(bamg, inputs, torch, N, nrhs, reps):
+    """GB/s of the Dhat kernel: 64 N^2 bytes per right-hand side per apply
+    (x and y 16 N^2 each, links 32 N^2), algorithmic; operator-only handle."""
+    U = torch.from_numpy(inputs.gauge_random(N, 77)).to("cuda:0")
+    p = bamg.bamg_default_params(N=N, n_levels=1)
+    h = bamg.bamg_setup(U, -0.05, p)
+    x = torch.from_numpy(inputs.gaussian((nrhs, N * N), 78)).to("cuda:0")
+    y = torch.empty_like(x)
+    t = time_launches(lambda: bamg.bamg_apply_dhat(h, x, y, nrhs), reps, 1, torch)
+    bytes_ = 64.0 * N * N * nrhs
+    bamg.bamg_free(h)
+    del x, y, U
+    torch.cuda.empty_cache()
+    return {"N": N, "nrhs": nrhs, "us": t * 1e6, "GB/s": bytes_ / t / 1e9}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (a multi-GPU run would shard "
+              "right-hand sides, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import inputs
+    import paper_1308_5992_amd as bamg
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = inputs.workload(args.workload)
+    N = w["N"]
+    t0 = time.time()
+    U_np = inputs.load_gauge(w)
+    t_gauge = time.time() - t0
+    U = torch.from_numpy(U_np).to("cuda:0")
+    b = torch.from_numpy(inputs.gaussian(2 * N * N, w["rhs_seed"])).to("cuda:0")
+    x = torch.zeros_like(b)
+    p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    h = bamg.bamg_setup(U, w["m"], p)
+    torch.cuda.synchronize()
+    t_setup = time.time() - t0
+    n_levels = bamg.bamg_n_levels(h)
+
+    for _ in range(args.warmup):
+        bamg.bamg_solve(h, b, x, args.tol)
+    torch.cuda.synchronize()
+    times, infos = [], []
+    t_all0 = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        st, info = bamg.bamg_solve(h, b, x, args.tol)
+        times.append(time.perf_counter() - t1)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all0
+    ok = all(i["relres_reduced"] <= args.tol for i in infos)
+    ms = [1e3 * t for t in times]
+    value = args.steps / t_all
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_all / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w["name"], "N": N, "beta": w["beta"], "metropolis_sweeps": w["sweeps"],
+            "m": w["m"], "min_abs_eig_D": w["min_abs_eig_D"], "levels": n_levels,
+            "aggregates": "4x4 half-x, then 2x2", "test_vectors": 8, "cycle": "V(4,4)",
+            "krylov": "FGMRES(32)", "tol": args.tol, "nrhs": 1, "precision": "fp64",
+        },
+        "p50_ms": statistics.median(ms),
+        "p99_ms": float(np.percentile(ms, 99)),
+        "iters": infos[-1]["iters"],
+        "relres_reduced": infos[-1]["relres_reduced"],
+        "converged": ok,
+        "setup_s": t_setup,
+        "gauge_gen_s": t_gauge,
+    }
+
+    # ---- Dhat ("D_oe") bandwidth: cache-resident, batched, cache-busting
+    if not args.no_dhat:
+        pts = []
+        for (n_, r_, reps) in ((256, 1, 200), (512, 64, 20), (4096, 1, 20)):
+            pts.append(dhat_bandwidth(bamg, inputs, torch, n_, r_, reps))
+        out["dhat_bandwidth"] = pts
+
+    # ---- roofline of the dominant kernel of the solve
+    if not args.no_roofline:
+        out["roofline"] = roofline(bamg, torch, h, N)
+
+    # ---- CPU oracle on a bounded sample of the same workload
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, U_np, args.tol)
+
+    bamg.bamg_free(h)
+    print(json.dumps(out), flush=True)
+
+
+def roofline(bamg, torch, h, N):
+    """Coarse Kaczmarz colour pass on level 1 (the kernel with the largest share
+    of solve time in the kernel trace of this workload).  Algorithmic bytes per
+    sweep: per coarse site the 7 blocks of 16x16 complex (28672 B), the 16x16
+    smoother matrix (4096 B), the site's unknowns read and written (512 B) and
+    its right-hand side (256 B); one launch is one of the colours."""
+    inf = bamg.bamg_level_info(h, 1)
+    ns = inf["ex"] * inf["ey"]
+    ncol = inf["colours"]
+    n = inf["n"]
+    xb = torch.zeros(n, dtype=torch.complex128, device="cuda:0")
+    bb = torch.ones(n, dtype=torch.complex128, device="cuda:0")
+    reps = 50
+    t = time_launches(lambda: bamg.bamg_level_op(h, 1, bamg.OP_SWEEP, bb, xb, 1), reps, ncol, torch)
+    bytes_launch = ns * (28672 + 4096 + 512 + 256) / ncol
+    achieved = bytes_launch / t / 1e9
+    return {"kernel": "k_kaczmarz_coarse (level 1)", "bound": "hbm", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "avg_launch_us": t * 1e6, "bytes_per_launch": bytes_launch}
+
+
+def cpu_baseline(w, U_np, tol):
+    """The oracle (single-threaded C++ FP64) solving the same system: its setup
+    runs untimed, the sample is one full solve."""
+    import numpy as np
+    import inputs
+    import oracle
+    N = w["N"]
+    b = inputs.gaussian(2 * N * N, w["rhs_seed"])
+    o = oracle.Hierarchy(U_np, w["m"], n_levels=w["n_levels"], seed=w["tv_seed"])
+    t0 = time.perf_counter()
+    st, xo, info = o.solve(b, tol=tol)
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / t, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full solve of the same workload ({info['iters']} FGMRES iterations, "
+                      f"{t:.2f} s); oracle setup untimed", "iters": info["iters"]}
+
+
+if __name__ == "__main__":
+    main()

@@ -122,6 +122,17 @@ struct bamg_hierarchy {
   zd* hhost = nullptr;  // pinned
   zd* tvsave = nullptr; // level-0 test vectors after the last setup pass
 
+  void ensure_krylov() {
+    if (V) return;
+    const size_t n0 = lv[0].n;
+    V = dalloc<zd>(n0 * (kdim + 1));
+    Z = dalloc<zd>(n0 * kdim);
+    w = dalloc<zd>(n0);
+    bh = dalloc<zd>(n0);
+    xe = dalloc<zd>(n0);
+    rr = dalloc<zd>(n0);
+  }
+
   ~bamg_hierarchy() {
     for (auto& L : lv) {
       dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.col_sites); dfree(L.P);
@@ -185,6 +196,10 @@ struct bamg_hierarchy {
   // (pre-smoothing, residual, restriction, coarse correction, prolongation,
   // post-smoothing; Sec. 1 two-grid scheme applied recursively, Sec. 4)
   void cycle(int l, const zd* b, zd* x, int nrhs) {
+    if (L() == 1) {  // one level: the cycle reduces to its smoothing sweeps
+      for (int i = 0; i < p.pre + p.post; ++i) sweep(0, x, b, nrhs);
+      return;
+    }
     if (coarsest(l)) {
       coarsest_solve(b, x, nrhs);
       return;
@@ -292,6 +307,7 @@ bool level_shapes(const bamg_params* p, Shape& sh, std::string& why) {
   if (N < 16 || N % 8 != 0) { why = "N must be a multiple of 8 and >= 16"; return false; }
   sh.ext.clear();
   sh.ext.push_back({N / 2, N});
+  if (p->n_levels == 1) return true;  // operator only: smoother-preconditioned Krylov
   int ex = N / 8, ey = N / 4;
   sh.ext.push_back({ex, ey});
   while (true) {
@@ -305,7 +321,7 @@ bool level_shapes(const bamg_params* p, Shape& sh, std::string& why) {
   }
   if (p->n_levels > 0 && (int)sh.ext.size() != p->n_levels) { why = "n_levels not reachable for this N"; return false; }
   const size_t nL = (size_t)sh.ext.back().first * sh.ext.back().second * 16;
-  if (nL > 8192) { why = "coarsest level dimension exceeds 8192 (dense inverse); raise n_levels"; return false; }
+  if (sh.ext.size() > 1 && nL > 8192) { why = "coarsest level dimension exceeds 8192 (dense inverse); raise n_levels"; return false; }
   return true;
 }
 
@@ -361,6 +377,7 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
   for (int l = 0; l < L; ++l) {
     const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
     const size_t n = ns * (l == 0 ? 2 : 16);
+    if (L == 1) { bytes += 3 * n * z; break; }  // operator only
     bytes += (3 + k) * n * z;  // work vectors + test vectors
     if (l >= 1) bytes += ns * NOFF * 256 * z;
     if (l >= 1 && l < L - 1) bytes += ns * 256 * z;
@@ -399,6 +416,7 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
     launch_gauge_pack((const zd*)gauge, h->Ue, h->Uo, N, h->s);
     check_launch();
     const int L = (int)sh.ext.size(), k = p->n_tv;
+    const bool mg = L > 1;
     h->lv.resize(L);
     for (int l = 0; l < L; ++l) {
       Level& Lv = h->lv[l];
@@ -406,53 +424,51 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
       Lv.ey = sh.ext[l].second;
       Lv.dps = (l == 0) ? 2 : 16;
       Lv.n = (size_t)Lv.ex * Lv.ey * Lv.dps;
-      Lv.tv = dalloc<zd>(Lv.n * k);
+      if (mg) Lv.tv = dalloc<zd>(Lv.n * k);
       if (l >= 1) Lv.D = dalloc<zd>((size_t)Lv.ex * Lv.ey * NOFF * 256);
-      if (l < L - 1) {
-        Lv.prow = (l == 0) ? 16 : 32;
-        Lv.P = dalloc<zd>(Lv.n * 8);
+      if (!mg || l < L - 1) {
         h->build_colours(l);
+        if (mg) {
+          Lv.prow = (l == 0) ? 16 : 32;
+          Lv.P = dalloc<zd>(Lv.n * 8);
+        }
         if (l >= 1) Lv.Kinv = dalloc<zd>((size_t)Lv.ex * Lv.ey * 256);
       } else {
         Lv.Ainv = dalloc<zd>(Lv.n * Lv.n);
       }
     }
-    h->ensure_cap(k);
+    h->ensure_cap(mg ? k : 1);
     const size_t n0 = h->lv[0].n;
-    h->gjcol = dalloc<zd>(h->lv.back().n);
-    h->gjperm = dalloc<int>(h->lv.back().n);
     h->dflag = dalloc<int>(1);
     HIPCHK(hipHostMalloc((void**)&h->hflag, sizeof(int)));
     h->kdim = p->restart;
-    h->V = dalloc<zd>(n0 * (h->kdim + 1));
-    h->Z = dalloc<zd>(n0 * h->kdim);
-    h->w = dalloc<zd>(n0);
-    h->bh = dalloc<zd>(n0);
-    h->xe = dalloc<zd>(n0);
-    h->rr = dalloc<zd>(n0);
     h->partial = dalloc<zd>((size_t)blas_nblocks(n0) * 64);
     h->hdev = dalloc<zd>(256);
     HIPCHK(hipHostMalloc((void**)&h->hhost, 256 * sizeof(zd)));
-    h->tvsave = dalloc<zd>(n0 * k);
-    // initial test vectors (Sec. 4: random, normal, mean 0, variance 1)
-    if (p->init_tv_host) {
-      HIPCHK(hipMemcpyAsync(h->lv[0].tv, p->init_tv_host, n0 * k * sizeof(zd), hipMemcpyHostToDevice, h->s));
-    } else {
-      launch_philox_tv((int)n0, k, p->seed, h->lv[0].tv, h->s);
-      check_launch();
-    }
-    h->setup_pass();
-    // adaptive passes: two cycles of the current hierarchy on Dhat v = 0 for
-    // every saved level-0 test vector, then relax-fit-coarsen again
-    for (int a = 0; a < p->setup_adapt; ++a) {
-      Level& L0 = h->lv[0];
-      launch_copy(h->tvsave, L0.tv, n0 * k, h->s);
-      launch_fill_zero(L0.b, n0 * k, h->s);
-      for (int c = 0; c < 2; ++c) h->cycle(0, L0.b, L0.tv, k);
-      launch_norms(L0.tv, n0, k, n0, h->partial, h->hdev, h->s);
-      launch_normalize(L0.tv, n0, k, n0, h->hdev, h->s);
-      check_launch();
+    if (mg) {
+      h->gjcol = dalloc<zd>(h->lv.back().n);
+      h->gjperm = dalloc<int>(h->lv.back().n);
+      h->tvsave = dalloc<zd>(n0 * k);
+      // initial test vectors (Sec. 4: random, normal, mean 0, variance 1)
+      if (p->init_tv_host) {
+        HIPCHK(hipMemcpyAsync(h->lv[0].tv, p->init_tv_host, n0 * k * sizeof(zd), hipMemcpyHostToDevice, h->s));
+      } else {
+        launch_philox_tv((int)n0, k, p->seed, h->lv[0].tv, h->s);
+        check_launch();
+      }
       h->setup_pass();
+      // adaptive passes: two cycles of the current hierarchy on Dhat v = 0 for
+      // every saved level-0 test vector, then relax-fit-coarsen again
+      for (int a = 0; a < p->setup_adapt; ++a) {
+        Level& L0 = h->lv[0];
+        launch_copy(h->tvsave, L0.tv, n0 * k, h->s);
+        launch_fill_zero(L0.b, n0 * k, h->s);
+        for (int c = 0; c < 2; ++c) h->cycle(0, L0.b, L0.tv, k);
+        launch_norms(L0.tv, n0, k, n0, h->partial, h->hdev, h->s);
+        launch_normalize(L0.tv, n0, k, n0, h->hdev, h->s);
+        check_launch();
+        h->setup_pass();
+      }
     }
     HIPCHK(hipStreamSynchronize(h->s));
   } catch (const HipFail& e) {
@@ -520,7 +536,7 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         h->apply(l, xi, xo, nullptr, nrhs);
         break;
       case BAMG_OP_SWEEP:
-        if (h->coarsest(l)) return fail(BAMG_EINVAL, "no smoother on the coarsest level");
+        if (h->coarsest(l) && h->L() > 1) return fail(BAMG_EINVAL, "no smoother on the coarsest level");
         h->sweep(l, xo, xi, nrhs);
         break;
       case BAMG_OP_RESTRICT:
@@ -532,7 +548,7 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         h->prolong(l, xi, xo, nrhs);
         break;
       case BAMG_OP_COARSEST:
-        if (!h->coarsest(l)) return fail(BAMG_EINVAL, "level is not the coarsest");
+        if (!h->coarsest(l) || h->L() == 1) return fail(BAMG_EINVAL, "level is not a directly solved coarsest level");
         h->coarsest_solve(xi, xo, nrhs);
         break;
       case BAMG_OP_CYCLE:
@@ -571,7 +587,7 @@ int bamg_export_level(const bamg_hierarchy* hc, int32_t l, void* P_host, void* D
       HIPCHK(hipMemcpyAsync(Dl_host, Lv.D, (size_t)Lv.ex * Lv.ey * NOFF * 256 * sizeof(zd), hipMemcpyDeviceToHost, h->s));
     }
     if (tv_host) {
-      if (l != 0) return fail(BAMG_EINVAL, "test vectors are exported from level 0");
+      if (l != 0 || !h->tvsave) return fail(BAMG_EINVAL, "test vectors are exported from level 0 of a multigrid hierarchy");
       HIPCHK(hipMemcpyAsync(tv_host, h->tvsave, Lv.n * h->p.n_tv * sizeof(zd), hipMemcpyDeviceToHost, h->s));
     }
     HIPCHK(hipStreamSynchronize(h->s));
@@ -715,6 +731,7 @@ int bamg_solve(bamg_hierarchy* h, const void* b, void* x, double tol, bamg_solve
   const auto t0 = std::chrono::steady_clock::now();
   int st;
   try {
+    h->ensure_krylov();
     launch_eo_reduce(h->f, (const zd*)b, h->bh, 1, h->s);
     HIPCHK(hipMemsetAsync(h->dflag, 0, sizeof(int), h->s));
     launch_check_finite(h->bh, h->lv[0].n, h->dflag, h->s);
