@@ -75,11 +75,6 @@ int coarse_ncol(int ex, int ey) {
   if (ex % 4 == 0 && ey % 4 == 0) return 16;
   return ex * ey;
 }
-int coarse_colour_of(int ax, int ay, int ex, int ey) {
-  if (ex % 8 == 0 && ey % 8 == 0) return floor_mod(ax - 3 * ay, 8);
-  if (ex % 4 == 0 && ey % 4 == 0) return 4 * (ay % 4) + (ax % 4);
-  return ay * ex + ax;
-}
 
 }  // namespace
 
@@ -89,8 +84,7 @@ struct Level {
   zd* D = nullptr;              // coarse block stencil (levels >= 1)
   zd* Kinv = nullptr;           // smoother data (non-coarsest coarse levels)
   zd* Ainv = nullptr;           // inverse of the coarsest operator
-  std::vector<int> col_off;     // colour c: sites [col_off[c], col_off[c+1]) of col_sites
-  int* col_sites = nullptr;
+  int ncol = 0, cmode = 0, per_colour = 0;  // smoother colours, colouring mode, sites per colour
   zd* P = nullptr;              // interpolation from level l+1 (non-coarsest levels)
   int prow = 0;                 // rows of P_{a,s}
   zd *x = nullptr, *b = nullptr, *r = nullptr;  // work vectors, cap right-hand sides
@@ -135,7 +129,7 @@ struct bamg_hierarchy {
 
   ~bamg_hierarchy() {
     for (auto& L : lv) {
-      dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.col_sites); dfree(L.P);
+      dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.P);
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
     }
     dfree(Ue); dfree(Uo); dfree(gjcol); dfree(gjperm); dfree(dflag);
@@ -167,12 +161,9 @@ struct bamg_hierarchy {
   }
   void sweep(int l, zd* x, const zd* b, int nrhs) {
     Level& Lv = lv[l];
-    const int nc = (int)Lv.col_off.size() - 1;
-    for (int c = 0; c < nc; ++c) {
-      const int lo = Lv.col_off[c], cnt = Lv.col_off[c + 1] - lo;
-      if (cnt == 0) continue;
-      if (l == 0) launch_kaczmarz_fine(f, Lv.col_sites + lo, cnt, x, b, nrhs, s);
-      else launch_kaczmarz_coarse(Lv.coarse(), Lv.col_sites + lo, cnt, x, b, nrhs, s);
+    for (int c = 0; c < Lv.ncol; ++c) {
+      if (l == 0) launch_kaczmarz_fine(f, c, Lv.per_colour, x, b, nrhs, s);
+      else launch_kaczmarz_coarse(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
     }
     check_launch();
   }
@@ -220,28 +211,19 @@ struct bamg_hierarchy {
   }
 
   // ---------------------------------------------------------------- setup
+  // colour classes of the smoother (the kernels enumerate the sites of a
+  // colour arithmetically)
   void build_colours(int l) {
     Level& Lv = lv[l];
-    std::vector<std::vector<int>> bins;
     if (l == 0) {
-      bins.resize(16);
-      const int N = f.N, NH = f.NH;
-      for (int y = 0; y < N; ++y)
-        for (int xh = 0; xh < NH; ++xh) bins[fine_colour_of(2 * xh + (y & 1), y)].push_back(y * NH + xh);
+      Lv.ncol = 16;
+      Lv.cmode = 0;
+      Lv.per_colour = f.N * f.N / 32;
     } else {
-      bins.resize(coarse_ncol(Lv.ex, Lv.ey));
-      for (int ay = 0; ay < Lv.ey; ++ay)
-        for (int ax = 0; ax < Lv.ex; ++ax) bins[coarse_colour_of(ax, ay, Lv.ex, Lv.ey)].push_back(ay * Lv.ex + ax);
+      Lv.ncol = coarse_ncol(Lv.ex, Lv.ey);
+      Lv.cmode = Lv.ncol == 8 ? 8 : (Lv.ncol == 16 ? 16 : 1);
+      Lv.per_colour = Lv.ex * Lv.ey / (Lv.cmode == 1 ? Lv.ex * Lv.ey : Lv.cmode);
     }
-    std::vector<int> flat;
-    Lv.col_off.assign(1, 0);
-    for (auto& b : bins) {
-      flat.insert(flat.end(), b.begin(), b.end());
-      Lv.col_off.push_back((int)flat.size());
-    }
-    Lv.col_sites = dalloc<int>(flat.size());
-    HIPCHK(hipMemcpyAsync(Lv.col_sites, flat.data(), flat.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
   }
 
   // D_{l+1} from P_l, then its smoother data or (coarsest) its inverse
@@ -496,7 +478,7 @@ int bamg_level_info(const bamg_hierarchy* h, int32_t l, int32_t* info) {
   info[1] = Lv.ey;
   info[2] = Lv.dps;
   info[3] = (int32_t)Lv.n;
-  info[4] = Lv.col_off.empty() ? 0 : (int32_t)Lv.col_off.size() - 1;
+  info[4] = Lv.ncol;
   return BAMG_OK;
 }
 

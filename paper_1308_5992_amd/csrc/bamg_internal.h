@@ -71,9 +71,8 @@ void launch_eo_reduce(const Fine& f, const zd* b, zd* bh, int nrhs, hipStream_t 
 void launch_eo_reconstruct(const Fine& f, const zd* b, const zd* xe, zd* x, int nrhs, hipStream_t s);
 // y = Dhat x, or y = b - Dhat x if b != nullptr
 void launch_dhat(const Fine& f, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s);
-// one colour pass: sites[0..nsites) half-x indices of one colour
-void launch_kaczmarz_fine(const Fine& f, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
-                          hipStream_t s);
+// one colour pass over the nsites = N^2/32 sites of fine colour `colour`
+void launch_kaczmarz_fine(const Fine& f, int colour, int nsites, zd* x, const zd* b, int nrhs, hipStream_t s);
 // rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
 void launch_restrict_fine(const Fine& f, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s);
 void launch_prolong_fine(const Fine& f, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s);
@@ -90,7 +89,8 @@ struct Coarse {
   const zd* Kinv = nullptr;
 };
 void launch_coarse_apply(const Coarse& c, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s);
-void launch_kaczmarz_coarse(const Coarse& c, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
+// one colour pass; mode 8 / 16: the 8- or 16-colouring, mode 1: one site per colour
+void launch_kaczmarz_coarse(const Coarse& c, int colour, int mode, int nsites, zd* x, const zd* b, int nrhs,
                             hipStream_t s);
 void launch_kaczmarz_prep(const Coarse& c, zd* Kinv, hipStream_t s);
 // level l (ex x ey) -> l+1 (ex/2 x ey/2)

@@ -73,60 +73,104 @@ void launch_coarse_apply(const Coarse& c, const zd* x, zd* y, const zd* b, int n
 // One colour pass of the coarse Kaczmarz smoother.  The 16 rows d_i of a site
 // are projected one after the other (i = 0..15).  With G = A_a A_a^H the
 // sequence is exactly alpha = tril(G)^{-1} (b_a - A_a x), x += A_a^H alpha
-// (row i sees the updates of rows m < i through G_im), so a wave computes the
-// residual block, applies the precomputed Kinv = tril(G)^{-1} and scatters.
-// One wave per block; the scatter sums over rows go through LDS.
+// (row i sees the updates of rows m < i through G_im), so a work-group
+// computes the residual block, applies the precomputed Kinv = tril(G)^{-1}
+// and scatters.  128 threads per site: thread (i, q) holds row i, columns
+// 2q, 2q+1 of each of the 7 blocks; the column sums of the scatter go
+// through LDS.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_kaczmarz_coarse(Coarse c, const int* __restrict__ sites, int nsites,
-                                                        zd* __restrict__ x, const zd* __restrict__ b) {
-  __shared__ zd part[16][NOFF * 16];
+// t-th site of coarse colour c (see coarse_ncolours in the host code):
+// mode 8: (ax - 3 ay) = c mod 8; mode 16: (ax, ay) = (c mod 4, c / 4) mod 4;
+// mode 1: one site per colour.
+__device__ __forceinline__ int coarse_colour_site(int c, int mode, int t, int ex) {
+  if (mode == 8) {
+    const int per = ex >> 3, ay = t / per;
+    return ay * ex + 8 * (t - ay * per) + ((c + 3 * ay) & 7);
+  }
+  if (mode == 16) {
+    const int per = ex >> 2, r = t / per;
+    return (4 * r + (c >> 2)) * ex + 4 * (t - r * per) + (c & 3);
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(128) void k_kaczmarz_coarse(Coarse c, int colour, int mode, zd* __restrict__ x,
+                                                         const zd* __restrict__ b) {
+  constexpr int dxo[NOFF] = {0, 1, -1, 0, 0, 1, -1};
+  constexpr int dyo[NOFF] = {0, 0, 0, 1, -1, 1, -1};
+  __shared__ zd part[16][NOFF * 16 + 1];
+  __shared__ zd rsh[16];
+  __shared__ zd xsh[NOFF * 16];
   const int ns = c.ex * c.ey;
-  const int t = blockIdx.x;
-  if (t >= nsites) return;
-  const int lane = threadIdx.x, i = lane >> 2, q = lane & 3;
-  const int site = sites[t];
+  const int tid = threadIdx.x, i = tid >> 3, q = tid & 7;
+  const int site = coarse_colour_site(colour, mode, blockIdx.x, c.ex);
+  const int ax = site % c.ex, ay = site / c.ex;
   const size_t n = (size_t)ns * 16;
   zd* xv = x + blockIdx.y * n;
-  int nb[NOFF];
-  zd Dv[NOFF][4];
-  for (int o = 0; o < NOFF; ++o) {
-    nb[o] = neighbour_site(site, o, c.ex, c.ey);
-    const zd* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 4 * q;
-    for (int jj = 0; jj < 4; ++jj) Dv[o][jj] = Dr[jj];
-  }
-  // residual of the 16 rows
-  zd acc = {0, 0};
-  for (int o = 0; o < NOFF; ++o)
-    for (int jj = 0; jj < 4; ++jj) acc = acc + Dv[o][jj] * xv[nb[o] * 16 + 4 * q + jj];
-  acc = acc + shfl_xor_z(acc, 1);
-  acc = acc + shfl_xor_z(acc, 2);
+  // smoother row and right-hand side: independent of everything else
+  const zd* K = c.Kinv + ((size_t)site * 16 + i) * 16 + 2 * q;
+  const zd k0 = K[0], k1 = K[1];
   const zd bi = b ? b[blockIdx.y * n + site * 16 + i] : zd{0, 0};
-  const zd res = bi - acc;  // r_i in all four lanes of row i
-  // alpha_i = sum_{j <= i} Kinv[i][j] r_j
-  const zd* K = c.Kinv + ((size_t)site * 16 + i) * 16 + 4 * q;
-  zd al = {0, 0};
-  for (int jj = 0; jj < 4; ++jj) {
-    const zd rj = shfl_z(res, 4 * (4 * q + jj));
-    al = al + K[jj] * rj;
+  int nb[NOFF];
+  zd Dv[NOFF][2], xo[NOFF][2];
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    nb[o] = cwrap(ay + dyo[o], c.ey) * c.ex + cwrap(ax + dxo[o], c.ex);
+    const zd* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 2 * q;
+    Dv[o][0] = Dr[0];
+    Dv[o][1] = Dr[1];
+    const zd* xp = xv + nb[o] * 16 + 2 * q;
+    xo[o][0] = xp[0];
+    xo[o][1] = xp[1];
   }
+  zd acc[NOFF];
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) acc[o] = Dv[o][0] * xo[o][0] + Dv[o][1] * xo[o][1];
+  if (i == 0) {
+#pragma unroll
+    for (int o = 0; o < NOFF; ++o) {
+      xsh[o * 16 + 2 * q] = xo[o][0];
+      xsh[o * 16 + 2 * q + 1] = xo[o][1];
+    }
+  }
+  zd r = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
+  r = r + shfl_xor_z(r, 1);
+  r = r + shfl_xor_z(r, 2);
+  r = r + shfl_xor_z(r, 4);
+  if (q == 0) rsh[i] = bi - r;
+  __syncthreads();
+  // alpha_i = sum_{j <= i} Kinv[i][j] r_j
+  zd al = k0 * rsh[2 * q] + k1 * rsh[2 * q + 1];
   al = al + shfl_xor_z(al, 1);
   al = al + shfl_xor_z(al, 2);
-  // x_col += sum_i conj(D[i][col]) alpha_i
-  for (int o = 0; o < NOFF; ++o)
-    for (int jj = 0; jj < 4; ++jj) part[i][o * 16 + 4 * q + jj] = cjmul(Dv[o][jj], al);
+  al = al + shfl_xor_z(al, 4);
+  // x_col += sum_i conj(D[i][col]) alpha_i; thread (i < 14, q) finishes
+  // column j = 2q + (i & 1) of offset o = i / 2 from the value it already holds
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    part[i][o * 16 + 2 * q] = cjmul(Dv[o][0], al);
+    part[i][o * 16 + 2 * q + 1] = cjmul(Dv[o][1], al);
+  }
   __syncthreads();
-  for (int col = lane; col < NOFF * 16; col += 64) {
-    zd sum = {0, 0};
-    for (int r = 0; r < 16; ++r) sum = sum + part[r][col];
-    const int o = col >> 4, j = col & 15;
-    zd* xp = xv + nb[o] * 16 + j;
-    *xp = *xp + sum;
+  if (i < 2 * NOFF) {
+    const int o = i >> 1, h = i & 1, col = o * 16 + 2 * q + h;
+    zd s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+    for (int rr = 0; rr < 16; rr += 2) {
+      s0 = s0 + part[rr][col];
+      s1 = s1 + part[rr + 1][col];
+    }
+    // offsets packed as 4-bit fields (+1): (0,0) (+1,0) (-1,0) (0,+1) (0,-1) (+1,+1) (-1,-1)
+    const int dx = (int)((0x0211021u >> (4 * o)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * o)) & 15u) - 1;
+    const int nbo = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
+    const zd xold = xsh[col];
+    xv[nbo * 16 + 2 * q + h] = xold + (s0 + s1);
   }
 }
 
-void launch_kaczmarz_coarse(const Coarse& c, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
+void launch_kaczmarz_coarse(const Coarse& c, int colour, int mode, int nsites, zd* x, const zd* b, int nrhs,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_kaczmarz_coarse, dim3(nsites, nrhs), dim3(64), 0, s, c, sites, nsites, x, b);
+  hipLaunchKernelGGL(k_kaczmarz_coarse, dim3(nsites, nrhs), dim3(128), 0, s, c, colour, mode, x, b);
 }
 
 // ---------------------------------------------------------------------------

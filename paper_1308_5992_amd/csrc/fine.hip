@@ -269,44 +269,121 @@ __device__ void dhat_rows(const Fine& f, int xh, int y, zd e[9][2][2], int jn[9]
 // projects its spin-0 row, then its spin-1 row:
 //   alpha = (b_r - d_r . x) / ||d_r||^2,  x_j += alpha conj(d_rj).
 // Sites of one colour touch disjoint sets of unknowns.
+//
+// A group of 16 lanes owns one site; lane n < 9 owns stencil slot n (the even
+// site at displacement (SLOT_DX2, SLOT_DY2 field n) - 2): it builds the 2x2 block of Dhat
+// coupling the site to slot n from the one or two two-hop paths that reach
+// it, and holds the two unknowns of that slot.  With G10 = d_1 d_0^H the two
+// sequential projections are
+//   alpha_0 = (b_0 - d_0 x) / nu_0,
+//   alpha_1 = (b_1 - d_1 x - G10 alpha_0) / nu_1,
+// so one group reduction of (d_0 x, d_1 x, nu_0, nu_1, G10) suffices.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_kaczmarz_fine(Fine f, const int* __restrict__ sites, int nsites,
-                                                      zd* __restrict__ x, const zd* __restrict__ b) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nsites) return;
+// Per-slot tables packed in 4-bit fields so that a lane-dependent lookup is
+// pure register arithmetic: displacement + 2 of slot n, and d + 1 of the
+// first / second hop of the (up to two) two-hop paths reaching slot n.
+constexpr uint64_t SLOT_DX2 = 0x113322042ull, SLOT_DY2 = 0x131304222ull;
+constexpr uint64_t PATH_A1 = 0x221143210ull, PATH_B1 = 0x434300000ull;  // path 0 / 1, first hop
+constexpr uint64_t PATH_A2 = 0x434343210ull, PATH_B2 = 0x221100000ull;  // path 0 / 1, second hop
+__device__ __forceinline__ int nib(uint64_t c, int n) { return (int)((c >> (4 * n)) & 15ull); }
+
+__device__ __forceinline__ zd grp16_sum(zd v) {
+  for (int off = 8; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+// 2x2 block of Dhat between even site (x, y) (half-x index i) and its slot n
+// (half-x index jn): -kappa^2/4 sum over paths of Pi_{d1} Pi_{d2} u1 u2, plus I
+// on slot 0.  Pi_d = 2 P = [[1, a], [conj(a), 1]] with a = -1, 1, -i, i for
+// d = +x, -x, +y, -y, so Pi_1 Pi_2 = [[1 + a1 conj(a2), a1 + a2],
+// [conj(a1 + a2), 1 + conj(a1) a2]]; links are selected without branches.
+__device__ __forceinline__ zd hop_phase(int d) {
+  const double sg = (d & 1) ? 1.0 : -1.0;
+  return (d < 2) ? zd{sg, 0.0} : zd{0.0, sg};
+}
+
+__device__ __forceinline__ void dhat_slot_block(const Fine& f, int x, int y, int i, int n, int jn, zd B[2][2]) {
+  const int N = f.N, NH = f.NH;
+  zd b00 = {0, 0}, b01 = {0, 0}, b10 = {0, 0}, b11 = {0, 0};
+#pragma unroll
+  for (int pth = 0; pth < 2; ++pth) {
+    const int d1 = nib(pth ? PATH_B1 : PATH_A1, n) - 1, d2 = nib(pth ? PATH_B2 : PATH_A2, n) - 1;
+    if (d1 >= 0) {
+      const int dx1 = d1 == 0 ? 1 : (d1 == 1 ? -1 : 0), dy1 = d1 == 2 ? 1 : (d1 == 3 ? -1 : 0);
+      const int w = hidx(x + dx1, y + dy1, N, NH);
+      const bool bk1 = d1 & 1, bk2 = d2 & 1;
+      // first hop: forward link at i (even) or conj of the link at w (odd);
+      // second hop: forward link at w (odd) or conj of the link at jn (even)
+      const zd* p1 = bk1 ? f.Uo + 2 * w + (d1 >> 1) : f.Ue + 2 * i + (d1 >> 1);
+      const zd* p2 = bk2 ? f.Ue + 2 * jn + (d2 >> 1) : f.Uo + 2 * w + (d2 >> 1);
+      zd l1 = *p1, l2 = *p2;
+      l1.y = bk1 ? -l1.y : l1.y;
+      l2.y = bk2 ? -l2.y : l2.y;
+      const zd u = l1 * l2;
+      const zd a1 = hop_phase(d1), a2 = hop_phase(d2);
+      const zd s12 = a1 + a2;
+      b00 = b00 + (zd{1, 0} + a1 * conj(a2)) * u;
+      b01 = b01 + s12 * u;
+      b10 = b10 + conj(s12) * u;
+      b11 = b11 + (zd{1, 0} + conj(a1) * a2) * u;
+    }
+  }
+  const double k2q = 0.25 * f.kappa2;
+  const double one = (n == 0) ? 1.0 : 0.0;
+  B[0][0] = zd{one, 0} - k2q * b00;
+  B[0][1] = -(k2q * b01);
+  B[1][0] = -(k2q * b10);
+  B[1][1] = zd{one, 0} - k2q * b11;
+}
+
+// t-th even site of fine colour c = 4a + b (a = (x+y)/2 mod 4, b = (x-y)/2 mod 4):
+// rows y = a - b (mod 4), and in such a row x = 2a - y (mod 8); N^2/32 sites.
+__device__ __forceinline__ void fine_colour_site(int c, int t, int N, int& x, int& y) {
+  const int a = c >> 2, b = c & 3, per = N >> 3;
+  const int r = t / per, k = t - r * per;
+  y = 4 * r + ((a - b) & 3);
+  x = 8 * k + ((2 * a - y) & 7);
+}
+
+__global__ __launch_bounds__(64) void k_kaczmarz_fine(Fine f, int colour, int nsites, zd* __restrict__ x,
+                                                      const zd* __restrict__ b) {
+  const int lane = threadIdx.x & 15;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 4);
+  if (t >= nsites) return;  // whole 16-lane groups leave together
   const size_t n = (size_t)f.N * f.NH * 2;
   zd* xv = x + blockIdx.y * n;
-  const int i = sites[t];
-  const int y = i / f.NH, xh = i - y * f.NH;
-  zd e[9][2][2];
-  int jn[9];
-  dhat_rows(f, xh, y, e, jn);
-  zd xs[9][2];
-  for (int q = 0; q < 9; ++q) {
-    xs[q][0] = xv[2 * jn[q]];
-    xs[q][1] = xv[2 * jn[q] + 1];
+  int px, y;
+  fine_colour_site(colour, t, f.N, px, y);
+  const int i = y * f.NH + (px >> 1);
+  const bool act = lane < 9;
+  const int slot = act ? lane : 0;
+  const int jn = hidx(px + nib(SLOT_DX2, slot) - 2, y + nib(SLOT_DY2, slot) - 2, f.N, f.NH);
+  zd x0 = {0, 0}, x1 = {0, 0};
+  if (act) {
+    x0 = xv[2 * jn];
+    x1 = xv[2 * jn + 1];
   }
-  for (int s = 0; s < 2; ++s) {
-    double nu = 0;
-    zd res = b ? b[blockIdx.y * n + 2 * i + s] : zd{0, 0};
-    for (int q = 0; q < 9; ++q)
-      for (int u = 0; u < 2; ++u) {
-        nu += norm2(e[q][s][u]);
-        res = res - e[q][s][u] * xs[q][u];
-      }
-    const zd alpha = cdiv_real(res, nu);
-    for (int q = 0; q < 9; ++q)
-      for (int u = 0; u < 2; ++u) xs[q][u] = xs[q][u] + cjmul(e[q][s][u], alpha);
-  }
-  for (int q = 0; q < 9; ++q) {
-    xv[2 * jn[q]] = xs[q][0];
-    xv[2 * jn[q] + 1] = xs[q][1];
+  const zd b0 = b ? b[blockIdx.y * n + 2 * i] : zd{0, 0};
+  const zd b1 = b ? b[blockIdx.y * n + 2 * i + 1] : zd{0, 0};
+  zd B[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+  if (act) dhat_slot_block(f, px, y, i, slot, jn, B);
+  const zd r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
+  const zd r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
+  const zd nu = grp16_sum(zd{norm2(B[0][0]) + norm2(B[0][1]), norm2(B[1][0]) + norm2(B[1][1])});
+  const zd g10 = grp16_sum(cjmul(B[0][0], B[1][0]) + cjmul(B[0][1], B[1][1]));
+  const zd a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : zd{0, 0};
+  const zd a1 = nu.y > 0 ? cdiv_real(b1 - r1 - g10 * a0, nu.y) : zd{0, 0};
+  if (act) {
+    xv[2 * jn] = x0 + cjmul(B[0][0], a0) + cjmul(B[1][0], a1);
+    xv[2 * jn + 1] = x1 + cjmul(B[0][1], a0) + cjmul(B[1][1], a1);
   }
 }
 
-void launch_kaczmarz_fine(const Fine& f, const int* sites, int nsites, zd* x, const zd* b, int nrhs,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_kaczmarz_fine, dim3((nsites + 63) / 64, nrhs), dim3(64), 0, s, f, sites, nsites, x, b);
+void launch_kaczmarz_fine(const Fine& f, int colour, int nsites, zd* x, const zd* b, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_kaczmarz_fine, dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b);
 }
 
 // ---------------------------------------------------------------------------
