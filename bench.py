@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dhat", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--batch", default="8,32", help="right-hand sides per batched solve (comma list, '' for none)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -146,6 +148,25 @@ def main():
         "setup_s": t_setup,
         "gauge_gen_s": t_gauge,
     }
+
+    # ---- batched solves: R right-hand sides per call, lockstep FGMRES
+    batched = []
+    for R in [int(v) for v in args.batch.split(",") if v.strip()]:
+        B = torch.from_numpy(inputs.gaussian((R, 2 * N * N), w["rhs_seed"] + 1000)).to("cuda:0")
+        X = torch.zeros_like(B)
+        bamg.bamg_solve_batch(h, B, X, R, args.tol)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            st, infs = bamg.bamg_solve_batch(h, B, X, R, args.tol)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - tb0) / args.batch_steps
+        batched.append({"nrhs": R, "solves_per_s": R / tb, "ms_per_batch": 1e3 * tb,
+                        "max_iters": max(i["iters"] for i in infs),
+                        "converged": all(i["relres_reduced"] <= args.tol for i in infs)})
+        del B, X
+    if batched:
+        out["batched"] = batched
 
     # ---- Dhat ("D_oe") bandwidth: cache-resident, batched, cache-busting
     if not args.no_dhat:

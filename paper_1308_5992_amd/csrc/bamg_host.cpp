@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/bamg.h"
@@ -109,22 +110,49 @@ struct bamg_hierarchy {
   int* gjperm = nullptr;
   int* dflag = nullptr;   // device flag
   int* hflag = nullptr;   // pinned host mirror
-  // Krylov workspace
-  int kdim = 0;
+  // Krylov workspace for kcap right-hand sides (basis layout [j][r][n])
+  int kdim = 0, kcap = 0;
   zd *V = nullptr, *Z = nullptr, *w = nullptr, *bh = nullptr, *xe = nullptr, *rr = nullptr;
-  zd *partial = nullptr, *hdev = nullptr;
-  zd* hhost = nullptr;  // pinned
+  zd *partial = nullptr, *hdev = nullptr;  // reduction partials; [3][kcap][64] results
+  zd* hhost = nullptr;                     // pinned mirror of hdev
+  double *scal_dev = nullptr, *scal_host = nullptr;  // per right-hand side scale factors
+  zd *ycoef_dev = nullptr, *ycoef_host = nullptr;    // per right-hand side update coefficients
   zd* tvsave = nullptr; // level-0 test vectors after the last setup pass
 
-  void ensure_krylov() {
-    if (V) return;
+  void free_krylov() {
+    dfree(V); dfree(Z); dfree(w); dfree(bh); dfree(xe); dfree(rr); dfree(partial); dfree(hdev);
+    dfree(scal_dev); dfree(ycoef_dev);
+    if (hhost) (void)hipHostFree(hhost);
+    if (scal_host) (void)hipHostFree(scal_host);
+    if (ycoef_host) (void)hipHostFree(ycoef_host);
+    V = Z = w = bh = xe = rr = partial = hdev = hhost = ycoef_dev = ycoef_host = nullptr;
+    scal_dev = scal_host = nullptr;
+    kcap = 0;
+  }
+  // reduction scratch for at least R right-hand sides (always), Krylov bases if `bases`
+  void ensure_krylov(int R, bool bases) {
     const size_t n0 = lv[0].n;
-    V = dalloc<zd>(n0 * (kdim + 1));
-    Z = dalloc<zd>(n0 * kdim);
-    w = dalloc<zd>(n0);
-    bh = dalloc<zd>(n0);
-    xe = dalloc<zd>(n0);
-    rr = dalloc<zd>(n0);
+    if (R > kcap || (bases && !V)) {
+      const int cap2 = std::max(R, kcap);
+      const bool had_bases = V != nullptr || bases;
+      free_krylov();
+      kcap = cap2;
+      partial = dalloc<zd>((size_t)blas_nblocks(n0) * 64 * kcap);
+      hdev = dalloc<zd>((size_t)3 * 64 * kcap);
+      HIPCHK(hipHostMalloc((void**)&hhost, (size_t)3 * 64 * kcap * sizeof(zd)));
+      scal_dev = dalloc<double>(kcap);
+      HIPCHK(hipHostMalloc((void**)&scal_host, (size_t)kcap * sizeof(double)));
+      ycoef_dev = dalloc<zd>((size_t)64 * kcap);
+      HIPCHK(hipHostMalloc((void**)&ycoef_host, (size_t)64 * kcap * sizeof(zd)));
+      if (had_bases) {
+        V = dalloc<zd>(n0 * (kdim + 1) * kcap);
+        Z = dalloc<zd>(n0 * kdim * kcap);
+        w = dalloc<zd>(n0 * kcap);
+        bh = dalloc<zd>(n0 * kcap);
+        xe = dalloc<zd>(n0 * kcap);
+        rr = dalloc<zd>(n0 * kcap);
+      }
+    }
   }
 
   ~bamg_hierarchy() {
@@ -134,8 +162,7 @@ struct bamg_hierarchy {
     }
     dfree(Ue); dfree(Uo); dfree(gjcol); dfree(gjperm); dfree(dflag);
     if (hflag) (void)hipHostFree(hflag);
-    dfree(V); dfree(Z); dfree(w); dfree(bh); dfree(xe); dfree(rr); dfree(partial); dfree(hdev);
-    if (hhost) (void)hipHostFree(hhost);
+    free_krylov();
     dfree(tvsave);
   }
 
@@ -424,9 +451,7 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
     h->dflag = dalloc<int>(1);
     HIPCHK(hipHostMalloc((void**)&h->hflag, sizeof(int)));
     h->kdim = p->restart;
-    h->partial = dalloc<zd>((size_t)blas_nblocks(n0) * 64);
-    h->hdev = dalloc<zd>(256);
-    HIPCHK(hipHostMalloc((void**)&h->hhost, 256 * sizeof(zd)));
+    h->ensure_krylov(1, false);
     if (mg) {
       h->gjcol = dalloc<zd>(h->lv.back().n);
       h->gjperm = dalloc<int>(h->lv.back().n);
@@ -603,105 +628,179 @@ int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void* out, void* strea
 }
 
 // Flexible GMRES(restart), right preconditioned by one cycle (Sec. 4), on the
-// reduced system; classical Gram-Schmidt applied twice; Givens rotations;
-// true residual recomputed at every restart.
-static int fgmres(bamg_hierarchy* h, double tol, bamg_solve_info* info) {
+// reduced systems of R right-hand sides in lockstep: every right-hand side
+// has its own Arnoldi basis, Hessenberg matrix and Givens rotations; the
+// cycle, the operator and the Gram-Schmidt reductions run batched.  Classical
+// Gram-Schmidt applied twice; true residual recomputed at every restart.  A
+// right-hand side that stops early keeps zero basis vectors until the others
+// finish, so its arithmetic is that of a solve on its own.
+// Input: h->bh [R][n]; output: h->xe [R][n], infos[R].
+static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* infos) {
+  typedef std::complex<double> C;
   const size_t n = h->lv[0].n;
   const int m = h->kdim;
   hipStream_t s = h->s;
   zd* hh = h->hhost;
-  // ||bhat||
-  launch_norms(h->bh, n, 1, n, h->partial, h->hdev, s);
-  HIPCHK(hipMemcpyAsync(hh, h->hdev, sizeof(zd), hipMemcpyDeviceToHost, s));
+  zd* h1 = h->hdev;
+  zd* h2 = h->hdev + 64 * R;
+  zd* hn2 = h->hdev + 128 * R;
+  // ||bhat_r||
+  launch_norms(h->bh, n, R, n, h->partial, hn2, s);
+  HIPCHK(hipMemcpyAsync(hh, hn2, R * sizeof(zd), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const double bnorm = std::sqrt(hh[0].x);
-  launch_fill_zero(h->xe, n, s);
-  info->iters = 0;
-  info->restarts = 0;
-  info->relres_reduced = 0;
-  if (bnorm == 0.0) return BAMG_OK;
-  launch_copy(h->bh, h->rr, n, s);
-  int it = 0, cycles = 0;
-  double relres = 1.0;
-  std::vector<std::complex<double>> H((size_t)(m + 1) * m), g(m + 1), sn(m);
-  std::vector<double> cs(m);
-  while (true) {
-    launch_norms(h->rr, n, 1, n, h->partial, h->hdev, s);
-    HIPCHK(hipMemcpyAsync(hh, h->hdev, sizeof(zd), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double beta = std::sqrt(hh[0].x);
-    relres = beta / bnorm;
-    if (!(relres > tol) || it >= h->p.max_iter) break;
-    launch_scale_copy(h->rr, h->V, n, 1.0 / beta, s);
-    std::fill(g.begin(), g.end(), 0.0);
-    std::fill(H.begin(), H.end(), 0.0);
-    g[0] = beta;
-    int jend = 0;
-    for (int j = 0; j < m; ++j) {
-      zd* vj = h->V + (size_t)j * n;
-      zd* zj = h->Z + (size_t)j * n;
-      launch_fill_zero(zj, n, s);
-      h->cycle(0, vj, zj, 1);
-      h->apply(0, zj, h->w, nullptr, 1);
-      // CGS2: h1 = V^H w; w -= V h1; h2 = V^H w; w -= V h2; ||w||
-      launch_multidot(h->V, n, j + 1, h->w, n, h->partial, h->hdev, s);
-      launch_multiaxpy(h->V, n, j + 1, h->hdev, -1.0, h->w, n, s);
-      launch_multidot(h->V, n, j + 1, h->w, n, h->partial, h->hdev + 64, s);
-      launch_multiaxpy(h->V, n, j + 1, h->hdev + 64, -1.0, h->w, n, s);
-      launch_norms(h->w, n, 1, n, h->partial, h->hdev + 128, s);
-      check_launch();
-      HIPCHK(hipMemcpyAsync(hh, h->hdev, 129 * sizeof(zd), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int q = 0; q <= j; ++q)
-        H[(size_t)q * m + j] = std::complex<double>(hh[q].x, hh[q].y) + std::complex<double>(hh[64 + q].x, hh[64 + q].y);
-      const double hn = std::sqrt(hh[128].x);
-      if (!std::isfinite(hn)) throw HipFail("non-finite Arnoldi vector");
-      for (int q = 0; q < j; ++q) {
-        const std::complex<double> a = H[(size_t)q * m + j], b = H[(size_t)(q + 1) * m + j];
-        H[(size_t)q * m + j] = cs[q] * a + sn[q] * b;
-        H[(size_t)(q + 1) * m + j] = -std::conj(sn[q]) * a + cs[q] * b;
-      }
-      const std::complex<double> a = H[(size_t)j * m + j];
-      const double aa = std::abs(a);
-      double c;
-      std::complex<double> sv;
-      if (hn == 0.0) { c = 1.0; sv = 0.0; }
-      else if (aa == 0.0) { c = 0.0; sv = 1.0; }
-      else {
-        const double t = std::sqrt(aa * aa + hn * hn);
-        c = aa / t;
-        sv = (a / aa) * (hn / t);
-      }
-      cs[j] = c;
-      sn[j] = sv;
-      H[(size_t)j * m + j] = c * a + sv * hn;
-      g[j + 1] = -std::conj(sv) * g[j];
-      g[j] = c * g[j];
-      ++it;
-      jend = j + 1;
-      if (hn != 0.0) launch_scale_copy(h->w, h->V + (size_t)(j + 1) * n, n, 1.0 / hn, s);
-      if (std::abs(g[j + 1]) <= tol * bnorm || it >= h->p.max_iter || hn == 0.0) break;
-    }
-    std::vector<std::complex<double>> y(jend);
-    for (int i = jend - 1; i >= 0; --i) {
-      std::complex<double> sum = g[i];
-      for (int q = i + 1; q < jend; ++q) sum -= H[(size_t)i * m + q] * y[q];
-      y[i] = sum / H[(size_t)i * m + i];
-    }
-    std::vector<double> coef(2 * jend);
-    for (int q = 0; q < jend; ++q) {
-      coef[2 * q] = y[q].real();
-      coef[2 * q + 1] = y[q].imag();
-    }
-    launch_lincomb_host(h->Z, n, jend, coef.data(), h->xe, n, s);
-    h->apply(0, h->xe, h->rr, h->bh, 1);  // true residual
-    ++cycles;
+  std::vector<double> bnorm(R), relres(R, 1.0), beta(R);
+  std::vector<int> it(R, 0), cycles(R, 0), jend(R, 0);
+  std::vector<char> done(R, 0), arn(R, 0);
+  for (int r = 0; r < R; ++r) {
+    bnorm[r] = std::sqrt(hh[r].x);
+    if (bnorm[r] == 0.0) { done[r] = 1; relres[r] = 0.0; }
   }
-  info->iters = it;
-  info->restarts = cycles > 0 ? cycles - 1 : 0;
-  info->relres_reduced = relres;
-  info->rho_est = it > 0 ? std::pow(relres, 1.0 / it) : 0.0;
-  return relres <= tol ? BAMG_OK : BAMG_NOT_CONVERGED;
+  launch_fill_zero(h->xe, n * R, s);
+  launch_copy(h->bh, h->rr, n * R, s);
+  std::vector<C> H((size_t)R * (m + 1) * m), g((size_t)R * (m + 1)), sn((size_t)R * m);
+  std::vector<double> cs((size_t)R * m);
+  while (true) {
+    launch_norms(h->rr, n, R, n, h->partial, hn2, s);
+    HIPCHK(hipMemcpyAsync(hh, hn2, R * sizeof(zd), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool any = false;
+    for (int r = 0; r < R; ++r) {
+      arn[r] = 0;
+      if (done[r] && bnorm[r] == 0.0) continue;
+      beta[r] = std::sqrt(hh[r].x);
+      relres[r] = beta[r] / bnorm[r];
+      if (!(relres[r] > tol) || it[r] >= h->p.max_iter) done[r] = 1;
+      if (!done[r]) {
+        arn[r] = 1;
+        any = true;
+        ++cycles[r];
+      }
+      jend[r] = 0;
+      h->scal_host[r] = arn[r] ? 1.0 / beta[r] : 0.0;
+      std::fill(g.begin() + (size_t)r * (m + 1), g.begin() + (size_t)(r + 1) * (m + 1), C(0.0));
+      std::fill(H.begin() + (size_t)r * (m + 1) * m, H.begin() + (size_t)(r + 1) * (m + 1) * m, C(0.0));
+      g[(size_t)r * (m + 1)] = arn[r] ? beta[r] : 0.0;
+    }
+    if (!any) break;
+    HIPCHK(hipMemcpyAsync(h->scal_dev, h->scal_host, R * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_bscale(h->rr, h->V, n, R, h->scal_dev, s);
+    int jmax = 0;
+    for (int j = 0; j < m; ++j) {
+      zd* vj = h->V + (size_t)j * R * n;
+      zd* zj = h->Z + (size_t)j * R * n;
+      launch_fill_zero(zj, n * R, s);
+      h->cycle(0, vj, zj, R);
+      h->apply(0, zj, h->w, nullptr, R);
+      launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, s);
+      launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, s);
+      launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, s);
+      launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, s);
+      launch_norms(h->w, n, R, n, h->partial, hn2, s);
+      check_launch();
+      HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      jmax = j + 1;
+      bool still = false;
+      for (int r = 0; r < R; ++r) {
+        h->scal_host[r] = 0.0;
+        if (!arn[r]) continue;
+        C* Hr = &H[(size_t)r * (m + 1) * m];
+        C* gr = &g[(size_t)r * (m + 1)];
+        C* snr = &sn[(size_t)r * m];
+        double* csr = &cs[(size_t)r * m];
+        for (int q = 0; q <= j; ++q)
+          Hr[(size_t)q * m + j] = C(hh[r * 64 + q].x, hh[r * 64 + q].y) + C(hh[64 * R + r * 64 + q].x, hh[64 * R + r * 64 + q].y);
+        const double hn = std::sqrt(hh[128 * R + r].x);
+        if (!std::isfinite(hn)) throw HipFail("non-finite Arnoldi vector");
+        for (int q = 0; q < j; ++q) {
+          const C a = Hr[(size_t)q * m + j], bq = Hr[(size_t)(q + 1) * m + j];
+          Hr[(size_t)q * m + j] = csr[q] * a + snr[q] * bq;
+          Hr[(size_t)(q + 1) * m + j] = -std::conj(snr[q]) * a + csr[q] * bq;
+        }
+        const C a = Hr[(size_t)j * m + j];
+        const double aa = std::abs(a);
+        double c;
+        C sv;
+        if (hn == 0.0) { c = 1.0; sv = 0.0; }
+        else if (aa == 0.0) { c = 0.0; sv = 1.0; }
+        else {
+          const double t = std::sqrt(aa * aa + hn * hn);
+          c = aa / t;
+          sv = (a / aa) * (hn / t);
+        }
+        csr[j] = c;
+        snr[j] = sv;
+        Hr[(size_t)j * m + j] = c * a + sv * hn;
+        gr[j + 1] = -std::conj(sv) * gr[j];
+        gr[j] = c * gr[j];
+        ++it[r];
+        jend[r] = j + 1;
+        if (std::abs(gr[j + 1]) <= tol * bnorm[r] || it[r] >= h->p.max_iter || hn == 0.0) {
+          arn[r] = 0;
+        } else {
+          h->scal_host[r] = 1.0 / hn;
+          still = true;
+        }
+      }
+      if (!still) break;
+      HIPCHK(hipMemcpyAsync(h->scal_dev, h->scal_host, R * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_bscale(h->w, h->V + (size_t)(j + 1) * R * n, n, R, h->scal_dev, s);
+    }
+    // y_r = H_r^{-1} g_r (upper triangular), x_r += Z_r y_r, true residual
+    for (int r = 0; r < R; ++r) {
+      zd* yc = h->ycoef_host + (size_t)r * 64;
+      for (int q = 0; q < 64; ++q) yc[q] = zd{0, 0};
+      const C* Hr = &H[(size_t)r * (m + 1) * m];
+      const C* gr = &g[(size_t)r * (m + 1)];
+      std::vector<C> y(jend[r]);
+      for (int i = jend[r] - 1; i >= 0; --i) {
+        C sum = gr[i];
+        for (int q = i + 1; q < jend[r]; ++q) sum -= Hr[(size_t)i * m + q] * y[q];
+        y[i] = sum / Hr[(size_t)i * m + i];
+      }
+      for (int q = 0; q < jend[r]; ++q) yc[q] = zd{y[q].real(), y[q].imag()};
+    }
+    HIPCHK(hipMemcpyAsync(h->ycoef_dev, h->ycoef_host, (size_t)64 * R * sizeof(zd), hipMemcpyHostToDevice, s));
+    launch_blincomb(h->Z, jmax, h->ycoef_dev, h->xe, n, R, s);
+    h->apply(0, h->xe, h->rr, h->bh, R);
+  }
+  int worst = BAMG_OK;
+  for (int r = 0; r < R; ++r) {
+    infos[r].iters = it[r];
+    infos[r].restarts = cycles[r] > 0 ? cycles[r] - 1 : 0;
+    infos[r].relres_reduced = relres[r];
+    infos[r].relres_full = 0.0;
+    infos[r].rho_est = it[r] > 0 ? std::pow(relres[r], 1.0 / it[r]) : 0.0;
+    if (relres[r] > tol) worst = BAMG_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+static int solve_common(bamg_hierarchy* h, const void* B, void* X, int R, double tol, bamg_solve_info* infos) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int st;
+  try {
+    h->ensure_krylov(R, true);
+    h->ensure_cap(R);
+    const size_t n = h->lv[0].n;
+    launch_eo_reduce(h->f, (const zd*)B, h->bh, R, h->s);
+    HIPCHK(hipMemsetAsync(h->dflag, 0, sizeof(int), h->s));
+    launch_check_finite(h->bh, n * R, h->dflag, h->s);
+    check_launch();
+    HIPCHK(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    if (*h->hflag) return fail(BAMG_EINVAL, "right-hand side is not finite");
+    st = fgmres_batch(h, R, tol, infos);
+    launch_eo_reconstruct(h->f, (const zd*)B, h->xe, (zd*)X, R, h->s);
+    check_launch();
+    HIPCHK(hipStreamSynchronize(h->s));
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < R; ++r) infos[r].t_solve_ms = ms;
+  if (st == BAMG_NOT_CONVERGED) g_err = "not converged within max_iter";
+  return st;
 }
 
 int bamg_solve(bamg_hierarchy* h, const void* b, void* x, double tol, bamg_solve_info* info) {
@@ -710,39 +809,20 @@ int bamg_solve(bamg_hierarchy* h, const void* b, void* x, double tol, bamg_solve
   bamg_solve_info tmp{};
   if (!info) info = &tmp;
   *info = bamg_solve_info{};
-  const auto t0 = std::chrono::steady_clock::now();
-  int st;
-  try {
-    h->ensure_krylov();
-    launch_eo_reduce(h->f, (const zd*)b, h->bh, 1, h->s);
-    HIPCHK(hipMemsetAsync(h->dflag, 0, sizeof(int), h->s));
-    launch_check_finite(h->bh, h->lv[0].n, h->dflag, h->s);
-    check_launch();
-    HIPCHK(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->s));
-    HIPCHK(hipStreamSynchronize(h->s));
-    if (*h->hflag) return fail(BAMG_EINVAL, "right-hand side is not finite");
-    st = fgmres(h, tol, info);
-    launch_eo_reconstruct(h->f, (const zd*)b, h->xe, (zd*)x, 1, h->s);
-    check_launch();
-    HIPCHK(hipStreamSynchronize(h->s));
-  } catch (const HipFail& e) {
-    return fail(BAMG_EDEVICE, e.msg);
-  }
-  info->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  if (st == BAMG_NOT_CONVERGED) g_err = "not converged within max_iter";
-  return st;
+  return solve_common(h, b, x, 1, tol, info);
 }
 
 int bamg_solve_batch(bamg_hierarchy* h, const void* B, void* X, int32_t nrhs, double tol, bamg_solve_info* infos) {
   if (!h || !B || !X || nrhs < 1) return fail(BAMG_EINVAL, "bad arguments");
-  const size_t nf = 2 * h->lv[0].n;
-  int worst = BAMG_OK;
-  for (int r = 0; r < nrhs; ++r) {
-    int st = bamg_solve(h, (const zd*)B + r * nf, (zd*)X + r * nf, tol, infos ? infos + r : nullptr);
-    if (st < 0) return st;
-    if (st > worst) worst = st;
+  if (!(tol > 0)) return fail(BAMG_EINVAL, "tol must be > 0");
+  if (nrhs > 4096) return fail(BAMG_EINVAL, "nrhs > 4096");
+  std::vector<bamg_solve_info> tmp;
+  if (!infos) {
+    tmp.resize(nrhs);
+    infos = tmp.data();
   }
-  return worst;
+  for (int r = 0; r < nrhs; ++r) infos[r] = bamg_solve_info{};
+  return solve_common(h, B, X, nrhs, tol, infos);
 }
 
 }  // extern "C"

@@ -123,16 +123,17 @@ void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* ou
 void launch_normalize(zd* X, size_t ldx, int nv, size_t n, const zd* nrm, hipStream_t s);
 // y = alpha x (alpha real, host scalar)
 void launch_scale_copy(const zd* x, zd* y, size_t n, double alpha, hipStream_t s);
-// y = x / h (h device complex scalar, real part used)
-void launch_div_by_dev(const zd* x, zd* y, size_t n, const zd* h, hipStream_t s);
-// y += sum_v X_v c_v (c host array copied by value, nv <= 64)
-void launch_lincomb_host(const zd* X, size_t ldx, int nv, const double* c_host, zd* y, size_t n,
-                         hipStream_t s);
 void launch_fill_zero(zd* x, size_t n, hipStream_t s);
 void launch_copy(const zd* x, zd* y, size_t n, hipStream_t s);
-// y = a - b
-void launch_sub(const zd* a, const zd* b, zd* y, size_t n, hipStream_t s);
 // flag[0] = 1 if any entry of x is not finite
 void launch_check_finite(const zd* x, size_t n, int* flag, hipStream_t s);
+// batched forms over R right-hand sides: basis vector v of right-hand side r
+// at X + (v*R + r)*n, w_r at W + r*n, coefficients at stride 64 per r
+void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s);
+void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, hipStream_t s);
+// y_r = c[r] x_r (c device, real)
+void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStream_t s);
+// x_r += sum_q Z_{q,r} y[r*64 + q]
+void launch_blincomb(const zd* Z, int nq, const zd* y, zd* x, size_t n, int R, hipStream_t s);
 
 }  // namespace bamg

@@ -107,33 +107,6 @@ void launch_scale_copy(const zd* x, zd* y, size_t n, double alpha, hipStream_t s
   hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, alpha);
 }
 
-__global__ void k_div_by_dev(const zd* __restrict__ x, zd* __restrict__ y, size_t n, const zd* __restrict__ h) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = cdiv_real(x[i], h[0].x);
-}
-
-void launch_div_by_dev(const zd* x, zd* y, size_t n, const zd* h, hipStream_t s) {
-  hipLaunchKernelGGL(k_div_by_dev, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, h);
-}
-
-struct Coef64 {
-  double c[128];
-};
-
-__global__ void k_lincomb(const zd* __restrict__ X, size_t ldx, int nv, Coef64 c, zd* __restrict__ y, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  zd acc = {0, 0};
-  for (int v = 0; v < nv; ++v) acc = acc + X[(size_t)v * ldx + i] * zd{c.c[2 * v], c.c[2 * v + 1]};
-  y[i] = y[i] + acc;
-}
-
-void launch_lincomb_host(const zd* X, size_t ldx, int nv, const double* c_host, zd* y, size_t n, hipStream_t s) {
-  Coef64 c;
-  for (int v = 0; v < 2 * nv && v < 128; ++v) c.c[v] = c_host[v];
-  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, ldx, nv, c, y, n);
-}
-
 __global__ void k_fill_zero(zd* __restrict__ x, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = zd{0, 0};
@@ -154,15 +127,6 @@ void launch_copy(const zd* x, zd* y, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
 }
 
-__global__ void k_sub(const zd* __restrict__ a, const zd* __restrict__ b, zd* __restrict__ y, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a[i] - b[i];
-}
-
-void launch_sub(const zd* a, const zd* b, zd* y, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, y, n);
-}
-
 __global__ void k_check_finite(const zd* __restrict__ x, size_t n, int* __restrict__ flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -173,6 +137,81 @@ __global__ void k_check_finite(const zd* __restrict__ x, size_t n, int* __restri
 
 void launch_check_finite(const zd* x, size_t n, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms for R right-hand sides.  Basis vector v of right-hand side r
+// lives at X + (v*R + r)*n (layout [v][r][n]); w_r at W + r*n; coefficient
+// arrays have a stride of 64 per right-hand side.  Each right-hand side uses
+// exactly the block decomposition of the single form, so its results do not
+// depend on R.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BT) void k_bdot_partial(const zd* __restrict__ X, int R, const zd* __restrict__ W,
+                                                     size_t n, zd* __restrict__ partial) {
+  __shared__ zd sh[BT];
+  const int b = blockIdx.x, v = blockIdx.y, r = blockIdx.z, nb = gridDim.x;
+  const size_t chunk = (n + nb - 1) / nb;
+  const size_t lo = (size_t)b * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
+  const zd* xv = X + ((size_t)v * R + r) * n;
+  const zd* wv = W + (size_t)r * n;
+  zd acc = {0, 0};
+  for (size_t i = lo + threadIdx.x; i < hi; i += BT) acc = acc + cjmul(xv[i], wv[i]);
+  const zd s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[((size_t)r * nb + b) * 64 + v] = s;
+}
+
+__global__ __launch_bounds__(BT) void k_breduce(const zd* __restrict__ partial, int nb, zd* __restrict__ out) {
+  __shared__ zd sh[BT];
+  const int v = blockIdx.x, r = blockIdx.y;
+  zd acc = {0, 0};
+  for (int b = threadIdx.x; b < nb; b += BT) acc = acc + partial[((size_t)r * nb + b) * 64 + v];
+  const zd s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[(size_t)r * 64 + v] = s;
+}
+
+void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s) {
+  const int nb = blas_nblocks(n);
+  hipLaunchKernelGGL(k_bdot_partial, dim3(nb, nv, R), dim3(BT), 0, s, X, R, W, n, partial);
+  hipLaunchKernelGGL(k_breduce, dim3(nv, R), dim3(BT), 0, s, partial, nb, out);
+}
+
+__global__ void k_bmultiaxpy(const zd* __restrict__ X, int nv, int R, const zd* __restrict__ h, double sign,
+                             zd* __restrict__ W, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  zd acc = {0, 0};
+  for (int v = 0; v < nv; ++v) acc = acc + X[((size_t)v * R + r) * n + i] * h[(size_t)r * 64 + v];
+  W[(size_t)r * n + i] = W[(size_t)r * n + i] + sign * acc;
+}
+
+void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, hipStream_t s) {
+  hipLaunchKernelGGL(k_bmultiaxpy, dim3((unsigned)((n + 255) / 256), R), dim3(256), 0, s, X, nv, R, h, sign, W, n);
+}
+
+__global__ void k_bscale(const zd* __restrict__ x, zd* __restrict__ y, size_t n, const double* __restrict__ c) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i < n) y[(size_t)r * n + i] = c[r] * x[(size_t)r * n + i];
+}
+
+void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_bscale, dim3((unsigned)((n + 255) / 256), R), dim3(256), 0, s, x, y, n, c);
+}
+
+__global__ void k_blincomb(const zd* __restrict__ Z, int nq, int R, const zd* __restrict__ y, zd* __restrict__ x,
+                           size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  zd acc = {0, 0};
+  for (int q = 0; q < nq; ++q) acc = acc + Z[((size_t)q * R + r) * n + i] * y[(size_t)r * 64 + q];
+  x[(size_t)r * n + i] = x[(size_t)r * n + i] + acc;
+}
+
+void launch_blincomb(const zd* Z, int nq, const zd* y, zd* x, size_t n, int R, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_blincomb, dim3((unsigned)((n + 255) / 256), R), dim3(256), 0, s, Z, nq, R, y, x, n);
 }
 
 }  // namespace bamg

@@ -287,3 +287,24 @@ def test_not_converged_status(bamg):
     st, info = bamg.bamg_solve(h, dev(b), x, 1e-14)
     assert st == bamg.BAMG_NOT_CONVERGED and info["iters"] == 1
     assert np.isfinite(host(x)).all()
+
+
+def test_batch_equals_single_solves(bamg, c1):
+    """Each right-hand side of a batched solve gives the result of its own solve
+    (the kernels treat right-hand sides independently with fixed reduction
+    orders): identical iteration counts and bitwise-equal solutions."""
+    w, U, h, o = c1
+    N = w["N"]
+    R = 3
+    B = inputs.gaussian((R, 2 * N * N), 555)
+    B[1] *= 1e-3  # different scales converge at different iterations
+    X = torch.zeros(R, 2 * N * N, dtype=torch.complex128, device="cuda:0")
+    st, infos = bamg.bamg_solve_batch(h, dev(B), X, R, 1e-10)
+    assert st == 0
+    Xb = host(X)
+    for r in range(R):
+        x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
+        st1, info = bamg.bamg_solve(h, dev(B[r]), x, 1e-10)
+        assert st1 == 0
+        assert info["iters"] == infos[r]["iters"]
+        assert np.array_equal(host(x), Xb[r])
