@@ -137,9 +137,14 @@ int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *
  *   op 4 BAMG_OP_COARSEST: out = A_L^-1 in  (l must be the coarsest level)
  *   op 5 BAMG_OP_CYCLE:    out = one multigrid cycle from level l on A_l out = in, zero start
  *   op 6 BAMG_OP_RESIDUAL: out = in - A_l out  (in: right-hand side; out: iterate, overwritten)
+ * Mixed-precision hierarchies only (in and out stay complex128; the work is
+ * done in FP32 with the coarse operator in the hierarchy's storage type):
+ *   op 7 BAMG_OP_APPLY_MIXED, op 8 BAMG_OP_SWEEP_MIXED: as ops 0 and 1 (l not the coarsest)
+ *   op 9 BAMG_OP_CYCLE_MIXED: out = the preconditioner of the solve applied to in (l = 0)
  * Level 0 is the fine reduced system (A_0 = Dhat). */
 enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLONG = 3,
-       BAMG_OP_COARSEST = 4, BAMG_OP_CYCLE = 5, BAMG_OP_RESIDUAL = 6 };
+       BAMG_OP_COARSEST = 4, BAMG_OP_CYCLE = 5, BAMG_OP_RESIDUAL = 6,
+       BAMG_OP_APPLY_MIXED = 7, BAMG_OP_SWEEP_MIXED = 8, BAMG_OP_CYCLE_MIXED = 9 };
 int bamg_level_op(bamg_hierarchy *h, int32_t level, int32_t op, const void *in, void *out, int32_t nrhs);
 
 /* Number of levels, or a negative status. */

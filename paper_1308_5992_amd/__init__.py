@@ -21,6 +21,7 @@ BAMG_EINVAL, BAMG_ENOMEM, BAMG_EDEVICE, BAMG_ESINGULAR, BAMG_ENOTIMPL = -1, -2, 
 BAMG_CYCLE_V, BAMG_CYCLE_W = 0, 1
 BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
 OP_APPLY, OP_SWEEP, OP_RESTRICT, OP_PROLONG, OP_COARSEST, OP_CYCLE, OP_RESIDUAL = range(7)
+OP_APPLY_MIXED, OP_SWEEP_MIXED, OP_CYCLE_MIXED = 7, 8, 9
 
 EXPORTED = [
     "bamg_default_params", "bamg_setup", "bamg_solve", "bamg_solve_batch", "bamg_apply_dhat",

@@ -90,6 +90,12 @@ struct Level {
   int prow = 0;                 // rows of P_{a,s}
   zd *x = nullptr, *b = nullptr, *r = nullptr;  // work vectors, cap right-hand sides
   zd* tv = nullptr;             // test vectors on this level [k][n]
+  // mixed-precision cycle: FP32 interpolation and smoother data, operator in
+  // the storage type of the hierarchy (FP32, FP16 or BF16), FP32 work vectors
+  zf* P32 = nullptr;
+  void* Dst = nullptr;
+  zf* Kinv32 = nullptr;
+  zf *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
   Coarse coarse() const {
     Coarse c;
     c.ex = ex; c.ey = ey; c.D = D; c.Kinv = Kinv;
@@ -103,6 +109,8 @@ struct bamg_hierarchy {
   hipStream_t s = nullptr;
   Fine f;
   zd *Ue = nullptr, *Uo = nullptr;
+  FineT<float> f32;
+  zf *Ue32 = nullptr, *Uo32 = nullptr;
   std::vector<Level> lv;
   int cap = 0;  // right-hand sides the work vectors hold
   // coarsest inversion scratch
@@ -159,8 +167,9 @@ struct bamg_hierarchy {
     for (auto& L : lv) {
       dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.P);
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
+      dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
     }
-    dfree(Ue); dfree(Uo); dfree(gjcol); dfree(gjperm); dfree(dflag);
+    dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(gjcol); dfree(gjperm); dfree(dflag);
     if (hflag) (void)hipHostFree(hflag);
     free_krylov();
     dfree(tvsave);
@@ -169,13 +178,22 @@ struct bamg_hierarchy {
   int L() const { return (int)lv.size(); }
   bool coarsest(int l) const { return l == L() - 1; }
 
+  bool mixed() const { return p.precision != BAMG_FP64; }
+
   void ensure_cap(int nrhs) {
     if (nrhs <= cap) return;
     for (auto& Lv : lv) {
       dfree(Lv.x); dfree(Lv.b); dfree(Lv.r);
+      dfree(Lv.x32); dfree(Lv.b32); dfree(Lv.r32);
+      Lv.x32 = Lv.b32 = Lv.r32 = nullptr;
       Lv.x = dalloc<zd>(Lv.n * nrhs);
       Lv.b = dalloc<zd>(Lv.n * nrhs);
       Lv.r = dalloc<zd>(Lv.n * nrhs);
+      if (mixed()) {
+        Lv.x32 = dalloc<zf>(Lv.n * nrhs);
+        Lv.b32 = dalloc<zf>(Lv.n * nrhs);
+        Lv.r32 = dalloc<zf>(Lv.n * nrhs);
+      }
     }
     cap = nrhs;
   }
@@ -196,12 +214,12 @@ struct bamg_hierarchy {
   }
   void restrict_(int l, const zd* r, zd* rc, int nrhs) {
     if (l == 0) launch_restrict_fine(f, lv[0].P, r, rc, nrhs, s);
-    else launch_restrict_coarse(lv[l].coarse(), lv[l].P, r, rc, nrhs, s);
+    else launch_restrict_coarse(lv[l].ex, lv[l].ey, lv[l].P, r, rc, nrhs, s);
     check_launch();
   }
   void prolong(int l, const zd* xc, zd* x, int nrhs) {
     if (l == 0) launch_prolong_fine(f, lv[0].P, xc, x, nrhs, s);
-    else launch_prolong_coarse(lv[l].coarse(), lv[l].P, xc, x, nrhs, s);
+    else launch_prolong_coarse(lv[l].ex, lv[l].ey, lv[l].P, xc, x, nrhs, s);
     check_launch();
   }
   void coarsest_solve(const zd* b, zd* x, int nrhs) {
@@ -235,6 +253,124 @@ struct bamg_hierarchy {
     }
     prolong(l, C.x, x, nrhs);
     for (int i = 0; i < p.post; ++i) sweep(l, x, b, nrhs);
+  }
+
+  // ------------------------------------------------ mixed-precision cycle
+  // The preconditioner of the mixed modes: the same cycle in FP32 with the
+  // coarse operators read from their reduced-precision copies and the
+  // coarsest level solved with the FP64 inverse (FP64 in, FP64 out).
+  template <typename S>
+  CoarseT<float, S> coarse32(int l) const {
+    CoarseT<float, S> c;
+    c.ex = lv[l].ex; c.ey = lv[l].ey; c.D = (const S*)lv[l].Dst; c.Kinv = lv[l].Kinv32;
+    return c;
+  }
+  template <typename S>
+  void apply32(int l, const zf* x, zf* y, const zf* b, int nrhs) {
+    if (l == 0) launch_dhat(f32, x, y, b, nrhs, s);
+    else launch_coarse_apply(coarse32<S>(l), x, y, b, nrhs, s);
+  }
+  template <typename S>
+  void sweep32(int l, zf* x, const zf* b, int nrhs) {
+    Level& Lv = lv[l];
+    for (int c = 0; c < Lv.ncol; ++c) {
+      if (l == 0) launch_kaczmarz_fine(f32, c, Lv.per_colour, x, b, nrhs, s);
+      else launch_kaczmarz_coarse(coarse32<S>(l), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+    }
+  }
+  template <typename S>
+  void cycle32(int l, const zf* b, zf* x, int nrhs) {
+    if (L() == 1) {
+      for (int i = 0; i < p.pre + p.post; ++i) sweep32<S>(0, x, b, nrhs);
+      check_launch();
+      return;
+    }
+    if (coarsest(l)) {
+      Level& C = lv[l];
+      launch_convert(b, C.b, C.n * nrhs, s);
+      launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, s);
+      launch_convert(C.x, x, C.n * nrhs, s);
+      check_launch();
+      return;
+    }
+    Level& Lv = lv[l];
+    Level& C = lv[l + 1];
+    for (int i = 0; i < p.pre; ++i) sweep32<S>(l, x, b, nrhs);
+    apply32<S>(l, x, Lv.r32, b, nrhs);
+    if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s);
+    else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s);
+    launch_zero(C.x32, C.n * nrhs * sizeof(zf), s);
+    const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
+    for (int g = 0; g < gamma; ++g) {
+      cycle32<S>(l + 1, C.b32, C.x32, nrhs);
+      if (coarsest(l + 1)) break;
+    }
+    if (l == 0) launch_prolong_fine(f32, Lv.P32, C.x32, x, nrhs, s);
+    else launch_prolong_coarse(Lv.ex, Lv.ey, Lv.P32, C.x32, x, nrhs, s);
+    for (int i = 0; i < p.post; ++i) sweep32<S>(l, x, b, nrhs);
+    check_launch();
+  }
+  // z = M v for nrhs FP64 level-0 vectors through the FP32 cycle
+  void precondition_mixed(const zd* v, zd* z, int nrhs) {
+    Level& L0 = lv[0];
+    launch_convert(v, L0.b32, L0.n * nrhs, s);
+    launch_zero(L0.x32, L0.n * nrhs * sizeof(zf), s);
+    switch (p.precision) {
+      case BAMG_MIXED_FP16: cycle32<hcx>(0, L0.b32, L0.x32, nrhs); break;
+      case BAMG_MIXED_BF16: cycle32<bcx>(0, L0.b32, L0.x32, nrhs); break;
+      default: cycle32<zf>(0, L0.b32, L0.x32, nrhs); break;
+    }
+    launch_convert(L0.x32, z, L0.n * nrhs, s);
+    check_launch();
+  }
+  // z = M v in the hierarchy's precision
+  void precondition(const zd* v, zd* z, int nrhs) {
+    if (mixed()) {
+      precondition_mixed(v, z, nrhs);
+    } else {
+      launch_fill_zero(z, lv[0].n * nrhs, s);
+      cycle(0, v, z, nrhs);
+    }
+  }
+  template <typename S>
+  void store_op(int l) {
+    Level& Lv = lv[l];
+    const size_t ne = (size_t)Lv.ex * Lv.ey * NOFF * 256;
+    if (!Lv.Dst) Lv.Dst = dalloc<S>(ne);
+    launch_convert(Lv.D, (S*)Lv.Dst, ne, s);
+    if (!coarsest(l)) {
+      if (!Lv.Kinv32) Lv.Kinv32 = dalloc<zf>((size_t)Lv.ex * Lv.ey * 256);
+      launch_kaczmarz_prep(coarse32<S>(l), Lv.Kinv32, s);
+    }
+  }
+  // reduced-precision copies of the solve-phase data (after setup / import)
+  void refresh_mixed() {
+    if (!mixed()) return;
+    const size_t nl = (size_t)f.N * f.N;
+    if (!Ue32) {
+      Ue32 = dalloc<zf>(nl);
+      Uo32 = dalloc<zf>(nl);
+    }
+    launch_convert(Ue, Ue32, nl, s);
+    launch_convert(Uo, Uo32, nl, s);
+    f32.N = f.N; f32.NH = f.NH; f32.c = f.c; f32.kappa = f.kappa; f32.kappa2 = f.kappa2;
+    f32.Ue = Ue32; f32.Uo = Uo32;
+    for (int l = 0; l < L(); ++l) {
+      Level& Lv = lv[l];
+      if (Lv.P) {
+        if (!Lv.P32) Lv.P32 = dalloc<zf>(Lv.n * 8);
+        launch_convert(Lv.P, Lv.P32, Lv.n * 8, s);
+      }
+      if (l >= 1 && !(coarsest(l) && L() > 1)) {
+        switch (p.precision) {
+          case BAMG_MIXED_FP16: store_op<hcx>(l); break;
+          case BAMG_MIXED_BF16: store_op<bcx>(l); break;
+          default: store_op<zf>(l); break;
+        }
+      }
+    }
+    check_launch();
+    HIPCHK(hipStreamSynchronize(s));
   }
 
   // ---------------------------------------------------------------- setup
@@ -339,7 +475,7 @@ bool valid_params(const bamg_params* p, std::string& why) {
   if (p->n_tv != 8) { why = "n_tv must be 8"; return false; }
   if (p->setup_sweeps < 0 || p->setup_adapt < 0 || p->pre < 0 || p->post < 0) { why = "negative count"; return false; }
   if (p->cycle != BAMG_CYCLE_V && p->cycle != BAMG_CYCLE_W) { why = "unknown cycle"; return false; }
-  if (p->precision != BAMG_FP64) { why = "precision not available"; return false; }
+  if (p->precision < BAMG_FP64 || p->precision > BAMG_MIXED_FP32) { why = "unknown precision"; return false; }
   if (p->restart < 1 || p->restart > 60) { why = "restart must be in [1, 60]"; return false; }
   if (p->max_iter < 0) { why = "max_iter < 0"; return false; }
   if (p->max_coarse < 16) { why = "max_coarse < 16"; return false; }
@@ -477,6 +613,7 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
         h->setup_pass();
       }
     }
+    h->refresh_mixed();
     HIPCHK(hipStreamSynchronize(h->s));
   } catch (const HipFail& e) {
     delete h;
@@ -571,6 +708,42 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         check_launch();
         break;
       }
+      case BAMG_OP_APPLY_MIXED:
+      case BAMG_OP_SWEEP_MIXED:
+      case BAMG_OP_CYCLE_MIXED: {
+        if (!h->mixed()) return fail(BAMG_EINVAL, "hierarchy is FP64");
+        if (op == BAMG_OP_CYCLE_MIXED) {
+          if (l != 0) return fail(BAMG_EINVAL, "the mixed cycle starts on level 0");
+          h->ensure_cap(nrhs);
+          h->precondition_mixed(xi, xo, nrhs);
+          break;
+        }
+        if (op == BAMG_OP_SWEEP_MIXED && h->coarsest(l) && h->L() > 1)
+          return fail(BAMG_EINVAL, "no smoother on the coarsest level");
+        if (l >= 1 && h->coarsest(l)) return fail(BAMG_EINVAL, "the coarsest level is solved in FP64");
+        h->ensure_cap(nrhs);
+        Level& Lv = h->lv[l];
+        const size_t nn = Lv.n * nrhs;
+        launch_convert(xi, Lv.b32, nn, h->s);
+        if (op == BAMG_OP_SWEEP_MIXED) launch_convert((const zd*)xo, Lv.x32, nn, h->s);
+        switch (h->p.precision) {
+          case BAMG_MIXED_FP16:
+            if (op == BAMG_OP_APPLY_MIXED) h->apply32<hcx>(l, Lv.b32, Lv.x32, nullptr, nrhs);
+            else h->sweep32<hcx>(l, Lv.x32, Lv.b32, nrhs);
+            break;
+          case BAMG_MIXED_BF16:
+            if (op == BAMG_OP_APPLY_MIXED) h->apply32<bcx>(l, Lv.b32, Lv.x32, nullptr, nrhs);
+            else h->sweep32<bcx>(l, Lv.x32, Lv.b32, nrhs);
+            break;
+          default:
+            if (op == BAMG_OP_APPLY_MIXED) h->apply32<zf>(l, Lv.b32, Lv.x32, nullptr, nrhs);
+            else h->sweep32<zf>(l, Lv.x32, Lv.b32, nrhs);
+            break;
+        }
+        launch_convert(Lv.x32, xo, nn, h->s);
+        check_launch();
+        break;
+      }
       default:
         return fail(BAMG_EINVAL, "unknown op");
     }
@@ -611,6 +784,7 @@ int bamg_import_level(bamg_hierarchy* h, int32_t l, const void* P_host, const vo
     Level& Lv = h->lv[l];
     HIPCHK(hipMemcpyAsync(Lv.P, P_host, Lv.n * 8 * sizeof(zd), hipMemcpyHostToDevice, h->s));
     h->build_next(l);
+    h->refresh_mixed();
     HIPCHK(hipStreamSynchronize(h->s));
   } catch (const HipFail& e) {
     return fail(BAMG_EDEVICE, e.msg);
@@ -688,8 +862,7 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
     for (int j = 0; j < m; ++j) {
       zd* vj = h->V + (size_t)j * R * n;
       zd* zj = h->Z + (size_t)j * R * n;
-      launch_fill_zero(zj, n * R, s);
-      h->cycle(0, vj, zj, R);
+      h->precondition(vj, zj, R);
       h->apply(0, zj, h->w, nullptr, R);
       launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, s);
       launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, s);

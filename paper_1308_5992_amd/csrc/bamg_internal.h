@@ -13,6 +13,8 @@
 //                               (the block row A_a of site a), used to run the
 //                               16 sequential row projections of a site at once
 #pragma once
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
@@ -24,6 +26,22 @@ struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
 using zd = cx<double>;
+using zf = cx<float>;
+// reduced-precision storage of complex operator entries (accumulated in FP32)
+struct alignas(4) hcx {
+  __half x, y;
+};
+struct alignas(4) bcx {
+  __hip_bfloat16 x, y;
+};
+template <typename T>
+__device__ __forceinline__ cx<T> widen(cx<double> v) { return {(T)v.x, (T)v.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> widen(cx<float> v) { return {(T)v.x, (T)v.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> widen(hcx v) { return {(T)__half2float(v.x), (T)__half2float(v.y)}; }
+template <typename T>
+__device__ __forceinline__ cx<T> widen(bcx v) { return {(T)__bfloat162float(v.x), (T)__bfloat162float(v.y)}; }
 
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> cmk(T a, T b) { return cx<T>{a, b}; }
@@ -57,25 +75,32 @@ __host__ __device__ __forceinline__ cx<T> cdiv_real(cx<T> a, T s) { return {a.x 
 constexpr int NOFF = 7;  // coarse stencil offsets
 constexpr int NC = 16;   // dofs per coarse site
 
-// Fine-level geometry and links
-struct Fine {
+// Fine-level geometry and links (links in the arithmetic type T)
+template <typename T>
+struct FineT {
   int N = 0, NH = 0;
   double c = 0, kappa = 0, kappa2 = 0;  // c = m + 2, kappa = 1/c
-  const zd* Ue = nullptr;
-  const zd* Uo = nullptr;
+  const cx<T>* Ue = nullptr;
+  const cx<T>* Uo = nullptr;
 };
+using Fine = FineT<double>;
 
 // ---- fine.hip ---------------------------------------------------------------
 void launch_gauge_pack(const zd* U, zd* Ue, zd* Uo, int N, hipStream_t s);
 void launch_eo_reduce(const Fine& f, const zd* b, zd* bh, int nrhs, hipStream_t s);
 void launch_eo_reconstruct(const Fine& f, const zd* b, const zd* xe, zd* x, int nrhs, hipStream_t s);
-// y = Dhat x, or y = b - Dhat x if b != nullptr
-void launch_dhat(const Fine& f, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s);
+// y = Dhat x, or y = b - Dhat x if b != nullptr  (T = double or float)
+template <typename T>
+void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s);
 // one colour pass over the nsites = N^2/32 sites of fine colour `colour`
-void launch_kaczmarz_fine(const Fine& f, int colour, int nsites, zd* x, const zd* b, int nrhs, hipStream_t s);
+template <typename T>
+void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
+                          hipStream_t s);
 // rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
-void launch_restrict_fine(const Fine& f, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s);
-void launch_prolong_fine(const Fine& f, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s);
+template <typename T>
+void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);
+template <typename T>
+void launch_prolong_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s);
 // D_1 = P^H Dhat P in 7-offset blocks
 void launch_galerkin_fine(const Fine& f, const zd* P, zd* D1, hipStream_t s);
 // gather test vectors into aggregate blocks and fit P (level 0)
@@ -83,19 +108,29 @@ void launch_fit_fine(const Fine& f, const zd* V, int k, zd* P, hipStream_t s);
 void launch_philox_tv(int n, int k, uint64_t seed, zd* out, hipStream_t s);
 
 // ---- coarse.hip -------------------------------------------------------------
-struct Coarse {
+// coarse level: arithmetic type T, operator storage type S (cx<double>,
+// cx<float>, hcx or bcx); Kinv in T
+template <typename T, typename S>
+struct CoarseT {
   int ex = 0, ey = 0;  // extents in sites
-  const zd* D = nullptr;
-  const zd* Kinv = nullptr;
+  const S* D = nullptr;
+  const cx<T>* Kinv = nullptr;
 };
-void launch_coarse_apply(const Coarse& c, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s);
+using Coarse = CoarseT<double, zd>;
+template <typename T, typename S>
+void launch_coarse_apply(const CoarseT<T, S>& c, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s);
 // one colour pass; mode 8 / 16: the 8- or 16-colouring, mode 1: one site per colour
-void launch_kaczmarz_coarse(const Coarse& c, int colour, int mode, int nsites, zd* x, const zd* b, int nrhs,
-                            hipStream_t s);
-void launch_kaczmarz_prep(const Coarse& c, zd* Kinv, hipStream_t s);
+template <typename T, typename S>
+void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
+                            int nrhs, hipStream_t s);
+// Kinv (type T) from the stored operator (type S), computed in FP64
+template <typename T, typename S>
+void launch_kaczmarz_prep(const CoarseT<T, S>& c, cx<T>* Kinv, hipStream_t s);
 // level l (ex x ey) -> l+1 (ex/2 x ey/2)
-void launch_restrict_coarse(const Coarse& c, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s);
-void launch_prolong_coarse(const Coarse& c, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s);
+template <typename T>
+void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);
+template <typename T>
+void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s);
 void launch_galerkin_coarse(const Coarse& c, const zd* P, zd* Dc, hipStream_t s);
 void launch_fit_coarse(const Coarse& c, const zd* V, int k, zd* P, hipStream_t s);
 // expand the block stencil into a dense n x n matrix (coarsest level)
@@ -124,9 +159,15 @@ void launch_normalize(zd* X, size_t ldx, int nv, size_t n, const zd* nrm, hipStr
 // y = alpha x (alpha real, host scalar)
 void launch_scale_copy(const zd* x, zd* y, size_t n, double alpha, hipStream_t s);
 void launch_fill_zero(zd* x, size_t n, hipStream_t s);
+// zero `bytes` bytes (a multiple of 8) with a kernel (no memset node)
+void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_copy(const zd* x, zd* y, size_t n, hipStream_t s);
 // flag[0] = 1 if any entry of x is not finite
 void launch_check_finite(const zd* x, size_t n, int* flag, hipStream_t s);
+// element-wise precision conversion (complex): out[i] = in[i] rounded to the
+// output type (round to nearest)
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* in, Tout* out, size_t n, hipStream_t s);
 // batched forms over R right-hand sides: basis vector v of right-hand side r
 // at X + (v*R + r)*n, w_r at W + r*n, coefficients at stride 64 per r
 void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s);

@@ -117,6 +117,17 @@ void launch_fill_zero(zd* x, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
 }
 
+__global__ void k_zero(uint2* __restrict__ p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = uint2{0u, 0u};
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 8;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint2*)p, n);
+}
+
 __global__ void k_copy(const zd* __restrict__ x, zd* __restrict__ y, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i];
@@ -138,6 +149,36 @@ __global__ void k_check_finite(const zd* __restrict__ x, size_t n, int* __restri
 void launch_check_finite(const zd* x, size_t n, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, flag);
 }
+
+// ---------------------------------------------------------------------------
+// precision conversion (round to nearest even)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cvt(const zd& a, zf& b) { b = zf{(float)a.x, (float)a.y}; }
+__device__ __forceinline__ void cvt(const zf& a, zd& b) { b = zd{(double)a.x, (double)a.y}; }
+__device__ __forceinline__ void cvt(const zd& a, hcx& b) {
+  b.x = __float2half_rn((float)a.x);
+  b.y = __float2half_rn((float)a.y);
+}
+__device__ __forceinline__ void cvt(const zd& a, bcx& b) {
+  b.x = __float2bfloat16((float)a.x);
+  b.y = __float2bfloat16((float)a.y);
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cvt(in[i], out[i]);
+}
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* in, Tout* out, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+}
+template void launch_convert<zd, zf>(const zd*, zf*, size_t, hipStream_t);
+template void launch_convert<zf, zd>(const zf*, zd*, size_t, hipStream_t);
+template void launch_convert<zd, hcx>(const zd*, hcx*, size_t, hipStream_t);
+template void launch_convert<zd, bcx>(const zd*, bcx*, size_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Batched forms for R right-hand sides.  Basis vector v of right-hand side r

@@ -27,32 +27,34 @@ __device__ __forceinline__ int neighbour_site(int site, int o, int ex, int ey) {
   return cwrap(ay + ODY[o], ey) * ex + cwrap(ax + ODX[o], ex);
 }
 
-__device__ __forceinline__ zd shfl_xor_z(zd v, int m) {
-  return zd{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_xor_z(cx<T> v, int m) {
+  return cx<T>{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
 }
-__device__ __forceinline__ zd shfl_z(zd v, int src) { return zd{__shfl(v.x, src, 64), __shfl(v.y, src, 64)}; }
 
 // ---------------------------------------------------------------------------
 // y = D x  (or y = b - D x)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_coarse_apply(Coarse c, const zd* __restrict__ x, zd* __restrict__ y,
-                                                      const zd* __restrict__ b, int nrhs) {
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_coarse_apply(CoarseT<T, S> c, const cx<T>* __restrict__ x,
+                                                      cx<T>* __restrict__ y, const cx<T>* __restrict__ b, int nrhs) {
+  using C = cx<T>;
   const int ns = c.ex * c.ey;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int site = blockIdx.x * 4 + wave;
   if (site >= ns) return;
   const int i = lane >> 2, q = lane & 3;
   int nb[NOFF];
-  zd Dv[NOFF][4];
+  C Dv[NOFF][4];
   for (int o = 0; o < NOFF; ++o) {
     nb[o] = neighbour_site(site, o, c.ex, c.ey);
-    const zd* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 4 * q;
-    for (int jj = 0; jj < 4; ++jj) Dv[o][jj] = Dr[jj];
+    const S* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 4 * q;
+    for (int jj = 0; jj < 4; ++jj) Dv[o][jj] = widen<T>(Dr[jj]);
   }
   const size_t n = (size_t)ns * 16;
   for (int r = 0; r < nrhs; ++r) {
-    const zd* xv = x + r * n;
-    zd acc = {0, 0};
+    const C* xv = x + r * n;
+    C acc = {0, 0};
     for (int o = 0; o < NOFF; ++o)
       for (int jj = 0; jj < 4; ++jj) acc = acc + Dv[o][jj] * xv[nb[o] * 16 + 4 * q + jj];
     acc = acc + shfl_xor_z(acc, 1);
@@ -64,9 +66,10 @@ __global__ __launch_bounds__(256) void k_coarse_apply(Coarse c, const zd* __rest
   }
 }
 
-void launch_coarse_apply(const Coarse& c, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s) {
+template <typename T, typename S>
+void launch_coarse_apply(const CoarseT<T, S>& c, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s) {
   int ns = c.ex * c.ey;
-  hipLaunchKernelGGL(k_coarse_apply, dim3((ns + 3) / 4), dim3(256), 0, s, c, x, y, b, nrhs);
+  hipLaunchKernelGGL((k_coarse_apply<T, S>), dim3((ns + 3) / 4), dim3(256), 0, s, c, x, y, b, nrhs);
 }
 
 // ---------------------------------------------------------------------------
@@ -94,36 +97,38 @@ __device__ __forceinline__ int coarse_colour_site(int c, int mode, int t, int ex
   return c;
 }
 
-__global__ __launch_bounds__(128) void k_kaczmarz_coarse(Coarse c, int colour, int mode, zd* __restrict__ x,
-                                                         const zd* __restrict__ b) {
+template <typename T, typename S>
+__global__ __launch_bounds__(128) void k_kaczmarz_coarse(CoarseT<T, S> c, int colour, int mode, cx<T>* __restrict__ x,
+                                                         const cx<T>* __restrict__ b) {
+  using C = cx<T>;
   constexpr int dxo[NOFF] = {0, 1, -1, 0, 0, 1, -1};
   constexpr int dyo[NOFF] = {0, 0, 0, 1, -1, 1, -1};
-  __shared__ zd part[16][NOFF * 16 + 1];
-  __shared__ zd rsh[16];
-  __shared__ zd xsh[NOFF * 16];
+  __shared__ C part[16][NOFF * 16 + 1];
+  __shared__ C rsh[16];
+  __shared__ C xsh[NOFF * 16];
   const int ns = c.ex * c.ey;
   const int tid = threadIdx.x, i = tid >> 3, q = tid & 7;
   const int site = coarse_colour_site(colour, mode, blockIdx.x, c.ex);
   const int ax = site % c.ex, ay = site / c.ex;
   const size_t n = (size_t)ns * 16;
-  zd* xv = x + blockIdx.y * n;
+  C* xv = x + blockIdx.y * n;
   // smoother row and right-hand side: independent of everything else
-  const zd* K = c.Kinv + ((size_t)site * 16 + i) * 16 + 2 * q;
-  const zd k0 = K[0], k1 = K[1];
-  const zd bi = b ? b[blockIdx.y * n + site * 16 + i] : zd{0, 0};
+  const C* K = c.Kinv + ((size_t)site * 16 + i) * 16 + 2 * q;
+  const C k0 = K[0], k1 = K[1];
+  const C bi = b ? b[blockIdx.y * n + site * 16 + i] : C{0, 0};
   int nb[NOFF];
-  zd Dv[NOFF][2], xo[NOFF][2];
+  C Dv[NOFF][2], xo[NOFF][2];
 #pragma unroll
   for (int o = 0; o < NOFF; ++o) {
     nb[o] = cwrap(ay + dyo[o], c.ey) * c.ex + cwrap(ax + dxo[o], c.ex);
-    const zd* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 2 * q;
-    Dv[o][0] = Dr[0];
-    Dv[o][1] = Dr[1];
-    const zd* xp = xv + nb[o] * 16 + 2 * q;
+    const S* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 2 * q;
+    Dv[o][0] = widen<T>(Dr[0]);
+    Dv[o][1] = widen<T>(Dr[1]);
+    const C* xp = xv + nb[o] * 16 + 2 * q;
     xo[o][0] = xp[0];
     xo[o][1] = xp[1];
   }
-  zd acc[NOFF];
+  C acc[NOFF];
 #pragma unroll
   for (int o = 0; o < NOFF; ++o) acc[o] = Dv[o][0] * xo[o][0] + Dv[o][1] * xo[o][1];
   if (i == 0) {
@@ -133,14 +138,14 @@ __global__ __launch_bounds__(128) void k_kaczmarz_coarse(Coarse c, int colour, i
       xsh[o * 16 + 2 * q + 1] = xo[o][1];
     }
   }
-  zd r = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
+  C r = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
   r = r + shfl_xor_z(r, 1);
   r = r + shfl_xor_z(r, 2);
   r = r + shfl_xor_z(r, 4);
   if (q == 0) rsh[i] = bi - r;
   __syncthreads();
   // alpha_i = sum_{j <= i} Kinv[i][j] r_j
-  zd al = k0 * rsh[2 * q] + k1 * rsh[2 * q + 1];
+  C al = k0 * rsh[2 * q] + k1 * rsh[2 * q + 1];
   al = al + shfl_xor_z(al, 1);
   al = al + shfl_xor_z(al, 2);
   al = al + shfl_xor_z(al, 4);
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(128) void k_kaczmarz_coarse(Coarse c, int colour, i
   __syncthreads();
   if (i < 2 * NOFF) {
     const int o = i >> 1, h = i & 1, col = o * 16 + 2 * q + h;
-    zd s0 = {0, 0}, s1 = {0, 0};
+    C s0 = {0, 0}, s1 = {0, 0};
 #pragma unroll
     for (int rr = 0; rr < 16; rr += 2) {
       s0 = s0 + part[rr][col];
@@ -163,14 +168,15 @@ __global__ __launch_bounds__(128) void k_kaczmarz_coarse(Coarse c, int colour, i
     // offsets packed as 4-bit fields (+1): (0,0) (+1,0) (-1,0) (0,+1) (0,-1) (+1,+1) (-1,-1)
     const int dx = (int)((0x0211021u >> (4 * o)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * o)) & 15u) - 1;
     const int nbo = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
-    const zd xold = xsh[col];
+    const C xold = xsh[col];
     xv[nbo * 16 + 2 * q + h] = xold + (s0 + s1);
   }
 }
 
-void launch_kaczmarz_coarse(const Coarse& c, int colour, int mode, int nsites, zd* x, const zd* b, int nrhs,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_kaczmarz_coarse, dim3(nsites, nrhs), dim3(128), 0, s, c, colour, mode, x, b);
+template <typename T, typename S>
+void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
+                            int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL((k_kaczmarz_coarse<T, S>), dim3(nsites, nrhs), dim3(128), 0, s, c, colour, mode, x, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -178,7 +184,8 @@ void launch_kaczmarz_coarse(const Coarse& c, int colour, int mode, int nsites, z
 // A zero row (G_ii = 0) is skipped by the smoother: its row and column of Kinv
 // are zero.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_kaczmarz_prep(Coarse c, zd* __restrict__ Kinv) {
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_kaczmarz_prep(CoarseT<T, S> c, cx<T>* __restrict__ Kinv) {
   __shared__ zd G[16][16];
   __shared__ zd K[16][16];
   const int site = blockIdx.x;
@@ -186,9 +193,9 @@ __global__ __launch_bounds__(256) void k_kaczmarz_prep(Coarse c, zd* __restrict_
   zd g = {0, 0};
   if (j <= i) {
     for (int o = 0; o < NOFF; ++o) {
-      const zd* Di = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16;
-      const zd* Dj = c.D + (((size_t)site * NOFF + o) * 16 + j) * 16;
-      for (int m = 0; m < 16; ++m) g = g + cjmul(Dj[m], Di[m]);
+      const S* Di = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16;
+      const S* Dj = c.D + (((size_t)site * NOFF + o) * 16 + j) * 16;
+      for (int m = 0; m < 16; ++m) g = g + cjmul(widen<double>(Dj[m]), widen<double>(Di[m]));
     }
   }
   G[i][j] = g;
@@ -207,59 +214,84 @@ __global__ __launch_bounds__(256) void k_kaczmarz_prep(Coarse c, zd* __restrict_
     }
   }
   __syncthreads();
-  Kinv[((size_t)site * 16 + i) * 16 + j] = K[i][j];
+  Kinv[((size_t)site * 16 + i) * 16 + j] = cx<T>{(T)K[i][j].x, (T)K[i][j].y};
 }
 
-void launch_kaczmarz_prep(const Coarse& c, zd* Kinv, hipStream_t s) {
-  hipLaunchKernelGGL(k_kaczmarz_prep, dim3(c.ex * c.ey), dim3(256), 0, s, c, Kinv);
+template <typename T, typename S>
+void launch_kaczmarz_prep(const CoarseT<T, S>& c, cx<T>* Kinv, hipStream_t s) {
+  hipLaunchKernelGGL((k_kaczmarz_prep<T, S>), dim3(c.ex * c.ey), dim3(256), 0, s, c, Kinv);
 }
 
 // ---------------------------------------------------------------------------
 // 2x2 aggregation: coarse site A = AY*(ex/2) + AX holds the sites
 // (2AX + (t&1), 2AY + (t>>1)), local t; P rows 8t + (d mod 8) for spin d/8.
 // ---------------------------------------------------------------------------
-__global__ void k_restrict_coarse(Coarse c, const zd* __restrict__ P, const zd* __restrict__ r, zd* __restrict__ rc) {
-  const int cex = c.ex / 2, cey = c.ey / 2;
+template <typename T>
+__global__ void k_restrict_coarse(int ex, int ey, const cx<T>* __restrict__ P, const cx<T>* __restrict__ r,
+                                  cx<T>* __restrict__ rc) {
+  using C = cx<T>;
+  const int cex = ex / 2, cey = ey / 2;
   const int tt = blockIdx.x * blockDim.x + threadIdx.x;
   if (tt >= cex * cey * 16) return;
   const int A = tt >> 4, d = tt & 15, s = d >> 3, k = d & 7;
   const int AX = A % cex, AY = A / cex;
-  const size_t n = (size_t)c.ex * c.ey * 16, nc = (size_t)cex * cey * 16;
-  const zd* rv = r + blockIdx.y * n;
-  const zd* Pa = P + ((size_t)A * 2 + s) * 32 * 8;
-  zd acc = {0, 0};
+  const size_t n = (size_t)ex * ey * 16, nc = (size_t)cex * cey * 16;
+  const C* rv = r + blockIdx.y * n;
+  const C* Pa = P + ((size_t)A * 2 + s) * 32 * 8;
+  C acc = {0, 0};
   for (int t = 0; t < 4; ++t) {
-    const int site = (2 * AY + (t >> 1)) * c.ex + 2 * AX + (t & 1);
+    const int site = (2 * AY + (t >> 1)) * ex + 2 * AX + (t & 1);
     for (int j = 0; j < 8; ++j) acc = acc + cjmul(Pa[(8 * t + j) * 8 + k], rv[site * 16 + 8 * s + j]);
   }
   rc[blockIdx.y * nc + tt] = acc;
 }
 
-void launch_restrict_coarse(const Coarse& c, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s) {
-  int n = (c.ex / 2) * (c.ey / 2) * 16;
-  hipLaunchKernelGGL(k_restrict_coarse, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, c, P, r, rc);
+template <typename T>
+void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s) {
+  int n = (ex / 2) * (ey / 2) * 16;
+  hipLaunchKernelGGL(k_restrict_coarse<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, ex, ey, P, r, rc);
 }
 
-__global__ void k_prolong_coarse(Coarse c, const zd* __restrict__ P, const zd* __restrict__ xc, zd* __restrict__ x) {
-  const int cex = c.ex / 2, cey = c.ey / 2;
+template <typename T>
+__global__ void k_prolong_coarse(int ex, int ey, const cx<T>* __restrict__ P, const cx<T>* __restrict__ xc,
+                                 cx<T>* __restrict__ x) {
+  using C = cx<T>;
+  const int cex = ex / 2, cey = ey / 2;
   const int tt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ns = c.ex * c.ey;
+  const int ns = ex * ey;
   if (tt >= ns * 16) return;
   const int site = tt >> 4, d = tt & 15, s = d >> 3, j = d & 7;
-  const int ax = site % c.ex, ay = site / c.ex;
+  const int ax = site % ex, ay = site / ex;
   const int A = (ay >> 1) * cex + (ax >> 1), t = 2 * (ay & 1) + (ax & 1);
   const size_t n = (size_t)ns * 16, nc = (size_t)cex * cey * 16;
-  const zd* Pr = P + (((size_t)A * 2 + s) * 32 + 8 * t + j) * 8;
-  const zd* xcv = xc + blockIdx.y * nc + A * 16 + 8 * s;
-  zd acc = {0, 0};
+  const C* Pr = P + (((size_t)A * 2 + s) * 32 + 8 * t + j) * 8;
+  const C* xcv = xc + blockIdx.y * nc + A * 16 + 8 * s;
+  C acc = {0, 0};
   for (int k = 0; k < 8; ++k) acc = acc + Pr[k] * xcv[k];
   x[blockIdx.y * n + tt] = x[blockIdx.y * n + tt] + acc;
 }
 
-void launch_prolong_coarse(const Coarse& c, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s) {
-  int n = c.ex * c.ey * 16;
-  hipLaunchKernelGGL(k_prolong_coarse, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, c, P, xc, x);
+template <typename T>
+void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s) {
+  int n = ex * ey * 16;
+  hipLaunchKernelGGL(k_prolong_coarse<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, ex, ey, P, xc, x);
 }
+
+#define BAMG_COARSE_INST(T, S)                                                                          \
+  template void launch_coarse_apply<T, S>(const CoarseT<T, S>&, const cx<T>*, cx<T>*, const cx<T>*, int, \
+                                          hipStream_t);                                                 \
+  template void launch_kaczmarz_coarse<T, S>(const CoarseT<T, S>&, int, int, int, cx<T>*, const cx<T>*, \
+                                             int, hipStream_t);                                         \
+  template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);
+BAMG_COARSE_INST(double, zd)
+BAMG_COARSE_INST(float, zf)
+BAMG_COARSE_INST(float, hcx)
+BAMG_COARSE_INST(float, bcx)
+#undef BAMG_COARSE_INST
+template void launch_restrict_coarse<double>(int, int, const zd*, const zd*, zd*, int, hipStream_t);
+template void launch_restrict_coarse<float>(int, int, const zf*, const zf*, zf*, int, hipStream_t);
+template void launch_prolong_coarse<double>(int, int, const zd*, const zd*, zd*, int, hipStream_t);
+template void launch_prolong_coarse<float>(int, int, const zf*, const zf*, zf*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Galerkin product of the next level by fine displacement:

@@ -24,8 +24,9 @@ __device__ __forceinline__ int hidx(int x, int y, int N, int NH) {
 
 // accumulate the hop in direction d (0:+x 1:-x 2:+y 3:-y) of spinor (a, b) with link u
 // (u already conjugated for backward hops) into (o0, o1), without the factor 1/2
-__device__ __forceinline__ void hop_acc(int d, zd u, zd a, zd b, zd& o0, zd& o1) {
-  zd h;
+template <typename T>
+__device__ __forceinline__ void hop_acc(int d, cx<T> u, cx<T> a, cx<T> b, cx<T>& o0, cx<T>& o1) {
+  cx<T> h;
   switch (d) {
     case 0: h = u * (a - b); o0 = o0 + h; o1 = o1 - h; break;
     case 1: h = u * (a + b); o0 = o0 + h; o1 = o1 + h; break;
@@ -133,17 +134,18 @@ void launch_eo_reconstruct(const Fine& f, const zd* b, const zd* xe, zd* x, int 
 // halo into LDS; stage 2 applies H_eo from LDS.  x and the links are read
 // once from HBM per tile (halo re-reads hit L2).
 // ---------------------------------------------------------------------------
-template <int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_dhat(Fine f, const zd* __restrict__ x, zd* __restrict__ y,
-                                                 const zd* __restrict__ b) {
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_dhat(FineT<T> f, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                 const cx<T>* __restrict__ b) {
+  using C = cx<T>;
   constexpr int W = TX + 2, NREG = (TY + 2) * (TX + 2), NT = TX * TY;
-  __shared__ zd t0[NREG], t1[NREG];
+  __shared__ C t0[NREG], t1[NREG];
   const int N = f.N, NH = f.NH;
   const size_t n = (size_t)N * NH * 2;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const zd* __restrict__ xv = x + blockIdx.z * n;
-  const zd* __restrict__ Ue = f.Ue;
-  const zd* __restrict__ Uo = f.Uo;
+  const C* __restrict__ xv = x + blockIdx.z * n;
+  const C* __restrict__ Ue = f.Ue;
+  const C* __restrict__ Uo = f.Uo;
   const int tid = threadIdx.x;
   for (int q = tid; q < NREG; q += NT) {
     int cy = q / W, cxh = q - cy * W;
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(TX* TY) void k_dhat(Fine f, const zd* __restrict__ 
     int w = yy * NH + xhh;
     int jpx = hidx(lx + 1, yy, N, NH), jmx = hidx(lx - 1, yy, N, NH);
     int jpy = hidx(lx, yy + 1, N, NH), jmy = hidx(lx, yy - 1, N, NH);
-    zd a0 = {0, 0}, a1 = {0, 0};
+    C a0 = {0, 0}, a1 = {0, 0};
     hop_acc(0, Uo[2 * w], xv[2 * jpx], xv[2 * jpx + 1], a0, a1);
     hop_acc(1, conj(Ue[2 * jmx]), xv[2 * jmx], xv[2 * jmx + 1], a0, a1);
     hop_acc(2, Uo[2 * w + 1], xv[2 * jpy], xv[2 * jpy + 1], a0, a1);
@@ -167,16 +169,16 @@ __global__ __launch_bounds__(TX* TY) void k_dhat(Fine f, const zd* __restrict__ 
   const int qpx = (ly + 1) * W + lxh + 1 + p, qmx = (ly + 1) * W + lxh + p;
   const int qpy = (ly + 2) * W + lxh + 1, qmy = ly * W + lxh + 1;
   const int omx = yy * NH + wrapn(xhh + p - 1, NH), omy = wrapn(yy - 1, N) * NH + xhh;
-  zd a0 = {0, 0}, a1 = {0, 0};
+  C a0 = {0, 0}, a1 = {0, 0};
   hop_acc(0, Ue[2 * e], t0[qpx], t1[qpx], a0, a1);
   hop_acc(1, conj(Uo[2 * omx]), t0[qmx], t1[qmx], a0, a1);
   hop_acc(2, Ue[2 * e + 1], t0[qpy], t1[qpy], a0, a1);
   hop_acc(3, conj(Uo[2 * omy + 1]), t0[qmy], t1[qmy], a0, a1);
-  const double k2q = 0.25 * f.kappa2;
-  zd r0 = xv[2 * e] - k2q * a0, r1 = xv[2 * e + 1] - k2q * a1;
-  zd* yv = y + blockIdx.z * n;
+  const T k2q = (T)(0.25 * f.kappa2);
+  C r0 = xv[2 * e] - k2q * a0, r1 = xv[2 * e + 1] - k2q * a1;
+  C* yv = y + blockIdx.z * n;
   if (b) {
-    const zd* bv = b + blockIdx.z * n;
+    const C* bv = b + blockIdx.z * n;
     r0 = bv[2 * e] - r0;
     r1 = bv[2 * e + 1] - r1;
   }
@@ -184,18 +186,21 @@ __global__ __launch_bounds__(TX* TY) void k_dhat(Fine f, const zd* __restrict__ 
   yv[2 * e + 1] = r1;
 }
 
-void launch_dhat(const Fine& f, const zd* x, zd* y, const zd* b, int nrhs, hipStream_t s) {
+template <typename T>
+void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s) {
   const int N = f.N, NH = f.NH;
   dim3 g;
 #define DHAT_CASE(TX)                                                                     \
   if (NH % TX == 0) {                                                                     \
     g = dim3(NH / TX, N / 4, nrhs);                                                       \
-    hipLaunchKernelGGL((k_dhat<TX, 4>), g, dim3(TX * 4), 0, s, f, x, y, b);              \
+    hipLaunchKernelGGL((k_dhat<T, TX, 4>), g, dim3(TX * 4), 0, s, f, x, y, b);              \
     return;                                                                               \
   }
   DHAT_CASE(64) DHAT_CASE(32) DHAT_CASE(16) DHAT_CASE(8) DHAT_CASE(4)
 #undef DHAT_CASE
 }
+template void launch_dhat<double>(const FineT<double>&, const zd*, zd*, const zd*, int, hipStream_t);
+template void launch_dhat<float>(const FineT<float>&, const zf*, zf*, const zf*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Rows of Dhat at even site (xh, y): e[n][s][t] = Dhat[(i,s), (j_n,t)] for the
@@ -287,7 +292,8 @@ constexpr uint64_t PATH_A1 = 0x221143210ull, PATH_B1 = 0x434300000ull;  // path 
 constexpr uint64_t PATH_A2 = 0x434343210ull, PATH_B2 = 0x221100000ull;  // path 0 / 1, second hop
 __device__ __forceinline__ int nib(uint64_t c, int n) { return (int)((c >> (4 * n)) & 15ull); }
 
-__device__ __forceinline__ zd grp16_sum(zd v) {
+template <typename T>
+__device__ __forceinline__ cx<T> grp16_sum(cx<T> v) {
   for (int off = 8; off > 0; off >>= 1) {
     v.x += __shfl_xor(v.x, off, 64);
     v.y += __shfl_xor(v.y, off, 64);
@@ -300,14 +306,17 @@ __device__ __forceinline__ zd grp16_sum(zd v) {
 // on slot 0.  Pi_d = 2 P = [[1, a], [conj(a), 1]] with a = -1, 1, -i, i for
 // d = +x, -x, +y, -y, so Pi_1 Pi_2 = [[1 + a1 conj(a2), a1 + a2],
 // [conj(a1 + a2), 1 + conj(a1) a2]]; links are selected without branches.
-__device__ __forceinline__ zd hop_phase(int d) {
-  const double sg = (d & 1) ? 1.0 : -1.0;
-  return (d < 2) ? zd{sg, 0.0} : zd{0.0, sg};
+template <typename T>
+__device__ __forceinline__ cx<T> hop_phase(int d) {
+  const T sg = (d & 1) ? T(1) : T(-1);
+  return (d < 2) ? cx<T>{sg, T(0)} : cx<T>{T(0), sg};
 }
 
-__device__ __forceinline__ void dhat_slot_block(const Fine& f, int x, int y, int i, int n, int jn, zd B[2][2]) {
+template <typename T>
+__device__ __forceinline__ void dhat_slot_block(const FineT<T>& f, int x, int y, int i, int n, int jn, cx<T> B[2][2]) {
+  using C = cx<T>;
   const int N = f.N, NH = f.NH;
-  zd b00 = {0, 0}, b01 = {0, 0}, b10 = {0, 0}, b11 = {0, 0};
+  C b00 = {0, 0}, b01 = {0, 0}, b10 = {0, 0}, b11 = {0, 0};
 #pragma unroll
   for (int pth = 0; pth < 2; ++pth) {
     const int d1 = nib(pth ? PATH_B1 : PATH_A1, n) - 1, d2 = nib(pth ? PATH_B2 : PATH_A2, n) - 1;
@@ -317,26 +326,26 @@ __device__ __forceinline__ void dhat_slot_block(const Fine& f, int x, int y, int
       const bool bk1 = d1 & 1, bk2 = d2 & 1;
       // first hop: forward link at i (even) or conj of the link at w (odd);
       // second hop: forward link at w (odd) or conj of the link at jn (even)
-      const zd* p1 = bk1 ? f.Uo + 2 * w + (d1 >> 1) : f.Ue + 2 * i + (d1 >> 1);
-      const zd* p2 = bk2 ? f.Ue + 2 * jn + (d2 >> 1) : f.Uo + 2 * w + (d2 >> 1);
-      zd l1 = *p1, l2 = *p2;
+      const C* p1 = bk1 ? f.Uo + 2 * w + (d1 >> 1) : f.Ue + 2 * i + (d1 >> 1);
+      const C* p2 = bk2 ? f.Ue + 2 * jn + (d2 >> 1) : f.Uo + 2 * w + (d2 >> 1);
+      C l1 = *p1, l2 = *p2;
       l1.y = bk1 ? -l1.y : l1.y;
       l2.y = bk2 ? -l2.y : l2.y;
-      const zd u = l1 * l2;
-      const zd a1 = hop_phase(d1), a2 = hop_phase(d2);
-      const zd s12 = a1 + a2;
-      b00 = b00 + (zd{1, 0} + a1 * conj(a2)) * u;
+      const C u = l1 * l2;
+      const C a1 = hop_phase<T>(d1), a2 = hop_phase<T>(d2);
+      const C s12 = a1 + a2;
+      b00 = b00 + (C{1, 0} + a1 * conj(a2)) * u;
       b01 = b01 + s12 * u;
       b10 = b10 + conj(s12) * u;
-      b11 = b11 + (zd{1, 0} + conj(a1) * a2) * u;
+      b11 = b11 + (C{1, 0} + conj(a1) * a2) * u;
     }
   }
-  const double k2q = 0.25 * f.kappa2;
-  const double one = (n == 0) ? 1.0 : 0.0;
-  B[0][0] = zd{one, 0} - k2q * b00;
+  const T k2q = (T)(0.25 * f.kappa2);
+  const T one = (n == 0) ? T(1) : T(0);
+  B[0][0] = C{one, 0} - k2q * b00;
   B[0][1] = -(k2q * b01);
   B[1][0] = -(k2q * b10);
-  B[1][1] = zd{one, 0} - k2q * b11;
+  B[1][1] = C{one, 0} - k2q * b11;
 }
 
 // t-th even site of fine colour c = 4a + b (a = (x+y)/2 mod 4, b = (x-y)/2 mod 4):
@@ -348,59 +357,66 @@ __device__ __forceinline__ void fine_colour_site(int c, int t, int N, int& x, in
   x = 8 * k + ((2 * a - y) & 7);
 }
 
-__global__ __launch_bounds__(64) void k_kaczmarz_fine(Fine f, int colour, int nsites, zd* __restrict__ x,
-                                                      const zd* __restrict__ b) {
+template <typename T>
+__global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, int nsites, cx<T>* __restrict__ x,
+                                                      const cx<T>* __restrict__ b) {
+  using C = cx<T>;
   const int lane = threadIdx.x & 15;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 4);
   if (t >= nsites) return;  // whole 16-lane groups leave together
   const size_t n = (size_t)f.N * f.NH * 2;
-  zd* xv = x + blockIdx.y * n;
+  C* xv = x + blockIdx.y * n;
   int px, y;
   fine_colour_site(colour, t, f.N, px, y);
   const int i = y * f.NH + (px >> 1);
   const bool act = lane < 9;
   const int slot = act ? lane : 0;
   const int jn = hidx(px + nib(SLOT_DX2, slot) - 2, y + nib(SLOT_DY2, slot) - 2, f.N, f.NH);
-  zd x0 = {0, 0}, x1 = {0, 0};
+  C x0 = {0, 0}, x1 = {0, 0};
   if (act) {
     x0 = xv[2 * jn];
     x1 = xv[2 * jn + 1];
   }
-  const zd b0 = b ? b[blockIdx.y * n + 2 * i] : zd{0, 0};
-  const zd b1 = b ? b[blockIdx.y * n + 2 * i + 1] : zd{0, 0};
-  zd B[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+  const C b0 = b ? b[blockIdx.y * n + 2 * i] : C{0, 0};
+  const C b1 = b ? b[blockIdx.y * n + 2 * i + 1] : C{0, 0};
+  C B[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
   if (act) dhat_slot_block(f, px, y, i, slot, jn, B);
-  const zd r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
-  const zd r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
-  const zd nu = grp16_sum(zd{norm2(B[0][0]) + norm2(B[0][1]), norm2(B[1][0]) + norm2(B[1][1])});
-  const zd g10 = grp16_sum(cjmul(B[0][0], B[1][0]) + cjmul(B[0][1], B[1][1]));
-  const zd a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : zd{0, 0};
-  const zd a1 = nu.y > 0 ? cdiv_real(b1 - r1 - g10 * a0, nu.y) : zd{0, 0};
+  const C r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
+  const C r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
+  const C nu = grp16_sum(C{norm2(B[0][0]) + norm2(B[0][1]), norm2(B[1][0]) + norm2(B[1][1])});
+  const C g10 = grp16_sum(cjmul(B[0][0], B[1][0]) + cjmul(B[0][1], B[1][1]));
+  const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
+  const C a1 = nu.y > 0 ? cdiv_real(b1 - r1 - g10 * a0, nu.y) : C{0, 0};
   if (act) {
     xv[2 * jn] = x0 + cjmul(B[0][0], a0) + cjmul(B[1][0], a1);
     xv[2 * jn + 1] = x1 + cjmul(B[0][1], a0) + cjmul(B[1][1], a1);
   }
 }
 
-void launch_kaczmarz_fine(const Fine& f, int colour, int nsites, zd* x, const zd* b, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_kaczmarz_fine, dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b);
+template <typename T>
+void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_kaczmarz_fine<T>, dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b);
 }
+template void launch_kaczmarz_fine<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t);
+template void launch_kaczmarz_fine<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Transfers between level 0 and the 4x4 aggregates of the half-x grid.
 // Aggregate a = Ay*(NH/4) + Ax holds the even sites xh = 4Ax + lx, y = 4Ay + ly,
 // local row 4*ly + lx.  rc[a][8s + k] = sum_row conj(P[a][s][row][k]) r[site][s].
 // ---------------------------------------------------------------------------
-__global__ void k_restrict_fine(Fine f, const zd* __restrict__ P, const zd* __restrict__ r, zd* __restrict__ rc) {
+template <typename T>
+__global__ void k_restrict_fine(FineT<T> f, const cx<T>* __restrict__ P, const cx<T>* __restrict__ r, cx<T>* __restrict__ rc) {
+  using C = cx<T>;
   const int cxn = f.NH / 4, cyn = f.N / 4;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cxn * cyn * 16) return;
   const int a = t >> 4, d = t & 15, s = d >> 3, k = d & 7;
   const int Ax = a % cxn, Ay = a / cxn;
   const size_t n = (size_t)f.N * f.NH * 2, nc = (size_t)cxn * cyn * 16;
-  const zd* rv = r + blockIdx.y * n;
-  const zd* Pa = P + ((size_t)a * 2 + s) * 16 * 8;
-  zd acc = {0, 0};
+  const C* rv = r + blockIdx.y * n;
+  const C* Pa = P + ((size_t)a * 2 + s) * 16 * 8;
+  C acc = {0, 0};
   for (int row = 0; row < 16; ++row) {
     int ly = row >> 2, lx = row & 3;
     int e = (4 * Ay + ly) * f.NH + 4 * Ax + lx;
@@ -409,12 +425,15 @@ __global__ void k_restrict_fine(Fine f, const zd* __restrict__ P, const zd* __re
   rc[blockIdx.y * nc + t] = acc;
 }
 
-void launch_restrict_fine(const Fine& f, const zd* P, const zd* r, zd* rc, int nrhs, hipStream_t s) {
+template <typename T>
+void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s) {
   int n = (f.NH / 4) * (f.N / 4) * 16;
-  hipLaunchKernelGGL(k_restrict_fine, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, r, rc);
+  hipLaunchKernelGGL(k_restrict_fine<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, r, rc);
 }
 
-__global__ void k_prolong_fine(Fine f, const zd* __restrict__ P, const zd* __restrict__ xc, zd* __restrict__ x) {
+template <typename T>
+__global__ void k_prolong_fine(FineT<T> f, const cx<T>* __restrict__ P, const cx<T>* __restrict__ xc, cx<T>* __restrict__ x) {
+  using C = cx<T>;
   const int cxn = f.NH / 4, cyn = f.N / 4;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= f.N * f.NH * 2) return;
@@ -422,17 +441,22 @@ __global__ void k_prolong_fine(Fine f, const zd* __restrict__ P, const zd* __res
   const int y = e / f.NH, xh = e - y * f.NH;
   const int a = (y >> 2) * cxn + (xh >> 2), row = 4 * (y & 3) + (xh & 3);
   const size_t n = (size_t)f.N * f.NH * 2, nc = (size_t)cxn * cyn * 16;
-  const zd* Pr = P + (((size_t)a * 2 + s) * 16 + row) * 8;
-  const zd* xcv = xc + blockIdx.y * nc + a * 16 + 8 * s;
-  zd acc = {0, 0};
+  const C* Pr = P + (((size_t)a * 2 + s) * 16 + row) * 8;
+  const C* xcv = xc + blockIdx.y * nc + a * 16 + 8 * s;
+  C acc = {0, 0};
   for (int k = 0; k < 8; ++k) acc = acc + Pr[k] * xcv[k];
   x[blockIdx.y * n + t] = x[blockIdx.y * n + t] + acc;
 }
 
-void launch_prolong_fine(const Fine& f, const zd* P, const zd* xc, zd* x, int nrhs, hipStream_t s) {
+template <typename T>
+void launch_prolong_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s) {
   int n = f.N * f.NH * 2;
-  hipLaunchKernelGGL(k_prolong_fine, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, xc, x);
+  hipLaunchKernelGGL(k_prolong_fine<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, xc, x);
 }
+template void launch_restrict_fine<double>(const FineT<double>&, const zd*, const zd*, zd*, int, hipStream_t);
+template void launch_restrict_fine<float>(const FineT<float>&, const zf*, const zf*, zf*, int, hipStream_t);
+template void launch_prolong_fine<double>(const FineT<double>&, const zd*, const zd*, zd*, int, hipStream_t);
+template void launch_prolong_fine<float>(const FineT<float>&, const zf*, const zf*, zf*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Galerkin product D_1 = P^H Dhat P, assembled per aggregate A by fine

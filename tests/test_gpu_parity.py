@@ -308,3 +308,68 @@ def test_batch_equals_single_solves(bamg, c1):
         assert st1 == 0
         assert info["iters"] == infos[r]["iters"]
         assert np.array_equal(host(x), Xb[r])
+
+
+# ---------------------------------------------------------------- mixed precision
+# FP32 arithmetic with operators stored in FP32 / FP16 / BF16: errors against
+# the FP64 oracle scale with the unit roundoff of the storage type
+# (FP32 6e-8, FP16 4.9e-4, BF16 3.9e-3) times a small growth factor.
+MIXED = {"fp32": (3, 2e-5), "fp16": (1, 2e-2), "bf16": (2, 1e-1)}
+
+
+@pytest.fixture(scope="module", params=list(MIXED))
+def imported_mixed(bamg, request):
+    prec, tol = MIXED[request.param]
+    N = 64
+    U = inputs.gauge_metropolis(N, 3.0, 40, 5)
+    m = -0.05
+    kw = dict(n_levels=3, max_coarse=512, setup_sweeps=2, setup_adapt=0)
+    h = make_h(bamg, U, m, precision=prec, **kw)
+    o = oracle.Hierarchy(U, m, **kw)
+    for l in range(2):
+        P = _random_P(o.P_blocks(l).shape, 100 + l)
+        bamg.bamg_import_level(h, l, P)
+        o.import_P(l, P)
+    return request.param, tol, N, U, m, h, o
+
+
+@pytest.mark.parametrize("l", [0, 1])
+def test_mixed_apply_and_sweep(bamg, imported_mixed, l):
+    name, tol, N, U, m, h, o = imported_mixed
+    n = bamg.bamg_level_info(h, l)["n"]
+    x = inputs.gaussian((2, n), 160 + l)
+    y = torch.zeros(2, n, dtype=torch.complex128, device="cuda:0")
+    bamg.bamg_level_op(h, l, bamg.OP_APPLY_MIXED, dev(x), y, 2)
+    ea = rel(host(y), o.apply(l, x, nrhs=2).reshape(2, n))
+    b = inputs.gaussian((2, n), 170 + l)
+    xs = dev(x)
+    bamg.bamg_level_op(h, l, bamg.OP_SWEEP_MIXED, dev(b), xs, 2)
+    es = rel(host(xs), o.sweep(l, x, b, nrhs=2).reshape(2, n))
+    # level 0 is FP32 links in every mixed mode
+    t = 2e-5 if l == 0 else tol
+    log(f"mixed {name} level {l}: apply err {ea:.2e} sweep err {es:.2e}")
+    assert ea < t and es < t
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_mixed_solve_reaches_fp64_accuracy(bamg, prec):
+    """The FP64 outer FGMRES drives the true residual to 1e-10 whatever the
+    precision of the preconditioner; the solution agrees with the FP64
+    oracle's to the conditioning of the problem."""
+    w = inputs.workload("c2_128_b6")
+    U = inputs.load_gauge(w)
+    N = w["N"]
+    tv = oracle.gaussian_tv(N, 8, w["tv_seed"])
+    h = make_h(bamg, U, w["m"], n_levels=w["n_levels"], init_tv=tv, precision=MIXED[prec][0])
+    b = inputs.gaussian(2 * N * N, w["rhs_seed"])
+    x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
+    st, info = bamg.bamg_solve(h, dev(b), x, 1e-10)
+    xg = host(x)
+    o = oracle.Hierarchy(U, w["m"], n_levels=w["n_levels"], init_tv=tv)
+    sto, xo, io = o.solve(b, tol=1e-10)
+    full = np.linalg.norm(b - oracle.wilson_apply(U, w["m"], xg)) / np.linalg.norm(b)
+    dx = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    log(f"mixed {prec} solve: iters {info['iters']} (fp64 oracle {io['iters']}), full relres {full:.2e}, "
+        f"|x - x_fp64|/|x| {dx:.2e}")
+    assert st == 0 and info["relres_reduced"] <= 1e-10
+    assert full < 2e-10 and dx < 1e-7
