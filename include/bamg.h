@@ -115,7 +115,9 @@ int bamg_solve(bamg_hierarchy *h, const void *b, void *x, double tol, bamg_solve
 
 /* nrhs independent solves with one shared hierarchy: B and X are [nrhs][y][x][s].
  * infos (host, may be NULL) receives nrhs records.  Each right-hand side
- * converges on its own; results equal those of bamg_solve up to rounding. */
+ * converges on its own (lockstep FGMRES with per-RHS bases) and its result is
+ * bitwise independent of nrhs and of the other right-hand sides; it equals the
+ * result of bamg_solve up to rounding (bamg_solve uses single-RHS kernels). */
 int bamg_solve_batch(bamg_hierarchy *h, const void *B, void *X, int32_t nrhs, double tol,
                      bamg_solve_info *infos);
 

@@ -65,6 +65,9 @@ void dfree(void* p) {
 
 int floor_mod(int a, int n) { return ((a % n) + n) % n; }
 
+// right-hand sides from which the smoothers use their multi-RHS kernels
+constexpr int MR_MIN = 4;
+
 // ---- multicolour orderings (Sec. 3.1 leaves the colouring open) -------------
 // fine even site (x, y): 4 * (((x+y)/2) mod 4) + (((x-y)/2) mod 4); 16 colours
 int fine_colour_of(int x, int y) { return 4 * floor_mod((x + y) / 2, 4) + floor_mod((x - y) / 2, 4); }
@@ -113,6 +116,9 @@ struct bamg_hierarchy {
   zf *Ue32 = nullptr, *Uo32 = nullptr;
   std::vector<Level> lv;
   int cap = 0;  // right-hand sides the work vectors hold
+  // batched path: multi-RHS kernels for every batch size, so that a right-hand
+  // side's arithmetic does not depend on how many others share the batch
+  bool force_mr = false;
   // coarsest inversion scratch
   zd* gjcol = nullptr;
   int* gjperm = nullptr;
@@ -206,9 +212,15 @@ struct bamg_hierarchy {
   }
   void sweep(int l, zd* x, const zd* b, int nrhs) {
     Level& Lv = lv[l];
+    const bool mr = force_mr || nrhs >= MR_MIN;
     for (int c = 0; c < Lv.ncol; ++c) {
-      if (l == 0) launch_kaczmarz_fine(f, c, Lv.per_colour, x, b, nrhs, s);
-      else launch_kaczmarz_coarse(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+      if (l == 0) {
+        if (mr) launch_kaczmarz_fine_mr(f, c, Lv.per_colour, x, b, nrhs, s);
+        else launch_kaczmarz_fine(f, c, Lv.per_colour, x, b, nrhs, s);
+      } else {
+        if (mr) launch_kaczmarz_coarse_mr(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+        else launch_kaczmarz_coarse(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+      }
     }
     check_launch();
   }
@@ -224,7 +236,7 @@ struct bamg_hierarchy {
   }
   void coarsest_solve(const zd* b, zd* x, int nrhs) {
     Level& Lv = lv.back();
-    launch_dense_mv(Lv.Ainv, (int)Lv.n, b, x, nrhs, s);
+    launch_dense_mv(Lv.Ainv, (int)Lv.n, b, x, nrhs, force_mr, s);
     check_launch();
   }
 
@@ -273,9 +285,15 @@ struct bamg_hierarchy {
   template <typename S>
   void sweep32(int l, zf* x, const zf* b, int nrhs) {
     Level& Lv = lv[l];
+    const bool mr = force_mr || nrhs >= MR_MIN;
     for (int c = 0; c < Lv.ncol; ++c) {
-      if (l == 0) launch_kaczmarz_fine(f32, c, Lv.per_colour, x, b, nrhs, s);
-      else launch_kaczmarz_coarse(coarse32<S>(l), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+      if (l == 0) {
+        if (mr) launch_kaczmarz_fine_mr(f32, c, Lv.per_colour, x, b, nrhs, s);
+        else launch_kaczmarz_fine(f32, c, Lv.per_colour, x, b, nrhs, s);
+      } else {
+        if (mr) launch_kaczmarz_coarse_mr(coarse32<S>(l), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+        else launch_kaczmarz_coarse(coarse32<S>(l), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+      }
     }
   }
   template <typename S>
@@ -288,7 +306,7 @@ struct bamg_hierarchy {
     if (coarsest(l)) {
       Level& C = lv[l];
       launch_convert(b, C.b, C.n * nrhs, s);
-      launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, s);
+      launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, force_mr, s);
       launch_convert(C.x, x, C.n * nrhs, s);
       check_launch();
       return;
@@ -949,9 +967,15 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
   return worst;
 }
 
-static int solve_common(bamg_hierarchy* h, const void* B, void* X, int R, double tol, bamg_solve_info* infos) {
+static int solve_common(bamg_hierarchy* h, const void* B, void* X, int R, double tol, bamg_solve_info* infos,
+                        bool batched) {
   const auto t0 = std::chrono::steady_clock::now();
   int st;
+  struct ModeGuard {
+    bamg_hierarchy* h;
+    ~ModeGuard() { h->force_mr = false; }
+  } guard{h};
+  h->force_mr = batched;
   try {
     h->ensure_krylov(R, true);
     h->ensure_cap(R);
@@ -982,7 +1006,7 @@ int bamg_solve(bamg_hierarchy* h, const void* b, void* x, double tol, bamg_solve
   bamg_solve_info tmp{};
   if (!info) info = &tmp;
   *info = bamg_solve_info{};
-  return solve_common(h, b, x, 1, tol, info);
+  return solve_common(h, b, x, 1, tol, info, false);
 }
 
 int bamg_solve_batch(bamg_hierarchy* h, const void* B, void* X, int32_t nrhs, double tol, bamg_solve_info* infos) {
@@ -995,7 +1019,7 @@ int bamg_solve_batch(bamg_hierarchy* h, const void* B, void* X, int32_t nrhs, do
     infos = tmp.data();
   }
   for (int r = 0; r < nrhs; ++r) infos[r] = bamg_solve_info{};
-  return solve_common(h, B, X, nrhs, tol, infos);
+  return solve_common(h, B, X, nrhs, tol, infos, true);
 }
 
 }  // extern "C"

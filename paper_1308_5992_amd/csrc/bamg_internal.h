@@ -96,6 +96,10 @@ void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, in
 template <typename T>
 void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
                           hipStream_t s);
+// the same pass for many right-hand sides: slot blocks built once per site and 16 RHS
+template <typename T>
+void launch_kaczmarz_fine_mr(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
+                             hipStream_t s);
 // rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
 template <typename T>
 void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);
@@ -123,6 +127,10 @@ void launch_coarse_apply(const CoarseT<T, S>& c, const cx<T>* x, cx<T>* y, const
 template <typename T, typename S>
 void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
                             int nrhs, hipStream_t s);
+// the same pass for many right-hand sides: operator staged once per site and 16 RHS
+template <typename T, typename S>
+void launch_kaczmarz_coarse_mr(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
+                               int nrhs, hipStream_t s);
 // Kinv (type T) from the stored operator (type S), computed in FP64
 template <typename T, typename S>
 void launch_kaczmarz_prep(const CoarseT<T, S>& c, cx<T>* Kinv, hipStream_t s);
@@ -141,8 +149,10 @@ void launch_densify(const Coarse& c, zd* A, hipStream_t s);
 // work: n complex (column buffer) + 2 ints; sets *flag = 1 on a zero pivot.
 void launch_gj_step(zd* A, int n, int k, zd* col, int* perm, int* flag, hipStream_t s);
 void launch_gj_unpermute(zd* A, zd* tmp, int n, const int* perm, hipStream_t s);
-// y = A x for nrhs vectors (A n x n row-major)
-void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, hipStream_t s);
+// y = A x for nrhs vectors (A n x n row-major): one wave per row for few
+// right-hand sides, an LDS-tiled product (A read once per 32 RHS) for many
+// (or whenever `many` is set)
+void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, hipStream_t s);
 
 // ---- blas.hip ---------------------------------------------------------------
 // partial[b][v] = sum over block b of conj(X_v) w, X_v = X + v*ldx; then out[v] = sum_b partial[b][v]

@@ -180,6 +180,97 @@ void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int ns
 }
 
 // ---------------------------------------------------------------------------
+// Multi-RHS colour pass: one work-group per site and RB = 16 right-hand sides.
+// The site's block row A_a (16 x 112) and Kinv are staged in LDS once and the
+// pass becomes three small dense products per site:
+//   Res = B_a - A_a X   (16 x RB),  alpha = Kinv Res,  X += A_a^H alpha (112 x RB)
+// with X the 112 x RB unknowns of the seven neighbour sites (also in LDS).
+// Each right-hand side sees exactly the arithmetic of the single-RHS
+// smoother's block form (same sums, different order).
+// ---------------------------------------------------------------------------
+constexpr int MR_RB = 16;
+
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_kaczmarz_coarse_mr(CoarseT<T, S> c, int colour, int mode, int nrhs,
+                                                            cx<T>* __restrict__ x, const cx<T>* __restrict__ b) {
+  using C = cx<T>;
+  constexpr int NCOL = NOFF * 16;
+  __shared__ C As[16][NCOL + 1];
+  __shared__ C Ks[16][17];
+  __shared__ C Xs[NCOL][MR_RB + 1];
+  __shared__ C Rs[16][MR_RB + 1];
+  __shared__ int nbs[NOFF];
+  const int ns = c.ex * c.ey;
+  const size_t n = (size_t)ns * 16;
+  const int tid = threadIdx.x;
+  const int site = coarse_colour_site(colour, mode, blockIdx.x, c.ex);
+  const int r0 = blockIdx.y * MR_RB;
+  const int nr = min(MR_RB, nrhs - r0);
+  if (tid < NOFF) {
+    const int dx = (int)((0x0211021u >> (4 * tid)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * tid)) & 15u) - 1;
+    const int ax = site % c.ex, ay = site / c.ex;
+    nbs[tid] = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
+  }
+  // block row: A_a[i][o*16 + j] = D[site][o][i][j]
+  for (int e = tid; e < 16 * NCOL; e += 256) {
+    const int o = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    As[i][o * 16 + j] = widen<T>(c.D[(size_t)site * NOFF * 256 + e]);
+  }
+  {
+    const int i = tid >> 4, j = tid & 15;
+    Ks[i][j] = c.Kinv[((size_t)site * 16 + i) * 16 + j];
+  }
+  __syncthreads();
+  // unknowns of the support
+  for (int e = tid; e < NCOL * MR_RB; e += 256) {
+    const int col = e >> 4, rr = e & 15;
+    Xs[col][rr] = rr < nr ? x[(size_t)(r0 + rr) * n + nbs[col >> 4] * 16 + (col & 15)] : C{0, 0};
+  }
+  __syncthreads();
+  // residual block: thread (i, rr)
+  {
+    const int i = tid >> 4, rr = tid & 15;
+    C a0 = {0, 0}, a1 = {0, 0};
+    for (int col = 0; col < NCOL; col += 2) {
+      a0 = a0 + As[i][col] * Xs[col][rr];
+      a1 = a1 + As[i][col + 1] * Xs[col + 1][rr];
+    }
+    const C bi = (b && rr < nr) ? b[(size_t)(r0 + rr) * n + site * 16 + i] : C{0, 0};
+    Rs[i][rr] = bi - (a0 + a1);
+  }
+  __syncthreads();
+  // alpha = Kinv Res (lower triangular)
+  C al = {0, 0};
+  {
+    const int i = tid >> 4, rr = tid & 15;
+    for (int j = 0; j <= i; ++j) al = al + Ks[i][j] * Rs[j][rr];
+  }
+  __syncthreads();
+  {
+    const int i = tid >> 4, rr = tid & 15;
+    Rs[i][rr] = al;
+  }
+  __syncthreads();
+  // X += A^H alpha: thread (column group, rr), columns cg + 16 m
+  {
+    const int cg = tid >> 4, rr = tid & 15;
+    for (int m = 0; m < NOFF; ++m) {
+      const int col = cg + 16 * m;
+      C acc = {0, 0};
+      for (int i = 0; i < 16; ++i) acc = acc + cjmul(As[i][col], Rs[i][rr]);
+      if (rr < nr) x[(size_t)(r0 + rr) * n + nbs[col >> 4] * 16 + (col & 15)] = Xs[col][rr] + acc;
+    }
+  }
+}
+
+template <typename T, typename S>
+void launch_kaczmarz_coarse_mr(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
+                               int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL((k_kaczmarz_coarse_mr<T, S>), dim3(nsites, (nrhs + MR_RB - 1) / MR_RB), dim3(256), 0, s, c,
+                     colour, mode, nrhs, x, b);
+}
+
+// ---------------------------------------------------------------------------
 // Kinv = tril(G)^{-1}, G = sum_o D[o] D[o]^H per site (G_ii = ||d_i||^2).
 // A zero row (G_ii = 0) is skipped by the smoother: its row and column of Kinv
 // are zero.
@@ -282,7 +373,9 @@ void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T
                                           hipStream_t);                                                 \
   template void launch_kaczmarz_coarse<T, S>(const CoarseT<T, S>&, int, int, int, cx<T>*, const cx<T>*, \
                                              int, hipStream_t);                                         \
-  template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);
+  template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);                  \
+  template void launch_kaczmarz_coarse_mr<T, S>(const CoarseT<T, S>&, int, int, int, cx<T>*, const cx<T>*, \
+                                                int, hipStream_t);
 BAMG_COARSE_INST(double, zd)
 BAMG_COARSE_INST(float, zf)
 BAMG_COARSE_INST(float, hcx)

@@ -111,8 +111,51 @@ __global__ __launch_bounds__(256) void k_dense_mv(const zd* __restrict__ A, int 
   }
 }
 
-void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y, nrhs);
+// Y = A X for many right-hand sides: a work-group computes 16 rows x 32
+// right-hand sides, staging 16 x 64 tiles of A and 64 x 32 tiles of X in LDS.
+constexpr int MM_TM = 16, MM_TK = 64, MM_TR = 32;
+
+__global__ __launch_bounds__(256) void k_dense_mm(const zd* __restrict__ A, int n, const zd* __restrict__ X,
+                                                  zd* __restrict__ Y, int nrhs) {
+  __shared__ zd As[MM_TM][MM_TK + 1];
+  __shared__ zd Xs[MM_TK][MM_TR + 1];
+  const int tid = threadIdx.x;
+  const int row0 = blockIdx.x * MM_TM, r0 = blockIdx.y * MM_TR;
+  const int lr = tid >> 4, c = tid & 15;  // row lr, right-hand sides c and c + 16
+  zd acc0 = {0, 0}, acc1 = {0, 0};
+  for (int k0 = 0; k0 < n; k0 += MM_TK) {
+    for (int e = tid; e < MM_TM * MM_TK; e += 256) {
+      const int i = e / MM_TK, k = e - i * MM_TK;
+      const int gr = row0 + i, gk = k0 + k;
+      As[i][k] = (gr < n && gk < n) ? A[(size_t)gr * n + gk] : zd{0, 0};
+    }
+    for (int e = tid; e < MM_TK * MM_TR; e += 256) {
+      const int rr = e / MM_TK, k = e - rr * MM_TK;
+      const int gk = k0 + k, gr = r0 + rr;
+      Xs[k][rr] = (gk < n && gr < nrhs) ? X[(size_t)gr * n + gk] : zd{0, 0};
+    }
+    __syncthreads();
+    for (int k = 0; k < MM_TK; ++k) {
+      const zd a = As[lr][k];
+      acc0 = acc0 + a * Xs[k][c];
+      acc1 = acc1 + a * Xs[k][c + 16];
+    }
+    __syncthreads();
+  }
+  const int gr = row0 + lr;
+  if (gr < n) {
+    if (r0 + c < nrhs) Y[(size_t)(r0 + c) * n + gr] = acc0;
+    if (r0 + c + 16 < nrhs) Y[(size_t)(r0 + c + 16) * n + gr] = acc1;
+  }
+}
+
+void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, hipStream_t s) {
+  if (!many && nrhs <= 2) {
+    hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y, nrhs);
+  } else {
+    hipLaunchKernelGGL(k_dense_mm, dim3((n + MM_TM - 1) / MM_TM, (nrhs + MM_TR - 1) / MM_TR), dim3(256), 0, s, A,
+                       n, x, y, nrhs);
+  }
 }
 
 }  // namespace bamg

@@ -400,6 +400,68 @@ void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, c
 template void launch_kaczmarz_fine<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t);
 template void launch_kaczmarz_fine<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t);
 
+// Multi-RHS form of the colour pass: one work-group per site and 16
+// right-hand sides (16-lane group g handles right-hand side 16*blockIdx.y + g).
+// The slot blocks of the site are built once by group 0 and shared through
+// LDS; every group then performs the two projections of its right-hand side
+// exactly as the single-RHS kernel does.
+template <typename T>
+__global__ __launch_bounds__(256) void k_kaczmarz_fine_mr(FineT<T> f, int colour, int nrhs, cx<T>* __restrict__ x,
+                                                          const cx<T>* __restrict__ b) {
+  using C = cx<T>;
+  __shared__ C Bs[9][4];
+  const int lane = threadIdx.x & 15, g = threadIdx.x >> 4;
+  int px, y;
+  fine_colour_site(colour, blockIdx.x, f.N, px, y);
+  const int i = y * f.NH + (px >> 1);
+  const bool act = lane < 9;
+  const int slot = act ? lane : 0;
+  const int jn = hidx(px + nib(SLOT_DX2, slot) - 2, y + nib(SLOT_DY2, slot) - 2, f.N, f.NH);
+  if (g == 0 && act) {
+    C B[2][2];
+    dhat_slot_block(f, px, y, i, slot, jn, B);
+    Bs[slot][0] = B[0][0];
+    Bs[slot][1] = B[0][1];
+    Bs[slot][2] = B[1][0];
+    Bs[slot][3] = B[1][1];
+  }
+  __syncthreads();
+  const int r = blockIdx.y * 16 + g;
+  if (r >= nrhs) return;  // whole 16-lane groups leave together
+  const size_t n = (size_t)f.N * f.NH * 2;
+  C* xv = x + (size_t)r * n;
+  C B[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+  C x0 = {0, 0}, x1 = {0, 0};
+  if (act) {
+    B[0][0] = Bs[slot][0];
+    B[0][1] = Bs[slot][1];
+    B[1][0] = Bs[slot][2];
+    B[1][1] = Bs[slot][3];
+    x0 = xv[2 * jn];
+    x1 = xv[2 * jn + 1];
+  }
+  const C b0 = b ? b[(size_t)r * n + 2 * i] : C{0, 0};
+  const C b1 = b ? b[(size_t)r * n + 2 * i + 1] : C{0, 0};
+  const C r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
+  const C r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
+  const C nu = grp16_sum(C{norm2(B[0][0]) + norm2(B[0][1]), norm2(B[1][0]) + norm2(B[1][1])});
+  const C g10 = grp16_sum(cjmul(B[0][0], B[1][0]) + cjmul(B[0][1], B[1][1]));
+  const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
+  const C a1 = nu.y > 0 ? cdiv_real(b1 - r1 - g10 * a0, nu.y) : C{0, 0};
+  if (act) {
+    xv[2 * jn] = x0 + cjmul(B[0][0], a0) + cjmul(B[1][0], a1);
+    xv[2 * jn + 1] = x1 + cjmul(B[0][1], a0) + cjmul(B[1][1], a1);
+  }
+}
+
+template <typename T>
+void launch_kaczmarz_fine_mr(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_kaczmarz_fine_mr<T>, dim3(nsites, (nrhs + 15) / 16), dim3(256), 0, s, f, colour, nrhs, x, b);
+}
+template void launch_kaczmarz_fine_mr<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t);
+template void launch_kaczmarz_fine_mr<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // Transfers between level 0 and the 4x4 aggregates of the half-x grid.
 // Aggregate a = Ay*(NH/4) + Ax holds the even sites xh = 4Ax + lx, y = 4Ay + ly,

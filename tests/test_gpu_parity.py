@@ -77,8 +77,9 @@ def test_eo_reduce_reconstruct(bamg, N, nrhs):
     assert rel(host(x), oracle.eo_reconstruct(U, m, b, xe).reshape(nrhs, -1)) < 1e-13
 
 
-@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1)])
+@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (64, 17)])
 def test_fine_kaczmarz_sweep(bamg, N, nrhs):
+    """nrhs >= 4 runs the multi-RHS kernel (slot blocks shared by 16 RHS)."""
     log(f"kaczmarz fine N={N}")
     U = inputs.gauge_random(N, 7)
     m = 0.02
@@ -162,15 +163,17 @@ def test_level_apply(bamg, imported, l):
     assert rel(host(y), o.apply(l, x, nrhs=2).reshape(2, n)) < 1e-12
 
 
-def test_coarse_kaczmarz_sweep(bamg, imported):
+@pytest.mark.parametrize("nrhs", [2, 5, 19])
+def test_coarse_kaczmarz_sweep(bamg, imported, nrhs):
+    """nrhs >= 4 runs the multi-RHS kernel (block row staged once per 16 RHS)."""
     N, U, m, h, o = imported
     l = 1
     n = bamg.bamg_level_info(h, l)["n"]
-    x0 = inputs.gaussian((2, n), 70)
-    b = inputs.gaussian((2, n), 71)
+    x0 = inputs.gaussian((nrhs, n), 70)
+    b = inputs.gaussian((nrhs, n), 71)
     x = dev(x0)
-    bamg.bamg_level_op(h, l, bamg.OP_SWEEP, dev(b), x, 2)
-    ref = o.sweep(l, x0, b, nrhs=2).reshape(2, n)
+    bamg.bamg_level_op(h, l, bamg.OP_SWEEP, dev(b), x, nrhs)
+    ref = o.sweep(l, x0, b, nrhs=nrhs).reshape(nrhs, n)
     # block form tril(G)^-1 of the 16 sequential projections: rounding
     # differences scale with cond(tril(G)); random P keeps it moderate
     assert rel(host(x), ref) < 1e-11
@@ -190,13 +193,14 @@ def test_coarsest_solve(bamg, imported):
     assert rel(host(x), ref) < max(1e-12, 10 * kappa * 2.2e-16)
 
 
-def test_cycle(bamg, imported):
+@pytest.mark.parametrize("nrhs", [2, 6])
+def test_cycle(bamg, imported, nrhs):
     N, U, m, h, o = imported
     n = N * N
-    b = inputs.gaussian((2, n), 90)
-    x = torch.zeros(2, n, dtype=torch.complex128, device="cuda:0")
-    bamg.bamg_level_op(h, 0, bamg.OP_CYCLE, dev(b), x, 2)
-    ref = o.cycle(b, nrhs=2).reshape(2, n)
+    b = inputs.gaussian((nrhs, n), 90)
+    x = torch.zeros(nrhs, n, dtype=torch.complex128, device="cuda:0")
+    bamg.bamg_level_op(h, 0, bamg.OP_CYCLE, dev(b), x, nrhs)
+    ref = o.cycle(b, nrhs=nrhs).reshape(nrhs, n)
     kappa = np.linalg.cond(o.operator(2).toarray())
     log(f"cycle diff {rel(host(x), ref):.2e}")
     assert rel(host(x), ref) < max(1e-11, 10 * kappa * 2.2e-16)
@@ -289,25 +293,31 @@ def test_not_converged_status(bamg):
     assert np.isfinite(host(x)).all()
 
 
-def test_batch_equals_single_solves(bamg, c1):
-    """Each right-hand side of a batched solve gives the result of its own solve
-    (the kernels treat right-hand sides independently with fixed reduction
-    orders): identical iteration counts and bitwise-equal solutions."""
+def test_batch_results_do_not_depend_on_the_batch(bamg, c1):
+    """Each right-hand side of a batched solve gives bitwise the result of a
+    batched solve of that right-hand side alone (the batched path uses the
+    same kernels for every batch size and treats right-hand sides
+    independently with fixed reduction orders), and the result of the
+    single-RHS solver up to rounding."""
     w, U, h, o = c1
     N = w["N"]
-    R = 3
+    R = 5
     B = inputs.gaussian((R, 2 * N * N), 555)
     B[1] *= 1e-3  # different scales converge at different iterations
+    B[3] = inputs.gaussian(2 * N * N, 556) + 1e2 * B[3]
     X = torch.zeros(R, 2 * N * N, dtype=torch.complex128, device="cuda:0")
     st, infos = bamg.bamg_solve_batch(h, dev(B), X, R, 1e-10)
     assert st == 0
     Xb = host(X)
     for r in range(R):
+        x1 = torch.zeros(1, 2 * N * N, dtype=torch.complex128, device="cuda:0")
+        st1, inf1 = bamg.bamg_solve_batch(h, dev(B[r:r + 1]), x1, 1, 1e-10)
+        assert st1 == 0 and inf1[0]["iters"] == infos[r]["iters"]
+        assert np.array_equal(host(x1)[0], Xb[r])
         x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
-        st1, info = bamg.bamg_solve(h, dev(B[r]), x, 1e-10)
-        assert st1 == 0
-        assert info["iters"] == infos[r]["iters"]
-        assert np.array_equal(host(x), Xb[r])
+        st2, info = bamg.bamg_solve(h, dev(B[r]), x, 1e-10)
+        assert st2 == 0 and abs(info["iters"] - infos[r]["iters"]) <= 1
+        assert rel(host(x), Xb[r]) < 1e-9
 
 
 # ---------------------------------------------------------------- mixed precision
