@@ -111,14 +111,15 @@ struct bamg_hierarchy {
   double m = 0;
   hipStream_t s = nullptr;
   Fine f;
-  zd *Ue = nullptr, *Uo = nullptr;
+  zd *Ue = nullptr, *Uo = nullptr, *Bst = nullptr;
   FineT<float> f32;
-  zf *Ue32 = nullptr, *Uo32 = nullptr;
+  zf *Ue32 = nullptr, *Uo32 = nullptr, *Bst32 = nullptr;
   std::vector<Level> lv;
   int cap = 0;  // right-hand sides the work vectors hold
   // batched path: multi-RHS kernels for every batch size, so that a right-hand
   // side's arithmetic does not depend on how many others share the batch
   bool force_mr = false;
+  zd* mmwork = nullptr;  // split-K partials of the coarsest product, cap right-hand sides
   // coarsest inversion scratch
   zd* gjcol = nullptr;
   int* gjperm = nullptr;
@@ -175,7 +176,8 @@ struct bamg_hierarchy {
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
       dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
     }
-    dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(gjcol); dfree(gjperm); dfree(dflag);
+    dfree(mmwork);
+    dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(Bst); dfree(Bst32); dfree(gjcol); dfree(gjperm); dfree(dflag);
     if (hflag) (void)hipHostFree(hflag);
     free_krylov();
     dfree(tvsave);
@@ -188,6 +190,9 @@ struct bamg_hierarchy {
 
   void ensure_cap(int nrhs) {
     if (nrhs <= cap) return;
+    dfree(mmwork);
+    mmwork = nullptr;
+    if (L() > 1) mmwork = dalloc<zd>(dense_mm_workspace((int)lv.back().n, nrhs));
     for (auto& Lv : lv) {
       dfree(Lv.x); dfree(Lv.b); dfree(Lv.r);
       dfree(Lv.x32); dfree(Lv.b32); dfree(Lv.r32);
@@ -212,15 +217,9 @@ struct bamg_hierarchy {
   }
   void sweep(int l, zd* x, const zd* b, int nrhs) {
     Level& Lv = lv[l];
-    const bool mr = force_mr || nrhs >= MR_MIN;
     for (int c = 0; c < Lv.ncol; ++c) {
-      if (l == 0) {
-        if (mr) launch_kaczmarz_fine_mr(f, c, Lv.per_colour, x, b, nrhs, s);
-        else launch_kaczmarz_fine(f, c, Lv.per_colour, x, b, nrhs, s);
-      } else {
-        if (mr) launch_kaczmarz_coarse_mr(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
-        else launch_kaczmarz_coarse(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
-      }
+      if (l == 0) launch_kaczmarz_fine(f, c, Lv.per_colour, x, b, nrhs, s);
+      else launch_kaczmarz_coarse(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
     }
     check_launch();
   }
@@ -236,7 +235,8 @@ struct bamg_hierarchy {
   }
   void coarsest_solve(const zd* b, zd* x, int nrhs) {
     Level& Lv = lv.back();
-    launch_dense_mv(Lv.Ainv, (int)Lv.n, b, x, nrhs, force_mr, s);
+    if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
+    launch_dense_mv(Lv.Ainv, (int)Lv.n, b, x, nrhs, force_mr, mmwork, s);
     check_launch();
   }
 
@@ -288,10 +288,9 @@ struct bamg_hierarchy {
     const bool mr = force_mr || nrhs >= MR_MIN;
     for (int c = 0; c < Lv.ncol; ++c) {
       if (l == 0) {
-        if (mr) launch_kaczmarz_fine_mr(f32, c, Lv.per_colour, x, b, nrhs, s);
-        else launch_kaczmarz_fine(f32, c, Lv.per_colour, x, b, nrhs, s);
+        launch_kaczmarz_fine(f32, c, Lv.per_colour, x, b, nrhs, s);
       } else {
-        if (mr) launch_kaczmarz_coarse_mr(coarse32<S>(l), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
+        if (mr) launch_kaczmarz_coarse_mfma(coarse32<S>(l), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
         else launch_kaczmarz_coarse(coarse32<S>(l), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
       }
     }
@@ -305,8 +304,9 @@ struct bamg_hierarchy {
     }
     if (coarsest(l)) {
       Level& C = lv[l];
+      if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
       launch_convert(b, C.b, C.n * nrhs, s);
-      launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, force_mr, s);
+      launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, force_mr, mmwork, s);
       launch_convert(C.x, x, C.n * nrhs, s);
       check_launch();
       return;
@@ -373,6 +373,9 @@ struct bamg_hierarchy {
     launch_convert(Uo, Uo32, nl, s);
     f32.N = f.N; f32.NH = f.NH; f32.c = f.c; f32.kappa = f.kappa; f32.kappa2 = f.kappa2;
     f32.Ue = Ue32; f32.Uo = Uo32;
+    if (!Bst32) Bst32 = dalloc<zf>(nl / 2 * 36);
+    launch_slot_blocks(f32, Bst32, s);
+    f32.Bst = Bst32;
     for (int l = 0; l < L(); ++l) {
       Level& Lv = lv[l];
       if (Lv.P) {
@@ -535,7 +538,7 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
   Shape sh;
   if (!valid_params(p, why) || !level_shapes(p, sh, why)) return 0;
   const size_t N = p->N, k = p->n_tv, z = sizeof(zd);
-  size_t bytes = 2 * N * N * z;  // links
+  size_t bytes = 2 * N * N * z + (N * N / 2) * 36 * z;  // links, stored slot blocks of Dhat
   const int L = (int)sh.ext.size();
   for (int l = 0; l < L; ++l) {
     const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
@@ -577,6 +580,9 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
     h->f.Ue = h->Ue;
     h->f.Uo = h->Uo;
     launch_gauge_pack((const zd*)gauge, h->Ue, h->Uo, N, h->s);
+    h->Bst = dalloc<zd>((size_t)N * N / 2 * 36);
+    launch_slot_blocks(h->f, h->Bst, h->s);
+    h->f.Bst = h->Bst;
     check_launch();
     const int L = (int)sh.ext.size(), k = p->n_tv;
     const bool mg = L > 1;
@@ -711,6 +717,7 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         break;
       case BAMG_OP_COARSEST:
         if (!h->coarsest(l) || h->L() == 1) return fail(BAMG_EINVAL, "level is not a directly solved coarsest level");
+        h->ensure_cap(nrhs);  // the split-K product needs workspace for nrhs right-hand sides
         h->coarsest_solve(xi, xo, nrhs);
         break;
       case BAMG_OP_CYCLE:

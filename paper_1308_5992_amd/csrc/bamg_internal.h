@@ -82,6 +82,7 @@ struct FineT {
   double c = 0, kappa = 0, kappa2 = 0;  // c = m + 2, kappa = 1/c
   const cx<T>* Ue = nullptr;
   const cx<T>* Uo = nullptr;
+  const cx<T>* Bst = nullptr;  // stored slot blocks of Dhat, [site][9][4] (smoother)
 };
 using Fine = FineT<double>;
 
@@ -92,14 +93,14 @@ void launch_eo_reconstruct(const Fine& f, const zd* b, const zd* xe, zd* x, int 
 // y = Dhat x, or y = b - Dhat x if b != nullptr  (T = double or float)
 template <typename T>
 void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s);
+// Bst[site][slot][4]: the 2x2 blocks of Dhat coupling each even site to its 9
+// stencil slots (built from the links)
+template <typename T>
+void launch_slot_blocks(const FineT<T>& f, cx<T>* Bst, hipStream_t s);
 // one colour pass over the nsites = N^2/32 sites of fine colour `colour`
 template <typename T>
 void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
                           hipStream_t s);
-// the same pass for many right-hand sides: slot blocks built once per site and 16 RHS
-template <typename T>
-void launch_kaczmarz_fine_mr(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
-                             hipStream_t s);
 // rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
 template <typename T>
 void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);
@@ -127,10 +128,10 @@ void launch_coarse_apply(const CoarseT<T, S>& c, const cx<T>* x, cx<T>* y, const
 template <typename T, typename S>
 void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
                             int nrhs, hipStream_t s);
-// the same pass for many right-hand sides: operator staged once per site and 16 RHS
-template <typename T, typename S>
-void launch_kaczmarz_coarse_mr(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
-                               int nrhs, hipStream_t s);
+// the same pass on the matrix cores (FP32 arithmetic, one wave per site and 16 RHS)
+template <typename S>
+void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mode, int nsites, zf* x, const zf* b,
+                                 int nrhs, hipStream_t s);
 // Kinv (type T) from the stored operator (type S), computed in FP64
 template <typename T, typename S>
 void launch_kaczmarz_prep(const CoarseT<T, S>& c, cx<T>* Kinv, hipStream_t s);
@@ -151,8 +152,9 @@ void launch_gj_step(zd* A, int n, int k, zd* col, int* perm, int* flag, hipStrea
 void launch_gj_unpermute(zd* A, zd* tmp, int n, const int* perm, hipStream_t s);
 // y = A x for nrhs vectors (A n x n row-major): one wave per row for few
 // right-hand sides, an LDS-tiled product (A read once per 32 RHS) for many
-// (or whenever `many` is set)
-void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, hipStream_t s);
+// (or whenever `many` is set; work holds dense_mm_workspace(n, nrhs) complex)
+void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, zd* work, hipStream_t s);
+size_t dense_mm_workspace(int n, int nrhs);
 
 // ---- blas.hip ---------------------------------------------------------------
 // partial[b][v] = sum over block b of conj(X_v) w, X_v = X + v*ldx; then out[v] = sum_b partial[b][v]

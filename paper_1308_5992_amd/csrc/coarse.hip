@@ -180,95 +180,155 @@ void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int ns
 }
 
 // ---------------------------------------------------------------------------
-// Multi-RHS colour pass: one work-group per site and RB = 16 right-hand sides.
-// The site's block row A_a (16 x 112) and Kinv are staged in LDS once and the
-// pass becomes three small dense products per site:
-//   Res = B_a - A_a X   (16 x RB),  alpha = Kinv Res,  X += A_a^H alpha (112 x RB)
-// with X the 112 x RB unknowns of the seven neighbour sites (also in LDS).
-// Each right-hand side sees exactly the arithmetic of the single-RHS
-// smoother's block form (same sums, different order).
+// Multi-RHS colour pass on the matrix cores (FP32 arithmetic, operator in its
+// storage type S): one wave per site and 16 right-hand sides.  The three
+// products of the block form run as real 16x16x4 FP32 MFMA tiles on the real
+// and imaginary parts:
+//   R = A X       (16 x 112) (112 x 16):  28 K-steps x 4 MFMA
+//   alpha = Kinv (B - R)  (16 x 16) (16 x 16): 4 K-steps x 4 MFMA
+//   X += A^H alpha  (112 x 16) (16 x 16):  7 tiles x 4 K-steps x 4 MFMA
+// MFMA lane layout (v_mfma_f32_16x16x4f32): lane l supplies A[l%16][k0 + l/16]
+// and B[k0 + l/16][l%16] and receives C[4(l/16) + e][l%16], e = 0..3.
+// The unknowns of the support go through LDS so that the global loads and
+// stores run along the site dimension of each right-hand side.
 // ---------------------------------------------------------------------------
-constexpr int MR_RB = 16;
+typedef float mf4 __attribute__((ext_vector_type(4)));
 
-template <typename T, typename S>
-__global__ __launch_bounds__(256) void k_kaczmarz_coarse_mr(CoarseT<T, S> c, int colour, int mode, int nrhs,
-                                                            cx<T>* __restrict__ x, const cx<T>* __restrict__ b) {
-  using C = cx<T>;
+__device__ __forceinline__ mf4 mfma4(float a, float b, mf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename S>
+__global__ __launch_bounds__(64) void k_kaczmarz_coarse_mfma(CoarseT<float, S> c, int colour, int mode, int nrhs,
+                                                             zf* __restrict__ x, const zf* __restrict__ b) {
   constexpr int NCOL = NOFF * 16;
-  __shared__ C As[16][NCOL + 1];
-  __shared__ C Ks[16][17];
-  __shared__ C Xs[NCOL][MR_RB + 1];
-  __shared__ C Rs[16][MR_RB + 1];
-  __shared__ int nbs[NOFF];
+  __shared__ float Xr[NCOL][17], Xi[NCOL][17];
+  __shared__ float Vr[16][17], Vi[16][17];  // right-hand side block, then residual, then alpha
+  const int l = threadIdx.x, lm = l & 15, lq = l >> 4;
   const int ns = c.ex * c.ey;
   const size_t n = (size_t)ns * 16;
-  const int tid = threadIdx.x;
   const int site = coarse_colour_site(colour, mode, blockIdx.x, c.ex);
-  const int r0 = blockIdx.y * MR_RB;
-  const int nr = min(MR_RB, nrhs - r0);
-  if (tid < NOFF) {
-    const int dx = (int)((0x0211021u >> (4 * tid)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * tid)) & 15u) - 1;
-    const int ax = site % c.ex, ay = site / c.ex;
-    nbs[tid] = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
+  const int r0 = blockIdx.y * 16;
+  const int nr = min(16, nrhs - r0);
+  const int ax = site % c.ex, ay = site / c.ex;
+  int nb[NOFF];
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    const int dx = (int)((0x0211021u >> (4 * o)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * o)) & 15u) - 1;
+    nb[o] = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
   }
-  // block row: A_a[i][o*16 + j] = D[site][o][i][j]
-  for (int e = tid; e < 16 * NCOL; e += 256) {
-    const int o = e >> 8, i = (e >> 4) & 15, j = e & 15;
-    As[i][o * 16 + j] = widen<T>(c.D[(size_t)site * NOFF * 256 + e]);
-  }
-  {
-    const int i = tid >> 4, j = tid & 15;
-    Ks[i][j] = c.Kinv[((size_t)site * 16 + i) * 16 + j];
-  }
-  __syncthreads();
-  // unknowns of the support
-  for (int e = tid; e < NCOL * MR_RB; e += 256) {
-    const int col = e >> 4, rr = e & 15;
-    Xs[col][rr] = rr < nr ? x[(size_t)(r0 + rr) * n + nbs[col >> 4] * 16 + (col & 15)] : C{0, 0};
-  }
-  __syncthreads();
-  // residual block: thread (i, rr)
-  {
-    const int i = tid >> 4, rr = tid & 15;
-    C a0 = {0, 0}, a1 = {0, 0};
-    for (int col = 0; col < NCOL; col += 2) {
-      a0 = a0 + As[i][col] * Xs[col][rr];
-      a1 = a1 + As[i][col + 1] * Xs[col + 1][rr];
+  // stage X (112 x 16) and the right-hand side block (16 x 16)
+  for (int e = l; e < NCOL * 16; e += 64) {
+    const int rr = e / NCOL, col = e - rr * NCOL;
+    zf v = {0, 0};
+    if (rr < nr) {
+      int nbo = nb[0];
+#pragma unroll
+      for (int o = 1; o < NOFF; ++o)
+        if ((col >> 4) == o) nbo = nb[o];
+      v = x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)];
     }
-    const C bi = (b && rr < nr) ? b[(size_t)(r0 + rr) * n + site * 16 + i] : C{0, 0};
-    Rs[i][rr] = bi - (a0 + a1);
+    Xr[col][rr] = v.x;
+    Xi[col][rr] = v.y;
+  }
+  for (int e = l; e < 256; e += 64) {
+    const int rr = e >> 4, i = e & 15;
+    const zf v = (b && rr < nr) ? b[(size_t)(r0 + rr) * n + site * 16 + i] : zf{0, 0};
+    Vr[i][rr] = v.x;
+    Vi[i][rr] = v.y;
   }
   __syncthreads();
-  // alpha = Kinv Res (lower triangular)
-  C al = {0, 0};
-  {
-    const int i = tid >> 4, rr = tid & 15;
-    for (int j = 0; j <= i; ++j) al = al + Ks[i][j] * Rs[j][rr];
+  // R = A X: A[i][k] = D[site][k/16][i][k%16]
+  const S* Dsite = c.D + (size_t)site * NOFF * 256;
+  mf4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < NCOL; k0 += 4) {
+    const int k = k0 + lq;
+    const zf a = widen<float>(Dsite[(k >> 4) * 256 + lm * 16 + (k & 15)]);
+    const float xr = Xr[k][lm], xi = Xi[k][lm];
+    cr = mfma4(a.x, xr, cr);
+    cr = mfma4(-a.y, xi, cr);
+    ci = mfma4(a.x, xi, ci);
+    ci = mfma4(a.y, xr, ci);
+  }
+  // residual B - R into V (lane holds rows 4 lq + e, column lm)
+  float resr[4], resi[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    resr[e] = Vr[4 * lq + e][lm] - cr[e];
+    resi[e] = Vi[4 * lq + e][lm] - ci[e];
   }
   __syncthreads();
-  {
-    const int i = tid >> 4, rr = tid & 15;
-    Rs[i][rr] = al;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    Vr[4 * lq + e][lm] = resr[e];
+    Vi[4 * lq + e][lm] = resi[e];
   }
   __syncthreads();
-  // X += A^H alpha: thread (column group, rr), columns cg + 16 m
-  {
-    const int cg = tid >> 4, rr = tid & 15;
-    for (int m = 0; m < NOFF; ++m) {
-      const int col = cg + 16 * m;
-      C acc = {0, 0};
-      for (int i = 0; i < 16; ++i) acc = acc + cjmul(As[i][col], Rs[i][rr]);
-      if (rr < nr) x[(size_t)(r0 + rr) * n + nbs[col >> 4] * 16 + (col & 15)] = Xs[col][rr] + acc;
+  // alpha = Kinv (B - R)
+  const zf* Ks = c.Kinv + (size_t)site * 256;
+  mf4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    const int k = k0 + lq;
+    const zf a = Ks[lm * 16 + k];
+    const float vr = Vr[k][lm], vi = Vi[k][lm];
+    gr = mfma4(a.x, vr, gr);
+    gr = mfma4(-a.y, vi, gr);
+    gi = mfma4(a.x, vi, gi);
+    gi = mfma4(a.y, vr, gi);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    Vr[4 * lq + e][lm] = gr[e];
+    Vi[4 * lq + e][lm] = gi[e];
+  }
+  __syncthreads();
+  // X += A^H alpha, tile o: rows (columns of A) 16 o + m, A^H[m][i] = conj(A[i][16 o + m])
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    mf4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+      const int i = k0 + lq;
+      const zf a = widen<float>(Dsite[o * 256 + i * 16 + lm]);
+      const float vr = Vr[i][lm], vi = Vi[i][lm];
+      // (a.x - i a.y)(vr + i vi) = (a.x vr + a.y vi) + i (a.x vi - a.y vr)
+      ur = mfma4(a.x, vr, ur);
+      ur = mfma4(a.y, vi, ur);
+      ui = mfma4(a.x, vi, ui);
+      ui = mfma4(-a.y, vr, ui);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int col = 16 * o + 4 * lq + e;
+      Xr[col][lm] += ur[e];
+      Xi[col][lm] += ui[e];
+    }
+  }
+  __syncthreads();
+  for (int e = l; e < NCOL * 16; e += 64) {
+    const int rr = e / NCOL, col = e - rr * NCOL;
+    if (rr < nr) {
+      int nbo = nb[0];
+#pragma unroll
+      for (int o = 1; o < NOFF; ++o)
+        if ((col >> 4) == o) nbo = nb[o];
+      x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)] = zf{Xr[col][rr], Xi[col][rr]};
     }
   }
 }
 
-template <typename T, typename S>
-void launch_kaczmarz_coarse_mr(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
-                               int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL((k_kaczmarz_coarse_mr<T, S>), dim3(nsites, (nrhs + MR_RB - 1) / MR_RB), dim3(256), 0, s, c,
-                     colour, mode, nrhs, x, b);
+template <typename S>
+void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mode, int nsites, zf* x, const zf* b,
+                                 int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL((k_kaczmarz_coarse_mfma<S>), dim3(nsites, (nrhs + 15) / 16), dim3(64), 0, s, c, colour, mode,
+                     nrhs, x, b);
 }
+template void launch_kaczmarz_coarse_mfma<zf>(const CoarseT<float, zf>&, int, int, int, zf*, const zf*, int,
+                                              hipStream_t);
+template void launch_kaczmarz_coarse_mfma<hcx>(const CoarseT<float, hcx>&, int, int, int, zf*, const zf*, int,
+                                               hipStream_t);
+template void launch_kaczmarz_coarse_mfma<bcx>(const CoarseT<float, bcx>&, int, int, int, zf*, const zf*, int,
+                                               hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Kinv = tril(G)^{-1}, G = sum_o D[o] D[o]^H per site (G_ii = ||d_i||^2).
@@ -373,9 +433,7 @@ void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T
                                           hipStream_t);                                                 \
   template void launch_kaczmarz_coarse<T, S>(const CoarseT<T, S>&, int, int, int, cx<T>*, const cx<T>*, \
                                              int, hipStream_t);                                         \
-  template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);                  \
-  template void launch_kaczmarz_coarse_mr<T, S>(const CoarseT<T, S>&, int, int, int, cx<T>*, const cx<T>*, \
-                                                int, hipStream_t);
+  template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);
 BAMG_COARSE_INST(double, zd)
 BAMG_COARSE_INST(float, zf)
 BAMG_COARSE_INST(float, hcx)

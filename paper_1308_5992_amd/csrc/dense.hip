@@ -111,50 +111,76 @@ __global__ __launch_bounds__(256) void k_dense_mv(const zd* __restrict__ A, int 
   }
 }
 
-// Y = A X for many right-hand sides: a work-group computes 16 rows x 32
-// right-hand sides, staging 16 x 64 tiles of A and 64 x 32 tiles of X in LDS.
-constexpr int MM_TM = 16, MM_TK = 64, MM_TR = 32;
+// Y = A X for many right-hand sides: split-K tiled product.  Work-group
+// (row tile, RHS tile, K quarter) computes a 32 x 32 tile over a quarter of
+// K with 32-wide K chunks staged in LDS (next chunk prefetched into
+// registers); the four partial tiles are summed in a fixed order by a second
+// kernel (deterministic, no atomics).
+constexpr int MM_T = 32, MM_K = 32, MM_SPLIT = 4;
 
 __global__ __launch_bounds__(256) void k_dense_mm(const zd* __restrict__ A, int n, const zd* __restrict__ X,
-                                                  zd* __restrict__ Y, int nrhs) {
-  __shared__ zd As[MM_TM][MM_TK + 1];
-  __shared__ zd Xs[MM_TK][MM_TR + 1];
+                                                  zd* __restrict__ part, int nrhs) {
+  __shared__ zd As[MM_T][MM_K + 1];
+  __shared__ zd Xs[MM_K][MM_T + 1];
   const int tid = threadIdx.x;
-  const int row0 = blockIdx.x * MM_TM, r0 = blockIdx.y * MM_TR;
-  const int lr = tid >> 4, c = tid & 15;  // row lr, right-hand sides c and c + 16
-  zd acc0 = {0, 0}, acc1 = {0, 0};
-  for (int k0 = 0; k0 < n; k0 += MM_TK) {
-    for (int e = tid; e < MM_TM * MM_TK; e += 256) {
-      const int i = e / MM_TK, k = e - i * MM_TK;
-      const int gr = row0 + i, gk = k0 + k;
-      As[i][k] = (gr < n && gk < n) ? A[(size_t)gr * n + gk] : zd{0, 0};
+  const int row0 = blockIdx.x * MM_T, r0 = blockIdx.y * MM_T;
+  const int kq = (n + MM_SPLIT - 1) / MM_SPLIT;
+  const int kbeg = blockIdx.z * kq, kend = min(n, kbeg + kq);
+  const int rr = tid & 31, rq = tid >> 5;  // right-hand side rr, rows 4 rq .. 4 rq + 3
+  zd acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  zd pa[4], px[4];
+  auto fetch = [&](int k0) {
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int i = e >> 5, k = e & 31;  // A tile element (row i, k) ; X tile element (rhs i, k)
+      const int gk = k0 + k;
+      pa[q] = (row0 + i < n && gk < kend) ? A[(size_t)(row0 + i) * n + gk] : zd{0, 0};
+      px[q] = (r0 + i < nrhs && gk < kend) ? X[(size_t)(r0 + i) * n + gk] : zd{0, 0};
     }
-    for (int e = tid; e < MM_TK * MM_TR; e += 256) {
-      const int rr = e / MM_TK, k = e - rr * MM_TK;
-      const int gk = k0 + k, gr = r0 + rr;
-      Xs[k][rr] = (gk < n && gr < nrhs) ? X[(size_t)gr * n + gk] : zd{0, 0};
+  };
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += MM_K) {
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int i = e >> 5, k = e & 31;
+      As[i][k] = pa[q];
+      Xs[k][i] = px[q];
     }
     __syncthreads();
-    for (int k = 0; k < MM_TK; ++k) {
-      const zd a = As[lr][k];
-      acc0 = acc0 + a * Xs[k][c];
-      acc1 = acc1 + a * Xs[k][c + 16];
+    if (k0 + MM_K < kend) fetch(k0 + MM_K);
+    for (int k = 0; k < MM_K; ++k) {
+      const zd xv = Xs[k][rr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = acc[j] + As[4 * rq + j][k] * xv;
     }
-    __syncthreads();
   }
-  const int gr = row0 + lr;
-  if (gr < n) {
-    if (r0 + c < nrhs) Y[(size_t)(r0 + c) * n + gr] = acc0;
-    if (r0 + c + 16 < nrhs) Y[(size_t)(r0 + c + 16) * n + gr] = acc1;
-  }
+  if (r0 + rr < nrhs)
+    for (int j = 0; j < 4; ++j) {
+      const int gr = row0 + 4 * rq + j;
+      if (gr < n) part[((size_t)blockIdx.z * nrhs + r0 + rr) * n + gr] = acc[j];
+    }
 }
 
-void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, hipStream_t s) {
+__global__ void k_dense_mm_reduce(const zd* __restrict__ part, int n, int nrhs, zd* __restrict__ Y) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t tot = (size_t)n * nrhs;
+  if (t >= tot) return;
+  zd s = part[t];
+  for (int q = 1; q < MM_SPLIT; ++q) s = s + part[(size_t)q * tot + t];
+  Y[t] = s;
+}
+
+size_t dense_mm_workspace(int n, int nrhs) { return (size_t)MM_SPLIT * n * nrhs; }
+
+void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, zd* work, hipStream_t s) {
   if (!many && nrhs <= 2) {
     hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y, nrhs);
   } else {
-    hipLaunchKernelGGL(k_dense_mm, dim3((n + MM_TM - 1) / MM_TM, (nrhs + MM_TR - 1) / MM_TR), dim3(256), 0, s, A,
-                       n, x, y, nrhs);
+    hipLaunchKernelGGL(k_dense_mm, dim3((n + MM_T - 1) / MM_T, (nrhs + MM_T - 1) / MM_T, MM_SPLIT), dim3(256), 0, s,
+                       A, n, x, work, nrhs);
+    const size_t tot = (size_t)n * nrhs;
+    hipLaunchKernelGGL(k_dense_mm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, n, nrhs, y);
   }
 }
 

@@ -348,6 +348,34 @@ __device__ __forceinline__ void dhat_slot_block(const FineT<T>& f, int x, int y,
   B[1][1] = C{one, 0} - k2q * b11;
 }
 
+// The slot blocks of every even site, stored once at setup (and after the
+// links change): Bst[site][slot][4] = (B00, B01, B10, B11).  The smoother
+// reads them instead of rebuilding them from the links in every pass.
+template <typename T>
+__global__ void k_slot_blocks(FineT<T> f, cx<T>* __restrict__ Bst) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= f.N * f.NH * 16) return;
+  const int i = t >> 4, slot = t & 15;
+  if (slot >= 9) return;
+  const int y = i / f.NH, xh = i - y * f.NH, px = 2 * xh + (y & 1);
+  const int jn = hidx(px + nib(SLOT_DX2, slot) - 2, y + nib(SLOT_DY2, slot) - 2, f.N, f.NH);
+  cx<T> B[2][2];
+  dhat_slot_block(f, px, y, i, slot, jn, B);
+  cx<T>* o = Bst + ((size_t)i * 9 + slot) * 4;
+  o[0] = B[0][0];
+  o[1] = B[0][1];
+  o[2] = B[1][0];
+  o[3] = B[1][1];
+}
+
+template <typename T>
+void launch_slot_blocks(const FineT<T>& f, cx<T>* Bst, hipStream_t s) {
+  const int n = f.N * f.NH * 16;
+  hipLaunchKernelGGL(k_slot_blocks<T>, dim3((n + 255) / 256), dim3(256), 0, s, f, Bst);
+}
+template void launch_slot_blocks<double>(const FineT<double>&, zd*, hipStream_t);
+template void launch_slot_blocks<float>(const FineT<float>&, zf*, hipStream_t);
+
 // t-th even site of fine colour c = 4a + b (a = (x+y)/2 mod 4, b = (x-y)/2 mod 4):
 // rows y = a - b (mod 4), and in such a row x = 2a - y (mod 8); N^2/32 sites.
 __device__ __forceinline__ void fine_colour_site(int c, int t, int N, int& x, int& y) {
@@ -380,7 +408,13 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
   const C b0 = b ? b[blockIdx.y * n + 2 * i] : C{0, 0};
   const C b1 = b ? b[blockIdx.y * n + 2 * i + 1] : C{0, 0};
   C B[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
-  if (act) dhat_slot_block(f, px, y, i, slot, jn, B);
+  if (act) {
+    const C* bp = f.Bst + ((size_t)i * 9 + slot) * 4;
+    B[0][0] = bp[0];
+    B[0][1] = bp[1];
+    B[1][0] = bp[2];
+    B[1][1] = bp[3];
+  }
   const C r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
   const C r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
   const C nu = grp16_sum(C{norm2(B[0][0]) + norm2(B[0][1]), norm2(B[1][0]) + norm2(B[1][1])});
@@ -399,68 +433,6 @@ void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, c
 }
 template void launch_kaczmarz_fine<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t);
 template void launch_kaczmarz_fine<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t);
-
-// Multi-RHS form of the colour pass: one work-group per site and 16
-// right-hand sides (16-lane group g handles right-hand side 16*blockIdx.y + g).
-// The slot blocks of the site are built once by group 0 and shared through
-// LDS; every group then performs the two projections of its right-hand side
-// exactly as the single-RHS kernel does.
-template <typename T>
-__global__ __launch_bounds__(256) void k_kaczmarz_fine_mr(FineT<T> f, int colour, int nrhs, cx<T>* __restrict__ x,
-                                                          const cx<T>* __restrict__ b) {
-  using C = cx<T>;
-  __shared__ C Bs[9][4];
-  const int lane = threadIdx.x & 15, g = threadIdx.x >> 4;
-  int px, y;
-  fine_colour_site(colour, blockIdx.x, f.N, px, y);
-  const int i = y * f.NH + (px >> 1);
-  const bool act = lane < 9;
-  const int slot = act ? lane : 0;
-  const int jn = hidx(px + nib(SLOT_DX2, slot) - 2, y + nib(SLOT_DY2, slot) - 2, f.N, f.NH);
-  if (g == 0 && act) {
-    C B[2][2];
-    dhat_slot_block(f, px, y, i, slot, jn, B);
-    Bs[slot][0] = B[0][0];
-    Bs[slot][1] = B[0][1];
-    Bs[slot][2] = B[1][0];
-    Bs[slot][3] = B[1][1];
-  }
-  __syncthreads();
-  const int r = blockIdx.y * 16 + g;
-  if (r >= nrhs) return;  // whole 16-lane groups leave together
-  const size_t n = (size_t)f.N * f.NH * 2;
-  C* xv = x + (size_t)r * n;
-  C B[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
-  C x0 = {0, 0}, x1 = {0, 0};
-  if (act) {
-    B[0][0] = Bs[slot][0];
-    B[0][1] = Bs[slot][1];
-    B[1][0] = Bs[slot][2];
-    B[1][1] = Bs[slot][3];
-    x0 = xv[2 * jn];
-    x1 = xv[2 * jn + 1];
-  }
-  const C b0 = b ? b[(size_t)r * n + 2 * i] : C{0, 0};
-  const C b1 = b ? b[(size_t)r * n + 2 * i + 1] : C{0, 0};
-  const C r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
-  const C r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
-  const C nu = grp16_sum(C{norm2(B[0][0]) + norm2(B[0][1]), norm2(B[1][0]) + norm2(B[1][1])});
-  const C g10 = grp16_sum(cjmul(B[0][0], B[1][0]) + cjmul(B[0][1], B[1][1]));
-  const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
-  const C a1 = nu.y > 0 ? cdiv_real(b1 - r1 - g10 * a0, nu.y) : C{0, 0};
-  if (act) {
-    xv[2 * jn] = x0 + cjmul(B[0][0], a0) + cjmul(B[1][0], a1);
-    xv[2 * jn + 1] = x1 + cjmul(B[0][1], a0) + cjmul(B[1][1], a1);
-  }
-}
-
-template <typename T>
-void launch_kaczmarz_fine_mr(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_kaczmarz_fine_mr<T>, dim3(nsites, (nrhs + 15) / 16), dim3(256), 0, s, f, colour, nrhs, x, b);
-}
-template void launch_kaczmarz_fine_mr<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t);
-template void launch_kaczmarz_fine_mr<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Transfers between level 0 and the 4x4 aggregates of the half-x grid.

@@ -179,16 +179,18 @@ def test_coarse_kaczmarz_sweep(bamg, imported, nrhs):
     assert rel(host(x), ref) < 1e-11
 
 
-def test_coarsest_solve(bamg, imported):
+@pytest.mark.parametrize("nrhs", [2, 37])
+def test_coarsest_solve(bamg, imported, nrhs):
+    """nrhs > 2 runs the split-K tiled product with the inverse."""
     N, U, m, h, o = imported
     L = 2
     n = bamg.bamg_level_info(h, L)["n"]
-    b = inputs.gaussian((2, n), 80)
-    x = torch.zeros(2, n, dtype=torch.complex128, device="cuda:0")
-    bamg.bamg_level_op(h, L, bamg.OP_COARSEST, dev(b), x, 2)
+    b = inputs.gaussian((nrhs, n), 80)
+    x = torch.zeros(nrhs, n, dtype=torch.complex128, device="cuda:0")
+    bamg.bamg_level_op(h, L, bamg.OP_COARSEST, dev(b), x, nrhs)
     A = o.operator(L).toarray()
     kappa = np.linalg.cond(A)
-    ref = o.coarsest_solve(b, nrhs=2).reshape(2, n)
+    ref = o.coarsest_solve(b, nrhs=nrhs).reshape(nrhs, n)
     log(f"coarsest cond {kappa:.2e} diff {rel(host(x), ref):.2e}")
     assert rel(host(x), ref) < max(1e-12, 10 * kappa * 2.2e-16)
 
@@ -343,21 +345,22 @@ def imported_mixed(bamg, request):
     return request.param, tol, N, U, m, h, o
 
 
-@pytest.mark.parametrize("l", [0, 1])
-def test_mixed_apply_and_sweep(bamg, imported_mixed, l):
+@pytest.mark.parametrize("l,nrhs", [(0, 2), (1, 2), (1, 5), (1, 21)])
+def test_mixed_apply_and_sweep(bamg, imported_mixed, l, nrhs):
+    """On coarse levels nrhs >= 4 runs the MFMA smoother (16 RHS per wave)."""
     name, tol, N, U, m, h, o = imported_mixed
     n = bamg.bamg_level_info(h, l)["n"]
-    x = inputs.gaussian((2, n), 160 + l)
-    y = torch.zeros(2, n, dtype=torch.complex128, device="cuda:0")
-    bamg.bamg_level_op(h, l, bamg.OP_APPLY_MIXED, dev(x), y, 2)
-    ea = rel(host(y), o.apply(l, x, nrhs=2).reshape(2, n))
-    b = inputs.gaussian((2, n), 170 + l)
+    x = inputs.gaussian((nrhs, n), 160 + l)
+    y = torch.zeros(nrhs, n, dtype=torch.complex128, device="cuda:0")
+    bamg.bamg_level_op(h, l, bamg.OP_APPLY_MIXED, dev(x), y, nrhs)
+    ea = rel(host(y), o.apply(l, x, nrhs=nrhs).reshape(nrhs, n))
+    b = inputs.gaussian((nrhs, n), 170 + l)
     xs = dev(x)
-    bamg.bamg_level_op(h, l, bamg.OP_SWEEP_MIXED, dev(b), xs, 2)
-    es = rel(host(xs), o.sweep(l, x, b, nrhs=2).reshape(2, n))
+    bamg.bamg_level_op(h, l, bamg.OP_SWEEP_MIXED, dev(b), xs, nrhs)
+    es = rel(host(xs), o.sweep(l, x, b, nrhs=nrhs).reshape(nrhs, n))
     # level 0 is FP32 links in every mixed mode
     t = 2e-5 if l == 0 else tol
-    log(f"mixed {name} level {l}: apply err {ea:.2e} sweep err {es:.2e}")
+    log(f"mixed {name} level {l} nrhs {nrhs}: apply err {ea:.2e} sweep err {es:.2e}")
     assert ea < t and es < t
 
 
@@ -383,3 +386,25 @@ def test_mixed_solve_reaches_fp64_accuracy(bamg, prec):
         f"|x - x_fp64|/|x| {dx:.2e}")
     assert st == 0 and info["relres_reduced"] <= 1e-10
     assert full < 2e-10 and dx < 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mixed_batch_results_do_not_depend_on_the_batch(bamg, prec):
+    w = inputs.workload("c1_32_b3")
+    U = inputs.load_gauge(w)
+    N = w["N"]
+    h = make_h(bamg, U, w["m"], n_levels=w["n_levels"], precision=MIXED[prec][0], seed=w["tv_seed"])
+    R = 19
+    B = inputs.gaussian((R, 2 * N * N), 777)
+    B[2] *= 1e4
+    X = torch.zeros(R, 2 * N * N, dtype=torch.complex128, device="cuda:0")
+    st, infos = bamg.bamg_solve_batch(h, dev(B), X, R, 1e-10)
+    assert st == 0
+    Xb = host(X)
+    for r in (0, 2, 17, 18):
+        x1 = torch.zeros(1, 2 * N * N, dtype=torch.complex128, device="cuda:0")
+        st1, inf1 = bamg.bamg_solve_batch(h, dev(B[r:r + 1]), x1, 1, 1e-10)
+        assert st1 == 0 and inf1[0]["iters"] == infos[r]["iters"]
+        assert np.array_equal(host(x1)[0], Xb[r])
+        full = np.linalg.norm(B[r] - oracle.wilson_apply(U, w["m"], Xb[r])) / np.linalg.norm(B[r])
+        assert full < 2e-10
