@@ -47,7 +47,31 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--precisions", default="mixed_fp16,fp64,mixed_bf16,mixed_fp32",
                     help="single-RHS precisions to time; the first one is the headline value")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="set up the headline hierarchy, time only the roofline kernel and a plain copy of "
+                         "COPY_MIB MiB (the scale of the HBM byte counters), print them and exit")
     return ap.parse_args()
+
+
+COPY_MIB = 256
+
+
+def copy_calibration(torch):
+    """One plain copy kernel of known size (reads and writes COPY_MIB MiB):
+    its FETCH_SIZE / WRITE_SIZE counters give the scale of those counters."""
+    src = torch.ones(COPY_MIB * 2 ** 20 // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    torch.mul(src, 1.0, out=dst)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
+    del src, dst
+    return {"kernel": "torch mul(src, 1.0) (vectorized elementwise)", "bytes_read": COPY_MIB * 2 ** 20,
+            "bytes_written": COPY_MIB * 2 ** 20, "us": t * 1e6, "GB/s": 2 * COPY_MIB * 2 ** 20 / t / 1e9}
 
 
 def time_launches(fn, reps, launches_per_call, torch):
@@ -104,6 +128,14 @@ def main():
     b = torch.from_numpy(inputs.gaussian(2 * N * N, w["rhs_seed"])).to("cuda:0")
     precs = [v.strip() for v in args.precisions.split(",") if v.strip()]
     head = precs[0]
+    if args.roofline_only:
+        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[head])
+        h = bamg.bamg_setup(U, w["m"], p)
+        out = {"workload": w["name"], "precision": head, "roofline": roofline(bamg, torch, h, head),
+               "copy_calibration": copy_calibration(torch)}
+        bamg.bamg_free(h)
+        print(json.dumps(out), flush=True)
+        return
     results, hier, xs = {}, {}, {}
     for prec in precs:
         p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[prec])
@@ -198,7 +230,7 @@ def main():
 
     # ---- roofline of the dominant kernel of the solve
     if not args.no_roofline:
-        out["roofline"] = roofline(bamg, torch, hier.get("fp64", h), N)
+        out["roofline"] = roofline(bamg, torch, h, head)
 
     # ---- CPU oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:
@@ -209,25 +241,70 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def roofline(bamg, torch, h, N):
-    """Coarse Kaczmarz colour pass on level 1 (the kernel with the largest share
-    of solve time in the kernel trace of this workload).  Algorithmic bytes per
-    sweep: per coarse site the 7 blocks of 16x16 complex (28672 B), the 16x16
-    smoother matrix (4096 B), the site's unknowns read and written (512 B) and
-    its right-hand side (256 B); one launch is one of the colours."""
+# Algorithmic bytes one coarse site moves in its colour pass of the Kaczmarz
+# smoother: the 7 blocks of 16x16 complex of its rows (storage type), the 16x16
+# smoother matrix Kinv (cycle type), its 16 right-hand-side entries, and the
+# 7 x 16 unknowns of its row support read and written (the supports of one
+# colour are disjoint, so nothing is counted twice within a launch).
+def _site_bytes(s_op, s_vec):
+    return 7 * 256 * s_op + 256 * s_vec + 16 * s_vec + 2 * 7 * 16 * s_vec
+
+
+SITE_SWEEP_BYTES = {"fp64": _site_bytes(16, 16), "mixed_fp32": _site_bytes(8, 8),
+                    "mixed_fp16": _site_bytes(4, 8), "mixed_bf16": _site_bytes(4, 8)}
+
+# HBM byte counters of the same launches (rocprofv3 --pmc FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch, median over the roofline sweeps), each divided
+# by what the counter reads per KiB moved by a plain 256 MiB copy kernel in the
+# same run.  Valid only for the kernel source they were taken on (sha256 of
+# coarse.hip); any change to it makes the reported traffic null.
+PMC_TRAFFIC = {
+    "mixed_fp16": {"coarse_hip_sha256": "676578ea4fbb84cbfe95f0270878300590c3ed8b8a3c4a9fb0a712aea4efed1e",
+                   "fetch_kib": 1313.0, "write_kib": 224.0, "fetch_per_kib": 131090.6 / 262144.0,
+                   "write_per_kib": 262144.0 / 262144.0,
+                   "profile": "profiles/kaczmarz_coarse_level1_c3_256_mixed_fp16_pmc.md"},
+}
+
+
+def pmc_traffic(prec):
+    import hashlib
+    e = PMC_TRAFFIC.get(prec)
+    if e is None:
+        return None
+    with open(os.path.join(ROOT, "paper_1308_5992_amd", "csrc", "coarse.hip"), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != e["coarse_hip_sha256"]:
+            return None
+    return 1024.0 * (e["fetch_kib"] / e["fetch_per_kib"] + e["write_kib"] / e["write_per_kib"])
+
+
+def roofline(bamg, torch, h, prec):
+    """Coarse Kaczmarz colour pass on level 1 of the headline hierarchy (with
+    the fine pass, the kernels that take the solve's time; see the kernel
+    trace).  One launch is one colour: 1/ncol of the level's sites, each moving
+    SITE_SWEEP_BYTES[prec] algorithmic bytes.  Timed with HIP events over 50
+    sweeps on the library's stream (torch's current stream); a mixed hierarchy
+    is driven through the complex64 hook, which launches exactly the ncol
+    colour passes of one sweep and nothing else."""
     inf = bamg.bamg_level_info(h, 1)
     ns = inf["ex"] * inf["ey"]
     ncol = inf["colours"]
     n = inf["n"]
-    xb = torch.zeros(n, dtype=torch.complex128, device="cuda:0")
-    bb = torch.ones(n, dtype=torch.complex128, device="cuda:0")
-    reps = 50
-    t = time_launches(lambda: bamg.bamg_level_op(h, 1, bamg.OP_SWEEP, bb, xb, 1), reps, ncol, torch)
-    bytes_launch = ns * (28672 + 4096 + 512 + 256) / ncol
+    if prec == "fp64":
+        dt, op = torch.complex128, bamg.OP_SWEEP
+        kname = "k_kaczmarz_coarse<double,cx<double>>"
+    else:
+        dt, op = torch.complex64, bamg.OP_SWEEP_F32
+        kname = {"mixed_fp16": "k_kaczmarz_coarse<float,hcx>", "mixed_bf16": "k_kaczmarz_coarse<float,bcx>",
+                 "mixed_fp32": "k_kaczmarz_coarse<float,cx<float>>"}[prec]
+    xb = torch.zeros(n, dtype=dt, device="cuda:0")
+    bb = torch.ones(n, dtype=dt, device="cuda:0")
+    t = time_launches(lambda: bamg.bamg_level_op(h, 1, op, bb, xb, 1), 50, ncol, torch)
+    bytes_launch = ns * SITE_SWEEP_BYTES[prec] / ncol
     achieved = bytes_launch / t / 1e9
-    return {"kernel": "k_kaczmarz_coarse (level 1)", "bound": "hbm", "achieved": achieved,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "avg_launch_us": t * 1e6, "bytes_per_launch": bytes_launch}
+    return {"kernel": kname + f" (level 1, {ns // ncol} sites per launch)", "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": pmc_traffic(prec), "traffic_unit": "bytes per launch",
+            "avg_launch_us": t * 1e6, "bytes_per_launch": bytes_launch}
 
 
 def cpu_baseline(w, U_np, tol):

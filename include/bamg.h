@@ -143,10 +143,14 @@ int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *
  * done in FP32 with the coarse operator in the hierarchy's storage type):
  *   op 7 BAMG_OP_APPLY_MIXED, op 8 BAMG_OP_SWEEP_MIXED: as ops 0 and 1 (l not the coarsest)
  *   op 9 BAMG_OP_CYCLE_MIXED: out = the preconditioner of the solve applied to in (l = 0)
+ *   op 10 BAMG_OP_APPLY_F32, op 11 BAMG_OP_SWEEP_F32: as ops 7 and 8, but in and out
+ *         are complex64 (interleaved float) arrays used as they are, with no
+ *         conversion launches: exactly the kernels of one FP32 apply or sweep
  * Level 0 is the fine reduced system (A_0 = Dhat). */
 enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLONG = 3,
        BAMG_OP_COARSEST = 4, BAMG_OP_CYCLE = 5, BAMG_OP_RESIDUAL = 6,
-       BAMG_OP_APPLY_MIXED = 7, BAMG_OP_SWEEP_MIXED = 8, BAMG_OP_CYCLE_MIXED = 9 };
+       BAMG_OP_APPLY_MIXED = 7, BAMG_OP_SWEEP_MIXED = 8, BAMG_OP_CYCLE_MIXED = 9,
+       BAMG_OP_APPLY_F32 = 10, BAMG_OP_SWEEP_F32 = 11 };
 int bamg_level_op(bamg_hierarchy *h, int32_t level, int32_t op, const void *in, void *out, int32_t nrhs);
 
 /* Number of levels, or a negative status. */

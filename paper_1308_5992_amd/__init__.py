@@ -22,6 +22,7 @@ BAMG_CYCLE_V, BAMG_CYCLE_W = 0, 1
 BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
 OP_APPLY, OP_SWEEP, OP_RESTRICT, OP_PROLONG, OP_COARSEST, OP_CYCLE, OP_RESIDUAL = range(7)
 OP_APPLY_MIXED, OP_SWEEP_MIXED, OP_CYCLE_MIXED = 7, 8, 9
+OP_APPLY_F32, OP_SWEEP_F32 = 10, 11
 
 EXPORTED = [
     "bamg_default_params", "bamg_setup", "bamg_solve", "bamg_solve_batch", "bamg_apply_dhat",
@@ -97,12 +98,13 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t):
+def _ptr(t, complex64=False):
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
-    if not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous():
-        raise TypeError("expected a contiguous complex128 GPU tensor")
+    want = torch.complex64 if complex64 else torch.complex128
+    if not t.is_cuda or t.dtype != want or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {want} GPU tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -183,7 +185,9 @@ def bamg_eo_reconstruct(h, b, xe, x, nrhs: int = 1):
 
 
 def bamg_level_op(h, level: int, op: int, inp, out, nrhs: int = 1):
-    _check(lib.bamg_level_op(h, int(level), int(op), _ptr(inp), _ptr(out), int(nrhs)), "bamg_level_op")
+    """Ops 10 and 11 take complex64 tensors, every other op complex128."""
+    c64 = op in (OP_APPLY_F32, OP_SWEEP_F32)
+    _check(lib.bamg_level_op(h, int(level), int(op), _ptr(inp, c64), _ptr(out, c64), int(nrhs)), "bamg_level_op")
 
 
 def bamg_n_levels(h) -> int:

@@ -735,7 +735,9 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
       }
       case BAMG_OP_APPLY_MIXED:
       case BAMG_OP_SWEEP_MIXED:
-      case BAMG_OP_CYCLE_MIXED: {
+      case BAMG_OP_CYCLE_MIXED:
+      case BAMG_OP_APPLY_F32:
+      case BAMG_OP_SWEEP_F32: {
         if (!h->mixed()) return fail(BAMG_EINVAL, "hierarchy is FP64");
         if (op == BAMG_OP_CYCLE_MIXED) {
           if (l != 0) return fail(BAMG_EINVAL, "the mixed cycle starts on level 0");
@@ -743,29 +745,37 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
           h->precondition_mixed(xi, xo, nrhs);
           break;
         }
-        if (op == BAMG_OP_SWEEP_MIXED && h->coarsest(l) && h->L() > 1)
+        if ((op == BAMG_OP_SWEEP_MIXED || op == BAMG_OP_SWEEP_F32) && h->coarsest(l) && h->L() > 1)
           return fail(BAMG_EINVAL, "no smoother on the coarsest level");
         if (l >= 1 && h->coarsest(l)) return fail(BAMG_EINVAL, "the coarsest level is solved in FP64");
+        if (op == BAMG_OP_APPLY_F32 && in == out) return fail(BAMG_EINVAL, "in and out must not alias");
         h->ensure_cap(nrhs);
         Level& Lv = h->lv[l];
         const size_t nn = Lv.n * nrhs;
-        launch_convert(xi, Lv.b32, nn, h->s);
-        if (op == BAMG_OP_SWEEP_MIXED) launch_convert((const zd*)xo, Lv.x32, nn, h->s);
+        const bool f32io = (op == BAMG_OP_APPLY_F32 || op == BAMG_OP_SWEEP_F32);
+        const bool is_apply = (op == BAMG_OP_APPLY_MIXED || op == BAMG_OP_APPLY_F32);
+        // complex64 operands are used in place; complex128 ones go through the level's FP32 vectors
+        const zf* bi = f32io ? (const zf*)in : Lv.b32;
+        zf* xw = f32io ? (zf*)out : Lv.x32;
+        if (!f32io) {
+          launch_convert(xi, Lv.b32, nn, h->s);
+          if (!is_apply) launch_convert((const zd*)xo, Lv.x32, nn, h->s);
+        }
         switch (h->p.precision) {
           case BAMG_MIXED_FP16:
-            if (op == BAMG_OP_APPLY_MIXED) h->apply32<hcx>(l, Lv.b32, Lv.x32, nullptr, nrhs);
-            else h->sweep32<hcx>(l, Lv.x32, Lv.b32, nrhs);
+            if (is_apply) h->apply32<hcx>(l, bi, xw, nullptr, nrhs);
+            else h->sweep32<hcx>(l, xw, bi, nrhs);
             break;
           case BAMG_MIXED_BF16:
-            if (op == BAMG_OP_APPLY_MIXED) h->apply32<bcx>(l, Lv.b32, Lv.x32, nullptr, nrhs);
-            else h->sweep32<bcx>(l, Lv.x32, Lv.b32, nrhs);
+            if (is_apply) h->apply32<bcx>(l, bi, xw, nullptr, nrhs);
+            else h->sweep32<bcx>(l, xw, bi, nrhs);
             break;
           default:
-            if (op == BAMG_OP_APPLY_MIXED) h->apply32<zf>(l, Lv.b32, Lv.x32, nullptr, nrhs);
-            else h->sweep32<zf>(l, Lv.x32, Lv.b32, nrhs);
+            if (is_apply) h->apply32<zf>(l, bi, xw, nullptr, nrhs);
+            else h->sweep32<zf>(l, xw, bi, nrhs);
             break;
         }
-        launch_convert(Lv.x32, xo, nn, h->s);
+        if (!f32io) launch_convert(Lv.x32, xo, nn, h->s);
         check_launch();
         break;
       }

@@ -201,7 +201,7 @@ __device__ __forceinline__ mf4 mfma4(float a, float b, mf4 c) {
 template <typename S>
 __global__ __launch_bounds__(64) void k_kaczmarz_coarse_mfma(CoarseT<float, S> c, int colour, int mode, int nrhs,
                                                              zf* __restrict__ x, const zf* __restrict__ b) {
-  constexpr int NCOL = NOFF * 16;
+  constexpr int NCOL = NOFF * 16, NQ = NCOL * 16 / 64;  // 28 staged unknowns per lane
   __shared__ float Xr[NCOL][17], Xi[NCOL][17];
   __shared__ float Vr[16][17], Vi[16][17];  // right-hand side block, then residual, then alpha
   const int l = threadIdx.x, lm = l & 15, lq = l >> 4;
@@ -217,40 +217,65 @@ __global__ __launch_bounds__(64) void k_kaczmarz_coarse_mfma(CoarseT<float, S> c
     const int dx = (int)((0x0211021u >> (4 * o)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * o)) & 15u) - 1;
     nb[o] = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
   }
-  // stage X (112 x 16) and the right-hand side block (16 x 16)
-  for (int e = l; e < NCOL * 16; e += 64) {
-    const int rr = e / NCOL, col = e - rr * NCOL;
-    zf v = {0, 0};
-    if (rr < nr) {
-      int nbo = nb[0];
+  // ---- every global load first (independent, all in flight together)
+  // unknowns: element e = l + 64 q -> right-hand side e / 112, column e % 112;
+  // 64 consecutive elements never straddle more than two offsets
+  zf xin[NQ];
 #pragma unroll
-      for (int o = 1; o < NOFF; ++o)
-        if ((col >> 4) == o) nbo = nb[o];
-      v = x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)];
-    }
-    Xr[col][rr] = v.x;
-    Xi[col][rr] = v.y;
+  for (int q = 0; q < NQ; ++q) {
+    const int e = l + 64 * q, rr = e / NCOL, col = e - rr * NCOL, o = col >> 4;
+    int nbo = nb[0];
+#pragma unroll
+    for (int oo = 1; oo < NOFF; ++oo) nbo = (o == oo) ? nb[oo] : nbo;
+    xin[q] = (rr < nr) ? x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)] : zf{0, 0};
   }
-  for (int e = l; e < 256; e += 64) {
-    const int rr = e >> 4, i = e & 15;
-    const zf v = (b && rr < nr) ? b[(size_t)(r0 + rr) * n + site * 16 + i] : zf{0, 0};
-    Vr[i][rr] = v.x;
-    Vi[i][rr] = v.y;
+  const S* Dsite = c.D + (size_t)site * NOFF * 256;
+  S ar[NCOL / 4];  // A[lm][4 q + lq]: D[site][q / 4][lm][(4 q + lq) % 16]
+#pragma unroll
+  for (int q = 0; q < NCOL / 4; ++q) {
+    const int k = 4 * q + lq;
+    ar[q] = Dsite[(k >> 4) * 256 + lm * 16 + (k & 15)];
+  }
+  S au[NOFF][4];   // A[4 q + lq][16 o + lm]: D[site][o][4 q + lq][lm]
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) au[o][q] = Dsite[o * 256 + (4 * q + lq) * 16 + lm];
+  zf kin[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) kin[q] = c.Kinv[(size_t)site * 256 + lm * 16 + 4 * q + lq];
+  zf bin[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = l + 64 * q, rr = e >> 4, i = e & 15;
+    bin[q] = (b && rr < nr) ? b[(size_t)(r0 + rr) * n + site * 16 + i] : zf{0, 0};
+  }
+  // ---- stage into LDS
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = l + 64 * q, rr = e / NCOL, col = e - rr * NCOL;
+    Xr[col][rr] = xin[q].x;
+    Xi[col][rr] = xin[q].y;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = l + 64 * q, rr = e >> 4, i = e & 15;
+    Vr[i][rr] = bin[q].x;
+    Vi[i][rr] = bin[q].y;
   }
   __syncthreads();
-  // R = A X: A[i][k] = D[site][k/16][i][k%16]
-  const S* Dsite = c.D + (size_t)site * NOFF * 256;
+  // ---- R = A X
   mf4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < NCOL; k0 += 4) {
-    const int k = k0 + lq;
-    const zf a = widen<float>(Dsite[(k >> 4) * 256 + lm * 16 + (k & 15)]);
+#pragma unroll
+  for (int q = 0; q < NCOL / 4; ++q) {
+    const int k = 4 * q + lq;
+    const zf a = widen<float>(ar[q]);
     const float xr = Xr[k][lm], xi = Xi[k][lm];
     cr = mfma4(a.x, xr, cr);
     cr = mfma4(-a.y, xi, cr);
     ci = mfma4(a.x, xi, ci);
     ci = mfma4(a.y, xr, ci);
   }
-  // residual B - R into V (lane holds rows 4 lq + e, column lm)
   float resr[4], resi[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -264,12 +289,12 @@ __global__ __launch_bounds__(64) void k_kaczmarz_coarse_mfma(CoarseT<float, S> c
     Vi[4 * lq + e][lm] = resi[e];
   }
   __syncthreads();
-  // alpha = Kinv (B - R)
-  const zf* Ks = c.Kinv + (size_t)site * 256;
+  // ---- alpha = Kinv (B - R)
   mf4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < 16; k0 += 4) {
-    const int k = k0 + lq;
-    const zf a = Ks[lm * 16 + k];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = 4 * q + lq;
+    const zf a = kin[q];
     const float vr = Vr[k][lm], vi = Vi[k][lm];
     gr = mfma4(a.x, vr, gr);
     gr = mfma4(-a.y, vi, gr);
@@ -283,13 +308,14 @@ __global__ __launch_bounds__(64) void k_kaczmarz_coarse_mfma(CoarseT<float, S> c
     Vi[4 * lq + e][lm] = gi[e];
   }
   __syncthreads();
-  // X += A^H alpha, tile o: rows (columns of A) 16 o + m, A^H[m][i] = conj(A[i][16 o + m])
+  // ---- X += A^H alpha, tile o: A^H[m][i] = conj(A[i][16 o + m])
 #pragma unroll
   for (int o = 0; o < NOFF; ++o) {
     mf4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < 16; k0 += 4) {
-      const int i = k0 + lq;
-      const zf a = widen<float>(Dsite[o * 256 + i * 16 + lm]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 4 * q + lq;
+      const zf a = widen<float>(au[o][q]);
       const float vr = Vr[i][lm], vi = Vi[i][lm];
       // (a.x - i a.y)(vr + i vi) = (a.x vr + a.y vi) + i (a.x vi - a.y vr)
       ur = mfma4(a.x, vr, ur);
@@ -305,15 +331,13 @@ __global__ __launch_bounds__(64) void k_kaczmarz_coarse_mfma(CoarseT<float, S> c
     }
   }
   __syncthreads();
-  for (int e = l; e < NCOL * 16; e += 64) {
-    const int rr = e / NCOL, col = e - rr * NCOL;
-    if (rr < nr) {
-      int nbo = nb[0];
 #pragma unroll
-      for (int o = 1; o < NOFF; ++o)
-        if ((col >> 4) == o) nbo = nb[o];
-      x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)] = zf{Xr[col][rr], Xi[col][rr]};
-    }
+  for (int q = 0; q < NQ; ++q) {
+    const int e = l + 64 * q, rr = e / NCOL, col = e - rr * NCOL, o = col >> 4;
+    int nbo = nb[0];
+#pragma unroll
+    for (int oo = 1; oo < NOFF; ++oo) nbo = (o == oo) ? nb[oo] : nbo;
+    if (rr < nr) x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)] = zf{Xr[col][rr], Xi[col][rr]};
   }
 }
 

@@ -364,6 +364,26 @@ def test_mixed_apply_and_sweep(bamg, imported_mixed, l, nrhs):
     assert ea < t and es < t
 
 
+@pytest.mark.parametrize("l,nrhs", [(0, 1), (1, 1), (1, 6)])
+def test_f32_operand_ops_match_mixed_ops(bamg, imported_mixed, l, nrhs):
+    """Ops 10/11 run the same kernels as ops 7/8 on complex64 operands in
+    place: for inputs exactly representable in FP32 the results agree bitwise."""
+    name, tol, N, U, m, h, o = imported_mixed
+    n = bamg.bamg_level_info(h, l)["n"]
+    x = inputs.gaussian((nrhs, n), 180 + l).astype(np.complex64)
+    b = inputs.gaussian((nrhs, n), 190 + l).astype(np.complex64)
+    y64 = torch.zeros(nrhs, n, dtype=torch.complex128, device="cuda:0")
+    bamg.bamg_level_op(h, l, bamg.OP_APPLY_MIXED, dev(x.astype(np.complex128)), y64, nrhs)
+    y32 = torch.zeros(nrhs, n, dtype=torch.complex64, device="cuda:0")
+    bamg.bamg_level_op(h, l, bamg.OP_APPLY_F32, torch.from_numpy(x).to("cuda:0"), y32, nrhs)
+    assert np.array_equal(host(y64).astype(np.complex64), y32.cpu().numpy())
+    xs64 = dev(x.astype(np.complex128))
+    bamg.bamg_level_op(h, l, bamg.OP_SWEEP_MIXED, dev(b.astype(np.complex128)), xs64, nrhs)
+    xs32 = torch.from_numpy(x).to("cuda:0")
+    bamg.bamg_level_op(h, l, bamg.OP_SWEEP_F32, torch.from_numpy(b).to("cuda:0"), xs32, nrhs)
+    assert np.array_equal(host(xs64).astype(np.complex64), xs32.cpu().numpy())
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 def test_mixed_solve_reaches_fp64_accuracy(bamg, prec):
     """The FP64 outer FGMRES drives the true residual to 1e-10 whatever the
