@@ -54,6 +54,7 @@ typedef struct bamg_hierarchy bamg_hierarchy;
 typedef enum {
   BAMG_OK = 0,
   BAMG_NOT_CONVERGED = 1,
+  BAMG_PENDING = 2,        /* bamg_server_wait: the request is not finished yet */
   BAMG_EINVAL = -1,
   BAMG_ENOMEM = -2,
   BAMG_EDEVICE = -3,
@@ -179,6 +180,69 @@ int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void *out, void *strea
 
 /* Release the hierarchy (NULL is ignored). */
 void bamg_free(bamg_hierarchy *h);
+
+/* ---- Serving: continuous batching over resident hierarchies ----------------
+ * The paper's setting is many right-hand sides per gauge configuration (Sec. 1);
+ * a server holds the hierarchies of several gauge fields (any lattice sizes,
+ * masses and precisions) on the device and solves the right-hand sides of the
+ * requests submitted for them as they arrive.
+ *  - Memory admission: a field's hierarchy is built (bamg_setup) when a request
+ *    for it is first scheduled and its footprint (hierarchy + slots_per_field
+ *    solve slots, bamg_server_field_bytes) fits in hbm_budget beside the
+ *    resident fields; idle resident fields are evicted, least recently used
+ *    first, to make room.  A field larger than the whole budget fails its
+ *    requests with BAMG_ENOMEM.
+ *  - Continuous batching: every scheduling round moves queued right-hand sides
+ *    into free slots of their field, then advances every occupied slot of every
+ *    field by one FGMRES iteration (the fields' work overlaps on the device on
+ *    one stream per field).  A request finishes when all its right-hand sides
+ *    have.  Each right-hand side is solved exactly as by bamg_solve_batch: its
+ *    result is bitwise the same alone or in any mix.
+ *  - Pointers: B and X are DEVICE arrays [nrhs][y][x][s] (complex128) that must
+ *    stay valid, with B unchanged and X untouched, until the request finishes;
+ *    B must be complete (its producer synchronised) before bamg_server_submit.
+ *  - Threads: with threaded = 1 a worker thread drives the device and
+ *    bamg_server_wait blocks; with threaded = 0 the caller drives it with
+ *    bamg_server_progress and bamg_server_wait only polls.  All calls may be made
+ *    from any thread.  bamg_server_free stops the worker after its current round
+ *    and drops unfinished requests. */
+typedef struct bamg_server bamg_server;
+
+typedef struct {
+  size_t hbm_budget;        /* device bytes for hierarchies and slots (0: 80% of the free memory) */
+  int32_t slots_per_field;  /* right-hand sides in flight per field (default 32, at most 4096) */
+  int32_t threaded;         /* 1 (default): own worker thread; 0: driven by bamg_server_progress */
+} bamg_server_params;
+
+typedef struct {
+  int64_t submitted, completed;     /* requests */
+  int64_t rhs_completed;            /* right-hand sides of completed requests */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* request latency, submit to completion (nearest rank) */
+  double busy_s;                    /* first submit to last completion */
+  double solves_per_s;              /* rhs_completed / busy_s */
+  int32_t resident_fields, evictions, setups;
+  size_t bytes_in_use, budget_bytes;
+  int64_t rounds;                   /* scheduling rounds run */
+} bamg_server_stats;
+
+int bamg_server_default_params(bamg_server_params *sp);
+int bamg_server_create(const bamg_server_params *sp, bamg_server **out);
+/* Register a gauge field (device U[mu][y][x], copied to the host) with its mass
+ * and hierarchy parameters (p->stream is ignored: each field gets a stream). */
+int bamg_server_add_field(bamg_server *s, const void *gauge, double m, const bamg_params *p, int32_t *field_id);
+/* Device bytes the field occupies while resident (admission footprint). */
+int bamg_server_field_bytes(bamg_server *s, int32_t field_id, size_t *bytes);
+/* Queue nrhs right-hand sides (1..4096) for a field; returns at once. */
+int bamg_server_submit(bamg_server *s, int32_t field_id, const void *B, void *X, int32_t nrhs, double tol,
+                       int64_t *request_id);
+/* One scheduling round (threaded = 0 only); *pending (may be NULL) = unfinished requests. */
+int bamg_server_progress(bamg_server *s, int32_t *pending);
+/* Wait up to timeout_ms (< 0: forever) for a request.  Finished: its status
+ * (BAMG_OK, BAMG_NOT_CONVERGED or a failure), infos_host[nrhs] filled (may be
+ * NULL) and the request forgotten; else BAMG_PENDING. */
+int bamg_server_wait(bamg_server *s, int64_t request_id, double timeout_ms, bamg_solve_info *infos_host);
+int bamg_server_get_stats(bamg_server *s, bamg_server_stats *out);
+void bamg_server_free(bamg_server *s);
 
 /* Text of the last error on this thread ("" if none). */
 const char *bamg_last_error(void);

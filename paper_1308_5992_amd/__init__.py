@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbamg.so")
 
-BAMG_OK, BAMG_NOT_CONVERGED = 0, 1
+BAMG_OK, BAMG_NOT_CONVERGED, BAMG_PENDING = 0, 1, 2
 BAMG_EINVAL, BAMG_ENOMEM, BAMG_EDEVICE, BAMG_ESINGULAR, BAMG_ENOTIMPL = -1, -2, -3, -4, -5
 BAMG_CYCLE_V, BAMG_CYCLE_W = 0, 1
 BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
@@ -29,6 +29,8 @@ EXPORTED = [
     "bamg_eo_reduce", "bamg_eo_reconstruct", "bamg_level_op", "bamg_n_levels", "bamg_level_info",
     "bamg_export_level", "bamg_import_level", "bamg_footprint_bytes", "bamg_gaussian_tv",
     "bamg_free", "bamg_last_error",
+    "bamg_server_default_params", "bamg_server_create", "bamg_server_add_field", "bamg_server_field_bytes",
+    "bamg_server_submit", "bamg_server_progress", "bamg_server_wait", "bamg_server_get_stats", "bamg_server_free",
 ]
 
 
@@ -46,6 +48,23 @@ class bamg_solve_info(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("relres_reduced", ctypes.c_double),
         ("relres_full", ctypes.c_double), ("rho_est", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class bamg_server_params(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("slots_per_field", ctypes.c_int32), ("threaded", ctypes.c_int32)]
+
+
+class bamg_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rhs_completed", ctypes.c_int64),
+        ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+        ("resident_fields", ctypes.c_int32), ("evictions", ctypes.c_int32), ("setups", ctypes.c_int32),
+        ("bytes_in_use", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t), ("rounds", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -76,6 +95,15 @@ def _load():
         "bamg_gaussian_tv": (I32, [I32, I32, U64, P, P]),
         "bamg_free": (None, [P]),
         "bamg_last_error": (ctypes.c_char_p, []),
+        "bamg_server_default_params": (I32, [ctypes.POINTER(bamg_server_params)]),
+        "bamg_server_create": (I32, [ctypes.POINTER(bamg_server_params), ctypes.POINTER(P)]),
+        "bamg_server_add_field": (I32, [P, P, D, PP, ctypes.POINTER(I32)]),
+        "bamg_server_field_bytes": (I32, [P, I32, ctypes.POINTER(SZ)]),
+        "bamg_server_submit": (I32, [P, I32, P, P, I32, D, ctypes.POINTER(ctypes.c_int64)]),
+        "bamg_server_progress": (I32, [P, ctypes.POINTER(I32)]),
+        "bamg_server_wait": (I32, [P, ctypes.c_int64, D, PI]),
+        "bamg_server_get_stats": (I32, [P, ctypes.POINTER(bamg_server_stats)]),
+        "bamg_server_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -231,3 +259,83 @@ def bamg_free(h):
     if h is not None and h.value:
         lib.bamg_free(h)
         h.value = None
+
+
+# ---------------------------------------------------------------- serving
+class Server(ctypes.c_void_p):
+    """Opaque server handle (freed by bamg_server_free or when collected)."""
+
+    def __del__(self):
+        if self.value:
+            lib.bamg_server_free(self)
+            self.value = None
+
+
+def bamg_server_default_params(**kw) -> bamg_server_params:
+    sp = bamg_server_params()
+    lib.bamg_server_default_params(ctypes.byref(sp))
+    for k, v in kw.items():
+        setattr(sp, k, v)
+    return sp
+
+
+def bamg_server_create(sp: bamg_server_params) -> Server:
+    s = Server()
+    _check(lib.bamg_server_create(ctypes.byref(sp), ctypes.byref(s)), "bamg_server_create")
+    return s
+
+
+def bamg_server_add_field(s, gauge, m: float, p: bamg_params) -> int:
+    import torch
+    torch.cuda.current_stream().synchronize()
+    p.init_tv_host = None
+    fid = ctypes.c_int32()
+    _check(lib.bamg_server_add_field(s, _ptr(gauge), float(m), ctypes.byref(p), ctypes.byref(fid)),
+           "bamg_server_add_field")
+    return fid.value
+
+
+def bamg_server_field_bytes(s, field: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib.bamg_server_field_bytes(s, int(field), ctypes.byref(b)), "bamg_server_field_bytes")
+    return b.value
+
+
+def bamg_server_submit(s, field: int, B, X, nrhs: int, tol: float) -> int:
+    """B and X: complex128 GPU tensors [nrhs][2 N^2]; B must not change and X
+    must not be read until the request finishes (the caller keeps both alive)."""
+    import torch
+    torch.cuda.current_stream().synchronize()  # B complete before the server's streams read it
+    rid = ctypes.c_int64()
+    _check(lib.bamg_server_submit(s, int(field), _ptr(B), _ptr(X), int(nrhs), float(tol), ctypes.byref(rid)),
+           "bamg_server_submit")
+    return rid.value
+
+
+def bamg_server_progress(s) -> int:
+    pend = ctypes.c_int32()
+    _check(lib.bamg_server_progress(s, ctypes.byref(pend)), "bamg_server_progress")
+    return pend.value
+
+
+def bamg_server_wait(s, request: int, nrhs: int, timeout_ms: float = -1.0):
+    """(status, infos) once finished, (BAMG_PENDING, None) otherwise.  Failure
+    statuses are returned, not raised, so that a failed request can be told
+    apart from a failed call."""
+    infos = (bamg_solve_info * nrhs)()
+    st = lib.bamg_server_wait(s, ctypes.c_int64(request), float(timeout_ms), infos)
+    if st == BAMG_PENDING:
+        return st, None
+    return st, [i.as_dict() for i in infos]
+
+
+def bamg_server_get_stats(s) -> dict:
+    st = bamg_server_stats()
+    _check(lib.bamg_server_get_stats(s, ctypes.byref(st)), "bamg_server_get_stats")
+    return st.as_dict()
+
+
+def bamg_server_free(s):
+    if s is not None and s.value:
+        lib.bamg_server_free(s)
+        s.value = None

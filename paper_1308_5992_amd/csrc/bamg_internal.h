@@ -164,8 +164,10 @@ void launch_multidot(const zd* X, size_t ldx, int nv, const zd* w, size_t n, zd*
 // w += sign * sum_v X_v h_v   (h on device)
 void launch_multiaxpy(const zd* X, size_t ldx, int nv, const zd* h, double sign, zd* w, size_t n,
                       hipStream_t s);
-// per-vector squared norms of nv vectors of length n: out[v] (real part)
-void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s);
+// per-vector squared norms of nv vectors of length n: out[v] (real part);
+// vector v at X + map[v] * ldx when map (device) is given, else X + v * ldx
+void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s,
+                  const int* map = nullptr);
 // X_v *= 1/sqrt(nrm[v].x) for nrm > 0
 void launch_normalize(zd* X, size_t ldx, int nv, size_t n, const zd* nrm, hipStream_t s);
 // y = alpha x (alpha real, host scalar)
@@ -188,5 +190,22 @@ void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, siz
 void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStream_t s);
 // x_r += sum_q Z_{q,r} y[r*64 + q]
 void launch_blincomb(const zd* Z, int nq, const zd* y, zd* x, size_t n, int R, hipStream_t s);
+// slot-mapped forms (continuous batching): entry a of a launch uses slot slot[a]
+// (device int arrays); vector v of that slot at X + slot[a]*lds + v*ldv, the
+// first cnt[a] vectors; gathered vectors contiguous at W + a*n; coefficients
+// at stride 64 per entry.  Per entry the arithmetic equals the batched forms.
+void launch_smultidot(const zd* X, size_t lds, size_t ldv, const int* slot, const int* cnt, int maxcnt, const zd* W,
+                      size_t n, int A, zd* partial, zd* out, hipStream_t s);
+void launch_smultiaxpy(const zd* X, size_t lds, size_t ldv, const int* slot, const int* cnt, const zd* h, double sign,
+                       zd* W, size_t n, int A, hipStream_t s);
+// x_{slot[a]} (stride n) += sum_{q < cnt[a]} Z_{slot[a], q} y[a*64 + q]
+void launch_slincomb(const zd* Z, size_t lds, size_t ldv, const int* slot, const int* cnt, const zd* y, zd* x,
+                     size_t n, int A, hipStream_t s);
+// Y_a = X_{slot[a], j[a]} (j may be NULL: vector 0)
+void launch_sgather(const zd* X, size_t lds, size_t ldv, const int* slot, const int* j, zd* Y, size_t n, int A,
+                    hipStream_t s);
+// X_{slot[a], j[a]} = c[a] * Y_{src[a]} with Y_k at Y + k*ldy (c NULL: copy; src NULL: a; j NULL: 0)
+void launch_sscatter(const zd* Y, size_t ldy, const int* src, zd* X, size_t lds, size_t ldv, const int* slot,
+                     const int* j, const double* c, size_t n, int A, hipStream_t s);
 
 }  // namespace bamg

@@ -28,13 +28,15 @@ __device__ __forceinline__ zd block_sum(zd v, zd* sh) {
 }
 
 // partial[b * nv + v] = sum_{i in chunk b} conj(X_v[i]) w[i]   (w == nullptr: |X_v[i]|^2)
+// X_v = X + map[v] * ldx (map == nullptr: X + v * ldx)
 __global__ __launch_bounds__(BT) void k_dot_partial(const zd* __restrict__ X, size_t ldx, int nv,
-                                                    const zd* __restrict__ w, size_t n, zd* __restrict__ partial) {
+                                                    const zd* __restrict__ w, size_t n, zd* __restrict__ partial,
+                                                    const int* __restrict__ map) {
   __shared__ zd sh[BT];
   const int b = blockIdx.x, v = blockIdx.y, nb = gridDim.x;
   const size_t chunk = (n + nb - 1) / nb;
   const size_t lo = (size_t)b * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
-  const zd* xv = X + (size_t)v * ldx;
+  const zd* xv = X + (size_t)(map ? map[v] : v) * ldx;
   zd acc = {0, 0};
   if (w) {
     for (size_t i = lo + threadIdx.x; i < hi; i += BT) acc = acc + cjmul(xv[i], w[i]);
@@ -58,13 +60,13 @@ __global__ __launch_bounds__(BT) void k_reduce_partial(const zd* __restrict__ pa
 void launch_multidot(const zd* X, size_t ldx, int nv, const zd* w, size_t n, zd* partial, zd* out,
                      hipStream_t s) {
   const int nb = blas_nblocks(n);
-  hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, w, n, partial);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, w, n, partial, (const int*)nullptr);
   hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
 }
 
-void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s) {
+void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s, const int* map) {
   const int nb = blas_nblocks(n);
-  hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, (const zd*)nullptr, n, partial);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, (const zd*)nullptr, n, partial, map);
   hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
 }
 
@@ -253,6 +255,126 @@ __global__ void k_blincomb(const zd* __restrict__ Z, int nq, int R, const zd* __
 void launch_blincomb(const zd* Z, int nq, const zd* y, zd* x, size_t n, int R, hipStream_t s) {
   if (nq <= 0) return;
   hipLaunchKernelGGL(k_blincomb, dim3((unsigned)((n + 255) / 256), R), dim3(256), 0, s, Z, nq, R, y, x, n);
+}
+
+// ---------------------------------------------------------------------------
+// Slot-mapped forms for continuous batching.  Entry a of a launch works on the
+// right-hand side held in slot slot[a]; vector v of that slot's basis lives at
+// X + slot[a] * lds + v * ldv, and only its first cnt[a] vectors are used.
+// Gathered per-launch vectors (w, the inputs and outputs of the cycle) are
+// contiguous at W + a * n.  Each entry repeats exactly the arithmetic of the
+// unmapped batched forms above (same block decomposition, same accumulation
+// order), so a right-hand side's results depend neither on its slot nor on
+// the other entries of the launch.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BT) void k_sdot_partial(const zd* __restrict__ X, size_t lds, size_t ldv,
+                                                     const int* __restrict__ slot, const int* __restrict__ cnt,
+                                                     const zd* __restrict__ W, size_t n, zd* __restrict__ partial) {
+  __shared__ zd sh[BT];
+  const int b = blockIdx.x, v = blockIdx.y, a = blockIdx.z, nb = gridDim.x;
+  if (v >= cnt[a]) return;  // uniform over the block
+  const size_t chunk = (n + nb - 1) / nb;
+  const size_t lo = (size_t)b * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
+  const zd* xv = X + (size_t)slot[a] * lds + (size_t)v * ldv;
+  const zd* wv = W + (size_t)a * n;
+  zd acc = {0, 0};
+  for (size_t i = lo + threadIdx.x; i < hi; i += BT) acc = acc + cjmul(xv[i], wv[i]);
+  const zd s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[((size_t)a * nb + b) * 64 + v] = s;
+}
+
+__global__ __launch_bounds__(BT) void k_sreduce(const zd* __restrict__ partial, int nb, const int* __restrict__ cnt,
+                                                zd* __restrict__ out) {
+  __shared__ zd sh[BT];
+  const int v = blockIdx.x, a = blockIdx.y;
+  if (v >= cnt[a]) return;
+  zd acc = {0, 0};
+  for (int b = threadIdx.x; b < nb; b += BT) acc = acc + partial[((size_t)a * nb + b) * 64 + v];
+  const zd s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[(size_t)a * 64 + v] = s;
+}
+
+void launch_smultidot(const zd* X, size_t lds, size_t ldv, const int* slot, const int* cnt, int maxcnt, const zd* W,
+                      size_t n, int A, zd* partial, zd* out, hipStream_t s) {
+  if (A <= 0 || maxcnt <= 0) return;
+  const int nb = blas_nblocks(n);
+  hipLaunchKernelGGL(k_sdot_partial, dim3(nb, maxcnt, A), dim3(BT), 0, s, X, lds, ldv, slot, cnt, W, n, partial);
+  hipLaunchKernelGGL(k_sreduce, dim3(maxcnt, A), dim3(BT), 0, s, partial, nb, cnt, out);
+}
+
+__global__ void k_smultiaxpy(const zd* __restrict__ X, size_t lds, size_t ldv, const int* __restrict__ slot,
+                             const int* __restrict__ cnt, const zd* __restrict__ h, double sign, zd* __restrict__ W,
+                             size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= n) return;
+  const zd* xs = X + (size_t)slot[a] * lds;
+  const int nv = cnt[a];
+  zd acc = {0, 0};
+  for (int v = 0; v < nv; ++v) acc = acc + xs[(size_t)v * ldv + i] * h[(size_t)a * 64 + v];
+  W[(size_t)a * n + i] = W[(size_t)a * n + i] + sign * acc;
+}
+
+void launch_smultiaxpy(const zd* X, size_t lds, size_t ldv, const int* slot, const int* cnt, const zd* h, double sign,
+                       zd* W, size_t n, int A, hipStream_t s) {
+  if (A <= 0) return;
+  hipLaunchKernelGGL(k_smultiaxpy, dim3((unsigned)((n + 255) / 256), A), dim3(256), 0, s, X, lds, ldv, slot, cnt, h,
+                     sign, W, n);
+}
+
+// x_{slot[a]} += sum_{q < cnt[a]} Z_{slot[a], q} y[a][q]   (x slot-major, stride n)
+__global__ void k_slincomb(const zd* __restrict__ Z, size_t lds, size_t ldv, const int* __restrict__ slot,
+                           const int* __restrict__ cnt, const zd* __restrict__ y, zd* __restrict__ x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= n) return;
+  const zd* zs = Z + (size_t)slot[a] * lds;
+  const int nq = cnt[a];
+  zd acc = {0, 0};
+  for (int q = 0; q < nq; ++q) acc = acc + zs[(size_t)q * ldv + i] * y[(size_t)a * 64 + q];
+  zd* xs = x + (size_t)slot[a] * n;
+  xs[i] = xs[i] + acc;
+}
+
+void launch_slincomb(const zd* Z, size_t lds, size_t ldv, const int* slot, const int* cnt, const zd* y, zd* x,
+                     size_t n, int A, hipStream_t s) {
+  if (A <= 0) return;
+  hipLaunchKernelGGL(k_slincomb, dim3((unsigned)((n + 255) / 256), A), dim3(256), 0, s, Z, lds, ldv, slot, cnt, y, x,
+                     n);
+}
+
+// Y_a = X_{slot[a], j[a]}   (j == nullptr: vector 0)
+__global__ void k_sgather(const zd* __restrict__ X, size_t lds, size_t ldv, const int* __restrict__ slot,
+                          const int* __restrict__ j, zd* __restrict__ Y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= n) return;
+  Y[(size_t)a * n + i] = X[(size_t)slot[a] * lds + (size_t)(j ? j[a] : 0) * ldv + i];
+}
+
+void launch_sgather(const zd* X, size_t lds, size_t ldv, const int* slot, const int* j, zd* Y, size_t n, int A,
+                    hipStream_t s) {
+  if (A <= 0) return;
+  hipLaunchKernelGGL(k_sgather, dim3((unsigned)((n + 255) / 256), A), dim3(256), 0, s, X, lds, ldv, slot, j, Y, n);
+}
+
+// X_{slot[a], j[a]} = c[a] * Y_{src[a]}   (c == nullptr: plain copy; src == nullptr: a;
+// Y_k at Y + k * ldy)
+__global__ void k_sscatter(const zd* __restrict__ Y, size_t ldy, const int* __restrict__ src, zd* __restrict__ X,
+                           size_t lds, size_t ldv, const int* __restrict__ slot, const int* __restrict__ j,
+                           const double* __restrict__ c, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= n) return;
+  const zd v = Y[(size_t)(src ? src[a] : a) * ldy + i];
+  X[(size_t)slot[a] * lds + (size_t)(j ? j[a] : 0) * ldv + i] = c ? c[a] * v : v;
+}
+
+void launch_sscatter(const zd* Y, size_t ldy, const int* src, zd* X, size_t lds, size_t ldv, const int* slot,
+                     const int* j, const double* c, size_t n, int A, hipStream_t s) {
+  if (A <= 0) return;
+  hipLaunchKernelGGL(k_sscatter, dim3((unsigned)((n + 255) / 256), A), dim3(256), 0, s, Y, ldy, src, X, lds, ldv,
+                     slot, j, c, n);
 }
 
 }  // namespace bamg
