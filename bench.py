@@ -45,8 +45,11 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--batch", default="8,32", help="right-hand sides per batched solve (comma list, '' for none)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--precisions", default="mixed_fp16,fp64,mixed_bf16,mixed_fp32",
+    ap.add_argument("--precisions", default="mixed_fp16+graphs,mixed_fp16,fp64,fp64+graphs,mixed_bf16,mixed_fp32",
                     help="single-RHS precisions to time; the first one is the headline value")
+    ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
+    ap.add_argument("--c4", type=int, default=1, help="time the 512^2 x 64 RHS batched solve (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up the headline hierarchy, time only the roofline kernel and a plain copy of "
                          "COPY_MIB MiB (the scale of the HBM byte counters), print them and exit")
@@ -86,6 +89,118 @@ def time_launches(fn, reps, launches_per_call, torch):
     e1.record()
     e1.synchronize()
     return e0.elapsed_time(e1) * 1e-3 / (reps * launches_per_call)
+
+
+SERVE_FIELDS = ["s1_64_b3", "c2_128_b6", "c3_256_b10", "c4_512_b10"]
+
+
+def serving(bamg, inputs, torch, np, n_req, rate, tol):
+    """Poisson arrivals of solve requests over four gauge fields (64^2 beta=3,
+    128^2 beta=6, 256^2 beta=10, 512^2 beta=10), 1-32 right-hand sides each,
+    on a threaded server with memory admission and continuous batching (mixed
+    FP16 hierarchies, 32 slots per field).  The hierarchies are made resident
+    by one warm-up request per field; then every request's right-hand sides
+    are placed in HBM and the requests are submitted at their arrival times.
+    Latency is submit -> completion as the server measures it."""
+    rng = np.random.default_rng(4242)
+    sp = bamg.bamg_server_default_params(threaded=1, slots_per_field=32)
+    srv = bamg.bamg_server_create(sp)
+    fids, Ns = [], []
+    t0 = time.time()
+    for name in SERVE_FIELDS:
+        w = inputs.workload(name)
+        U = torch.from_numpy(inputs.load_gauge(w)).to("cuda:0")
+        p = bamg.bamg_default_params(N=w["N"], n_levels=w["n_levels"], seed=w["tv_seed"],
+                                     precision=PRECISIONS["mixed_fp16"])
+        fids.append(bamg.bamg_server_add_field(srv, U, w["m"], p))
+        Ns.append(w["N"])
+        del U
+    t_gauge = time.time() - t0
+    t0 = time.time()
+    keep = []
+    for f, N in zip(fids, Ns):  # warm-up: setup + one solve per field
+        B = torch.from_numpy(inputs.gaussian((1, 2 * N * N), 7000 + N)).to("cuda:0")
+        X = torch.zeros_like(B)
+        rid = bamg.bamg_server_submit(srv, f, B, X, 1, tol)
+        keep.append((rid, B, X))
+    for rid, B, X in keep:
+        bamg.bamg_server_wait(srv, rid, 1)
+    t_warm = time.time() - t0
+    warm = bamg.bamg_server_get_stats(srv)
+    bamg.bamg_server_reset_stats(srv)
+    # the request stream
+    which = rng.integers(0, len(fids), n_req)
+    nrhs = rng.integers(1, 33, n_req)
+    gaps = rng.exponential(1.0 / rate, n_req)
+    reqs = []
+    for i in range(n_req):
+        N = Ns[which[i]]
+        B = torch.from_numpy(inputs.gaussian((int(nrhs[i]), 2 * N * N), 8000 + i)).to("cuda:0")
+        reqs.append((fids[which[i]], int(nrhs[i]), B, torch.zeros_like(B)))
+    torch.cuda.synchronize()
+    ids = []
+    t_start = time.perf_counter()
+    t_next = t_start
+    for i, (f, k, B, X) in enumerate(reqs):
+        t_next += gaps[i]
+        dt = t_next - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(bamg.bamg_server_submit(srv, f, B, X, k, tol))
+    iters, conv = [], True
+    per_field = {name: 0 for name in SERVE_FIELDS}
+    for (f, k, B, X), rid in zip(reqs, ids):
+        st, infos = bamg.bamg_server_wait(srv, rid, k)
+        conv = conv and st == 0 and all(v["relres_reduced"] <= tol for v in infos)
+        iters.append(max(v["iters"] for v in infos))
+        per_field[SERVE_FIELDS[fids.index(f)]] += k
+    t_end = time.perf_counter()
+    st = bamg.bamg_server_get_stats(srv)
+    bamg.bamg_server_free(srv)
+    n_timed, rhs_timed = st["completed"], st["rhs_completed"]
+    return {
+        "fields": {n: {"N": N_} for n, N_ in zip(SERVE_FIELDS, Ns)}, "precision": "mixed_fp16",
+        "slots_per_field": sp.slots_per_field, "requests": n_timed, "rhs": rhs_timed, "rhs_per_field": per_field,
+        "arrival_rate_per_s": rate, "offered_s": float(np.sum(gaps)),
+        "solves_per_s": rhs_timed / (t_end - t_start), "wall_s": t_end - t_start,
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+        "latency": "submit to completion per request (server clock), nearest-rank percentiles",
+        "max_iters": int(max(iters)), "converged": conv, "setups": st["setups"], "evictions": st["evictions"],
+        "bytes_in_use": st["bytes_in_use"], "budget_bytes": st["budget_bytes"], "rounds": st["rounds"],
+        "setup_warmup_s": t_warm, "warmup_setups": warm["setups"], "gauge_gen_s": t_gauge,
+    }
+
+
+def c4_batched(bamg, inputs, torch, tol, reps=2):
+    """512^2, beta=10, 64 right-hand sides on one gauge field: the multi-RHS
+    solve (mixed FP16 hierarchy, MFMA coarse smoother, batched kernels)."""
+    w = inputs.workload("c4_512_b10")
+    N = w["N"]
+    U = torch.from_numpy(inputs.load_gauge(w)).to("cuda:0")
+    out = {"workload": w["name"], "N": N, "nrhs": w["nrhs"], "m": w["m"], "precision": "mixed_fp16"}
+    p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS["mixed_fp16"])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    h = bamg.bamg_setup(U, w["m"], p)
+    torch.cuda.synchronize()
+    out["setup_s"] = time.time() - t0
+    out["levels"] = bamg.bamg_n_levels(h)
+    R = w["nrhs"]
+    B = torch.from_numpy(inputs.gaussian((R, 2 * N * N), w["rhs_seed"])).to("cuda:0")
+    X = torch.zeros_like(B)
+    bamg.bamg_solve_batch(h, B, X, R, tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st, infos = bamg.bamg_solve_batch(h, B, X, R, tol)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    out.update({"solves_per_s": R / t, "ms_per_batch": 1e3 * t, "max_iters": max(i["iters"] for i in infos),
+                "converged": all(i["relres_reduced"] <= tol for i in infos)})
+    bamg.bamg_free(h)
+    del U, B, X
+    torch.cuda.empty_cache()
+    return out
 
 
 def dhat_bandwidth(bamg, inputs, torch, N, nrhs, reps):
@@ -129,16 +244,19 @@ def main():
     precs = [v.strip() for v in args.precisions.split(",") if v.strip()]
     head = precs[0]
     if args.roofline_only:
-        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[head])
+        hp = head.partition("+")[0]
+        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[hp])
         h = bamg.bamg_setup(U, w["m"], p)
-        out = {"workload": w["name"], "precision": head, "roofline": roofline(bamg, torch, h, head),
+        out = {"workload": w["name"], "precision": hp, "roofline": roofline(bamg, torch, h, hp),
                "copy_calibration": copy_calibration(torch)}
         bamg.bamg_free(h)
         print(json.dumps(out), flush=True)
         return
     results, hier, xs = {}, {}, {}
     for prec in precs:
-        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[prec])
+        base, _, opt = prec.partition("+")  # "<precision>+graphs": iterations replayed as hipGraphs
+        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[base],
+                                     graphs=1 if opt == "graphs" else 0)
         torch.cuda.synchronize()
         t0 = time.time()
         h = bamg.bamg_setup(U, w["m"], p)
@@ -185,7 +303,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPES[head],
+        "dtype": DTYPES[head.partition("+")[0]],
         "data": "synthetic",
         "config": {
             "workload": w["name"], "N": N, "beta": w["beta"], "metropolis_sweeps": w["sweeps"],
@@ -221,6 +339,15 @@ def main():
     if batched:
         out["batched"] = batched
 
+    # ---- 512^2 x 64 right-hand sides on one field (multi-RHS form)
+    if args.c4:
+        out["c4_512x64"] = c4_batched(bamg, inputs, torch, args.tol)
+
+    # ---- serving: Poisson arrivals over four fields, continuous batching
+    if args.serve > 0:
+        out["serving"] = serving(bamg, inputs, torch, np, args.serve, args.serve_rate, args.tol)
+        out["serving_p99_ms"] = out["serving"]["p99_ms"]
+
     # ---- Dhat ("D_oe") bandwidth: cache-resident, batched, cache-busting
     if not args.no_dhat:
         pts = []
@@ -230,7 +357,7 @@ def main():
 
     # ---- roofline of the dominant kernel of the solve
     if not args.no_roofline:
-        out["roofline"] = roofline(bamg, torch, h, head)
+        out["roofline"] = roofline(bamg, torch, h, head.partition("+")[0])
 
     # ---- CPU oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:

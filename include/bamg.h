@@ -86,6 +86,9 @@ typedef struct {
   uint64_t seed;        /* Philox4x32-10 key of the random initial test vectors */
   const double *init_tv_host; /* optional HOST [n_tv][N*N] complex reduced vectors; overrides seed */
   void *stream;         /* hipStream_t for all work, or NULL for the null stream */
+  int32_t graphs;       /* 1: replay each FGMRES iteration (cycle, Dhat, Gram-Schmidt, norms) as a
+                           captured hipGraph, one per (iteration index | batch size); 0 (default):
+                           launch the kernels one by one.  Results are bitwise the same. */
 } bamg_params;
 
 typedef struct {
@@ -242,6 +245,8 @@ int bamg_server_progress(bamg_server *s, int32_t *pending);
  * NULL) and the request forgotten; else BAMG_PENDING. */
 int bamg_server_wait(bamg_server *s, int64_t request_id, double timeout_ms, bamg_solve_info *infos_host);
 int bamg_server_get_stats(bamg_server *s, bamg_server_stats *out);
+/* Zero the statistics (counters and latencies); resident fields stay. */
+int bamg_server_reset_stats(bamg_server *s);
 void bamg_server_free(bamg_server *s);
 
 /* Text of the last error on this thread ("" if none). */

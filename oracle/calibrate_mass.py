@@ -40,6 +40,9 @@ WORKLOADS = {
                        n_levels=0, nrhs=1),
     "c4_512_b10": dict(N=512, beta=10.0, sweeps=500, gauge_seed=4, target=1e-4, rhs_seed=1001, tv_seed=204,
                        n_levels=0, nrhs=64),
+    # the fourth field of the serving mix (with c2, c3 and c4)
+    "s1_64_b3": dict(N=64, beta=3.0, sweeps=200, gauge_seed=5, target=1e-3, rhs_seed=105, tv_seed=205,
+                     n_levels=0, nrhs=1),
 }
 
 

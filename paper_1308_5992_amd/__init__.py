@@ -30,7 +30,8 @@ EXPORTED = [
     "bamg_export_level", "bamg_import_level", "bamg_footprint_bytes", "bamg_gaussian_tv",
     "bamg_free", "bamg_last_error",
     "bamg_server_default_params", "bamg_server_create", "bamg_server_add_field", "bamg_server_field_bytes",
-    "bamg_server_submit", "bamg_server_progress", "bamg_server_wait", "bamg_server_get_stats", "bamg_server_free",
+    "bamg_server_submit", "bamg_server_progress", "bamg_server_wait", "bamg_server_get_stats", "bamg_server_reset_stats",
+    "bamg_server_free",
 ]
 
 
@@ -41,6 +42,7 @@ class bamg_params(ctypes.Structure):
         ("pre", ctypes.c_int32), ("post", ctypes.c_int32), ("cycle", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("init_tv_host", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+        ("graphs", ctypes.c_int32),
     ]
 
 
@@ -73,7 +75,7 @@ class bamg_server_stats(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libbamg.so is not built ({LIB_PATH}); run python -m paper_1308_5992_amd.build")
+        raise ImportError(f"libbamg.so is not built ({LIB_PATH}); run python paper_1308_5992_amd/build.py")
     L = ctypes.CDLL(LIB_PATH)
     P, I32, D, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_size_t
     PP = ctypes.POINTER(bamg_params)
@@ -103,6 +105,7 @@ def _load():
         "bamg_server_progress": (I32, [P, ctypes.POINTER(I32)]),
         "bamg_server_wait": (I32, [P, ctypes.c_int64, D, PI]),
         "bamg_server_get_stats": (I32, [P, ctypes.POINTER(bamg_server_stats)]),
+        "bamg_server_reset_stats": (I32, [P]),
         "bamg_server_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
@@ -333,6 +336,10 @@ def bamg_server_get_stats(s) -> dict:
     st = bamg_server_stats()
     _check(lib.bamg_server_get_stats(s, ctypes.byref(st)), "bamg_server_get_stats")
     return st.as_dict()
+
+
+def bamg_server_reset_stats(s):
+    _check(lib.bamg_server_reset_stats(s), "bamg_server_reset_stats")
 
 
 def bamg_server_free(s):

@@ -1,6 +1,6 @@
 """Build libbamg.so in-tree with hipcc for gfx950.
 
-Run:  python -m paper_1308_5992_amd.build
+Run:  python paper_1308_5992_amd/build.py   (by path: importing the package loads the library)
 """
 from __future__ import annotations
 

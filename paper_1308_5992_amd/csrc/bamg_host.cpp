@@ -72,6 +72,7 @@ bool valid_params(const bamg_params* p, std::string& why) {
   if (p->restart < 1 || p->restart > 60) { why = "restart must be in [1, 60]"; return false; }
   if (p->max_iter < 0) { why = "max_iter < 0"; return false; }
   if (p->max_coarse < 16) { why = "max_coarse < 16"; return false; }
+  if (p->graphs != 0 && p->graphs != 1) { why = "graphs must be 0 or 1"; return false; }
   return true;
 }
 
@@ -489,15 +490,19 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
     for (int j = 0; j < m; ++j) {
       zd* vj = h->V + (size_t)j * R * n;
       zd* zj = h->Z + (size_t)j * R * n;
-      h->precondition(vj, zj, R);
-      h->apply(0, zj, h->w, nullptr, R);
-      launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, s);
-      launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, s);
-      launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, s);
-      launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, s);
-      launch_norms(h->w, n, R, n, h->partial, hn2, s);
-      check_launch();
-      HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, s));
+      // z_j = M v_j, w = Dhat z_j, CGS2 against v_0..v_j, |w|^2, to the host
+      h->run_graph(((uint64_t)R << 8) | (uint64_t)j, [&] {
+        hipStream_t sc = h->s;
+        h->precondition(vj, zj, R);
+        h->apply(0, zj, h->w, nullptr, R);
+        launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, sc);
+        launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, sc);
+        launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, sc);
+        launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, sc);
+        launch_norms(h->w, n, R, n, h->partial, hn2, sc);
+        check_launch();
+        HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
+      });
       HIPCHK(hipStreamSynchronize(s));
       jmax = j + 1;
       bool still = false;

@@ -141,6 +141,7 @@ SlotEngine* engine_create(bamg_hierarchy* h, int S) {
     HIPCHK(hipHostMalloc((void**)&e->yh, (size_t)64 * S * sizeof(zd)));
     e->slots.assign(S, Slot{});
     h->ensure_cap(S);
+    ++h->graph_gen;  // captured graphs name the engine's buffers
   } catch (...) {
     delete e;
     throw;
@@ -148,7 +149,11 @@ SlotEngine* engine_create(bamg_hierarchy* h, int S) {
   return e;
 }
 
-void engine_destroy(SlotEngine* e) { delete e; }
+void engine_destroy(SlotEngine* e) {
+  if (!e) return;
+  ++e->h->graph_gen;
+  delete e;
+}
 int engine_capacity(const SlotEngine* e) { return e->S; }
 int engine_free_slots(const SlotEngine* e) { return e->S - e->busy; }
 int engine_busy(const SlotEngine* e) { return e->busy; }
@@ -283,25 +288,31 @@ void engine_issue_main(SlotEngine* e) {
   zd* h1 = e->hdev;
   zd* h2 = e->hdev + (size_t)64 * S;
   zd* hn = e->hdev + (size_t)128 * S;
-  launch_sgather(e->V, ldsV, n, d_slot, d_j, e->cur, n, A, s);
   const bool saved = h->force_mr;
   h->force_mr = true;  // the same kernels for every A: batch invariance
+  // with graphs every Gram-Schmidt launch covers all m + 1 basis vectors (the
+  // blocks beyond an entry's count exit), so one graph serves each A
+  const int mc = h->p.graphs ? m + 1 : maxcnt;
   try {
-    h->precondition(e->cur, e->zc, A);
+    h->run_graph((1ull << 40) | (uint64_t)A, [&] {
+      hipStream_t sc = h->s;
+      launch_sgather(e->V, ldsV, n, d_slot, d_j, e->cur, n, A, sc);
+      h->precondition(e->cur, e->zc, A);
+      launch_sscatter(e->zc, n, nullptr, e->Z, ldsZ, n, d_slot, d_j, nullptr, n, A, sc);
+      h->apply(0, e->zc, e->w, nullptr, A);
+      launch_smultidot(e->V, ldsV, n, d_slot, d_cnt, mc, e->w, n, A, e->partial, h1, sc);
+      launch_smultiaxpy(e->V, ldsV, n, d_slot, d_cnt, h1, -1.0, e->w, n, A, sc);
+      launch_smultidot(e->V, ldsV, n, d_slot, d_cnt, mc, e->w, n, A, e->partial, h2, sc);
+      launch_smultiaxpy(e->V, ldsV, n, d_slot, d_cnt, h2, -1.0, e->w, n, A, sc);
+      launch_norms(e->w, n, A, n, e->partial, hn, sc);
+      check_launch();
+      HIPCHK(hipMemcpyAsync(e->hhost, e->hdev, ((size_t)128 * S + A) * sizeof(zd), hipMemcpyDeviceToHost, sc));
+    });
   } catch (...) {
     h->force_mr = saved;
     throw;
   }
   h->force_mr = saved;
-  launch_sscatter(e->zc, n, nullptr, e->Z, ldsZ, n, d_slot, d_j, nullptr, n, A, s);
-  h->apply(0, e->zc, e->w, nullptr, A);
-  launch_smultidot(e->V, ldsV, n, d_slot, d_cnt, maxcnt, e->w, n, A, e->partial, h1, s);
-  launch_smultiaxpy(e->V, ldsV, n, d_slot, d_cnt, h1, -1.0, e->w, n, A, s);
-  launch_smultidot(e->V, ldsV, n, d_slot, d_cnt, maxcnt, e->w, n, A, e->partial, h2, s);
-  launch_smultiaxpy(e->V, ldsV, n, d_slot, d_cnt, h2, -1.0, e->w, n, A, s);
-  launch_norms(e->w, n, A, n, e->partial, hn, s);
-  check_launch();
-  HIPCHK(hipMemcpyAsync(e->hhost, e->hdev, ((size_t)128 * S + A) * sizeof(zd), hipMemcpyDeviceToHost, s));
 }
 
 void engine_finish_main(SlotEngine* e, std::vector<SlotDone>& done) {

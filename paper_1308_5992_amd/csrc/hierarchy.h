@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdint>
 #include <complex>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -127,6 +128,52 @@ struct bamg_hierarchy {
   zd *ycoef_dev = nullptr, *ycoef_host = nullptr;    // per right-hand side update coefficients
   zd* tvsave = nullptr; // level-0 test vectors after the last setup pass
   SlotEngine* engine = nullptr;  // batched solves (slot engine, created on first use)
+  // captured launch sequences (p.graphs): one executable graph per key, valid
+  // while the buffers they name stay allocated (graph_gen counts reallocations)
+  std::map<uint64_t, hipGraphExec_t> graphs;
+  uint64_t graph_gen = 0, graphs_gen = 0;
+  hipStream_t cap_stream = nullptr;
+
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+  // run issue() (launches on `s`) directly, or as the replay of its captured graph
+  template <typename F>
+  void run_graph(uint64_t key, F&& issue) {
+    if (!p.graphs) {
+      issue();
+      return;
+    }
+    if (graphs_gen != graph_gen) {
+      drop_graphs();
+      graphs_gen = graph_gen;
+    }
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+      if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+      hipStream_t saved = s;
+      s = cap_stream;
+      HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
+      hipGraph_t g = nullptr;
+      try {
+        issue();
+      } catch (...) {
+        (void)hipStreamEndCapture(cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        s = saved;
+        throw;
+      }
+      s = saved;
+      HIPCHK(hipStreamEndCapture(cap_stream, &g));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) throw HipFail(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      it = graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, s));
+  }
 
   void free_krylov() {
     dfree(V); dfree(Z); dfree(w); dfree(bh); dfree(xe); dfree(rr); dfree(partial); dfree(hdev);
@@ -142,6 +189,7 @@ struct bamg_hierarchy {
   void ensure_krylov(int R, bool bases) {
     const size_t n0 = lv[0].n;
     if (R > kcap || (bases && !V)) {
+      ++graph_gen;
       const int cap2 = std::max(R, kcap);
       const bool had_bases = V != nullptr || bases;
       free_krylov();
@@ -176,6 +224,8 @@ struct bamg_hierarchy {
     free_krylov();
     dfree(tvsave);
     if (engine) engine_destroy(engine);
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 
   int L() const { return (int)lv.size(); }
@@ -185,6 +235,7 @@ struct bamg_hierarchy {
 
   void ensure_cap(int nrhs) {
     if (nrhs <= cap) return;
+    ++graph_gen;
     dfree(mmwork);
     mmwork = nullptr;
     if (L() > 1) mmwork = dalloc<zd>(dense_mm_workspace((int)lv.back().n, nrhs));

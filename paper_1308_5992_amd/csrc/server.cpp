@@ -430,6 +430,18 @@ int bamg_server_get_stats(bamg_server* s, bamg_server_stats* out) {
   return BAMG_OK;
 }
 
+int bamg_server_reset_stats(bamg_server* s) {
+  if (!s) return api_fail(BAMG_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->submitted = s->completed = s->rhs_completed = s->rounds = 0;
+  s->evictions = s->setups = 0;
+  s->latencies.clear();
+  s->any_submit = false;
+  for (const auto& kv : s->reqs)
+    if (!kv.second.finished) ++s->submitted;  // still in flight: counted as submitted from now on
+  return BAMG_OK;
+}
+
 void bamg_server_free(bamg_server* s) {
   if (!s) return;
   {

@@ -428,3 +428,37 @@ def test_mixed_batch_results_do_not_depend_on_the_batch(bamg, prec):
         assert np.array_equal(host(x1)[0], Xb[r])
         full = np.linalg.norm(B[r] - oracle.wilson_apply(U, w["m"], Xb[r])) / np.linalg.norm(B[r])
         assert full < 2e-10
+
+
+# ---------------------------------------------------------------- hipGraph replay
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replay_equals_eager(bamg, prec):
+    """graphs = 1 replays each FGMRES iteration as a captured graph (one per
+    iteration index, and one per batch size in the batched engine).  Every
+    replay, with eager work and synchronisations in between, gives bitwise the
+    eager result, single and batched."""
+    w = inputs.workload("c1_32_b3")
+    U = inputs.load_gauge(w)
+    N = w["N"]
+    kw = dict(n_levels=w["n_levels"], seed=w["tv_seed"], precision=prec)
+    he = make_h(bamg, U, w["m"], **kw)
+    hg = make_h(bamg, U, w["m"], graphs=1, **kw)
+    B = inputs.gaussian((6, 2 * N * N), 61)
+    for rep in range(3):
+        for r in range(2):
+            b = dev(B[r + rep])
+            xe = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
+            xg = torch.zeros_like(xe)
+            ste, ie = bamg.bamg_solve(he, b, xe, 1e-10)
+            junk = torch.randn(1000, device="cuda:0").sum()  # eager work between replays
+            stg, ig = bamg.bamg_solve(hg, b, xg, 1e-10)
+            torch.cuda.synchronize()
+            assert ste == 0 and stg == 0 and ie["iters"] == ig["iters"]
+            assert np.array_equal(host(xe), host(xg)), (rep, r)
+        for R in (3, 2):
+            Xe = torch.zeros(R, 2 * N * N, dtype=torch.complex128, device="cuda:0")
+            Xg = torch.zeros_like(Xe)
+            bamg.bamg_solve_batch(he, dev(B[:R]), Xe, R, 1e-10)
+            float(junk)
+            bamg.bamg_solve_batch(hg, dev(B[:R]), Xg, R, 1e-10)
+            assert np.array_equal(host(Xe), host(Xg)), (rep, R)
