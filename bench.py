@@ -77,6 +77,14 @@ def copy_calibration(torch):
             "bytes_written": COPY_MIB * 2 ** 20, "us": t * 1e6, "GB/s": 2 * COPY_MIB * 2 ** 20 / t / 1e9}
 
 
+T0 = time.time()
+
+
+def progress(msg):
+    """One line per finished stage on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg} ({time.time() - T0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def time_launches(fn, reps, launches_per_call, torch):
     """Average duration per kernel launch of fn() (events on the library's stream)."""
     fn()
@@ -284,6 +292,7 @@ def main():
         }
         hier[prec] = h
         xs[prec] = x.cpu().numpy()
+        progress(f"{prec}: {results[prec]['solves_per_s']:.1f} solves/s")
     if "fp64" in xs:
         for prec in precs:
             if prec != "fp64":
@@ -336,17 +345,20 @@ def main():
                         "max_iters": max(i["iters"] for i in infs),
                         "converged": all(i["relres_reduced"] <= args.tol for i in infs)})
         del B, X
+        progress(f"batched R={R}: {batched[-1]['solves_per_s']:.1f} solves/s")
     if batched:
         out["batched"] = batched
 
     # ---- 512^2 x 64 right-hand sides on one field (multi-RHS form)
     if args.c4:
         out["c4_512x64"] = c4_batched(bamg, inputs, torch, args.tol)
+        progress(f"512^2 x 64: {out['c4_512x64']['solves_per_s']:.1f} solves/s")
 
     # ---- serving: Poisson arrivals over four fields, continuous batching
     if args.serve > 0:
         out["serving"] = serving(bamg, inputs, torch, np, args.serve, args.serve_rate, args.tol)
         out["serving_p99_ms"] = out["serving"]["p99_ms"]
+        progress(f"serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms")
 
     # ---- Dhat ("D_oe") bandwidth: cache-resident, batched, cache-busting
     if not args.no_dhat:
@@ -354,14 +366,17 @@ def main():
         for (n_, r_, reps) in ((256, 1, 200), (512, 64, 20), (4096, 1, 20)):
             pts.append(dhat_bandwidth(bamg, inputs, torch, n_, r_, reps))
         out["dhat_bandwidth"] = pts
+        progress("dhat bandwidth")
 
     # ---- roofline of the dominant kernel of the solve
     if not args.no_roofline:
         out["roofline"] = roofline(bamg, torch, h, head.partition("+")[0])
+        progress("roofline")
 
     # ---- CPU oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, U_np, args.tol)
+        progress("cpu baseline")
 
     for hh in hier.values():
         bamg.bamg_free(hh)
