@@ -3,10 +3,13 @@
 
 Workload (default): 256 x 256 periodic lattice, quenched U(1) links from 500
 Metropolis sweeps at beta = 10 (seed 3), mass calibrated so that
-min |eig(D)| ~ 1e-4, one complex Gaussian right-hand side (seed 103); 4-level
-hierarchy (4x4 then 2x2 aggregates, 8 test vectors), V(4,4) cycle, FGMRES(32)
-to a relative residual of 1e-10 on the reduced system.  Setup is done once
-and timed separately; every timed step is one full solve (reduction, FGMRES,
+min |eig(D)| ~ 1e-4, one complex Gaussian right-hand side (seed 103); the
+hierarchy has 3 levels (4x4 then 2x2 aggregates, 8 test vectors, coarsest
+level of dimension 8192 solved with its dense FP64 inverse), FGMRES(32) to a
+relative residual of 1e-10 on the reduced system.  The headline variant is
+mixed FP16 with a V(2,2) cycle and hipGraph replay; the other variants (FP64,
+V(4,4), BF16 and FP32 storage) are timed beside it.  Setup is done once and
+timed separately; every timed step is one full solve (reduction, FGMRES,
 reconstruction) with the right-hand side already in HBM.
 
 Prints one JSON line (rank 0).  Besides solves/s it reports the Dhat
@@ -45,8 +48,11 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--batch", default="8,32", help="right-hand sides per batched solve (comma list, '' for none)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--precisions", default="mixed_fp16+graphs,mixed_fp16,fp64,fp64+graphs,mixed_bf16,mixed_fp32",
-                    help="single-RHS precisions to time; the first one is the headline value")
+    ap.add_argument("--precisions",
+                    default="mixed_fp16+graphs+v22,fp64+graphs+v22,mixed_fp16+graphs,fp64+graphs,mixed_fp16,"
+                            "mixed_bf16+graphs+v22,mixed_fp32+graphs+v22",
+                    help="single-RHS variants to time, <precision>[+graphs][+v22] (graphs: iterations replayed as "
+                         "hipGraphs; v22: V(2,2) cycle instead of V(4,4)); the first one is the headline value")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
     ap.add_argument("--c4", type=int, default=1, help="time the 512^2 x 64 RHS batched solve (0: skip)")
@@ -57,6 +63,18 @@ def parse():
 
 
 COPY_MIB = 256
+
+
+def variant(spec):
+    """Solver parameters of a bench variant '<precision>[+graphs][+v22]'."""
+    base, *opts = spec.split("+")
+    kw = {"precision": PRECISIONS[base], "graphs": 1 if "graphs" in opts else 0}
+    if "v22" in opts:
+        kw.update(pre=2, post=2)
+    unknown = set(opts) - {"graphs", "v22"}
+    if unknown:
+        raise SystemExit(f"bench.py: unknown variant option(s) {sorted(unknown)} in {spec!r}")
+    return base, kw
 
 
 def copy_calibration(torch):
@@ -102,11 +120,11 @@ def time_launches(fn, reps, launches_per_call, torch):
 SERVE_FIELDS = ["s1_64_b3", "c2_128_b6", "c3_256_b10", "c4_512_b10"]
 
 
-def serving(bamg, inputs, torch, np, n_req, rate, tol):
+def serving(bamg, inputs, torch, np, n_req, rate, tol, kw):
     """Poisson arrivals of solve requests over four gauge fields (64^2 beta=3,
     128^2 beta=6, 256^2 beta=10, 512^2 beta=10), 1-32 right-hand sides each,
-    on a threaded server with memory admission and continuous batching (mixed
-    FP16 hierarchies, 32 slots per field).  The hierarchies are made resident
+    on a threaded server with memory admission and continuous batching (the
+    headline solver parameters, 32 slots per field).  The hierarchies are made resident
     by one warm-up request per field; then every request's right-hand sides
     are placed in HBM and the requests are submitted at their arrival times.
     Latency is submit -> completion as the server measures it."""
@@ -118,8 +136,7 @@ def serving(bamg, inputs, torch, np, n_req, rate, tol):
     for name in SERVE_FIELDS:
         w = inputs.workload(name)
         U = torch.from_numpy(inputs.load_gauge(w)).to("cuda:0")
-        p = bamg.bamg_default_params(N=w["N"], n_levels=w["n_levels"], seed=w["tv_seed"],
-                                     precision=PRECISIONS["mixed_fp16"])
+        p = bamg.bamg_default_params(N=w["N"], n_levels=w["n_levels"], seed=w["tv_seed"], **kw)
         fids.append(bamg.bamg_server_add_field(srv, U, w["m"], p))
         Ns.append(w["N"])
         del U
@@ -167,7 +184,7 @@ def serving(bamg, inputs, torch, np, n_req, rate, tol):
     bamg.bamg_server_free(srv)
     n_timed, rhs_timed = st["completed"], st["rhs_completed"]
     return {
-        "fields": {n: {"N": N_} for n, N_ in zip(SERVE_FIELDS, Ns)}, "precision": "mixed_fp16",
+        "fields": {n: {"N": N_} for n, N_ in zip(SERVE_FIELDS, Ns)}, "solver": kw,
         "slots_per_field": sp.slots_per_field, "requests": n_timed, "rhs": rhs_timed, "rhs_per_field": per_field,
         "arrival_rate_per_s": rate, "offered_s": float(np.sum(gaps)),
         "solves_per_s": rhs_timed / (t_end - t_start), "wall_s": t_end - t_start,
@@ -179,14 +196,16 @@ def serving(bamg, inputs, torch, np, n_req, rate, tol):
     }
 
 
-def c4_batched(bamg, inputs, torch, tol, reps=2):
+def c4_batched(bamg, inputs, torch, tol, kw, reps=2):
     """512^2, beta=10, 64 right-hand sides on one gauge field: the multi-RHS
-    solve (mixed FP16 hierarchy, MFMA coarse smoother, batched kernels)."""
+    solve with the headline solver parameters (MFMA coarse smoother, batched
+    kernels)."""
     w = inputs.workload("c4_512_b10")
     N = w["N"]
     U = torch.from_numpy(inputs.load_gauge(w)).to("cuda:0")
-    out = {"workload": w["name"], "N": N, "nrhs": w["nrhs"], "m": w["m"], "precision": "mixed_fp16"}
-    p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS["mixed_fp16"])
+    p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], **kw)
+    out = {"workload": w["name"], "N": N, "nrhs": w["nrhs"], "m": w["m"], "precision": p.precision,
+           "cycle": f"V({p.pre},{p.post})", "graphs": bool(p.graphs)}
     torch.cuda.synchronize()
     t0 = time.time()
     h = bamg.bamg_setup(U, w["m"], p)
@@ -251,20 +270,20 @@ def main():
     b = torch.from_numpy(inputs.gaussian(2 * N * N, w["rhs_seed"])).to("cuda:0")
     precs = [v.strip() for v in args.precisions.split(",") if v.strip()]
     head = precs[0]
+    head_base, head_kw = variant(head)
     if args.roofline_only:
-        hp = head.partition("+")[0]
-        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[hp])
+        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], **head_kw)
         h = bamg.bamg_setup(U, w["m"], p)
-        out = {"workload": w["name"], "precision": hp, "roofline": roofline(bamg, torch, h, hp),
+        dom, others = roofline(bamg, torch, h, head_base)
+        out = {"workload": w["name"], "precision": head_base, "roofline": dom, "roofline_others": others,
                "copy_calibration": copy_calibration(torch)}
         bamg.bamg_free(h)
         print(json.dumps(out), flush=True)
         return
     results, hier, xs = {}, {}, {}
     for prec in precs:
-        base, _, opt = prec.partition("+")  # "<precision>+graphs": iterations replayed as hipGraphs
-        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], precision=PRECISIONS[base],
-                                     graphs=1 if opt == "graphs" else 0)
+        _, kw = variant(prec)
+        p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], **kw)
         torch.cuda.synchronize()
         t0 = time.time()
         h = bamg.bamg_setup(U, w["m"], p)
@@ -289,15 +308,19 @@ def main():
             "p50_ms": statistics.median(ms), "p99_ms": float(np.percentile(ms, 99)),
             "iters": infos[-1]["iters"], "relres_reduced": infos[-1]["relres_reduced"],
             "converged": all(i["relres_reduced"] <= args.tol for i in infos), "setup_s": t_setup,
+            "levels": bamg.bamg_n_levels(h), "cycle": f"V({p.pre},{p.post})", "graphs": bool(p.graphs),
         }
         hier[prec] = h
         xs[prec] = x.cpu().numpy()
         progress(f"{prec}: {results[prec]['solves_per_s']:.1f} solves/s")
-    if "fp64" in xs:
-        for prec in precs:
-            if prec != "fp64":
-                results[prec]["rel_err_vs_fp64"] = float(np.linalg.norm(xs[prec] - xs["fp64"]) /
-                                                         np.linalg.norm(xs["fp64"]))
+    # error of every variant against the FP64 solve with the same cycle
+    for prec in precs:
+        base, kw = variant(prec)
+        refs = [q for q in precs if variant(q)[0] == "fp64" and
+                (variant(q)[1].get("pre"), variant(q)[1].get("post")) == (kw.get("pre"), kw.get("post"))]
+        if base != "fp64" and refs:
+            results[prec]["rel_err_vs_fp64"] = float(np.linalg.norm(xs[prec] - xs[refs[0]]) /
+                                                     np.linalg.norm(xs[refs[0]]))
     h = hier[head]
     n_levels = bamg.bamg_n_levels(h)
     r0 = results[head]
@@ -312,13 +335,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPES[head.partition("+")[0]],
+        "dtype": DTYPES[head_base],
         "data": "synthetic",
         "config": {
             "workload": w["name"], "N": N, "beta": w["beta"], "metropolis_sweeps": w["sweeps"],
             "m": w["m"], "min_abs_eig_D": w["min_abs_eig_D"], "levels": n_levels,
-            "aggregates": "4x4 half-x, then 2x2", "test_vectors": 8, "cycle": "V(4,4)",
-            "krylov": "FGMRES(32)", "tol": args.tol, "nrhs": 1, "precision": head,
+            "aggregates": "4x4 half-x, then 2x2", "test_vectors": 8, "cycle": r0["cycle"],
+            "coarsest": "dense inverse, FP64", "hipgraph": r0["graphs"],
+            "krylov": "FGMRES(32)", "tol": args.tol, "nrhs": 1, "precision": head_base, "variant": head,
         },
         "p50_ms": r0["p50_ms"],
         "p99_ms": r0["p99_ms"],
@@ -351,12 +375,12 @@ def main():
 
     # ---- 512^2 x 64 right-hand sides on one field (multi-RHS form)
     if args.c4:
-        out["c4_512x64"] = c4_batched(bamg, inputs, torch, args.tol)
+        out["c4_512x64"] = c4_batched(bamg, inputs, torch, args.tol, head_kw)
         progress(f"512^2 x 64: {out['c4_512x64']['solves_per_s']:.1f} solves/s")
 
     # ---- serving: Poisson arrivals over four fields, continuous batching
     if args.serve > 0:
-        out["serving"] = serving(bamg, inputs, torch, np, args.serve, args.serve_rate, args.tol)
+        out["serving"] = serving(bamg, inputs, torch, np, args.serve, args.serve_rate, args.tol, head_kw)
         out["serving_p99_ms"] = out["serving"]["p99_ms"]
         progress(f"serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms")
 
@@ -370,7 +394,7 @@ def main():
 
     # ---- roofline of the dominant kernel of the solve
     if not args.no_roofline:
-        out["roofline"] = roofline(bamg, torch, h, head.partition("+")[0])
+        out["roofline"], out["roofline_others"] = roofline(bamg, torch, h, head_base)
         progress("roofline")
 
     # ---- CPU oracle on a bounded sample of the same workload
@@ -383,87 +407,120 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-# Algorithmic bytes one coarse site moves in its colour pass of the Kaczmarz
-# smoother: the 7 blocks of 16x16 complex of its rows (storage type), the 16x16
-# smoother matrix Kinv (cycle type), its 16 right-hand-side entries, and the
-# 7 x 16 unknowns of its row support read and written (the supports of one
-# colour are disjoint, so nothing is counted twice within a launch).
-def _site_bytes(s_op, s_vec):
+# Algorithmic bytes of the three kernels that take the solve's time (see the
+# kernel trace), per launch:
+#  - fine colour pass: per even site of the colour, its 9 x 4 stored couplings
+#    Bst (storage = cycle type), its 2 right-hand-side entries and the 9 x 2
+#    unknowns of its row support read and written (the supports of one colour
+#    are disjoint, so nothing is counted twice within a launch);
+#  - coarse colour pass: per site of the colour, the 7 blocks of 16 x 16 of its
+#    rows (operator storage type), the 16 x 16 smoother matrix Kinv (cycle type),
+#    its 16 right-hand-side entries and the 7 x 16 unknowns of its support read
+#    and written;
+#  - coarsest product: the n x n FP64 inverse and the two vectors.
+def fine_site_bytes(s_vec):
+    return 36 * s_vec + 2 * s_vec + 2 * 9 * 2 * s_vec
+
+
+def coarse_site_bytes(s_op, s_vec):
     return 7 * 256 * s_op + 256 * s_vec + 16 * s_vec + 2 * 7 * 16 * s_vec
 
 
-SITE_SWEEP_BYTES = {"fp64": _site_bytes(16, 16), "mixed_fp32": _site_bytes(8, 8),
-                    "mixed_fp16": _site_bytes(4, 8), "mixed_bf16": _site_bytes(4, 8)}
+VEC_BYTES = {"fp64": 16, "mixed_fp32": 8, "mixed_fp16": 8, "mixed_bf16": 8}
+OP_BYTES = {"fp64": 16, "mixed_fp32": 8, "mixed_fp16": 4, "mixed_bf16": 4}
 
 # HBM byte counters of the same launches (rocprofv3 --pmc FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch, median over the roofline sweeps), each divided
-# by what the counter reads per KiB moved by a plain 256 MiB copy kernel in the
-# same run.  Valid only for the kernel source they were taken on (sha256 of
-# coarse.hip); any change to it makes the reported traffic null.
+# WRITE_SIZE, KiB per dispatch, median over the roofline launches), each
+# divided by what the counter reads per KiB moved by a plain 256 MiB copy
+# kernel in the same run.  Valid only for the kernel source they were taken on
+# (sha256 of the kernel's file); any change to it makes the traffic null.
+COPY_SCALE = {"fetch_per_kib": 131090.6 / 262144.0, "write_per_kib": 262144.0 / 262144.0}
 PMC_TRAFFIC = {
-    "mixed_fp16": {"coarse_hip_sha256": "676578ea4fbb84cbfe95f0270878300590c3ed8b8a3c4a9fb0a712aea4efed1e",
-                   "fetch_kib": 1313.0, "write_kib": 224.0, "fetch_per_kib": 131090.6 / 262144.0,
-                   "write_per_kib": 262144.0 / 262144.0,
-                   "profile": "profiles/kaczmarz_coarse_level1_c3_256_mixed_fp16_pmc.md"},
+    ("coarse", "mixed_fp16"): {"src": "coarse.hip",
+                               "sha256": "676578ea4fbb84cbfe95f0270878300590c3ed8b8a3c4a9fb0a712aea4efed1e",
+                               "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE,
+                               "profile": "profiles/kaczmarz_coarse_level1_c3_256_mixed_fp16_pmc.md"},
 }
 
 
-def pmc_traffic(prec):
+def pmc_traffic(kind, prec):
     import hashlib
-    e = PMC_TRAFFIC.get(prec)
+    e = PMC_TRAFFIC.get((kind, prec))
     if e is None:
         return None
-    with open(os.path.join(ROOT, "paper_1308_5992_amd", "csrc", "coarse.hip"), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != e["coarse_hip_sha256"]:
+    with open(os.path.join(ROOT, "paper_1308_5992_amd", "csrc", e["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
             return None
     return 1024.0 * (e["fetch_kib"] / e["fetch_per_kib"] + e["write_kib"] / e["write_per_kib"])
 
 
-def roofline(bamg, torch, h, prec):
-    """Coarse Kaczmarz colour pass on level 1 of the headline hierarchy (with
-    the fine pass, the kernels that take the solve's time; see the kernel
-    trace).  One launch is one colour: 1/ncol of the level's sites, each moving
-    SITE_SWEEP_BYTES[prec] algorithmic bytes.  Timed with HIP events over 50
-    sweeps on the library's stream (torch's current stream); a mixed hierarchy
-    is driven through the complex64 hook, which launches exactly the ncol
-    colour passes of one sweep and nothing else."""
-    inf = bamg.bamg_level_info(h, 1)
-    ns = inf["ex"] * inf["ey"]
-    ncol = inf["colours"]
-    n = inf["n"]
-    if prec == "fp64":
-        dt, op = torch.complex128, bamg.OP_SWEEP
-        kname = "k_kaczmarz_coarse<double,cx<double>>"
-    else:
-        dt, op = torch.complex64, bamg.OP_SWEEP_F32
-        kname = {"mixed_fp16": "k_kaczmarz_coarse<float,hcx>", "mixed_bf16": "k_kaczmarz_coarse<float,bcx>",
-                 "mixed_fp32": "k_kaczmarz_coarse<float,cx<float>>"}[prec]
-    xb = torch.zeros(n, dtype=dt, device="cuda:0")
-    bb = torch.ones(n, dtype=dt, device="cuda:0")
-    t = time_launches(lambda: bamg.bamg_level_op(h, 1, op, bb, xb, 1), 50, ncol, torch)
-    bytes_launch = ns * SITE_SWEEP_BYTES[prec] / ncol
+def _roof(kname, kind, prec, bytes_launch, t):
     achieved = bytes_launch / t / 1e9
-    return {"kernel": kname + f" (level 1, {ns // ncol} sites per launch)", "bound": "hbm",
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": pmc_traffic(prec), "traffic_unit": "bytes per launch",
+    return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(kind, prec), "traffic_unit": "bytes per launch",
             "avg_launch_us": t * 1e6, "bytes_per_launch": bytes_launch}
 
 
+def roofline(bamg, torch, h, prec):
+    """The three kernels that take the solve's time, each timed with HIP events
+    on the library's stream (torch's current stream) over back-to-back
+    launches driven through the level hooks: the fine colour pass (the
+    largest share; 16 launches per sweep), the coarse colour pass on level 1
+    (ncol launches per sweep) and the coarsest dense product (one launch per
+    call).  A mixed hierarchy is driven through the complex64 hooks, which
+    launch exactly the colour passes of one sweep and nothing else.  Returns
+    (dominant, [others])."""
+    mixed = prec != "fp64"
+    dt = torch.complex64 if mixed else torch.complex128
+    sweep = bamg.OP_SWEEP_F32 if mixed else bamg.OP_SWEEP
+    tname = "float" if mixed else "double"
+    sname = {"fp64": "cx<double>", "mixed_fp32": "cx<float>", "mixed_fp16": "hcx", "mixed_bf16": "bcx"}[prec]
+    out = []
+    # fine pass, level 0
+    inf = bamg.bamg_level_info(h, 0)
+    nsite = inf["n"] // 2 // 16  # even sites per colour
+    xb = torch.zeros(inf["n"], dtype=dt, device="cuda:0")
+    bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
+    t = time_launches(lambda: bamg.bamg_level_op(h, 0, sweep, bb, xb, 1), 50, 16, torch)
+    out.append(_roof(f"k_kaczmarz_fine<{tname}> (level 0, {nsite} sites per launch)", "fine", prec,
+                     nsite * fine_site_bytes(VEC_BYTES[prec]), t))
+    L = bamg.bamg_n_levels(h)
+    if L > 2:  # coarse pass, level 1
+        inf = bamg.bamg_level_info(h, 1)
+        ns, ncol = inf["ex"] * inf["ey"], inf["colours"]
+        xb = torch.zeros(inf["n"], dtype=dt, device="cuda:0")
+        bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
+        t = time_launches(lambda: bamg.bamg_level_op(h, 1, sweep, bb, xb, 1), 50, ncol, torch)
+        out.append(_roof(f"k_kaczmarz_coarse<{tname},{sname}> (level 1, {ns // ncol} sites per launch)", "coarse",
+                         prec, ns // ncol * coarse_site_bytes(OP_BYTES[prec], VEC_BYTES[prec]), t))
+    if L > 1:  # coarsest product
+        inf = bamg.bamg_level_info(h, L - 1)
+        n = inf["n"]
+        xb = torch.zeros(n, dtype=torch.complex128, device="cuda:0")
+        bb = torch.ones(n, dtype=torch.complex128, device="cuda:0")
+        t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, bamg.OP_COARSEST, bb, xb, 1), 20, 1, torch)
+        out.append(_roof(f"k_dense_mv (coarsest inverse, n = {n})", "dense", prec, 16.0 * n * n + 32.0 * n, t))
+    return out[0], out[1:]
+
+
 def cpu_baseline(w, U_np, tol):
-    """The oracle (single-threaded C++ FP64) solving the same system: its setup
-    runs untimed, the sample is one full solve."""
-    import numpy as np
+    """The oracle (single-threaded C++ FP64) solving the same system, timed on
+    one full solve with its setup untimed.  It runs with 4 levels (coarsest
+    dimension 2048): with the GPU path's 3 levels its setup would spend ~3
+    minutes in the dense LU of the 8192-dim coarsest operator, and per solve
+    the 4-level oracle is the faster of the two (1.8 s against 2.7 s), so the
+    baseline errs in the CPU's favour."""
     import inputs
     import oracle
     N = w["N"]
     b = inputs.gaussian(2 * N * N, w["rhs_seed"])
-    o = oracle.Hierarchy(U_np, w["m"], n_levels=w["n_levels"], seed=w["tv_seed"])
+    o = oracle.Hierarchy(U_np, w["m"], n_levels=4, seed=w["tv_seed"])
     t0 = time.perf_counter()
     st, xo, info = o.solve(b, tol=tol)
     t = time.perf_counter() - t0
     return {"value": 1.0 / t, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full solve of the same workload ({info['iters']} FGMRES iterations, "
-                      f"{t:.2f} s); oracle setup untimed", "iters": info["iters"]}
+            "sample": f"one full solve of the same 256^2 system, oracle FP64 with 4 levels and V(4,4) "
+                      f"({info['iters']} FGMRES iterations, {t:.2f} s); oracle setup untimed", "iters": info["iters"]}
 
 
 if __name__ == "__main__":

@@ -74,7 +74,7 @@ typedef enum {
 typedef struct {
   int32_t N;            /* lattice extent, N % 8 == 0, N >= 16 */
   int32_t n_levels;     /* 0: automatic (coarsen until the level dimension <= max_coarse) */
-  int32_t max_coarse;   /* dimension bound of the directly solved coarsest level (default 2048) */
+  int32_t max_coarse;   /* dimension bound of the directly solved coarsest level (default 8192, at most 8192) */
   int32_t n_tv;         /* test vectors k (Sec. 4: k_r = 8); must be 8 */
   int32_t setup_sweeps; /* Kaczmarz sweeps on A_l v = 0 per level and setup pass (default 20) */
   int32_t setup_adapt;  /* adaptive passes after the first setup pass (default 1) */

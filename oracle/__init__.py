@@ -176,7 +176,7 @@ def coarse_ncolours(ex, ey):
 class Hierarchy:
     """Oracle bootstrap-AMG hierarchy (setup, cycle, FGMRES)."""
 
-    def __init__(self, U, m, *, n_levels=0, max_coarse=2048, n_tv=8, setup_sweeps=20,
+    def __init__(self, U, m, *, n_levels=0, max_coarse=8192, n_tv=8, setup_sweeps=20,
                  setup_adapt=1, pre=4, post=4, cycle=0, seed=0, init_tv=None):
         U = _c(U)
         self.N = U.shape[-1]

@@ -90,7 +90,7 @@ int bamg_default_params(bamg_params* p) {
   std::memset(p, 0, sizeof(*p));
   p->N = 0;
   p->n_levels = 0;
-  p->max_coarse = 2048;
+  p->max_coarse = 8192;
   p->n_tv = 8;
   p->setup_sweeps = 20;
   p->setup_adapt = 1;
@@ -206,7 +206,7 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
     h->kdim = p->restart;
     h->ensure_krylov(1, false);
     if (mg) {
-      h->gjcol = dalloc<zd>(h->lv.back().n);
+      h->gjcol = dalloc<zd>(gj_workspace((int)h->lv.back().n));
       h->gjperm = dalloc<int>(h->lv.back().n);
       h->tvsave = dalloc<zd>(n0 * k);
       // initial test vectors (Sec. 4: random, normal, mean 0, variance 1)

@@ -147,9 +147,13 @@ void launch_densify(const Coarse& c, zd* A, hipStream_t s);
 
 // ---- dense.hip --------------------------------------------------------------
 // In-place Gauss-Jordan inversion with partial pivoting of the n x n matrix A;
-// work: n complex (column buffer) + 2 ints; sets *flag = 1 on a zero pivot.
-void launch_gj_step(zd* A, int n, int k, zd* col, int* perm, int* flag, hipStream_t s);
-void launch_gj_unpermute(zd* A, zd* tmp, int n, const int* perm, hipStream_t s);
+// in-place inverse of the n x n row-major A by blocked Gauss-Jordan elimination
+// with partial pivoting (row interchanges recorded in perm[n]); T holds
+// gj_workspace(n) complex; sets *flag = 1 on a zero pivot.  The inverse's
+// columns are put back in order by launch_gj_unpermute.
+size_t gj_workspace(int n);
+void launch_gj_invert(zd* A, int n, zd* T, int* perm, int* flag, hipStream_t s);
+void launch_gj_unpermute(zd* A, int n, const int* perm, hipStream_t s);
 // y = A x for nrhs vectors (A n x n row-major): one wave per row for few
 // right-hand sides, an LDS-tiled product (A read once per 32 RHS) for many
 // (or whenever `many` is set; work holds dense_mm_workspace(n, nrhs) complex)

@@ -1,25 +1,44 @@
 // Coarsest level: the paper solves the coarsest system directly (Sec. 4).  The
-// library inverts the dense coarsest operator once at setup (Gauss-Jordan
-// elimination with partial pivoting, pivot = largest modulus, lowest row on
-// ties) and applies the inverse as a dense matrix-vector product in every
-// cycle, which is fully parallel where forward/back substitution would be a
-// chain of n dependent steps.  In exact arithmetic this is the same map
-// x = A_L^{-1} b as an LU solve.
+// library inverts the dense coarsest operator once at setup (blocked
+// Gauss-Jordan elimination with partial pivoting, pivot = largest modulus,
+// lowest row on ties) and applies the inverse as a dense matrix-vector (or
+// matrix-matrix) product in every cycle, which is fully parallel where
+// forward/back substitution would be a chain of n dependent steps.  In exact
+// arithmetic this is the same map x = A_L^{-1} b as an LU solve.
 #include "bamg_internal.h"
 
 namespace bamg {
 
-// pivot search, row swap, pivot-row scaling and saving of column k
-__global__ __launch_bounds__(1024) void k_gj_pivot(zd* __restrict__ A, int n, int k, zd* __restrict__ col,
-                                                   int* __restrict__ perm, int* __restrict__ flag) {
+// Blocked Gauss-Jordan elimination.  The b pivot steps k0 .. k0+b-1 of the
+// unblocked elimination act on the panel columns K = [k0, k0+b) on their own
+// (a row operation with pivot row k changes column j by a multiple of the
+// pivot row's entry in column j), so the panel is eliminated first, one pivot
+// step per pair of launches, with the pivot search and row interchanges, into
+//     A[K][K] <- inv(A11),   A[I][K] <- -A[I][K] inv(A11)   (I = rows not in K).
+// The same b steps act on every other column j as
+//     A[K][j] <- inv(A11) A[K][j],   A[I][j] <- A[I][j] - A[I][K] inv(A11) A[K][j],
+// i.e. with T = A[K][j] (after the interchanges) and the eliminated panel C:
+//     A[i][j] <- [i not in K] A[i][j] + sum_k C[i][k] T[k][j],
+// one rank-b update of the whole matrix.  In exact arithmetic this is the
+// unblocked elimination; the pivots are the same (pivot = largest modulus
+// among rows >= k, lowest row on ties).
+constexpr int GJ_B = 32;  // panel width
+
+// one pivot step k of the panel: pivot search in column k (rows >= k), row
+// interchange and pivot-row scaling inside the panel columns, and the saved
+// multipliers col[i] = A[i][k] (col[k] = 0)
+__global__ __launch_bounds__(1024) void k_gjp_pivot(zd* __restrict__ A, int n, int k0, int bw, int k,
+                                                    zd* __restrict__ col, int* __restrict__ perm,
+                                                    int* __restrict__ flag) {
   __shared__ double bv[1024];
   __shared__ int bi[1024];
+  __shared__ zd prow[GJ_B];
   const int tid = threadIdx.x;
+  const int kk = k - k0;
   double best = -1.0;
   int besti = n;
   for (int i = k + tid; i < n; i += blockDim.x) {
-    const zd a = A[(size_t)i * n + k];
-    const double v = sqrt(norm2(a));
+    const double v = sqrt(norm2(A[(size_t)i * n + k]));
     if (v > best || (v == best && i < besti)) { best = v; besti = i; }
   }
   bv[tid] = best;
@@ -38,38 +57,106 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(zd* __restrict__ A, int n, in
     perm[k] = p;
     if (!(bv[0] > 0.0)) flag[0] = 1;
   }
-  if (p != k)
-    for (int j = tid; j < n; j += blockDim.x) {
-      const zd t = A[(size_t)k * n + j];
-      A[(size_t)k * n + j] = A[(size_t)p * n + j];
-      A[(size_t)p * n + j] = t;
-    }
+  if (tid < bw) {  // interchange rows k and p inside the panel
+    const int j = k0 + tid;
+    const zd ak = A[(size_t)k * n + j], ap = A[(size_t)p * n + j];
+    if (p != k) A[(size_t)p * n + j] = ak;
+    prow[tid] = (p != k) ? ap : ak;
+  }
   __syncthreads();
-  const zd piv = A[(size_t)k * n + k];
+  const zd piv = prow[kk];
   const double pn = norm2(piv);
   const zd inv = pn > 0 ? zd{piv.x / pn, -piv.y / pn} : zd{0, 0};
-  __syncthreads();
-  for (int j = tid; j < n; j += blockDim.x) {
-    const zd a = (j == k) ? zd{1.0, 0.0} : A[(size_t)k * n + j];
-    A[(size_t)k * n + j] = a * inv;
+  if (tid < bw) {
+    const zd a = (tid == kk) ? zd{1.0, 0.0} : prow[tid];
+    A[(size_t)k * n + k0 + tid] = a * inv;
   }
   for (int i = tid; i < n; i += blockDim.x) col[i] = (i == k) ? zd{0, 0} : A[(size_t)i * n + k];
 }
 
-// eliminate column k from every row but k
-__global__ void k_gj_elim(zd* __restrict__ A, int n, int k, const zd* __restrict__ col) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= n || i == k) return;
-  const zd f = col[i];
-  const zd akj = A[(size_t)k * n + j];
-  const zd aij = (j == k) ? zd{0, 0} : A[(size_t)i * n + j];
-  A[(size_t)i * n + j] = aij - f * akj;
+// eliminate column k from every other row, panel columns only
+__global__ void k_gjp_elim(zd* __restrict__ A, int n, int k0, int bw, int k, const zd* __restrict__ col) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / GJ_B, j = t % GJ_B;
+  if (i >= n || j >= bw || i == k) return;
+  const int kk = k - k0;
+  zd* aij = A + (size_t)i * n + k0 + j;
+  const zd a = (j == kk) ? zd{0, 0} : *aij;
+  *aij = a - col[i] * A[(size_t)k * n + k0 + j];
 }
 
-void launch_gj_step(zd* A, int n, int k, zd* col, int* perm, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, A, n, k, col, perm, flag);
-  hipLaunchKernelGGL(k_gj_elim, dim3((n + 255) / 256, n), dim3(256), 0, s, A, n, k, col);
+// the panel's row interchanges, in order, on every column outside the panel;
+// then T[kk][j] = A[k0 + kk][j]
+__global__ void k_gj_swap_copy(zd* __restrict__ A, int n, int k0, int bw, const int* __restrict__ perm,
+                               zd* __restrict__ T) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + bw)) return;
+  for (int kk = 0; kk < bw; ++kk) {
+    const int k = k0 + kk, p = perm[k];
+    if (p != k) {
+      const zd t = A[(size_t)k * n + j];
+      A[(size_t)k * n + j] = A[(size_t)p * n + j];
+      A[(size_t)p * n + j] = t;
+    }
+  }
+  for (int kk = 0; kk < bw; ++kk) T[(size_t)kk * n + j] = A[(size_t)(k0 + kk) * n + j];
+}
+
+// A[i][j] = [i not in K] A[i][j] + sum_kk A[i][k0+kk] T[kk][j] for j outside the panel:
+// 64 x 64 output tiles, the panel rows and the T columns of the tile in LDS
+constexpr int GU_T = 64;
+__global__ __launch_bounds__(256) void k_gj_update(zd* __restrict__ A, int n, int k0, int bw, const zd* __restrict__ T) {
+  __shared__ zd Cs[GU_T][GJ_B + 1];
+  __shared__ zd Ts[GJ_B][GU_T + 1];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.y * GU_T, j0 = blockIdx.x * GU_T;
+  // tiles that lie entirely inside the panel columns have nothing to do
+  if (j0 >= k0 && j0 + GU_T <= k0 + bw) return;
+  for (int e = tid; e < GU_T * GJ_B; e += 256) {
+    const int r = e / GJ_B, c = e % GJ_B;
+    Cs[r][c] = (i0 + r < n && c < bw) ? A[(size_t)(i0 + r) * n + k0 + c] : zd{0, 0};
+    const int c2 = e % GU_T, r2 = e / GU_T;
+    Ts[r2][c2] = (j0 + c2 < n && r2 < bw) ? T[(size_t)r2 * n + j0 + c2] : zd{0, 0};
+  }
+  __syncthreads();
+  const int tr = tid >> 4, tc = tid & 15;  // 4 x 4 outputs: rows tr + 16 a, columns tc + 16 b
+  zd acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) acc[a][b] = zd{0, 0};
+  for (int kk = 0; kk < bw; ++kk) {
+    zd cv[4], tv[4];
+    for (int a = 0; a < 4; ++a) cv[a] = Cs[tr + 16 * a][kk];
+    for (int b = 0; b < 4; ++b) tv[b] = Ts[kk][tc + 16 * b];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + cv[a] * tv[b];
+  }
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + tr + 16 * a;
+    if (i >= n) continue;
+    const bool in_panel_row = (i >= k0 && i < k0 + bw);
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + tc + 16 * b;
+      if (j >= n || (j >= k0 && j < k0 + bw)) continue;
+      zd* aij = A + (size_t)i * n + j;
+      *aij = (in_panel_row ? zd{0, 0} : *aij) + acc[a][b];
+    }
+  }
+}
+
+size_t gj_workspace(int n) { return (size_t)(GJ_B + 1) * n; }
+
+void launch_gj_invert(zd* A, int n, zd* T, int* perm, int* flag, hipStream_t s) {
+  zd* col = T + (size_t)GJ_B * n;
+  for (int k0 = 0; k0 < n; k0 += GJ_B) {
+    const int bw = (n - k0 < GJ_B) ? n - k0 : GJ_B;
+    for (int k = k0; k < k0 + bw; ++k) {
+      hipLaunchKernelGGL(k_gjp_pivot, dim3(1), dim3(1024), 0, s, A, n, k0, bw, k, col, perm, flag);
+      hipLaunchKernelGGL(k_gjp_elim, dim3((n * GJ_B + 255) / 256), dim3(256), 0, s, A, n, k0, bw, k, col);
+    }
+    hipLaunchKernelGGL(k_gj_swap_copy, dim3((n + 255) / 256), dim3(256), 0, s, A, n, k0, bw, perm, T);
+    hipLaunchKernelGGL(k_gj_update, dim3((n + GU_T - 1) / GU_T, (n + GU_T - 1) / GU_T), dim3(256), 0, s, A, n, k0,
+                       bw, T);
+  }
 }
 
 // undo the row interchanges on the columns of the inverse (last swap first)
@@ -87,8 +174,7 @@ __global__ void k_gj_unpermute(zd* __restrict__ A, int n, const int* __restrict_
   }
 }
 
-void launch_gj_unpermute(zd* A, zd* tmp, int n, const int* perm, hipStream_t s) {
-  (void)tmp;
+void launch_gj_unpermute(zd* A, int n, const int* perm, hipStream_t s) {
   hipLaunchKernelGGL(k_gj_unpermute, dim3((n + 63) / 64), dim3(64), 0, s, A, n, perm);
 }
 

@@ -475,8 +475,8 @@ struct bamg_hierarchy {
     const int n = (int)C.n;
     launch_densify(C.coarse(), C.Ainv, s);
     HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), s));
-    for (int k = 0; k < n; ++k) launch_gj_step(C.Ainv, n, k, gjcol, gjperm, dflag, s);
-    launch_gj_unpermute(C.Ainv, nullptr, n, gjperm, s);
+    launch_gj_invert(C.Ainv, n, gjcol, gjperm, dflag, s);
+    launch_gj_unpermute(C.Ainv, n, gjperm, s);
     check_launch();
     HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

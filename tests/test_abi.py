@@ -39,7 +39,7 @@ def test_host_only_entry_points():
         pytest.skip("libbamg.so not built")
     import paper_1308_5992_amd as b
     p = b.bamg_default_params(N=256)
-    assert (p.max_coarse, p.n_tv, p.pre, p.post, p.restart) == (2048, 8, 4, 4, 32)
+    assert (p.max_coarse, p.n_tv, p.pre, p.post, p.restart) == (8192, 8, 4, 4, 32)
     fb = b.bamg_footprint_bytes(p)
     assert 50 * 2 ** 20 < fb < 2 * 2 ** 30
     assert b.bamg_footprint_bytes(b.bamg_default_params(N=36)) == 0
