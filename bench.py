@@ -82,6 +82,7 @@ def copy_calibration(torch):
     its FETCH_SIZE / WRITE_SIZE counters give the scale of those counters."""
     src = torch.ones(COPY_MIB * 2 ** 20 // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
+    torch.mul(src[:1024], 1.0, out=dst[:1024])  # load the kernel before the timed call
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -434,12 +435,18 @@ OP_BYTES = {"fp64": 16, "mixed_fp32": 8, "mixed_fp16": 4, "mixed_bf16": 4}
 # divided by what the counter reads per KiB moved by a plain 256 MiB copy
 # kernel in the same run.  Valid only for the kernel source they were taken on
 # (sha256 of the kernel's file); any change to it makes the traffic null.
-COPY_SCALE = {"fetch_per_kib": 131090.6 / 262144.0, "write_per_kib": 262144.0 / 262144.0}
+COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 262144.0}
+PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
+    ("fine", "mixed_fp16"): {"src": "fine.hip",
+                             "sha256": "8c39c9a77e138498145ad1ad2a7e41431415a9eb744eb5b82f4a795a289d4e75",
+                             "fetch_kib": 761.0, "write_kib": 448.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "676578ea4fbb84cbfe95f0270878300590c3ed8b8a3c4a9fb0a712aea4efed1e",
-                               "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE,
-                               "profile": "profiles/kaczmarz_coarse_level1_c3_256_mixed_fp16_pmc.md"},
+                               "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE},
+    ("dense", "mixed_fp16"): {"src": "dense.hip",
+                              "sha256": "3bda07c52fd0de7174965fd6d8055bbd8a99cf6b56514334c75565d26c2cfaca",
+                              "fetch_kib": 524812.5, "write_kib": 128.0, **COPY_SCALE},
 }
 
 
