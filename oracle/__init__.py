@@ -60,6 +60,13 @@ def lib():
             "oracle_level_op": (I, [P, I, I, P, P, I]),
             "oracle_solve_reduced": (I, [P, P, P, D, I, I, P]),
             "oracle_solve": (I, [P, P, P, D, I, I, P]),
+            "oracle_setup_boot": (P, [I, P, D, I, I, I, I, I, U64, P, I, I, I, I, I]),
+            "oracle_jacobi_eig": (None, [I, P, P, P]),
+            "oracle_ritz": (None, [P, I, P, P, I]),
+            "oracle_sweep_shifted": (None, [P, I, P, P, I]),
+            "oracle_coarsest_eigs": (None, [P, I, P, P]),
+            "oracle_fit_ls": (None, [P, I, P, I]),
+            "oracle_export_boot": (I, [P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -173,18 +180,38 @@ def coarse_ncolours(ex, ey):
 
 
 # ---------------------------------------------------------------- hierarchy
+def jacobi_eig(H):
+    """Eigenvalues (unsorted) and eigenvectors (columns) of a Hermitian matrix by cyclic Jacobi."""
+    H = _c(H)
+    n = H.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n), dtype=np.complex128)
+    lib().oracle_jacobi_eig(n, _p(H), _p(w), _p(V))
+    return w, V
+
+
 class Hierarchy:
-    """Oracle bootstrap-AMG hierarchy (setup, cycle, FGMRES)."""
+    """Oracle bootstrap-AMG hierarchy (setup, cycle, FGMRES).
+
+    boot = 0: relax-fit setup passes (setup_sweeps, setup_adapt); boot = 1: the
+    bootstrap W setup cycle schedule with the multigrid eigensolver (k_e
+    eigenvector approximations, W(nu1,nu1), adaptive step, W(nu2,nu2));
+    boot = 2: the super-V schedule (mu 2^l sweeps on level l, mu = nu1 then nu2)."""
 
     def __init__(self, U, m, *, n_levels=0, max_coarse=8192, n_tv=8, setup_sweeps=20,
-                 setup_adapt=1, pre=4, post=4, cycle=0, seed=0, init_tv=None):
+                 setup_adapt=1, pre=4, post=4, cycle=0, seed=0, init_tv=None,
+                 boot=0, k_e=8, nu1=10, nu2=5, adapt_cycles=2):
         U = _c(U)
         self.N = U.shape[-1]
         self.U, self.m = U, float(m)
         self._tv = None if init_tv is None else _c(init_tv)
-        h = lib().oracle_setup(self.N, _p(U), self.m, n_levels, max_coarse, n_tv, setup_sweeps,
-                               setup_adapt, pre, post, cycle, seed,
-                               None if self._tv is None else _p(self._tv))
+        tvp = None if self._tv is None else _p(self._tv)
+        if boot:
+            h = lib().oracle_setup_boot(self.N, _p(U), self.m, n_levels, max_coarse, pre, post, cycle, seed,
+                                        tvp, boot, k_e, nu1, nu2, adapt_cycles)
+        else:
+            h = lib().oracle_setup(self.N, _p(U), self.m, n_levels, max_coarse, n_tv, setup_sweeps,
+                                   setup_adapt, pre, post, cycle, seed, tvp)
         if not h:
             raise ValueError("oracle_setup rejected the parameters")
         self.h = h
@@ -267,6 +294,38 @@ class Hierarchy:
 
     def cycle(self, b, l=0, nrhs=1):
         return self.level_op(l, 5, b, nrhs=nrhs)
+
+    # ---- bootstrap eigensolver pieces (Sec. 3.4, Theorem 1)
+    def ritz(self, l, X, nrhs=1):
+        X = _c(X)
+        lam = np.zeros(nrhs)
+        lib().oracle_ritz(self.h, l, _p(X), _p(lam), nrhs)
+        return lam
+
+    def sweep_shifted(self, l, X, lam, nrhs=1):
+        X = _c(X).copy()
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        lib().oracle_sweep_shifted(self.h, l, _p(X), _p(lam), nrhs)
+        return X
+
+    def coarsest_eigs(self, ke):
+        n = self.level_info(self.n_levels - 1)["n"]
+        vals = np.zeros(ke)
+        vecs = np.zeros((ke, n), dtype=np.complex128)
+        lib().oracle_coarsest_eigs(self.h, ke, _p(vals), _p(vecs))
+        return vals, vecs
+
+    def fit_ls(self, l, V):
+        V = _c(V)
+        lib().oracle_fit_ls(self.h, l, _p(V), V.shape[0])
+
+    def boot_vectors(self):
+        """(Ritz values, level-1 eigenvector approximations) after a bootstrap setup."""
+        ke = lib().oracle_export_boot(self.h, None, None)
+        lam = np.zeros(ke)
+        ve = np.zeros((ke, self.N * self.N), dtype=np.complex128)
+        lib().oracle_export_boot(self.h, _p(lam), _p(ve))
+        return lam, ve
 
     def solve_reduced(self, bh, tol=1e-10, restart=32, max_iter=1000):
         bh = _c(bh)

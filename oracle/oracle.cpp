@@ -434,6 +434,9 @@ struct Hier {
   int pre = 4, post = 4, cycle = 0;  // cycle: 0 V, 1 W
   int n_tv = 8, sweeps = 20, adapt = 1;
   std::vector<cplx> tv;  // level-1 test vectors after setup, [k][n1]
+  // bootstrap eigensolver: eigenvector approximations V^e on level 1 and their Ritz values
+  std::vector<cplx> tve;
+  std::vector<double> lam;
 };
 
 double vnorm(const cplx* v, int n) {
@@ -500,6 +503,325 @@ void setup_pass(Hier& h, std::vector<cplx> V) {
     for (int j = 0; j < k; ++j) csr_mv(h.lv[l].PH, &V[(size_t)j * n], &Vc[(size_t)j * nc]);
     V.swap(Vc);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Bootstrap multigrid eigensolver (Sec. 3.4, Theorem 1 of Sec. 3.5).  With
+// R = (Gamma_5 P)^H and P orthonormal per aggregate, Q_l = T_l = P_l^H P_l = I,
+// and the singular-triplet systems (eq. SVDRnP1-4) reduce to the Hermitian
+// eigenproblem Z_l v = lambda v with Z_l = Gamma_5 D_l (Theorem 1 (i), (ii));
+// singular values are |lambda| (Theorem 1 (iii)).
+// ---------------------------------------------------------------------------
+
+// Gamma_5 on a level: +1 for spin 0, -1 for spin 1 (fine dof 2*site + s,
+// coarse dof 16*site + 8*s + k)
+double gamma5(const Level& L, int dof) {
+  int s = (L.dps == 2) ? (dof & 1) : ((dof % 16) / 8);
+  return s == 0 ? 1.0 : -1.0;
+}
+
+// eigen-decomposition of the n x n Hermitian H (row-major, destroyed) by cyclic
+// Jacobi rotations: w = eigenvalues (unsorted), V = eigenvectors as columns
+// (row-major n x n)
+void jacobi_eig(int n, std::vector<cplx>& H, std::vector<double>& w, std::vector<cplx>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto at = [&](int i, int j) -> cplx& { return H[(size_t)i * n + j]; };
+  double fro = 0.0;
+  for (auto& z : H) fro += std::norm(z);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        if (i != j) off += std::norm(at(i, j));
+    if (off <= 1e-30 * fro || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const cplx hpq = at(p, q);
+        const double r = std::abs(hpq);
+        if (r == 0.0) continue;
+        // phase to a real off-diagonal entry, then the real 2x2 rotation
+        const cplx ph = hpq / r;  // e^{i phi}
+        const double a = at(p, p).real(), b = at(q, q).real();
+        const double tau = (b - a) / (2.0 * r);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        // U = [[c, sn], [-sn e^{-i phi}, c e^{-i phi}]] on columns (p, q)
+        const cplx upp = c, upq = sn, uqp = -sn * std::conj(ph), uqq = c * std::conj(ph);
+        for (int k = 0; k < n; ++k) {  // H <- H U
+          const cplx hkp = at(k, p), hkq = at(k, q);
+          at(k, p) = hkp * upp + hkq * uqp;
+          at(k, q) = hkp * upq + hkq * uqq;
+        }
+        for (int k = 0; k < n; ++k) {  // H <- U^H H
+          const cplx hpk = at(p, k), hqk = at(q, k);
+          at(p, k) = std::conj(upp) * hpk + std::conj(uqp) * hqk;
+          at(q, k) = std::conj(upq) * hpk + std::conj(uqq) * hqk;
+        }
+        at(p, q) = 0.0; at(q, p) = 0.0;
+        at(p, p) = at(p, p).real(); at(q, q) = at(q, q).real();
+        for (int k = 0; k < n; ++k) {  // V <- V U
+          const cplx vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = vkp * upp + vkq * uqp;
+          V[(size_t)k * n + q] = vkp * upq + vkq * uqq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = at(i, i).real();
+}
+
+// Ritz value of eq. eqevZ with T = I: <Z v, v> / <v, v>
+double ritz_value(const Level& L, const cplx* v) {
+  int n = L.A.nr;
+  std::vector<cplx> Av(n);
+  csr_mv(L.A, v, Av.data());
+  cplx num = 0.0;
+  double den = 0.0;
+  for (int i = 0; i < n; ++i) {
+    num += std::conj(v[i]) * gamma5(L, i) * Av[i];
+    den += std::norm(v[i]);
+  }
+  return den > 0 ? num.real() / den : 0.0;
+}
+
+// One Kaczmarz sweep (rows in the level's order) on (A - lam Gamma_5) x = 0,
+// the row form of Z x = lam x (Theorem 1 (ii)).
+void kaczmarz_sweep_shifted(const Level& L, cplx* x, double lam) {
+  const CSR& A = L.A;
+  for (int r : L.order) {
+    const cplx sh = -lam * gamma5(L, r);  // added to the diagonal entry of row r
+    bool has_diag = false;
+    double nu = 0.0;
+    cplx res = 0.0;
+    for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
+      cplx a = A.val[p];
+      if (A.col[p] == r) { a += sh; has_diag = true; }
+      nu += std::norm(a);
+      res -= a * x[A.col[p]];
+    }
+    if (!has_diag) { nu += std::norm(sh); res -= sh * x[r]; }
+    if (nu == 0.0) continue;
+    const cplx alpha = res / nu;
+    for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
+      cplx a = A.val[p];
+      if (A.col[p] == r) a += sh;
+      x[A.col[p]] += alpha * std::conj(a);
+    }
+    if (!has_diag) x[r] += alpha * std::conj(sh);
+  }
+}
+
+// the ke eigenpairs of Z_L = Gamma_5 A_L with the smallest |lambda| (ties by
+// index), eigenvectors of unit norm: vals[ke], vecs[ke][n]
+void coarsest_eigs(const Level& L, int ke, std::vector<double>& vals, std::vector<cplx>& vecs) {
+  int n = L.A.nr;
+  std::vector<cplx> Z((size_t)n * n, 0.0);
+  for (int r = 0; r < n; ++r)
+    for (int p = L.A.ptr[r]; p < L.A.ptr[r + 1]; ++p) Z[(size_t)r * n + L.A.col[p]] += gamma5(L, r) * L.A.val[p];
+  std::vector<double> w;
+  std::vector<cplx> V;
+  jacobi_eig(n, Z, w, V);
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return std::abs(w[a]) < std::abs(w[b]); });
+  vals.resize(ke);
+  vecs.assign((size_t)ke * n, 0.0);
+  for (int k = 0; k < ke && k < n; ++k) {
+    vals[k] = w[idx[k]];
+    for (int i = 0; i < n; ++i) vecs[(size_t)k * n + i] = V[(size_t)i * n + idx[k]];
+  }
+}
+
+// Least squares fit (eq. LSfuncrowi) with k > 8 test vectors and 8 columns per
+// aggregate and spin: the columns of P_{a,s} span the best rank-8 fit of the
+// block of test vectors (unit weights), i.e. the 8 dominant eigenvectors of
+// B B^H; the basis is fixed as the Gram-Schmidt basis (applied twice, R_jj > 0)
+// of the projections of the first 8 test vectors onto that space.  For k <= 8
+// this is fit_P.
+void fit_P_ls(Level& F, bool fine, const std::vector<cplx>& V, int k) {
+  if (k <= 8) { fit_P(F, fine, V, k); return; }
+  AggMap M = aggregate_map(F, fine);
+  int n = F.A.nr, na = F.cx * F.cy, R = F.rows_per;
+  F.Pblk.assign((size_t)na * 2 * R * 8, 0.0);
+  std::vector<cplx> blk((size_t)na * 2 * R * k, 0.0);  // [a][s][row][j]
+  for (int j = 0; j < k; ++j)
+    for (int dof = 0; dof < n; ++dof)
+      blk[(((size_t)M.agg[dof] * 2 + M.spin[dof]) * R + M.row[dof]) * k + j] = V[(size_t)j * n + dof];
+  for (int a = 0; a < na; ++a)
+    for (int s = 0; s < 2; ++s) {
+      const cplx* B = &blk[(((size_t)a * 2 + s) * R) * k];
+      std::vector<cplx> G((size_t)R * R, 0.0);
+      for (int i = 0; i < R; ++i)
+        for (int i2 = 0; i2 < R; ++i2)
+          for (int j = 0; j < k; ++j) G[(size_t)i * R + i2] += B[i * k + j] * std::conj(B[i2 * k + j]);
+      std::vector<double> w;
+      std::vector<cplx> E;
+      jacobi_eig(R, G, w, E);
+      std::vector<int> idx(R);
+      for (int i = 0; i < R; ++i) idx[i] = i;
+      std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return w[x] > w[y]; });
+      cplx* Q = &F.Pblk[(((size_t)a * 2 + s) * R) * 8];
+      for (int j = 0; j < 8; ++j) {
+        // projection of test vector j onto the span of the 8 dominant eigenvectors
+        std::vector<cplx> wv(R, 0.0);
+        for (int e = 0; e < 8; ++e) {
+          cplx c = 0.0;
+          for (int i = 0; i < R; ++i) c += std::conj(E[(size_t)i * R + idx[e]]) * B[i * k + j];
+          for (int i = 0; i < R; ++i) wv[i] += E[(size_t)i * R + idx[e]] * c;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+          std::vector<cplx> hq(j, 0.0);
+          for (int q = 0; q < j; ++q)
+            for (int i = 0; i < R; ++i) hq[q] += std::conj(Q[i * 8 + q]) * wv[i];
+          for (int q = 0; q < j; ++q)
+            for (int i = 0; i < R; ++i) wv[i] -= Q[i * 8 + q] * hq[q];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < R; ++i) nrm += std::norm(wv[i]);
+        nrm = std::sqrt(nrm);
+        if (nrm > 0.0)
+          for (int i = 0; i < R; ++i) Q[i * 8 + j] = wv[i] / nrm;
+      }
+    }
+  build_P_csr(F, fine);
+}
+
+// ---------------------------------------------------------------------------
+// Bootstrap setup cycles (Sec. 3.4, its setup-cycle figure, Sec. 4.1 / 4.2).
+// Per level: relaxation test vectors V^r (k_r) and eigenvector approximations
+// V^e (k_e) with their Ritz values.  Node kinds of the setup-cycle figure:
+//   arrive (first visit of the first cycle): relax V^r on Z v = 0, compute P;
+//   arrive (later): relax V^r on Z v = 0 and V^e on Z v = lambda T v, recompute P;
+//   coarsest: the k_e eigenpairs of Z_L with the smallest |lambda| replace V^e;
+//   after the last visit below: relax V^e on Z v = lambda T v.
+// Computing P on level l also rebuilds level l+1 (Galerkin) and restricts
+// both sets of test vectors to it; coming back up, V^e_l = P_l V^e_{l+1}.
+// ---------------------------------------------------------------------------
+struct BootSets {
+  std::vector<std::vector<cplx>> Vr, Ve;  // per level, [k][n_l]
+  std::vector<double> lam;                // Ritz values of V^e
+  int kr = 8, ke = 0;
+  bool have_e = false;
+};
+
+void unit_normalise(cplx* v, int n) {
+  double nv = vnorm(v, n);
+  if (nv > 0) for (int i = 0; i < n; ++i) v[i] /= nv;
+}
+
+void boot_relax_r(Hier& h, int l, BootSets& B, int nu) {
+  Level& L = h.lv[l]; int n = L.A.nr;
+  for (int j = 0; j < B.kr; ++j) {
+    cplx* v = &B.Vr[l][(size_t)j * n];
+    for (int s = 0; s < nu; ++s) kaczmarz_sweep(L, v, nullptr);
+    unit_normalise(v, n);
+  }
+}
+
+// Kaczmarz on (A - lambda Gamma_5) v = 0 with the Ritz value updated after every sweep (eq. eqevZ)
+void boot_relax_e(Hier& h, int l, BootSets& B, int nu) {
+  if (!B.have_e) return;
+  Level& L = h.lv[l]; int n = L.A.nr;
+  for (int j = 0; j < B.ke; ++j) {
+    cplx* v = &B.Ve[l][(size_t)j * n];
+    for (int s = 0; s < nu; ++s) {
+      kaczmarz_sweep_shifted(L, v, B.lam[j]);
+      B.lam[j] = ritz_value(L, v);
+    }
+    unit_normalise(v, n);
+  }
+}
+
+void boot_fit(Hier& h, int l, BootSets& B) {
+  Level& L = h.lv[l]; int n = L.A.nr;
+  int k = B.kr + (B.have_e ? B.ke : 0);
+  std::vector<cplx> V((size_t)k * n);
+  std::copy(B.Vr[l].begin(), B.Vr[l].end(), V.begin());
+  if (B.have_e) std::copy(B.Ve[l].begin(), B.Ve[l].end(), V.begin() + (size_t)B.kr * n);
+  fit_P_ls(L, l == 0, V, k);
+  coarsen_level(h, l);
+  int nc = h.lv[l + 1].A.nr;
+  B.Vr[l + 1].assign((size_t)B.kr * nc, 0.0);
+  for (int j = 0; j < B.kr; ++j) csr_mv(L.PH, &B.Vr[l][(size_t)j * n], &B.Vr[l + 1][(size_t)j * nc]);
+  if (B.have_e) {
+    B.Ve[l + 1].assign((size_t)B.ke * nc, 0.0);
+    for (int j = 0; j < B.ke; ++j) csr_mv(L.PH, &B.Ve[l][(size_t)j * n], &B.Ve[l + 1][(size_t)j * nc]);
+  }
+}
+
+void boot_interp_e(Hier& h, int l, BootSets& B) {
+  Level& L = h.lv[l]; int n = L.A.nr, nc = h.lv[l + 1].A.nr;
+  B.Ve[l].assign((size_t)B.ke * n, 0.0);
+  for (int j = 0; j < B.ke; ++j) csr_mv(L.P, &B.Ve[l + 1][(size_t)j * nc], &B.Ve[l][(size_t)j * n]);
+}
+
+void boot_coarsest(Hier& h, BootSets& B, int ke) {
+  int Lc = (int)h.lv.size() - 1;
+  coarsest_eigs(h.lv[Lc], ke, B.lam, B.Ve[Lc]);
+  B.ke = ke;
+  B.have_e = true;
+}
+
+void boot_arrive(Hier& h, int l, BootSets& B, int nu, bool first) {
+  boot_relax_r(h, l, B, nu);
+  if (!first) boot_relax_e(h, l, B, nu);
+  boot_fit(h, l, B);
+}
+
+// visit of level l >= 1 inside a setup cycle; nu[l] sweeps per node, gamma visits below
+void boot_visit(Hier& h, int l, BootSets& B, const std::vector<int>& nu, bool first, int gamma, int ke) {
+  int Lc = (int)h.lv.size() - 1;
+  boot_arrive(h, l, B, nu[l], first);
+  for (int g = 0; g < gamma; ++g) {
+    if (l + 1 == Lc) boot_coarsest(h, B, ke);
+    else boot_visit(h, l + 1, B, nu, first && g == 0, gamma, ke);
+    boot_interp_e(h, l, B);
+    if (g < gamma - 1) boot_arrive(h, l, B, nu[l], false);
+    else boot_relax_e(h, l, B, nu[l]);
+  }
+}
+
+// one setup cycle from the finest level (visited once per cycle)
+void boot_cycle(Hier& h, BootSets& B, const std::vector<int>& nu, bool first, int gamma, int ke) {
+  int Lc = (int)h.lv.size() - 1;
+  boot_arrive(h, 0, B, nu[0], first);
+  if (Lc == 1) boot_coarsest(h, B, ke);
+  else boot_visit(h, 1, B, nu, first, gamma, ke);
+  boot_interp_e(h, 0, B);
+  boot_relax_e(h, 0, B, nu[0]);
+}
+
+// the schedule of Sec. 4.1 (mode 1: W(nu1,nu1) setup cycle, adaptive step, W(nu2,nu2))
+// or Sec. 4.2 (mode 2: super-V, mu 2^l sweeps on level l, mu = nu1 then nu2)
+void boot_setup(Hier& h, const std::vector<cplx>& V0, int mode, int ke, int nu1, int nu2, int adapt_cycles) {
+  int L = (int)h.lv.size();
+  BootSets B;
+  B.kr = h.n_tv;
+  B.Vr.resize(L); B.Ve.resize(L);
+  B.Vr[0] = V0;
+  int gamma = (mode == 1) ? 2 : 1;
+  auto sweeps = [&](int mu) {
+    std::vector<int> nu(L);
+    for (int l = 0; l < L; ++l) nu[l] = (mode == 1) ? mu : mu * (1 << l);
+    return nu;
+  };
+  boot_cycle(h, B, sweeps(nu1), true, gamma, ke);
+  // adaptive step: cycles of the current solver on Dhat v = 0 for the
+  // eigenvector approximation with the smallest |Ritz value|
+  int n1 = h.lv[0].A.nr;
+  int kmin = 0;
+  for (int j = 1; j < B.ke; ++j)
+    if (std::abs(B.lam[j]) < std::abs(B.lam[kmin])) kmin = j;
+  std::vector<cplx> zero(n1, 0.0);
+  cplx* v = &B.Ve[0][(size_t)kmin * n1];
+  for (int c = 0; c < adapt_cycles; ++c) mg_cycle(h, 0, zero.data(), v);
+  unit_normalise(v, n1);
+  B.lam[kmin] = ritz_value(h.lv[0], v);
+  boot_cycle(h, B, sweeps(nu2), false, gamma, ke);
+  h.tv = B.Vr[0];
+  h.tve = B.Ve[0];
+  h.lam = B.lam;
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from its definition.
@@ -699,6 +1021,7 @@ void* oracle_setup(int N, const double* U, double m, int n_levels, int max_coars
   std::vector<cplx> V((size_t)n_tv * n1);
   if (init_tv) std::copy((const cplx*)init_tv, (const cplx*)init_tv + V.size(), V.begin());
   else for (int j = 0; j < n_tv; ++j) for (int d = 0; d < n1; ++d) V[(size_t)j * n1 + d] = tv_entry(seed, j, d);
+  if (adapt < 0) return h;  // shapes and operator only (the bootstrap setup builds the rest)
   setup_pass(*h, V);
   for (int a = 0; a < adapt; ++a) {
     // adaptive step: two cycles of the current hierarchy on Dhat v = 0 per test vector
@@ -716,6 +1039,73 @@ void* oracle_setup(int N, const double* U, double m, int n_levels, int max_coars
 }
 
 void oracle_free(void* hp) { delete (Hier*)hp; }
+
+// Hierarchy by the bootstrap setup cycles (mode 1: W, mode 2: super-V; see
+// boot_setup); the other arguments as oracle_setup.
+void* oracle_setup_boot(int N, const double* U, double m, int n_levels, int max_coarse, int pre, int post,
+                        int cycle, uint64_t seed, const double* init_tv, int mode, int ke, int nu1, int nu2,
+                        int adapt_cycles) {
+  if (mode != 1 && mode != 2) return nullptr;
+  // shapes, operator and random test vectors as in oracle_setup, without its setup passes
+  Hier* h = (Hier*)oracle_setup(N, U, m, n_levels, max_coarse, 8, 0, -1, pre, post, cycle, seed, init_tv);
+  if (!h || h->lv.size() < 2) return h;
+  int n1 = N * N;
+  std::vector<cplx> V((size_t)8 * n1);
+  if (init_tv) std::copy((const cplx*)init_tv, (const cplx*)init_tv + V.size(), V.begin());
+  else for (int j = 0; j < 8; ++j) for (int d = 0; d < n1; ++d) V[(size_t)j * n1 + d] = tv_entry(seed, j, d);
+  boot_setup(*h, V, mode, ke, nu1, nu2, adapt_cycles);
+  return h;
+}
+
+// eigen-decomposition of a Hermitian n x n matrix (row-major) by cyclic Jacobi
+void oracle_jacobi_eig(int n, const double* H, double* w, double* V) {
+  std::vector<cplx> A((const cplx*)H, (const cplx*)H + (size_t)n * n);
+  std::vector<double> ww;
+  std::vector<cplx> VV;
+  jacobi_eig(n, A, ww, VV);
+  std::copy(ww.begin(), ww.end(), w);
+  std::copy(VV.begin(), VV.end(), (cplx*)V);
+}
+
+// Ritz values (eq. eqevZ, T = I) of nrhs level-l vectors
+void oracle_ritz(void* hp, int l, const double* x, double* lam, int nrhs) {
+  Level& L = ((Hier*)hp)->lv[l];
+  for (int j = 0; j < nrhs; ++j) lam[j] = ritz_value(L, (const cplx*)x + (size_t)j * L.A.nr);
+}
+
+// one Kaczmarz sweep on (A_l - lam_j Gamma_5) x_j = 0 for nrhs vectors (in place)
+void oracle_sweep_shifted(void* hp, int l, double* x, const double* lam, int nrhs) {
+  Level& L = ((Hier*)hp)->lv[l];
+  for (int j = 0; j < nrhs; ++j) kaczmarz_sweep_shifted(L, (cplx*)x + (size_t)j * L.A.nr, lam[j]);
+}
+
+// the ke eigenpairs of Z_L with the smallest |lambda|: vals[ke], vecs[ke][n_L]
+void oracle_coarsest_eigs(void* hp, int ke, double* vals, double* vecs) {
+  Hier* h = (Hier*)hp;
+  std::vector<double> w;
+  std::vector<cplx> V;
+  coarsest_eigs(h->lv.back(), ke, w, V);
+  std::copy(w.begin(), w.end(), vals);
+  std::copy(V.begin(), V.end(), (cplx*)vecs);
+}
+
+// refit P_l from k level-l test vectors (least squares, rank-8) and rebuild level l+1
+void oracle_fit_ls(void* hp, int l, const double* V, int k) {
+  Hier* h = (Hier*)hp;
+  Level& L = h->lv[l];
+  std::vector<cplx> VV((const cplx*)V, (const cplx*)V + (size_t)k * L.A.nr);
+  fit_P_ls(L, l == 0, VV, k);
+  coarsen_level(*h, l);
+}
+
+// eigenvector approximations on level 1 and their Ritz values after a bootstrap setup
+int oracle_export_boot(void* hp, double* lam, double* ve) {
+  Hier* h = (Hier*)hp;
+  int ke = (int)h->lam.size();
+  if (lam) std::copy(h->lam.begin(), h->lam.end(), lam);
+  if (ve) std::copy(h->tve.begin(), h->tve.end(), (cplx*)ve);
+  return ke;
+}
 
 int oracle_n_levels(void* hp) { return (int)((Hier*)hp)->lv.size(); }
 
