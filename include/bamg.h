@@ -89,6 +89,13 @@ typedef struct {
   int32_t graphs;       /* 1: replay each FGMRES iteration (cycle, Dhat, Gram-Schmidt, norms) as a
                            captured hipGraph, one per (iteration index | batch size); 0 (default):
                            launch the kernels one by one.  Results are bitwise the same. */
+  int32_t setup_mode;   /* 0 (default): relax-fit passes (setup_sweeps, setup_adapt);
+                           1: bootstrap W setup cycles with the multigrid eigensolver (Sec. 3.4,
+                              Sec. 4.1): W(boot_nu1) cycle, adaptive step (two solve cycles on the
+                              eigenvector approximation of smallest |Ritz value|), W(boot_nu2) cycle;
+                           2: the same with super-V cycles, boot_nu 2^l sweeps on level l (Sec. 4.2) */
+  int32_t n_ev;         /* k_e eigenvector approximations of the bootstrap modes (1..8, default 8) */
+  int32_t boot_nu1, boot_nu2; /* sweeps of the two bootstrap setup cycles (default 10, 5) */
 } bamg_params;
 
 typedef struct {
@@ -156,6 +163,22 @@ enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLO
        BAMG_OP_APPLY_MIXED = 7, BAMG_OP_SWEEP_MIXED = 8, BAMG_OP_CYCLE_MIXED = 9,
        BAMG_OP_APPLY_F32 = 10, BAMG_OP_SWEEP_F32 = 11 };
 int bamg_level_op(bamg_hierarchy *h, int32_t level, int32_t op, const void *in, void *out, int32_t nrhs);
+
+/* Pieces of the bootstrap multigrid eigensolver (Sec. 3.4, Theorem 1 of Sec. 3.5;
+ * test hook), FP64, on k level-l vectors X (device, [k][n_l]) and host lam_host[k]:
+ *   op 0 BAMG_BOOT_RITZ:   lam_host[r] = <Z_l x_r, x_r> / <x_r, x_r>, Z_l = Gamma_5 D_l (eq. eqevZ)
+ *   op 1 BAMG_BOOT_SWEEP:  x_r <- one Kaczmarz sweep on (D_l - lam_r Gamma_5) x_r = 0 (l not coarsest)
+ *   op 2 BAMG_BOOT_EIGS:   X = the k (<= 8) eigenvectors of Z_L with the smallest |lambda|, lam_host
+ *                          their eigenvalues (l = L-1, the coarsest level)
+ *   op 3 BAMG_BOOT_FIT:    P_l = least squares fit to the k (<= 16) test vectors X (rank-8 fit per
+ *                          aggregate and spin); level l+1 is rebuilt (Galerkin, smoother data or inverse)
+ * Gamma_5 is +1 on spin 0 and -1 on spin 1. */
+enum { BAMG_BOOT_RITZ = 0, BAMG_BOOT_SWEEP = 1, BAMG_BOOT_EIGS = 2, BAMG_BOOT_FIT = 3 };
+int bamg_boot_op(bamg_hierarchy *h, int32_t level, int32_t op, void *X, double *lam_host, int32_t k);
+
+/* After a bootstrap setup (setup_mode 1 or 2): the k_e Ritz values (lam_host) and
+ * level-0 eigenvector approximations (ve_host, [k_e][N*N], may be NULL); returns k_e. */
+int bamg_export_boot(const bamg_hierarchy *h, double *lam_host, void *ve_host);
 
 /* Number of levels, or a negative status. */
 int bamg_n_levels(const bamg_hierarchy *h);

@@ -23,12 +23,13 @@ BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
 OP_APPLY, OP_SWEEP, OP_RESTRICT, OP_PROLONG, OP_COARSEST, OP_CYCLE, OP_RESIDUAL = range(7)
 OP_APPLY_MIXED, OP_SWEEP_MIXED, OP_CYCLE_MIXED = 7, 8, 9
 OP_APPLY_F32, OP_SWEEP_F32 = 10, 11
+BOOT_RITZ, BOOT_SWEEP, BOOT_EIGS, BOOT_FIT = range(4)
 
 EXPORTED = [
     "bamg_default_params", "bamg_setup", "bamg_solve", "bamg_solve_batch", "bamg_apply_dhat",
     "bamg_eo_reduce", "bamg_eo_reconstruct", "bamg_level_op", "bamg_n_levels", "bamg_level_info",
     "bamg_export_level", "bamg_import_level", "bamg_footprint_bytes", "bamg_gaussian_tv",
-    "bamg_free", "bamg_last_error",
+    "bamg_free", "bamg_last_error", "bamg_boot_op", "bamg_export_boot",
     "bamg_server_default_params", "bamg_server_create", "bamg_server_add_field", "bamg_server_field_bytes",
     "bamg_server_submit", "bamg_server_progress", "bamg_server_wait", "bamg_server_get_stats", "bamg_server_reset_stats",
     "bamg_server_free",
@@ -42,7 +43,8 @@ class bamg_params(ctypes.Structure):
         ("pre", ctypes.c_int32), ("post", ctypes.c_int32), ("cycle", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("init_tv_host", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-        ("graphs", ctypes.c_int32),
+        ("graphs", ctypes.c_int32), ("setup_mode", ctypes.c_int32), ("n_ev", ctypes.c_int32),
+        ("boot_nu1", ctypes.c_int32), ("boot_nu2", ctypes.c_int32),
     ]
 
 
@@ -97,6 +99,8 @@ def _load():
         "bamg_gaussian_tv": (I32, [I32, I32, U64, P, P]),
         "bamg_free": (None, [P]),
         "bamg_last_error": (ctypes.c_char_p, []),
+        "bamg_boot_op": (I32, [P, I32, I32, P, P, I32]),
+        "bamg_export_boot": (I32, [P, P, P]),
         "bamg_server_default_params": (I32, [ctypes.POINTER(bamg_server_params)]),
         "bamg_server_create": (I32, [ctypes.POINTER(bamg_server_params), ctypes.POINTER(P)]),
         "bamg_server_add_field": (I32, [P, P, D, PP, ctypes.POINTER(I32)]),
@@ -219,6 +223,23 @@ def bamg_level_op(h, level: int, op: int, inp, out, nrhs: int = 1):
     """Ops 10 and 11 take complex64 tensors, every other op complex128."""
     c64 = op in (OP_APPLY_F32, OP_SWEEP_F32)
     _check(lib.bamg_level_op(h, int(level), int(op), _ptr(inp, c64), _ptr(out, c64), int(nrhs)), "bamg_level_op")
+
+
+def bamg_boot_op(h, level: int, op: int, X, lam, k: int):
+    """Bootstrap eigensolver pieces (see bamg.h); lam: numpy float64 array of k
+    entries (input for BOOT_SWEEP, output for BOOT_RITZ and BOOT_EIGS)."""
+    if lam.dtype != np.float64 or not lam.flags.c_contiguous or lam.size < k:
+        raise TypeError("lam must be a contiguous float64 array of k entries")
+    _check(lib.bamg_boot_op(h, int(level), int(op), _ptr(X), lam.ctypes.data, int(k)), "bamg_boot_op")
+
+
+def bamg_export_boot(h, N: int):
+    """(Ritz values, level-0 eigenvector approximations [k_e][N*N]) of a bootstrap hierarchy."""
+    lam = np.zeros(16)
+    ke = _check(lib.bamg_export_boot(h, lam.ctypes.data, None), "bamg_export_boot")
+    ve = np.zeros((ke, N * N), dtype=np.complex128)
+    lib.bamg_export_boot(h, lam.ctypes.data, ve.ctypes.data)
+    return lam[:ke].copy(), ve
 
 
 def bamg_n_levels(h) -> int:

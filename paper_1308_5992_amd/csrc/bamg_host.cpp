@@ -73,6 +73,9 @@ bool valid_params(const bamg_params* p, std::string& why) {
   if (p->max_iter < 0) { why = "max_iter < 0"; return false; }
   if (p->max_coarse < 16) { why = "max_coarse < 16"; return false; }
   if (p->graphs != 0 && p->graphs != 1) { why = "graphs must be 0 or 1"; return false; }
+  if (p->setup_mode < 0 || p->setup_mode > 2) { why = "setup_mode must be 0, 1 or 2"; return false; }
+  if (p->setup_mode && (p->n_ev < 1 || p->n_ev > 8)) { why = "n_ev must be in [1, 8]"; return false; }
+  if (p->setup_mode && (p->boot_nu1 < 0 || p->boot_nu2 < 0)) { why = "negative bootstrap sweep count"; return false; }
   return true;
 }
 
@@ -103,6 +106,11 @@ int bamg_default_params(bamg_params* p) {
   p->seed = 0;
   p->init_tv_host = nullptr;
   p->stream = nullptr;
+  p->graphs = 0;
+  p->setup_mode = 0;
+  p->n_ev = 8;
+  p->boot_nu1 = 10;
+  p->boot_nu2 = 5;
   return BAMG_OK;
 }
 
@@ -186,7 +194,7 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
       Lv.ey = sh.ext[l].second;
       Lv.dps = (l == 0) ? 2 : 16;
       Lv.n = (size_t)Lv.ex * Lv.ey * Lv.dps;
-      if (mg) Lv.tv = dalloc<zd>(Lv.n * k);
+      if (mg) Lv.tv = dalloc<zd>(Lv.n * (k + (p->setup_mode ? p->n_ev : 0)));
       if (l >= 1) Lv.D = dalloc<zd>((size_t)Lv.ex * Lv.ey * NOFF * 256);
       if (!mg || l < L - 1) {
         h->build_colours(l);
@@ -199,7 +207,7 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
         Lv.Ainv = dalloc<zd>(Lv.n * Lv.n);
       }
     }
-    h->ensure_cap(mg ? k : 1);
+    h->ensure_cap(mg ? k + (p->setup_mode ? p->n_ev : 0) : 1);
     const size_t n0 = h->lv[0].n;
     h->dflag = dalloc<int>(1);
     HIPCHK(hipHostMalloc((void**)&h->hflag, sizeof(int)));
@@ -216,10 +224,11 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
         launch_philox_tv((int)n0, k, p->seed, h->lv[0].tv, h->s);
         check_launch();
       }
-      h->setup_pass();
+      if (p->setup_mode) h->boot_setup();
+      else h->setup_pass();
       // adaptive passes: two cycles of the current hierarchy on Dhat v = 0 for
       // every saved level-0 test vector, then relax-fit-coarsen again
-      for (int a = 0; a < p->setup_adapt; ++a) {
+      for (int a = 0; a < (p->setup_mode ? 0 : p->setup_adapt); ++a) {
         Level& L0 = h->lv[0];
         launch_copy(h->tvsave, L0.tv, n0 * k, h->s);
         launch_fill_zero(L0.b, n0 * k, h->s);
@@ -420,6 +429,81 @@ int bamg_import_level(bamg_hierarchy* h, int32_t l, const void* P_host, const vo
     return fail(BAMG_ESINGULAR, e.msg);
   }
   return BAMG_OK;
+}
+
+int bamg_boot_op(bamg_hierarchy* h, int32_t l, int32_t op, void* X, double* lam_host, int32_t k) {
+  if (!h || !X || !lam_host || k < 1 || l < 0 || l >= h->L()) return fail(BAMG_EINVAL, "bad arguments");
+  if (h->L() < 2) return fail(BAMG_EINVAL, "no hierarchy (one level)");
+  try {
+    h->ensure_boot(8);
+    zd* x = (zd*)X;
+    switch (op) {
+      case BAMG_BOOT_RITZ:
+      case BAMG_BOOT_SWEEP:
+        if (k > 16) return fail(BAMG_EINVAL, "k > 16");
+        h->ensure_cap(k);
+        if (op == BAMG_BOOT_SWEEP) {
+          if (h->coarsest(l)) return fail(BAMG_EINVAL, "no smoother on the coarsest level");
+          HIPCHK(hipMemcpyAsync(h->lam_dev, lam_host, k * sizeof(double), hipMemcpyHostToDevice, h->s));
+          h->sweep_shift(l, x, h->lam_dev, k);
+        } else {
+          h->ritz(l, x, k, h->lam_dev);
+          HIPCHK(hipMemcpyAsync(lam_host, h->lam_dev, k * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        }
+        break;
+      case BAMG_BOOT_EIGS: {
+        if (!h->coarsest(l)) return fail(BAMG_EINVAL, "eigenpairs are computed on the coarsest level");
+        if (k > 8) return fail(BAMG_EINVAL, "k > 8");
+        const int ke_save = h->ke;
+        const bool he_save = h->have_e;
+        h->ke = k;
+        h->boot_coarsest(x);
+        h->ke = ke_save;
+        h->have_e = he_save;
+        HIPCHK(hipMemcpyAsync(lam_host, h->lam_dev, k * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        break;
+      }
+      case BAMG_BOOT_FIT: {
+        if (h->coarsest(l)) return fail(BAMG_EINVAL, "no interpolation from the coarsest level");
+        if (k > 16) return fail(BAMG_EINVAL, "k > 16");
+        Level& Lv = h->lv[l];
+        if (k <= 8) {
+          if (k != h->p.n_tv) return fail(BAMG_EINVAL, "k must be n_tv or in (8, 16]");
+          h->fit(l, x);
+        } else {
+          launch_fit_ls(l == 0, Lv.ex, Lv.ey, x, k, Lv.P, h->s);
+          check_launch();
+        }
+        h->build_next(l);
+        h->refresh_mixed();
+        break;
+      }
+      default:
+        return fail(BAMG_EINVAL, "unknown op");
+    }
+    HIPCHK(hipStreamSynchronize(h->s));
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  } catch (const BadArg& e) {
+    return fail(BAMG_ESINGULAR, e.msg);
+  }
+  return BAMG_OK;
+}
+
+int bamg_export_boot(const bamg_hierarchy* hc, double* lam_host, void* ve_host) {
+  bamg_hierarchy* h = const_cast<bamg_hierarchy*>(hc);
+  if (!h || !lam_host) return fail(BAMG_EINVAL, "bad arguments");
+  if (!h->p.setup_mode || !h->have_e) return fail(BAMG_EINVAL, "not a bootstrap hierarchy");
+  try {
+    for (int k = 0; k < h->ke; ++k) lam_host[k] = h->lam_final[k];
+    if (ve_host) {
+      HIPCHK(hipMemcpyAsync(ve_host, h->tve(0), h->lv[0].n * h->ke * sizeof(zd), hipMemcpyDeviceToHost, h->s));
+      HIPCHK(hipStreamSynchronize(h->s));
+    }
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  }
+  return h->ke;
 }
 
 int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void* out, void* stream) {

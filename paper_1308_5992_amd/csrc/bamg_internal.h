@@ -98,9 +98,10 @@ void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, in
 template <typename T>
 void launch_slot_blocks(const FineT<T>& f, cx<T>* Bst, hipStream_t s);
 // one colour pass over the nsites = N^2/32 sites of fine colour `colour`
+// (lam != NULL: per right-hand side shift lam[r], the pass on (Dhat - lam Gamma_5) x = 0)
 template <typename T>
 void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
-                          hipStream_t s);
+                          hipStream_t s, const double* lam = nullptr);
 // rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
 template <typename T>
 void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);
@@ -211,5 +212,21 @@ void launch_sgather(const zd* X, size_t lds, size_t ldv, const int* slot, const 
 // X_{slot[a], j[a]} = c[a] * Y_{src[a]} with Y_k at Y + k*ldy (c NULL: copy; src NULL: a; j NULL: 0)
 void launch_sscatter(const zd* Y, size_t ldy, const int* src, zd* X, size_t lds, size_t ldv, const int* slot,
                      const int* j, const double* c, size_t n, int A, hipStream_t s);
+
+// ---- boot.hip: bootstrap multigrid eigensolver (Sec. 3.4, Theorem 1) -------
+// lam[r] = <Gamma_5 A v_r, v_r> / <v_r, v_r> for k vectors V with AV = A V
+// (dps = 2 on level 0, 16 above); partial holds blas_nblocks(n) * k complex
+void launch_ritz(const zd* V, const zd* AV, size_t n, int dps, int k, zd* partial, double* lam, hipStream_t s);
+void launch_gamma5(const zd* x, zd* y, size_t n, int dps, int k, hipStream_t s);
+// Y_j = sum_i X_i C[i][j], p vectors of length n, C (device) p x p row-major
+void launch_block_combine(const zd* X, const zd* C, zd* Y, size_t n, int p, hipStream_t s);
+// R_j = A_j - lam_j B_j for k vectors (lam device)
+void launch_eig_residual(const zd* A, const zd* B, const double* lam, zd* R, size_t n, int k, hipStream_t s);
+// one coarse colour pass on (D - lam_r Gamma_5) x_r = 0 (rows of a site in order)
+void launch_kaczmarz_coarse_shift(const Coarse& c, int colour, int mode, int nsites, zd* x, const double* lam,
+                                  int nrhs, hipStream_t s);
+// P from k (<= 16) test vectors: rank-8 least squares fit per aggregate and spin
+// (fine: ex = N/2, ey = N; coarse: the level's site extents)
+void launch_fit_ls(bool fine, int ex, int ey, const zd* V, int k, zd* P, hipStream_t s);
 
 }  // namespace bamg

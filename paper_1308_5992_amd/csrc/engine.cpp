@@ -264,7 +264,6 @@ void engine_issue_main(SlotEngine* e) {
   bamg_hierarchy* h = e->h;
   const size_t n = e->n;
   const int m = e->m, S = e->S;
-  hipStream_t s = h->s;
   e->act.clear();
   for (int q = 0; q < S; ++q)
     if (e->slots[q].state == ARNOLDI) e->act.push_back(q);

@@ -385,9 +385,12 @@ __device__ __forceinline__ void fine_colour_site(int c, int t, int N, int& x, in
   x = 8 * k + ((2 * a - y) & 7);
 }
 
+// lam (may be NULL): per right-hand side shift, the pass then works on
+// (Dhat - lam Gamma_5) x = 0 (the eigen-relaxation of the bootstrap setup,
+// Sec. 3.4 / Theorem 1), Gamma_5 = +1 on spin 0 and -1 on spin 1
 template <typename T>
 __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, int nsites, cx<T>* __restrict__ x,
-                                                      const cx<T>* __restrict__ b) {
+                                                      const cx<T>* __restrict__ b, const double* __restrict__ lam) {
   using C = cx<T>;
   const int lane = threadIdx.x & 15;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 4);
@@ -414,6 +417,11 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
     B[0][1] = bp[1];
     B[1][0] = bp[2];
     B[1][1] = bp[3];
+    if (lam && slot == 0) {  // slot 0 is the site itself: the diagonal 2 x 2 block
+      const T l = (T)lam[blockIdx.y];
+      B[0][0].x -= l;
+      B[1][1].x += l;
+    }
   }
   const C r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
   const C r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
@@ -428,11 +436,14 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
 }
 
 template <typename T>
-void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_kaczmarz_fine<T>, dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b);
+void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs, hipStream_t s,
+                          const double* lam) {
+  hipLaunchKernelGGL(k_kaczmarz_fine<T>, dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b, lam);
 }
-template void launch_kaczmarz_fine<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t);
-template void launch_kaczmarz_fine<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t);
+template void launch_kaczmarz_fine<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t,
+                                           const double*);
+template void launch_kaczmarz_fine<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t,
+                                          const double*);
 
 // ---------------------------------------------------------------------------
 // Transfers between level 0 and the 4x4 aggregates of the half-x grid.

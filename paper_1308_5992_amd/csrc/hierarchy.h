@@ -128,6 +128,14 @@ struct bamg_hierarchy {
   zd *ycoef_dev = nullptr, *ycoef_host = nullptr;    // per right-hand side update coefficients
   zd* tvsave = nullptr; // level-0 test vectors after the last setup pass
   SlotEngine* engine = nullptr;  // batched solves (slot engine, created on first use)
+  // bootstrap eigensolver state (setup_mode 1, 2): per level the test vectors
+  // are [V^r (n_tv) | V^e (ke)] in Level::tv; Ritz values on the device
+  int ke = 0;
+  bool have_e = false;
+  double *lam_dev = nullptr, *lam_host = nullptr;
+  zd *eigX = nullptr, *eigY = nullptr, *eigT = nullptr, *eigR = nullptr, *eigC = nullptr, *eigW = nullptr;
+  zd* eigH = nullptr;  // pinned host p x p
+  std::vector<double> lam_final;  // Ritz values at the end of the bootstrap setup
   // captured launch sequences (p.graphs): one executable graph per key, valid
   // while the buffers they name stay allocated (graph_gen counts reallocations)
   std::map<uint64_t, hipGraphExec_t> graphs;
@@ -224,6 +232,9 @@ struct bamg_hierarchy {
     free_krylov();
     dfree(tvsave);
     if (engine) engine_destroy(engine);
+    dfree(lam_dev); dfree(eigX); dfree(eigY); dfree(eigT); dfree(eigR); dfree(eigC); dfree(eigW); dfree(eigmm);
+    if (lam_host) (void)hipHostFree(lam_host);
+    if (eigH) (void)hipHostFree(eigH);
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
@@ -505,6 +516,297 @@ struct bamg_hierarchy {
       restrict_(l, Lv.tv, lv[l + 1].tv, k);
     }
     HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // ---------------------------------------------------------- bootstrap cycles
+  // The bootstrap setup of Sec. 3.4 with the multigrid eigensolver, in the
+  // Hermitian form of Theorem 1 (Z_l = Gamma_5 D_l, T_l = I): relaxation test
+  // vectors V^r on Z v = 0, eigenvector approximations V^e on Z v = lambda v
+  // (Kaczmarz on (D_l - lambda Gamma_5) v = 0, Ritz value after every sweep),
+  // the k_e eigenpairs of Z_L with the smallest |lambda| on the coarsest
+  // level, least squares P from V^r and V^e together.  Node kinds and their
+  // order follow the setup-cycle figure of Sec. 3.5 (see boot_visit).
+  zd* tve(int l) { return lv[l].tv + lv[l].n * p.n_tv; }
+
+  void normalise(int l, zd* X, int k) {
+    const size_t n = lv[l].n;
+    launch_norms(X, n, k, n, partial, hdev, s);
+    launch_normalize(X, n, k, n, hdev, s);
+    check_launch();
+  }
+  // one Kaczmarz sweep on (A_l - lam_r Gamma_5) x_r = 0 for k vectors
+  void sweep_shift(int l, zd* X, const double* lam, int k) {
+    Level& Lv = lv[l];
+    for (int c = 0; c < Lv.ncol; ++c) {
+      if (l == 0) launch_kaczmarz_fine(f, c, Lv.per_colour, X, (const zd*)nullptr, k, s, lam);
+      else launch_kaczmarz_coarse_shift(Lv.coarse(), c, Lv.cmode, Lv.per_colour, X, lam, k, s);
+    }
+    check_launch();
+  }
+  // lam[r] = <Z_l x_r, x_r> / <x_r, x_r> (eq. eqevZ, T = I)
+  void ritz(int l, const zd* X, int k, double* lam) {
+    Level& Lv = lv[l];
+    apply(l, X, Lv.r, nullptr, k);
+    launch_ritz(X, Lv.r, Lv.n, Lv.dps, k, partial, lam, s);
+    check_launch();
+  }
+  void boot_relax_r(int l, int nu) {
+    for (int i = 0; i < nu; ++i) sweep(l, lv[l].tv, nullptr, p.n_tv);
+    normalise(l, lv[l].tv, p.n_tv);
+  }
+  void boot_relax_e(int l, int nu) {
+    if (!have_e) return;
+    for (int i = 0; i < nu; ++i) {
+      sweep_shift(l, tve(l), lam_dev, ke);
+      ritz(l, tve(l), ke, lam_dev);
+    }
+    normalise(l, tve(l), ke);
+  }
+  void boot_fit(int l) {
+    Level& Lv = lv[l];
+    const int k = p.n_tv + (have_e ? ke : 0);
+    if (k <= 8) fit(l, Lv.tv);
+    else launch_fit_ls(l == 0, Lv.ex, Lv.ey, Lv.tv, k, Lv.P, s);
+    check_launch();
+    build_next(l);
+    restrict_(l, Lv.tv, lv[l + 1].tv, k);
+  }
+  void boot_interp_e(int l) {
+    launch_fill_zero(tve(l), lv[l].n * ke, s);
+    prolong(l, tve(l + 1), tve(l), ke);
+  }
+  // Hermitian eigen-decomposition of a small host matrix by cyclic Jacobi
+  // rotations (w unsorted, E columns = eigenvectors)
+  static void small_heig(int n, std::vector<std::complex<double>>& H, std::vector<double>& w,
+                         std::vector<std::complex<double>>& E) {
+    typedef std::complex<double> Cd;
+    E.assign((size_t)n * n, Cd(0.0));
+    for (int i = 0; i < n; ++i) E[(size_t)i * n + i] = 1.0;
+    double fro = 0;
+    for (auto& z : H) fro += std::norm(z);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+      double off = 0;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+          if (i != j) off += std::norm(H[(size_t)i * n + j]);
+      if (off <= 1e-30 * fro || off == 0.0) break;
+      for (int a = 0; a < n - 1; ++a)
+        for (int b = a + 1; b < n; ++b) {
+          const Cd hab = H[(size_t)a * n + b];
+          const double r = std::abs(hab);
+          if (r == 0.0) continue;
+          const Cd ph = hab / r;
+          const double ta = (H[(size_t)b * n + b].real() - H[(size_t)a * n + a].real()) / (2.0 * r);
+          const double t = (ta >= 0 ? 1.0 : -1.0) / (std::abs(ta) + std::sqrt(1.0 + ta * ta));
+          const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+          const Cd u00 = c, u01 = sn, u10 = -sn * std::conj(ph), u11 = c * std::conj(ph);
+          for (int k = 0; k < n; ++k) {
+            const Cd x0 = H[(size_t)k * n + a], x1 = H[(size_t)k * n + b];
+            H[(size_t)k * n + a] = x0 * u00 + x1 * u10;
+            H[(size_t)k * n + b] = x0 * u01 + x1 * u11;
+          }
+          for (int k = 0; k < n; ++k) {
+            const Cd x0 = H[(size_t)a * n + k], x1 = H[(size_t)b * n + k];
+            H[(size_t)a * n + k] = std::conj(u00) * x0 + std::conj(u10) * x1;
+            H[(size_t)b * n + k] = std::conj(u01) * x0 + std::conj(u11) * x1;
+          }
+          H[(size_t)a * n + b] = 0.0;
+          H[(size_t)b * n + a] = 0.0;
+          for (int k = 0; k < n; ++k) {
+            const Cd x0 = E[(size_t)k * n + a], x1 = E[(size_t)k * n + b];
+            E[(size_t)k * n + a] = x0 * u00 + x1 * u10;
+            E[(size_t)k * n + b] = x0 * u01 + x1 * u11;
+          }
+        }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = H[(size_t)i * n + i].real();
+  }
+  // G = X^H Y for pc vectors of length n (device), result on the host (column j: X^H Y_j)
+  void block_gram(const zd* X, const zd* Y, size_t n, int pc, std::vector<std::complex<double>>& G) {
+    for (int j = 0; j < pc; ++j) launch_multidot(X, n, pc, Y + (size_t)j * n, n, partial, eigC + (size_t)j * pc, s);
+    check_launch();
+    HIPCHK(hipMemcpyAsync(eigH, eigC, (size_t)pc * pc * sizeof(zd), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    G.assign((size_t)pc * pc, 0.0);
+    for (int j = 0; j < pc; ++j)
+      for (int i = 0; i < pc; ++i) G[(size_t)i * pc + j] = {eigH[(size_t)j * pc + i].x, eigH[(size_t)j * pc + i].y};
+  }
+  // Y = X C with the host pc x pc matrix C
+  void block_combine(const zd* X, const std::vector<std::complex<double>>& Cm, zd* Y, size_t n, int pc) {
+    for (size_t e = 0; e < (size_t)pc * pc; ++e) eigH[e] = zd{Cm[e].real(), Cm[e].imag()};
+    HIPCHK(hipMemcpyAsync(eigW, eigH, (size_t)pc * pc * sizeof(zd), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // eigH is reused by the next host step
+    launch_block_combine(X, eigW, Y, n, pc, s);
+    check_launch();
+  }
+  // eigX <- an orthonormal basis of the pc vectors `in` (Cholesky QR applied
+  // twice; `in` and `work` are overwritten, neither may be eigX unless in == eigX)
+  void cholqr2(zd* in, zd* work, size_t n, int pc) {
+    typedef std::complex<double> Cd;
+    for (int pass = 0; pass < 2; ++pass) {
+      const zd* src = pass == 0 ? in : work;
+      zd* dst = pass == 0 ? work : eigX;
+      std::vector<Cd> G;
+      block_gram(src, src, n, pc, G);
+      // G = L L^H, then dst = src L^{-H}
+      std::vector<Cd> Lm((size_t)pc * pc, 0.0);
+      for (int j = 0; j < pc; ++j) {
+        double d = G[(size_t)j * pc + j].real();
+        for (int k = 0; k < j; ++k) d -= std::norm(Lm[(size_t)j * pc + k]);
+        if (!(d > 0)) throw BadArg("coarsest eigensolver: rank-deficient block");
+        const double ljj = std::sqrt(d);
+        Lm[(size_t)j * pc + j] = ljj;
+        for (int i = j + 1; i < pc; ++i) {
+          Cd sum = G[(size_t)i * pc + j];
+          for (int k = 0; k < j; ++k) sum -= Lm[(size_t)i * pc + k] * std::conj(Lm[(size_t)j * pc + k]);
+          Lm[(size_t)i * pc + j] = sum / ljj;
+        }
+      }
+      // Ci = L^{-H} (upper triangular): L^H Ci = I column by column
+      std::vector<Cd> Ci((size_t)pc * pc, 0.0);
+      for (int c = 0; c < pc; ++c)
+        for (int i = pc - 1; i >= 0; --i) {
+          Cd sum = (i == c) ? Cd(1.0) : Cd(0.0);
+          for (int k = i + 1; k < pc; ++k) sum -= std::conj(Lm[(size_t)k * pc + i]) * Ci[(size_t)k * pc + c];
+          Ci[(size_t)i * pc + c] = sum / Lm[(size_t)i * pc + i].real();
+        }
+      block_combine(src, Ci, dst, n, pc);
+    }
+  }
+  // the ke eigenpairs of Z_L = Gamma_5 D_L with the smallest |lambda| by block
+  // inverse iteration with Z_L^{-1} = A_L^{-1} Gamma_5 (the coarsest inverse)
+  // and Rayleigh-Ritz on 2 ke vectors, until the residuals |Z x - lambda x| of
+  // the ke Ritz pairs are below 1e-12 max |lambda| (or 500 iterations)
+  void boot_coarsest(zd* out = nullptr) {
+    typedef std::complex<double> Cd;
+    Level& C = lv.back();
+    const size_t n = C.n;
+    const int pc = (int)std::min<size_t>((size_t)2 * ke, n);
+    launch_philox_tv((int)n, pc, p.seed ^ 0x3c6ef372fe94f82bull, eigX, s);
+    cholqr2(eigX, eigY, n, pc);  // eigX <- orthonormal
+    std::vector<double> vals, sorted(pc);
+    std::vector<Cd> H, E, G;
+    for (int it = 0; it < 500; ++it) {
+      launch_gamma5(eigX, eigT, n, 16, pc, s);
+      launch_dense_mv(C.Ainv, (int)n, eigT, eigY, pc, true, eigmm, s);
+      check_launch();
+      cholqr2(eigY, eigT, n, pc);  // eigX <- orthonormal basis of A^{-1} Gamma_5 X
+      launch_coarse_apply(C.coarse(), (const zd*)eigX, eigT, (const zd*)nullptr, pc, s);
+      launch_gamma5(eigT, eigY, n, 16, pc, s);  // eigY = Z X
+      check_launch();
+      block_gram(eigX, eigY, n, pc, H);  // X^H Z X
+      for (int i = 0; i < pc; ++i)       // symmetrise the rounding
+        for (int j = i + 1; j < pc; ++j) {
+          const Cd a = 0.5 * (H[(size_t)i * pc + j] + std::conj(H[(size_t)j * pc + i]));
+          H[(size_t)i * pc + j] = a;
+          H[(size_t)j * pc + i] = std::conj(a);
+        }
+      for (int i = 0; i < pc; ++i) H[(size_t)i * pc + i] = H[(size_t)i * pc + i].real();
+      small_heig(pc, H, vals, E);
+      std::vector<int> idx(pc);
+      for (int i = 0; i < pc; ++i) idx[i] = i;
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return std::abs(vals[a]) < std::abs(vals[b]); });
+      std::vector<Cd> W((size_t)pc * pc);
+      for (int i = 0; i < pc; ++i)
+        for (int j = 0; j < pc; ++j) W[(size_t)i * pc + j] = E[(size_t)i * pc + idx[j]];
+      for (int j = 0; j < pc; ++j) sorted[j] = vals[idx[j]];
+      // Ritz vectors X W (into eigT), Z X W (into eigX), residuals of the first ke (into eigR)
+      block_combine(eigX, W, eigT, n, pc);
+      block_combine(eigY, W, eigX, n, pc);
+      for (int j = 0; j < ke; ++j) lam_host[j] = sorted[j];
+      HIPCHK(hipMemcpyAsync(lam_dev, lam_host, ke * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_eig_residual(eigX, eigT, lam_dev, eigR, n, ke, s);
+      launch_norms(eigR, n, ke, n, partial, eigC, s);
+      check_launch();
+      HIPCHK(hipMemcpyAsync(eigH, eigC, ke * sizeof(zd), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      std::swap(eigX, eigT);  // eigX = Ritz vectors
+      double res = 0, scale = 0;
+      for (int j = 0; j < ke; ++j) {
+        res = std::max(res, std::sqrt(eigH[j].x));
+        scale = std::max(scale, std::abs(sorted[j]));
+      }
+      if (res <= 1e-12 * scale) break;
+    }
+    // V^e on the coarsest level: the ke Ritz vectors of smallest |lambda| (unit norm)
+    launch_copy(eigX, out ? out : tve((int)lv.size() - 1), n * ke, s);
+    check_launch();
+    have_e = true;
+  }
+  void boot_arrive(int l, int nu, bool first) {
+    boot_relax_r(l, nu);
+    if (!first) boot_relax_e(l, nu);
+    boot_fit(l);
+  }
+  // a visit of level l >= 1 in a setup cycle: arrive, then gamma visits of the
+  // level below, each followed by the interpolation of V^e; between two visits
+  // the level relaxes both sets and recomputes P, after the last it relaxes V^e
+  void boot_visit(int l, const std::vector<int>& nu, bool first, int gamma) {
+    const int Lc = L() - 1;
+    boot_arrive(l, nu[l], first);
+    for (int g = 0; g < gamma; ++g) {
+      if (l + 1 == Lc) boot_coarsest();
+      else boot_visit(l + 1, nu, first && g == 0, gamma);
+      boot_interp_e(l);
+      if (g < gamma - 1) boot_arrive(l, nu[l], false);
+      else boot_relax_e(l, nu[l]);
+    }
+  }
+  void boot_cycle(const std::vector<int>& nu, bool first, int gamma) {
+    boot_arrive(0, nu[0], first);
+    if (L() == 2) boot_coarsest();
+    else boot_visit(1, nu, first, gamma);
+    boot_interp_e(0);
+    boot_relax_e(0, nu[0]);
+  }
+  zd* eigmm = nullptr;
+  // buffers of the eigensolver for ke_ (<= 8) eigenpairs
+  void ensure_boot(int ke_) {
+    if (lam_dev) return;
+    ke = ke_;
+    const size_t nL = lv.back().n;
+    const int pc = (int)std::min<size_t>((size_t)2 * 8, nL);
+    lam_dev = dalloc<double>(16);
+    HIPCHK(hipHostMalloc((void**)&lam_host, 16 * sizeof(double)));
+    eigX = dalloc<zd>(nL * pc);
+    eigY = dalloc<zd>(nL * pc);
+    eigT = dalloc<zd>(nL * pc);
+    eigR = dalloc<zd>(nL * pc);
+    eigC = dalloc<zd>((size_t)pc * pc);
+    eigW = dalloc<zd>((size_t)pc * pc);
+    eigmm = dalloc<zd>(dense_mm_workspace((int)nL, pc));
+    HIPCHK(hipHostMalloc((void**)&eigH, (size_t)pc * pc * sizeof(zd)));
+  }
+  void boot_setup() {
+    ensure_boot(p.n_ev);
+    ke = p.n_ev;
+    have_e = false;
+    const int gamma = (p.setup_mode == 1) ? 2 : 1;
+    auto sweeps = [&](int mu) {
+      std::vector<int> nu(L());
+      for (int l = 0; l < L(); ++l) nu[l] = (p.setup_mode == 1) ? mu : mu * (1 << l);
+      return nu;
+    };
+    boot_cycle(sweeps(p.boot_nu1), true, gamma);
+    // adaptive step (Sec. 4.1): two cycles of the current solver on Dhat v = 0
+    // for the eigenvector approximation with the smallest |Ritz value|
+    HIPCHK(hipMemcpyAsync(lam_host, lam_dev, ke * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int kmin = 0;
+    for (int k = 1; k < ke; ++k)
+      if (std::abs(lam_host[k]) < std::abs(lam_host[kmin])) kmin = k;
+    Level& L0 = lv[0];
+    zd* v = tve(0) + L0.n * kmin;
+    launch_fill_zero(L0.b, L0.n, s);
+    for (int c = 0; c < 2; ++c) cycle(0, L0.b, v, 1);
+    normalise(0, v, 1);
+    ritz(0, v, 1, lam_dev + kmin);
+    boot_cycle(sweeps(p.boot_nu2), false, gamma);
+    launch_copy(L0.tv, tvsave, L0.n * p.n_tv, s);
+    HIPCHK(hipMemcpyAsync(lam_host, lam_dev, ke * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    lam_final.assign(lam_host, lam_host + ke);
   }
 };
 

@@ -1,0 +1,151 @@
+"""GPU parity of the bootstrap multigrid eigensolver (Sec. 3.4; Theorem 1 of
+Sec. 3.5) against the oracle, through bamg_boot_op and bamg_setup with
+setup_mode 1 (W setup cycles) and 2 (super-V):
+
+* Ritz values and the Kaczmarz sweep on (D - lambda Gamma_5) v = 0 on the fine
+  and a coarse level, on identical inputs (imported P): 1e-12;
+* the coarsest eigenpairs (GPU: block inverse iteration with Rayleigh-Ritz;
+  oracle: Jacobi on the dense Z_L): eigenvalues 1e-10, eigenspace projector 1e-8;
+* the rank-8 least squares fit with 16 test vectors: P 1e-10;
+* the whole bootstrap setup from identical initial test vectors: Ritz values
+  and interpolation projectors agree to the accuracy of the coarsest
+  eigensolve (1e-7), the solves converge with equal iteration counts.
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from tests.gpu_util import projector_diff, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bamg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1308_5992_amd as b
+    return b
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def _random_P(shape, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    Q, _ = np.linalg.qr(A)
+    return Q
+
+
+@pytest.fixture(scope="module")
+def imported(bamg):
+    """32^2, 3 levels (level 2: 2 x 4 sites, 128 unknowns), identical P on both sides."""
+    N = 32
+    U = inputs.gauge_metropolis(N, 3.0, 40, 21)
+    m = -0.1
+    kw = dict(n_levels=3, setup_sweeps=2, setup_adapt=0)
+    h = bamg.bamg_setup(dev(U), m, bamg.bamg_default_params(N=N, **kw))
+    o = oracle.Hierarchy(U, m, **kw)
+    for l in range(2):
+        P = _random_P(o.P_blocks(l).shape, 300 + l)
+        bamg.bamg_import_level(h, l, P)
+        o.import_P(l, P)
+    return N, U, m, h, o
+
+
+@pytest.mark.parametrize("l", [0, 1])
+def test_ritz_and_shifted_sweep(bamg, imported, l):
+    N, U, m, h, o = imported
+    n = bamg.bamg_level_info(h, l)["n"]
+    k = 5
+    X = inputs.gaussian((k, n), 310 + l)
+    lam = np.zeros(k)
+    bamg.bamg_boot_op(h, l, bamg.BOOT_RITZ, dev(X), lam, k)
+    lo = o.ritz(l, X, nrhs=k)
+    assert np.abs(lam - lo).max() < 1e-12 * (1 + np.abs(lo).max())
+    shifts = np.linspace(-0.3, 0.4, k)
+    Xg = dev(X)
+    bamg.bamg_boot_op(h, l, bamg.BOOT_SWEEP, Xg, shifts.copy(), k)
+    Xo = o.sweep_shifted(l, X, shifts, nrhs=k).reshape(k, n)
+    e = rel(host(Xg), Xo)
+    log(f"level {l}: ritz err {np.abs(lam - lo).max():.1e}, shifted sweep err {e:.1e}")
+    assert e < 1e-12
+
+
+def test_coarsest_eigenpairs(bamg, imported):
+    N, U, m, h, o = imported
+    L = bamg.bamg_n_levels(h) - 1
+    n = bamg.bamg_level_info(h, L)["n"]
+    k = 8
+    X = torch.zeros(k, n, dtype=torch.complex128, device="cuda:0")
+    lam = np.zeros(k)
+    bamg.bamg_boot_op(h, L, bamg.BOOT_EIGS, X, lam, k)
+    vo, Vo = o.coarsest_eigs(k)
+    log(f"coarsest eigenvalues gpu {lam} oracle {vo}")
+    assert np.abs(lam - vo).max() < 1e-10 * np.abs(vo).max()
+    Xg = host(X)
+    Pg = Xg.T @ Xg.conj()
+    Po = Vo.T @ Vo.conj()
+    assert np.abs(Pg - Po).max() < 1e-8
+
+
+@pytest.mark.parametrize("l", [0, 1])
+def test_least_squares_fit_16_vectors(bamg, imported, l):
+    N, U, m, h, o = imported
+    n = bamg.bamg_level_info(h, l)["n"]
+    V = inputs.gaussian((16, n), 320 + l)
+    lam = np.zeros(16)
+    bamg.bamg_boot_op(h, l, bamg.BOOT_FIT, dev(V), lam, 16)
+    o.fit_ls(l, V)
+    Pg, _, _ = bamg.bamg_export_level(h, l, P=True, D=False)
+    Po = o.P_blocks(l)
+    assert np.abs(Pg - Po).max() < 1e-10
+    # the rebuilt coarse operator follows
+    _, Dg, _ = bamg.bamg_export_level(h, l + 1, P=False, D=True)
+    if Dg is not None and l + 1 < bamg.bamg_n_levels(h) - 1:
+        from tests.gpu_util import blocks_to_csr
+        inf = bamg.bamg_level_info(h, l + 1)
+        A = blocks_to_csr(Dg, inf["ex"], inf["ey"]).toarray()
+        Ao = o.operator(l + 1).toarray()
+        assert np.abs(A - Ao).max() < 1e-12 * np.abs(Ao).max()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_bootstrap_setup_matches_oracle(bamg, mode):
+    N = 32
+    U = inputs.gauge_metropolis(N, 3.0, 60, 11)
+    m = -0.12
+    tv = oracle.gaussian_tv(N, 8, 12)
+    kw = dict(n_levels=3)
+    p = bamg.bamg_default_params(N=N, setup_mode=mode, n_ev=8, boot_nu1=10, boot_nu2=5, **kw)
+    h = bamg.bamg_setup(dev(U), m, p, init_tv=tv)
+    o = oracle.Hierarchy(U, m, boot=mode, k_e=8, nu1=10, nu2=5, init_tv=tv, **kw)
+    lg, veg = bamg.bamg_export_boot(h, N)
+    lo, veo = o.boot_vectors()
+    dl = np.abs(lg - lo).max() / np.abs(lo).max()
+    dps = [projector_diff(bamg.bamg_export_level(h, l, P=True, D=False)[0], o.P_blocks(l)) for l in range(2)]
+    log(f"mode {mode}: ritz gpu {np.sort(np.abs(lg))[:3]} oracle {np.sort(np.abs(lo))[:3]}, "
+        f"ritz diff {dl:.1e}, projector diffs {dps}")
+    assert dl < 1e-7
+    assert max(dps) < 1e-7
+    b = inputs.gaussian(2 * N * N, 13)
+    x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
+    st, info = bamg.bamg_solve(h, dev(b), x, 1e-10)
+    sto, xo, io = o.solve(b, tol=1e-10)
+    assert st == 0 and sto == 0 and abs(info["iters"] - io["iters"]) <= 1
+    full = np.linalg.norm(b - oracle.wilson_apply(U, m, host(x))) / np.linalg.norm(b)
+    assert full < 2e-10
