@@ -49,10 +49,12 @@ def parse():
     ap.add_argument("--batch", default="8,32", help="right-hand sides per batched solve (comma list, '' for none)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--precisions",
-                    default="mixed_fp16+graphs+v22,fp64+graphs+v22,mixed_fp16+graphs,fp64+graphs,mixed_fp16,"
+                    default="mixed_fp16+graphs+v22+bootV,fp64+graphs+v22+bootV,mixed_fp16+graphs+v22,"
+                            "fp64+graphs+v22,mixed_fp16+graphs+v22+bootW,mixed_fp16+graphs,fp64+graphs,mixed_fp16,"
                             "mixed_bf16+graphs+v22,mixed_fp32+graphs+v22",
-                    help="single-RHS variants to time, <precision>[+graphs][+v22] (graphs: iterations replayed as "
-                         "hipGraphs; v22: V(2,2) cycle instead of V(4,4)); the first one is the headline value")
+                    help="single-RHS variants to time, <precision>[+graphs][+v22][+bootW|+bootV] (graphs: iterations "
+                         "replayed as hipGraphs; v22: V(2,2) cycle instead of V(4,4); bootW / bootV: bootstrap setup "
+                         "with the multigrid eigensolver, W or super-V cycles); the first one is the headline value")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
     ap.add_argument("--c4", type=int, default=1, help="time the 512^2 x 64 RHS batched solve (0: skip)")
@@ -66,12 +68,18 @@ COPY_MIB = 256
 
 
 def variant(spec):
-    """Solver parameters of a bench variant '<precision>[+graphs][+v22]'."""
+    """Solver parameters of a bench variant '<precision>[+graphs][+v22][+bootW|+bootV]'
+    (bootW / bootV: bootstrap setup with the multigrid eigensolver, W or super-V
+    setup cycles)."""
     base, *opts = spec.split("+")
     kw = {"precision": PRECISIONS[base], "graphs": 1 if "graphs" in opts else 0}
     if "v22" in opts:
         kw.update(pre=2, post=2)
-    unknown = set(opts) - {"graphs", "v22"}
+    if "bootW" in opts:
+        kw.update(setup_mode=1)
+    if "bootV" in opts:
+        kw.update(setup_mode=2)
+    unknown = set(opts) - {"graphs", "v22", "bootW", "bootV"}
     if unknown:
         raise SystemExit(f"bench.py: unknown variant option(s) {sorted(unknown)} in {spec!r}")
     return base, kw
@@ -310,6 +318,7 @@ def main():
             "iters": infos[-1]["iters"], "relres_reduced": infos[-1]["relres_reduced"],
             "converged": all(i["relres_reduced"] <= args.tol for i in infos), "setup_s": t_setup,
             "levels": bamg.bamg_n_levels(h), "cycle": f"V({p.pre},{p.post})", "graphs": bool(p.graphs),
+            "setup": {0: "relax-fit passes", 1: "bootstrap W cycles", 2: "bootstrap super-V"}[p.setup_mode],
         }
         hier[prec] = h
         xs[prec] = x.cpu().numpy()
@@ -317,8 +326,8 @@ def main():
     # error of every variant against the FP64 solve with the same cycle
     for prec in precs:
         base, kw = variant(prec)
-        refs = [q for q in precs if variant(q)[0] == "fp64" and
-                (variant(q)[1].get("pre"), variant(q)[1].get("post")) == (kw.get("pre"), kw.get("post"))]
+        key = lambda kw_: (kw_.get("pre"), kw_.get("post"), kw_.get("setup_mode"))
+        refs = [q for q in precs if variant(q)[0] == "fp64" and key(variant(q)[1]) == key(kw)]
         if base != "fp64" and refs:
             results[prec]["rel_err_vs_fp64"] = float(np.linalg.norm(xs[prec] - xs[refs[0]]) /
                                                      np.linalg.norm(xs[refs[0]]))
@@ -342,7 +351,7 @@ def main():
             "workload": w["name"], "N": N, "beta": w["beta"], "metropolis_sweeps": w["sweeps"],
             "m": w["m"], "min_abs_eig_D": w["min_abs_eig_D"], "levels": n_levels,
             "aggregates": "4x4 half-x, then 2x2", "test_vectors": 8, "cycle": r0["cycle"],
-            "coarsest": "dense inverse, FP64", "hipgraph": r0["graphs"],
+            "coarsest": "dense inverse, FP64", "hipgraph": r0["graphs"], "setup": r0["setup"],
             "krylov": "FGMRES(32)", "tol": args.tol, "nrhs": 1, "precision": head_base, "variant": head,
         },
         "p50_ms": r0["p50_ms"],
@@ -376,12 +385,17 @@ def main():
 
     # ---- 512^2 x 64 right-hand sides on one field (multi-RHS form)
     if args.c4:
-        out["c4_512x64"] = c4_batched(bamg, inputs, torch, args.tol, head_kw)
+        # the 512^2 batch and the serving mix use the headline parameters with the
+        # relax-fit setup (at 512^2 it gives fewer iterations than the bootstrap
+        # cycles, and the serving warm-up builds four hierarchies)
+        multi_kw = {k: v for k, v in head_kw.items() if k != "setup_mode"}
+        out["c4_512x64"] = c4_batched(bamg, inputs, torch, args.tol, multi_kw)
         progress(f"512^2 x 64: {out['c4_512x64']['solves_per_s']:.1f} solves/s")
 
     # ---- serving: Poisson arrivals over four fields, continuous batching
     if args.serve > 0:
-        out["serving"] = serving(bamg, inputs, torch, np, args.serve, args.serve_rate, args.tol, head_kw)
+        multi_kw = {k: v for k, v in head_kw.items() if k != "setup_mode"}
+        out["serving"] = serving(bamg, inputs, torch, np, args.serve, args.serve_rate, args.tol, multi_kw)
         out["serving_p99_ms"] = out["serving"]["p99_ms"]
         progress(f"serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms")
 
