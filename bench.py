@@ -453,8 +453,8 @@ COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine", "mixed_fp16"): {"src": "fine.hip",
-                             "sha256": "8c39c9a77e138498145ad1ad2a7e41431415a9eb744eb5b82f4a795a289d4e75",
-                             "fetch_kib": 761.0, "write_kib": 448.0, **COPY_SCALE},
+                             "sha256": "483fde11dc092bbc1c0280d483f52373b5303f4848dbc7df97b4a982dc3fbf7c",
+                             "fetch_kib": 762.0, "write_kib": 448.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "676578ea4fbb84cbfe95f0270878300590c3ed8b8a3c4a9fb0a712aea4efed1e",
                                "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE},
