@@ -157,11 +157,16 @@ int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *
  *   op 10 BAMG_OP_APPLY_F32, op 11 BAMG_OP_SWEEP_F32: as ops 7 and 8, but in and out
  *         are complex64 (interleaved float) arrays used as they are, with no
  *         conversion launches: exactly the kernels of one FP32 apply or sweep
+ *   op 12 BAMG_OP_COARSEST_F32: out = A_L^-1 in with complex64 in and out
+ *         (l the coarsest level), read from the FP32 copy of the inverse that
+ *         the mixed cycle uses: one product launch for nrhs <= 2, else the
+ *         split-K product on the matrix cores and its reduction
+ * Ops 4 and 12 require in and out not to alias.
  * Level 0 is the fine reduced system (A_0 = Dhat). */
 enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLONG = 3,
        BAMG_OP_COARSEST = 4, BAMG_OP_CYCLE = 5, BAMG_OP_RESIDUAL = 6,
        BAMG_OP_APPLY_MIXED = 7, BAMG_OP_SWEEP_MIXED = 8, BAMG_OP_CYCLE_MIXED = 9,
-       BAMG_OP_APPLY_F32 = 10, BAMG_OP_SWEEP_F32 = 11 };
+       BAMG_OP_APPLY_F32 = 10, BAMG_OP_SWEEP_F32 = 11, BAMG_OP_COARSEST_F32 = 12 };
 int bamg_level_op(bamg_hierarchy *h, int32_t level, int32_t op, const void *in, void *out, int32_t nrhs);
 
 /* Pieces of the bootstrap multigrid eigensolver (Sec. 3.4, Theorem 1 of Sec. 3.5;

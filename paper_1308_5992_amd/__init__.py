@@ -22,7 +22,7 @@ BAMG_CYCLE_V, BAMG_CYCLE_W = 0, 1
 BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
 OP_APPLY, OP_SWEEP, OP_RESTRICT, OP_PROLONG, OP_COARSEST, OP_CYCLE, OP_RESIDUAL = range(7)
 OP_APPLY_MIXED, OP_SWEEP_MIXED, OP_CYCLE_MIXED = 7, 8, 9
-OP_APPLY_F32, OP_SWEEP_F32 = 10, 11
+OP_APPLY_F32, OP_SWEEP_F32, OP_COARSEST_F32 = 10, 11, 12
 BOOT_RITZ, BOOT_SWEEP, BOOT_EIGS, BOOT_FIT = range(4)
 
 EXPORTED = [
@@ -220,8 +220,8 @@ def bamg_eo_reconstruct(h, b, xe, x, nrhs: int = 1):
 
 
 def bamg_level_op(h, level: int, op: int, inp, out, nrhs: int = 1):
-    """Ops 10 and 11 take complex64 tensors, every other op complex128."""
-    c64 = op in (OP_APPLY_F32, OP_SWEEP_F32)
+    """Ops 10, 11 and 12 take complex64 tensors, every other op complex128."""
+    c64 = op in (OP_APPLY_F32, OP_SWEEP_F32, OP_COARSEST_F32)
     _check(lib.bamg_level_op(h, int(level), int(op), _ptr(inp, c64), _ptr(out, c64), int(nrhs)), "bamg_level_op")
 
 

@@ -319,9 +319,20 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         break;
       case BAMG_OP_COARSEST:
         if (!h->coarsest(l) || h->L() == 1) return fail(BAMG_EINVAL, "level is not a directly solved coarsest level");
+        if (in == out) return fail(BAMG_EINVAL, "in and out must not alias");
         h->ensure_cap(nrhs);  // the split-K product needs workspace for nrhs right-hand sides
         h->coarsest_solve(xi, xo, nrhs);
         break;
+      case BAMG_OP_COARSEST_F32: {
+        if (!h->mixed()) return fail(BAMG_EINVAL, "hierarchy is FP64");
+        if (!h->coarsest(l) || h->L() == 1) return fail(BAMG_EINVAL, "level is not a directly solved coarsest level");
+        if (in == out) return fail(BAMG_EINVAL, "in and out must not alias");
+        h->ensure_cap(nrhs);
+        Level& C = h->lv[l];
+        launch_dense_mv32(C.Ainv32, (int)C.n, (const zf*)in, (zf*)out, nrhs, h->force_mr, (zf*)h->mmwork, h->s);
+        check_launch();
+        break;
+      }
       case BAMG_OP_CYCLE:
         h->ensure_cap(nrhs);
         launch_fill_zero(xo, h->lv[l].n * nrhs, h->s);
@@ -349,7 +360,7 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         }
         if ((op == BAMG_OP_SWEEP_MIXED || op == BAMG_OP_SWEEP_F32) && h->coarsest(l) && h->L() > 1)
           return fail(BAMG_EINVAL, "no smoother on the coarsest level");
-        if (l >= 1 && h->coarsest(l)) return fail(BAMG_EINVAL, "the coarsest level is solved in FP64");
+        if (l >= 1 && h->coarsest(l)) return fail(BAMG_EINVAL, "the coarsest level has no smoother; its solve is op 12");
         if (op == BAMG_OP_APPLY_F32 && in == out) return fail(BAMG_EINVAL, "in and out must not alias");
         h->ensure_cap(nrhs);
         Level& Lv = h->lv[l];

@@ -160,6 +160,12 @@ void launch_gj_unpermute(zd* A, int n, const int* perm, hipStream_t s);
 // (or whenever `many` is set; work holds dense_mm_workspace(n, nrhs) complex)
 void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, zd* work, hipStream_t s);
 size_t dense_mm_workspace(int n, int nrhs);
+// FP32 operands (mixed-precision cycle): y = A x with A the n x n FP32 copy of
+// the coarsest inverse, n a multiple of 16; one wave per row for up to two
+// right-hand sides, else split-K MFMA tiles with
+// dense_mm32_workspace_bytes(n, nrhs) bytes of partials in work
+void launch_dense_mv32(const zf* A, int n, const zf* x, zf* y, int nrhs, bool many, zf* work, hipStream_t s);
+size_t dense_mm32_workspace_bytes(int n, int nrhs);
 
 // ---- blas.hip ---------------------------------------------------------------
 // partial[b][v] = sum over block b of conj(X_v) w, X_v = X + v*ldx; then out[v] = sum_b partial[b][v]

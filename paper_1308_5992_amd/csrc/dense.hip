@@ -270,4 +270,185 @@ void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many
   }
 }
 
+// ---------------------------------------------------------------------------
+// The coarsest solve of the mixed-precision cycle: the cycle's coarse
+// correction is FP32 in and out, and the inverse is read from an FP32 copy
+// (rounded to nearest from the FP64 inverse), which halves the bytes of the
+// dominant read.
+// ---------------------------------------------------------------------------
+
+// y = A x for NR = 1 or 2 right-hand sides: one wave per row, two complex
+// entries per 16-byte load, products and sums in FP64, the row of A read once
+// for both right-hand sides.  n is a multiple of 16.
+template <int NR>
+__global__ __launch_bounds__(256) void k_dense_mv32(const zf* __restrict__ A, int n, const zf* __restrict__ x,
+                                                    zf* __restrict__ y) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wave;
+  if (row >= n) return;
+  const float4* Ar = reinterpret_cast<const float4*>(A + (size_t)row * n);
+  const int n2 = n >> 1;
+  double re[NR], im[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) re[r] = im[r] = 0.0;
+#pragma unroll 4
+  for (int j = lane; j < n2; j += 64) {
+    const float4 a = Ar[j];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const float4 v = reinterpret_cast<const float4*>(x + (size_t)r * n)[j];
+      re[r] += (double)a.x * v.x - (double)a.y * v.y + (double)a.z * v.z - (double)a.w * v.w;
+      im[r] += (double)a.x * v.y + (double)a.y * v.x + (double)a.z * v.w + (double)a.w * v.z;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    for (int off = 32; off > 0; off >>= 1) {
+      re[r] += __shfl_xor(re[r], off, 64);
+      im[r] += __shfl_xor(im[r], off, 64);
+    }
+    if (lane == 0) y[(size_t)r * n + row] = zf{(float)re[r], (float)im[r]};
+  }
+}
+
+// Y = A X for many right-hand sides on the matrix cores.  The complex product
+// is the real product of A viewed as an n x 2n real matrix (re, im
+// interleaved, as stored) with the 2n x 2R real matrix whose column pair for
+// right-hand side r holds (Re x, -Im x) and (Im x, Re x) interleaved along K:
+// column 2r gives Re y_r and column 2r+1 gives Im y_r.  A work-group owns 64
+// rows (16 per wave) and 8 NT right-hand sides over one K slice (split-K);
+// each lane streams 8 complex entries of its row per 32-complex chunk (four
+// 16-byte loads, prefetched one chunk ahead), the chunk of X goes through LDS.
+// Every output element sums its K range in a fixed order that does not depend
+// on the other columns, so a column's result does not depend on the batch.
+constexpr int M32_KC = 32, M32_SPLIT = 8;
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+// v_mfma_f32_16x16x4f32: lane l supplies A[l%16][k0 + l/16] and
+// B[k0 + l/16][l%16] and receives C[4(l/16) + e][l%16], e = 0..3
+static __device__ __forceinline__ mf4 mfma4(float a, float b, mf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_dense_mm32(const zf* __restrict__ A, int n, const zf* __restrict__ X,
+                                                    zf* __restrict__ part, int nrhs, int chunks_per_split) {
+  constexpr int RB = 8 * NT;            // right-hand sides of the work-group
+  constexpr int XQ = M32_KC / 2;        // float4 (two complex) per right-hand side and chunk
+  constexpr int XS = XQ + 1;            // padded LDS row
+  constexpr int XPT = (RB * XQ + 255) / 256;
+  constexpr int XBYTES = 2 * RB * XS * 16, TBYTES = RB * 64 * 8;
+  __shared__ __align__(16) char lds[XBYTES > TBYTES ? XBYTES : TBYTES];
+  float4 (*Xs)[RB][XS] = reinterpret_cast<float4 (*)[RB][XS]>(lds);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int c = lane & 15, g = lane >> 4, q = c & 1;
+  const int row0 = blockIdx.x * 64;
+  const bool wave_rows = row0 + wave * 16 < n;  // n is a multiple of 16
+  const int r0 = blockIdx.y * RB;
+  const int nch = (n + M32_KC - 1) / M32_KC;
+  const int ch0 = blockIdx.z * chunks_per_split;
+  const int ch1 = min(nch, ch0 + chunks_per_split);
+  const float4* Arow = reinterpret_cast<const float4*>(A + (size_t)min(row0 + wave * 16 + c, n - 1) * n);
+  mf4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mf4{0.f, 0.f, 0.f, 0.f};
+  float4 a[4], xr[XPT];
+  const float4 z4 = {0.f, 0.f, 0.f, 0.f};
+  auto load_a = [&](int ch) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = ch * M32_KC + 8 * g + 2 * t;  // complex column of the pair
+      a[t] = (wave_rows && k < n) ? Arow[k >> 1] : z4;
+    }
+  };
+  auto load_x = [&](int ch) {
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+      const int idx = tid + 256 * e, r = idx / XQ, j = idx % XQ;
+      const int k = ch * M32_KC + 2 * j;
+      xr[e] = (idx < RB * XQ && r0 + r < nrhs && k < n)
+                  ? reinterpret_cast<const float4*>(X + (size_t)(r0 + r) * n)[k >> 1]
+                  : z4;
+    }
+  };
+  if (ch0 < ch1) {
+    load_a(ch0);
+    load_x(ch0);
+  }
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int buf = (ch - ch0) & 1;
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+      const int idx = tid + 256 * e;
+      if (idx < RB * XQ) Xs[buf][idx / XQ][idx % XQ] = xr[e];
+    }
+    __syncthreads();
+    float4 cur[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cur[t] = a[t];
+    if (ch + 1 < ch1) {
+      load_a(ch + 1);
+      load_x(ch + 1);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        // complex entries k = 8g + 2t and k + 1 of right-hand side 8 ct + c / 2
+        const float4 v = Xs[buf][8 * ct + (c >> 1)][4 * g + t];
+        acc[ct] = mfma4(cur[t].x, q ? v.y : v.x, acc[ct]);
+        acc[ct] = mfma4(cur[t].y, q ? v.x : -v.y, acc[ct]);
+        acc[ct] = mfma4(cur[t].z, q ? v.w : v.z, acc[ct]);
+        acc[ct] = mfma4(cur[t].w, q ? v.z : -v.w, acc[ct]);
+      }
+    }
+  }
+  // transpose the 64 x RB tile through LDS so that the partials are written
+  // along the rows of each right-hand side
+  __syncthreads();
+  float (*T)[130] = reinterpret_cast<float (*)[130]>(lds);
+  static_assert(RB * 130 * 4 <= (XBYTES > TBYTES ? XBYTES : TBYTES), "transpose tile exceeds LDS");
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) T[8 * ct + (c >> 1)][2 * (wave * 16 + 4 * g + e) + q] = acc[ct][e];
+  __syncthreads();
+  zf* out = part + (size_t)blockIdx.z * nrhs * n;
+  for (int idx = tid; idx < RB * 64; idx += 256) {
+    const int r = idx >> 6, i = idx & 63;
+    if (r0 + r < nrhs && row0 + i < n) out[(size_t)(r0 + r) * n + row0 + i] = zf{T[r][2 * i], T[r][2 * i + 1]};
+  }
+}
+
+__global__ void k_dense_mm32_reduce(const zf* __restrict__ part, size_t tot, zf* __restrict__ Y) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tot) return;
+  zf s = part[t];
+#pragma unroll
+  for (int q = 1; q < M32_SPLIT; ++q) s = s + part[(size_t)q * tot + t];
+  Y[t] = s;
+}
+
+size_t dense_mm32_workspace_bytes(int n, int nrhs) { return (size_t)M32_SPLIT * n * nrhs * sizeof(zf); }
+
+void launch_dense_mv32(const zf* A, int n, const zf* x, zf* y, int nrhs, bool many, zf* work, hipStream_t s) {
+  if (!many && nrhs <= 2) {
+    if (nrhs == 1) hipLaunchKernelGGL(k_dense_mv32<1>, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y);
+    else hipLaunchKernelGGL(k_dense_mv32<2>, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y);
+    return;
+  }
+  const int nch = (n + M32_KC - 1) / M32_KC;
+  const int cps = (nch + M32_SPLIT - 1) / M32_SPLIT;
+  const int nt = nrhs <= 8 ? 1 : nrhs <= 16 ? 2 : nrhs <= 32 ? 4 : 8;
+  const dim3 grid((n + 63) / 64, (nrhs + 8 * nt - 1) / (8 * nt), M32_SPLIT);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL(k_dense_mm32<1>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+    case 2: hipLaunchKernelGGL(k_dense_mm32<2>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+    case 4: hipLaunchKernelGGL(k_dense_mm32<4>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+    default: hipLaunchKernelGGL(k_dense_mm32<8>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+  }
+  const size_t tot = (size_t)n * nrhs;
+  hipLaunchKernelGGL(k_dense_mm32_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, tot, y);
+}
+
 }  // namespace bamg

@@ -92,6 +92,7 @@ struct Level {
   zf* P32 = nullptr;
   void* Dst = nullptr;
   zf* Kinv32 = nullptr;
+  zf* Ainv32 = nullptr;         // FP32 copy of the coarsest inverse
   zf *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
   Coarse coarse() const {
     Coarse c;
@@ -224,7 +225,7 @@ struct bamg_hierarchy {
     for (auto& L : lv) {
       dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.P);
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
-      dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
+      dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
     }
     dfree(mmwork);
     dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(Bst); dfree(Bst32); dfree(gjcol); dfree(gjperm); dfree(dflag);
@@ -327,7 +328,7 @@ struct bamg_hierarchy {
   // ------------------------------------------------ mixed-precision cycle
   // The preconditioner of the mixed modes: the same cycle in FP32 with the
   // coarse operators read from their reduced-precision copies and the
-  // coarsest level solved with the FP64 inverse (FP64 in, FP64 out).
+  // coarsest level solved with the FP32 copy of the inverse (FP32 in and out).
   template <typename S>
   CoarseT<float, S> coarse32(int l) const {
     CoarseT<float, S> c;
@@ -362,9 +363,7 @@ struct bamg_hierarchy {
     if (coarsest(l)) {
       Level& C = lv[l];
       if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
-      launch_convert(b, C.b, C.n * nrhs, s);
-      launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, force_mr, mmwork, s);
-      launch_convert(C.x, x, C.n * nrhs, s);
+      launch_dense_mv32(C.Ainv32, (int)C.n, b, x, nrhs, force_mr, (zf*)mmwork, s);
       check_launch();
       return;
     }
@@ -438,6 +437,12 @@ struct bamg_hierarchy {
       if (Lv.P) {
         if (!Lv.P32) Lv.P32 = dalloc<zf>(Lv.n * 8);
         launch_convert(Lv.P, Lv.P32, Lv.n * 8, s);
+      }
+      if (coarsest(l) && L() > 1) {
+        if (Lv.n % 16 != 0 || dense_mm32_workspace_bytes((int)Lv.n, cap) > dense_mm_workspace((int)Lv.n, cap) * sizeof(zd))
+          throw HipFail("coarsest level: FP32 inverse needs n % 16 == 0 and the split-K workspace");
+        if (!Lv.Ainv32) Lv.Ainv32 = dalloc<zf>(Lv.n * Lv.n);
+        launch_convert(Lv.Ainv, Lv.Ainv32, Lv.n * Lv.n, s);
       }
       if (l >= 1 && !(coarsest(l) && L() > 1)) {
         switch (p.precision) {

@@ -384,6 +384,40 @@ def test_f32_operand_ops_match_mixed_ops(bamg, imported_mixed, l, nrhs):
     assert np.array_equal(host(xs64).astype(np.complex64), xs32.cpu().numpy())
 
 
+U32 = 2.0 ** -24  # unit roundoff of FP32
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 9, 17, 40, 70])
+def test_mixed_coarsest_solve_fp32_inverse(bamg, imported_mixed, nrhs):
+    """Op 12: the mixed cycle's coarsest solve with the FP32 copy of the
+    inverse, complex64 in and out.  nrhs <= 2: one wave per row with FP64 sums;
+    else the split-K MFMA product (8, 16, 32 and 64 right-hand sides per
+    work-group; 70 spans two groups).  Componentwise bounds: rounding the
+    inverse to FP32 costs u |A^-1| |b| (u = 2^-24); FP32 sums over the 2n real
+    products of a row add at most 2n u |A^-1| |b|."""
+    name, tol, N, U, m, h, o = imported_mixed
+    L = 2
+    n = bamg.bamg_level_info(h, L)["n"]
+    b = inputs.gaussian((nrhs, n), 190 + nrhs).astype(np.complex64)
+    x = torch.zeros(nrhs, n, dtype=torch.complex64, device="cuda:0")
+    bamg.bamg_level_op(h, L, bamg.OP_COARSEST_F32, torch.from_numpy(b).to("cuda:0"), x, nrhs)
+    xg = host(x).astype(np.complex128)
+    b64 = b.astype(np.complex128)
+    ref = o.coarsest_solve(b64, nrhs=nrhs).reshape(nrhs, n)
+    Ainv_abs = np.abs(np.linalg.inv(o.operator(L).toarray()))
+    scale = np.abs(b64) @ Ainv_abs.T  # (|A^-1| |b_r|)_i per right-hand side
+    k = 4 if nrhs <= 2 else 2 * n + 8
+    worst = (np.abs(xg - ref) / scale).max()
+    log(f"mixed {name} coarsest FP32 nrhs {nrhs}: normwise {rel(xg, ref):.2e}, "
+        f"componentwise {worst:.2e} (bound {k * U32:.1e})")
+    assert worst <= k * U32
+    assert rel(xg, ref) < 1e-4
+    if nrhs > 8:  # a column's result does not depend on the other columns of the product
+        x9 = torch.zeros(9, n, dtype=torch.complex64, device="cuda:0")
+        bamg.bamg_level_op(h, L, bamg.OP_COARSEST_F32, torch.from_numpy(b[:9].copy()).to("cuda:0"), x9, 9)
+        assert np.array_equal(host(x9), host(x)[:9])
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 def test_mixed_solve_reaches_fp64_accuracy(bamg, prec):
     """The FP64 outer FGMRES drives the true residual to 1e-10 whatever the
