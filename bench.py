@@ -5,11 +5,11 @@ Workload (default): 256 x 256 periodic lattice, quenched U(1) links from 500
 Metropolis sweeps at beta = 10 (seed 3), mass calibrated so that
 min |eig(D)| ~ 1e-4, one complex Gaussian right-hand side (seed 103); the
 hierarchy has 3 levels (4x4 then 2x2 aggregates, 8 test vectors, coarsest
-level of dimension 8192 solved with its dense inverse: computed in FP64, read
-as an FP32 copy by the mixed modes), FGMRES(32) to a
+level of dimension 8192 solved with its dense FP64 inverse), FGMRES(32) to a
 relative residual of 1e-10 on the reduced system.  The headline variant is
 mixed FP16 with a V(2,2) cycle and hipGraph replay; the other variants (FP64,
-V(4,4), BF16 and FP32 storage) are timed beside it.  Setup is done once and
+V(4,4), BF16 and FP32 storage, the FP32 copy of the coarsest inverse) are timed
+beside it.  Setup is done once and
 timed separately; every timed step is one full solve (reduction, FGMRES,
 reconstruction) with the right-hand side already in HBM.
 
@@ -50,12 +50,15 @@ def parse():
     ap.add_argument("--batch", default="8,32", help="right-hand sides per batched solve (comma list, '' for none)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--precisions",
-                    default="mixed_fp16+graphs+v22+bootV,fp64+graphs+v22+bootV,mixed_fp16+graphs+v22,"
+                    default="mixed_fp16+graphs+v22+bootV,mixed_fp16+graphs+v22+bootV+c32,fp64+graphs+v22+bootV,"
+                            "mixed_fp16+graphs+v22,"
                             "fp64+graphs+v22,mixed_fp16+graphs+v22+bootW,mixed_fp16+graphs,fp64+graphs,mixed_fp16,"
                             "mixed_bf16+graphs+v22,mixed_fp32+graphs+v22",
-                    help="single-RHS variants to time, <precision>[+graphs][+v22][+bootW|+bootV] (graphs: iterations "
-                         "replayed as hipGraphs; v22: V(2,2) cycle instead of V(4,4); bootW / bootV: bootstrap setup "
-                         "with the multigrid eigensolver, W or super-V cycles); the first one is the headline value")
+                    help="single-RHS variants to time, <precision>[+graphs][+v22][+bootW|+bootV][+c32] (graphs: "
+                         "iterations replayed as hipGraphs; v22: V(2,2) cycle instead of V(4,4); bootW / bootV: "
+                         "bootstrap setup with the multigrid eigensolver, W or super-V cycles; c32: the mixed cycle's "
+                         "coarsest solve reads an FP32 copy of the FP64 inverse); the first one is the headline value; "
+                         "the batched solves also run on the first +c32 variant")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
     ap.add_argument("--c4", type=int, default=1, help="time the 512^2 x 64 RHS batched solve (0: skip)")
@@ -69,9 +72,9 @@ COPY_MIB = 256
 
 
 def variant(spec):
-    """Solver parameters of a bench variant '<precision>[+graphs][+v22][+bootW|+bootV]'
+    """Solver parameters of a bench variant '<precision>[+graphs][+v22][+bootW|+bootV][+c32]'
     (bootW / bootV: bootstrap setup with the multigrid eigensolver, W or super-V
-    setup cycles)."""
+    setup cycles; c32: FP32 copy of the coarsest inverse in the mixed cycle)."""
     base, *opts = spec.split("+")
     kw = {"precision": PRECISIONS[base], "graphs": 1 if "graphs" in opts else 0}
     if "v22" in opts:
@@ -80,7 +83,9 @@ def variant(spec):
         kw.update(setup_mode=1)
     if "bootV" in opts:
         kw.update(setup_mode=2)
-    unknown = set(opts) - {"graphs", "v22", "bootW", "bootV"}
+    if "c32" in opts:
+        kw.update(coarsest_fp32=1)
+    unknown = set(opts) - {"graphs", "v22", "bootW", "bootV", "c32"}
     if unknown:
         raise SystemExit(f"bench.py: unknown variant option(s) {sorted(unknown)} in {spec!r}")
     return base, kw
@@ -284,7 +289,7 @@ def main():
     if args.roofline_only:
         p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], **head_kw)
         h = bamg.bamg_setup(U, w["m"], p)
-        dom, others = roofline(bamg, torch, h, head_base)
+        dom, others = roofline(bamg, torch, h, head_base, head_kw.get("coarsest_fp32", 0))
         out = {"workload": w["name"], "precision": head_base, "roofline": dom, "roofline_others": others,
                "copy_calibration": copy_calibration(torch)}
         bamg.bamg_free(h)
@@ -352,7 +357,7 @@ def main():
             "workload": w["name"], "N": N, "beta": w["beta"], "metropolis_sweeps": w["sweeps"],
             "m": w["m"], "min_abs_eig_D": w["min_abs_eig_D"], "levels": n_levels,
             "aggregates": "4x4 half-x, then 2x2", "test_vectors": 8, "cycle": r0["cycle"],
-            "coarsest": "dense inverse, FP64" if head_base == "fp64" else "dense inverse, FP64 built, FP32 applied",
+            "coarsest": "dense inverse, FP64" if not head_kw.get("coarsest_fp32") else "dense inverse, FP64 built, FP32 applied",
             "hipgraph": r0["graphs"], "setup": r0["setup"],
             "krylov": "FGMRES(32)", "tol": args.tol, "nrhs": 1, "precision": head_base, "variant": head,
         },
@@ -367,21 +372,24 @@ def main():
 
     # ---- batched solves: R right-hand sides per call, lockstep FGMRES
     batched = []
-    for R in [int(v) for v in args.batch.split(",") if v.strip()]:
-        B = torch.from_numpy(inputs.gaussian((R, 2 * N * N), w["rhs_seed"] + 1000)).to("cuda:0")
-        X = torch.zeros_like(B)
-        bamg.bamg_solve_batch(h, B, X, R, args.tol)
-        torch.cuda.synchronize()
-        tb0 = time.perf_counter()
-        for _ in range(args.batch_steps):
-            st, infs = bamg.bamg_solve_batch(h, B, X, R, args.tol)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - tb0) / args.batch_steps
-        batched.append({"nrhs": R, "precision": head, "solves_per_s": R / tb, "ms_per_batch": 1e3 * tb,
-                        "max_iters": max(i["iters"] for i in infs),
-                        "converged": all(i["relres_reduced"] <= args.tol for i in infs)})
-        del B, X
-        progress(f"batched R={R}: {batched[-1]['solves_per_s']:.1f} solves/s")
+    bvars = [head] + [q for q in precs if "c32" in q.split("+")[1:] and q != head][:1]
+    for bv in bvars:
+        hb = hier[bv]
+        for R in [int(v) for v in args.batch.split(",") if v.strip()]:
+            B = torch.from_numpy(inputs.gaussian((R, 2 * N * N), w["rhs_seed"] + 1000)).to("cuda:0")
+            X = torch.zeros_like(B)
+            bamg.bamg_solve_batch(hb, B, X, R, args.tol)
+            torch.cuda.synchronize()
+            tb0 = time.perf_counter()
+            for _ in range(args.batch_steps):
+                st, infs = bamg.bamg_solve_batch(hb, B, X, R, args.tol)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - tb0) / args.batch_steps
+            batched.append({"nrhs": R, "precision": bv, "solves_per_s": R / tb, "ms_per_batch": 1e3 * tb,
+                            "max_iters": max(i["iters"] for i in infs),
+                            "converged": all(i["relres_reduced"] <= args.tol for i in infs)})
+            del B, X
+            progress(f"batched {bv} R={R}: {batched[-1]['solves_per_s']:.1f} solves/s")
     if batched:
         out["batched"] = batched
 
@@ -411,7 +419,10 @@ def main():
 
     # ---- roofline of the dominant kernel of the solve
     if not args.no_roofline:
-        out["roofline"], out["roofline_others"] = roofline(bamg, torch, h, head_base)
+        out["roofline"], out["roofline_others"] = roofline(bamg, torch, h, head_base, head_kw.get("coarsest_fp32", 0))
+        if head_base != "fp64":
+            hm = next((hier[q] for q in precs if "c32" in q.split("+")[1:]), h)
+            out["mfma"] = mfma_utilisation(bamg, torch, hm)
         progress("roofline")
 
     # ---- CPU oracle on a bounded sample of the same workload
@@ -462,7 +473,10 @@ PMC_TRAFFIC = {
                                "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE},
     ("dense", "mixed_fp16"): {"src": "dense.hip",
                               "sha256": "2b3837a67c198d055924253ea7b62e9d0fafaa1f6fed9a31a26ab11b32b1ea62",
-                              "fetch_kib": 262622.75, "write_kib": 74.5, **COPY_SCALE},
+                              "fetch_kib": 524814.5, "write_kib": 128.0, **COPY_SCALE},
+    ("dense32", "mixed_fp16"): {"src": "dense.hip",
+                                "sha256": "2b3837a67c198d055924253ea7b62e9d0fafaa1f6fed9a31a26ab11b32b1ea62",
+                                "fetch_kib": 262618.0, "write_kib": 75.0, **COPY_SCALE},
 }
 
 
@@ -484,15 +498,16 @@ def _roof(kname, kind, prec, bytes_launch, t):
             "avg_launch_us": t * 1e6, "bytes_per_launch": bytes_launch}
 
 
-def roofline(bamg, torch, h, prec):
+def roofline(bamg, torch, h, prec, c32=0):
     """The three kernels that take the solve's time, each timed with HIP events
     on the library's stream (torch's current stream) over back-to-back
     launches driven through the level hooks: the fine colour pass (the
     largest share; 16 launches per sweep), the coarse colour pass on level 1
     (ncol launches per sweep) and the coarsest dense product (one launch per
     call).  A mixed hierarchy is driven through the complex64 hooks, which
-    launch exactly the colour passes of one sweep and nothing else.  Returns
-    (dominant, [others])."""
+    launch exactly the colour passes of one sweep and nothing else.  The
+    coarsest product is the FP64 inverse's (op 4) or, with c32, its FP32
+    copy's (op 12).  Returns (dominant, [others])."""
     mixed = prec != "fp64"
     dt = torch.complex64 if mixed else torch.complex128
     sweep = bamg.OP_SWEEP_F32 if mixed else bamg.OP_SWEEP
@@ -516,17 +531,58 @@ def roofline(bamg, torch, h, prec):
         t = time_launches(lambda: bamg.bamg_level_op(h, 1, sweep, bb, xb, 1), 50, ncol, torch)
         out.append(_roof(f"k_kaczmarz_coarse<{tname},{sname}> (level 1, {ns // ncol} sites per launch)", "coarse",
                          prec, ns // ncol * coarse_site_bytes(OP_BYTES[prec], VEC_BYTES[prec]), t))
-    if L > 1:  # coarsest product: the FP32 copy of the inverse in the mixed modes
+    if L > 1:  # coarsest product
         inf = bamg.bamg_level_info(h, L - 1)
         n = inf["n"]
-        xb = torch.zeros(n, dtype=dt, device="cuda:0")
-        bb = torch.ones(n, dtype=dt, device="cuda:0")
-        op = bamg.OP_COARSEST_F32 if mixed else bamg.OP_COARSEST
+        cdt = torch.complex64 if c32 else torch.complex128
+        xb = torch.zeros(n, dtype=cdt, device="cuda:0")
+        bb = torch.ones(n, dtype=cdt, device="cuda:0")
+        op = bamg.OP_COARSEST_F32 if c32 else bamg.OP_COARSEST
         t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, op, bb, xb, 1), 20, 1, torch)
-        z = 8.0 if mixed else 16.0
-        out.append(_roof(f"k_dense_mv{'32' if mixed else ''} (coarsest inverse, n = {n})", "dense", prec,
-                         z * n * n + 2 * z * n, t))
+        z = 8.0 if c32 else 16.0
+        out.append(_roof(f"k_dense_mv{'32' if c32 else ''} (coarsest inverse, n = {n})",
+                         "dense32" if c32 else "dense", prec, z * n * n + 2 * z * n, t))
     return out[0], out[1:]
+
+
+MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix peak of the MI355X
+
+
+def mfma_utilisation(bamg, torch, h, R=32):
+    """Achieved FP32 matrix-core rate of the MFMA kernels of the batched solve
+    at R right-hand sides, timed with HIP events like the roofline kernels:
+    - the coarse block-stencil smoother k_kaczmarz_coarse_mfma on level 1
+      (per site and 16 right-hand sides 240 v_mfma_f32_16x16x4f32 of 2048 flops:
+      residual 112, Kinv step 16, update 112), one launch per colour;
+    - with an FP32 copy of the coarsest inverse (op 12), the split-K product
+      k_dense_mm32 (8 n^2 R flops; the call's small reduction launch is
+      included in its time)."""
+    out = []
+    L = bamg.bamg_n_levels(h)
+    if L > 2:
+        inf = bamg.bamg_level_info(h, 1)
+        ns, ncol, n = inf["ex"] * inf["ey"], inf["colours"], inf["n"]
+        xb = torch.zeros(R, n, dtype=torch.complex64, device="cuda:0")
+        bb = torch.ones(R, n, dtype=torch.complex64, device="cuda:0")
+        t = time_launches(lambda: bamg.bamg_level_op(h, 1, bamg.OP_SWEEP_F32, bb, xb, R), 20, ncol, torch)
+        fl = (ns // ncol) * ((R + 15) // 16) * 240 * 2048.0
+        out.append({"kernel": f"k_kaczmarz_coarse_mfma (level 1, {ns // ncol} sites x {R} RHS per launch)",
+                    "flops_per_launch": fl, "avg_launch_us": 1e6 * t, "achieved_tflops": fl / t / 1e12,
+                    "peak_tflops": MFMA_F32_PEAK_TFLOPS, "frac": fl / t / 1e12 / MFMA_F32_PEAK_TFLOPS})
+    p = bamg.bamg_level_info(h, L - 1) if L > 1 else None
+    if p is not None:
+        n = p["n"]
+        xb = torch.zeros(R, n, dtype=torch.complex64, device="cuda:0")
+        bb = torch.ones(R, n, dtype=torch.complex64, device="cuda:0")
+        try:
+            t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, bamg.OP_COARSEST_F32, bb, xb, R), 10, 1, torch)
+        except bamg.BamgError:  # no FP32 copy of the coarsest inverse on this hierarchy
+            return out
+        fl = 8.0 * n * n * R
+        out.append({"kernel": f"k_dense_mm32 (coarsest inverse, n = {n}, {R} RHS)", "flops_per_launch": fl,
+                    "avg_launch_us": 1e6 * t, "achieved_tflops": fl / t / 1e12, "peak_tflops": MFMA_F32_PEAK_TFLOPS,
+                    "frac": fl / t / 1e12 / MFMA_F32_PEAK_TFLOPS})
+    return out
 
 
 def cpu_baseline(w, U_np, tol):

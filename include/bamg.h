@@ -66,7 +66,8 @@ typedef enum { BAMG_CYCLE_V = 0, BAMG_CYCLE_W = 1 } bamg_cycle;
 
 typedef enum {
   BAMG_FP64 = 0,        /* everything in FP64 */
-  BAMG_MIXED_FP16 = 1,  /* FP64 outer FGMRES + coarsest solve; FP32 cycle; coarse operators stored FP16 */
+  BAMG_MIXED_FP16 = 1,  /* FP64 outer FGMRES + coarsest solve (see coarsest_fp32); FP32 cycle; coarse
+                           operators stored FP16 */
   BAMG_MIXED_BF16 = 2,  /* as above with BF16 storage */
   BAMG_MIXED_FP32 = 3   /* as above with FP32 storage */
 } bamg_precision;
@@ -96,6 +97,10 @@ typedef struct {
                            2: the same with super-V cycles, boot_nu 2^l sweeps on level l (Sec. 4.2) */
   int32_t n_ev;         /* k_e eigenvector approximations of the bootstrap modes (1..8, default 8) */
   int32_t boot_nu1, boot_nu2; /* sweeps of the two bootstrap setup cycles (default 10, 5) */
+  int32_t coarsest_fp32; /* mixed precisions only.  0 (default): the cycle's coarsest solve applies the
+                           FP64 inverse (FP64 in and out).  1: it reads an FP32 copy of that inverse
+                           (rounded to nearest), FP32 in and out: half the bytes of the dominant read,
+                           relative rounding 2^-24 per entry */
 } bamg_params;
 
 typedef struct {
@@ -158,9 +163,9 @@ int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *
  *         are complex64 (interleaved float) arrays used as they are, with no
  *         conversion launches: exactly the kernels of one FP32 apply or sweep
  *   op 12 BAMG_OP_COARSEST_F32: out = A_L^-1 in with complex64 in and out
- *         (l the coarsest level), read from the FP32 copy of the inverse that
- *         the mixed cycle uses: one product launch for nrhs <= 2, else the
- *         split-K product on the matrix cores and its reduction
+ *         (l the coarsest level, coarsest_fp32 = 1), read from the FP32 copy of
+ *         the inverse that the mixed cycle then uses: one product launch for
+ *         nrhs <= 2, else the split-K product on the matrix cores and its reduction
  * Ops 4 and 12 require in and out not to alias.
  * Level 0 is the fine reduced system (A_0 = Dhat). */
 enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLONG = 3,
@@ -202,7 +207,12 @@ int bamg_export_level(const bamg_hierarchy *h, int32_t l, void *P_host, void *Dl
  * importing them in order. */
 int bamg_import_level(bamg_hierarchy *h, int32_t l, const void *P_host, const void *Dl_host);
 
-/* Device bytes a hierarchy with parameters p (and one right-hand side) needs. */
+/* Device bytes a hierarchy with parameters p holds after bamg_setup and a first
+ * single-RHS solve: every level's data and work vectors (sized for the setup's
+ * n_tv + n_ev test vectors), the FP32 copies of the mixed modes, the coarsest
+ * inverse with its scratch, the bootstrap eigensolver's blocks and the FGMRES
+ * workspace of one right-hand side.  0 for invalid parameters.  Batched solves
+ * add workspace per right-hand side. */
 size_t bamg_footprint_bytes(const bamg_params *p);
 
 /* k test vectors from the Philox4x32-10 generator (as used by setup):

@@ -44,7 +44,7 @@ class bamg_params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("init_tv_host", ctypes.c_void_p), ("stream", ctypes.c_void_p),
         ("graphs", ctypes.c_int32), ("setup_mode", ctypes.c_int32), ("n_ev", ctypes.c_int32),
-        ("boot_nu1", ctypes.c_int32), ("boot_nu2", ctypes.c_int32),
+        ("boot_nu1", ctypes.c_int32), ("boot_nu2", ctypes.c_int32), ("coarsest_fp32", ctypes.c_int32),
     ]
 
 

@@ -76,6 +76,8 @@ bool valid_params(const bamg_params* p, std::string& why) {
   if (p->setup_mode < 0 || p->setup_mode > 2) { why = "setup_mode must be 0, 1 or 2"; return false; }
   if (p->setup_mode && (p->n_ev < 1 || p->n_ev > 8)) { why = "n_ev must be in [1, 8]"; return false; }
   if (p->setup_mode && (p->boot_nu1 < 0 || p->boot_nu2 < 0)) { why = "negative bootstrap sweep count"; return false; }
+  if (p->coarsest_fp32 != 0 && p->coarsest_fp32 != 1) { why = "coarsest_fp32 must be 0 or 1"; return false; }
+  if (p->coarsest_fp32 && p->precision == BAMG_FP64) { why = "coarsest_fp32 needs a mixed precision"; return false; }
   return true;
 }
 
@@ -111,6 +113,7 @@ int bamg_default_params(bamg_params* p) {
   p->n_ev = 8;
   p->boot_nu1 = 10;
   p->boot_nu2 = 5;
+  p->coarsest_fp32 = 0;
   return BAMG_OK;
 }
 
@@ -119,20 +122,34 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
   Shape sh;
   if (!valid_params(p, why) || !level_shapes(p, sh, why)) return 0;
   const size_t N = p->N, k = p->n_tv, z = sizeof(zd);
-  size_t bytes = 2 * N * N * z + (N * N / 2) * 36 * z;  // links, stored slot blocks of Dhat
   const int L = (int)sh.ext.size();
+  const bool mg = L > 1, mixed = p->precision != BAMG_FP64;
+  const size_t ne = (mg && p->setup_mode) ? p->n_ev : 0;
+  const size_t cap = mg ? k + ne : 1;  // right-hand sides of the level work vectors after setup
+  const size_t zm = z + (mixed ? sizeof(zf) : 0);  // an entry and its FP32 copy in the mixed modes
+  const size_t zc = z + (mixed && p->coarsest_fp32 ? sizeof(zf) : 0);  // entry of the coarsest inverse
+  const size_t sst = p->precision == BAMG_MIXED_FP32 ? sizeof(zf) : sizeof(hcx);  // stored coarse operator entry
+  size_t bytes = (2 * N * N + (N * N / 2) * 36) * zm;  // links, stored slot blocks of Dhat
   for (int l = 0; l < L; ++l) {
     const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
     const size_t n = ns * (l == 0 ? 2 : 16);
-    if (L == 1) { bytes += 3 * n * z; break; }  // operator only
-    bytes += (3 + k) * n * z;  // work vectors + test vectors
-    if (l >= 1) bytes += ns * NOFF * 256 * z;
-    if (l >= 1 && l < L - 1) bytes += ns * 256 * z;
-    if (l < L - 1) bytes += n * 8 * z;  // P
-    if (l == L - 1) bytes += n * n * z;
+    const bool last = l == L - 1;
+    bytes += 3 * n * cap * zm;  // x, b, r
+    if (!mg) break;
+    bytes += n * (k + ne) * z;  // test vectors
+    if (l >= 1) bytes += ns * NOFF * 256 * z;  // coarse operator
+    if (l >= 1 && !last) bytes += ns * 256 * zm + (mixed ? ns * NOFF * 256 * sst : 0);  // Kinv; stored operator
+    if (!last) bytes += n * 8 * zm;  // P
+    if (last)  // inverse, split-K partials, inversion scratch
+      bytes += n * n * zc + (dense_mm_workspace((int)n, (int)cap) + gj_workspace((int)n)) * z + n * sizeof(int);
   }
   const size_t n0 = N * N, kd = p->restart;
-  bytes += (2 * kd + 5) * n0 * z + n0 * k * z;
+  bytes += (2 * kd + 5) * n0 * z;  // FGMRES bases and vectors, one right-hand side
+  if (mg) bytes += n0 * k * z;     // saved test vectors
+  if (ne) {                        // eigensolver blocks
+    const size_t nL = (size_t)sh.ext[L - 1].first * sh.ext[L - 1].second * 16, pc = std::min<size_t>(16, nL);
+    bytes += (4 * nL * pc + 2 * pc * pc + dense_mm_workspace((int)nL, (int)pc)) * z;
+  }
   return bytes;
 }
 
@@ -142,14 +159,17 @@ size_t bamg::hierarchy_slot_extra_bytes(const bamg_params* p, int slots) {
   std::string why;
   Shape sh;
   if (!valid_params(p, why) || !level_shapes(p, sh, why) || slots < 1) return 0;
-  const size_t S = slots;
-  size_t bytes = 0;
   const int L = (int)sh.ext.size();
+  const size_t cap = L > 1 ? p->n_tv + (p->setup_mode ? p->n_ev : 0) : 1;  // as counted by the footprint
+  const size_t S = slots;
+  if (S <= cap) return 0;
+  const size_t zm = sizeof(zd) + (p->precision != BAMG_FP64 ? sizeof(zf) : 0);
+  size_t bytes = 0;
   for (int l = 0; l < L; ++l) {
     const size_t n = (size_t)sh.ext[l].first * sh.ext[l].second * (l == 0 ? 2 : 16);
-    bytes += 3 * n * (S - 1) * sizeof(zd);
-    if (p->precision != BAMG_FP64) bytes += 3 * n * S * sizeof(zf);
-    if (l == L - 1 && L > 1) bytes += dense_mm_workspace((int)n, slots) * sizeof(zd);
+    bytes += 3 * n * (S - cap) * zm;  // the level work vectors grow to S right-hand sides
+    if (l == L - 1 && L > 1)
+      bytes += (dense_mm_workspace((int)n, slots) - dense_mm_workspace((int)n, (int)cap)) * sizeof(zd);
   }
   return bytes;
 }
@@ -324,7 +344,7 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         h->coarsest_solve(xi, xo, nrhs);
         break;
       case BAMG_OP_COARSEST_F32: {
-        if (!h->mixed()) return fail(BAMG_EINVAL, "hierarchy is FP64");
+        if (!h->c32()) return fail(BAMG_EINVAL, "no FP32 copy of the coarsest inverse (coarsest_fp32 = 0)");
         if (!h->coarsest(l) || h->L() == 1) return fail(BAMG_EINVAL, "level is not a directly solved coarsest level");
         if (in == out) return fail(BAMG_EINVAL, "in and out must not alias");
         h->ensure_cap(nrhs);

@@ -244,6 +244,7 @@ struct bamg_hierarchy {
   bool coarsest(int l) const { return l == L() - 1; }
 
   bool mixed() const { return p.precision != BAMG_FP64; }
+  bool c32() const { return mixed() && p.coarsest_fp32; }
 
   void ensure_cap(int nrhs) {
     if (nrhs <= cap) return;
@@ -328,7 +329,8 @@ struct bamg_hierarchy {
   // ------------------------------------------------ mixed-precision cycle
   // The preconditioner of the mixed modes: the same cycle in FP32 with the
   // coarse operators read from their reduced-precision copies and the
-  // coarsest level solved with the FP32 copy of the inverse (FP32 in and out).
+  // coarsest level solved with the FP64 inverse (FP64 in and out) or, with
+  // coarsest_fp32, with its FP32 copy (FP32 in and out).
   template <typename S>
   CoarseT<float, S> coarse32(int l) const {
     CoarseT<float, S> c;
@@ -363,7 +365,13 @@ struct bamg_hierarchy {
     if (coarsest(l)) {
       Level& C = lv[l];
       if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
-      launch_dense_mv32(C.Ainv32, (int)C.n, b, x, nrhs, force_mr, (zf*)mmwork, s);
+      if (c32()) {
+        launch_dense_mv32(C.Ainv32, (int)C.n, b, x, nrhs, force_mr, (zf*)mmwork, s);
+      } else {
+        launch_convert(b, C.b, C.n * nrhs, s);
+        launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, force_mr, mmwork, s);
+        launch_convert(C.x, x, C.n * nrhs, s);
+      }
       check_launch();
       return;
     }
@@ -438,7 +446,7 @@ struct bamg_hierarchy {
         if (!Lv.P32) Lv.P32 = dalloc<zf>(Lv.n * 8);
         launch_convert(Lv.P, Lv.P32, Lv.n * 8, s);
       }
-      if (coarsest(l) && L() > 1) {
+      if (coarsest(l) && L() > 1 && c32()) {
         if (Lv.n % 16 != 0 || dense_mm32_workspace_bytes((int)Lv.n, cap) > dense_mm_workspace((int)Lv.n, cap) * sizeof(zd))
           throw HipFail("coarsest level: FP32 inverse needs n % 16 == 0 and the split-K workspace");
         if (!Lv.Ainv32) Lv.Ainv32 = dalloc<zf>(Lv.n * Lv.n);

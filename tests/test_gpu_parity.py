@@ -336,7 +336,7 @@ def imported_mixed(bamg, request):
     U = inputs.gauge_metropolis(N, 3.0, 40, 5)
     m = -0.05
     kw = dict(n_levels=3, max_coarse=512, setup_sweeps=2, setup_adapt=0)
-    h = make_h(bamg, U, m, precision=prec, **kw)
+    h = make_h(bamg, U, m, precision=prec, coarsest_fp32=1, **kw)
     o = oracle.Hierarchy(U, m, **kw)
     for l in range(2):
         P = _random_P(o.P_blocks(l).shape, 100 + l)
@@ -390,7 +390,7 @@ U32 = 2.0 ** -24  # unit roundoff of FP32
 @pytest.mark.parametrize("nrhs", [1, 2, 3, 9, 17, 40, 70])
 def test_mixed_coarsest_solve_fp32_inverse(bamg, imported_mixed, nrhs):
     """Op 12: the mixed cycle's coarsest solve with the FP32 copy of the
-    inverse, complex64 in and out.  nrhs <= 2: one wave per row with FP64 sums;
+    inverse (coarsest_fp32 = 1), complex64 in and out.  nrhs <= 2: one wave per row with FP64 sums;
     else the split-K MFMA product (8, 16, 32 and 64 right-hand sides per
     work-group; 70 spans two groups).  Componentwise bounds: rounding the
     inverse to FP32 costs u |A^-1| |b| (u = 2^-24); FP32 sums over the 2n real
@@ -418,16 +418,29 @@ def test_mixed_coarsest_solve_fp32_inverse(bamg, imported_mixed, nrhs):
         assert np.array_equal(host(x9), host(x)[:9])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
-def test_mixed_solve_reaches_fp64_accuracy(bamg, prec):
+def test_fp32_coarsest_needs_the_copy(bamg):
+    U = inputs.gauge_random(32, 17)
+    h = make_h(bamg, U, -0.05, n_levels=2, setup_sweeps=1, setup_adapt=0, precision=1)
+    n = bamg.bamg_level_info(h, 1)["n"]
+    x = torch.zeros(n, dtype=torch.complex64, device="cuda:0")
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.bamg_level_op(h, 1, bamg.OP_COARSEST_F32, torch.ones_like(x), x, 1)
+    assert e.value.status == bamg.BAMG_EINVAL
+    with pytest.raises(bamg.BamgError):
+        make_h(bamg, U, -0.05, n_levels=2, coarsest_fp32=1)  # FP64 hierarchy
+
+
+@pytest.mark.parametrize("prec,c32", [("fp32", 0), ("fp16", 0), ("bf16", 0), ("fp16", 1), ("bf16", 1)])
+def test_mixed_solve_reaches_fp64_accuracy(bamg, prec, c32):
     """The FP64 outer FGMRES drives the true residual to 1e-10 whatever the
-    precision of the preconditioner; the solution agrees with the FP64
-    oracle's to the conditioning of the problem."""
+    precision of the preconditioner (c32: the cycle's coarsest solve reads the
+    FP32 copy of the inverse); the solution agrees with the FP64 oracle's to
+    the conditioning of the problem."""
     w = inputs.workload("c2_128_b6")
     U = inputs.load_gauge(w)
     N = w["N"]
     tv = oracle.gaussian_tv(N, 8, w["tv_seed"])
-    h = make_h(bamg, U, w["m"], n_levels=w["n_levels"], init_tv=tv, precision=MIXED[prec][0])
+    h = make_h(bamg, U, w["m"], n_levels=w["n_levels"], init_tv=tv, precision=MIXED[prec][0], coarsest_fp32=c32)
     b = inputs.gaussian(2 * N * N, w["rhs_seed"])
     x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
     st, info = bamg.bamg_solve(h, dev(b), x, 1e-10)
@@ -436,18 +449,20 @@ def test_mixed_solve_reaches_fp64_accuracy(bamg, prec):
     sto, xo, io = o.solve(b, tol=1e-10)
     full = np.linalg.norm(b - oracle.wilson_apply(U, w["m"], xg)) / np.linalg.norm(b)
     dx = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    log(f"mixed {prec} solve: iters {info['iters']} (fp64 oracle {io['iters']}), full relres {full:.2e}, "
+    log(f"mixed {prec} (coarsest fp32 {c32}) solve: iters {info['iters']} (fp64 oracle {io['iters']}), "
+        f"full relres {full:.2e}, "
         f"|x - x_fp64|/|x| {dx:.2e}")
     assert st == 0 and info["relres_reduced"] <= 1e-10
     assert full < 2e-10 and dx < 1e-7
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_mixed_batch_results_do_not_depend_on_the_batch(bamg, prec):
+@pytest.mark.parametrize("prec,c32", [("fp16", 0), ("bf16", 0), ("fp16", 1)])
+def test_mixed_batch_results_do_not_depend_on_the_batch(bamg, prec, c32):
     w = inputs.workload("c1_32_b3")
     U = inputs.load_gauge(w)
     N = w["N"]
-    h = make_h(bamg, U, w["m"], n_levels=w["n_levels"], precision=MIXED[prec][0], seed=w["tv_seed"])
+    h = make_h(bamg, U, w["m"], n_levels=w["n_levels"], precision=MIXED[prec][0], seed=w["tv_seed"],
+               coarsest_fp32=c32)
     R = 19
     B = inputs.gaussian((R, 2 * N * N), 777)
     B[2] *= 1e4

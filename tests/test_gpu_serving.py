@@ -3,7 +3,8 @@ gauge fields join and leave the running batch; every right-hand side's result
 must be bitwise the one it gets alone (the slot engine treats right-hand sides
 independently with fixed reduction orders), and correct against the Wilson
 operator.  Memory admission and eviction, and per-request failures, are
-checked through the statistics and statuses."""
+checked through the statistics and statuses; the footprint estimate that
+admission uses is checked against what a setup allocates on the device."""
 import numpy as np
 import pytest
 
@@ -238,3 +239,33 @@ def test_non_finite_request_fails_alone(bamg, fields):
     assert res[r1][0] == bamg.BAMG_EINVAL
     assert res[r2][0] == 0 and res[r2][1][0]["relres_reduced"] <= TOL
     bamg.bamg_server_free(srv)
+
+
+@pytest.mark.parametrize("kw", [dict(precision=0), dict(precision=1), dict(precision=1, setup_mode=2, n_ev=8)],
+                         ids=["fp64", "mixed_fp16", "mixed_fp16_bootV"])
+def test_footprint_matches_device_allocation(bamg, kw):
+    """bamg_footprint_bytes against the device memory a 256^2 setup and one
+    solve (3 levels, coarsest n = 8192: 1 GiB FP64 inverse, 0.5 GiB FP32 copy)
+    take, and bamg_free gives all of it back."""
+    warm = bamg.bamg_setup(dev(inputs.gauge_random(32, 40)), -0.05,
+                           bamg.bamg_default_params(N=32, setup_sweeps=1, setup_adapt=0, **kw))
+    bamg.bamg_free(warm)  # code objects and runtime state are loaded before the measurement
+    N = 256
+    U = dev(inputs.gauge_random(N, 41))
+    b = dev(inputs.gaussian(2 * N * N, 42))
+    x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    p = bamg.bamg_default_params(N=N, setup_sweeps=1, setup_adapt=0, **kw)
+    h = bamg.bamg_setup(U, -0.05, p)
+    st, _ = bamg.bamg_solve(h, b, x, 1e-8)
+    assert st == 0
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    fp = bamg.bamg_footprint_bytes(p)
+    bamg.bamg_free(h)
+    torch.cuda.synchronize()
+    left = free0 - torch.cuda.mem_get_info()[0]
+    log(f"footprint {fp / 2**20:.1f} MiB, allocated {used / 2**20:.1f} MiB, after free {left / 2**20:.1f} MiB")
+    assert abs(used - fp) <= 0.01 * fp + 8 * 2**20
+    assert abs(left) <= 8 * 2**20
