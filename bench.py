@@ -246,15 +246,16 @@ def c4_batched(bamg, inputs, torch, tol, kw, reps=2):
 
 
 def dhat_bandwidth(bamg, inputs, torch, N, nrhs, reps):
-    """GB/s of the Dhat kernel: 64 N^2 bytes per right-hand side per apply
-    (x and y 16 N^2 each, links 32 N^2), algorithmic; operator-only handle."""
+    """GB/s of the FP64 Dhat kernel from its compulsory bytes per apply: x read
+    and y written for every right-hand side (16 N^2 each) and the links read
+    once (32 N^2), (32 R + 32) N^2 in all; operator-only handle."""
     U = torch.from_numpy(inputs.gauge_random(N, 77)).to("cuda:0")
     p = bamg.bamg_default_params(N=N, n_levels=1)
     h = bamg.bamg_setup(U, -0.05, p)
     x = torch.from_numpy(inputs.gaussian((nrhs, N * N), 78)).to("cuda:0")
     y = torch.empty_like(x)
     t = time_launches(lambda: bamg.bamg_apply_dhat(h, x, y, nrhs), reps, 1, torch)
-    bytes_ = 64.0 * N * N * nrhs
+    bytes_ = (32.0 * nrhs + 32.0) * N * N
     bamg.bamg_free(h)
     del x, y, U
     torch.cuda.empty_cache()

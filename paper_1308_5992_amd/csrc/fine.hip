@@ -186,9 +186,128 @@ __global__ __launch_bounds__(TX* TY) void k_dhat(FineT<T> f, const cx<T>* __rest
   yv[2 * e + 1] = r1;
 }
 
+// The same operator for lattices with many tiles: 32 x 16 even sites per
+// work-group of 256 threads, right-hand sides looped inside the work-group
+// (grid.z splits them into groups), each thread's links and neighbour
+// indices loaded once into registers and reused for every right-hand side,
+// the odd intermediate double-buffered in LDS (one barrier per right-hand
+// side), and each output's own entries loaded before that barrier.  The
+// arithmetic is that of k_dhat, term by term.
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(256) void k_dhat_tile(FineT<T> f, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                   const cx<T>* __restrict__ b, int rpg, int nrhs) {
+  using C = cx<T>;
+  constexpr int NT = 256, W = TX + 2, NREG = (TY + 2) * W;
+  constexpr int Q1 = (NREG + NT - 1) / NT, Q2 = TX * TY / NT;
+  static_assert(TX * TY % NT == 0, "outputs per thread");
+  __shared__ C t0[2][NREG], t1[2][NREG];
+  const int N = f.N, NH = f.NH;
+  const size_t n = (size_t)N * NH * 2;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int tid = threadIdx.x;
+  const C* __restrict__ Ue = f.Ue;
+  const C* __restrict__ Uo = f.Uo;
+  // odd sites of the tile and its one-site halo: neighbours and links
+  int j1[Q1][4];
+  C l1[Q1][4];
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) {
+    const int q = min(tid + NT * i, NREG - 1);
+    const int cy = q / W, cxh = q - cy * W;
+    const int yy = wrapn(y0 - 1 + cy, N), xhh = wrapn(x0 - 1 + cxh, NH);
+    const int lx = 2 * xhh + 1 - (yy & 1);
+    const int w = yy * NH + xhh;
+    j1[i][0] = hidx(lx + 1, yy, N, NH);
+    j1[i][1] = hidx(lx - 1, yy, N, NH);
+    j1[i][2] = hidx(lx, yy + 1, N, NH);
+    j1[i][3] = hidx(lx, yy - 1, N, NH);
+    l1[i][0] = Uo[2 * w];
+    l1[i][1] = conj(Ue[2 * j1[i][1]]);
+    l1[i][2] = Uo[2 * w + 1];
+    l1[i][3] = conj(Ue[2 * j1[i][3] + 1]);
+  }
+  // even outputs: LDS slots of the four odd neighbours and links
+  int e2[Q2], s2[Q2][4];
+  C l2[Q2][4];
+#pragma unroll
+  for (int k = 0; k < Q2; ++k) {
+    const int o = tid + NT * k;
+    const int ly = o / TX, lxh = o - ly * TX;
+    const int yy = y0 + ly, xhh = x0 + lxh, p = yy & 1;
+    const int e = yy * NH + xhh;
+    e2[k] = e;
+    s2[k][0] = (ly + 1) * W + lxh + 1 + p;
+    s2[k][1] = (ly + 1) * W + lxh + p;
+    s2[k][2] = (ly + 2) * W + lxh + 1;
+    s2[k][3] = ly * W + lxh + 1;
+    const int omx = yy * NH + wrapn(xhh + p - 1, NH), omy = wrapn(yy - 1, N) * NH + xhh;
+    l2[k][0] = Ue[2 * e];
+    l2[k][1] = conj(Uo[2 * omx]);
+    l2[k][2] = Ue[2 * e + 1];
+    l2[k][3] = conj(Uo[2 * omy + 1]);
+  }
+  const T k2q = (T)(0.25 * f.kappa2);
+  const int rbeg = blockIdx.z * rpg, rend = min(nrhs, rbeg + rpg);
+  for (int r = rbeg; r < rend; ++r) {
+    const int bb = (r - rbeg) & 1;
+    const C* __restrict__ xv = x + (size_t)r * n;
+#pragma unroll
+    for (int i = 0; i < Q1; ++i) {
+      const int q = tid + NT * i;
+      if (q < NREG) {
+        C a0 = {0, 0}, a1 = {0, 0};
+        hop_acc(0, l1[i][0], xv[2 * j1[i][0]], xv[2 * j1[i][0] + 1], a0, a1);
+        hop_acc(1, l1[i][1], xv[2 * j1[i][1]], xv[2 * j1[i][1] + 1], a0, a1);
+        hop_acc(2, l1[i][2], xv[2 * j1[i][2]], xv[2 * j1[i][2] + 1], a0, a1);
+        hop_acc(3, l1[i][3], xv[2 * j1[i][3]], xv[2 * j1[i][3] + 1], a0, a1);
+        t0[bb][q] = a0;
+        t1[bb][q] = a1;
+      }
+    }
+    C xe[Q2][2], be[Q2][2];
+#pragma unroll
+    for (int k = 0; k < Q2; ++k) {
+      xe[k][0] = xv[2 * e2[k]];
+      xe[k][1] = xv[2 * e2[k] + 1];
+      if (b) {
+        be[k][0] = b[(size_t)r * n + 2 * e2[k]];
+        be[k][1] = b[(size_t)r * n + 2 * e2[k] + 1];
+      }
+    }
+    __syncthreads();
+    C* __restrict__ yv = y + (size_t)r * n;
+#pragma unroll
+    for (int k = 0; k < Q2; ++k) {
+      C a0 = {0, 0}, a1 = {0, 0};
+      hop_acc(0, l2[k][0], t0[bb][s2[k][0]], t1[bb][s2[k][0]], a0, a1);
+      hop_acc(1, l2[k][1], t0[bb][s2[k][1]], t1[bb][s2[k][1]], a0, a1);
+      hop_acc(2, l2[k][2], t0[bb][s2[k][2]], t1[bb][s2[k][2]], a0, a1);
+      hop_acc(3, l2[k][3], t0[bb][s2[k][3]], t1[bb][s2[k][3]], a0, a1);
+      C r0 = xe[k][0] - k2q * a0, r1 = xe[k][1] - k2q * a1;
+      if (b) {
+        r0 = be[k][0] - r0;
+        r1 = be[k][1] - r1;
+      }
+      yv[2 * e2[k]] = r0;
+      yv[2 * e2[k] + 1] = r1;
+    }
+  }
+}
+
 template <typename T>
 void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s) {
   const int N = f.N, NH = f.NH;
+  constexpr int TTX = 32, TTY = 16;
+  if (NH % TTX == 0 && N % TTY == 0) {
+    const int tiles = (NH / TTX) * (N / TTY);
+    if (tiles >= 256) {  // enough work-groups without splitting the lattice finer
+      const int groups = std::max(1, std::min(nrhs, (1024 + tiles - 1) / tiles));
+      const int rpg = (nrhs + groups - 1) / groups;
+      const dim3 g(NH / TTX, N / TTY, (nrhs + rpg - 1) / rpg);
+      hipLaunchKernelGGL((k_dhat_tile<T, TTX, TTY>), g, dim3(256), 0, s, f, x, y, b, rpg, nrhs);
+      return;
+    }
+  }
   dim3 g;
 #define DHAT_CASE(TX)                                                                     \
   if (NH % TX == 0) {                                                                     \

@@ -48,8 +48,10 @@ def make_h(bamg, U, m, **kw):
 
 
 # ---------------------------------------------------------------- fine level
-@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (128, 3), (256, 1)])
+@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (128, 3), (256, 1), (512, 1), (512, 5)])
 def test_dhat_apply(bamg, N, nrhs):
+    """N <= 256: tiles of 64 x 4 sites; N = 512: 32 x 16 tiles with the
+    right-hand sides looped inside the work-group (5 in 4 groups: 2, 2, 1)."""
     log(f"dhat N={N} nrhs={nrhs}")
     U = inputs.gauge_random(N, 10 + N)
     m = -0.07
@@ -59,6 +61,23 @@ def test_dhat_apply(bamg, N, nrhs):
     bamg.bamg_apply_dhat(h, dev(x), y, nrhs)
     ref = oracle.dhat_apply(U, m, x).reshape(nrhs, N * N)
     assert rel(host(y), ref) < 1e-13
+
+
+@pytest.mark.parametrize("N,nrhs", [(128, 2), (512, 3)])
+def test_dhat_apply_fp32(bamg, N, nrhs):
+    """The FP32 operator of the mixed cycle (level op 10 on level 0, FP32 links
+    rounded from FP64) against the FP64 oracle: within a few FP32 roundings of
+    the 9-term sums (|Dhat| |x| scale)."""
+    U = inputs.gauge_random(N, 30 + N)
+    m = -0.07
+    h = make_h(bamg, U, m, n_levels=1, precision=3)
+    x = inputs.gaussian((nrhs, N * N), 31 + N).astype(np.complex64)
+    y = torch.zeros(nrhs, N * N, dtype=torch.complex64, device="cuda:0")
+    bamg.bamg_level_op(h, 0, bamg.OP_APPLY_F32, torch.from_numpy(x).to("cuda:0"), y, nrhs)
+    ref = oracle.dhat_apply(U, m, x.astype(np.complex128)).reshape(nrhs, N * N)
+    e = rel(host(y).astype(np.complex128), ref)
+    log(f"dhat fp32 N={N} nrhs={nrhs}: {e:.2e}")
+    assert e < 2e-6
 
 
 @pytest.mark.parametrize("N,nrhs", [(16, 2), (40, 1)])
