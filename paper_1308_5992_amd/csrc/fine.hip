@@ -24,14 +24,28 @@ __device__ __forceinline__ int hidx(int x, int y, int N, int NH) {
 
 // accumulate the hop in direction d (0:+x 1:-x 2:+y 3:-y) of spinor (a, b) with link u
 // (u already conjugated for backward hops) into (o0, o1), without the factor 1/2
+// Complex product with its contraction fixed: each component is one fused
+// multiply-add on the exactly rounded other product, whatever the compiler
+// would otherwise fuse, so every kernel that evaluates a hop gets the same
+// bits (the operator kernels are chosen by problem size and must agree).
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_fixed(cx<T> a, cx<T> b) {
+  return cx<T>{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
+}
+// x - k a with one fused multiply-add per component
+template <typename T>
+__device__ __forceinline__ cx<T> sub_scaled(cx<T> x, T k, cx<T> a) {
+  return cx<T>{fma(-k, a.x, x.x), fma(-k, a.y, x.y)};
+}
+
 template <typename T>
 __device__ __forceinline__ void hop_acc(int d, cx<T> u, cx<T> a, cx<T> b, cx<T>& o0, cx<T>& o1) {
   cx<T> h;
   switch (d) {
-    case 0: h = u * (a - b); o0 = o0 + h; o1 = o1 - h; break;
-    case 1: h = u * (a + b); o0 = o0 + h; o1 = o1 + h; break;
-    case 2: h = u * (a - mul_i(b)); o0 = o0 + h; o1 = o1 + mul_i(h); break;
-    default: h = u * (a + mul_i(b)); o0 = o0 + h; o1 = o1 - mul_i(h); break;
+    case 0: h = cmul_fixed(u, a - b); o0 = o0 + h; o1 = o1 - h; break;
+    case 1: h = cmul_fixed(u, a + b); o0 = o0 + h; o1 = o1 + h; break;
+    case 2: h = cmul_fixed(u, a - mul_i(b)); o0 = o0 + h; o1 = o1 + mul_i(h); break;
+    default: h = cmul_fixed(u, a + mul_i(b)); o0 = o0 + h; o1 = o1 - mul_i(h); break;
   }
 }
 
@@ -175,7 +189,7 @@ __global__ __launch_bounds__(TX* TY) void k_dhat(FineT<T> f, const cx<T>* __rest
   hop_acc(2, Ue[2 * e + 1], t0[qpy], t1[qpy], a0, a1);
   hop_acc(3, conj(Uo[2 * omy + 1]), t0[qmy], t1[qmy], a0, a1);
   const T k2q = (T)(0.25 * f.kappa2);
-  C r0 = xv[2 * e] - k2q * a0, r1 = xv[2 * e + 1] - k2q * a1;
+  C r0 = sub_scaled(xv[2 * e], k2q, a0), r1 = sub_scaled(xv[2 * e + 1], k2q, a1);
   C* yv = y + blockIdx.z * n;
   if (b) {
     const C* bv = b + blockIdx.z * n;
@@ -283,7 +297,7 @@ __global__ __launch_bounds__(256) void k_dhat_tile(FineT<T> f, const cx<T>* __re
       hop_acc(1, l2[k][1], t0[bb][s2[k][1]], t1[bb][s2[k][1]], a0, a1);
       hop_acc(2, l2[k][2], t0[bb][s2[k][2]], t1[bb][s2[k][2]], a0, a1);
       hop_acc(3, l2[k][3], t0[bb][s2[k][3]], t1[bb][s2[k][3]], a0, a1);
-      C r0 = xe[k][0] - k2q * a0, r1 = xe[k][1] - k2q * a1;
+      C r0 = sub_scaled(xe[k][0], k2q, a0), r1 = sub_scaled(xe[k][1], k2q, a1);
       if (b) {
         r0 = be[k][0] - r0;
         r1 = be[k][1] - r1;
@@ -294,9 +308,160 @@ __global__ __launch_bounds__(256) void k_dhat_tile(FineT<T> f, const cx<T>* __re
   }
 }
 
+// The same operator streamed: one wave per (strip, segment, right-hand
+// side).  A strip is 64 consecutive half-x columns, lane l on column
+// 62 s - 1 + l; lanes 1..62 write, lanes 0 and 63 carry the halo columns
+// whose odd intermediate the edge outputs need.  The wave marches down the H
+// rows of its segment: per row it loads one coalesced row segment of x and
+// of both link arrays, forms the odd intermediate of that row (the +-x even
+// neighbours from the adjacent lanes, the +-y ones from its own ring of
+// three x rows) and then the output of the row above it (the +-x odd
+// neighbours again from the adjacent lanes, the +-y ones from its ring of
+// three intermediate rows).  No LDS, no barriers; each entry is read once
+// per segment, apart from 2 rows of x and the 2 halo columns.  The
+// arithmetic is that of k_dhat, term by term.
+constexpr int STRIP = 62;
+
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_up1(cx<T> v) {
+  return cx<T>{__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_down1(cx<T> v) {
+  return cx<T>{__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64)};
+}
+
+template <typename T>
+struct DhatRow {
+  cx<T> x0, x1, e0, e1, o0, o1;  // x (both spins), Ue and Uo (both directions) of one row at this lane's column
+};
+
+template <typename T, int PF>
+__global__ __launch_bounds__(256) void k_dhat_strip(FineT<T> f, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                    const cx<T>* __restrict__ b, int nstrips, int H, int nseg,
+                                                    int nrhs) {
+  using C = cx<T>;
+  using Row = DhatRow<T>;
+  constexpr int U = 3 + PF;  // row slots: rows ty-1, ty, ty+1 and PF rows in flight
+  const int lane = threadIdx.x & 63;
+  const long item = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= (long)nstrips * nseg * nrhs) return;  // whole waves leave together
+  const int r = (int)(item % nrhs);
+  const long sg = item / nrhs;
+  const int strip = (int)(sg % nstrips), seg = (int)(sg / nstrips);
+  const int N = f.N, NH = f.NH;
+  const size_t n = (size_t)N * NH * 2;
+  const int cl = strip * STRIP - 1 + lane;  // column of this lane before wrapping; NH >= 64
+  const int c = cl < 0 ? cl + NH : (cl >= NH ? cl - NH : cl);
+  const bool writes = lane >= 1 && lane <= STRIP && cl < NH;
+  const int y0 = seg * H;
+  const C* __restrict__ xv = x + (size_t)r * n;
+  const C* __restrict__ bv = b ? b + (size_t)r * n : nullptr;
+  C* __restrict__ yv = y + (size_t)r * n;
+  const C* __restrict__ Ue = f.Ue;
+  const C* __restrict__ Uo = f.Uo;
+  const T k2q = (T)(0.25 * f.kappa2);
+  auto at = [&](int yy) { return 2 * ((size_t)wrapn(yy, N) * NH + c); };
+  auto load = [&](int yy) {
+    const size_t i = at(yy);
+    return Row{xv[i], xv[i + 1], Ue[i], Ue[i + 1], Uo[i], Uo[i + 1]};
+  };
+  // slot k holds row y0 - 2 + m for the latest m = k (mod U) loaded; step g
+  // (t row ty = y0 - 1 + g) reads rows m = g, g+1, g+2 and loads m = g+2+PF
+  // into the slot of m = g-1, which step g-1 was the last to read.  The march
+  // is unrolled by U so that every slot is a fixed register set, and a row is
+  // first read PF steps after its load was issued.
+  Row S[U];
+#pragma unroll
+  for (int k = 0; k < U - 1; ++k) S[k] = load(y0 - 2 + k);
+  C uomm1 = {0, 0}, tmm0 = {0, 0}, tmm1 = {0, 0}, tm0 = {0, 0}, tm1 = {0, 0};
+  C bn0 = {0, 0}, bn1 = {0, 0};
+  const int steps = H + 2, last = y0 + H + 1;  // t rows y0-1 .. y0+H; rows used up to y0+H+1
+  for (int g0 = 0; g0 < steps; g0 += U) {
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int g = g0 + j;
+      if (g < steps) {
+        const int ty = y0 - 1 + g;
+        Row& rm = S[j % U];
+        Row& r0 = S[(j + 1) % U];
+        Row& rp = S[(j + 2) % U];
+        if (ty + 1 + PF <= last) S[(j + U - 1) % U] = load(ty + 1 + PF);  // into the slot of row ty-2
+        const int p = ty & 1;  // N is even, so the parity survives the wrap
+        // odd intermediate of row ty
+        C xpx0, xpx1, xmx0, xmx1, uex;
+        if (p) {
+          xpx0 = r0.x0; xpx1 = r0.x1;
+          xmx0 = shfl_up1(r0.x0); xmx1 = shfl_up1(r0.x1);
+          uex = shfl_up1(r0.e0);
+        } else {
+          xpx0 = shfl_down1(r0.x0); xpx1 = shfl_down1(r0.x1);
+          xmx0 = r0.x0; xmx1 = r0.x1;
+          uex = r0.e0;
+        }
+        C t0 = {0, 0}, t1 = {0, 0};
+        hop_acc(0, r0.o0, xpx0, xpx1, t0, t1);
+        hop_acc(1, conj(uex), xmx0, xmx1, t0, t1);
+        hop_acc(2, r0.o1, rp.x0, rp.x1, t0, t1);
+        hop_acc(3, conj(rm.e1), rm.x0, rm.x1, t0, t1);
+        // output of row ty - 1 (parity 1 - p)
+        if (ty >= y0 + 1) {
+          C tpx0, tpx1, tmx0, tmx1, uox;
+          if (p) {
+            tpx0 = tm0; tpx1 = tm1;
+            tmx0 = shfl_up1(tm0); tmx1 = shfl_up1(tm1);
+            uox = shfl_up1(rm.o0);
+          } else {
+            tpx0 = shfl_down1(tm0); tpx1 = shfl_down1(tm1);
+            tmx0 = tm0; tmx1 = tm1;
+            uox = rm.o0;
+          }
+          C a0 = {0, 0}, a1 = {0, 0};
+          hop_acc(0, rm.e0, tpx0, tpx1, a0, a1);
+          hop_acc(1, conj(uox), tmx0, tmx1, a0, a1);
+          hop_acc(2, rm.e1, t0, t1, a0, a1);
+          hop_acc(3, conj(uomm1), tmm0, tmm1, a0, a1);
+          C r0v = sub_scaled(rm.x0, k2q, a0), r1v = sub_scaled(rm.x1, k2q, a1);
+          if (bv) {
+            r0v = bn0 - r0v;
+            r1v = bn1 - r1v;
+          }
+          if (writes) {
+            const size_t i = at(ty - 1);
+            yv[i] = r0v;
+            yv[i + 1] = r1v;
+          }
+        }
+        if (bv && ty < y0 + H) {  // right-hand side of the next output row, ty
+          const size_t i = at(ty);
+          bn0 = bv[i];
+          bn1 = bv[i + 1];
+        }
+        tmm0 = tm0; tmm1 = tm1; tm0 = t0; tm1 = t1;
+        uomm1 = rm.o1;
+      }
+    }
+  }
+}
+
 template <typename T>
 void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s) {
   const int N = f.N, NH = f.NH;
+  // Kernel choice by measured speed (all three give the same bits): FP64
+  // streams 16-row strip segments when they make >= 2048 waves; FP32 streams
+  // 64-row segments for up to 4 right-hand sides when they make >= 2048
+  // waves, and otherwise uses the 32 x 16 tiles, whose right-hand-side loop
+  // keeps the links in registers.
+  if (NH >= 64) {
+    const int S = (NH + STRIP - 1) / STRIP;
+    const int H = sizeof(T) == 8 ? 16 : 64;
+    const long items = (N % H == 0) ? (long)S * (N / H) * nrhs : 0;
+    if (items >= 2048 && (sizeof(T) == 8 || nrhs <= 4)) {
+      hipLaunchKernelGGL((k_dhat_strip<T, 1>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, f, x, y, b, S, H,
+                         N / H, nrhs);
+      return;
+    }
+  }
   constexpr int TTX = 32, TTY = 16;
   if (NH % TTX == 0 && N % TTY == 0) {
     const int tiles = (NH / TTX) * (N / TTY);

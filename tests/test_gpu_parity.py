@@ -48,10 +48,12 @@ def make_h(bamg, U, m, **kw):
 
 
 # ---------------------------------------------------------------- fine level
-@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (128, 3), (256, 1), (512, 1), (512, 5)])
+@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (128, 3), (256, 1), (512, 1), (512, 5), (1024, 1), (1024, 4)])
 def test_dhat_apply(bamg, N, nrhs):
-    """N <= 256: tiles of 64 x 4 sites; N = 512: 32 x 16 tiles with the
-    right-hand sides looped inside the work-group (5 in 4 groups: 2, 2, 1)."""
+    """The three kernels of the operator, chosen by the amount of work:
+    N <= 256 (few right-hand sides): tiles of 64 x 4 sites; 512^2 x 1, 512^2 x 5
+    and 1024^2 x 1: 32 x 16 tiles; 1024^2 x 4: strips of 62 columns streamed
+    down segments of 16 rows."""
     log(f"dhat N={N} nrhs={nrhs}")
     U = inputs.gauge_random(N, 10 + N)
     m = -0.07
@@ -63,7 +65,7 @@ def test_dhat_apply(bamg, N, nrhs):
     assert rel(host(y), ref) < 1e-13
 
 
-@pytest.mark.parametrize("N,nrhs", [(128, 2), (512, 3)])
+@pytest.mark.parametrize("N,nrhs", [(128, 2), (512, 3), (1024, 2)])
 def test_dhat_apply_fp32(bamg, N, nrhs):
     """The FP32 operator of the mixed cycle (level op 10 on level 0, FP32 links
     rounded from FP64) against the FP64 oracle: within a few FP32 roundings of
@@ -78,6 +80,34 @@ def test_dhat_apply_fp32(bamg, N, nrhs):
     e = rel(host(y).astype(np.complex128), ref)
     log(f"dhat fp32 N={N} nrhs={nrhs}: {e:.2e}")
     assert e < 2e-6
+
+
+@pytest.mark.parametrize("N,R,prec", [(256, 64, 0), (512, 64, 0), (2048, 4, 3)])
+def test_dhat_kernels_give_the_same_bits(bamg, N, R, prec):
+    """The operator's kernels are chosen by the amount of work, so a batch and
+    its right-hand sides applied one at a time take different kernels (256^2:
+    strips against 64 x 4 tiles; 512^2: strips against 32 x 16 tiles; FP32
+    2048^2: 64-row strips against 32 x 16 tiles).  Each product is rounded
+    the same way in all of them, so the batch result is bitwise the single
+    one, which the batched solver's independence of its batch relies on."""
+    U = inputs.gauge_random(N, 50 + N)
+    m = -0.07
+    h = make_h(bamg, U, m, n_levels=1, precision=prec)
+    dt = torch.complex64 if prec else torch.complex128
+    X = torch.from_numpy(inputs.gaussian((R, N * N), 51 + N)).to("cuda:0").to(dt)
+    Y = torch.zeros_like(X)
+
+    def apply(x, y, k):
+        if prec:
+            bamg.bamg_level_op(h, 0, bamg.OP_APPLY_F32, x, y, k)
+        else:
+            bamg.bamg_apply_dhat(h, x, y, k)
+
+    apply(X, Y, R)
+    for r in sorted({0, R // 2, R - 1}):
+        y1 = torch.zeros_like(X[r:r + 1])
+        apply(X[r:r + 1].contiguous(), y1, 1)
+        assert torch.equal(y1[0], Y[r]), r
 
 
 @pytest.mark.parametrize("N,nrhs", [(16, 2), (40, 1)])
