@@ -552,9 +552,10 @@ MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix peak of the MI355X
 def mfma_utilisation(bamg, torch, h, R=32):
     """Achieved FP32 matrix-core rate of the MFMA kernels of the batched solve
     at R right-hand sides, timed with HIP events like the roofline kernels:
-    - the coarse block-stencil smoother k_kaczmarz_coarse_mfma on level 1
+    - the coarse block-stencil smoother k_kaczmarz_coarse_mfma4 on level 1
       (per site and 16 right-hand sides 240 v_mfma_f32_16x16x4f32 of 2048 flops:
-      residual 112, Kinv step 16, update 112), one launch per colour;
+      residual 112, Kinv step 16 (counted once although the four waves each
+      form it), update 112), one launch per colour;
     - with an FP32 copy of the coarsest inverse (op 12), the split-K product
       k_dense_mm32 (8 n^2 R flops; the call's small reduction launch is
       included in its time)."""
@@ -567,7 +568,7 @@ def mfma_utilisation(bamg, torch, h, R=32):
         bb = torch.ones(R, n, dtype=torch.complex64, device="cuda:0")
         t = time_launches(lambda: bamg.bamg_level_op(h, 1, bamg.OP_SWEEP_F32, bb, xb, R), 20, ncol, torch)
         fl = (ns // ncol) * ((R + 15) // 16) * 240 * 2048.0
-        out.append({"kernel": f"k_kaczmarz_coarse_mfma (level 1, {ns // ncol} sites x {R} RHS per launch)",
+        out.append({"kernel": f"k_kaczmarz_coarse_mfma4 (level 1, {ns // ncol} sites x {R} RHS per launch)",
                     "flops_per_launch": fl, "avg_launch_us": 1e6 * t, "achieved_tflops": fl / t / 1e12,
                     "peak_tflops": MFMA_F32_PEAK_TFLOPS, "frac": fl / t / 1e12 / MFMA_F32_PEAK_TFLOPS})
     p = bamg.bamg_level_info(h, L - 1) if L > 1 else None

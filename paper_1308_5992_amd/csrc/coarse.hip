@@ -341,10 +341,173 @@ __global__ __launch_bounds__(64) void k_kaczmarz_coarse_mfma(CoarseT<float, S> c
   }
 }
 
+// The same colour pass with each (site, 16 right-hand sides) block split over
+// the four waves of a 256-thread work-group, so that the matrix-core chain of
+// one wave is 76 MFMAs instead of 240: wave w forms the partial residual over
+// K-steps 7w .. 7w+6 of the 28, the partials are summed through LDS in wave
+// order, every wave forms alpha = Kinv (B - R) from the summed residual, and
+// wave w updates the column tiles o = w and w + 4.  The global loads are
+// shared by the four waves.
+template <typename S>
+__global__ __launch_bounds__(256) void k_kaczmarz_coarse_mfma4(CoarseT<float, S> c, int colour, int mode, int nrhs,
+                                                               zf* __restrict__ x, const zf* __restrict__ b) {
+  constexpr int NCOL = NOFF * 16, NQ = NCOL * 16 / 256;  // 7 staged unknowns per thread
+  constexpr int KW = NCOL / 4 / 4;                       // K-steps per wave: 7
+  __shared__ float Xr[NCOL][17], Xi[NCOL][17];
+  __shared__ float Vr[16][17], Vi[16][17];          // right-hand side block, then the residual
+  __shared__ float Pr[4][16][17], Pi[4][16][17];    // partial products of the four waves, then alpha per wave
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lm = l & 15, lq = l >> 4;
+  const int ns = c.ex * c.ey;
+  const size_t n = (size_t)ns * 16;
+  const int site = coarse_colour_site(colour, mode, blockIdx.x, c.ex);
+  const int r0 = blockIdx.y * 16;
+  const int nr = min(16, nrhs - r0);
+  const int ax = site % c.ex, ay = site / c.ex;
+  int nb[NOFF];
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    const int dx = (int)((0x0211021u >> (4 * o)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * o)) & 15u) - 1;
+    nb[o] = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
+  }
+  // ---- every global load first
+  zf xin[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + 256 * q, rr = e / NCOL, col = e - rr * NCOL, o = col >> 4;
+    int nbo = nb[0];
+#pragma unroll
+    for (int oo = 1; oo < NOFF; ++oo) nbo = (o == oo) ? nb[oo] : nbo;
+    xin[q] = (rr < nr) ? x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)] : zf{0, 0};
+  }
+  const S* Dsite = c.D + (size_t)site * NOFF * 256;
+  S ar[KW];  // A[lm][4 q + lq] for this wave's K-steps q = KW w + j
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    const int k = 4 * (KW * w + j) + lq;
+    ar[j] = Dsite[(k >> 4) * 256 + lm * 16 + (k & 15)];
+  }
+  S au[2][4];  // A[4 q + lq][16 o + lm] for the tiles o = w, w + 4
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int o = min(w + 4 * t, NOFF - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) au[t][q] = Dsite[o * 256 + (4 * q + lq) * 16 + lm];
+  }
+  zf kin[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) kin[q] = c.Kinv[(size_t)site * 256 + lm * 16 + 4 * q + lq];
+  zf bin = {0, 0};
+  {
+    const int rr = tid >> 4, i = tid & 15;
+    if (b && rr < nr) bin = b[(size_t)(r0 + rr) * n + site * 16 + i];
+  }
+  // ---- stage into LDS
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + 256 * q, rr = e / NCOL, col = e - rr * NCOL;
+    Xr[col][rr] = xin[q].x;
+    Xi[col][rr] = xin[q].y;
+  }
+  {
+    const int rr = tid >> 4, i = tid & 15;
+    Vr[i][rr] = bin.x;
+    Vi[i][rr] = bin.y;
+  }
+  __syncthreads();
+  // ---- partial R = A X over this wave's K-steps
+  mf4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    const int k = 4 * (KW * w + j) + lq;
+    const zf a = widen<float>(ar[j]);
+    const float xr = Xr[k][lm], xi = Xi[k][lm];
+    cr = mfma4(a.x, xr, cr);
+    cr = mfma4(-a.y, xi, cr);
+    ci = mfma4(a.x, xi, ci);
+    ci = mfma4(a.y, xr, ci);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    Pr[w][4 * lq + e][lm] = cr[e];
+    Pi[w][4 * lq + e][lm] = ci[e];
+  }
+  __syncthreads();
+  // ---- residual B - R, the partials summed in wave order (wave 0 writes it)
+  float resr[4], resi[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = 4 * lq + e;
+    const float rr_ = ((Pr[0][i][lm] + Pr[1][i][lm]) + Pr[2][i][lm]) + Pr[3][i][lm];
+    const float ri_ = ((Pi[0][i][lm] + Pi[1][i][lm]) + Pi[2][i][lm]) + Pi[3][i][lm];
+    resr[e] = Vr[i][lm] - rr_;
+    resi[e] = Vi[i][lm] - ri_;
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      Vr[4 * lq + e][lm] = resr[e];
+      Vi[4 * lq + e][lm] = resi[e];
+    }
+  }
+  __syncthreads();
+  // ---- alpha = Kinv (B - R), formed by every wave into its own slot of P
+  mf4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = 4 * q + lq;
+    const zf a = kin[q];
+    const float vr = Vr[k][lm], vi = Vi[k][lm];
+    gr = mfma4(a.x, vr, gr);
+    gr = mfma4(-a.y, vi, gr);
+    gi = mfma4(a.x, vi, gi);
+    gi = mfma4(a.y, vr, gi);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    Pr[w][4 * lq + e][lm] = gr[e];
+    Pi[w][4 * lq + e][lm] = gi[e];
+  }
+  __syncthreads();
+  // ---- X += A^H alpha on the tiles o = w, w + 4 (disjoint columns per wave)
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int o = w + 4 * t;
+    if (o < NOFF) {
+      mf4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * q + lq;
+        const zf a = widen<float>(au[t][q]);
+        const float vr = Pr[w][i][lm], vi = Pi[w][i][lm];
+        ur = mfma4(a.x, vr, ur);
+        ur = mfma4(a.y, vi, ur);
+        ui = mfma4(a.x, vi, ui);
+        ui = mfma4(-a.y, vr, ui);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int col = 16 * o + 4 * lq + e;
+        Xr[col][lm] += ur[e];
+        Xi[col][lm] += ui[e];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + 256 * q, rr = e / NCOL, col = e - rr * NCOL, o = col >> 4;
+    int nbo = nb[0];
+#pragma unroll
+    for (int oo = 1; oo < NOFF; ++oo) nbo = (o == oo) ? nb[oo] : nbo;
+    if (rr < nr) x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)] = zf{Xr[col][rr], Xi[col][rr]};
+  }
+}
+
 template <typename S>
 void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mode, int nsites, zf* x, const zf* b,
                                  int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL((k_kaczmarz_coarse_mfma<S>), dim3(nsites, (nrhs + 15) / 16), dim3(64), 0, s, c, colour, mode,
+  hipLaunchKernelGGL((k_kaczmarz_coarse_mfma4<S>), dim3(nsites, (nrhs + 15) / 16), dim3(256), 0, s, c, colour, mode,
                      nrhs, x, b);
 }
 template void launch_kaczmarz_coarse_mfma<zf>(const CoarseT<float, zf>&, int, int, int, zf*, const zf*, int,
