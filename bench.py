@@ -467,10 +467,10 @@ COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine", "mixed_fp16"): {"src": "fine.hip",
-                             "sha256": "483fde11dc092bbc1c0280d483f52373b5303f4848dbc7df97b4a982dc3fbf7c",
-                             "fetch_kib": 762.0, "write_kib": 448.0, **COPY_SCALE},
+                             "sha256": "7d66678a6a58d73d7d7ac81841d39762677320c4317232ea532462fe72a27091",
+                             "fetch_kib": 755.0, "write_kib": 448.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
-                               "sha256": "676578ea4fbb84cbfe95f0270878300590c3ed8b8a3c4a9fb0a712aea4efed1e",
+                               "sha256": "648c9669d7a9f63a0e0beee951cee527d9f7a1ed39c3dced91e3f6ea4af983fe",
                                "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE},
     ("dense", "mixed_fp16"): {"src": "dense.hip",
                               "sha256": "2b3837a67c198d055924253ea7b62e9d0fafaa1f6fed9a31a26ab11b32b1ea62",
