@@ -547,6 +547,7 @@ def roofline(bamg, torch, h, prec, c32=0):
 
 
 MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix peak of the MI355X
+MFMA_F64_PEAK_TFLOPS = 78.6   # dense FP64 matrix peak of the MI355X
 
 
 def mfma_utilisation(bamg, torch, h, R=32):
@@ -556,9 +557,11 @@ def mfma_utilisation(bamg, torch, h, R=32):
       (per site and 16 right-hand sides 240 v_mfma_f32_16x16x4f32 of 2048 flops:
       residual 112, Kinv step 16 (counted once although the four waves each
       form it), update 112), one launch per colour;
+    - the split-K product with the FP64 coarsest inverse, k_dense_mm64 (op 4;
+      8 n^2 R flops, FP64 matrix peak; the call's small reduction launch is
+      included in its time);
     - with an FP32 copy of the coarsest inverse (op 12), the split-K product
-      k_dense_mm32 (8 n^2 R flops; the call's small reduction launch is
-      included in its time)."""
+      k_dense_mm32 (likewise)."""
     out = []
     L = bamg.bamg_n_levels(h)
     if L > 2:
@@ -574,6 +577,14 @@ def mfma_utilisation(bamg, torch, h, R=32):
     p = bamg.bamg_level_info(h, L - 1) if L > 1 else None
     if p is not None:
         n = p["n"]
+        xb = torch.zeros(R, n, dtype=torch.complex128, device="cuda:0")
+        bb = torch.ones(R, n, dtype=torch.complex128, device="cuda:0")
+        t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, bamg.OP_COARSEST, bb, xb, R), 10, 1, torch)
+        fl = 8.0 * n * n * R
+        out.append({"kernel": f"k_dense_mm64 (coarsest inverse, FP64, n = {n}, {R} RHS)", "flops_per_launch": fl,
+                    "avg_launch_us": 1e6 * t, "achieved_tflops": fl / t / 1e12, "peak_tflops": MFMA_F64_PEAK_TFLOPS,
+                    "frac": fl / t / 1e12 / MFMA_F64_PEAK_TFLOPS})
+        del xb, bb
         xb = torch.zeros(R, n, dtype=torch.complex64, device="cuda:0")
         bb = torch.ones(R, n, dtype=torch.complex64, device="cuda:0")
         try:

@@ -257,11 +257,138 @@ __global__ void k_dense_mm_reduce(const zd* __restrict__ part, int n, int nrhs, 
   Y[t] = s;
 }
 
+// The FP64 product for many right-hand sides on the matrix cores
+// (v_mfma_f64_16x16x4f64), the real form of k_dense_mm32: A as an n x 2n
+// real matrix (re, im interleaved as stored) times the 2n x 2R matrix of
+// (Re x, -Im x) / (Im x, Re x) column pairs.  A work-group owns 64 rows (16
+// per wave) and 8 NT right-hand sides over one quarter of K; per 16-complex
+// chunk each lane streams 4 complex entries of its row (prefetched one chunk
+// ahead) and the chunk of X goes through LDS.  The partial tiles leave
+// through LDS in passes of 16 right-hand sides and k_dense_mm_reduce sums
+// the quarters in a fixed order, so a column's result does not depend on the
+// other columns.
+typedef double md4 __attribute__((ext_vector_type(4)));
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][k0 + l/16] and
+// B[k0 + l/16][l%16] and receives C[l/16 + 4e][l%16], e = 0..3
+static __device__ __forceinline__ md4 mfma64(double a, double b, md4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+constexpr int M64_KC = 16;
+static_assert(MM_SPLIT == 4, "k_dense_mm64 writes the partials k_dense_mm_reduce sums");
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_dense_mm64(const zd* __restrict__ A, int n, const zd* __restrict__ X,
+                                                    zd* __restrict__ part, int nrhs, int chunks_per_split) {
+  constexpr int RB = 8 * NT, XS = M64_KC + 1;
+  constexpr int XPT = (RB * M64_KC + 255) / 256;
+  constexpr int XBYTES = 2 * RB * XS * 16, TBYTES = 16 * 130 * 8;
+  __shared__ __align__(16) char lds[XBYTES > TBYTES ? XBYTES : TBYTES];
+  zd (*Xs)[RB][XS] = reinterpret_cast<zd (*)[RB][XS]>(lds);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int c = lane & 15, g = lane >> 4, q = c & 1;
+  const int row0 = blockIdx.x * 64;
+  const bool wave_rows = row0 + wave * 16 < n;  // n is a multiple of 16
+  const int r0 = blockIdx.y * RB;
+  const int nch = (n + M64_KC - 1) / M64_KC;
+  const int ch0 = blockIdx.z * chunks_per_split;
+  const int ch1 = min(nch, ch0 + chunks_per_split);
+  const zd* Arow = A + (size_t)min(row0 + wave * 16 + c, n - 1) * n;
+  md4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = md4{0.0, 0.0, 0.0, 0.0};
+  zd a[4], xr[XPT];
+  // chunk loads: each entry is set to zero and then loaded if in range (a
+  // conditional expression between a load and a named zero makes the
+  // compiler select between addresses and keep the arrays in scratch)
+#define MM64_LOAD(CH)                                                                      \
+  do {                                                                                     \
+    _Pragma("unroll") for (int t = 0; t < 4; ++t) {                                        \
+      const int k = (CH) * M64_KC + 4 * g + t;                                             \
+      a[t].x = 0.0;                                                                        \
+      a[t].y = 0.0;                                                                        \
+      if (wave_rows && k < n) a[t] = Arow[k];                                              \
+    }                                                                                      \
+    _Pragma("unroll") for (int e = 0; e < XPT; ++e) {                                      \
+      const int idx = tid + 256 * e, r = idx / M64_KC, k = (CH) * M64_KC + idx % M64_KC;   \
+      xr[e].x = 0.0;                                                                       \
+      xr[e].y = 0.0;                                                                       \
+      if (idx < RB * M64_KC && r0 + r < nrhs && k < n) xr[e] = X[(size_t)(r0 + r) * n + k]; \
+    }                                                                                      \
+  } while (0)
+  if (ch0 < ch1) MM64_LOAD(ch0);
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int buf = (ch - ch0) & 1;
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+      const int idx = tid + 256 * e;
+      if (idx < RB * M64_KC) Xs[buf][idx / M64_KC][idx % M64_KC] = xr[e];
+    }
+    __syncthreads();
+    zd cur[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cur[t] = a[t];
+    if (ch + 1 < ch1) MM64_LOAD(ch + 1);
+    // issue across the independent column-tile accumulators (each column
+    // still accumulates its K-steps in the same order)
+    // B entries straight from LDS at a lane-dependent offset (see k_dense_mm32)
+    const double sg = q ? 1.0 : -1.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      double b0[NT], b1[NT];
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        // complex entry k = 4g + t of right-hand side 8 ct + c / 2
+        const double* v = reinterpret_cast<const double*>(&Xs[buf][8 * ct + (c >> 1)][4 * g + t]);
+        b0[ct] = v[q];
+        b1[ct] = sg * v[1 - q];
+      }
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[ct] = mfma64(cur[t].x, b0[ct], acc[ct]);
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[ct] = mfma64(cur[t].y, b1[ct], acc[ct]);
+    }
+  }
+#undef MM64_LOAD
+  // the 64 x RB partial tile through LDS, 16 right-hand sides (two column tiles) per pass
+  double (*T)[130] = reinterpret_cast<double (*)[130]>(lds);
+  zd* out = part + (size_t)blockIdx.z * nrhs * n;
+#pragma unroll
+  for (int h = 0; h < (NT + 1) / 2; ++h) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int ct = 2 * h + u;
+      if (ct < NT) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T[8 * u + (c >> 1)][2 * (wave * 16 + g + 4 * e) + q] = acc[ct][e];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 16 * 64; idx += 256) {
+      const int rl = idx >> 6, i = idx & 63, rb = 16 * h + rl;
+      if (rb < RB && r0 + rb < nrhs && row0 + i < n) out[(size_t)(r0 + rb) * n + row0 + i] = zd{T[rl][2 * i], T[rl][2 * i + 1]};
+    }
+  }
+}
+
 size_t dense_mm_workspace(int n, int nrhs) { return (size_t)MM_SPLIT * n * nrhs; }
 
 void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, zd* work, hipStream_t s) {
   if (!many && nrhs <= 2) {
     hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y, nrhs);
+  } else if (n % 16 == 0) {
+    const int nch = (n + M64_KC - 1) / M64_KC;
+    const int cps = (nch + MM_SPLIT - 1) / MM_SPLIT;
+    const int nt = nrhs <= 8 ? 1 : nrhs <= 16 ? 2 : nrhs <= 32 ? 4 : 8;
+    const dim3 grid((n + 63) / 64, (nrhs + 8 * nt - 1) / (8 * nt), MM_SPLIT);
+    switch (nt) {
+      case 1: hipLaunchKernelGGL(k_dense_mm64<1>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+      case 2: hipLaunchKernelGGL(k_dense_mm64<2>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+      case 4: hipLaunchKernelGGL(k_dense_mm64<4>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+      default: hipLaunchKernelGGL(k_dense_mm64<8>, grid, dim3(256), 0, s, A, n, x, work, nrhs, cps); break;
+    }
+    const size_t tot = (size_t)n * nrhs;
+    hipLaunchKernelGGL(k_dense_mm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, n, nrhs, y);
   } else {
     hipLaunchKernelGGL(k_dense_mm, dim3((n + MM_T - 1) / MM_T, (nrhs + MM_T - 1) / MM_T, MM_SPLIT), dim3(256), 0, s,
                        A, n, x, work, nrhs);
@@ -353,28 +480,24 @@ __global__ __launch_bounds__(256) void k_dense_mm32(const zf* __restrict__ A, in
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = mf4{0.f, 0.f, 0.f, 0.f};
   float4 a[4], xr[XPT];
-  const float4 z4 = {0.f, 0.f, 0.f, 0.f};
-  auto load_a = [&](int ch) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int k = ch * M32_KC + 8 * g + 2 * t;  // complex column of the pair
-      a[t] = (wave_rows && k < n) ? Arow[k >> 1] : z4;
-    }
-  };
-  auto load_x = [&](int ch) {
-#pragma unroll
-    for (int e = 0; e < XPT; ++e) {
-      const int idx = tid + 256 * e, r = idx / XQ, j = idx % XQ;
-      const int k = ch * M32_KC + 2 * j;
-      xr[e] = (idx < RB * XQ && r0 + r < nrhs && k < n)
-                  ? reinterpret_cast<const float4*>(X + (size_t)(r0 + r) * n)[k >> 1]
-                  : z4;
-    }
-  };
-  if (ch0 < ch1) {
-    load_a(ch0);
-    load_x(ch0);
-  }
+  // chunk loads: each entry is set to zero and then loaded if in range (a
+  // conditional expression between a load and a named zero makes the
+  // compiler select between addresses and keep the arrays in scratch)
+#define MM32_LOAD(CH)                                                                      \
+  do {                                                                                     \
+    _Pragma("unroll") for (int t = 0; t < 4; ++t) {                                        \
+      const int k = (CH) * M32_KC + 8 * g + 2 * t; /* complex column of the pair */        \
+      a[t] = make_float4(0.f, 0.f, 0.f, 0.f);                                              \
+      if (wave_rows && k < n) a[t] = Arow[k >> 1];                                         \
+    }                                                                                      \
+    _Pragma("unroll") for (int e = 0; e < XPT; ++e) {                                      \
+      const int idx = tid + 256 * e, r = idx / XQ, k = (CH) * M32_KC + 2 * (idx % XQ);     \
+      xr[e] = make_float4(0.f, 0.f, 0.f, 0.f);                                             \
+      if (idx < RB * XQ && r0 + r < nrhs && k < n)                                         \
+        xr[e] = reinterpret_cast<const float4*>(X + (size_t)(r0 + r) * n)[k >> 1];         \
+    }                                                                                      \
+  } while (0)
+  if (ch0 < ch1) MM32_LOAD(ch0);
   for (int ch = ch0; ch < ch1; ++ch) {
     const int buf = (ch - ch0) & 1;
 #pragma unroll
@@ -386,23 +509,36 @@ __global__ __launch_bounds__(256) void k_dense_mm32(const zf* __restrict__ A, in
     float4 cur[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) cur[t] = a[t];
-    if (ch + 1 < ch1) {
-      load_a(ch + 1);
-      load_x(ch + 1);
-    }
+    if (ch + 1 < ch1) MM32_LOAD(ch + 1);
+    // the column tiles' accumulators are independent: issue across them so
+    // that consecutive MFMAs do not wait on each other (each column still
+    // accumulates its K-steps in the same order)
+    // B entries straight from LDS at a lane-dependent offset: for the pair
+    // (Re x_k, Im x_k) the column 2r takes (Re, -Im) and 2r+1 takes (Im, Re)
+    const float sg = q ? 1.f : -1.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
+      float b0[NT], b1[NT], b2[NT], b3[NT];
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) {
         // complex entries k = 8g + 2t and k + 1 of right-hand side 8 ct + c / 2
-        const float4 v = Xs[buf][8 * ct + (c >> 1)][4 * g + t];
-        acc[ct] = mfma4(cur[t].x, q ? v.y : v.x, acc[ct]);
-        acc[ct] = mfma4(cur[t].y, q ? v.x : -v.y, acc[ct]);
-        acc[ct] = mfma4(cur[t].z, q ? v.w : v.z, acc[ct]);
-        acc[ct] = mfma4(cur[t].w, q ? v.z : -v.w, acc[ct]);
+        const float* v = reinterpret_cast<const float*>(&Xs[buf][8 * ct + (c >> 1)][4 * g + t]);
+        b0[ct] = v[q];
+        b1[ct] = sg * v[1 - q];
+        b2[ct] = v[2 + q];
+        b3[ct] = sg * v[3 - q];
       }
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[ct] = mfma4(cur[t].x, b0[ct], acc[ct]);
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[ct] = mfma4(cur[t].y, b1[ct], acc[ct]);
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[ct] = mfma4(cur[t].z, b2[ct], acc[ct]);
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[ct] = mfma4(cur[t].w, b3[ct], acc[ct]);
     }
   }
+#undef MM32_LOAD
   // transpose the 64 x RB tile through LDS so that the partials are written
   // along the rows of each right-hand side
   __syncthreads();

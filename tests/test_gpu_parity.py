@@ -228,9 +228,11 @@ def test_coarse_kaczmarz_sweep(bamg, imported, nrhs):
     assert rel(host(x), ref) < 1e-11
 
 
-@pytest.mark.parametrize("nrhs", [2, 37])
+@pytest.mark.parametrize("nrhs", [2, 3, 9, 17, 37, 70])
 def test_coarsest_solve(bamg, imported, nrhs):
-    """nrhs > 2 runs the split-K tiled product with the inverse."""
+    """nrhs <= 2: one wave per row; else the split-K FP64 MFMA product with the
+    inverse (8, 16, 32 and 64 right-hand sides per work-group; 70 spans two
+    groups), whose columns do not depend on the other columns."""
     N, U, m, h, o = imported
     L = 2
     n = bamg.bamg_level_info(h, L)["n"]
@@ -242,6 +244,10 @@ def test_coarsest_solve(bamg, imported, nrhs):
     ref = o.coarsest_solve(b, nrhs=nrhs).reshape(nrhs, n)
     log(f"coarsest cond {kappa:.2e} diff {rel(host(x), ref):.2e}")
     assert rel(host(x), ref) < max(1e-12, 10 * kappa * 2.2e-16)
+    if nrhs > 8:
+        x9 = torch.zeros(9, n, dtype=torch.complex128, device="cuda:0")
+        bamg.bamg_level_op(h, L, bamg.OP_COARSEST, dev(b[:9]), x9, 9)
+        assert np.array_equal(host(x9), host(x)[:9])
 
 
 @pytest.mark.parametrize("nrhs", [2, 6])
