@@ -467,14 +467,14 @@ COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine", "mixed_fp16"): {"src": "fine.hip",
-                             "sha256": "7d66678a6a58d73d7d7ac81841d39762677320c4317232ea532462fe72a27091",
-                             "fetch_kib": 755.0, "write_kib": 448.0, **COPY_SCALE},
+                             "sha256": "2311ab60fdd99bd26377791aabe194ee77a389f555ab54f859caf2f20b52a691",
+                             "fetch_kib": 766.0, "write_kib": 448.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "648c9669d7a9f63a0e0beee951cee527d9f7a1ed39c3dced91e3f6ea4af983fe",
                                "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE},
     ("dense", "mixed_fp16"): {"src": "dense.hip",
-                              "sha256": "2b3837a67c198d055924253ea7b62e9d0fafaa1f6fed9a31a26ab11b32b1ea62",
-                              "fetch_kib": 524814.5, "write_kib": 128.0, **COPY_SCALE},
+                              "sha256": "091dbc73896e7f9ed78d2e01839ad407e48ffe378fcd5bb93763554a284cb777",
+                              "fetch_kib": 524812.5, "write_kib": 128.0, **COPY_SCALE},
     ("dense32", "mixed_fp16"): {"src": "dense.hip",
                                 "sha256": "2b3837a67c198d055924253ea7b62e9d0fafaa1f6fed9a31a26ab11b32b1ea62",
                                 "fetch_kib": 262618.0, "write_kib": 75.0, **COPY_SCALE},
@@ -521,7 +521,7 @@ def roofline(bamg, torch, h, prec, c32=0):
     xb = torch.zeros(inf["n"], dtype=dt, device="cuda:0")
     bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
     t = time_launches(lambda: bamg.bamg_level_op(h, 0, sweep, bb, xb, 1), 50, 16, torch)
-    out.append(_roof(f"k_kaczmarz_fine<{tname}> (level 0, {nsite} sites per launch)", "fine", prec,
+    out.append(_roof(f"k_kaczmarz_fine<{tname}, 1> (level 0, {nsite} sites per launch)", "fine", prec,
                      nsite * fine_site_bytes(VEC_BYTES[prec]), t))
     L = bamg.bamg_n_levels(h)
     if L > 2:  # coarse pass, level 1

@@ -669,31 +669,41 @@ __device__ __forceinline__ void fine_colour_site(int c, int t, int N, int& x, in
   x = 8 * k + ((2 * a - y) & 7);
 }
 
+// conj(a) b with its contraction fixed (see cmul_fixed)
+template <typename T>
+__device__ __forceinline__ cx<T> cjmul_fixed(cx<T> a, cx<T> b) {
+  return cx<T>{fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x))};
+}
+template <typename T>
+__device__ __forceinline__ T norm2_fixed(cx<T> a) {
+  return fma(a.x, a.x, a.y * a.y);
+}
+
 // lam (may be NULL): per right-hand side shift, the pass then works on
 // (Dhat - lam Gamma_5) x = 0 (the eigen-relaxation of the bootstrap setup,
-// Sec. 3.4 / Theorem 1), Gamma_5 = +1 on spin 0 and -1 on spin 1
-template <typename T>
+// Sec. 3.4 / Theorem 1), Gamma_5 = +1 on spin 0 and -1 on spin 1.
+// A 16-lane group (lane = stencil slot) takes one site of the colour for RB
+// right-hand sides: the site's stored slot blocks, row norms and G_10 are
+// read and formed once, the supports and right-hand sides of all RB are
+// loaded before the first update.  Every product is contracted the same way
+// whatever RB is (cmul_fixed, cjmul_fixed, norm2_fixed), so a right-hand
+// side's result does not depend on how many share the group.
+template <typename T, int RB>
 __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, int nsites, cx<T>* __restrict__ x,
-                                                      const cx<T>* __restrict__ b, const double* __restrict__ lam) {
+                                                      const cx<T>* __restrict__ b, const double* __restrict__ lam,
+                                                      int nrhs) {
   using C = cx<T>;
   const int lane = threadIdx.x & 15;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 4);
-  if (t >= nsites) return;  // whole 16-lane groups leave together
+  const int rbeg = blockIdx.y * RB;
+  if (t >= nsites || rbeg >= nrhs) return;  // whole 16-lane groups leave together
   const size_t n = (size_t)f.N * f.NH * 2;
-  C* xv = x + blockIdx.y * n;
   int px, y;
   fine_colour_site(colour, t, f.N, px, y);
   const int i = y * f.NH + (px >> 1);
   const bool act = lane < 9;
   const int slot = act ? lane : 0;
   const int jn = hidx(px + nib(SLOT_DX2, slot) - 2, y + nib(SLOT_DY2, slot) - 2, f.N, f.NH);
-  C x0 = {0, 0}, x1 = {0, 0};
-  if (act) {
-    x0 = xv[2 * jn];
-    x1 = xv[2 * jn + 1];
-  }
-  const C b0 = b ? b[blockIdx.y * n + 2 * i] : C{0, 0};
-  const C b1 = b ? b[blockIdx.y * n + 2 * i + 1] : C{0, 0};
   C B[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
   if (act) {
     const C* bp = f.Bst + ((size_t)i * 9 + slot) * 4;
@@ -701,28 +711,63 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
     B[0][1] = bp[1];
     B[1][0] = bp[2];
     B[1][1] = bp[3];
-    if (lam && slot == 0) {  // slot 0 is the site itself: the diagonal 2 x 2 block
-      const T l = (T)lam[blockIdx.y];
-      B[0][0].x -= l;
-      B[1][1].x += l;
+  }
+  C x0[RB], x1[RB], b0[RB], b1[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int r = rbeg + k;
+    x0[k].x = x0[k].y = x1[k].x = x1[k].y = T(0);
+    b0[k].x = b0[k].y = b1[k].x = b1[k].y = T(0);
+    if (r < nrhs) {
+      if (act) {
+        x0[k] = x[r * n + 2 * jn];
+        x1[k] = x[r * n + 2 * jn + 1];
+      }
+      if (b) {
+        b0[k] = b[r * n + 2 * i];
+        b1[k] = b[r * n + 2 * i + 1];
+      }
     }
   }
-  const C r0 = grp16_sum(B[0][0] * x0 + B[0][1] * x1);
-  const C r1 = grp16_sum(B[1][0] * x0 + B[1][1] * x1);
-  const C nu = grp16_sum(C{norm2(B[0][0]) + norm2(B[0][1]), norm2(B[1][0]) + norm2(B[1][1])});
-  const C g10 = grp16_sum(cjmul(B[0][0], B[1][0]) + cjmul(B[0][1], B[1][1]));
-  const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
-  const C a1 = nu.y > 0 ? cdiv_real(b1 - r1 - g10 * a0, nu.y) : C{0, 0};
-  if (act) {
-    xv[2 * jn] = x0 + cjmul(B[0][0], a0) + cjmul(B[1][0], a1);
-    xv[2 * jn + 1] = x1 + cjmul(B[0][1], a0) + cjmul(B[1][1], a1);
+  auto gram = [&](const C (&Bm)[2][2], C& nu, C& g10) {
+    nu = grp16_sum(C{norm2_fixed(Bm[0][0]) + norm2_fixed(Bm[0][1]), norm2_fixed(Bm[1][0]) + norm2_fixed(Bm[1][1])});
+    g10 = grp16_sum(cjmul_fixed(Bm[0][0], Bm[1][0]) + cjmul_fixed(Bm[0][1], Bm[1][1]));
+  };
+  C nu, g10;
+  if (!lam) gram(B, nu, g10);
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int r = rbeg + k;
+    if (r >= nrhs) break;  // uniform over the group
+    C Bk[2][2] = {{B[0][0], B[0][1]}, {B[1][0], B[1][1]}};
+    if (lam) {
+      if (act && slot == 0) {  // slot 0 is the site itself: the diagonal 2 x 2 block
+        const T l = (T)lam[r];
+        Bk[0][0].x -= l;
+        Bk[1][1].x += l;
+      }
+      gram(Bk, nu, g10);
+    }
+    const C r0 = grp16_sum(cmul_fixed(Bk[0][0], x0[k]) + cmul_fixed(Bk[0][1], x1[k]));
+    const C r1 = grp16_sum(cmul_fixed(Bk[1][0], x0[k]) + cmul_fixed(Bk[1][1], x1[k]));
+    const C a0 = nu.x > 0 ? cdiv_real(b0[k] - r0, nu.x) : C{0, 0};
+    const C a1 = nu.y > 0 ? cdiv_real((b1[k] - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+    if (act) {
+      x[r * n + 2 * jn] = (x0[k] + cjmul_fixed(Bk[0][0], a0)) + cjmul_fixed(Bk[1][0], a1);
+      x[r * n + 2 * jn + 1] = (x1[k] + cjmul_fixed(Bk[0][1], a0)) + cjmul_fixed(Bk[1][1], a1);
+    }
   }
 }
 
 template <typename T>
 void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs, hipStream_t s,
                           const double* lam) {
-  hipLaunchKernelGGL(k_kaczmarz_fine<T>, dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b, lam);
+  if (nrhs >= 16)
+    hipLaunchKernelGGL((k_kaczmarz_fine<T, 4>), dim3((nsites + 3) / 4, (nrhs + 3) / 4), dim3(64), 0, s, f, colour,
+                       nsites, x, b, lam, nrhs);
+  else
+    hipLaunchKernelGGL((k_kaczmarz_fine<T, 1>), dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b,
+                       lam, nrhs);
 }
 template void launch_kaczmarz_fine<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t,
                                            const double*);
