@@ -45,7 +45,10 @@ def parse():
     ap.add_argument("--workload", default="c3_256_b10")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-dhat", action="store_true")
+    ap.add_argument("--no-dhat", action="store_true", help="skip the Dhat and fine-sweep bandwidth points")
+    ap.add_argument("--bandwidth-only", action="store_true",
+                    help="time only the Dhat and fine-sweep bandwidth points (and the copy of COPY_MIB MiB), print "
+                         "them and exit")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--batch", default="8,32", help="right-hand sides per batched solve (comma list, '' for none)")
     ap.add_argument("--batch-steps", type=int, default=3)
@@ -259,7 +262,34 @@ def dhat_bandwidth(bamg, inputs, torch, N, nrhs, reps):
     bamg.bamg_free(h)
     del x, y, U
     torch.cuda.empty_cache()
-    return {"N": N, "nrhs": nrhs, "us": t * 1e6, "GB/s": bytes_ / t / 1e9}
+    return {"N": N, "nrhs": nrhs, "us": t * 1e6, "GB/s": bytes_ / t / 1e9, "frac": bytes_ / t / 1e9 / HBM_PEAK_GBS}
+
+
+def sweep_bandwidth(bamg, inputs, torch, N, nrhs, reps):
+    """GB/s of one FP64 fine multicolour Kaczmarz sweep (16 colour passes, b = 0)
+    from this design's compulsory bytes per sweep: the stored slot blocks once
+    (36 complex per even site, 288 N^2) and, per right-hand side, x read and
+    written (32 N^2), (288 + 32 R) N^2 in all; b = 0 is not read.
+    Operator-only handle."""
+    U = torch.from_numpy(inputs.gauge_random(N, 77)).to("cuda:0")
+    p = bamg.bamg_default_params(N=N, n_levels=1)
+    h = bamg.bamg_setup(U, -0.05, p)
+    x = torch.from_numpy(inputs.gaussian((nrhs, N * N), 79)).to("cuda:0")
+    b = torch.zeros_like(x)
+    t = time_launches(lambda: bamg.bamg_level_op(h, 0, bamg.OP_SWEEP, b, x, nrhs), reps, 1, torch)
+    bytes_ = (288.0 + 32.0 * nrhs) * N * N
+    bamg.bamg_free(h)
+    del x, b, U
+    torch.cuda.empty_cache()
+    return {"N": N, "nrhs": nrhs, "us_per_sweep": t * 1e6, "GB/s": bytes_ / t / 1e9, "frac": bytes_ / t / 1e9 / HBM_PEAK_GBS}
+
+
+BANDWIDTH_POINTS = ((256, 1, 200), (512, 64, 20), (4096, 1, 20))
+
+
+def bandwidth_points(bamg, inputs, torch):
+    return ([dhat_bandwidth(bamg, inputs, torch, n_, r_, reps) for (n_, r_, reps) in BANDWIDTH_POINTS],
+            [sweep_bandwidth(bamg, inputs, torch, n_, r_, max(3, reps // 10)) for (n_, r_, reps) in BANDWIDTH_POINTS])
 
 
 def main():
@@ -287,6 +317,11 @@ def main():
     precs = [v.strip() for v in args.precisions.split(",") if v.strip()]
     head = precs[0]
     head_base, head_kw = variant(head)
+    if args.bandwidth_only:
+        d_, s_ = bandwidth_points(bamg, inputs, torch)
+        print(json.dumps({"dhat_bandwidth": d_, "fine_sweep_bandwidth": s_, "copy_calibration": copy_calibration(torch)}),
+              flush=True)
+        return
     if args.roofline_only:
         p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], **head_kw)
         h = bamg.bamg_setup(U, w["m"], p)
@@ -321,7 +356,8 @@ def main():
         ms = [1e3 * t for t in times]
         results[prec] = {
             "solves_per_s": args.steps / t_all, "ms_per_solve": 1e3 * t_all / args.steps,
-            "p50_ms": statistics.median(ms), "p99_ms": float(np.percentile(ms, 99)),
+            "p10_ms": float(np.percentile(ms, 10)), "p50_ms": statistics.median(ms),
+            "p90_ms": float(np.percentile(ms, 90)), "p99_ms": float(np.percentile(ms, 99)),
             "iters": infos[-1]["iters"], "relres_reduced": infos[-1]["relres_reduced"],
             "converged": all(i["relres_reduced"] <= args.tol for i in infos), "setup_s": t_setup,
             "levels": bamg.bamg_n_levels(h), "cycle": f"V({p.pre},{p.post})", "graphs": bool(p.graphs),
@@ -412,11 +448,8 @@ def main():
 
     # ---- Dhat ("D_oe") bandwidth: cache-resident, batched, cache-busting
     if not args.no_dhat:
-        pts = []
-        for (n_, r_, reps) in ((256, 1, 200), (512, 64, 20), (4096, 1, 20)):
-            pts.append(dhat_bandwidth(bamg, inputs, torch, n_, r_, reps))
-        out["dhat_bandwidth"] = pts
-        progress("dhat bandwidth")
+        out["dhat_bandwidth"], out["fine_sweep_bandwidth"] = bandwidth_points(bamg, inputs, torch)
+        progress("dhat and fine-sweep bandwidth")
 
     # ---- roofline of the dominant kernel of the solve
     if not args.no_roofline:
@@ -613,9 +646,16 @@ def cpu_baseline(w, U_np, tol):
     t0 = time.perf_counter()
     st, xo, info = o.solve(b, tol=tol)
     t = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / t, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"one full solve of the same 256^2 system, oracle FP64 with 4 levels and V(4,4) "
-                      f"({info['iters']} FGMRES iterations, {t:.2f} s); oracle setup untimed", "iters": info["iters"]}
+                      f"({info['iters']} FGMRES iterations, {t:.2f} s); oracle setup untimed", "iters": info["iters"],
+            "host_cores_available": len(os.sched_getaffinity(0)), "host_cpu": model}
 
 
 if __name__ == "__main__":
