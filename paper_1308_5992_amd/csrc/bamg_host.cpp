@@ -144,6 +144,7 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
       bytes += n * n * zc + (dense_mm_workspace((int)n, (int)cap) + gj_workspace((int)n)) * z + n * sizeof(int);
   }
   const size_t n0 = N * N, kd = p->restart;
+  if (mg && cap >= (size_t)IL_MIN) bytes += 2 * n0 * cap * zm;  // interleaved level-0 x and b
   bytes += (2 * kd + 5) * n0 * z;  // FGMRES bases and vectors, one right-hand side
   if (mg) bytes += n0 * k * z;     // saved test vectors
   if (ne) {                        // eigensolver blocks
@@ -165,6 +166,8 @@ size_t bamg::hierarchy_slot_extra_bytes(const bamg_params* p, int slots) {
   if (S <= cap) return 0;
   const size_t zm = sizeof(zd) + (p->precision != BAMG_FP64 ? sizeof(zf) : 0);
   size_t bytes = 0;
+  const size_t n0 = (size_t)sh.ext[0].first * sh.ext[0].second * 2;
+  if (S >= (size_t)IL_MIN) bytes += 2 * n0 * (S - (cap >= (size_t)IL_MIN ? cap : 0)) * zm;  // interleaved level 0
   for (int l = 0; l < L; ++l) {
     const size_t n = (size_t)sh.ext[l].first * sh.ext[l].second * (l == 0 ? 2 : 16);
     bytes += 3 * n * (S - cap) * zm;  // the level work vectors grow to S right-hand sides
@@ -327,7 +330,8 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         break;
       case BAMG_OP_SWEEP:
         if (h->coarsest(l) && h->L() > 1) return fail(BAMG_EINVAL, "no smoother on the coarsest level");
-        h->sweep(l, xo, xi, nrhs);
+        if (nrhs > h->cap && nrhs >= IL_MIN) h->ensure_cap(nrhs);
+        h->smooth(l, xo, xi, nrhs, 1);
         break;
       case BAMG_OP_RESTRICT:
         if (h->coarsest(l)) return fail(BAMG_EINVAL, "no restriction from the coarsest level");
@@ -397,15 +401,15 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         switch (h->p.precision) {
           case BAMG_MIXED_FP16:
             if (is_apply) h->apply32<hcx>(l, bi, xw, nullptr, nrhs);
-            else h->sweep32<hcx>(l, xw, bi, nrhs);
+            else h->smooth32<hcx>(l, xw, bi, nrhs, 1);
             break;
           case BAMG_MIXED_BF16:
             if (is_apply) h->apply32<bcx>(l, bi, xw, nullptr, nrhs);
-            else h->sweep32<bcx>(l, xw, bi, nrhs);
+            else h->smooth32<bcx>(l, xw, bi, nrhs, 1);
             break;
           default:
             if (is_apply) h->apply32<zf>(l, bi, xw, nullptr, nrhs);
-            else h->sweep32<zf>(l, xw, bi, nrhs);
+            else h->smooth32<zf>(l, xw, bi, nrhs, 1);
             break;
         }
         if (!f32io) launch_convert(Lv.x32, xo, nn, h->s);

@@ -102,6 +102,12 @@ void launch_slot_blocks(const FineT<T>& f, cx<T>* Bst, hipStream_t s);
 template <typename T>
 void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, const cx<T>* b, int nrhs,
                           hipStream_t s, const double* lam = nullptr);
+// count fine sweeps for R >= 16 right-hand sides through the right-hand-side
+// interleaved layout (xi, bi: n R entries each; b may be NULL for b = 0);
+// bitwise the same as count sweeps of launch_kaczmarz_fine
+template <typename T>
+void launch_smooth_fine_il(const FineT<T>& f, int ncol, int per_colour, cx<T>* x, const cx<T>* b, cx<T>* xi,
+                           cx<T>* bi, int R, int count, hipStream_t s);
 // rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
 template <typename T>
 void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);

@@ -769,6 +769,155 @@ void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, c
     hipLaunchKernelGGL((k_kaczmarz_fine<T, 1>), dim3((nsites + 3) / 4, nrhs), dim3(64), 0, s, f, colour, nsites, x, b,
                        lam, nrhs);
 }
+// ---------------------------------------------------------------------------
+// The colour pass on right-hand-side-interleaved vectors, xi[(site*2 + s)*R + r]:
+// a lane is one right-hand side of one site (16, 32 or 64 lanes per site), so
+// that every support entry of a site is one contiguous run of R entries.  Each
+// lane adds the slot terms in the pair order of the 16-lane butterfly of
+// k_kaczmarz_fine (slots 9-15 contributing +0), and every product has the same
+// fixed contraction, so the result is bitwise that of k_kaczmarz_fine.
+// ---------------------------------------------------------------------------
+// lane 0 of the 16-lane butterfly (xor 8, 4, 2, 1) over slots 0..8 with the
+// inactive lanes 9..15 holding z
+template <typename T>
+__device__ __forceinline__ cx<T> tree9(const cx<T> (&v)[9], cx<T> z) {
+  cx<T> t8[8], t4[4];
+  t8[0] = v[0] + v[8];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) t8[i] = v[i] + z;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t4[i] = t8[i] + t8[i + 4];
+  return (t4[0] + t4[2]) + (t4[1] + t4[3]);
+}
+
+template <typename T, int RL>
+__global__ __launch_bounds__(64) void k_kaczmarz_fine_il(FineT<T> f, int colour, int nsites, cx<T>* __restrict__ xi,
+                                                         const cx<T>* __restrict__ bi, int R) {
+  using C = cx<T>;
+  constexpr int SPW = 64 / RL;  // sites per wave
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x * SPW + lane / RL;
+  const int r = blockIdx.y * RL + lane % RL;
+  if (t >= nsites || r >= R) return;  // no cross-lane operations below
+  int px, y;
+  fine_colour_site(colour, t, f.N, px, y);
+  const int i = y * f.NH + (px >> 1);
+  const C* bst = f.Bst + (size_t)i * 9 * 4;
+  int jn[9];
+#pragma unroll
+  for (int sl = 0; sl < 9; ++sl) jn[sl] = hidx(px + nib(SLOT_DX2, sl) - 2, y + nib(SLOT_DY2, sl) - 2, f.N, f.NH);
+  // what the inactive lanes of the butterfly contribute: products of zeros
+  const C c00 = cmul_fixed(C{0, 0}, C{0, 0}), j00 = cjmul_fixed(C{0, 0}, C{0, 0});
+  const T n00 = norm2_fixed(C{0, 0});
+  C nu, g10, r0, r1;
+  {  // row norms and G_10 of the site
+    C vn[9], vg[9];
+#pragma unroll
+    for (int sl = 0; sl < 9; ++sl) {
+      const C B00 = bst[sl * 4], B01 = bst[sl * 4 + 1], B10 = bst[sl * 4 + 2], B11 = bst[sl * 4 + 3];
+      vn[sl] = C{norm2_fixed(B00) + norm2_fixed(B01), norm2_fixed(B10) + norm2_fixed(B11)};
+      vg[sl] = cjmul_fixed(B00, B10) + cjmul_fixed(B01, B11);
+    }
+    nu = tree9(vn, C{n00 + n00, n00 + n00});
+    g10 = tree9(vg, j00 + j00);
+  }
+  {  // D x on the site's two rows
+    C v0[9], v1[9];
+#pragma unroll
+    for (int sl = 0; sl < 9; ++sl) {
+      const C B00 = bst[sl * 4], B01 = bst[sl * 4 + 1], B10 = bst[sl * 4 + 2], B11 = bst[sl * 4 + 3];
+      const C x0 = xi[((size_t)jn[sl] * 2) * R + r], x1 = xi[((size_t)jn[sl] * 2 + 1) * R + r];
+      v0[sl] = cmul_fixed(B00, x0) + cmul_fixed(B01, x1);
+      v1[sl] = cmul_fixed(B10, x0) + cmul_fixed(B11, x1);
+    }
+    r0 = tree9(v0, c00 + c00);
+    r1 = tree9(v1, c00 + c00);
+  }
+  C b0 = {0, 0}, b1 = {0, 0};
+  if (bi) {
+    b0 = bi[((size_t)i * 2) * R + r];
+    b1 = bi[((size_t)i * 2 + 1) * R + r];
+  }
+  const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
+  const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+  // update: the supports of the colour's sites are disjoint, so the entries
+  // read above are still this lane's and are read again from the cache
+#pragma unroll
+  for (int sl = 0; sl < 9; ++sl) {
+    const C B00 = bst[sl * 4], B01 = bst[sl * 4 + 1], B10 = bst[sl * 4 + 2], B11 = bst[sl * 4 + 3];
+    C* p0 = xi + ((size_t)jn[sl] * 2) * R + r;
+    C* p1 = xi + ((size_t)jn[sl] * 2 + 1) * R + r;
+    const C x0 = *p0, x1 = *p1;
+    *p0 = (x0 + cjmul_fixed(B00, a0)) + cjmul_fixed(B10, a1);
+    *p1 = (x1 + cjmul_fixed(B01, a0)) + cjmul_fixed(B11, a1);
+  }
+}
+
+// out[j * R + r] = in[r * n + j] (to_il) or back; 32 x 32 tiles through LDS
+template <typename C>
+__global__ __launch_bounds__(256) void k_transpose_rhs(const C* __restrict__ in, C* __restrict__ out, size_t n, int R,
+                                                       bool to_il) {
+  __shared__ C tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const size_t j0 = (size_t)blockIdx.x * 32;
+  const int r0 = blockIdx.y * 32;
+  if (to_il) {
+    for (int k = ty; k < 32; k += 8) {  // read rows r of [R][n] along j
+      const int r = r0 + k;
+      const size_t j = j0 + tx;
+      if (r < R && j < n) tile[k][tx] = in[(size_t)r * n + j];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {  // write rows j of [n][R] along r
+      const size_t j = j0 + k;
+      const int r = r0 + tx;
+      if (r < R && j < n) out[j * R + r] = tile[tx][k];
+    }
+  } else {
+    for (int k = ty; k < 32; k += 8) {
+      const size_t j = j0 + k;
+      const int r = r0 + tx;
+      if (r < R && j < n) tile[tx][k] = in[j * R + r];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      const int r = r0 + k;
+      const size_t j = j0 + tx;
+      if (r < R && j < n) out[(size_t)r * n + j] = tile[k][tx];
+    }
+  }
+}
+
+// count sweeps on level 0 for R right-hand sides through the interleaved
+// layout: x and b ([R][n]) are transposed into xi and bi, swept, and x is
+// transposed back
+template <typename T>
+void launch_smooth_fine_il(const FineT<T>& f, int ncol, int per_colour, cx<T>* x, const cx<T>* b, cx<T>* xi,
+                           cx<T>* bi, int R, int count, hipStream_t s) {
+  const size_t n = (size_t)f.N * f.NH * 2;
+  const dim3 tg((unsigned)((n + 31) / 32), (unsigned)((R + 31) / 32));
+  hipLaunchKernelGGL((k_transpose_rhs<cx<T>>), tg, dim3(256), 0, s, x, xi, n, R, true);
+  if (b) hipLaunchKernelGGL((k_transpose_rhs<cx<T>>), tg, dim3(256), 0, s, b, bi, n, R, true);
+  const cx<T>* bb = b ? bi : nullptr;
+  for (int it = 0; it < count; ++it)
+    for (int c = 0; c < ncol; ++c) {
+      if (R <= 16)
+        hipLaunchKernelGGL((k_kaczmarz_fine_il<T, 16>), dim3((per_colour + 3) / 4, 1), dim3(64), 0, s, f, c,
+                           per_colour, xi, bb, R);
+      else if (R <= 32)
+        hipLaunchKernelGGL((k_kaczmarz_fine_il<T, 32>), dim3((per_colour + 1) / 2, 1), dim3(64), 0, s, f, c,
+                           per_colour, xi, bb, R);
+      else
+        hipLaunchKernelGGL((k_kaczmarz_fine_il<T, 64>), dim3(per_colour, (R + 63) / 64), dim3(64), 0, s, f, c,
+                           per_colour, xi, bb, R);
+    }
+  hipLaunchKernelGGL((k_transpose_rhs<cx<T>>), tg, dim3(256), 0, s, xi, x, n, R, false);
+}
+template void launch_smooth_fine_il<double>(const FineT<double>&, int, int, zd*, const zd*, zd*, zd*, int, int,
+                                            hipStream_t);
+template void launch_smooth_fine_il<float>(const FineT<float>&, int, int, zf*, const zf*, zf*, zf*, int, int,
+                                           hipStream_t);
+
 template void launch_kaczmarz_fine<double>(const FineT<double>&, int, int, zd*, const zd*, int, hipStream_t,
                                            const double*);
 template void launch_kaczmarz_fine<float>(const FineT<float>&, int, int, zf*, const zf*, int, hipStream_t,

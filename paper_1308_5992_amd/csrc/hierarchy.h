@@ -56,6 +56,9 @@ inline int floor_mod(int a, int n) { return ((a % n) + n) % n; }
 
 // right-hand sides from which the smoothers use their multi-RHS kernels
 constexpr int MR_MIN = 4;
+// from this many right-hand sides the level-0 smoothing sweeps run on
+// right-hand-side-interleaved copies of x and b (launch_smooth_fine_il)
+constexpr int IL_MIN = 16;
 
 // ---- multicolour orderings (Sec. 3.1 leaves the colouring open) -------------
 // fine even site (x, y): 4 * (((x+y)/2) mod 4) + (((x-y)/2) mod 4); 16 colours
@@ -115,6 +118,9 @@ struct bamg_hierarchy {
   // side's arithmetic does not depend on how many others share the batch
   bool force_mr = false;
   zd* mmwork = nullptr;  // split-K partials of the coarsest product, cap right-hand sides
+  // level-0 right-hand-side-interleaved x and b for the smoothing sweeps (cap >= IL_MIN)
+  zd *xil = nullptr, *bil = nullptr;
+  zf *xil32 = nullptr, *bil32 = nullptr;
   // coarsest inversion scratch
   zd* gjcol = nullptr;
   int* gjperm = nullptr;
@@ -228,6 +234,7 @@ struct bamg_hierarchy {
       dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
     }
     dfree(mmwork);
+    dfree(xil); dfree(bil); dfree(xil32); dfree(bil32);
     dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(Bst); dfree(Bst32); dfree(gjcol); dfree(gjperm); dfree(dflag);
     if (hflag) (void)hipHostFree(hflag);
     free_krylov();
@@ -252,6 +259,17 @@ struct bamg_hierarchy {
     dfree(mmwork);
     mmwork = nullptr;
     if (L() > 1) mmwork = dalloc<zd>(dense_mm_workspace((int)lv.back().n, nrhs));
+    dfree(xil); dfree(bil); dfree(xil32); dfree(bil32);
+    xil = bil = nullptr;
+    xil32 = bil32 = nullptr;
+    if (nrhs >= IL_MIN) {
+      xil = dalloc<zd>(lv[0].n * nrhs);
+      bil = dalloc<zd>(lv[0].n * nrhs);
+      if (mixed()) {
+        xil32 = dalloc<zf>(lv[0].n * nrhs);
+        bil32 = dalloc<zf>(lv[0].n * nrhs);
+      }
+    }
     for (auto& Lv : lv) {
       dfree(Lv.x); dfree(Lv.b); dfree(Lv.r);
       dfree(Lv.x32); dfree(Lv.b32); dfree(Lv.r32);
@@ -282,6 +300,16 @@ struct bamg_hierarchy {
     }
     check_launch();
   }
+  // count sweeps on level l; on level 0 from IL_MIN right-hand sides through
+  // the interleaved copies (the same bits as count calls of sweep)
+  void smooth(int l, zd* x, const zd* b, int nrhs, int count) {
+    if (l == 0 && nrhs >= IL_MIN && xil && nrhs <= cap) {
+      launch_smooth_fine_il(f, lv[0].ncol, lv[0].per_colour, x, b, xil, bil, nrhs, count, s);
+      check_launch();
+      return;
+    }
+    for (int i = 0; i < count; ++i) sweep(l, x, b, nrhs);
+  }
   void restrict_(int l, const zd* r, zd* rc, int nrhs) {
     if (l == 0) launch_restrict_fine(f, lv[0].P, r, rc, nrhs, s);
     else launch_restrict_coarse(lv[l].ex, lv[l].ey, lv[l].P, r, rc, nrhs, s);
@@ -304,7 +332,7 @@ struct bamg_hierarchy {
   // post-smoothing; Sec. 1 two-grid scheme applied recursively, Sec. 4)
   void cycle(int l, const zd* b, zd* x, int nrhs) {
     if (L() == 1) {  // one level: the cycle reduces to its smoothing sweeps
-      for (int i = 0; i < p.pre + p.post; ++i) sweep(0, x, b, nrhs);
+      smooth(0, x, b, nrhs, p.pre + p.post);
       return;
     }
     if (coarsest(l)) {
@@ -313,7 +341,7 @@ struct bamg_hierarchy {
     }
     Level& Lv = lv[l];
     Level& C = lv[l + 1];
-    for (int i = 0; i < p.pre; ++i) sweep(l, x, b, nrhs);
+    smooth(l, x, b, nrhs, p.pre);
     apply(l, x, Lv.r, b, nrhs);  // r = b - A x
     restrict_(l, Lv.r, C.b, nrhs);
     launch_fill_zero(C.x, C.n * nrhs, s);
@@ -323,7 +351,7 @@ struct bamg_hierarchy {
       if (coarsest(l + 1)) break;
     }
     prolong(l, C.x, x, nrhs);
-    for (int i = 0; i < p.post; ++i) sweep(l, x, b, nrhs);
+    smooth(l, x, b, nrhs, p.post);
   }
 
   // ------------------------------------------------ mixed-precision cycle
@@ -356,9 +384,17 @@ struct bamg_hierarchy {
     }
   }
   template <typename S>
+  void smooth32(int l, zf* x, const zf* b, int nrhs, int count) {
+    if (l == 0 && nrhs >= IL_MIN && xil32 && nrhs <= cap) {
+      launch_smooth_fine_il(f32, lv[0].ncol, lv[0].per_colour, x, b, xil32, bil32, nrhs, count, s);
+      return;
+    }
+    for (int i = 0; i < count; ++i) sweep32<S>(l, x, b, nrhs);
+  }
+  template <typename S>
   void cycle32(int l, const zf* b, zf* x, int nrhs) {
     if (L() == 1) {
-      for (int i = 0; i < p.pre + p.post; ++i) sweep32<S>(0, x, b, nrhs);
+      smooth32<S>(0, x, b, nrhs, p.pre + p.post);
       check_launch();
       return;
     }
@@ -377,7 +413,7 @@ struct bamg_hierarchy {
     }
     Level& Lv = lv[l];
     Level& C = lv[l + 1];
-    for (int i = 0; i < p.pre; ++i) sweep32<S>(l, x, b, nrhs);
+    smooth32<S>(l, x, b, nrhs, p.pre);
     apply32<S>(l, x, Lv.r32, b, nrhs);
     if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s);
     else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s);
@@ -389,7 +425,7 @@ struct bamg_hierarchy {
     }
     if (l == 0) launch_prolong_fine(f32, Lv.P32, C.x32, x, nrhs, s);
     else launch_prolong_coarse(Lv.ex, Lv.ey, Lv.P32, C.x32, x, nrhs, s);
-    for (int i = 0; i < p.post; ++i) sweep32<S>(l, x, b, nrhs);
+    smooth32<S>(l, x, b, nrhs, p.post);
     check_launch();
   }
   // z = M v for nrhs FP64 level-0 vectors through the FP32 cycle

@@ -126,9 +126,10 @@ def test_eo_reduce_reconstruct(bamg, N, nrhs):
     assert rel(host(x), oracle.eo_reconstruct(U, m, b, xe).reshape(nrhs, -1)) < 1e-13
 
 
-@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (64, 17)])
+@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (40, 16), (64, 17), (64, 40), (40, 70)])
 def test_fine_kaczmarz_sweep(bamg, N, nrhs):
-    """nrhs >= 4 runs the multi-RHS kernel (slot blocks shared by 16 RHS)."""
+    """From 16 right-hand sides the sweeps run on right-hand-side-interleaved
+    copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64)."""
     log(f"kaczmarz fine N={N}")
     U = inputs.gauge_random(N, 7)
     m = 0.02
@@ -140,6 +141,27 @@ def test_fine_kaczmarz_sweep(bamg, N, nrhs):
         bamg.bamg_level_op(h, 0, bamg.OP_SWEEP, dev(b), x, nrhs)
     ref = oracle.kaczmarz_fine(U, m, x0, b, sweeps=2).reshape(nrhs, -1)
     assert rel(host(x), ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 3])
+def test_fine_sweep_batch_gives_the_same_bits(bamg, prec):
+    """20 right-hand sides take the interleaved sweep, one alone the plain one:
+    the same bits (each lane adds the slot terms in the butterfly's order)."""
+    N, R = 64, 20
+    U = inputs.gauge_random(N, 27)
+    h = make_h(bamg, U, 0.02, n_levels=1, precision=prec)
+    dt = torch.complex64 if prec else torch.complex128
+    op = bamg.OP_SWEEP_F32 if prec else bamg.OP_SWEEP
+    X = torch.from_numpy(inputs.gaussian((R, N * N), 28)).to("cuda:0").to(dt)
+    B = torch.from_numpy(inputs.gaussian((R, N * N), 29)).to("cuda:0").to(dt)
+    X1 = X.clone()
+    for _ in range(2):
+        bamg.bamg_level_op(h, 0, op, B, X, R)
+    for r in (0, 7, 19):
+        x1 = X1[r:r + 1].contiguous()
+        for _ in range(2):
+            bamg.bamg_level_op(h, 0, op, B[r:r + 1].contiguous(), x1, 1)
+        assert torch.equal(x1[0], X[r]), r
 
 
 def test_philox_test_vectors(bamg):
