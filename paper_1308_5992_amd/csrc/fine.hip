@@ -770,69 +770,72 @@ void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, c
                        lam, nrhs);
 }
 // ---------------------------------------------------------------------------
-// The colour pass on right-hand-side-interleaved vectors, xi[(site*2 + s)*R + r]:
-// a lane is one right-hand side of one site (16, 32 or 64 lanes per site), so
-// that every support entry of a site is one contiguous run of R entries.  Each
-// lane adds the slot terms in the pair order of the 16-lane butterfly of
-// k_kaczmarz_fine (slots 9-15 contributing +0), and every product has the same
+// The colour pass on right-hand-side-interleaved vectors, xi[(site*2 + s)*R + r],
+// so that every support entry of a site is one contiguous run of R entries.
+// The slot terms are added in the pair order of the 16-lane butterfly of
+// k_kaczmarz_fine (slots 9-15 contributing +0) and every product has the same
 // fixed contraction, so the result is bitwise that of k_kaczmarz_fine.
 // ---------------------------------------------------------------------------
-// lane 0 of the 16-lane butterfly (xor 8, 4, 2, 1) over slots 0..8 with the
-// inactive lanes 9..15 holding z
+// Four lanes per (site, right-hand side): lane q = lane / 16 takes the slots
+// q and q + 4 (and 8 for q = 0), the 16 lanes of a quarter are 16
+// consecutive right-hand sides.  A lane forms t4[q] = (v[q] + v'[q]) +
+// (v[q+4] + z) of the butterfly, with v'[0] = v[8] and v'[q] = z otherwise;
+// two exchanges (quarters q ^ 2, then q ^ 1) finish the butterfly in its own
+// pair order, so the sums are bitwise those of k_kaczmarz_fine.
 template <typename T>
-__device__ __forceinline__ cx<T> tree9(const cx<T> (&v)[9], cx<T> z) {
-  cx<T> t8[8], t4[4];
-  t8[0] = v[0] + v[8];
-#pragma unroll
-  for (int i = 1; i < 8; ++i) t8[i] = v[i] + z;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) t4[i] = t8[i] + t8[i + 4];
-  return (t4[0] + t4[2]) + (t4[1] + t4[3]);
+__device__ __forceinline__ cx<T> quarter_sum(cx<T> v) {
+  v.x += __shfl_xor(v.x, 32, 64);
+  v.y += __shfl_xor(v.y, 32, 64);
+  v.x += __shfl_xor(v.x, 16, 64);
+  v.y += __shfl_xor(v.y, 16, 64);
+  return v;
 }
 
-template <typename T, int RL>
+template <typename T>
 __global__ __launch_bounds__(64) void k_kaczmarz_fine_il(FineT<T> f, int colour, int nsites, cx<T>* __restrict__ xi,
                                                          const cx<T>* __restrict__ bi, int R) {
   using C = cx<T>;
-  constexpr int SPW = 64 / RL;  // sites per wave
-  const int lane = threadIdx.x;
-  const int t = blockIdx.x * SPW + lane / RL;
-  const int r = blockIdx.y * RL + lane % RL;
-  if (t >= nsites || r >= R) return;  // no cross-lane operations below
+  const int lane = threadIdx.x, q = lane >> 4;
+  const int t = blockIdx.x;
+  const int r = blockIdx.y * 16 + (lane & 15);
+  if (t >= nsites || r >= R) return;  // the four lanes of a (site, r) leave together
   int px, y;
   fine_colour_site(colour, t, f.N, px, y);
   const int i = y * f.NH + (px >> 1);
   const C* bst = f.Bst + (size_t)i * 9 * 4;
-  int jn[9];
-#pragma unroll
-  for (int sl = 0; sl < 9; ++sl) jn[sl] = hidx(px + nib(SLOT_DX2, sl) - 2, y + nib(SLOT_DY2, sl) - 2, f.N, f.NH);
-  // what the inactive lanes of the butterfly contribute: products of zeros
+  const int sa = q, sb = q + 4;  // this lane's slots; quarter 0 also takes slot 8
+  const int ja = hidx(px + nib(SLOT_DX2, sa) - 2, y + nib(SLOT_DY2, sa) - 2, f.N, f.NH);
+  const int jb = hidx(px + nib(SLOT_DX2, sb) - 2, y + nib(SLOT_DY2, sb) - 2, f.N, f.NH);
+  const int j8 = hidx(px + nib(SLOT_DX2, 8) - 2, y + nib(SLOT_DY2, 8) - 2, f.N, f.NH);
   const C c00 = cmul_fixed(C{0, 0}, C{0, 0}), j00 = cjmul_fixed(C{0, 0}, C{0, 0});
   const T n00 = norm2_fixed(C{0, 0});
-  C nu, g10, r0, r1;
-  {  // row norms and G_10 of the site
-    C vn[9], vg[9];
+  const C zr = c00 + c00, zg = j00 + j00, zn = C{n00 + n00, n00 + n00};
+  auto ld = [&](int j, int sp) { return xi[((size_t)j * 2 + sp) * R + r]; };
+  // slot terms: rows of D x, row norms, G_10
+  C B[3][4], X0[3], X1[3];
+  const int js[3] = {ja, jb, j8};
+  const int ss[3] = {sa, sb, 8};
 #pragma unroll
-    for (int sl = 0; sl < 9; ++sl) {
-      const C B00 = bst[sl * 4], B01 = bst[sl * 4 + 1], B10 = bst[sl * 4 + 2], B11 = bst[sl * 4 + 3];
-      vn[sl] = C{norm2_fixed(B00) + norm2_fixed(B01), norm2_fixed(B10) + norm2_fixed(B11)};
-      vg[sl] = cjmul_fixed(B00, B10) + cjmul_fixed(B01, B11);
-    }
-    nu = tree9(vn, C{n00 + n00, n00 + n00});
-    g10 = tree9(vg, j00 + j00);
-  }
-  {  // D x on the site's two rows
-    C v0[9], v1[9];
+  for (int k = 0; k < 3; ++k) {
+    const int sl = ss[k];
 #pragma unroll
-    for (int sl = 0; sl < 9; ++sl) {
-      const C B00 = bst[sl * 4], B01 = bst[sl * 4 + 1], B10 = bst[sl * 4 + 2], B11 = bst[sl * 4 + 3];
-      const C x0 = xi[((size_t)jn[sl] * 2) * R + r], x1 = xi[((size_t)jn[sl] * 2 + 1) * R + r];
-      v0[sl] = cmul_fixed(B00, x0) + cmul_fixed(B01, x1);
-      v1[sl] = cmul_fixed(B10, x0) + cmul_fixed(B11, x1);
-    }
-    r0 = tree9(v0, c00 + c00);
-    r1 = tree9(v1, c00 + c00);
+    for (int e = 0; e < 4; ++e) B[k][e] = bst[sl * 4 + e];
+    X0[k] = ld(js[k], 0);
+    X1[k] = ld(js[k], 1);
   }
+  C w0[3], w1[3], wn[3], wg[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w0[k] = cmul_fixed(B[k][0], X0[k]) + cmul_fixed(B[k][1], X1[k]);
+    w1[k] = cmul_fixed(B[k][2], X0[k]) + cmul_fixed(B[k][3], X1[k]);
+    wn[k] = C{norm2_fixed(B[k][0]) + norm2_fixed(B[k][1]), norm2_fixed(B[k][2]) + norm2_fixed(B[k][3])};
+    wg[k] = cjmul_fixed(B[k][0], B[k][2]) + cjmul_fixed(B[k][1], B[k][3]);
+  }
+  const bool q0 = q == 0;
+  const C r0 = quarter_sum((w0[0] + (q0 ? w0[2] : zr)) + (w0[1] + zr));
+  const C r1 = quarter_sum((w1[0] + (q0 ? w1[2] : zr)) + (w1[1] + zr));
+  const C nu = quarter_sum((wn[0] + (q0 ? wn[2] : zn)) + (wn[1] + zn));
+  const C g10 = quarter_sum((wg[0] + (q0 ? wg[2] : zg)) + (wg[1] + zg));
   C b0 = {0, 0}, b1 = {0, 0};
   if (bi) {
     b0 = bi[((size_t)i * 2) * R + r];
@@ -840,16 +843,11 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine_il(FineT<T> f, int colour,
   }
   const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
   const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
-  // update: the supports of the colour's sites are disjoint, so the entries
-  // read above are still this lane's and are read again from the cache
 #pragma unroll
-  for (int sl = 0; sl < 9; ++sl) {
-    const C B00 = bst[sl * 4], B01 = bst[sl * 4 + 1], B10 = bst[sl * 4 + 2], B11 = bst[sl * 4 + 3];
-    C* p0 = xi + ((size_t)jn[sl] * 2) * R + r;
-    C* p1 = xi + ((size_t)jn[sl] * 2 + 1) * R + r;
-    const C x0 = *p0, x1 = *p1;
-    *p0 = (x0 + cjmul_fixed(B00, a0)) + cjmul_fixed(B10, a1);
-    *p1 = (x1 + cjmul_fixed(B01, a0)) + cjmul_fixed(B11, a1);
+  for (int k = 0; k < 3; ++k) {
+    if (k == 2 && !q0) break;
+    xi[((size_t)js[k] * 2) * R + r] = (X0[k] + cjmul_fixed(B[k][0], a0)) + cjmul_fixed(B[k][2], a1);
+    xi[((size_t)js[k] * 2 + 1) * R + r] = (X1[k] + cjmul_fixed(B[k][1], a0)) + cjmul_fixed(B[k][3], a1);
   }
 }
 
@@ -900,17 +898,9 @@ void launch_smooth_fine_il(const FineT<T>& f, int ncol, int per_colour, cx<T>* x
   if (b) hipLaunchKernelGGL((k_transpose_rhs<cx<T>>), tg, dim3(256), 0, s, b, bi, n, R, true);
   const cx<T>* bb = b ? bi : nullptr;
   for (int it = 0; it < count; ++it)
-    for (int c = 0; c < ncol; ++c) {
-      if (R <= 16)
-        hipLaunchKernelGGL((k_kaczmarz_fine_il<T, 16>), dim3((per_colour + 3) / 4, 1), dim3(64), 0, s, f, c,
-                           per_colour, xi, bb, R);
-      else if (R <= 32)
-        hipLaunchKernelGGL((k_kaczmarz_fine_il<T, 32>), dim3((per_colour + 1) / 2, 1), dim3(64), 0, s, f, c,
-                           per_colour, xi, bb, R);
-      else
-        hipLaunchKernelGGL((k_kaczmarz_fine_il<T, 64>), dim3(per_colour, (R + 63) / 64), dim3(64), 0, s, f, c,
-                           per_colour, xi, bb, R);
-    }
+    for (int c = 0; c < ncol; ++c)
+      hipLaunchKernelGGL((k_kaczmarz_fine_il<T>), dim3(per_colour, (R + 15) / 16), dim3(64), 0, s, f, c, per_colour,
+                         xi, bb, R);
   hipLaunchKernelGGL((k_transpose_rhs<cx<T>>), tg, dim3(256), 0, s, xi, x, n, R, false);
 }
 template void launch_smooth_fine_il<double>(const FineT<double>&, int, int, zd*, const zd*, zd*, zd*, int, int,
