@@ -325,7 +325,7 @@ def main():
     if args.roofline_only:
         p = bamg.bamg_default_params(N=N, n_levels=w["n_levels"], seed=w["tv_seed"], **head_kw)
         h = bamg.bamg_setup(U, w["m"], p)
-        dom, others = roofline(bamg, torch, h, head_base, head_kw.get("coarsest_fp32", 0))
+        dom, others = roofline(bamg, torch, h, head_base, head_kw.get("coarsest_fp32", 0), p.pre + p.post)
         out = {"workload": w["name"], "precision": head_base, "roofline": dom, "roofline_others": others,
                "copy_calibration": copy_calibration(torch)}
         bamg.bamg_free(h)
@@ -453,7 +453,9 @@ def main():
 
     # ---- roofline of the dominant kernel of the solve
     if not args.no_roofline:
-        out["roofline"], out["roofline_others"] = roofline(bamg, torch, h, head_base, head_kw.get("coarsest_fp32", 0))
+        ph = bamg.bamg_default_params(**head_kw)
+        out["roofline"], out["roofline_others"] = roofline(bamg, torch, h, head_base, head_kw.get("coarsest_fp32", 0),
+                                                           ph.pre + ph.post)
         if head_base != "fp64":
             hm = next((hier[q] for q in precs if "c32" in q.split("+")[1:]), h)
             out["mfma"] = mfma_utilisation(bamg, torch, hm)
@@ -475,11 +477,25 @@ def main():
 #    Bst (storage = cycle type), its 2 right-hand-side entries and the 9 x 2
 #    unknowns of its row support read and written (the supports of one colour
 #    are disjoint, so nothing is counted twice within a launch);
+#  - fine sweep blocked in LDS (one launch per 16-colour sweep): per even site
+#    its 36 stored couplings, its 2 right-hand-side entries and its 2 unknowns
+#    read and written once (the compulsory bytes of a sweep);
 #  - coarse colour pass: per site of the colour, the 7 blocks of 16 x 16 of its
 #    rows (operator storage type), the 16 x 16 smoother matrix Kinv (cycle type),
 #    its 16 right-hand-side entries and the 7 x 16 unknowns of its support read
 #    and written;
 #  - coarsest product: the n x n FP64 inverse and the two vectors.
+def fine_sweep_site_bytes(s_vec):
+    return 36 * s_vec + 2 * s_vec + 2 * 2 * s_vec
+
+
+def fine_sweep_blocked(N, nrhs, s_vec):
+    """Whether the library runs a level-0 sweep as one launch blocked in LDS
+    (fine.hip: tiles need N >= 64 and N/2 a multiple of 8, and x of at most
+    1 MiB)."""
+    return N >= 64 and N % 16 == 0 and N * N * nrhs * s_vec <= 1 << 20
+
+
 def fine_site_bytes(s_vec):
     return 36 * s_vec + 2 * s_vec + 2 * 9 * 2 * s_vec
 
@@ -532,30 +548,44 @@ def _roof(kname, kind, prec, bytes_launch, t):
             "avg_launch_us": t * 1e6, "bytes_per_launch": bytes_launch}
 
 
-def roofline(bamg, torch, h, prec, c32=0):
-    """The three kernels that take the solve's time, each timed with HIP events
-    on the library's stream (torch's current stream) over back-to-back
-    launches driven through the level hooks: the fine colour pass (the
-    largest share; 16 launches per sweep), the coarse colour pass on level 1
-    (ncol launches per sweep) and the coarsest dense product (one launch per
-    call).  A mixed hierarchy is driven through the complex64 hooks, which
-    launch exactly the colour passes of one sweep and nothing else.  The
-    coarsest product is the FP64 inverse's (op 4) or, with c32, its FP32
-    copy's (op 12).  Returns (dominant, [others])."""
+def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
+    """The kernels that take the solve's time, each timed with HIP events on
+    the library's stream (torch's current stream) over back-to-back calls of
+    the level hooks: the fine smoother on level 0, the coarse colour pass on
+    level 1 (ncol launches per sweep) and the coarsest dense product (one
+    launch per call).  A mixed hierarchy is driven through the complex64 hooks.
+    The fine smoother is either 16 colour passes per sweep or, where the
+    library blocks the sweep in LDS, one launch per sweep; the hook then also
+    copies x once (it keeps x in place, the kernel writes a second copy), so
+    the time per call is an upper bound of the kernel's.  The coarsest product
+    is the FP64 inverse's (op 4) or, with c32, its FP32 copy's (op 12).
+    `sweeps` is the smoothing sweeps per cycle (pre + post); the dominant
+    kernel is the one with the largest time per cycle.  Returns (dominant,
+    [others])."""
     mixed = prec != "fp64"
     dt = torch.complex64 if mixed else torch.complex128
     sweep = bamg.OP_SWEEP_F32 if mixed else bamg.OP_SWEEP
     tname = "float" if mixed else "double"
     sname = {"fp64": "cx<double>", "mixed_fp32": "cx<float>", "mixed_fp16": "hcx", "mixed_bf16": "bcx"}[prec]
-    out = []
-    # fine pass, level 0
+    out = []  # (entry, time per cycle)
+    # fine smoother, level 0
     inf = bamg.bamg_level_info(h, 0)
-    nsite = inf["n"] // 2 // 16  # even sites per colour
+    N = int(round(inf["n"] ** 0.5))  # level 0: N^2 / 2 even sites, 2 unknowns each
+    sv = VEC_BYTES[prec]
     xb = torch.zeros(inf["n"], dtype=dt, device="cuda:0")
     bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
-    t = time_launches(lambda: bamg.bamg_level_op(h, 0, sweep, bb, xb, 1), 50, 16, torch)
-    out.append(_roof(f"k_kaczmarz_fine<{tname}, 1> (level 0, {nsite} sites per launch)", "fine", prec,
-                     nsite * fine_site_bytes(VEC_BYTES[prec]), t))
+    if fine_sweep_blocked(N, 1, sv):
+        t = time_launches(lambda: bamg.bamg_level_op(h, 0, sweep, bb, xb, 1), 50, 1, torch)
+        e = _roof(f"k_kaczmarz_fine_sweep<{tname}> (level 0, one 16-colour sweep of {inf['n'] // 2} sites per launch; "
+                  f"timed per sweep call, which also copies x)", "fine_sweep", prec,
+                  inf["n"] // 2 * fine_sweep_site_bytes(sv), t)
+        out.append((e, t * sweeps))
+    else:
+        nsite = inf["n"] // 2 // 16  # even sites per colour
+        t = time_launches(lambda: bamg.bamg_level_op(h, 0, sweep, bb, xb, 1), 50, 16, torch)
+        e = _roof(f"k_kaczmarz_fine<{tname}, 1> (level 0, {nsite} sites per launch)", "fine", prec,
+                  nsite * fine_site_bytes(sv), t)
+        out.append((e, t * 16 * sweeps))
     L = bamg.bamg_n_levels(h)
     if L > 2:  # coarse pass, level 1
         inf = bamg.bamg_level_info(h, 1)
@@ -563,8 +593,9 @@ def roofline(bamg, torch, h, prec, c32=0):
         xb = torch.zeros(inf["n"], dtype=dt, device="cuda:0")
         bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
         t = time_launches(lambda: bamg.bamg_level_op(h, 1, sweep, bb, xb, 1), 50, ncol, torch)
-        out.append(_roof(f"k_kaczmarz_coarse<{tname},{sname}> (level 1, {ns // ncol} sites per launch)", "coarse",
-                         prec, ns // ncol * coarse_site_bytes(OP_BYTES[prec], VEC_BYTES[prec]), t))
+        e = _roof(f"k_kaczmarz_coarse<{tname},{sname}> (level 1, {ns // ncol} sites per launch)", "coarse",
+                  prec, ns // ncol * coarse_site_bytes(OP_BYTES[prec], sv), t)
+        out.append((e, t * ncol * sweeps))
     if L > 1:  # coarsest product
         inf = bamg.bamg_level_info(h, L - 1)
         n = inf["n"]
@@ -574,9 +605,13 @@ def roofline(bamg, torch, h, prec, c32=0):
         op = bamg.OP_COARSEST_F32 if c32 else bamg.OP_COARSEST
         t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, op, bb, xb, 1), 20, 1, torch)
         z = 8.0 if c32 else 16.0
-        out.append(_roof(f"k_dense_mv{'32' if c32 else ''} (coarsest inverse, n = {n})",
-                         "dense32" if c32 else "dense", prec, z * n * n + 2 * z * n, t))
-    return out[0], out[1:]
+        e = _roof(f"k_dense_mv{'32' if c32 else ''} (coarsest inverse, n = {n})",
+                  "dense32" if c32 else "dense", prec, z * n * n + 2 * z * n, t)
+        out.append((e, t))
+    for e, tc in out:
+        e["us_per_cycle"] = tc * 1e6
+    out.sort(key=lambda et: -et[1])
+    return out[0][0], [e for e, _ in out[1:]]
 
 
 MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix peak of the MI355X

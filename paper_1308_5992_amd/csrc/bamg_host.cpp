@@ -134,7 +134,7 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
     const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
     const size_t n = ns * (l == 0 ? 2 : 16);
     const bool last = l == L - 1;
-    bytes += 3 * n * cap * zm;  // x, b, r
+    bytes += (l == 0 ? 4 : 3) * n * cap * zm;  // x, b, r (level 0: and the second x of the blocked sweeps)
     if (!mg) break;
     bytes += n * (k + ne) * z;  // test vectors
     if (l >= 1) bytes += ns * NOFF * 256 * z;  // coarse operator
@@ -170,7 +170,7 @@ size_t bamg::hierarchy_slot_extra_bytes(const bamg_params* p, int slots) {
   if (S >= (size_t)IL_MIN) bytes += 2 * n0 * (S - (cap >= (size_t)IL_MIN ? cap : 0)) * zm;  // interleaved level 0
   for (int l = 0; l < L; ++l) {
     const size_t n = (size_t)sh.ext[l].first * sh.ext[l].second * (l == 0 ? 2 : 16);
-    bytes += 3 * n * (S - cap) * zm;  // the level work vectors grow to S right-hand sides
+    bytes += (l == 0 ? 4 : 3) * n * (S - cap) * zm;  // the level work vectors grow to S right-hand sides
     if (l == L - 1 && L > 1)
       bytes += (dense_mm_workspace((int)n, slots) - dense_mm_workspace((int)n, (int)cap)) * sizeof(zd);
   }
@@ -330,7 +330,7 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         break;
       case BAMG_OP_SWEEP:
         if (h->coarsest(l) && h->L() > 1) return fail(BAMG_EINVAL, "no smoother on the coarsest level");
-        if (nrhs > h->cap && nrhs >= IL_MIN) h->ensure_cap(nrhs);
+        if (nrhs > h->cap) h->ensure_cap(nrhs);
         h->smooth(l, xo, xi, nrhs, 1);
         break;
       case BAMG_OP_RESTRICT:

@@ -108,6 +108,22 @@ void launch_kaczmarz_fine(const FineT<T>& f, int colour, int nsites, cx<T>* x, c
 template <typename T>
 void launch_smooth_fine_il(const FineT<T>& f, int ncol, int per_colour, cx<T>* x, const cx<T>* b, cx<T>* xi,
                            cx<T>* bi, int R, int count, hipStream_t s);
+// One fine sweep (the 16 colour passes) per launch, blocked in LDS: xout is
+// bitwise what the 16 launches of launch_kaczmarz_fine make of xin.  xin and
+// xout must not overlap.  fine_sweep_applies is false where no tile plan
+// applies (small lattices, no stored slot blocks); the caller then runs the
+// colour passes.
+struct FineSweepPlan {
+  int Tu, Tv, ntu, ntv;      // tile extents in (u, v) and tile counts
+  int i0, j0, Ru, Rv;        // region origin relative to the tile origin, region extents
+  int nupd;                  // projections per tile
+  int first[17];             // first projection of colour c
+  int si0[16], sj0[16], nj[16];  // colour c: first site (relative to the tile origin), sites along v
+};
+template <typename T>
+bool fine_sweep_applies(const FineT<T>& f, int nrhs);
+template <typename T>
+void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s);
 // rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
 template <typename T>
 void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);

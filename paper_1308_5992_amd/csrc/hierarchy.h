@@ -121,6 +121,10 @@ struct bamg_hierarchy {
   // level-0 right-hand-side-interleaved x and b for the smoothing sweeps (cap >= IL_MIN)
   zd *xil = nullptr, *bil = nullptr;
   zf *xil32 = nullptr, *bil32 = nullptr;
+  // level-0 second copy of x for the sweeps blocked in LDS (they read one
+  // copy and write the other), cap right-hand sides
+  zd* xsw = nullptr;
+  zf* xsw32 = nullptr;
   // coarsest inversion scratch
   zd* gjcol = nullptr;
   int* gjperm = nullptr;
@@ -234,7 +238,7 @@ struct bamg_hierarchy {
       dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
     }
     dfree(mmwork);
-    dfree(xil); dfree(bil); dfree(xil32); dfree(bil32);
+    dfree(xil); dfree(bil); dfree(xil32); dfree(bil32); dfree(xsw); dfree(xsw32);
     dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(Bst); dfree(Bst32); dfree(gjcol); dfree(gjperm); dfree(dflag);
     if (hflag) (void)hipHostFree(hflag);
     free_krylov();
@@ -259,9 +263,11 @@ struct bamg_hierarchy {
     dfree(mmwork);
     mmwork = nullptr;
     if (L() > 1) mmwork = dalloc<zd>(dense_mm_workspace((int)lv.back().n, nrhs));
-    dfree(xil); dfree(bil); dfree(xil32); dfree(bil32);
+    dfree(xil); dfree(bil); dfree(xil32); dfree(bil32); dfree(xsw); dfree(xsw32);
     xil = bil = nullptr;
     xil32 = bil32 = nullptr;
+    xsw = dalloc<zd>(lv[0].n * nrhs);
+    xsw32 = mixed() ? dalloc<zf>(lv[0].n * nrhs) : nullptr;
     if (nrhs >= IL_MIN) {
       xil = dalloc<zd>(lv[0].n * nrhs);
       bil = dalloc<zd>(lv[0].n * nrhs);
@@ -294,20 +300,42 @@ struct bamg_hierarchy {
   }
   void sweep(int l, zd* x, const zd* b, int nrhs) {
     Level& Lv = lv[l];
+    if (l == 0 && fine_sweeps(f, x, xsw, b, nrhs, 1)) return;
     for (int c = 0; c < Lv.ncol; ++c) {
       if (l == 0) launch_kaczmarz_fine(f, c, Lv.per_colour, x, b, nrhs, s);
       else launch_kaczmarz_coarse(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
     }
     check_launch();
   }
+  // count level-0 sweeps blocked in LDS, alternating between x and xs so that
+  // the last one writes x (an odd count starts from a copy of x in xs); false
+  // if they do not apply
+  template <typename T>
+  bool fine_sweeps(const FineT<T>& ff, cx<T>* x, cx<T>* xs, const cx<T>* b, int nrhs, int count) {
+    if (!xs || nrhs > cap || count < 1 || !fine_sweep_applies(ff, nrhs)) return false;
+    cx<T>* a = x;
+    cx<T>* o = xs;
+    if (count & 1) {
+      launch_copy(reinterpret_cast<const zd*>(x), reinterpret_cast<zd*>(xs), lv[0].n * nrhs * sizeof(cx<T>) / sizeof(zd), s);
+      std::swap(a, o);
+    }
+    for (int i = 0; i < count; ++i) {
+      launch_fine_sweep(ff, a, o, b, nrhs, s);
+      std::swap(a, o);
+    }
+    check_launch();
+    return true;
+  }
   // count sweeps on level l; on level 0 from IL_MIN right-hand sides through
-  // the interleaved copies (the same bits as count calls of sweep)
+  // the interleaved copies, below that blocked in LDS where a tile plan
+  // applies (the same bits as count calls of sweep)
   void smooth(int l, zd* x, const zd* b, int nrhs, int count) {
     if (l == 0 && nrhs >= IL_MIN && xil && nrhs <= cap) {
       launch_smooth_fine_il(f, lv[0].ncol, lv[0].per_colour, x, b, xil, bil, nrhs, count, s);
       check_launch();
       return;
     }
+    if (l == 0 && fine_sweeps(f, x, xsw, b, nrhs, count)) return;
     for (int i = 0; i < count; ++i) sweep(l, x, b, nrhs);
   }
   void restrict_(int l, const zd* r, zd* rc, int nrhs) {
@@ -373,6 +401,7 @@ struct bamg_hierarchy {
   template <typename S>
   void sweep32(int l, zf* x, const zf* b, int nrhs) {
     Level& Lv = lv[l];
+    if (l == 0 && fine_sweeps(f32, x, xsw32, b, nrhs, 1)) return;
     const bool mr = force_mr || nrhs >= MR_MIN;
     for (int c = 0; c < Lv.ncol; ++c) {
       if (l == 0) {
@@ -389,6 +418,7 @@ struct bamg_hierarchy {
       launch_smooth_fine_il(f32, lv[0].ncol, lv[0].per_colour, x, b, xil32, bil32, nrhs, count, s);
       return;
     }
+    if (l == 0 && fine_sweeps(f32, x, xsw32, b, nrhs, count)) return;
     for (int i = 0; i < count; ++i) sweep32<S>(l, x, b, nrhs);
   }
   template <typename S>

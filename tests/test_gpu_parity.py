@@ -126,10 +126,13 @@ def test_eo_reduce_reconstruct(bamg, N, nrhs):
     assert rel(host(x), oracle.eo_reconstruct(U, m, b, xe).reshape(nrhs, -1)) < 1e-13
 
 
-@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (40, 16), (64, 17), (64, 40), (40, 70)])
+@pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (40, 16), (64, 17), (64, 40), (40, 70),
+                                    (80, 3), (96, 2), (128, 1)])
 def test_fine_kaczmarz_sweep(bamg, N, nrhs):
     """From 16 right-hand sides the sweeps run on right-hand-side-interleaved
-    copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64)."""
+    copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64).  Below
+    that, from N = 64 on, one launch per sweep blocked in LDS (80: 8-wide
+    tiles in v, 96: tiles of 32 in u); 16 and 40 take the colour passes."""
     log(f"kaczmarz fine N={N}")
     U = inputs.gauge_random(N, 7)
     m = 0.02
@@ -143,11 +146,16 @@ def test_fine_kaczmarz_sweep(bamg, N, nrhs):
     assert rel(host(x), ref) < 1e-12
 
 
+@pytest.mark.parametrize("N", [40, 64, 96, 256])
 @pytest.mark.parametrize("prec", [0, 3])
-def test_fine_sweep_batch_gives_the_same_bits(bamg, prec):
-    """20 right-hand sides take the interleaved sweep, one alone the plain one:
-    the same bits (each lane adds the slot terms in the butterfly's order)."""
-    N, R = 64, 20
+def test_fine_sweep_batch_gives_the_same_bits(bamg, prec, N):
+    """20 right-hand sides take the interleaved sweep; one or three of them
+    alone take the colour passes (N = 40) or the sweep blocked in LDS (from
+    N = 64): the same bits (each lane adds the slot terms in the butterfly's
+    order; the blocked sweep projects every site its tile depends on with the
+    values the colour passes give it)."""
+    R = 20
+    log(f"sweep bits N={N} prec={prec}")
     U = inputs.gauge_random(N, 27)
     h = make_h(bamg, U, 0.02, n_levels=1, precision=prec)
     dt = torch.complex64 if prec else torch.complex128
@@ -157,11 +165,11 @@ def test_fine_sweep_batch_gives_the_same_bits(bamg, prec):
     X1 = X.clone()
     for _ in range(2):
         bamg.bamg_level_op(h, 0, op, B, X, R)
-    for r in (0, 7, 19):
-        x1 = X1[r:r + 1].contiguous()
+    for r0, r1 in ((0, 1), (7, 10), (19, 20)):
+        x1 = X1[r0:r1].contiguous()
         for _ in range(2):
-            bamg.bamg_level_op(h, 0, op, B[r:r + 1].contiguous(), x1, 1)
-        assert torch.equal(x1[0], X[r]), r
+            bamg.bamg_level_op(h, 0, op, B[r0:r1].contiguous(), x1, r1 - r0)
+        assert torch.equal(x1, X[r0:r1]), (r0, r1)
 
 
 def test_philox_test_vectors(bamg):
