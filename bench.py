@@ -515,9 +515,9 @@ OP_BYTES = {"fp64": 16, "mixed_fp32": 8, "mixed_fp16": 4, "mixed_bf16": 4}
 COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 262144.0}
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
-    ("fine", "mixed_fp16"): {"src": "fine.hip",
-                             "sha256": "2311ab60fdd99bd26377791aabe194ee77a389f555ab54f859caf2f20b52a691",
-                             "fetch_kib": 766.0, "write_kib": 448.0, **COPY_SCALE},
+    ("fine_sweep", "mixed_fp16"): {"src": "fine.hip",
+                                   "sha256": "e11e4cd3b8b24a96b942e98e78b1478ac73fd27a9ea67fc357ae11e35c190809",
+                                   "fetch_kib": 9341.5, "write_kib": 640.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "648c9669d7a9f63a0e0beee951cee527d9f7a1ed39c3dced91e3f6ea4af983fe",
                                "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE},
@@ -525,8 +525,8 @@ PMC_TRAFFIC = {
                               "sha256": "091dbc73896e7f9ed78d2e01839ad407e48ffe378fcd5bb93763554a284cb777",
                               "fetch_kib": 524812.5, "write_kib": 128.0, **COPY_SCALE},
     ("dense32", "mixed_fp16"): {"src": "dense.hip",
-                                "sha256": "2b3837a67c198d055924253ea7b62e9d0fafaa1f6fed9a31a26ab11b32b1ea62",
-                                "fetch_kib": 262618.0, "write_kib": 75.0, **COPY_SCALE},
+                                "sha256": "091dbc73896e7f9ed78d2e01839ad407e48ffe378fcd5bb93763554a284cb777",
+                                "fetch_kib": 262627.1, "write_kib": 74.6, **COPY_SCALE},
 }
 
 
