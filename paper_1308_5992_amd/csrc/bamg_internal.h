@@ -124,9 +124,11 @@ template <typename T>
 bool fine_sweep_applies(const FineT<T>& f, int nrhs);
 template <typename T>
 void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s);
-// rc = P^H r (level 0 -> 1); x += P xc (level 1 -> 0)
+// rc = P^H r (level 0 -> 1), and xz = 0 (level 1, same layout) if xz != NULL;
+// x += P xc (level 1 -> 0)
 template <typename T>
-void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);
+void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s,
+                          cx<T>* xz = nullptr);
 template <typename T>
 void launch_prolong_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s);
 // D_1 = P^H Dhat P in 7-offset blocks
@@ -158,9 +160,10 @@ void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mod
 // Kinv (type T) from the stored operator (type S), computed in FP64
 template <typename T, typename S>
 void launch_kaczmarz_prep(const CoarseT<T, S>& c, cx<T>* Kinv, hipStream_t s);
-// level l (ex x ey) -> l+1 (ex/2 x ey/2)
+// level l (ex x ey) -> l+1 (ex/2 x ey/2); xz as for launch_restrict_fine
 template <typename T>
-void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s);
+void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s,
+                            cx<T>* xz = nullptr);
 template <typename T>
 void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s);
 void launch_galerkin_coarse(const Coarse& c, const zd* P, zd* Dc, hipStream_t s);
@@ -181,6 +184,11 @@ void launch_gj_unpermute(zd* A, int n, const int* perm, hipStream_t s);
 // right-hand sides, an LDS-tiled product (A read once per 32 RHS) for many
 // (or whenever `many` is set; work holds dense_mm_workspace(n, nrhs) complex)
 void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, zd* work, hipStream_t s);
+// the same product with the FP64 inverse for complex64 x and y (x widened
+// exactly, sums in FP64, y rounded to nearest): bitwise the conversions
+// around launch_dense_mv, in one launch where it takes one wave per row
+// (returns false, launching nothing, otherwise)
+bool launch_dense_mv_f32io(const zd* A, int n, const zf* x, zf* y, int nrhs, bool many, hipStream_t s);
 size_t dense_mm_workspace(int n, int nrhs);
 // FP32 operands (mixed-precision cycle): y = A x with A the n x n FP32 copy of
 // the coarsest inverse, n a multiple of 16; one wave per row for up to two
@@ -215,6 +223,8 @@ void launch_check_finite(const zd* x, size_t n, int* flag, hipStream_t s);
 // output type (round to nearest)
 template <typename Tin, typename Tout>
 void launch_convert(const Tin* in, Tout* out, size_t n, hipStream_t s);
+// out = in rounded to FP32, zero_out = 0 (n entries each)
+void launch_convert_zero(const zd* in, zf* out, zf* zero_out, size_t n, hipStream_t s);
 // batched forms over R right-hand sides: basis vector v of right-hand side r
 // at X + (v*R + r)*n, w_r at W + r*n, coefficients at stride 64 per r
 void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s);

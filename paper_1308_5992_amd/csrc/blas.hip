@@ -177,6 +177,21 @@ void launch_convert(const Tin* in, Tout* out, size_t n, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
 }
+// out = in converted, and zero_out = 0 (the same n entries): the mixed
+// preconditioner's input and its zero initial guess in one launch
+template <typename Tin, typename Tout>
+__global__ void k_convert_zero(const Tin* __restrict__ in, Tout* __restrict__ out, Tout* __restrict__ zero_out,
+                               size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    cvt(in[i], out[i]);
+    zero_out[i] = Tout{0, 0};
+  }
+}
+void launch_convert_zero(const zd* in, zf* out, zf* zero_out, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_convert_zero<zd, zf>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, zero_out, n);
+}
 template void launch_convert<zd, zf>(const zd*, zf*, size_t, hipStream_t);
 template void launch_convert<zf, zd>(const zf*, zd*, size_t, hipStream_t);
 template void launch_convert<zd, hcx>(const zd*, hcx*, size_t, hipStream_t);

@@ -566,7 +566,7 @@ void launch_kaczmarz_prep(const CoarseT<T, S>& c, cx<T>* Kinv, hipStream_t s) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_restrict_coarse(int ex, int ey, const cx<T>* __restrict__ P, const cx<T>* __restrict__ r,
-                                  cx<T>* __restrict__ rc) {
+                                  cx<T>* __restrict__ rc, cx<T>* __restrict__ xz) {
   using C = cx<T>;
   const int cex = ex / 2, cey = ey / 2;
   const int tt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -582,12 +582,14 @@ __global__ void k_restrict_coarse(int ex, int ey, const cx<T>* __restrict__ P, c
     for (int j = 0; j < 8; ++j) acc = acc + cjmul(Pa[(8 * t + j) * 8 + k], rv[site * 16 + 8 * s + j]);
   }
   rc[blockIdx.y * nc + tt] = acc;
+  if (xz) xz[blockIdx.y * nc + tt] = C{0, 0};  // the coarser level's zero initial guess
 }
 
 template <typename T>
-void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s) {
+void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s,
+                            cx<T>* xz) {
   int n = (ex / 2) * (ey / 2) * 16;
-  hipLaunchKernelGGL(k_restrict_coarse<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, ex, ey, P, r, rc);
+  hipLaunchKernelGGL(k_restrict_coarse<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, ex, ey, P, r, rc, xz);
 }
 
 template <typename T>
@@ -626,8 +628,10 @@ BAMG_COARSE_INST(float, zf)
 BAMG_COARSE_INST(float, hcx)
 BAMG_COARSE_INST(float, bcx)
 #undef BAMG_COARSE_INST
-template void launch_restrict_coarse<double>(int, int, const zd*, const zd*, zd*, int, hipStream_t);
-template void launch_restrict_coarse<float>(int, int, const zf*, const zf*, zf*, int, hipStream_t);
+template void launch_restrict_coarse<double>(int, int, const zd*, const zd*, zd*, int, hipStream_t,
+                                             zd*);
+template void launch_restrict_coarse<float>(int, int, const zf*, const zf*, zf*, int, hipStream_t,
+                                             zf*);
 template void launch_prolong_coarse<double>(int, int, const zd*, const zd*, zd*, int, hipStream_t);
 template void launch_prolong_coarse<float>(int, int, const zf*, const zf*, zf*, int, hipStream_t);
 

@@ -179,21 +179,28 @@ void launch_gj_unpermute(zd* A, int n, const int* perm, hipStream_t s) {
 }
 
 // y = A x, one wave per row
-__global__ __launch_bounds__(256) void k_dense_mv(const zd* __restrict__ A, int n, const zd* __restrict__ x,
-                                                  zd* __restrict__ y, int nrhs) {
+// V = zd, or zf for the mixed cycle: x widened exactly, y rounded to nearest
+__device__ __forceinline__ zd mv_in(const zd& v) { return v; }
+__device__ __forceinline__ zd mv_in(const zf& v) { return zd{(double)v.x, (double)v.y}; }
+__device__ __forceinline__ void mv_out(const zd& a, zd& o) { o = a; }
+__device__ __forceinline__ void mv_out(const zd& a, zf& o) { o = zf{(float)a.x, (float)a.y}; }
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_dense_mv(const zd* __restrict__ A, int n, const V* __restrict__ x,
+                                                  V* __restrict__ y, int nrhs) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + wave;
   if (row >= n) return;
   const zd* Ar = A + (size_t)row * n;
   for (int r = 0; r < nrhs; ++r) {
-    const zd* xv = x + (size_t)r * n;
+    const V* xv = x + (size_t)r * n;
     zd acc = {0, 0};
-    for (int j = lane; j < n; j += 64) acc = acc + Ar[j] * xv[j];
+    for (int j = lane; j < n; j += 64) acc = acc + Ar[j] * mv_in(xv[j]);
     for (int off = 32; off > 0; off >>= 1) {
       acc.x += __shfl_xor(acc.x, off, 64);
       acc.y += __shfl_xor(acc.y, off, 64);
     }
-    if (lane == 0) y[(size_t)r * n + row] = acc;
+    if (lane == 0) mv_out(acc, y[(size_t)r * n + row]);
   }
 }
 
@@ -373,9 +380,15 @@ __global__ __launch_bounds__(256) void k_dense_mm64(const zd* __restrict__ A, in
 
 size_t dense_mm_workspace(int n, int nrhs) { return (size_t)MM_SPLIT * n * nrhs; }
 
+bool launch_dense_mv_f32io(const zd* A, int n, const zf* x, zf* y, int nrhs, bool many, hipStream_t s) {
+  if (many || nrhs > 2) return false;
+  hipLaunchKernelGGL(k_dense_mv<zf>, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y, nrhs);
+  return true;
+}
+
 void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many, zd* work, hipStream_t s) {
   if (!many && nrhs <= 2) {
-    hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y, nrhs);
+    hipLaunchKernelGGL(k_dense_mv<zd>, dim3((n + 3) / 4), dim3(256), 0, s, A, n, x, y, nrhs);
   } else if (n % 16 == 0) {
     const int nch = (n + M64_KC - 1) / M64_KC;
     const int cps = (nch + MM_SPLIT - 1) / MM_SPLIT;

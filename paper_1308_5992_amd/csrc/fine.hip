@@ -1276,7 +1276,8 @@ template void launch_kaczmarz_fine<float>(const FineT<float>&, int, int, zf*, co
 // local row 4*ly + lx.  rc[a][8s + k] = sum_row conj(P[a][s][row][k]) r[site][s].
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_restrict_fine(FineT<T> f, const cx<T>* __restrict__ P, const cx<T>* __restrict__ r, cx<T>* __restrict__ rc) {
+__global__ void k_restrict_fine(FineT<T> f, const cx<T>* __restrict__ P, const cx<T>* __restrict__ r, cx<T>* __restrict__ rc,
+                                cx<T>* __restrict__ xz) {
   using C = cx<T>;
   const int cxn = f.NH / 4, cyn = f.N / 4;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1293,12 +1294,14 @@ __global__ void k_restrict_fine(FineT<T> f, const cx<T>* __restrict__ P, const c
     acc = acc + cjmul(Pa[row * 8 + k], rv[2 * e + s]);
   }
   rc[blockIdx.y * nc + t] = acc;
+  if (xz) xz[blockIdx.y * nc + t] = C{0, 0};  // the coarse level's zero initial guess
 }
 
 template <typename T>
-void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s) {
+void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<T>* rc, int nrhs, hipStream_t s,
+                          cx<T>* xz) {
   int n = (f.NH / 4) * (f.N / 4) * 16;
-  hipLaunchKernelGGL(k_restrict_fine<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, r, rc);
+  hipLaunchKernelGGL(k_restrict_fine<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, r, rc, xz);
 }
 
 template <typename T>
@@ -1323,8 +1326,10 @@ void launch_prolong_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* xc, cx<
   int n = f.N * f.NH * 2;
   hipLaunchKernelGGL(k_prolong_fine<T>, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, f, P, xc, x);
 }
-template void launch_restrict_fine<double>(const FineT<double>&, const zd*, const zd*, zd*, int, hipStream_t);
-template void launch_restrict_fine<float>(const FineT<float>&, const zf*, const zf*, zf*, int, hipStream_t);
+template void launch_restrict_fine<double>(const FineT<double>&, const zd*, const zd*, zd*, int, hipStream_t,
+                                           zd*);
+template void launch_restrict_fine<float>(const FineT<float>&, const zf*, const zf*, zf*, int, hipStream_t,
+                                           zf*);
 template void launch_prolong_fine<double>(const FineT<double>&, const zd*, const zd*, zd*, int, hipStream_t);
 template void launch_prolong_fine<float>(const FineT<float>&, const zf*, const zf*, zf*, int, hipStream_t);
 

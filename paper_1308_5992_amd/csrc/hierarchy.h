@@ -338,9 +338,10 @@ struct bamg_hierarchy {
     if (l == 0 && fine_sweeps(f, x, xsw, b, nrhs, count)) return;
     for (int i = 0; i < count; ++i) sweep(l, x, b, nrhs);
   }
-  void restrict_(int l, const zd* r, zd* rc, int nrhs) {
-    if (l == 0) launch_restrict_fine(f, lv[0].P, r, rc, nrhs, s);
-    else launch_restrict_coarse(lv[l].ex, lv[l].ey, lv[l].P, r, rc, nrhs, s);
+  // rc = P^H r; xz (level l+1, may be NULL) = 0 in the same launch
+  void restrict_(int l, const zd* r, zd* rc, int nrhs, zd* xz = nullptr) {
+    if (l == 0) launch_restrict_fine(f, lv[0].P, r, rc, nrhs, s, xz);
+    else launch_restrict_coarse(lv[l].ex, lv[l].ey, lv[l].P, r, rc, nrhs, s, xz);
     check_launch();
   }
   void prolong(int l, const zd* xc, zd* x, int nrhs) {
@@ -371,8 +372,7 @@ struct bamg_hierarchy {
     Level& C = lv[l + 1];
     smooth(l, x, b, nrhs, p.pre);
     apply(l, x, Lv.r, b, nrhs);  // r = b - A x
-    restrict_(l, Lv.r, C.b, nrhs);
-    launch_fill_zero(C.x, C.n * nrhs, s);
+    restrict_(l, Lv.r, C.b, nrhs, coarsest(l + 1) ? nullptr : C.x);  // and the coarse initial guess x = 0
     const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
     for (int g = 0; g < gamma; ++g) {
       cycle(l + 1, C.b, C.x, nrhs);
@@ -433,7 +433,7 @@ struct bamg_hierarchy {
       if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
       if (c32()) {
         launch_dense_mv32(C.Ainv32, (int)C.n, b, x, nrhs, force_mr, (zf*)mmwork, s);
-      } else {
+      } else if (!launch_dense_mv_f32io(C.Ainv, (int)C.n, b, x, nrhs, force_mr, s)) {
         launch_convert(b, C.b, C.n * nrhs, s);
         launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, force_mr, mmwork, s);
         launch_convert(C.x, x, C.n * nrhs, s);
@@ -445,9 +445,11 @@ struct bamg_hierarchy {
     Level& C = lv[l + 1];
     smooth32<S>(l, x, b, nrhs, p.pre);
     apply32<S>(l, x, Lv.r32, b, nrhs);
-    if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s);
-    else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s);
-    launch_zero(C.x32, C.n * nrhs * sizeof(zf), s);
+    // the restriction also zeroes the coarse initial guess, which the coarsest
+    // solve does not need (it writes all of x)
+    zf* xz = coarsest(l + 1) ? nullptr : C.x32;
+    if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
+    else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
     const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
     for (int g = 0; g < gamma; ++g) {
       cycle32<S>(l + 1, C.b32, C.x32, nrhs);
@@ -461,8 +463,7 @@ struct bamg_hierarchy {
   // z = M v for nrhs FP64 level-0 vectors through the FP32 cycle
   void precondition_mixed(const zd* v, zd* z, int nrhs) {
     Level& L0 = lv[0];
-    launch_convert(v, L0.b32, L0.n * nrhs, s);
-    launch_zero(L0.x32, L0.n * nrhs * sizeof(zf), s);
+    launch_convert_zero(v, L0.b32, L0.x32, L0.n * nrhs, s);
     switch (p.precision) {
       case BAMG_MIXED_FP16: cycle32<hcx>(0, L0.b32, L0.x32, nrhs); break;
       case BAMG_MIXED_BF16: cycle32<bcx>(0, L0.b32, L0.x32, nrhs); break;
