@@ -72,6 +72,24 @@ __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * 
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> cdiv_real(cx<T> a, T s) { return {a.x / s, a.y / s}; }
 
+// Lane exchange by DPP moves (within rows of 16 lanes; no LDS round trip).
+// CTRL: quad permutations (0x00-0xFF), row shifts left / right by n (0x100 + n /
+// 0x110 + n: lane i reads lane i + n / i - n of its row), row rotations right
+// by n (0x120 + n).  A lane whose source lies outside the row reads 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E;  // quad_perm [1,0,3,2] and [2,3,0,1]
+constexpr int DPP_ROW_SHL4 = 0x104, DPP_ROW_SHR4 = 0x114, DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR8 = 0x128;
+
 constexpr int NOFF = 7;  // coarse stencil offsets
 constexpr int NC = 16;   // dofs per coarse site
 

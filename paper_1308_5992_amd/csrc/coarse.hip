@@ -32,6 +32,25 @@ __device__ __forceinline__ cx<T> shfl_xor_z(cx<T> v, int m) {
   return cx<T>{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
 }
 
+// the value of lane i ^ M (M = 1, 2, 4) by DPP moves: quad permutations for 1
+// and 2; for 4, a row shift down for lanes with bit 2 set, up for the others
+template <int M, typename R>
+__device__ __forceinline__ R dpp_xor(R v) {
+  if constexpr (M == 1) {
+    return dpp_mov<DPP_QUAD_XOR1>(v);
+  } else if constexpr (M == 2) {
+    return dpp_mov<DPP_QUAD_XOR2>(v);
+  } else {
+    static_assert(M == 4, "lane masks 1, 2, 4");
+    const R dn = dpp_mov<DPP_ROW_SHR4>(v), up = dpp_mov<DPP_ROW_SHL4>(v);
+    return (threadIdx.x & 4) ? dn : up;
+  }
+}
+template <int M, typename T>
+__device__ __forceinline__ cx<T> xor_add(cx<T> v) {
+  return cx<T>{v.x + dpp_xor<M>(v.x), v.y + dpp_xor<M>(v.y)};
+}
+
 // ---------------------------------------------------------------------------
 // y = D x  (or y = b - D x)
 // ---------------------------------------------------------------------------
@@ -57,8 +76,8 @@ __global__ __launch_bounds__(256) void k_coarse_apply(CoarseT<T, S> c, const cx<
     C acc = {0, 0};
     for (int o = 0; o < NOFF; ++o)
       for (int jj = 0; jj < 4; ++jj) acc = acc + Dv[o][jj] * xv[nb[o] * 16 + 4 * q + jj];
-    acc = acc + shfl_xor_z(acc, 1);
-    acc = acc + shfl_xor_z(acc, 2);
+    acc = xor_add<1>(acc);
+    acc = xor_add<2>(acc);
     if (q == 0) {
       if (b) acc = b[r * n + site * 16 + i] - acc;
       y[r * n + site * 16 + i] = acc;
@@ -139,16 +158,16 @@ __global__ __launch_bounds__(128) void k_kaczmarz_coarse(CoarseT<T, S> c, int co
     }
   }
   C r = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
-  r = r + shfl_xor_z(r, 1);
-  r = r + shfl_xor_z(r, 2);
-  r = r + shfl_xor_z(r, 4);
+  r = xor_add<1>(r);
+  r = xor_add<2>(r);
+  r = xor_add<4>(r);
   if (q == 0) rsh[i] = bi - r;
   __syncthreads();
   // alpha_i = sum_{j <= i} Kinv[i][j] r_j
   C al = k0 * rsh[2 * q] + k1 * rsh[2 * q + 1];
-  al = al + shfl_xor_z(al, 1);
-  al = al + shfl_xor_z(al, 2);
-  al = al + shfl_xor_z(al, 4);
+  al = xor_add<1>(al);
+  al = xor_add<2>(al);
+  al = xor_add<4>(al);
   // x_col += sum_i conj(D[i][col]) alpha_i; thread (i < 14, q) finishes
   // column j = 2q + (i & 1) of offset o = i / 2 from the value it already holds
 #pragma unroll

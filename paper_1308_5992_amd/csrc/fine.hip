@@ -583,18 +583,6 @@ __device__ __forceinline__ int nib(uint64_t c, int n) { return (int)((c >> (4 * 
 // lanes i and i ^ 8 hold equal sums; xor 2 and xor 1 as quad permutations.
 // Every lane adds the same pairs in the same order as the xor butterfly, so
 // the sums (and every kernel that reproduces that order) keep their bits.
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-constexpr int DPP_ROW_ROR8 = 0x128, DPP_ROW_ROR4 = 0x124, DPP_QUAD_XOR2 = 0x4E, DPP_QUAD_XOR1 = 0xB1;
 
 template <typename T>
 __device__ __forceinline__ cx<T> grp16_sum(cx<T> v) {
