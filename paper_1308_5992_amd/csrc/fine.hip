@@ -1104,10 +1104,176 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
   }
 }
 
+// The same sweep for larger lattices, streaming: LDS holds the region of x,
+// one colour's slot blocks and right-hand sides, and the projection tables.
+// While a colour is projected, the next colour's slot blocks and right-hand
+// sides are loaded into registers; after the colour's barrier they are
+// stored to LDS, and a second barrier makes them visible.  Larger tiles fit
+// than in the form above (1.3-1.6 projections per tile site), so each slot
+// block is read about 1.4 times per sweep instead of the 16 colour passes'
+// 9-fold touch of every x entry.  1024 threads: 64 groups of 16 lanes.
+constexpr int FSS_NT = 1024, FSS_GROUPS = FSS_NT / 16;
+// staged 16-byte loads per thread at most (more would spill FP64 registers)
+template <typename T>
+constexpr int FSS_SB_MAX = sizeof(T) == 8 ? 4 : 8;
+
+template <typename T>
+static size_t fine_sweep_lds_s(const FineSweepPlan& p, int maxcnt) {
+  return (size_t)(2 * p.Ru * p.Rv + 38 * maxcnt) * sizeof(cx<T>) + 8 * (size_t)p.nupd;
+}
+
+template <typename T, int LDSB, int ITER, int SB>
+__global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, FineSweepPlan p, int maxcnt,
+                                                                  const cx<T>* __restrict__ xin, cx<T>* __restrict__ xout,
+                                                                  const cx<T>* __restrict__ b) {
+  using C = cx<T>;
+  constexpr int UB = 36 * (int)sizeof(C) / 16;  // 16-byte units of a site's slot blocks
+  constexpr int US = 2 * (int)sizeof(C) / 16;   // 16-byte units of a site's two unknowns
+  __shared__ uint4 sm[LDSB / 16];
+  C* X = reinterpret_cast<C*>(sm);              // region of x, [Ru][Rv][2]
+  uint4* Bu = sm + p.Ru * p.Rv * US;            // the colour's slot blocks, [maxcnt][36]
+  uint4* bu = Bu + maxcnt * UB;                 // the colour's right-hand sides, [maxcnt][2]
+  int* usite = reinterpret_cast<int*>(bu + maxcnt * US);  // even-site index of every projection
+  int* uloc = usite + p.nupd;                             // its position in the region
+  const int tid = threadIdx.x;
+  const int N = f.N, NH = f.NH;
+  const int u0 = 1 + (int)(blockIdx.x % p.ntu) * p.Tu, v0 = 1 + (int)(blockIdx.x / p.ntu) * p.Tv;
+  const size_t n = (size_t)N * NH * 2;
+  const C* xr = xin + blockIdx.y * n;
+  C* xw = xout + blockIdx.y * n;
+  const C* br = b ? b + blockIdx.y * n : nullptr;
+  const int ub = UB + (br ? US : 0);  // units per projection
+  auto site = [&](int u, int v) {
+    const int xx = (u + v + 2 * N) % N, yy = (u - v + 2 * N) % N;
+    return yy * NH + (xx >> 1);
+  };
+  for (int q = tid; q < p.nupd; q += FSS_NT) {
+    int c = 0;
+    while (q >= p.first[c + 1]) ++c;
+    const int k = q - p.first[c];
+    const int i = p.si0[c] + 4 * (k / p.nj[c]), j = p.sj0[c] + 4 * (k % p.nj[c]);
+    usite[q] = site(u0 + i, v0 + j);
+    uloc[q] = (i - p.i0) * p.Rv + (j - p.j0);
+  }
+  {
+    const int t1 = p.Ru * p.Rv * US;
+    const uint4* x4 = reinterpret_cast<const uint4*>(xr);
+    for (int e0 = tid; e0 < t1; e0 += FSS_NT * 4) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * FSS_NT;
+        v[u] = make_uint4(0, 0, 0, 0);
+        if (e < t1) {
+          const int q = e / US, li = q / p.Rv;
+          v[u] = x4[(size_t)site(u0 + p.i0 + li, v0 + p.j0 + (q - li * p.Rv)) * US + (e - q * US)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * FSS_NT;
+        if (e < t1) sm[e] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  // colour c's data in 16-byte units: [0, cnt UB) slot blocks, then the
+  // right-hand sides (if any); loaded into stg[], stored to Bu / bu
+  const uint4* B4 = reinterpret_cast<const uint4*>(f.Bst);
+  const uint4* b4 = reinterpret_cast<const uint4*>(br);
+  uint4 stg[SB];
+  auto stage = [&](int c) {
+    const int f0 = p.first[c], cnt = p.first[c + 1] - f0, nB = cnt * UB, tot = cnt * ub;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = tid + u * FSS_NT;
+      stg[u] = make_uint4(0, 0, 0, 0);
+      if (e < tot) {
+        const uint4* src;
+        size_t idx;
+        if (e < nB) {
+          const int q = e / UB;
+          src = B4;
+          idx = (size_t)usite[f0 + q] * UB + (e - q * UB);
+        } else {
+          const int q = (e - nB) / US;
+          src = b4;
+          idx = (size_t)usite[f0 + q] * US + (e - nB - q * US);
+        }
+        stg[u] = src[idx];
+      }
+    }
+  };
+  auto commit = [&](int c) {
+    const int cnt = p.first[c + 1] - p.first[c], nB = cnt * UB, tot = cnt * ub;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = tid + u * FSS_NT;
+      if (e < tot) {
+        if (e < nB) Bu[e] = stg[u];
+        else bu[e - nB] = stg[u];
+      }
+    }
+  };
+  stage(0);
+  commit(0);
+  __syncthreads();
+  const int g = tid >> 4, lane = tid & 15;
+  const bool act = lane < 9;
+  const int slot = act ? lane : 0;
+  const int soff = (nib(SLOT_DU1, slot) - 1) * p.Rv + (nib(SLOT_DV1, slot) - 1);
+  const C* BC = reinterpret_cast<const C*>(Bu) + slot * 4;
+  const C* bC = reinterpret_cast<const C*>(bu);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    if (c < 15) stage(c + 1);  // in flight while colour c is projected
+    const int f0 = p.first[c], cnt = p.first[c + 1] - f0;
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int kl = g + it * FSS_GROUPS;
+      if (kl >= cnt) continue;  // whole 16-lane groups
+      const int e = uloc[f0 + kl] + soff;
+      C B[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      C x0 = {0, 0}, x1 = {0, 0}, b0 = {0, 0}, b1 = {0, 0};
+      if (act) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) B[w] = BC[kl * 36 + w];
+        x0 = X[2 * e];
+        x1 = X[2 * e + 1];
+      }
+      if (br) {
+        b0 = bC[2 * kl];
+        b1 = bC[2 * kl + 1];
+      }
+      const C nu = grp16_sum(C{norm2_fixed(B[0]) + norm2_fixed(B[1]), norm2_fixed(B[2]) + norm2_fixed(B[3])});
+      const C g10 = grp16_sum(cjmul_fixed(B[0], B[2]) + cjmul_fixed(B[1], B[3]));
+      const C r0 = grp16_sum(cmul_fixed(B[0], x0) + cmul_fixed(B[1], x1));
+      const C r1 = grp16_sum(cmul_fixed(B[2], x0) + cmul_fixed(B[3], x1));
+      const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
+      const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+      if (act) {
+        X[2 * e] = (x0 + cjmul_fixed(B[0], a0)) + cjmul_fixed(B[2], a1);
+        X[2 * e + 1] = (x1 + cjmul_fixed(B[1], a0)) + cjmul_fixed(B[3], a1);
+      }
+    }
+    __syncthreads();
+    if (c < 15) {
+      commit(c + 1);
+      __syncthreads();
+    }
+  }
+  uint4* xw4 = reinterpret_cast<uint4*>(xw);
+  for (int e = tid; e < p.Tu * p.Tv * US; e += FSS_NT) {
+    const int q = e / US, ti = q / p.Tv, tj = q - ti * p.Tv;
+    const int l = (ti - p.i0) * p.Rv + (tj - p.j0);
+    xw4[(size_t)site(u0 + ti, v0 + tj) * US + (e - q * US)] = sm[l * US + (e - q * US)];
+  }
+}
+
 // The dependence recursion for a Tu x Tv tile whose origin has u = v = 1 mod 4
 // (coordinates relative to the tile origin).  False if a projection count
 // exceeds the table or the region would meet itself across the torus.
-static bool fine_sweep_plan(int N, int Tu, int Tv, FineSweepPlan& p) {
+static bool fine_sweep_plan(int N, int Tu, int Tv, FineSweepPlan& p, int max_cnt = 2 * FS_GROUPS) {
   auto m4 = [](int a) { return ((a % 4) + 4) % 4; };
   int i0 = 0, i1 = Tu - 1, j0 = 0, j1 = Tv - 1;
   int cnt[16];
@@ -1142,7 +1308,7 @@ static bool fine_sweep_plan(int N, int Tu, int Tv, FineSweepPlan& p) {
   for (int c = 0; c < 16; ++c) p.first[c + 1] = p.first[c] + cnt[c];
   p.nupd = p.first[16];
   for (int c = 0; c < 16; ++c)
-    if (cnt[c] > 2 * FS_GROUPS) return false;  // at most two projection steps per group and colour
+    if (cnt[c] > max_cnt) return false;  // projection steps per group and colour are bounded
   return p.Ru <= N && p.Rv <= N && (2 * p.Ru <= N || 2 * p.Rv <= N);
 }
 
@@ -1185,23 +1351,6 @@ bool fine_sweep_choose(int N, int nrhs, FineSweepPlan& best) {
   return found;
 }
 
-template <typename T>
-static bool fine_sweep_cached_plan(int N, int nrhs, FineSweepPlan& out) {
-  struct Cached {
-    int N = -1, nrhs = -1;
-    bool ok = false;
-    FineSweepPlan p;
-  };
-  thread_local Cached cache;
-  if (cache.N != N || cache.nrhs != nrhs) {
-    cache.N = N;
-    cache.nrhs = nrhs;
-    cache.ok = fine_sweep_choose<T>(N, nrhs, cache.p);
-  }
-  out = cache.p;
-  return cache.ok;
-}
-
 // The blocked sweep pays for its redundant projections and its per-colour
 // barriers with 15 fewer launches; measured on MI355X it is the faster form
 // while x is small (FP32: 1.6-2.8x at 64^2-256^2 with one right-hand side,
@@ -1209,21 +1358,104 @@ static bool fine_sweep_cached_plan(int N, int nrhs, FineSweepPlan& out) {
 // slower one beyond, where the colour passes stream at memory bandwidth.
 constexpr size_t FS_MAX_X_BYTES = size_t(1) << 20;
 
+// The streaming form is bound by its arithmetic (16-lane groups, 16 colour
+// steps), not by memory; measured on MI355X it beats the colour passes up to
+// N^2 R = 2^20 entries of x in FP32 (512^2: 41 against 56 us per sweep,
+// 1024^2: 95 against 115, 256^2 x 8: 57 against 69) and 2^18 in FP64 (512^2:
+// 63 against 72), and loses beyond (FP32 2048^2: 415 against 390; FP64
+// 1024^2: 270 against 204), where the passes stream at memory bandwidth.
+template <typename T>
+constexpr size_t FSS_MAX_ENTRIES = sizeof(T) == 8 ? size_t(1) << 18 : size_t(1) << 20;
+
+// The streaming form's tile: the fewest projections per tile site among the
+// tiles whose LDS fits, whose colours need at most 4 steps of the 64 groups
+// and 8 staged loads per thread, preferring at least 256 work-groups.
+template <typename T>
+bool fine_sweep_choose_s(int N, int nrhs, FineSweepPlan& best, int& best_maxcnt) {
+  if (N % 8 != 0 || N < 64) return false;
+  constexpr int UB = 36 * (int)sizeof(cx<T>) / 16, US = 2 * (int)sizeof(cx<T>) / 16;
+  bool found = false;
+  double best_red = 0;
+  long best_wg = 0;
+  for (int Tu : {4, 8, 16, 32})
+    for (int Tv : {8, 16, 32, 64, 128}) {
+      if (N % Tu != 0 || (N / 2) % Tv != 0) continue;
+      FineSweepPlan p;
+      if (!fine_sweep_plan(N, Tu, Tv, p, 4 * FSS_GROUPS)) continue;
+      int maxcnt = 0;
+      for (int c = 0; c < 16; ++c) maxcnt = std::max(maxcnt, p.first[c + 1] - p.first[c]);
+      if (fine_sweep_lds_s<T>(p, maxcnt) > (size_t)FS_LDS_LARGE || maxcnt * (UB + US) > FSS_SB_MAX<T> * FSS_NT) continue;
+      const long wg = (long)p.ntu * p.ntv * nrhs;
+      const double red = (double)p.nupd / (Tu * Tv);
+      bool better;
+      if (!found) better = true;
+      else if (wg >= 256 && best_wg >= 256) better = red < best_red;
+      else better = wg > best_wg || (wg == best_wg && red < best_red);
+      if (better) {
+        best = p;
+        best_maxcnt = maxcnt;
+        best_red = red;
+        best_wg = wg;
+        found = true;
+      }
+    }
+  return found;
+}
+
+// 0: no blocked sweep, 1: LDS-resident form, 2: streaming form
+template <typename T>
+static int fine_sweep_cached_plan(int N, int nrhs, FineSweepPlan& out, int& maxcnt) {
+  struct Cached {
+    int N = -1, nrhs = -1, mode = 0, maxcnt = 0;
+    FineSweepPlan p;
+  };
+  thread_local Cached cache;
+  if (cache.N != N || cache.nrhs != nrhs) {
+    cache.N = N;
+    cache.nrhs = nrhs;
+    cache.mode = 0;
+    const size_t entries = (size_t)N * N * nrhs;
+    if (entries * sizeof(cx<T>) <= FS_MAX_X_BYTES && fine_sweep_choose<T>(N, nrhs, cache.p))
+      cache.mode = 1;
+    else if (entries <= FSS_MAX_ENTRIES<T> && fine_sweep_choose_s<T>(N, nrhs, cache.p, cache.maxcnt))
+      cache.mode = 2;
+  }
+  out = cache.p;
+  maxcnt = cache.maxcnt;
+  return cache.mode;
+}
+
 template <typename T>
 bool fine_sweep_applies(const FineT<T>& f, int nrhs) {
   FineSweepPlan p;
+  int maxcnt;
   if (!f.Bst || nrhs < 1 || nrhs > 65535) return false;
-  if ((size_t)f.N * f.N * nrhs * sizeof(cx<T>) > FS_MAX_X_BYTES) return false;
-  return fine_sweep_cached_plan<T>(f.N, nrhs, p);
+  return fine_sweep_cached_plan<T>(f.N, nrhs, p, maxcnt) != 0;
 }
 
 template <typename T>
 void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s) {
   FineSweepPlan p;
-  if (!fine_sweep_cached_plan<T>(f.N, nrhs, p)) return;
-  const dim3 grid((unsigned)(p.ntu * p.ntv), (unsigned)nrhs);
-  const size_t lds = fine_sweep_lds<T>(p);
   int maxcnt = 0;
+  const int mode = fine_sweep_cached_plan<T>(f.N, nrhs, p, maxcnt);
+  if (mode == 0) return;
+  const dim3 grid((unsigned)(p.ntu * p.ntv), (unsigned)nrhs);
+  if (mode == 2) {
+    constexpr int UB = 36 * (int)sizeof(cx<T>) / 16, US = 2 * (int)sizeof(cx<T>) / 16;
+    const bool it2 = maxcnt <= 2 * FSS_GROUPS, sb4 = maxcnt * (UB + US) <= 4 * FSS_NT;
+#define FSS_LAUNCH(I, S)                                                                                          \
+  hipLaunchKernelGGL((k_kaczmarz_fine_sweep_s<T, FS_LDS_LARGE, I, S>), grid, dim3(FSS_NT), 0, s, f, p, maxcnt, xin, \
+                     xout, b)
+    constexpr int SBM = FSS_SB_MAX<T>;
+    if (it2 && sb4) FSS_LAUNCH(2, 4);
+    else if (it2) FSS_LAUNCH(2, SBM);
+    else if (sb4) FSS_LAUNCH(4, 4);
+    else FSS_LAUNCH(4, SBM);  // (SBM = 4 for FP64: the plan keeps its colours within 4 loads per thread)
+#undef FSS_LAUNCH
+    return;
+  }
+  const size_t lds = fine_sweep_lds<T>(p);
+  maxcnt = 0;
   for (int c = 0; c < 16; ++c) maxcnt = std::max(maxcnt, p.first[c + 1] - p.first[c]);
 #define FS_LAUNCH(L, I) \
   hipLaunchKernelGGL((k_kaczmarz_fine_sweep<T, L, I>), grid, dim3(FS_NT), 0, s, f, p, xin, xout, b)

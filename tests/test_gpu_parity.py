@@ -127,12 +127,13 @@ def test_eo_reduce_reconstruct(bamg, N, nrhs):
 
 
 @pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (40, 16), (64, 17), (64, 40), (40, 70),
-                                    (80, 3), (96, 2), (128, 1)])
+                                    (80, 3), (96, 2), (128, 1), (512, 1), (256, 5)])
 def test_fine_kaczmarz_sweep(bamg, N, nrhs):
     """From 16 right-hand sides the sweeps run on right-hand-side-interleaved
     copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64).  Below
     that, from N = 64 on, one launch per sweep blocked in LDS (80: 8-wide
-    tiles in v, 96: tiles of 32 in u); 16 and 40 take the colour passes."""
+    tiles in v, 96: tiles of 32 in u; 512 x 1: the streaming form); 16, 40
+    and 256 x 5 take the colour passes."""
     log(f"kaczmarz fine N={N}")
     U = inputs.gauge_random(N, 7)
     m = 0.02
@@ -146,14 +147,15 @@ def test_fine_kaczmarz_sweep(bamg, N, nrhs):
     assert rel(host(x), ref) < 1e-12
 
 
-@pytest.mark.parametrize("N", [40, 64, 96, 256])
+@pytest.mark.parametrize("N", [40, 64, 96, 256, 512])
 @pytest.mark.parametrize("prec", [0, 3])
 def test_fine_sweep_batch_gives_the_same_bits(bamg, prec, N):
     """20 right-hand sides take the interleaved sweep; one or three of them
-    alone take the colour passes (N = 40) or the sweep blocked in LDS (from
-    N = 64): the same bits (each lane adds the slot terms in the butterfly's
-    order; the blocked sweep projects every site its tile depends on with the
-    values the colour passes give it)."""
+    alone take the colour passes (N = 40; FP64 512^2 x 3) or a sweep blocked
+    in LDS (from N = 64; the streaming form for 256^2 x 3, 512^2 x 1 and FP32
+    512^2 x 3): the same bits (each lane adds the slot terms in
+    the butterfly's order; the blocked sweeps project every site a tile depends
+    on with the values the colour passes give it)."""
     R = 20
     log(f"sweep bits N={N} prec={prec}")
     U = inputs.gauge_random(N, 27)
