@@ -516,17 +516,17 @@ COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine_sweep", "mixed_fp16"): {"src": "fine.hip",
-                                   "sha256": "e11e4cd3b8b24a96b942e98e78b1478ac73fd27a9ea67fc357ae11e35c190809",
-                                   "fetch_kib": 9341.5, "write_kib": 640.0, **COPY_SCALE},
+                                   "sha256": "1294994fb9f280268cd74c82c41f729cba8a970a9744ff82b9699089f48bda2b",
+                                   "fetch_kib": 9337.0, "write_kib": 640.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
-                               "sha256": "648c9669d7a9f63a0e0beee951cee527d9f7a1ed39c3dced91e3f6ea4af983fe",
-                               "fetch_kib": 1313.0, "write_kib": 224.0, **COPY_SCALE},
+                               "sha256": "9b18863221383c8e83eab8527f10b7b85196a3e1ffc57d35caba01889fbe3c73",
+                               "fetch_kib": 1312.5, "write_kib": 224.0, **COPY_SCALE},
     ("dense", "mixed_fp16"): {"src": "dense.hip",
-                              "sha256": "091dbc73896e7f9ed78d2e01839ad407e48ffe378fcd5bb93763554a284cb777",
-                              "fetch_kib": 524812.5, "write_kib": 128.0, **COPY_SCALE},
+                              "sha256": "bc287d776029b5de93e7ffa96e7c1217e34b7cb94f0ef0b31b3524c75457de73",
+                              "fetch_kib": 524816.0, "write_kib": 128.0, **COPY_SCALE},
     ("dense32", "mixed_fp16"): {"src": "dense.hip",
-                                "sha256": "091dbc73896e7f9ed78d2e01839ad407e48ffe378fcd5bb93763554a284cb777",
-                                "fetch_kib": 262627.1, "write_kib": 74.6, **COPY_SCALE},
+                                "sha256": "bc287d776029b5de93e7ffa96e7c1217e34b7cb94f0ef0b31b3524c75457de73",
+                                "fetch_kib": 262627.9, "write_kib": 74.6, **COPY_SCALE},
 }
 
 
