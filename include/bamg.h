@@ -215,6 +215,25 @@ int bamg_import_level(bamg_hierarchy *h, int32_t l, const void *P_host, const vo
  * add workspace per right-hand side. */
 size_t bamg_footprint_bytes(const bamg_params *p);
 
+/* The tile plan of the level-0 Kaczmarz sweep blocked in LDS (Sec. 3.1; one
+ * launch per 16-colour sweep, bitwise the colour-by-colour sweep), host only.
+ * The even sites are addressed by u = (x + y)/2, v = (x - y)/2, the colour is
+ * 4 (u mod 4) + (v mod 4); tiles of Tu x Tv sites start at u0 = 1 + a Tu,
+ * v0 = 1 + b Tv (a < ntu = N / Tu, b < ntv = N / 2 / Tv).  A tile's work-group
+ * reads the region [u0 + i0, u0 + i0 + Ru) x [v0 + j0, v0 + j0 + Rv) of x,
+ * projects, for colour c = 0..15, the sites u0 + si0[c] + 4 p, v0 + sj0[c] + 4 q
+ * (p < (first[c+1] - first[c]) / nj[c], q < nj[c]) in this order, and writes
+ * its own tile.
+ *   form: 0 the library's choice for nrhs right-hand sides, 1 the
+ *         LDS-resident form's tile, 2 the streaming form's tile;
+ *   fp32: nonzero for FP32 arithmetic (the mixed cycle), else FP64;
+ *   plan_out (host, 74 int32): Tu, Tv, ntu, ntv, i0, j0, Ru, Rv, nupd,
+ *         first[17], si0[16], sj0[16], nj[16] (nupd = first[16] projections).
+ * Returns the form of the plan written (1 or 2), 0 if the colour passes are
+ * used (form 0) or no tile applies (the lattice is too small or N/2 is not a
+ * multiple of 8), BAMG_EINVAL for bad arguments. */
+int bamg_fine_sweep_plan(int32_t N, int32_t nrhs, int32_t fp32, int32_t form, int32_t *plan_out);
+
 /* k test vectors from the Philox4x32-10 generator (as used by setup):
  * out (device) [k][N*N] reduced vectors, entries (re, im) i.i.d. N(0, 1/2). */
 int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void *out, void *stream);

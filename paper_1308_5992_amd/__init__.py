@@ -97,6 +97,7 @@ def _load():
         "bamg_import_level": (I32, [P, I32, P, P]),
         "bamg_footprint_bytes": (SZ, [PP]),
         "bamg_gaussian_tv": (I32, [I32, I32, U64, P, P]),
+        "bamg_fine_sweep_plan": (I32, [I32, I32, I32, I32, P]),
         "bamg_free": (None, [P]),
         "bamg_last_error": (ctypes.c_char_p, []),
         "bamg_boot_op": (I32, [P, I32, I32, P, P, I32]),
@@ -273,6 +274,25 @@ def bamg_export_level(h, level: int, P=True, D=True, tv=False, n_tv=8):
 def bamg_import_level(h, level: int, P):
     P = np.ascontiguousarray(P, dtype=np.complex128)
     _check(lib.bamg_import_level(h, int(level), P.ctypes.data, None), "bamg_import_level")
+
+
+def bamg_fine_sweep_plan(N: int, nrhs: int = 1, fp32: bool = False, form: int = 0):
+    """(form, plan) of the level-0 sweep blocked in LDS (host only): form 1 or 2
+    and a dict of the tile plan, or (0, None) where the colour passes are used
+    (form 0) or no tile applies."""
+    out = np.zeros(74, dtype=np.int32)
+    got = lib.bamg_fine_sweep_plan(int(N), int(nrhs), int(bool(fp32)), int(form), out.ctypes.data)
+    if got < 0:
+        _check(got, "bamg_fine_sweep_plan")
+    if got == 0:
+        return 0, None
+    keys = ["Tu", "Tv", "ntu", "ntv", "i0", "j0", "Ru", "Rv", "nupd"]
+    plan = {k: int(out[i]) for i, k in enumerate(keys)}
+    plan["first"] = out[9:26].tolist()
+    plan["si0"] = out[26:42].tolist()
+    plan["sj0"] = out[42:58].tolist()
+    plan["nj"] = out[58:74].tolist()
+    return int(got), plan
 
 
 def bamg_gaussian_tv(N: int, k: int, seed: int, out):

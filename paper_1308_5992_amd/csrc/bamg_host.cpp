@@ -541,6 +541,21 @@ int bamg_export_boot(const bamg_hierarchy* hc, double* lam_host, void* ve_host) 
   return h->ke;
 }
 
+int bamg_fine_sweep_plan(int32_t N, int32_t nrhs, int32_t fp32, int32_t form, int32_t* plan_out) {
+  if (!plan_out || N < 1 || nrhs < 1 || form < 0 || form > 2) return fail(BAMG_EINVAL, "bad arguments");
+  FineSweepPlan p;
+  const int got = fine_sweep_plan_query(N, nrhs, fp32 != 0, form, p);
+  if (got == 0) return 0;
+  int32_t* o = plan_out;
+  const int head[9] = {p.Tu, p.Tv, p.ntu, p.ntv, p.i0, p.j0, p.Ru, p.Rv, p.nupd};
+  for (int v : head) *o++ = v;
+  for (int c = 0; c < 17; ++c) *o++ = p.first[c];
+  for (int c = 0; c < 16; ++c) *o++ = p.si0[c];
+  for (int c = 0; c < 16; ++c) *o++ = p.sj0[c];
+  for (int c = 0; c < 16; ++c) *o++ = p.nj[c];
+  return got;
+}
+
 int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void* out, void* stream) {
   if (N < 2 || k < 1 || !out) return fail(BAMG_EINVAL, "bad arguments");
   launch_philox_tv(N * N, k, seed, (zd*)out, (hipStream_t)stream);

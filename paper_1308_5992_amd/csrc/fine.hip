@@ -1475,6 +1475,16 @@ void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const c
 #undef FS_ITER
 #undef FS_LAUNCH
 }
+// The plan of form (0: the library's choice, 1, 2) for the plan query of the
+// C ABI; returns the form written, 0 for none.
+int fine_sweep_plan_query(int N, int nrhs, bool fp32, int form, FineSweepPlan& p) {
+  int maxcnt = 0;
+  if (form == 0)
+    return fp32 ? fine_sweep_cached_plan<float>(N, nrhs, p, maxcnt) : fine_sweep_cached_plan<double>(N, nrhs, p, maxcnt);
+  if (form == 1) return (fp32 ? fine_sweep_choose<float>(N, nrhs, p) : fine_sweep_choose<double>(N, nrhs, p)) ? 1 : 0;
+  return (fp32 ? fine_sweep_choose_s<float>(N, nrhs, p, maxcnt) : fine_sweep_choose_s<double>(N, nrhs, p, maxcnt)) ? 2 : 0;
+}
+
 template bool fine_sweep_applies<double>(const FineT<double>&, int);
 template bool fine_sweep_applies<float>(const FineT<float>&, int);
 template void launch_fine_sweep<double>(const FineT<double>&, const zd*, zd*, const zd*, int, hipStream_t);
