@@ -129,7 +129,7 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
   const size_t zm = z + (mixed ? sizeof(zf) : 0);  // an entry and its FP32 copy in the mixed modes
   const size_t zc = z + (mixed && p->coarsest_fp32 ? sizeof(zf) : 0);  // entry of the coarsest inverse
   const size_t sst = p->precision == BAMG_MIXED_FP32 ? sizeof(zf) : sizeof(hcx);  // stored coarse operator entry
-  size_t bytes = (2 * N * N + (N * N / 2) * 36) * zm;  // links, stored slot blocks of Dhat
+  size_t bytes = (2 * N * N + (N * N / 2) * 38) * zm;  // links, stored slot blocks of Dhat and their Gram terms
   for (int l = 0; l < L; ++l) {
     const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
     const size_t n = ns * (l == 0 ? 2 : 16);
@@ -207,6 +207,9 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
     h->Bst = dalloc<zd>((size_t)N * N / 2 * 36);
     launch_slot_blocks(h->f, h->Bst, h->s);
     h->f.Bst = h->Bst;
+    h->Gst = dalloc<zd>((size_t)N * N / 2 * 2);
+    launch_slot_gram(h->f, h->Bst, h->Gst, h->s);
+    h->f.Gst = h->Gst;
     check_launch();
     const int L = (int)sh.ext.size(), k = p->n_tv;
     const bool mg = L > 1;

@@ -101,6 +101,7 @@ struct FineT {
   const cx<T>* Ue = nullptr;
   const cx<T>* Uo = nullptr;
   const cx<T>* Bst = nullptr;  // stored slot blocks of Dhat, [site][9][4] (smoother)
+  const cx<T>* Gst = nullptr;  // per even site (nu_0, nu_1), G_10 of its row pair (smoother)
 };
 using Fine = FineT<double>;
 
@@ -115,6 +116,11 @@ void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, in
 // stencil slots (built from the links)
 template <typename T>
 void launch_slot_blocks(const FineT<T>& f, cx<T>* Bst, hipStream_t s);
+// Gst[site] = ((nu_0, nu_1), G_10): the squared row norms and the Gram entry
+// of the site's row pair, from Bst, with the smoother's own expressions and
+// lane sums (the same bits as forming them in a pass)
+template <typename T>
+void launch_slot_gram(const FineT<T>& f, const cx<T>* Bst, cx<T>* Gst, hipStream_t s);
 // one colour pass over the nsites = N^2/32 sites of fine colour `colour`
 // (lam != NULL: per right-hand side shift lam[r], the pass on (Dhat - lam Gamma_5) x = 0)
 template <typename T>

@@ -691,6 +691,42 @@ __device__ __forceinline__ T norm2_fixed(cx<T> a) {
   return fma(a.x, a.x, a.y * a.y);
 }
 
+// ((nu_0, nu_1), G_10) of a row pair from its slot blocks (lane = slot, zero
+// blocks on lanes 9-15): the smoother's Gram terms, one definition for every
+// kernel that forms or stores them
+template <typename T>
+__device__ __forceinline__ void pair_gram(const cx<T> (&B)[4], cx<T>& nu, cx<T>& g10) {
+  nu = grp16_sum(cx<T>{norm2_fixed(B[0]) + norm2_fixed(B[1]), norm2_fixed(B[2]) + norm2_fixed(B[3])});
+  g10 = grp16_sum(cjmul_fixed(B[0], B[2]) + cjmul_fixed(B[1], B[3]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_slot_gram(int nsites, const cx<T>* __restrict__ Bst, cx<T>* __restrict__ Gst) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t >> 4, lane = t & 15;
+  if (i >= nsites) return;  // whole 16-lane groups
+  cx<T> B[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  if (lane < 9) {
+    const cx<T>* bp = Bst + ((size_t)i * 9 + lane) * 4;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) B[w] = bp[w];
+  }
+  cx<T> nu, g10;
+  pair_gram(B, nu, g10);
+  if (lane == 0) {
+    Gst[2 * (size_t)i] = nu;
+    Gst[2 * (size_t)i + 1] = g10;
+  }
+}
+
+template <typename T>
+void launch_slot_gram(const FineT<T>& f, const cx<T>* Bst, cx<T>* Gst, hipStream_t s) {
+  const int nsites = f.N * f.NH;
+  hipLaunchKernelGGL(k_slot_gram<T>, dim3((unsigned)((nsites * 16 + 255) / 256)), dim3(256), 0, s, nsites, Bst, Gst);
+}
+template void launch_slot_gram<double>(const FineT<double>&, const zd*, zd*, hipStream_t);
+template void launch_slot_gram<float>(const FineT<float>&, const zf*, zf*, hipStream_t);
+
 // lam (may be NULL): per right-hand side shift, the pass then works on
 // (Dhat - lam Gamma_5) x = 0 (the eigen-relaxation of the bootstrap setup,
 // Sec. 3.4 / Theorem 1), Gamma_5 = +1 on spin 0 and -1 on spin 1.
@@ -746,7 +782,14 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
     g10 = grp16_sum(cjmul_fixed(Bm[0][0], Bm[1][0]) + cjmul_fixed(Bm[0][1], Bm[1][1]));
   };
   C nu, g10;
-  if (!lam) gram(B, nu, g10);
+  if (!lam) {
+    if (f.Gst) {
+      nu = f.Gst[2 * (size_t)i];
+      g10 = f.Gst[2 * (size_t)i + 1];
+    } else {
+      gram(B, nu, g10);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < RB; ++k) {
     const int r = rbeg + k;
@@ -951,12 +994,13 @@ template <typename T, int ITER>
 struct FsColour {
   cx<T> B[ITER][4];
   cx<T> b[ITER][2];
+  cx<T> nu[ITER], g10[ITER];  // the row pair's stored Gram terms
   int e[ITER];
 };
 
 template <typename T, int ITER>
 __device__ __forceinline__ FsColour<T, ITER> fs_colour(const int (&k)[ITER], bool act, int soff, const cx<T>* Bl,
-                                                       const cx<T>* bs, const int* uloc, bool hasb) {
+                                                       const cx<T>* bs, const cx<T>* gs, const int* uloc, bool hasb) {
   // reads without branches (an absent projection reads entry 0 and drops
   // it), so that they stay in flight while the current step computes
   FsColour<T, ITER> r;
@@ -973,6 +1017,8 @@ __device__ __forceinline__ FsColour<T, ITER> fs_colour(const int (&k)[ITER], boo
     const cx<T> v0 = bs[2 * kq], v1 = bs[2 * kq + 1];
     r.b[it][0] = hasb ? v0 : z;
     r.b[it][1] = hasb ? v1 : z;
+    r.nu[it] = gs[2 * kq];
+    r.g10[it] = gs[2 * kq + 1];
   }
   return r;
 }
@@ -987,7 +1033,8 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
   C* X = reinterpret_cast<C*>(sm);      // region of x, [Ru][Rv][2]
   C* Bs = X + 2 * p.Ru * p.Rv;          // slot blocks of the projections, [nupd][36]
   C* bs = Bs + 36 * p.nupd;             // their right-hand sides, [nupd][2]
-  int* usite = reinterpret_cast<int*>(bs + 2 * p.nupd);  // their even-site index
+  C* gs = bs + 2 * p.nupd;              // their stored Gram terms, [nupd][2]
+  int* usite = reinterpret_cast<int*>(gs + 2 * p.nupd);  // their even-site index
   int* uloc = usite + p.nupd;                            // their position in the region
   const int tid = threadIdx.x;
   const int N = f.N, NH = f.NH;
@@ -1009,20 +1056,23 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
     uloc[q] = (i - p.i0) * p.Rv + (j - p.j0);
   }
   __syncthreads();
-  // One round of loads fills the region of x, the slot blocks and the
-  // right-hand sides, which lie in this order in LDS (16-byte units).
+  // One round of loads fills the region of x, the slot blocks, the
+  // right-hand sides (if any) and the Gram terms, which lie in this order in
+  // LDS (16-byte units; without right-hand sides their place stays empty).
   {
     const int t1 = p.Ru * p.Rv * US, t2 = t1 + p.nupd * UB, t3 = t2 + (br ? p.nupd * US : 0);
+    const int t4 = t3 + p.nupd * US, gshift = br ? 0 : p.nupd * US;
     const uint4* x4 = reinterpret_cast<const uint4*>(xr);
     const uint4* B4 = reinterpret_cast<const uint4*>(f.Bst);
     const uint4* b4 = reinterpret_cast<const uint4*>(br);
-    for (int e0 = tid; e0 < t3; e0 += FS_NT * FS_BATCH) {
+    const uint4* G4 = reinterpret_cast<const uint4*>(f.Gst);
+    for (int e0 = tid; e0 < t4; e0 += FS_NT * FS_BATCH) {
       uint4 v[FS_BATCH];
 #pragma unroll
       for (int u = 0; u < FS_BATCH; ++u) {
         const int e = e0 + u * FS_NT;
         v[u] = make_uint4(0, 0, 0, 0);
-        if (e < t3) {
+        if (e < t4) {
           const uint4* src;
           size_t idx;
           if (e < t1) {
@@ -1033,10 +1083,14 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
             const int q = (e - t1) / UB;
             src = B4;
             idx = (size_t)usite[q] * UB + (e - t1 - q * UB);
-          } else {
+          } else if (e < t3) {
             const int q = (e - t2) / US;
             src = b4;
             idx = (size_t)usite[q] * US + (e - t2 - q * US);
+          } else {
+            const int q = (e - t3) / US;
+            src = G4;
+            idx = (size_t)usite[q] * US + (e - t3 - q * US);
           }
           v[u] = src[idx];
         }
@@ -1044,7 +1098,7 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
 #pragma unroll
       for (int u = 0; u < FS_BATCH; ++u) {
         const int e = e0 + u * FS_NT;
-        if (e < t3) sm[e] = v[u];
+        if (e < t4) sm[e < t3 ? e : e + gshift] = v[u];
       }
     }
   }
@@ -1064,7 +1118,7 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
       const int k = p.first[c] + g + it * FS_GROUPS;
       kk[c][it] = k < p.first[c + 1] ? k : -1;
     }
-  FsColour<T, ITER> cur = fs_colour<T, ITER>(kk[0], act, soff, Bl, bs, uloc, hasb);
+  FsColour<T, ITER> cur = fs_colour<T, ITER>(kk[0], act, soff, Bl, bs, gs, uloc, hasb);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     C x0[ITER], x1[ITER];
@@ -1075,15 +1129,14 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
       x1[it] = act ? v1 : C{0, 0};
     }
     FsColour<T, ITER> nxt;
-    if (c < 15) nxt = fs_colour<T, ITER>(kk[c < 15 ? c + 1 : c], act, soff, Bl, bs, uloc, hasb);
+    if (c < 15) nxt = fs_colour<T, ITER>(kk[c < 15 ? c + 1 : c], act, soff, Bl, bs, gs, uloc, hasb);
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       if (kk[c][it] < 0) continue;  // whole 16-lane groups
       const int e = cur.e[it];
       const C* B = cur.B[it];
       const C b0 = cur.b[it][0], b1 = cur.b[it][1];
-      const C nu = grp16_sum(C{norm2_fixed(B[0]) + norm2_fixed(B[1]), norm2_fixed(B[2]) + norm2_fixed(B[3])});
-      const C g10 = grp16_sum(cjmul_fixed(B[0], B[2]) + cjmul_fixed(B[1], B[3]));
+      const C nu = cur.nu[it], g10 = cur.g10[it];
       const C r0 = grp16_sum(cmul_fixed(B[0], x0[it]) + cmul_fixed(B[1], x1[it]));
       const C r1 = grp16_sum(cmul_fixed(B[2], x0[it]) + cmul_fixed(B[3], x1[it]));
       const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
@@ -1119,7 +1172,7 @@ constexpr int FSS_SB_MAX = sizeof(T) == 8 ? 4 : 8;
 
 template <typename T>
 static size_t fine_sweep_lds_s(const FineSweepPlan& p, int maxcnt) {
-  return (size_t)(2 * p.Ru * p.Rv + 38 * maxcnt) * sizeof(cx<T>) + 8 * (size_t)p.nupd;
+  return (size_t)(2 * p.Ru * p.Rv + 40 * maxcnt) * sizeof(cx<T>) + 8 * (size_t)p.nupd;
 }
 
 template <typename T, int LDSB, int ITER, int SB>
@@ -1133,7 +1186,8 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
   C* X = reinterpret_cast<C*>(sm);              // region of x, [Ru][Rv][2]
   uint4* Bu = sm + p.Ru * p.Rv * US;            // the colour's slot blocks, [maxcnt][36]
   uint4* bu = Bu + maxcnt * UB;                 // the colour's right-hand sides, [maxcnt][2]
-  int* usite = reinterpret_cast<int*>(bu + maxcnt * US);  // even-site index of every projection
+  uint4* gu = bu + maxcnt * US;                 // the colour's stored Gram terms, [maxcnt][2]
+  int* usite = reinterpret_cast<int*>(gu + maxcnt * US);  // even-site index of every projection
   int* uloc = usite + p.nupd;                             // its position in the region
   const int tid = threadIdx.x;
   const int N = f.N, NH = f.NH;
@@ -1142,7 +1196,7 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
   const C* xr = xin + blockIdx.y * n;
   C* xw = xout + blockIdx.y * n;
   const C* br = b ? b + blockIdx.y * n : nullptr;
-  const int ub = UB + (br ? US : 0);  // units per projection
+  const int ub = UB + (br ? US : 0) + US;  // units per projection
   auto site = [&](int u, int v) {
     const int xx = (u + v + 2 * N) % N, yy = (u - v + 2 * N) % N;
     return yy * NH + (xx >> 1);
@@ -1178,12 +1232,14 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
   }
   __syncthreads();
   // colour c's data in 16-byte units: [0, cnt UB) slot blocks, then the
-  // right-hand sides (if any); loaded into stg[], stored to Bu / bu
+  // Gram terms, then the right-hand sides (if any); loaded into stg[],
+  // stored to Bu / gu / bu
   const uint4* B4 = reinterpret_cast<const uint4*>(f.Bst);
   const uint4* b4 = reinterpret_cast<const uint4*>(br);
+  const uint4* G4 = reinterpret_cast<const uint4*>(f.Gst);
   uint4 stg[SB];
   auto stage = [&](int c) {
-    const int f0 = p.first[c], cnt = p.first[c + 1] - f0, nB = cnt * UB, tot = cnt * ub;
+    const int f0 = p.first[c], cnt = p.first[c + 1] - f0, nB = cnt * UB, nG = nB + cnt * US, tot = cnt * ub;
 #pragma unroll
     for (int u = 0; u < SB; ++u) {
       const int e = tid + u * FSS_NT;
@@ -1195,23 +1251,28 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
           const int q = e / UB;
           src = B4;
           idx = (size_t)usite[f0 + q] * UB + (e - q * UB);
-        } else {
+        } else if (e < nG) {
           const int q = (e - nB) / US;
-          src = b4;
+          src = G4;
           idx = (size_t)usite[f0 + q] * US + (e - nB - q * US);
+        } else {
+          const int q = (e - nG) / US;
+          src = b4;
+          idx = (size_t)usite[f0 + q] * US + (e - nG - q * US);
         }
         stg[u] = src[idx];
       }
     }
   };
   auto commit = [&](int c) {
-    const int cnt = p.first[c + 1] - p.first[c], nB = cnt * UB, tot = cnt * ub;
+    const int cnt = p.first[c + 1] - p.first[c], nB = cnt * UB, nG = nB + cnt * US, tot = cnt * ub;
 #pragma unroll
     for (int u = 0; u < SB; ++u) {
       const int e = tid + u * FSS_NT;
       if (e < tot) {
         if (e < nB) Bu[e] = stg[u];
-        else bu[e - nB] = stg[u];
+        else if (e < nG) gu[e - nB] = stg[u];
+        else bu[e - nG] = stg[u];
       }
     }
   };
@@ -1224,6 +1285,7 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
   const int soff = (nib(SLOT_DU1, slot) - 1) * p.Rv + (nib(SLOT_DV1, slot) - 1);
   const C* BC = reinterpret_cast<const C*>(Bu) + slot * 4;
   const C* bC = reinterpret_cast<const C*>(bu);
+  const C* gC = reinterpret_cast<const C*>(gu);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c < 15) stage(c + 1);  // in flight while colour c is projected
@@ -1245,8 +1307,7 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
         b0 = bC[2 * kl];
         b1 = bC[2 * kl + 1];
       }
-      const C nu = grp16_sum(C{norm2_fixed(B[0]) + norm2_fixed(B[1]), norm2_fixed(B[2]) + norm2_fixed(B[3])});
-      const C g10 = grp16_sum(cjmul_fixed(B[0], B[2]) + cjmul_fixed(B[1], B[3]));
+      const C nu = gC[2 * kl], g10 = gC[2 * kl + 1];
       const C r0 = grp16_sum(cmul_fixed(B[0], x0) + cmul_fixed(B[1], x1));
       const C r1 = grp16_sum(cmul_fixed(B[2], x0) + cmul_fixed(B[3], x1));
       const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
@@ -1314,7 +1375,7 @@ static bool fine_sweep_plan(int N, int Tu, int Tv, FineSweepPlan& p, int max_cnt
 
 template <typename T>
 static size_t fine_sweep_lds(const FineSweepPlan& p) {
-  return (size_t)(2 * p.Ru * p.Rv + 38 * p.nupd) * sizeof(cx<T>) + 8 * (size_t)p.nupd;
+  return (size_t)(2 * p.Ru * p.Rv + 40 * p.nupd) * sizeof(cx<T>) + 8 * (size_t)p.nupd;
 }
 
 constexpr int FS_LDS_TINY = 40960, FS_LDS_SMALL = 81920, FS_LDS_LARGE = 163840;
@@ -1384,7 +1445,8 @@ bool fine_sweep_choose_s(int N, int nrhs, FineSweepPlan& best, int& best_maxcnt)
       if (!fine_sweep_plan(N, Tu, Tv, p, 4 * FSS_GROUPS)) continue;
       int maxcnt = 0;
       for (int c = 0; c < 16; ++c) maxcnt = std::max(maxcnt, p.first[c + 1] - p.first[c]);
-      if (fine_sweep_lds_s<T>(p, maxcnt) > (size_t)FS_LDS_LARGE || maxcnt * (UB + US) > FSS_SB_MAX<T> * FSS_NT) continue;
+      if (fine_sweep_lds_s<T>(p, maxcnt) > (size_t)FS_LDS_LARGE || maxcnt * (UB + 2 * US) > FSS_SB_MAX<T> * FSS_NT)
+        continue;
       const long wg = (long)p.ntu * p.ntv * nrhs;
       const double red = (double)p.nupd / (Tu * Tv);
       bool better;
@@ -1429,7 +1491,7 @@ template <typename T>
 bool fine_sweep_applies(const FineT<T>& f, int nrhs) {
   FineSweepPlan p;
   int maxcnt;
-  if (!f.Bst || nrhs < 1 || nrhs > 65535) return false;
+  if (!f.Bst || !f.Gst || nrhs < 1 || nrhs > 65535) return false;
   return fine_sweep_cached_plan<T>(f.N, nrhs, p, maxcnt) != 0;
 }
 
@@ -1442,7 +1504,7 @@ void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const c
   const dim3 grid((unsigned)(p.ntu * p.ntv), (unsigned)nrhs);
   if (mode == 2) {
     constexpr int UB = 36 * (int)sizeof(cx<T>) / 16, US = 2 * (int)sizeof(cx<T>) / 16;
-    const bool it2 = maxcnt <= 2 * FSS_GROUPS, sb4 = maxcnt * (UB + US) <= 4 * FSS_NT;
+    const bool it2 = maxcnt <= 2 * FSS_GROUPS, sb4 = maxcnt * (UB + 2 * US) <= 4 * FSS_NT;
 #define FSS_LAUNCH(I, S)                                                                                          \
   hipLaunchKernelGGL((k_kaczmarz_fine_sweep_s<T, FS_LDS_LARGE, I, S>), grid, dim3(FSS_NT), 0, s, f, p, maxcnt, xin, \
                      xout, b)

@@ -109,9 +109,9 @@ struct bamg_hierarchy {
   double m = 0;
   hipStream_t s = nullptr;
   Fine f;
-  zd *Ue = nullptr, *Uo = nullptr, *Bst = nullptr;
+  zd *Ue = nullptr, *Uo = nullptr, *Bst = nullptr, *Gst = nullptr;
   FineT<float> f32;
-  zf *Ue32 = nullptr, *Uo32 = nullptr, *Bst32 = nullptr;
+  zf *Ue32 = nullptr, *Uo32 = nullptr, *Bst32 = nullptr, *Gst32 = nullptr;
   std::vector<Level> lv;
   int cap = 0;  // right-hand sides the work vectors hold
   // batched path: multi-RHS kernels for every batch size, so that a right-hand
@@ -239,7 +239,7 @@ struct bamg_hierarchy {
     }
     dfree(mmwork);
     dfree(xil); dfree(bil); dfree(xil32); dfree(bil32); dfree(xsw); dfree(xsw32);
-    dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(Bst); dfree(Bst32); dfree(gjcol); dfree(gjperm); dfree(dflag);
+    dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(Bst); dfree(Bst32); dfree(Gst); dfree(Gst32); dfree(gjcol); dfree(gjperm); dfree(dflag);
     if (hflag) (void)hipHostFree(hflag);
     free_krylov();
     dfree(tvsave);
@@ -507,6 +507,9 @@ struct bamg_hierarchy {
     if (!Bst32) Bst32 = dalloc<zf>(nl / 2 * 36);
     launch_slot_blocks(f32, Bst32, s);
     f32.Bst = Bst32;
+    if (!Gst32) Gst32 = dalloc<zf>(nl / 2 * 2);
+    launch_slot_gram(f32, Bst32, Gst32, s);
+    f32.Gst = Gst32;
     for (int l = 0; l < L(); ++l) {
       Level& Lv = lv[l];
       if (Lv.P) {
