@@ -878,19 +878,29 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine_il(FineT<T> f, int colour,
     X0[k] = ld(js[k], 0);
     X1[k] = ld(js[k], 1);
   }
-  C w0[3], w1[3], wn[3], wg[3];
+  C w0[3], w1[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     w0[k] = cmul_fixed(B[k][0], X0[k]) + cmul_fixed(B[k][1], X1[k]);
     w1[k] = cmul_fixed(B[k][2], X0[k]) + cmul_fixed(B[k][3], X1[k]);
-    wn[k] = C{norm2_fixed(B[k][0]) + norm2_fixed(B[k][1]), norm2_fixed(B[k][2]) + norm2_fixed(B[k][3])};
-    wg[k] = cjmul_fixed(B[k][0], B[k][2]) + cjmul_fixed(B[k][1], B[k][3]);
   }
   const bool q0 = q == 0;
   const C r0 = quarter_sum((w0[0] + (q0 ? w0[2] : zr)) + (w0[1] + zr));
   const C r1 = quarter_sum((w1[0] + (q0 ? w1[2] : zr)) + (w1[1] + zr));
-  const C nu = quarter_sum((wn[0] + (q0 ? wn[2] : zn)) + (wn[1] + zn));
-  const C g10 = quarter_sum((wg[0] + (q0 ? wg[2] : zg)) + (wg[1] + zg));
+  C nu, g10;
+  if (f.Gst) {  // the stored Gram terms of the row pair (the same bits)
+    nu = f.Gst[2 * (size_t)i];
+    g10 = f.Gst[2 * (size_t)i + 1];
+  } else {
+    C wn[3], wg[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      wn[k] = C{norm2_fixed(B[k][0]) + norm2_fixed(B[k][1]), norm2_fixed(B[k][2]) + norm2_fixed(B[k][3])};
+      wg[k] = cjmul_fixed(B[k][0], B[k][2]) + cjmul_fixed(B[k][1], B[k][3]);
+    }
+    nu = quarter_sum((wn[0] + (q0 ? wn[2] : zn)) + (wn[1] + zn));
+    g10 = quarter_sum((wg[0] + (q0 ? wg[2] : zg)) + (wg[1] + zg));
+  }
   C b0 = {0, 0}, b1 = {0, 0};
   if (bi) {
     b0 = bi[((size_t)i * 2) * R + r];
