@@ -782,14 +782,9 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
     g10 = grp16_sum(cjmul_fixed(Bm[0][0], Bm[1][0]) + cjmul_fixed(Bm[0][1], Bm[1][1]));
   };
   C nu, g10;
-  if (!lam) {
-    if (f.Gst) {
-      nu = f.Gst[2 * (size_t)i];
-      g10 = f.Gst[2 * (size_t)i + 1];
-    } else {
-      gram(B, nu, g10);
-    }
-  }
+  // formed here rather than read from Gst: the passes run where memory, not
+  // arithmetic, bounds them, and the stored terms would add 2 entries per site
+  if (!lam) gram(B, nu, g10);
 #pragma unroll
   for (int k = 0; k < RB; ++k) {
     const int r = rbeg + k;
