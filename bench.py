@@ -516,8 +516,8 @@ COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine_sweep", "mixed_fp16"): {"src": "fine.hip",
-                                   "sha256": "1294994fb9f280268cd74c82c41f729cba8a970a9744ff82b9699089f48bda2b",
-                                   "fetch_kib": 9337.0, "write_kib": 640.0, **COPY_SCALE},
+                                   "sha256": "2fc340803188cb3298e717d49cc60c5a5fcb903ee35ceafd5f03568c1811d4b4",
+                                   "fetch_kib": 10153.0, "write_kib": 640.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "9b18863221383c8e83eab8527f10b7b85196a3e1ffc57d35caba01889fbe3c73",
                                "fetch_kib": 1312.5, "write_kib": 224.0, **COPY_SCALE},
