@@ -295,8 +295,8 @@ def bandwidth_points(bamg, inputs, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: the benchmark runs on one GPU; --gpus must be 1 (a multi-GPU run would shard "
-              "right-hand sides, see the design notes)", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU; --gpus must be 1 (a multi-GPU run would shard the "
+              "right-hand sides over GPUs, one hierarchy per GPU)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
