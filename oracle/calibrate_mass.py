@@ -30,7 +30,7 @@ import oracle  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(_HERE), "inputs", "workloads.json")
 
-# lattice, gauge recipe, target of min |eig(D)| and seeds; see the design notes
+# lattice, gauge recipe, target of min |eig(D)| and seeds
 WORKLOADS = {
     "c1_32_b3": dict(N=32, beta=3.0, sweeps=200, gauge_seed=1, target=1e-2, rhs_seed=101, tv_seed=201,
                      n_levels=2, nrhs=1),

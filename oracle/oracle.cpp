@@ -9,8 +9,7 @@
 // std::complex<double>, single-threaded loops over explicit sparse (CSR) or
 // dense matrices built from the paper's definitions.
 //
-// Readings of the paper that the code below takes (each is listed with its
-// reason in the design notes of the repository):
+// Readings of the paper that the code below takes:
 //   * Wilson operator: eq. (wilson) of Sec. 2 with m_q = m + 2 in 2D, the
 //     gamma matrices of Sec. 2 and U(1) links; the link sits on the forward
 //     hop and its conjugate on the backward hop exactly as eq. (wilson) says.

@@ -17,7 +17,7 @@ SOURCES = ["fine.hip", "coarse.hip", "dense.hip", "blas.hip", "boot.hip", "bamg_
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
-    # no packed FP32 instructions (see the design notes)
+    # no packed FP32 instructions: some of their forms have given wrong results without an error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(os.path.dirname(HERE), "include"),
 ]
