@@ -78,6 +78,12 @@ class bamg_server_stats(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libbamg.so is not built ({LIB_PATH}); run python paper_1308_5992_amd/build.py")
+    # torch first: the library then binds to the HIP runtime torch ships and
+    # shares its devices and streams.  Loaded first, it would bring in the
+    # system's runtime (same soname), and the two stacks in one process do not
+    # see the GPU alike.
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     P, I32, D, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_size_t
     PP = ctypes.POINTER(bamg_params)
