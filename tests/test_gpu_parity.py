@@ -65,6 +65,37 @@ def test_dhat_apply(bamg, N, nrhs):
     assert rel(host(y), ref) < 1e-13
 
 
+def test_binding_imported_before_torch():
+    """A process that imports the binding before torch: the library must bind
+    to the HIP runtime torch uses (the binding loads torch first), else it
+    sees no device.  Runs in a fresh process, as the import order is per
+    process."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import paper_1308_5992_amd as bamg\n"
+        "import numpy as np, torch, inputs, oracle\n"
+        "N = 16; U = inputs.gauge_random(N, 26); m = -0.07\n"
+        "d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to('cuda:0')\n"
+        "h = bamg.bamg_setup(d(U), m,"
+        " bamg.bamg_default_params(N=N, setup_sweeps=1, setup_adapt=0))\n"
+        "x = inputs.gaussian((1, N * N), 36)\n"
+        "y = torch.zeros(1, N * N, dtype=torch.complex128, device='cuda:0')\n"
+        "bamg.bamg_apply_dhat(h, d(x), y, 1)\n"
+        "ref = oracle.dhat_apply(U, m, x).reshape(1, N * N)\n"
+        "print(float(np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()))\n"
+    )
+    log("binding imported before torch (subprocess)")
+    env = dict(os.environ, PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert float(r.stdout.strip().splitlines()[-1]) < 1e-13
+
+
 @pytest.mark.parametrize("N,nrhs", [(128, 2), (512, 3), (1024, 2)])
 def test_dhat_apply_fp32(bamg, N, nrhs):
     """The FP32 operator of the mixed cycle (level op 10 on level 0, FP32 links
