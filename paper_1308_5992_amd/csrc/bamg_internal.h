@@ -72,6 +72,15 @@ __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * 
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> cdiv_real(cx<T> a, T s) { return {a.x / s, a.y / s}; }
 
+// Work-group p of a launch goes to XCD p mod 8 (the chip's 8 XCDs, each with
+// its own L2, take work-groups in turn).  xcd_block renumbers the nb
+// work-groups so that each XCD takes one contiguous range, in order: logical
+// neighbours run on one XCD at about the same time and share its L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned p, unsigned nb) {
+  const unsigned k = p & 7, q = nb >> 3, rem = nb & 7;
+  return k * q + (k < rem ? k : rem) + (p >> 3);
+}
+
 // Lane exchange by DPP moves (within rows of 16 lanes; no LDS round trip).
 // CTRL: quad permutations (0x00-0xFF), row shifts left / right by n (0x100 + n /
 // 0x110 + n: lane i reads lane i + n / i - n of its row), row rotations right

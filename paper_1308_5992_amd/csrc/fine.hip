@@ -344,7 +344,11 @@ __global__ __launch_bounds__(256) void k_dhat_strip(FineT<T> f, const cx<T>* __r
   using Row = DhatRow<T>;
   constexpr int U = 3 + PF;  // row slots: rows ty-1, ty, ty+1 and PF rows in flight
   const int lane = threadIdx.x & 63;
-  const long item = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // consecutive items: right-hand sides, then strips across the lattice, then
+  // segments; each XCD takes one contiguous range of them (a band of whole
+  // rows), so a segment's halo rows are rows that the segments above and
+  // below it load through the same L2
+  const long item = (long)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (item >= (long)nstrips * nseg * nrhs) return;  // whole waves leave together
   const int r = (int)(item % nrhs);
   const long sg = item / nrhs;
@@ -742,7 +746,9 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
                                                       int nrhs) {
   using C = cx<T>;
   const int lane = threadIdx.x & 15;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 4);
+  // each XCD takes a contiguous range of the colour's sites, so the cache
+  // lines that neighbouring sites' supports share stay in one L2
+  const int t = (int)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 4);
   const int rbeg = blockIdx.y * RB;
   if (t >= nsites || rbeg >= nrhs) return;  // whole 16-lane groups leave together
   const size_t n = (size_t)f.N * f.NH * 2;
