@@ -516,7 +516,7 @@ COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine_sweep", "mixed_fp16"): {"src": "fine.hip",
-                                   "sha256": "2fc340803188cb3298e717d49cc60c5a5fcb903ee35ceafd5f03568c1811d4b4",
+                                   "sha256": "700519d8cfbbc4e227dd6e109821949520989d291ad741fbf7c4fd135bfd8024",
                                    "fetch_kib": 10153.0, "write_kib": 640.0, **COPY_SCALE},
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "9b18863221383c8e83eab8527f10b7b85196a3e1ffc57d35caba01889fbe3c73",
@@ -526,7 +526,7 @@ PMC_TRAFFIC = {
                               "fetch_kib": 524816.0, "write_kib": 128.0, **COPY_SCALE},
     ("dense32", "mixed_fp16"): {"src": "dense.hip",
                                 "sha256": "bc287d776029b5de93e7ffa96e7c1217e34b7cb94f0ef0b31b3524c75457de73",
-                                "fetch_kib": 262627.9, "write_kib": 74.6, **COPY_SCALE},
+                                "fetch_kib": 262630.2, "write_kib": 74.5, **COPY_SCALE},
 }
 
 
