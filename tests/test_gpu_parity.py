@@ -158,17 +158,20 @@ def test_eo_reduce_reconstruct(bamg, N, nrhs):
 
 
 @pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (40, 16), (64, 17), (64, 40), (40, 70),
-                                    (80, 3), (96, 2), (128, 1), (512, 1), (256, 5)])
+                                    (80, 3), (96, 2), (128, 1), (512, 1), (256, 5), (1024, 1), (1040, 2)])
 def test_fine_kaczmarz_sweep(bamg, N, nrhs):
     """From 16 right-hand sides the sweeps run on right-hand-side-interleaved
     copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64).  Below
     that, from N = 64 on, one launch per sweep blocked in LDS (80: 8-wide
-    tiles in v, 96: tiles of 32 in u; 512 x 1: the streaming form); 16, 40
-    and 256 x 5 take the colour passes."""
+    tiles in v, 96: tiles of 32 in u; 512 x 1: the streaming form); 16, 40,
+    256 x 5, 1024 and 1040 x 2 take the colour passes (1024: 32768 sites per
+    colour, 8192 work-groups renumbered per XCD; 1040: 33800 sites, a count
+    of work-groups that is not a multiple of 8)."""
     log(f"kaczmarz fine N={N}")
     U = inputs.gauge_random(N, 7)
     m = 0.02
-    h = make_h(bamg, U, m, setup_sweeps=1, setup_adapt=0)
+    # operator-only handles for the large lattices (1040 has no 8192-dim coarsest level)
+    h = make_h(bamg, U, m, setup_sweeps=1, setup_adapt=0, **({"n_levels": 1} if N >= 1024 else {}))
     x0 = inputs.gaussian((nrhs, N * N), 8)
     b = inputs.gaussian((nrhs, N * N), 9)
     x = dev(x0)
