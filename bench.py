@@ -521,12 +521,13 @@ PMC_TRAFFIC = {
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "9b18863221383c8e83eab8527f10b7b85196a3e1ffc57d35caba01889fbe3c73",
                                "fetch_kib": 1312.5, "write_kib": 224.0, **COPY_SCALE},
-    ("dense", "mixed_fp16"): {"src": "dense.hip",
-                              "sha256": "bc287d776029b5de93e7ffa96e7c1217e34b7cb94f0ef0b31b3524c75457de73",
-                              "fetch_kib": 524816.0, "write_kib": 128.0, **COPY_SCALE},
+    # the packed product and its reduction, per call (the sum of the two kernels' counters)
+    ("dense_g5", "mixed_fp16"): {"src": "dense.hip",
+                                 "sha256": "23583344ee084764ef0adda786267fa2079706c6dc93ed3a0f57c10eb22a75dd",
+                                 "fetch_kib": 265259.5 + 8208.0, "write_kib": 16389.6 + 128.0, **COPY_SCALE},
     ("dense32", "mixed_fp16"): {"src": "dense.hip",
-                                "sha256": "bc287d776029b5de93e7ffa96e7c1217e34b7cb94f0ef0b31b3524c75457de73",
-                                "fetch_kib": 262630.2, "write_kib": 74.5, **COPY_SCALE},
+                                "sha256": "23583344ee084764ef0adda786267fa2079706c6dc93ed3a0f57c10eb22a75dd",
+                                "fetch_kib": 262624.8, "write_kib": 74.8, **COPY_SCALE},
 }
 
 
@@ -553,7 +554,9 @@ def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
     the library's stream (torch's current stream) over back-to-back calls of
     the level hooks: the fine smoother on level 0, the coarse colour pass on
     level 1 (ncol launches per sweep) and the coarsest dense product (one
-    launch per call).  A mixed hierarchy is driven through the complex64 hooks.
+    call per cycle: with the FP64 inverse the packed product and the reduction
+    of its partial products).  A mixed hierarchy is driven through the
+    complex64 hooks.
     The fine smoother is either 16 colour passes per sweep or, where the
     library blocks the sweep in LDS, one launch per sweep; the hook then also
     copies x once (it keeps x in place, the kernel writes a second copy), so
@@ -604,9 +607,16 @@ def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
         bb = torch.ones(n, dtype=cdt, device="cuda:0")
         op = bamg.OP_COARSEST_F32 if c32 else bamg.OP_COARSEST
         t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, op, bb, xb, 1), 20, 1, torch)
-        z = 8.0 if c32 else 16.0
-        e = _roof(f"k_dense_mv{'32' if c32 else ''} (coarsest inverse, n = {n})",
-                  "dense32" if c32 else "dense", prec, z * n * n + 2 * z * n, t)
+        if c32:
+            e = _roof(f"k_dense_mv32 (coarsest inverse, n = {n})", "dense32", prec, 8.0 * n * n + 16.0 * n, t)
+        elif n % 64 == 0:
+            # the gamma5-Hermitian inverse's 64 x 64 blocks on and above the block
+            # diagonal (n^2 / 2 + 32 n entries) and x, y; the call is the block
+            # product and the reduction of its partial products
+            e = _roof(f"k_dense_mv_g5 + k_dense_mv_g5_reduce (coarsest inverse, packed gamma5 half, n = {n}; "
+                      f"timed per call)", "dense_g5", prec, 16.0 * (n * n / 2 + 32 * n) + 32.0 * n, t)
+        else:
+            e = _roof(f"k_dense_mv (coarsest inverse, n = {n})", "dense", prec, 16.0 * n * n + 32.0 * n, t)
         out.append((e, t))
     for e, tc in out:
         e["us_per_cycle"] = tc * 1e6

@@ -140,8 +140,13 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
     if (l >= 1) bytes += ns * NOFF * 256 * z;  // coarse operator
     if (l >= 1 && !last) bytes += ns * 256 * zm + (mixed ? ns * NOFF * 256 * sst : 0);  // Kinv; stored operator
     if (!last) bytes += n * 8 * zm;  // P
-    if (last)  // inverse, split-K partials, inversion scratch
+    if (last) {  // inverse, split-K partials, inversion scratch
       bytes += n * n * zc + (dense_mm_workspace((int)n, (int)cap) + gj_workspace((int)n)) * z + n * sizeof(int);
+      if (n % 64 == 0) {  // packed gamma5 half of the inverse, its block table and partial products
+        const size_t nbk = n / 64, nblk = nbk * (nbk + 1) / 2;
+        bytes += nblk * 4096 * z + nblk * 2 * sizeof(int) + 2 * nbk * nbk * 64 * z;
+      }
+    }
   }
   const size_t n0 = N * N, kd = p->restart;
   if (mg && cap >= (size_t)IL_MIN) bytes += 2 * n0 * cap * zm;  // interleaved level-0 x and b
@@ -231,6 +236,16 @@ int bamg_setup(const void* gauge, double m, const bamg_params* p, bamg_hierarchy
         if (l >= 1) Lv.Kinv = dalloc<zd>((size_t)Lv.ex * Lv.ey * 256);
       } else {
         Lv.Ainv = dalloc<zd>(Lv.n * Lv.n);
+        if (mg && Lv.n % 64 == 0) {  // packed gamma5 half of the inverse for the single-RHS product
+          const int nbk = (int)(Lv.n / 64);
+          std::vector<int> blk;
+          for (int I = 0; I < nbk; ++I)
+            for (int J = I; J < nbk; ++J) blk.insert(blk.end(), {I, J});
+          Lv.Ablk = dalloc<int>(blk.size());
+          HIPCHK(hipMemcpy(Lv.Ablk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice));
+          Lv.Ap = dalloc<zd>(blk.size() / 2 * 64 * 64);
+          Lv.Apart = dalloc<zd>((size_t)2 * nbk * nbk * 64);
+        }
       }
     }
     h->ensure_cap(mg ? k + (p->setup_mode ? p->n_ev : 0) : 1);

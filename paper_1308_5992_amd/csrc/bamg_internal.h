@@ -225,6 +225,15 @@ void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many
 // around launch_dense_mv, in one launch where it takes one wave per row
 // (returns false, launching nothing, otherwise)
 bool launch_dense_mv_f32io(const zd* A, int n, const zf* x, zf* y, int nrhs, bool many, hipStream_t s);
+// The single-RHS coarsest product from the 64 x 64 blocks on and above the
+// block diagonal of the gamma5-Hermitian inverse (n % 64 == 0).  blk: the
+// (I, J) pairs of the packed blocks, I <= J, row by row; part: 2 (n / 64)^2 * 64
+// entries.  The product returns false (and launches nothing) unless Ap is set
+// and nrhs is 1 or 2.
+void launch_pack_g5(const zd* A, int n, const int* blk, zd* Ap, hipStream_t s);
+bool launch_dense_mv_g5(const zd* Ap, const int* blk, int n, const zd* x, zd* y, int nrhs, zd* part, hipStream_t s);
+bool launch_dense_mv_g5_f32io(const zd* Ap, const int* blk, int n, const zf* x, zf* y, int nrhs, zd* part,
+                              hipStream_t s);
 size_t dense_mm_workspace(int n, int nrhs);
 // FP32 operands (mixed-precision cycle): y = A x with A the n x n FP32 copy of
 // the coarsest inverse, n a multiple of 16; one wave per row for up to two

@@ -411,6 +411,180 @@ void launch_dense_mv(const zd* A, int n, const zd* x, zd* y, int nrhs, bool many
 }
 
 // ---------------------------------------------------------------------------
+// The product with half of the inverse.  The coarsest operator is
+// gamma5-Hermitian, Gamma_5 D_L Gamma_5 = D_L^H (Sec. 3.5: the aggregation
+// keeps the two spins apart, so every Galerkin level inherits the relation of
+// the Wilson operator), and so is its inverse: A[j][i] = g_i g_j conj(A[i][j])
+// with g = +1 on spin 0 and -1 on spin 1 (coarse dof 16 site + 8 s + k, so
+// within a block of 64 dofs g depends on the local index alone).  The
+// single-RHS product streams only the 64 x 64 blocks on and above the block
+// diagonal (n^2 / 2 + 32 n entries instead of n^2): each block gives its row
+// product to its own block row and its mirrored column product to the
+// transposed block row.  The partial products of block row K are summed over
+// the block columns in order by a second kernel (deterministic, no atomics).
+// ---------------------------------------------------------------------------
+constexpr int G5B = 64;
+__device__ __forceinline__ double g5_local(int r) { return (r & 8) ? -1.0 : 1.0; }
+
+// Ap[q] = block (I, J) = blk[q] of the inverse, row-major; a block off the
+// diagonal holds the average of A_IJ and the mirror of A_JI (the two agree up
+// to the inversion's rounding), so the packed matrix is exactly gamma5-Hermitian
+__global__ __launch_bounds__(256) void k_pack_g5(const zd* __restrict__ A, int n, const int* __restrict__ blk,
+                                                 zd* __restrict__ Ap) {
+  const int q = blockIdx.x, I = blk[2 * q], J = blk[2 * q + 1];
+  for (int e = threadIdx.x; e < G5B * G5B; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const zd a = A[(size_t)(I * G5B + r) * n + J * G5B + c];
+    zd v = a;
+    if (I != J) {
+      const zd m = A[(size_t)(J * G5B + c) * n + I * G5B + r];
+      const double g = g5_local(r) * g5_local(c);
+      v = zd{0.5 * (a.x + g * m.x), 0.5 * (a.y - g * m.y)};
+    }
+    Ap[(size_t)q * G5B * G5B + e] = v;
+  }
+}
+
+void launch_pack_g5(const zd* A, int n, const int* blk, zd* Ap, hipStream_t s) {
+  const int nbk = n / G5B;
+  hipLaunchKernelGGL(k_pack_g5, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, s, A, n, blk, Ap);
+}
+
+// One step of the reduce-scatter of 16 row partials over the 64 lanes: with
+// mask 4 H the lane keeps the half of its 2 H rows selected by its own bit
+// and adds the partner's values of the same rows
+template <int H>
+__device__ __forceinline__ void g5_rs_step(zd (&v)[16], int lane) {
+  const bool up = (lane & (4 * H)) != 0;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const zd keep = up ? v[k + H] : v[k], send = up ? v[k] : v[k + H];
+    v[k] = keep + zd{__shfl_xor(send.x, 4 * H, 64), __shfl_xor(send.y, 4 * H, 64)};
+  }
+}
+// v[k]: the lane's partial of row k (k = 0..15); returns in lane l the full
+// sum of row l >> 2 (the 4 lanes of a quad hold the same value)
+__device__ __forceinline__ zd g5_rowsum(zd (&v)[16], int lane) {
+  g5_rs_step<8>(v, lane);
+  g5_rs_step<4>(v, lane);
+  g5_rs_step<2>(v, lane);
+  g5_rs_step<1>(v, lane);
+  zd rs = v[0];
+  rs = rs + zd{__shfl_xor(rs.x, 2, 64), __shfl_xor(rs.y, 2, 64)};
+  return rs + zd{__shfl_xor(rs.x, 1, 64), __shfl_xor(rs.y, 1, 64)};
+}
+
+// One work-group per packed block: wave w holds rows w, w + 4, ..., w + 60,
+// lane c column c.  x_I and x_J go through LDS.  The column products come
+// first (sums along each lane's rows, then over the four waves in order
+// through LDS); the row products are then formed in place over the block's
+// registers and summed by a reduce-scatter over the lanes (xor 32, 16, 8, 4
+// halve the rows each lane carries, xor 2 and 1 finish), which keeps the
+// register count low enough for 5 work-groups per CU.
+// part[((r nbk + K) nbk + L) 64 + i]: block (K, L)'s contribution to y_r.
+template <typename V, int NR>
+__global__ __launch_bounds__(256) void k_dense_mv_g5(const zd* __restrict__ Ap, const int* __restrict__ blk, int nbk,
+                                                     int n, const V* __restrict__ x, zd* __restrict__ part) {
+  __shared__ zd xsh[NR][2][G5B];  // [r][0]: x_I, [r][1]: x_J
+  __shared__ zd colsh[NR][4][G5B];
+  const int q = blockIdx.x, I = blk[2 * q], J = blk[2 * q + 1];
+  // the wave index is uniform over the wave: the x_I values of its rows are
+  // then scalar operands, not registers per lane
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const zd* B = Ap + (size_t)q * G5B * G5B + (size_t)wave * G5B + lane;
+  zd a[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {  // streamed once per product: non-temporal loads
+    const double* src = reinterpret_cast<const double*>(B + (size_t)k * 4 * G5B);
+    a[k].x = __builtin_nontemporal_load(src);
+    a[k].y = __builtin_nontemporal_load(src + 1);
+  }
+  if (threadIdx.x < NR * 2 * G5B) {
+    const int r = threadIdx.x / (2 * G5B), h = (threadIdx.x / G5B) & 1;
+    xsh[r][h][lane] = mv_in(x[(size_t)r * n + (h ? J : I) * G5B + lane]);
+  }
+  __syncthreads();
+  if (I != J) {  // uniform over the work-group
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      zd cs = {0, 0};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int row = wave + 4 * k;
+        const zd t = cjmul(a[k], xsh[r][0][row]);
+        cs = cs + zd{g5_local(row) * t.x, g5_local(row) * t.y};
+      }
+      colsh[r][wave][lane] = cs;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const zd xj = xsh[r][1][lane];
+    zd rs;
+    if (r == NR - 1) {  // the block's last use: in place
+#pragma unroll
+      for (int k = 0; k < 16; ++k) a[k] = a[k] * xj;
+      rs = g5_rowsum(a, lane);
+    } else {
+      zd v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = a[k] * xj;
+      rs = g5_rowsum(v, lane);
+    }
+    if ((lane & 3) == 0) part[(((size_t)r * nbk + I) * nbk + J) * G5B + wave + 4 * (lane >> 2)] = rs;
+  }
+  if (I == J) return;  // uniform over the work-group
+  __syncthreads();
+  if (wave < NR) {
+    const zd c = ((colsh[wave][0][lane] + colsh[wave][1][lane]) + colsh[wave][2][lane]) + colsh[wave][3][lane];
+    const double g = g5_local(lane);
+    part[(((size_t)wave * nbk + J) * nbk + I) * G5B + lane] = zd{g * c.x, g * c.y};
+  }
+}
+
+// y_r[K 64 + e] = sum over the block columns L of part[r][K][L][e]: one
+// work-group per (K, r); thread group g (of 8) sums L = g, g + 8, ... in
+// order, then the 8 partial sums are added in order
+template <typename V>
+__global__ __launch_bounds__(512) void k_dense_mv_g5_reduce(const zd* __restrict__ part, int nbk, int n,
+                                                            V* __restrict__ y) {
+  __shared__ zd sh[8][G5B];
+  const int K = blockIdx.x, r = blockIdx.y, e = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const zd* p = part + (((size_t)r * nbk + K) * nbk) * G5B + e;
+  zd acc = {0, 0};
+#pragma unroll 4
+  for (int L = g; L < nbk; L += 8) acc = acc + p[(size_t)L * G5B];
+  sh[g][e] = acc;
+  __syncthreads();
+  if (g == 0) {
+    zd t = sh[0][e];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) t = t + sh[k][e];
+    mv_out(t, y[(size_t)r * n + K * G5B + e]);
+  }
+}
+
+template <typename V>
+static bool dense_mv_g5(const zd* Ap, const int* blk, int n, const V* x, V* y, int nrhs, zd* part, hipStream_t s) {
+  if (!Ap || nrhs < 1 || nrhs > 2 || n % G5B != 0) return false;
+  const int nbk = n / G5B, nblk = nbk * (nbk + 1) / 2;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_dense_mv_g5<V, 1>), dim3(nblk), dim3(256), 0, s, Ap, blk, nbk, n, x, part);
+  else
+    hipLaunchKernelGGL((k_dense_mv_g5<V, 2>), dim3(nblk), dim3(256), 0, s, Ap, blk, nbk, n, x, part);
+  hipLaunchKernelGGL(k_dense_mv_g5_reduce<V>, dim3(nbk, nrhs), dim3(512), 0, s, part, nbk, n, y);
+  return true;
+}
+
+bool launch_dense_mv_g5(const zd* Ap, const int* blk, int n, const zd* x, zd* y, int nrhs, zd* part, hipStream_t s) {
+  return dense_mv_g5(Ap, blk, n, x, y, nrhs, part, s);
+}
+bool launch_dense_mv_g5_f32io(const zd* Ap, const int* blk, int n, const zf* x, zf* y, int nrhs, zd* part,
+                              hipStream_t s) {
+  return dense_mv_g5(Ap, blk, n, x, y, nrhs, part, s);
+}
+
+// ---------------------------------------------------------------------------
 // The coarsest solve of the mixed-precision cycle: the cycle's coarse
 // correction is FP32 in and out, and the inverse is read from an FP32 copy
 // (rounded to nearest from the FP64 inverse), which halves the bytes of the

@@ -85,6 +85,9 @@ struct Level {
   zd* D = nullptr;              // coarse block stencil (levels >= 1)
   zd* Kinv = nullptr;           // smoother data (non-coarsest coarse levels)
   zd* Ainv = nullptr;           // inverse of the coarsest operator
+  zd* Ap = nullptr;             // its blocks on and above the block diagonal (single-RHS product)
+  int* Ablk = nullptr;          // (I, J) of each packed block
+  zd* Apart = nullptr;          // partial products of the packed form, 2 right-hand sides
   int ncol = 0, cmode = 0, per_colour = 0;  // smoother colours, colouring mode, sites per colour
   zd* P = nullptr;              // interpolation from level l+1 (non-coarsest levels)
   int prow = 0;                 // rows of P_{a,s}
@@ -233,7 +236,7 @@ struct bamg_hierarchy {
 
   ~bamg_hierarchy() {
     for (auto& L : lv) {
-      dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.P);
+      dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.Ap); dfree(L.Ablk); dfree(L.Apart); dfree(L.P);
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
       dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
     }
@@ -352,7 +355,8 @@ struct bamg_hierarchy {
   void coarsest_solve(const zd* b, zd* x, int nrhs) {
     Level& Lv = lv.back();
     if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
-    launch_dense_mv(Lv.Ainv, (int)Lv.n, b, x, nrhs, force_mr, mmwork, s);
+    if (force_mr || !launch_dense_mv_g5(Lv.Ap, Lv.Ablk, (int)Lv.n, b, x, nrhs, Lv.Apart, s))
+      launch_dense_mv(Lv.Ainv, (int)Lv.n, b, x, nrhs, force_mr, mmwork, s);
     check_launch();
   }
 
@@ -433,7 +437,8 @@ struct bamg_hierarchy {
       if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
       if (c32()) {
         launch_dense_mv32(C.Ainv32, (int)C.n, b, x, nrhs, force_mr, (zf*)mmwork, s);
-      } else if (!launch_dense_mv_f32io(C.Ainv, (int)C.n, b, x, nrhs, force_mr, s)) {
+      } else if ((force_mr || !launch_dense_mv_g5_f32io(C.Ap, C.Ablk, (int)C.n, b, x, nrhs, C.Apart, s)) &&
+                 !launch_dense_mv_f32io(C.Ainv, (int)C.n, b, x, nrhs, force_mr, s)) {
         launch_convert(b, C.b, C.n * nrhs, s);
         launch_dense_mv(C.Ainv, (int)C.n, C.b, C.x, nrhs, force_mr, mmwork, s);
         launch_convert(C.x, x, C.n * nrhs, s);
@@ -571,6 +576,7 @@ struct bamg_hierarchy {
     HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), s));
     launch_gj_invert(C.Ainv, n, gjcol, gjperm, dflag, s);
     launch_gj_unpermute(C.Ainv, n, gjperm, s);
+    if (C.Ap) launch_pack_g5(C.Ainv, n, C.Ablk, C.Ap, s);
     check_launch();
     HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -294,11 +294,13 @@ def test_coarse_kaczmarz_sweep(bamg, imported, nrhs):
     assert rel(host(x), ref) < 1e-11
 
 
-@pytest.mark.parametrize("nrhs", [2, 3, 9, 17, 37, 70])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 9, 17, 37, 70])
 def test_coarsest_solve(bamg, imported, nrhs):
-    """nrhs <= 2: one wave per row; else the split-K FP64 MFMA product with the
-    inverse (8, 16, 32 and 64 right-hand sides per work-group; 70 spans two
-    groups), whose columns do not depend on the other columns."""
+    """nrhs <= 2: the product with the packed gamma5-Hermitian half of the
+    inverse (64 x 64 blocks on and above the diagonal); else the split-K FP64
+    MFMA product with the whole inverse (8, 16, 32 and 64 right-hand sides per
+    work-group; 70 spans two groups), whose columns do not depend on the other
+    columns."""
     N, U, m, h, o = imported
     L = 2
     n = bamg.bamg_level_info(h, L)["n"]
@@ -314,6 +316,32 @@ def test_coarsest_solve(bamg, imported, nrhs):
         x9 = torch.zeros(9, n, dtype=torch.complex128, device="cuda:0")
         bamg.bamg_level_op(h, L, bamg.OP_COARSEST, dev(b[:9]), x9, 9)
         assert np.array_equal(host(x9), host(x)[:9])
+
+
+def test_coarsest_packed_half_matches_whole_inverse(bamg, imported):
+    """The single-RHS coarsest product reads only the blocks on and above the
+    diagonal of the inverse and mirrors the rest through gamma5-Hermiticity
+    (A[j][i] = g_i g_j conj(A[i][j]), Sec. 3.5); the off-diagonal blocks are
+    averaged with their mirrors.  Its result against the whole inverse's
+    (split-K product, 3 right-hand sides), within the inverse's rounding
+    (10 kappa eps), and the relation itself on the oracle's inverse."""
+    N, U, m, h, o = imported
+    L = 2
+    n = bamg.bamg_level_info(h, L)["n"]
+    A = o.operator(L).toarray()
+    kappa = np.linalg.cond(A)
+    Ainv = np.linalg.inv(A)
+    g = np.where((np.arange(n) % 16) >= 8, -1.0, 1.0)
+    assert rel(Ainv.conj().T, g[:, None] * Ainv * g[None, :]) < 10 * kappa * 2.2e-16
+    b = inputs.gaussian((3, n), 81)
+    X3 = torch.zeros(3, n, dtype=torch.complex128, device="cuda:0")
+    bamg.bamg_level_op(h, L, bamg.OP_COARSEST, dev(b), X3, 3)
+    for r in range(3):
+        x1 = torch.zeros(1, n, dtype=torch.complex128, device="cuda:0")
+        bamg.bamg_level_op(h, L, bamg.OP_COARSEST, dev(b[r:r + 1]), x1, 1)
+        e = rel(host(x1)[0], host(X3)[r])
+        log(f"packed half against whole inverse, rhs {r}: {e:.2e} (kappa {kappa:.1e})")
+        assert e < max(1e-12, 10 * kappa * 2.2e-16)
 
 
 @pytest.mark.parametrize("nrhs", [2, 6])
