@@ -521,13 +521,14 @@ PMC_TRAFFIC = {
     ("coarse", "mixed_fp16"): {"src": "coarse.hip",
                                "sha256": "9b18863221383c8e83eab8527f10b7b85196a3e1ffc57d35caba01889fbe3c73",
                                "fetch_kib": 1312.5, "write_kib": 224.0, **COPY_SCALE},
-    # the packed product and its reduction, per call (the sum of the two kernels' counters)
+    # the packed products and their reductions, per call (the sum of the two kernels' counters):
+    # the FP64 blocks (headline) and their FP32 copy (+c32)
     ("dense_g5", "mixed_fp16"): {"src": "dense.hip",
-                                 "sha256": "23583344ee084764ef0adda786267fa2079706c6dc93ed3a0f57c10eb22a75dd",
-                                 "fetch_kib": 265259.5 + 8208.0, "write_kib": 16389.6 + 128.0, **COPY_SCALE},
-    ("dense32", "mixed_fp16"): {"src": "dense.hip",
-                                "sha256": "23583344ee084764ef0adda786267fa2079706c6dc93ed3a0f57c10eb22a75dd",
-                                "fetch_kib": 262624.8, "write_kib": 74.8, **COPY_SCALE},
+                                 "sha256": "fcad5180b394c3da8894dd3f729d70e9d06cb378996fb119a42d132b8d768ba2",
+                                 "fetch_kib": 265259.5 + 8208.0, "write_kib": 16389.1 + 128.0, **COPY_SCALE},
+    ("dense32_g5", "mixed_fp16"): {"src": "dense.hip",
+                                   "sha256": "fcad5180b394c3da8894dd3f729d70e9d06cb378996fb119a42d132b8d768ba2",
+                                   "fetch_kib": 132908.5 + 8208.0, "write_kib": 16384.0 + 64.0, **COPY_SCALE},
 }
 
 
@@ -607,7 +608,11 @@ def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
         bb = torch.ones(n, dtype=cdt, device="cuda:0")
         op = bamg.OP_COARSEST_F32 if c32 else bamg.OP_COARSEST
         t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, op, bb, xb, 1), 20, 1, torch)
-        if c32:
+        if c32 and n % 64 == 0:
+            # the FP32 copy of the packed blocks (complex64 entries), x and y complex64
+            e = _roof(f"k_dense_mv_g5<cx<float>> + k_dense_mv_g5_reduce (coarsest inverse, FP32 copy of the packed "
+                      f"gamma5 half, n = {n}; timed per call)", "dense32_g5", prec, 8.0 * (n * n / 2 + 32 * n) + 16.0 * n, t)
+        elif c32:
             e = _roof(f"k_dense_mv32 (coarsest inverse, n = {n})", "dense32", prec, 8.0 * n * n + 16.0 * n, t)
         elif n % 64 == 0:
             # the gamma5-Hermitian inverse's 64 x 64 blocks on and above the block

@@ -142,9 +142,9 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
     if (!last) bytes += n * 8 * zm;  // P
     if (last) {  // inverse, split-K partials, inversion scratch
       bytes += n * n * zc + (dense_mm_workspace((int)n, (int)cap) + gj_workspace((int)n)) * z + n * sizeof(int);
-      if (n % 64 == 0) {  // packed gamma5 half of the inverse, its block table and partial products
+      if (n % 64 == 0) {  // packed gamma5 half of the inverse (and its FP32 copy), block table, partial products
         const size_t nbk = n / 64, nblk = nbk * (nbk + 1) / 2;
-        bytes += nblk * 4096 * z + nblk * 2 * sizeof(int) + 2 * nbk * nbk * 64 * z;
+        bytes += nblk * 4096 * zc + nblk * 2 * sizeof(int) + 2 * nbk * nbk * 64 * z;
       }
     }
   }
@@ -371,7 +371,9 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         if (in == out) return fail(BAMG_EINVAL, "in and out must not alias");
         h->ensure_cap(nrhs);
         Level& C = h->lv[l];
-        launch_dense_mv32(C.Ainv32, (int)C.n, (const zf*)in, (zf*)out, nrhs, h->force_mr, (zf*)h->mmwork, h->s);
+        if (h->force_mr ||
+            !launch_dense_mv_g5_c32(C.Ap32, C.Ablk, (int)C.n, (const zf*)in, (zf*)out, nrhs, C.Apart, h->s))
+          launch_dense_mv32(C.Ainv32, (int)C.n, (const zf*)in, (zf*)out, nrhs, h->force_mr, (zf*)h->mmwork, h->s);
         check_launch();
         break;
       }

@@ -234,6 +234,12 @@ void launch_pack_g5(const zd* A, int n, const int* blk, zd* Ap, hipStream_t s);
 bool launch_dense_mv_g5(const zd* Ap, const int* blk, int n, const zd* x, zd* y, int nrhs, zd* part, hipStream_t s);
 bool launch_dense_mv_g5_f32io(const zd* Ap, const int* blk, int n, const zf* x, zf* y, int nrhs, zd* part,
                               hipStream_t s);
+// the same from an FP32 copy of the packed blocks (rounded to nearest from the
+// averaged FP64 blocks), products and sums in FP64 (the mixed cycle with
+// coarsest_fp32)
+void launch_pack_g5_f32(const zd* A, int n, const int* blk, zf* Ap, hipStream_t s);
+bool launch_dense_mv_g5_c32(const zf* Ap, const int* blk, int n, const zf* x, zf* y, int nrhs, zd* part,
+                            hipStream_t s);
 size_t dense_mm_workspace(int n, int nrhs);
 // FP32 operands (mixed-precision cycle): y = A x with A the n x n FP32 copy of
 // the coarsest inverse, n a multiple of 16; one wave per row for up to two

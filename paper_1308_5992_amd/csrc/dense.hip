@@ -429,8 +429,9 @@ __device__ __forceinline__ double g5_local(int r) { return (r & 8) ? -1.0 : 1.0;
 // Ap[q] = block (I, J) = blk[q] of the inverse, row-major; a block off the
 // diagonal holds the average of A_IJ and the mirror of A_JI (the two agree up
 // to the inversion's rounding), so the packed matrix is exactly gamma5-Hermitian
+template <typename S>
 __global__ __launch_bounds__(256) void k_pack_g5(const zd* __restrict__ A, int n, const int* __restrict__ blk,
-                                                 zd* __restrict__ Ap) {
+                                                 S* __restrict__ Ap) {
   const int q = blockIdx.x, I = blk[2 * q], J = blk[2 * q + 1];
   for (int e = threadIdx.x; e < G5B * G5B; e += 256) {
     const int r = e >> 6, c = e & 63;
@@ -441,13 +442,28 @@ __global__ __launch_bounds__(256) void k_pack_g5(const zd* __restrict__ A, int n
       const double g = g5_local(r) * g5_local(c);
       v = zd{0.5 * (a.x + g * m.x), 0.5 * (a.y - g * m.y)};
     }
-    Ap[(size_t)q * G5B * G5B + e] = v;
+    mv_out(v, Ap[(size_t)q * G5B * G5B + e]);  // FP32 storage: rounded to nearest
   }
 }
 
 void launch_pack_g5(const zd* A, int n, const int* blk, zd* Ap, hipStream_t s) {
   const int nbk = n / G5B;
-  hipLaunchKernelGGL(k_pack_g5, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, s, A, n, blk, Ap);
+  hipLaunchKernelGGL(k_pack_g5<zd>, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, s, A, n, blk, Ap);
+}
+void launch_pack_g5_f32(const zd* A, int n, const int* blk, zf* Ap, hipStream_t s) {
+  const int nbk = n / G5B;
+  hipLaunchKernelGGL(k_pack_g5<zf>, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, s, A, n, blk, Ap);
+}
+
+// a packed entry, read once per product (non-temporal), widened to FP64
+__device__ __forceinline__ zd g5_load(const zd* p) {
+  const double* d = reinterpret_cast<const double*>(p);
+  return zd{__builtin_nontemporal_load(d), __builtin_nontemporal_load(d + 1)};
+}
+__device__ __forceinline__ zd g5_load(const zf* p) {
+  const double w = __builtin_nontemporal_load(reinterpret_cast<const double*>(p));  // the two floats at once
+  const zf v = __builtin_bit_cast(zf, w);
+  return zd{(double)v.x, (double)v.y};
 }
 
 // One step of the reduce-scatter of 16 row partials over the 64 lanes: with
@@ -482,8 +498,8 @@ __device__ __forceinline__ zd g5_rowsum(zd (&v)[16], int lane) {
 // halve the rows each lane carries, xor 2 and 1 finish), which keeps the
 // register count low enough for 5 work-groups per CU.
 // part[((r nbk + K) nbk + L) 64 + i]: block (K, L)'s contribution to y_r.
-template <typename V, int NR>
-__global__ __launch_bounds__(256) void k_dense_mv_g5(const zd* __restrict__ Ap, const int* __restrict__ blk, int nbk,
+template <typename S, typename V, int NR>
+__global__ __launch_bounds__(256) void k_dense_mv_g5(const S* __restrict__ Ap, const int* __restrict__ blk, int nbk,
                                                      int n, const V* __restrict__ x, zd* __restrict__ part) {
   __shared__ zd xsh[NR][2][G5B];  // [r][0]: x_I, [r][1]: x_J
   __shared__ zd colsh[NR][4][G5B];
@@ -491,14 +507,10 @@ __global__ __launch_bounds__(256) void k_dense_mv_g5(const zd* __restrict__ Ap, 
   // the wave index is uniform over the wave: the x_I values of its rows are
   // then scalar operands, not registers per lane
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const zd* B = Ap + (size_t)q * G5B * G5B + (size_t)wave * G5B + lane;
+  const S* B = Ap + (size_t)q * G5B * G5B + (size_t)wave * G5B + lane;
   zd a[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {  // streamed once per product: non-temporal loads
-    const double* src = reinterpret_cast<const double*>(B + (size_t)k * 4 * G5B);
-    a[k].x = __builtin_nontemporal_load(src);
-    a[k].y = __builtin_nontemporal_load(src + 1);
-  }
+  for (int k = 0; k < 16; ++k) a[k] = g5_load(B + (size_t)k * 4 * G5B);
   if (threadIdx.x < NR * 2 * G5B) {
     const int r = threadIdx.x / (2 * G5B), h = (threadIdx.x / G5B) & 1;
     xsh[r][h][lane] = mv_in(x[(size_t)r * n + (h ? J : I) * G5B + lane]);
@@ -564,14 +576,14 @@ __global__ __launch_bounds__(512) void k_dense_mv_g5_reduce(const zd* __restrict
   }
 }
 
-template <typename V>
-static bool dense_mv_g5(const zd* Ap, const int* blk, int n, const V* x, V* y, int nrhs, zd* part, hipStream_t s) {
+template <typename S, typename V>
+static bool dense_mv_g5(const S* Ap, const int* blk, int n, const V* x, V* y, int nrhs, zd* part, hipStream_t s) {
   if (!Ap || nrhs < 1 || nrhs > 2 || n % G5B != 0) return false;
   const int nbk = n / G5B, nblk = nbk * (nbk + 1) / 2;
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_dense_mv_g5<V, 1>), dim3(nblk), dim3(256), 0, s, Ap, blk, nbk, n, x, part);
+    hipLaunchKernelGGL((k_dense_mv_g5<S, V, 1>), dim3(nblk), dim3(256), 0, s, Ap, blk, nbk, n, x, part);
   else
-    hipLaunchKernelGGL((k_dense_mv_g5<V, 2>), dim3(nblk), dim3(256), 0, s, Ap, blk, nbk, n, x, part);
+    hipLaunchKernelGGL((k_dense_mv_g5<S, V, 2>), dim3(nblk), dim3(256), 0, s, Ap, blk, nbk, n, x, part);
   hipLaunchKernelGGL(k_dense_mv_g5_reduce<V>, dim3(nbk, nrhs), dim3(512), 0, s, part, nbk, n, y);
   return true;
 }
@@ -581,6 +593,10 @@ bool launch_dense_mv_g5(const zd* Ap, const int* blk, int n, const zd* x, zd* y,
 }
 bool launch_dense_mv_g5_f32io(const zd* Ap, const int* blk, int n, const zf* x, zf* y, int nrhs, zd* part,
                               hipStream_t s) {
+  return dense_mv_g5(Ap, blk, n, x, y, nrhs, part, s);
+}
+bool launch_dense_mv_g5_c32(const zf* Ap, const int* blk, int n, const zf* x, zf* y, int nrhs, zd* part,
+                            hipStream_t s) {
   return dense_mv_g5(Ap, blk, n, x, y, nrhs, part, s);
 }
 

@@ -99,6 +99,7 @@ struct Level {
   void* Dst = nullptr;
   zf* Kinv32 = nullptr;
   zf* Ainv32 = nullptr;         // FP32 copy of the coarsest inverse
+  zf* Ap32 = nullptr;           // FP32 copy of its packed blocks (single-RHS product)
   zf *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
   Coarse coarse() const {
     Coarse c;
@@ -238,7 +239,7 @@ struct bamg_hierarchy {
     for (auto& L : lv) {
       dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.Ap); dfree(L.Ablk); dfree(L.Apart); dfree(L.P);
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
-      dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
+      dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.Ap32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
     }
     dfree(mmwork);
     dfree(xil); dfree(bil); dfree(xil32); dfree(bil32); dfree(xsw); dfree(xsw32);
@@ -436,7 +437,8 @@ struct bamg_hierarchy {
       Level& C = lv[l];
       if (nrhs > cap) throw HipFail("coarsest solve: more right-hand sides than the workspace holds");
       if (c32()) {
-        launch_dense_mv32(C.Ainv32, (int)C.n, b, x, nrhs, force_mr, (zf*)mmwork, s);
+        if (force_mr || !launch_dense_mv_g5_c32(C.Ap32, C.Ablk, (int)C.n, b, x, nrhs, C.Apart, s))
+          launch_dense_mv32(C.Ainv32, (int)C.n, b, x, nrhs, force_mr, (zf*)mmwork, s);
       } else if ((force_mr || !launch_dense_mv_g5_f32io(C.Ap, C.Ablk, (int)C.n, b, x, nrhs, C.Apart, s)) &&
                  !launch_dense_mv_f32io(C.Ainv, (int)C.n, b, x, nrhs, force_mr, s)) {
         launch_convert(b, C.b, C.n * nrhs, s);
@@ -526,6 +528,11 @@ struct bamg_hierarchy {
           throw HipFail("coarsest level: FP32 inverse needs n % 16 == 0 and the split-K workspace");
         if (!Lv.Ainv32) Lv.Ainv32 = dalloc<zf>(Lv.n * Lv.n);
         launch_convert(Lv.Ainv, Lv.Ainv32, Lv.n * Lv.n, s);
+        if (Lv.Ap) {
+          const size_t nbk = Lv.n / 64;
+          if (!Lv.Ap32) Lv.Ap32 = dalloc<zf>(nbk * (nbk + 1) / 2 * 64 * 64);
+          launch_pack_g5_f32(Lv.Ainv, (int)Lv.n, Lv.Ablk, Lv.Ap32, s);
+        }
       }
       if (l >= 1 && !(coarsest(l) && L() > 1)) {
         switch (p.precision) {

@@ -44,9 +44,12 @@ def test_host_only_entry_points():
     assert 50 * 2 ** 20 < fb < 2 * 2 ** 30
     assert b.bamg_footprint_bytes(b.bamg_default_params(N=36)) == 0
     assert b.bamg_footprint_bytes(b.bamg_default_params(N=512)) > fb
-    # the FP32 copy of the 8192 x 8192 coarsest inverse: 8 n^2 bytes, mixed precisions only
+    # the FP32 copies of the 8192 x 8192 coarsest inverse, mixed precisions only: the whole
+    # matrix (8 n^2 bytes) and its packed 64 x 64 blocks on and above the diagonal
+    # (8 (n^2 / 2 + 32 n) bytes)
     assert p.coarsest_fp32 == 0
+    n = 8192
     f16 = b.bamg_footprint_bytes(b.bamg_default_params(N=256, precision=1))
     f16c = b.bamg_footprint_bytes(b.bamg_default_params(N=256, precision=1, coarsest_fp32=1))
-    assert f16c - f16 == 8 * 8192 ** 2
+    assert f16c - f16 == 8 * n ** 2 + 8 * (n ** 2 // 2 + 32 * n)
     assert b.bamg_footprint_bytes(b.bamg_default_params(N=256, coarsest_fp32=1)) == 0

@@ -539,8 +539,10 @@ U32 = 2.0 ** -24  # unit roundoff of FP32
 @pytest.mark.parametrize("nrhs", [1, 2, 3, 9, 17, 40, 70])
 def test_mixed_coarsest_solve_fp32_inverse(bamg, imported_mixed, nrhs):
     """Op 12: the mixed cycle's coarsest solve with the FP32 copy of the
-    inverse (coarsest_fp32 = 1), complex64 in and out.  nrhs <= 2: one wave per row with FP64 sums;
-    else the split-K MFMA product (8, 16, 32 and 64 right-hand sides per
+    inverse (coarsest_fp32 = 1), complex64 in and out.  nrhs <= 2: the FP32
+    copy of the packed gamma5-Hermitian half (64 x 64 blocks on and above the
+    diagonal, rounded from the averaged FP64 blocks) with FP64 sums; else the
+    split-K MFMA product with the whole FP32 copy (8, 16, 32 and 64 right-hand sides per
     work-group; 70 spans two groups).  Componentwise bounds: rounding the
     inverse to FP32 costs u |A^-1| |b| (u = 2^-24); FP32 sums over the 2n real
     products of a row add at most 2n u |A^-1| |b|."""
