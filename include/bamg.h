@@ -98,8 +98,8 @@ typedef struct {
   int32_t n_ev;         /* k_e eigenvector approximations of the bootstrap modes (1..8, default 8) */
   int32_t boot_nu1, boot_nu2; /* sweeps of the two bootstrap setup cycles (default 10, 5) */
   int32_t coarsest_fp32; /* mixed precisions only.  0 (default): the cycle's coarsest solve applies the
-                           FP64 inverse (FP64 in and out).  1: it reads an FP32 copy of that inverse
-                           (rounded to nearest), FP32 in and out: half the bytes of the dominant read,
+                           FP64 inverse (FP64 in and out).  1: it reads FP32 copies of that inverse
+                           (rounded to nearest), FP32 in and out: half the bytes of the coarsest read,
                            relative rounding 2^-24 per entry */
 } bamg_params;
 
@@ -152,7 +152,12 @@ int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *
  *   op 1 BAMG_OP_SWEEP:    out <- one multicolour Kaczmarz sweep on A_l out = in (in place on out)
  *   op 2 BAMG_OP_RESTRICT: out (level l+1) = P_l^H in
  *   op 3 BAMG_OP_PROLONG:  out (level l) += P_l in (level l+1)
- *   op 4 BAMG_OP_COARSEST: out = A_L^-1 in  (l must be the coarsest level)
+ *   op 4 BAMG_OP_COARSEST: out = A_L^-1 in  (l must be the coarsest level).  For nrhs <= 2
+ *         and a dimension that is a multiple of 64 the product reads only the 64 x 64
+ *         blocks on and above the diagonal of the inverse, which is gamma5-Hermitian
+ *         like the coarsest operator (Sec. 3.5), and takes the others as their
+ *         mirrors (each stored block is the average of A_IJ and the mirror of A_JI);
+ *         else the whole inverse
  *   op 5 BAMG_OP_CYCLE:    out = one multigrid cycle from level l on A_l out = in, zero start
  *   op 6 BAMG_OP_RESIDUAL: out = in - A_l out  (in: right-hand side; out: iterate, overwritten)
  * Mixed-precision hierarchies only (in and out stay complex128; the work is
@@ -163,9 +168,11 @@ int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *
  *         are complex64 (interleaved float) arrays used as they are, with no
  *         conversion launches: exactly the kernels of one FP32 apply or sweep
  *   op 12 BAMG_OP_COARSEST_F32: out = A_L^-1 in with complex64 in and out
- *         (l the coarsest level, coarsest_fp32 = 1), read from the FP32 copy of
- *         the inverse that the mixed cycle then uses: one product launch for
- *         nrhs <= 2, else the split-K product on the matrix cores and its reduction
+ *         (l the coarsest level, coarsest_fp32 = 1), read from the FP32 copies of
+ *         the inverse that the mixed cycle then uses: for nrhs <= 2 the packed
+ *         blocks of op 4 in FP32 (block product, then the reduction of its partial
+ *         products), else the split-K product with the whole FP32 copy on the
+ *         matrix cores and its reduction
  * Ops 4 and 12 require in and out not to alias.
  * Level 0 is the fine reduced system (A_0 = Dhat). */
 enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLONG = 3,
@@ -210,7 +217,7 @@ int bamg_import_level(bamg_hierarchy *h, int32_t l, const void *P_host, const vo
 /* Device bytes a hierarchy with parameters p holds after bamg_setup and a first
  * single-RHS solve: every level's data and work vectors (sized for the setup's
  * n_tv + n_ev test vectors), the FP32 copies of the mixed modes, the coarsest
- * inverse with its scratch, the bootstrap eigensolver's blocks and the FGMRES
+ * inverse with its packed half and scratch, the bootstrap eigensolver's blocks and the FGMRES
  * workspace of one right-hand side.  0 for invalid parameters.  Batched solves
  * add workspace per right-hand side. */
 size_t bamg_footprint_bytes(const bamg_params *p);
