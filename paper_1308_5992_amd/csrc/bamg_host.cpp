@@ -151,6 +151,7 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
   const size_t n0 = N * N, kd = p->restart;
   if (mg && cap >= (size_t)IL_MIN) bytes += 2 * n0 * cap * zm;  // interleaved level-0 x and b
   bytes += (2 * kd + 5) * n0 * z;  // FGMRES bases and vectors, one right-hand side
+  bytes += (size_t)blas_nblocks_fine(n0) * 64 * cap * z;  // reduction partials
   if (mg) bytes += n0 * k * z;     // saved test vectors
   if (ne) {                        // eigensolver blocks
     const size_t nL = (size_t)sh.ext[L - 1].first * sh.ext[L - 1].second * 16, pc = std::min<size_t>(16, nL);
@@ -601,7 +602,7 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
   zd* h2 = h->hdev + 64 * R;
   zd* hn2 = h->hdev + 128 * R;
   // ||bhat_r||
-  launch_norms(h->bh, n, R, n, h->partial, hn2, s);
+  launch_norms(h->bh, n, R, n, h->partial, hn2, s, nullptr, true);
   HIPCHK(hipMemcpyAsync(hh, hn2, R * sizeof(zd), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<double> bnorm(R), relres(R, 1.0), beta(R);
@@ -616,7 +617,7 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
   std::vector<C> H((size_t)R * (m + 1) * m), g((size_t)R * (m + 1)), sn((size_t)R * m);
   std::vector<double> cs((size_t)R * m);
   while (true) {
-    launch_norms(h->rr, n, R, n, h->partial, hn2, s);
+    launch_norms(h->rr, n, R, n, h->partial, hn2, s, nullptr, true);
     HIPCHK(hipMemcpyAsync(hh, hn2, R * sizeof(zd), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     bool any = false;
@@ -653,7 +654,7 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
         launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, sc);
         launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, sc);
         launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, sc);
-        launch_norms(h->w, n, R, n, h->partial, hn2, sc);
+        launch_norms(h->w, n, R, n, h->partial, hn2, sc, nullptr, true);
         check_launch();
         HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
       });

@@ -251,6 +251,11 @@ size_t dense_mm32_workspace_bytes(int n, int nrhs);
 // ---- blas.hip ---------------------------------------------------------------
 // partial[b][v] = sum over block b of conj(X_v) w, X_v = X + v*ldx; then out[v] = sum_b partial[b][v]
 int blas_nblocks(size_t n);
+// the finer blocks of the batched forms below and of launch_norms with fine =
+// true (the FGMRES of bamg_solve / fgmres_batch, whose launches hold few
+// vectors): 512 entries each, at most 512 blocks; never fewer than
+// blas_nblocks(n), at most 4 times as many
+int blas_nblocks_fine(size_t n);
 void launch_multidot(const zd* X, size_t ldx, int nv, const zd* w, size_t n, zd* partial, zd* out,
                      hipStream_t s);
 // w += sign * sum_v X_v h_v   (h on device)
@@ -259,7 +264,7 @@ void launch_multiaxpy(const zd* X, size_t ldx, int nv, const zd* h, double sign,
 // per-vector squared norms of nv vectors of length n: out[v] (real part);
 // vector v at X + map[v] * ldx when map (device) is given, else X + v * ldx
 void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s,
-                  const int* map = nullptr);
+                  const int* map = nullptr, bool fine = false);
 // X_v *= 1/sqrt(nrm[v].x) for nrm > 0
 void launch_normalize(zd* X, size_t ldx, int nv, size_t n, const zd* nrm, hipStream_t s);
 // y = alpha x (alpha real, host scalar)

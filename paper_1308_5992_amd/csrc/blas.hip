@@ -16,6 +16,16 @@ int blas_nblocks(size_t n) {
   return (int)nb;
 }
 
+// Short per-block chains matter more than the partial count where a launch
+// holds few vectors (the single-RHS Gram-Schmidt); the slot engine's launches
+// hold many and keep the coarser blocks
+int blas_nblocks_fine(size_t n) {
+  size_t nb = (n + 511) / 512;
+  if (nb < 1) nb = 1;
+  if (nb > 512) nb = 512;
+  return (int)nb;
+}
+
 __device__ __forceinline__ zd block_sum(zd v, zd* sh) {
   const int tid = threadIdx.x;
   sh[tid] = v;
@@ -64,8 +74,9 @@ void launch_multidot(const zd* X, size_t ldx, int nv, const zd* w, size_t n, zd*
   hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
 }
 
-void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s, const int* map) {
-  const int nb = blas_nblocks(n);
+void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s, const int* map,
+                  bool fine) {
+  const int nb = fine ? blas_nblocks_fine(n) : blas_nblocks(n);
   hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, (const zd*)nullptr, n, partial, map);
   hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
 }
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(BT) void k_breduce(const zd* __restrict__ partial, 
 }
 
 void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s) {
-  const int nb = blas_nblocks(n);
+  const int nb = blas_nblocks_fine(n);
   hipLaunchKernelGGL(k_bdot_partial, dim3(nb, nv, R), dim3(BT), 0, s, X, R, W, n, partial);
   hipLaunchKernelGGL(k_breduce, dim3(nv, R), dim3(BT), 0, s, partial, nb, out);
 }

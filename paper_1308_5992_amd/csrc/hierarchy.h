@@ -217,7 +217,7 @@ struct bamg_hierarchy {
       const bool had_bases = V != nullptr || bases;
       free_krylov();
       kcap = cap2;
-      partial = dalloc<zd>((size_t)blas_nblocks(n0) * 64 * kcap);
+      partial = dalloc<zd>((size_t)blas_nblocks_fine(n0) * 64 * kcap);  // the finer of the two block counts
       hdev = dalloc<zd>((size_t)3 * 64 * kcap);
       HIPCHK(hipHostMalloc((void**)&hhost, (size_t)3 * 64 * kcap * sizeof(zd)));
       scal_dev = dalloc<double>(kcap);
