@@ -85,6 +85,39 @@ def test_galerkin_and_gamma5_on_all_levels(hier32):
         assert np.abs(Z - Z.conj().T).max() < 1e-13 * np.abs(Z).max()
 
 
+def test_coarsest_inverse_is_gamma5_hermitian(hier32):
+    """Sec. 3.5 with spin-blocked P: the coarsest operator is gamma5-Hermitian,
+    so its inverse is too, A^H = G A G with G = diag(+1 on spin 0, -1 on spin
+    1) (coarse dof 16 site + 8 s + k).  The single-RHS coarsest product rests
+    on this: it reads the 64 x 64 blocks on and above the diagonal and mirrors
+    the rest.  Here on the oracle's own coarsest inverse (dense numpy
+    inverse), within 10 kappa eps, and the mirror of the upper blocks rebuilds
+    the whole product."""
+    U, h = hier32
+    L = h.n_levels - 1
+    Ac = h.operator(L).toarray()
+    n = Ac.shape[0]
+    assert n % 64 == 0
+    Ainv = np.linalg.inv(Ac)
+    kappa = np.linalg.cond(Ac)
+    g = np.tile(np.r_[np.ones(8), -np.ones(8)], n // 16)
+    scale = np.abs(Ainv).max()
+    assert np.abs(Ainv.conj().T - g[:, None] * Ainv * g[None, :]).max() < 10 * kappa * 2.2e-16 * scale
+    # the packed form: blocks (I, J), I <= J, and their mirrors for I > J
+    B = 64
+    nb = n // B
+    M = np.zeros_like(Ainv)
+    for I in range(nb):
+        for J in range(I, nb):
+            blk = Ainv[I * B:(I + 1) * B, J * B:(J + 1) * B]
+            M[I * B:(I + 1) * B, J * B:(J + 1) * B] = blk
+            if I != J:
+                gi, gj = g[I * B:(I + 1) * B], g[J * B:(J + 1) * B]
+                M[J * B:(J + 1) * B, I * B:(I + 1) * B] = gj[:, None] * blk.conj().T * gi[None, :]
+    x = inputs.gaussian(n, 5)
+    assert np.abs(M @ x - Ainv @ x).max() < 10 * kappa * 2.2e-16 * np.abs(Ainv @ x).max() * 10
+
+
 def test_coarse_stencil_is_the_seven_block_set(hier32):
     U, h = hier32
     inf = h.level_info(1)
