@@ -56,7 +56,9 @@ def lib():
             "oracle_export_op": (None, [P, I, P, P, P]),
             "oracle_export_P": (None, [P, I, P]),
             "oracle_export_tv": (None, [P, P]),
-            "oracle_import_P": (None, [P, I, P]),
+            "oracle_import_P": (None, [P, I, P, I]),
+            "oracle_set_coarsest_lu": (None, [P, P, P]),
+            "oracle_stationary": (None, [P, P, I, P]),
             "oracle_level_op": (I, [P, I, I, P, P, I]),
             "oracle_solve_reduced": (I, [P, P, P, D, I, I, P]),
             "oracle_solve": (I, [P, P, P, D, I, I, P]),
@@ -250,9 +252,30 @@ class Hierarchy:
         lib().oracle_export_P(self.h, l, _p(out))
         return out
 
-    def import_P(self, l, P):
+    def import_P(self, l, P, factor=True):
+        """Replace P_l and rebuild level l+1 by the Galerkin product.  With
+        factor=False a new coarsest level is not factored: the caller then
+        supplies its LU factors through set_coarsest_lu."""
         P = _c(P)
-        lib().oracle_import_P(self.h, l, _p(P))
+        lib().oracle_import_P(self.h, l, _p(P), 1 if factor else 0)
+
+    def set_coarsest_lu(self, lu, piv):
+        """Factors P A = L U of the coarsest operator (LAPACK getrf convention:
+        unit L below the diagonal, U on and above it, piv[k] the row swapped
+        with row k at step k, 0-based); the coarsest solve substitutes with them."""
+        n = self.level_info(self.n_levels - 1)["n"]
+        lu = np.ascontiguousarray(lu, dtype=np.complex128)
+        piv = np.ascontiguousarray(piv, dtype=np.int32)
+        assert lu.shape == (n, n) and piv.shape == (n,)
+        lib().oracle_set_coarsest_lu(self.h, _p(lu), _p(piv))
+
+    def stationary(self, x0, iters):
+        """Stand-alone iteration x <- x + M(0 - Dhat x) (Sec. 4) from x0:
+        (final x, norms of x after 0..iters iterations)."""
+        x = _c(x0).copy()
+        norms = np.zeros(iters + 1)
+        lib().oracle_stationary(self.h, _p(x), iters, _p(norms))
+        return x, norms
 
     def test_vectors(self):
         out = np.zeros((self.n_tv, self.N * self.N), dtype=np.complex128)

@@ -29,6 +29,15 @@
 //   * Coarsest grid solved directly (Sec. 4): dense LU with partial pivoting.
 //   * Outer Krylov (Sec. 4): flexible GMRES(32) right-preconditioned by one
 //     multigrid cycle, classical Gram-Schmidt applied twice, Givens rotations.
+//   * Cycles: the two-grid scheme of Sec. 1 applied recursively with gamma = 1
+//     (V) or gamma = 2 (W, the solve cycle of Sec. 4) coarse visits; the
+//     K-cycle option replaces the coarse visit of every level whose coarser
+//     neighbour is not the coarsest by two steps of flexible GCR on the coarse
+//     system, each preconditioned by one cycle from that level (the paper
+//     names no Krylov-accelerated cycle; this is the recursive Krylov cycle of
+//     the multigrid literature, with a fixed two steps).
+//   * Stand-alone convergence rate (Sec. 4): rho = ||e^nu|| / ||e^{nu-1}|| of
+//     the iteration x <- x + M (b - Dhat x) with M one cycle, on b = 0.
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -430,7 +439,7 @@ void lu_solve(const Level& L, const cplx* b, cplx* x) {
 struct Hier {
   Problem prob;
   std::vector<Level> lv;
-  int pre = 4, post = 4, cycle = 0;  // cycle: 0 V, 1 W
+  int pre = 4, post = 4, cycle = 0;  // cycle: 0 V, 1 W, 2 K
   int n_tv = 8, sweeps = 20, adapt = 1;
   std::vector<cplx> tv;  // level-1 test vectors after setup, [k][n1]
   // bootstrap eigensolver: eigenvector approximations V^e on level 1 and their Ritz values
@@ -445,6 +454,47 @@ double vnorm(const cplx* v, int n) {
 }
 
 void coarsen_level(Hier& h, int l);
+void mg_cycle(Hier& h, int l, const cplx* b, cplx* x);
+
+// <u, v> = sum_i conj(u_i) v_i
+cplx vdot(const cplx* u, const cplx* v, int n) {
+  cplx s = 0.0;
+  for (int i = 0; i < n; ++i) s += std::conj(u[i]) * v[i];
+  return s;
+}
+
+// K-cycle coarse visit: two steps of flexible GCR on A_c x = r0 from x = 0,
+// each step preconditioned by one cycle from level c.
+//   z1 = M r0, w1 = A z1, a1 = <w1, r0> / <w1, w1>, x = a1 z1, r1 = r0 - a1 w1,
+//   z2 = M r1, w2 = A z2, beta = <w1, w2> / <w1, w1>, w2 -= beta w1, z2 -= beta z1,
+//   a2 = <w2, r1> / <w2, w2>, x += a2 z2.
+// A step whose <w, w> vanishes adds nothing.
+void kcycle_visit(Hier& h, int c, const cplx* r0, cplx* x) {
+  const CSR& A = h.lv[c].A;
+  int n = A.nr;
+  std::vector<cplx> z1(n, 0.0), w1(n), r1(n), z2(n, 0.0), w2(n);
+  std::fill(x, x + n, cplx(0.0));
+  mg_cycle(h, c, r0, z1.data());
+  csr_mv(A, z1.data(), w1.data());
+  double rho1 = vdot(w1.data(), w1.data(), n).real();
+  if (rho1 == 0.0) return;
+  cplx a1 = vdot(w1.data(), r0, n) / rho1;
+  for (int i = 0; i < n; ++i) {
+    x[i] = a1 * z1[i];
+    r1[i] = r0[i] - a1 * w1[i];
+  }
+  mg_cycle(h, c, r1.data(), z2.data());
+  csr_mv(A, z2.data(), w2.data());
+  cplx beta = vdot(w1.data(), w2.data(), n) / rho1;
+  for (int i = 0; i < n; ++i) {
+    w2[i] -= beta * w1[i];
+    z2[i] -= beta * z1[i];
+  }
+  double rho2 = vdot(w2.data(), w2.data(), n).real();
+  if (rho2 == 0.0) return;
+  cplx a2 = vdot(w2.data(), r1.data(), n) / rho2;
+  for (int i = 0; i < n; ++i) x[i] += a2 * z2[i];
+}
 
 // multigrid cycle on level l: x (in/out, initial guess) for A_l x = b
 void mg_cycle(Hier& h, int l, const cplx* b, cplx* x) {
@@ -458,10 +508,15 @@ void mg_cycle(Hier& h, int l, const cplx* b, cplx* x) {
   int nc = h.lv[l + 1].A.nr;
   std::vector<cplx> bc(nc), xc(nc, 0.0);
   csr_mv(L.PH, r.data(), bc.data());
-  int gamma = (h.cycle == 1) ? 2 : 1;
-  for (int g = 0; g < gamma; ++g) {
-    mg_cycle(h, l + 1, bc.data(), xc.data());
-    if (l + 1 == (int)h.lv.size() - 1) break;  // exact solve: a second visit changes nothing
+  bool coarsest_next = (l + 1 == (int)h.lv.size() - 1);
+  if (h.cycle == 2 && !coarsest_next) {
+    kcycle_visit(h, l + 1, bc.data(), xc.data());
+  } else {
+    int gamma = (h.cycle == 1) ? 2 : 1;
+    for (int g = 0; g < gamma; ++g) {
+      mg_cycle(h, l + 1, bc.data(), xc.data());
+      if (coarsest_next) break;  // exact solve: a second visit changes nothing
+    }
   }
   std::vector<cplx> e(n);
   csr_mv(L.P, xc.data(), e.data());
@@ -1133,13 +1188,58 @@ void oracle_export_tv(void* hp, double* tv) {
   std::copy(h->tv.begin(), h->tv.end(), (cplx*)tv);
 }
 
-// replace P of level l (aggregate blocks) and rebuild level l+1 (and the LU if coarsest)
-void oracle_import_P(void* hp, int l, const double* P) {
+// replace P of level l (aggregate blocks) and rebuild level l+1 (and the LU if
+// coarsest and `factor` is nonzero; else the coarsest level waits for
+// oracle_set_coarsest_lu)
+void oracle_import_P(void* hp, int l, const double* P, int factor) {
   Hier* h = (Hier*)hp;
   Level& L = h->lv[l];
-  L.Pblk.assign((const cplx*)P, (const cplx*)P + L.Pblk.size());
+  L.Pblk.assign((const cplx*)P, (const cplx*)P + (size_t)L.cx * L.cy * 2 * L.rows_per * 8);
   build_P_csr(L, l == 0);
-  coarsen_level(*h, l);
+  if (factor) {
+    coarsen_level(*h, l);
+    return;
+  }
+  Level& C = h->lv[l + 1];
+  C.A = csr_mul(L.PH, csr_mul(L.A, L.P));
+  level_norms_and_order(C, false, h->prob.N);
+  if (l + 1 == (int)h->lv.size() - 1) { C.LU.clear(); C.piv.clear(); C.singular = true; }
+}
+
+// LU factors of the coarsest operator computed elsewhere (row-major n x n, unit
+// lower triangle below the diagonal, U on and above it; piv[k]: the row swapped
+// with row k at step k, 0-based), for the coarsest solve by substitution
+void oracle_set_coarsest_lu(void* hp, const double* LU, const int* piv) {
+  Hier* h = (Hier*)hp;
+  Level& C = h->lv.back();
+  int n = C.A.nr;
+  C.LU.assign((const cplx*)LU, (const cplx*)LU + (size_t)n * n);
+  C.piv.assign(piv, piv + n);
+  C.singular = false;
+  for (int i = 0; i < n; ++i)
+    if (C.LU[(size_t)i * n + i] == 0.0) C.singular = true;
+}
+
+// Stand-alone iteration of the solver on Dhat x = 0 (Sec. 4): x <- x + M(0 - Dhat x)
+// with M one cycle (zero initial guess), `iters` times from x (in/out);
+// norms[i] = ||x|| after i iterations (norms[0] = ||x0||), so the error
+// reduction of iteration i is norms[i] / norms[i-1].
+void oracle_stationary(void* hp, double* xio, int iters, double* norms) {
+  Hier* h = (Hier*)hp;
+  const CSR& A = h->lv[0].A;
+  int n = A.nr;
+  cplx* x = (cplx*)xio;
+  std::vector<cplx> r(n), z(n);
+  norms[0] = vnorm(x, n);
+  if (h->lv.size() > 1 && h->lv.back().LU.empty()) return;  // coarsest not factored
+  for (int it = 0; it < iters; ++it) {
+    csr_mv(A, x, r.data());
+    for (int i = 0; i < n; ++i) r[i] = -r[i];
+    std::fill(z.begin(), z.end(), cplx(0.0));
+    mg_cycle(*h, 0, r.data(), z.data());
+    for (int i = 0; i < n; ++i) x[i] += z[i];
+    norms[it + 1] = vnorm(x, n);
+  }
 }
 
 // level operations on nrhs vectors: op 0: y = A_l x; 1: x <- one Kaczmarz sweep on
@@ -1151,6 +1251,7 @@ int oracle_level_op(void* hp, int l, int op, const double* in, double* out, int 
   Level& L = h->lv[l];
   int n = L.A.nr;
   int nc = (l + 1 < (int)h->lv.size()) ? h->lv[l + 1].A.nr : 0;
+  if ((op == 4 || op == 5) && h->lv.back().LU.empty()) return -4;  // coarsest not factored
   for (int j = 0; j < nrhs; ++j) {
     switch (op) {
       case 0: csr_mv(L.A, (const cplx*)in + (size_t)j * n, (cplx*)out + (size_t)j * n); break;
@@ -1190,6 +1291,7 @@ int oracle_solve_reduced(void* hp, const double* bh, double* xo, double tol, int
   info[0] = 0; info[1] = 0; info[2] = 0; info[3] = 0; info[4] = 0;
   if (!std::isfinite(bnorm)) return -1;
   if (bnorm == 0.0) return 0;
+  if (h->lv.back().LU.empty()) return -4;  // coarsest not factored
   std::vector<cplx> r(b, b + n);
   int it = 0, restarts = 0;
   double relres = 1.0;
