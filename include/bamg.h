@@ -62,7 +62,19 @@ typedef enum {
   BAMG_ENOTIMPL = -5
 } bamg_status;
 
-typedef enum { BAMG_CYCLE_V = 0, BAMG_CYCLE_W = 1 } bamg_cycle;
+/* Cycle of the preconditioner (Sec. 1 two-grid scheme applied recursively; Sec. 4):
+ *   V: one visit of the coarser level per visit of a level;
+ *   W: two visits (the solve cycle of Sec. 4; on two levels the same as V);
+ *   K: every level l >= 1 that is not the coarsest is visited by two steps of
+ *      flexible GCR on its coarse system from a zero start, each preconditioned
+ *      by one (K-)cycle from that level: z1 = M r0, w1 = A z1, a1 = <w1, r0>/<w1, w1>,
+ *      r1 = r0 - a1 w1, z2 = M r1, w2 = A z2 made orthogonal to w1 (z2 alike),
+ *      x = a1 z1 + a2 z2 with a2 = <w2, r1>/<w2, w2>.  The paper names no
+ *      Krylov-accelerated cycle; this is the recursive Krylov cycle of the
+ *      multigrid literature with a fixed two steps (no norm test), so that a
+ *      visit is a fixed launch sequence.  It makes the preconditioner depend on
+ *      its input nonlinearly, which the flexible outer GMRES allows. */
+typedef enum { BAMG_CYCLE_V = 0, BAMG_CYCLE_W = 1, BAMG_CYCLE_K = 2 } bamg_cycle;
 
 typedef enum {
   BAMG_FP64 = 0,        /* everything in FP64 */
@@ -72,6 +84,11 @@ typedef enum {
   BAMG_MIXED_FP32 = 3   /* as above with FP32 storage */
 } bamg_precision;
 
+/* Aggregates are fixed (Sec. 3.3 aggregates, reading: 4 x 4 blocks): level 1 is
+ * built from 4 x 4 blocks of the half-x grid of even sites (16 sites, 32 dofs,
+ * 16 coarse dofs), every further level from 2 x 2 blocks of the sites below;
+ * there is no per-level shape parameter.  Levels are added while the
+ * extents stay even and >= 4 (up to n_levels, or until max_coarse). */
 typedef struct {
   int32_t N;            /* lattice extent, N % 8 == 0, N >= 16 */
   int32_t n_levels;     /* 0: automatic (coarsen until the level dimension <= max_coarse) */
@@ -107,8 +124,11 @@ typedef struct {
   int32_t iters;          /* FGMRES iterations (preconditioner applications) */
   int32_t restarts;       /* restarts performed */
   double relres_reduced;  /* ||bhat - Dhat x_e|| / ||bhat|| (true residual) */
-  double relres_full;     /* ||b - D x|| / ||b|| (0 when not computed) */
-  double rho_est;         /* relres_reduced^(1/iters) */
+  double relres_full;     /* ||b - D x|| / ||b|| of the unreduced system (eq. wilson), computed on the
+                             device after the reconstruction (one application of D); 0 for a
+                             request that failed before x was written */
+  double rho_est;         /* relres_reduced^(1/iters), the mean residual reduction per FGMRES
+                             iteration (the convergence rate of Sec. 4 is bamg_stationary's) */
   double t_solve_ms;      /* host wall time of the call */
 } bamg_solve_info;
 
@@ -208,11 +228,38 @@ int bamg_level_info(const bamg_hierarchy *h, int32_t level, int32_t *info_host);
  * [n_tv][N*N] after the last setup pass (l == 0 only). */
 int bamg_export_level(const bamg_hierarchy *h, int32_t l, void *P_host, void *Dl_host, void *tv_host);
 
-/* Replace P_l (host, aggregate blocks) and rebuild level l+1 by the Galerkin
- * product (and its smoother data, or the coarsest inverse).  Dl_host must be
- * NULL (reserved).  Levels below l+1 keep their old P and are rebuilt by
- * importing them in order. */
+/* Replace parts of level l from host buffers (at least one non-NULL):
+ *   Dl_host (l >= 1): the coarse operator D_l in blocks [site][7][16][16] (the
+ *     export layout); its smoother data, or on the coarsest level its inverse,
+ *     is rebuilt from it.  BAMG_ESINGULAR if a coarsest D_l is singular.
+ *   P_host (l < L-1): P_l in aggregate blocks; level l+1 is then rebuilt by the
+ *     Galerkin product P_l^H D_l P_l (Sec. 3.5) of the current D_l, with its
+ *     smoother data or inverse.
+ * D_l is replaced first, so both together give D_{l+1} = P^H D_l P from the new
+ * pair.  Levels below l+1 keep their old P and D and are rebuilt by importing
+ * them in order. */
 int bamg_import_level(bamg_hierarchy *h, int32_t l, const void *P_host, const void *Dl_host);
+
+/* Stand-alone iteration of the solver (Sec. 4: the convergence rate
+ * rho = ||e^nu|| / ||e^{nu-1}|| of BAMG used on its own): x <- x + M(0 - Dhat x)
+ * on the reduced system, M the hierarchy's preconditioner (one cycle in its
+ * precision, zero initial guess), `iters` times from x (device, reduced
+ * vector, overwritten by the last iterate).  With b = 0 the iterate is the
+ * error.  norms_host[i] = ||x|| after i iterations (iters + 1 entries), so the
+ * rate of iteration i is norms_host[i] / norms_host[i-1]. */
+int bamg_stationary(bamg_hierarchy *h, void *x, int32_t iters, double *norms_host);
+
+/* Residual norms of the unreduced system (Sec. 2, eq. wilson), independent of
+ * any hierarchy: relres[r] = ||b_r - D x_r|| / ||b_r|| (||b_r - D x_r|| where
+ * b_r = 0) for nrhs full-lattice pairs, D = (m + 2) I - H with the gauge field
+ * U[mu][y][x].  gauge, B, X ([nrhs][y][x][s]) and relres (nrhs doubles) are
+ * device arrays; the work is queued on `stream` (NULL: the null stream) and
+ * relres is valid when it completes.  The partial sums (2 * min(256,
+ * ceil(N^2 / 1024)) doubles per right-hand side) are allocated and freed on
+ * the stream by the call.  BAMG_EINVAL for bad sizes, BAMG_ENOMEM if the
+ * partial sums cannot be allocated. */
+int bamg_full_residual(int32_t N, const void *gauge, double m, const void *B, const void *X, int32_t nrhs,
+                       double *relres, void *stream);
 
 /* Device bytes a hierarchy with parameters p holds after bamg_setup and a first
  * single-RHS solve: every level's data and work vectors (sized for the setup's

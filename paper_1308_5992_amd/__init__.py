@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbamg.so")
 
 BAMG_OK, BAMG_NOT_CONVERGED, BAMG_PENDING = 0, 1, 2
 BAMG_EINVAL, BAMG_ENOMEM, BAMG_EDEVICE, BAMG_ESINGULAR, BAMG_ENOTIMPL = -1, -2, -3, -4, -5
-BAMG_CYCLE_V, BAMG_CYCLE_W = 0, 1
+BAMG_CYCLE_V, BAMG_CYCLE_W, BAMG_CYCLE_K = 0, 1, 2
 BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
 OP_APPLY, OP_SWEEP, OP_RESTRICT, OP_PROLONG, OP_COARSEST, OP_CYCLE, OP_RESIDUAL = range(7)
 OP_APPLY_MIXED, OP_SWEEP_MIXED, OP_CYCLE_MIXED = 7, 8, 9
@@ -32,7 +32,7 @@ EXPORTED = [
     "bamg_free", "bamg_last_error", "bamg_boot_op", "bamg_export_boot",
     "bamg_server_default_params", "bamg_server_create", "bamg_server_add_field", "bamg_server_field_bytes",
     "bamg_server_submit", "bamg_server_progress", "bamg_server_wait", "bamg_server_get_stats", "bamg_server_reset_stats",
-    "bamg_server_free",
+    "bamg_server_free", "bamg_stationary", "bamg_full_residual",
 ]
 
 
@@ -118,6 +118,8 @@ def _load():
         "bamg_server_get_stats": (I32, [P, ctypes.POINTER(bamg_server_stats)]),
         "bamg_server_reset_stats": (I32, [P]),
         "bamg_server_free": (None, [P]),
+        "bamg_stationary": (I32, [P, P, I32, P]),
+        "bamg_full_residual": (I32, [I32, P, D, P, P, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -277,9 +279,31 @@ def bamg_export_level(h, level: int, P=True, D=True, tv=False, n_tv=8):
     return Pa, Da, Ta
 
 
-def bamg_import_level(h, level: int, P):
-    P = np.ascontiguousarray(P, dtype=np.complex128)
-    _check(lib.bamg_import_level(h, int(level), P.ctypes.data, None), "bamg_import_level")
+def bamg_import_level(h, level: int, P=None, D=None):
+    """P: host P_l [agg][2][rows][8] (rebuilds level l+1); D: host D_l [site][7][16][16]
+    (level >= 1; replaced first)."""
+    P = None if P is None else np.ascontiguousarray(P, dtype=np.complex128)
+    D = None if D is None else np.ascontiguousarray(D, dtype=np.complex128)
+    _check(lib.bamg_import_level(h, int(level), None if P is None else P.ctypes.data,
+                                 None if D is None else D.ctypes.data), "bamg_import_level")
+
+
+def bamg_stationary(h, x, iters: int):
+    """x (reduced, complex128 GPU tensor) <- iters steps of x + M(0 - Dhat x);
+    returns the norms of x after 0..iters steps (numpy)."""
+    norms = np.zeros(int(iters) + 1)
+    _check(lib.bamg_stationary(h, _ptr(x), int(iters), norms.ctypes.data), "bamg_stationary")
+    return norms
+
+
+def bamg_full_residual(N: int, gauge, m: float, B, X, nrhs: int, relres):
+    """relres (float64 GPU tensor of nrhs) = ||b - D x|| / ||b|| per right-hand side."""
+    import torch
+    if not (isinstance(relres, torch.Tensor) and relres.is_cuda and relres.dtype == torch.float64
+            and relres.is_contiguous() and relres.numel() >= nrhs):
+        raise TypeError("relres must be a contiguous float64 GPU tensor of nrhs entries")
+    _check(lib.bamg_full_residual(int(N), _ptr(gauge), float(m), _ptr(B), _ptr(X), int(nrhs),
+                                  ctypes.c_void_p(relres.data_ptr()), _stream()), "bamg_full_residual")
 
 
 def bamg_fine_sweep_plan(N: int, nrhs: int = 1, fp32: bool = False, form: int = 0):

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbamg.so")
-SOURCES = ["fine.hip", "coarse.hip", "dense.hip", "blas.hip", "boot.hip", "bamg_host.cpp", "engine.cpp", "server.cpp"]
+SOURCES = ["fine.hip", "coarse.hip", "dense.hip", "blas.hip", "boot.hip", "kcycle.hip", "residual.hip", "bamg_host.cpp", "engine.cpp",
+           "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -67,7 +67,7 @@ bool valid_params(const bamg_params* p, std::string& why) {
   if (!p) { why = "params is NULL"; return false; }
   if (p->n_tv != 8) { why = "n_tv must be 8"; return false; }
   if (p->setup_sweeps < 0 || p->setup_adapt < 0 || p->pre < 0 || p->post < 0) { why = "negative count"; return false; }
-  if (p->cycle != BAMG_CYCLE_V && p->cycle != BAMG_CYCLE_W) { why = "unknown cycle"; return false; }
+  if (p->cycle != BAMG_CYCLE_V && p->cycle != BAMG_CYCLE_W && p->cycle != BAMG_CYCLE_K) { why = "unknown cycle"; return false; }
   if (p->precision < BAMG_FP64 || p->precision > BAMG_MIXED_FP32) { why = "unknown precision"; return false; }
   if (p->restart < 1 || p->restart > 60) { why = "restart must be in [1, 60]"; return false; }
   if (p->max_iter < 0) { why = "max_iter < 0"; return false; }
@@ -129,13 +129,17 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
   const size_t zm = z + (mixed ? sizeof(zf) : 0);  // an entry and its FP32 copy in the mixed modes
   const size_t zc = z + (mixed && p->coarsest_fp32 ? sizeof(zf) : 0);  // entry of the coarsest inverse
   const size_t sst = p->precision == BAMG_MIXED_FP32 ? sizeof(zf) : sizeof(hcx);  // stored coarse operator entry
+  auto kvis = [&](int l) { return p->cycle == BAMG_CYCLE_K && l >= 1 && l + 1 < L; };
   size_t bytes = (2 * N * N + (N * N / 2) * 38) * zm;  // links, stored slot blocks of Dhat and their Gram terms
+  if (L > 2 && p->cycle == BAMG_CYCLE_K)  // K-cycle reduction partials (the largest visited level is level 1)
+    bytes += (size_t)kcycle_nblocks((size_t)sh.ext[1].first * sh.ext[1].second * 16) * 2 * cap * z;
   for (int l = 0; l < L; ++l) {
     const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
     const size_t n = ns * (l == 0 ? 2 : 16);
     const bool last = l == L - 1;
     bytes += (l == 0 ? 4 : 3) * n * cap * zm;  // x, b, r (level 0: and the second x of the blocked sweeps)
     if (!mg) break;
+    if (kvis(l)) bytes += 5 * n * cap * zm + 4 * cap * z;  // K-cycle visit vectors and coefficients
     bytes += n * (k + ne) * z;  // test vectors
     if (l >= 1) bytes += ns * NOFF * 256 * z;  // coarse operator
     if (l >= 1 && !last) bytes += ns * 256 * zm + (mixed ? ns * NOFF * 256 * sst : 0);  // Kinv; stored operator
@@ -174,9 +178,12 @@ size_t bamg::hierarchy_slot_extra_bytes(const bamg_params* p, int slots) {
   size_t bytes = 0;
   const size_t n0 = (size_t)sh.ext[0].first * sh.ext[0].second * 2;
   if (S >= (size_t)IL_MIN) bytes += 2 * n0 * (S - (cap >= (size_t)IL_MIN ? cap : 0)) * zm;  // interleaved level 0
+  if (L > 2 && p->cycle == BAMG_CYCLE_K)
+    bytes += (size_t)kcycle_nblocks((size_t)sh.ext[1].first * sh.ext[1].second * 16) * 2 * (S - cap) * sizeof(zd);
   for (int l = 0; l < L; ++l) {
     const size_t n = (size_t)sh.ext[l].first * sh.ext[l].second * (l == 0 ? 2 : 16);
     bytes += (l == 0 ? 4 : 3) * n * (S - cap) * zm;  // the level work vectors grow to S right-hand sides
+    if (p->cycle == BAMG_CYCLE_K && l >= 1 && l + 1 < L) bytes += (5 * n * zm + 4 * sizeof(zd)) * (S - cap);
     if (l == L - 1 && L > 1)
       bytes += (dense_mm_workspace((int)n, slots) - dense_mm_workspace((int)n, (int)cap)) * sizeof(zd);
   }
@@ -471,12 +478,22 @@ int bamg_export_level(const bamg_hierarchy* hc, int32_t l, void* P_host, void* D
 }
 
 int bamg_import_level(bamg_hierarchy* h, int32_t l, const void* P_host, const void* Dl_host) {
-  if (!h || l < 0 || l + 1 >= h->L() || !P_host) return fail(BAMG_EINVAL, "bad level or P");
-  if (Dl_host) return fail(BAMG_EINVAL, "Dl_host is reserved and must be NULL");
+  if (!h || l < 0 || l >= h->L() || (!P_host && !Dl_host)) return fail(BAMG_EINVAL, "bad level, or neither P nor D_l");
+  if (P_host && l + 1 >= h->L()) return fail(BAMG_EINVAL, "no P on the coarsest level");
+  if (Dl_host && (l == 0 || h->L() < 2)) return fail(BAMG_EINVAL, "level 0 has no block operator");
   try {
     Level& Lv = h->lv[l];
-    HIPCHK(hipMemcpyAsync(Lv.P, P_host, Lv.n * 8 * sizeof(zd), hipMemcpyHostToDevice, h->s));
-    h->build_next(l);
+    if (Dl_host) {  // D_l replaced: its smoother data, or (coarsest) its inverse, follow
+      HIPCHK(hipMemcpyAsync(Lv.D, Dl_host, (size_t)Lv.ex * Lv.ey * NOFF * 256 * sizeof(zd), hipMemcpyHostToDevice,
+                            h->s));
+      if (h->coarsest(l)) h->invert_coarsest();
+      else launch_kaczmarz_prep(Lv.coarse(), Lv.Kinv, h->s);
+      check_launch();
+    }
+    if (P_host) {
+      HIPCHK(hipMemcpyAsync(Lv.P, P_host, Lv.n * 8 * sizeof(zd), hipMemcpyHostToDevice, h->s));
+      h->build_next(l);
+    }
     h->refresh_mixed();
     HIPCHK(hipStreamSynchronize(h->s));
   } catch (const HipFail& e) {
@@ -560,6 +577,48 @@ int bamg_export_boot(const bamg_hierarchy* hc, double* lam_host, void* ve_host) 
     return fail(BAMG_EDEVICE, e.msg);
   }
   return h->ke;
+}
+
+int bamg_stationary(bamg_hierarchy* h, void* x, int32_t iters, double* norms_host) {
+  if (!h || !x || !norms_host || iters < 0) return fail(BAMG_EINVAL, "bad arguments");
+  try {
+    h->ensure_krylov(1, true);
+    h->ensure_cap(1);
+    const size_t n = h->lv[0].n;
+    zd* e = (zd*)x;
+    hipStream_t s = h->s;
+    auto norm_to_host = [&](int i) {
+      launch_norms(e, n, 1, n, h->partial, h->hdev, s);
+      check_launch();
+      HIPCHK(hipMemcpyAsync(h->hhost, h->hdev, sizeof(zd), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      norms_host[i] = std::sqrt(h->hhost[0].x);
+    };
+    norm_to_host(0);
+    for (int it = 0; it < iters; ++it) {
+      h->apply(0, e, h->rr, nullptr, 1);  // r = Dhat e (the residual of Dhat e = 0 is -r)
+      h->precondition(h->rr, h->w, 1);    // w = M r
+      launch_sub(h->w, e, n, s);          // e <- e + M(0 - Dhat e) = e - M r
+      norm_to_host(it + 1);
+    }
+  } catch (const HipFail& e) {
+    return fail(BAMG_EDEVICE, e.msg);
+  }
+  return BAMG_OK;
+}
+
+int bamg_full_residual(int32_t N, const void* gauge, double m, const void* B, const void* X, int32_t nrhs,
+                       double* relres, void* stream) {
+  if (N < 2 || !gauge || !B || !X || !relres || nrhs < 1) return fail(BAMG_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  double* part = nullptr;
+  const size_t bytes = (size_t)2 * resnorm_nblocks(N) * nrhs * sizeof(double);
+  if (hipMallocAsync((void**)&part, bytes, s) != hipSuccess) return fail(BAMG_ENOMEM, "partial sums");
+  launch_wilson_resnorm(N, (const zd*)gauge, m + 2.0, (const zd*)B, (const zd*)X, nrhs, part, relres, s);
+  const hipError_t le = hipGetLastError();
+  (void)hipFreeAsync(part, s);
+  if (le != hipSuccess) return fail(BAMG_EDEVICE, std::string("launch: ") + hipGetErrorString(le));
+  return BAMG_OK;
 }
 
 int bamg_fine_sweep_plan(int32_t N, int32_t nrhs, int32_t fp32, int32_t form, int32_t* plan_out) {
@@ -752,8 +811,12 @@ static int solve_single(bamg_hierarchy* h, const void* B, void* X, double tol, b
     if (*h->hflag) return fail(BAMG_EINVAL, "right-hand side is not finite");
     st = fgmres_batch(h, 1, tol, info);
     launch_eo_reconstruct(h->f, (const zd*)B, h->xe, (zd*)X, 1, h->s);
+    // ||b - D x|| / ||b|| of the unreduced system (one apply of D and two norms)
+    launch_wilson_resnorm_packed(h->f, (const zd*)B, (const zd*)X, 1, (double*)h->partial, (double*)h->hdev, h->s);
     check_launch();
+    HIPCHK(hipMemcpyAsync(h->hhost, h->hdev, sizeof(double), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipStreamSynchronize(h->s));
+    info->relres_full = ((const double*)h->hhost)[0];
   } catch (const HipFail& e) {
     return fail(BAMG_EDEVICE, e.msg);
   }

@@ -270,6 +270,8 @@ void launch_normalize(zd* X, size_t ldx, int nv, size_t n, const zd* nrm, hipStr
 // y = alpha x (alpha real, host scalar)
 void launch_scale_copy(const zd* x, zd* y, size_t n, double alpha, hipStream_t s);
 void launch_fill_zero(zd* x, size_t n, hipStream_t s);
+// x -= z
+void launch_sub(const zd* z, zd* x, size_t n, hipStream_t s);
 // zero `bytes` bytes (a multiple of 8) with a kernel (no memset node)
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_copy(const zd* x, zd* y, size_t n, hipStream_t s);
@@ -306,6 +308,41 @@ void launch_sgather(const zd* X, size_t lds, size_t ldv, const int* slot, const 
 // X_{slot[a], j[a]} = c[a] * Y_{src[a]} with Y_k at Y + k*ldy (c NULL: copy; src NULL: a; j NULL: 0)
 void launch_sscatter(const zd* Y, size_t ldy, const int* src, zd* X, size_t lds, size_t ldv, const int* slot,
                      const int* j, const double* c, size_t n, int A, hipStream_t s);
+
+// ---- residual.hip: residual norms of the unreduced system (eq. wilson) -------
+// relres[r] = ||b_r - D x_r|| / ||b_r|| (||b_r - D x_r|| if b_r = 0) for nrhs
+// full-lattice pairs; partial holds 2 * resnorm_nblocks(N) * nrhs doubles,
+// relres nrhs doubles (both device)
+constexpr int RESNORM_MAX_BLOCKS = 256;
+int resnorm_nblocks(int N);
+// links from the caller's U[mu][y][x], c = m + 2
+void launch_wilson_resnorm(int N, const zd* U, double c, const zd* B, const zd* X, int nrhs, double* partial,
+                           double* relres, hipStream_t s);
+// links from the hierarchy's packed copy
+void launch_wilson_resnorm_packed(const Fine& f, const zd* B, const zd* X, int nrhs, double* partial,
+                                  double* relres, hipStream_t s);
+
+// ---- kcycle.hip: the Krylov-accelerated coarse visit of the K-cycle ---------
+// Vectors [R][n] (T = double or float), sums and coefficients in FP64;
+// coef holds 4 entries per right-hand side (a1, (rho1, 0), beta, a2);
+// partial holds kcycle_nblocks(n) * 2 * R complex.
+int kcycle_nblocks(size_t n);
+// partial sums of <A_r, X1_r> and <A_r, X2_r> (X2 may be NULL)
+template <typename T>
+void launch_kdots(const cx<T>* A, const cx<T>* X1, const cx<T>* X2, size_t n, int R, zd* partial, hipStream_t s);
+// W -= beta W', Z -= beta Z', then the partial sums of <W, W> and <W, X2>
+template <typename T>
+void launch_korth_dots(cx<T>* W, const cx<T>* Wp, cx<T>* Z, const cx<T>* Zp, const cx<T>* X2, const zd* coef,
+                       size_t n, int R, zd* partial, hipStream_t s);
+// mode 0: a1 = d2 / Re d1 (and rho1 = Re d1); 1: beta = d1 / rho1; 2: a2 = d2 / Re d1
+void launch_kcoef(const zd* partial, size_t n, int R, int mode, zd* coef, hipStream_t s);
+// x = a1 z1, r1 = r0 - a1 w1
+template <typename T>
+void launch_kstep1(const cx<T>* z1, const cx<T>* w1, const cx<T>* r0, const zd* coef, cx<T>* x, cx<T>* r1, size_t n,
+                   int R, hipStream_t s);
+// x += a2 z2
+template <typename T>
+void launch_kstep3(const cx<T>* z2, const zd* coef, cx<T>* x, size_t n, int R, hipStream_t s);
 
 // ---- boot.hip: bootstrap multigrid eigensolver (Sec. 3.4, Theorem 1) -------
 // lam[r] = <Gamma_5 A v_r, v_r> / <v_r, v_r> for k vectors V with AV = A V

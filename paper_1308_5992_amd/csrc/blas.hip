@@ -120,6 +120,15 @@ void launch_scale_copy(const zd* x, zd* y, size_t n, double alpha, hipStream_t s
   hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, alpha);
 }
 
+__global__ void k_sub(const zd* __restrict__ z, zd* __restrict__ x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = x[i] - z[i];
+}
+
+void launch_sub(const zd* z, zd* x, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, x, n);
+}
+
 __global__ void k_fill_zero(zd* __restrict__ x, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = zd{0, 0};

@@ -36,6 +36,7 @@ struct Slot {
   zd* X = nullptr;
   double tol = 0, bnorm = 0, beta = 0, relres = 1;
   int it = 0, cycles = 0, j = 0, status = BAMG_OK;
+  bool reconstructed = false;  // x written and its full-system residual queued
   std::chrono::steady_clock::time_point t0;
   std::vector<C> H, g, sn;
   std::vector<double> cs;
@@ -55,6 +56,8 @@ struct SlotEngine {
   zd *cur = nullptr, *zc = nullptr, *w = nullptr;
   zd *partial = nullptr, *hdev = nullptr, *hhost = nullptr;  // [4][S][64]
   int *flag_dev = nullptr, *flag_host = nullptr;              // [S][2]: non-finite input
+  // full-system residual of each finished slot: partial sums [S][2 RESNORM_MAX_BLOCKS], result [S]
+  double *rpart = nullptr, *rf_dev = nullptr, *rf_host = nullptr;
   // per phase: NI int arrays [S], one double array [S], y coefficients [S][64]
   int *ih = nullptr, *id = nullptr;
   double *ch = nullptr, *cd = nullptr;
@@ -79,6 +82,8 @@ struct SlotEngine {
   ~SlotEngine() {
     dfree(V); dfree(Z); dfree(bh); dfree(xe); dfree(rr); dfree(cur); dfree(zc); dfree(w);
     dfree(partial); dfree(hdev); dfree(flag_dev); dfree(id); dfree(cd); dfree(yd);
+    dfree(rpart); dfree(rf_dev);
+    if (rf_host) (void)hipHostFree(rf_host);
     if (hhost) (void)hipHostFree(hhost);
     if (flag_host) (void)hipHostFree(flag_host);
     if (ih) (void)hipHostFree(ih);
@@ -96,7 +101,7 @@ struct SlotEngine {
     d.info.iters = sl.it;
     d.info.restarts = sl.cycles > 0 ? sl.cycles - 1 : 0;
     d.info.relres_reduced = sl.relres;
-    d.info.relres_full = 0.0;
+    d.info.relres_full = sl.reconstructed ? rf_host[s] : 0.0;
     d.info.rho_est = sl.it > 0 ? std::pow(sl.relres, 1.0 / sl.it) : 0.0;
     d.info.t_solve_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - sl.t0).count();
@@ -109,7 +114,7 @@ struct SlotEngine {
 size_t engine_slot_bytes(size_t n0, int restart, int slots) {
   const size_t z = sizeof(zd);
   return (size_t)slots * n0 * z * (size_t)(2 * restart + 1 + 6) + (size_t)blas_nblocks(n0) * 64 * slots * z +
-         (size_t)4 * 64 * slots * z;
+         (size_t)4 * 64 * slots * z + (size_t)(2 * RESNORM_MAX_BLOCKS + 1) * slots * sizeof(double);
 }
 
 SlotEngine* engine_create(bamg_hierarchy* h, int S) {
@@ -131,6 +136,9 @@ SlotEngine* engine_create(bamg_hierarchy* h, int S) {
     e->partial = dalloc<zd>((size_t)blas_nblocks(n) * 64 * S);
     e->hdev = dalloc<zd>((size_t)4 * 64 * S);
     HIPCHK(hipHostMalloc((void**)&e->hhost, (size_t)4 * 64 * S * sizeof(zd)));
+    e->rpart = dalloc<double>((size_t)2 * RESNORM_MAX_BLOCKS * S);
+    e->rf_dev = dalloc<double>((size_t)S);
+    HIPCHK(hipHostMalloc((void**)&e->rf_host, (size_t)S * sizeof(double)));
     e->flag_dev = dalloc<int>((size_t)2 * S);
     HIPCHK(hipHostMalloc((void**)&e->flag_host, (size_t)2 * S * sizeof(int)));
     e->id = dalloc<int>((size_t)NPH * NI * S);
@@ -234,6 +242,11 @@ void engine_finish_pre(SlotEngine* e) {
     }
     if (sl.bnorm == 0.0 || !(sl.relres > sl.tol) || sl.it >= h->p.max_iter) {
       launch_eo_reconstruct(h->f, sl.B, e->xe + (size_t)q * n, sl.X, 1, s);
+      // ||b - D x|| / ||b|| of the unreduced system, read by finish_slot after the round's sync
+      launch_wilson_resnorm_packed(h->f, sl.B, sl.X, 1, e->rpart + (size_t)2 * RESNORM_MAX_BLOCKS * q,
+                                   e->rf_dev + q, s);
+      HIPCHK(hipMemcpyAsync(e->rf_host + q, e->rf_dev + q, sizeof(double), hipMemcpyDeviceToHost, s));
+      sl.reconstructed = true;
       sl.state = FINISHING;
       e->finishing.push_back(q);
       continue;

@@ -101,6 +101,12 @@ struct Level {
   zf* Ainv32 = nullptr;         // FP32 copy of the coarsest inverse
   zf* Ap32 = nullptr;           // FP32 copy of its packed blocks (single-RHS product)
   zf *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+  // K-cycle visits of this level (1 <= l <= L-2): z1, w1, r1, z2, w2 for cap
+  // right-hand sides each, in FP64 and (mixed modes) FP32; 4 coefficients per
+  // right-hand side
+  zd* kw = nullptr;
+  zf* kw32 = nullptr;
+  zd* kcoef = nullptr;
   Coarse coarse() const {
     Coarse c;
     c.ex = ex; c.ey = ey; c.D = D; c.Kinv = Kinv;
@@ -122,6 +128,7 @@ struct bamg_hierarchy {
   // side's arithmetic does not depend on how many others share the batch
   bool force_mr = false;
   zd* mmwork = nullptr;  // split-K partials of the coarsest product, cap right-hand sides
+  zd* kpart = nullptr;   // reduction partials of the K-cycle visits, cap right-hand sides
   // level-0 right-hand-side-interleaved x and b for the smoothing sweeps (cap >= IL_MIN)
   zd *xil = nullptr, *bil = nullptr;
   zf *xil32 = nullptr, *bil32 = nullptr;
@@ -240,8 +247,10 @@ struct bamg_hierarchy {
       dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.Ap); dfree(L.Ablk); dfree(L.Apart); dfree(L.P);
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
       dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.Ap32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
+      dfree(L.kw); dfree(L.kw32); dfree(L.kcoef);
     }
     dfree(mmwork);
+    dfree(kpart);
     dfree(xil); dfree(bil); dfree(xil32); dfree(bil32); dfree(xsw); dfree(xsw32);
     dfree(Ue); dfree(Uo); dfree(Ue32); dfree(Uo32); dfree(Bst); dfree(Bst32); dfree(Gst); dfree(Gst32); dfree(gjcol); dfree(gjperm); dfree(dflag);
     if (hflag) (void)hipHostFree(hflag);
@@ -259,6 +268,8 @@ struct bamg_hierarchy {
   bool coarsest(int l) const { return l == L() - 1; }
 
   bool mixed() const { return p.precision != BAMG_FP64; }
+  // level l takes Krylov-accelerated visits (K-cycle, l not the finest nor the coarsest)
+  bool kvisited(int l) const { return p.cycle == BAMG_CYCLE_K && l >= 1 && l + 1 < L(); }
   bool c32() const { return mixed() && p.coarsest_fp32; }
 
   void ensure_cap(int nrhs) {
@@ -280,10 +291,18 @@ struct bamg_hierarchy {
         bil32 = dalloc<zf>(lv[0].n * nrhs);
       }
     }
-    for (auto& Lv : lv) {
+    dfree(kpart);
+    kpart = nullptr;
+    size_t kpart_n = 0;
+    for (int l = 0; l < L(); ++l) {
+      Level& Lv = lv[l];
       dfree(Lv.x); dfree(Lv.b); dfree(Lv.r);
       dfree(Lv.x32); dfree(Lv.b32); dfree(Lv.r32);
+      dfree(Lv.kw); dfree(Lv.kw32); dfree(Lv.kcoef);
       Lv.x32 = Lv.b32 = Lv.r32 = nullptr;
+      Lv.kw = nullptr;
+      Lv.kw32 = nullptr;
+      Lv.kcoef = nullptr;
       Lv.x = dalloc<zd>(Lv.n * nrhs);
       Lv.b = dalloc<zd>(Lv.n * nrhs);
       Lv.r = dalloc<zd>(Lv.n * nrhs);
@@ -292,7 +311,14 @@ struct bamg_hierarchy {
         Lv.b32 = dalloc<zf>(Lv.n * nrhs);
         Lv.r32 = dalloc<zf>(Lv.n * nrhs);
       }
+      if (kvisited(l)) {
+        Lv.kw = dalloc<zd>(5 * Lv.n * nrhs);
+        if (mixed()) Lv.kw32 = dalloc<zf>(5 * Lv.n * nrhs);
+        Lv.kcoef = dalloc<zd>(4 * (size_t)nrhs);
+        kpart_n = std::max(kpart_n, (size_t)kcycle_nblocks(Lv.n) * 2 * nrhs);
+      }
     }
+    if (kpart_n) kpart = dalloc<zd>(kpart_n);
     cap = nrhs;
   }
 
@@ -378,13 +404,41 @@ struct bamg_hierarchy {
     smooth(l, x, b, nrhs, p.pre);
     apply(l, x, Lv.r, b, nrhs);  // r = b - A x
     restrict_(l, Lv.r, C.b, nrhs, coarsest(l + 1) ? nullptr : C.x);  // and the coarse initial guess x = 0
-    const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
-    for (int g = 0; g < gamma; ++g) {
-      cycle(l + 1, C.b, C.x, nrhs);
-      if (coarsest(l + 1)) break;
+    if (kvisited(l + 1)) {
+      kvisit(l + 1, C.b, C.x, nrhs);
+    } else {
+      const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
+      for (int g = 0; g < gamma; ++g) {
+        cycle(l + 1, C.b, C.x, nrhs);
+        if (coarsest(l + 1)) break;
+      }
     }
     prolong(l, C.x, x, nrhs);
     smooth(l, x, b, nrhs, p.post);
+  }
+
+  // K-cycle coarse visit of level c: two steps of flexible GCR on A_c x = r0
+  // from x = 0, each preconditioned by one cycle from level c (the sequence of
+  // kcycle.hip); x is written whole
+  void kvisit(int c, const zd* r0, zd* x, int nrhs) {
+    Level& Lv = lv[c];
+    const size_t n = Lv.n, nn = n * nrhs;
+    zd *z1 = Lv.kw, *w1 = z1 + nn, *r1 = w1 + nn, *z2 = r1 + nn, *w2 = z2 + nn;
+    launch_fill_zero(z1, nn, s);
+    cycle(c, r0, z1, nrhs);
+    apply(c, z1, w1, nullptr, nrhs);
+    launch_kdots(w1, w1, r0, n, nrhs, kpart, s);
+    launch_kcoef(kpart, n, nrhs, 0, Lv.kcoef, s);
+    launch_kstep1(z1, w1, r0, Lv.kcoef, x, r1, n, nrhs, s);
+    launch_fill_zero(z2, nn, s);
+    cycle(c, r1, z2, nrhs);
+    apply(c, z2, w2, nullptr, nrhs);
+    launch_kdots(w1, w2, (const zd*)nullptr, n, nrhs, kpart, s);
+    launch_kcoef(kpart, n, nrhs, 1, Lv.kcoef, s);
+    launch_korth_dots(w2, (const zd*)w1, z2, (const zd*)z1, (const zd*)r1, Lv.kcoef, n, nrhs, kpart, s);
+    launch_kcoef(kpart, n, nrhs, 2, Lv.kcoef, s);
+    launch_kstep3((const zd*)z2, Lv.kcoef, x, n, nrhs, s);
+    check_launch();
   }
 
   // ------------------------------------------------ mixed-precision cycle
@@ -457,14 +511,40 @@ struct bamg_hierarchy {
     zf* xz = coarsest(l + 1) ? nullptr : C.x32;
     if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
     else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
-    const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
-    for (int g = 0; g < gamma; ++g) {
-      cycle32<S>(l + 1, C.b32, C.x32, nrhs);
-      if (coarsest(l + 1)) break;
+    if (kvisited(l + 1)) {
+      kvisit32<S>(l + 1, C.b32, C.x32, nrhs);
+    } else {
+      const int gamma = (p.cycle == BAMG_CYCLE_W) ? 2 : 1;
+      for (int g = 0; g < gamma; ++g) {
+        cycle32<S>(l + 1, C.b32, C.x32, nrhs);
+        if (coarsest(l + 1)) break;
+      }
     }
     if (l == 0) launch_prolong_fine(f32, Lv.P32, C.x32, x, nrhs, s);
     else launch_prolong_coarse(Lv.ex, Lv.ey, Lv.P32, C.x32, x, nrhs, s);
     smooth32<S>(l, x, b, nrhs, p.post);
+    check_launch();
+  }
+  // the K-cycle visit of kvisit with FP32 vectors (FP64 sums and coefficients)
+  template <typename S>
+  void kvisit32(int c, const zf* r0, zf* x, int nrhs) {
+    Level& Lv = lv[c];
+    const size_t n = Lv.n, nn = n * nrhs;
+    zf *z1 = Lv.kw32, *w1 = z1 + nn, *r1 = w1 + nn, *z2 = r1 + nn, *w2 = z2 + nn;
+    launch_zero(z1, nn * sizeof(zf), s);
+    cycle32<S>(c, r0, z1, nrhs);
+    apply32<S>(c, z1, w1, nullptr, nrhs);
+    launch_kdots(w1, w1, r0, n, nrhs, kpart, s);
+    launch_kcoef(kpart, n, nrhs, 0, Lv.kcoef, s);
+    launch_kstep1(z1, w1, r0, Lv.kcoef, x, r1, n, nrhs, s);
+    launch_zero(z2, nn * sizeof(zf), s);
+    cycle32<S>(c, r1, z2, nrhs);
+    apply32<S>(c, z2, w2, nullptr, nrhs);
+    launch_kdots(w1, w2, (const zf*)nullptr, n, nrhs, kpart, s);
+    launch_kcoef(kpart, n, nrhs, 1, Lv.kcoef, s);
+    launch_korth_dots(w2, (const zf*)w1, z2, (const zf*)z1, (const zf*)r1, Lv.kcoef, n, nrhs, kpart, s);
+    launch_kcoef(kpart, n, nrhs, 2, Lv.kcoef, s);
+    launch_kstep3((const zf*)z2, Lv.kcoef, x, n, nrhs, s);
     check_launch();
   }
   // z = M v for nrhs FP64 level-0 vectors through the FP32 cycle

@@ -377,7 +377,7 @@ def test_setup_matches_oracle(bamg, c1):
     _, D, _ = bamg.bamg_export_level(h, 1)
     d_d = rel(blocks_to_csr(D, inf["ex"], inf["ey"]).toarray(), o.operator(1).toarray())
     log(f"setup: tv {d_tv:.2e} projector {d_p:.2e} coarse op {d_d:.2e}")
-    assert d_tv < 1e-11 and d_p < 1e-9 and d_d < 1e-9
+    assert d_tv < 1e-11 and d_p < 1e-11 and d_d < 1e-11
 
 
 def _check_solution(w, U, b, x, tol):
@@ -410,8 +410,9 @@ def test_full_solve(bamg, name):
         f"full relres {full:.2e} |x_gpu - x_oracle|/|x| {dx:.2e}")
     assert st == 0 and sto == 0
     assert rr <= 1.05e-10
-    assert abs(info["iters"] - io["iters"]) <= 1
-    assert dx < 1e-7
+    assert info["iters"] == io["iters"]
+    assert dx < 1e-10
+    assert abs(info["relres_full"] - full) <= 1e-6 * full + 1e-15
 
 
 def test_failure_handling(bamg, c1):
@@ -604,7 +605,9 @@ def test_mixed_solve_reaches_fp64_accuracy(bamg, prec, c32):
         f"full relres {full:.2e}, "
         f"|x - x_fp64|/|x| {dx:.2e}")
     assert st == 0 and info["relres_reduced"] <= 1e-10
-    assert full < 2e-10 and dx < 1e-7
+    # both solutions have reduced residuals <= 1e-10; their difference is bounded
+    # by about tol * cond(Dhat) (~1e-7 here) and measured near 1e-12
+    assert full < 2e-10 and dx < 1e-9
 
 
 @pytest.mark.parametrize("prec,c32", [("fp16", 0), ("bf16", 0), ("fp16", 1)])
