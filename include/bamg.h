@@ -261,6 +261,18 @@ int bamg_stationary(bamg_hierarchy *h, void *x, int32_t iters, double *norms_hos
 int bamg_full_residual(int32_t N, const void *gauge, double m, const void *B, const void *X, int32_t nrhs,
                        double *relres, void *stream);
 
+/* bamg_full_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, with the partial sums in a static device array
+ * of 1 MiB per GPU (131072 doubles) that the library holds until the process
+ * ends; the call allocates nothing.  It needs 2 * min(256, ceil(N^2 / 1024))
+ * doubles per right-hand side (at most 256 right-hand sides for N >= 512) and
+ * returns BAMG_EINVAL beyond that.  The array belongs to the current device,
+ * which `stream` must be on.  Calls that overlap on one GPU share the array
+ * and race: order them (one stream, or synchronise between them). */
+int bamg_full_residual_noalloc(int32_t N, const void *gauge, double m, const void *B, const void *X,
+                               int32_t nrhs, double *relres, void *stream);
+
 /* Device bytes a hierarchy with parameters p holds after bamg_setup and a first
  * single-RHS solve: every level's data and work vectors (sized for the setup's
  * n_tv + n_ev test vectors), the FP32 copies of the mixed modes, the coarsest

@@ -32,7 +32,7 @@ EXPORTED = [
     "bamg_free", "bamg_last_error", "bamg_boot_op", "bamg_export_boot",
     "bamg_server_default_params", "bamg_server_create", "bamg_server_add_field", "bamg_server_field_bytes",
     "bamg_server_submit", "bamg_server_progress", "bamg_server_wait", "bamg_server_get_stats", "bamg_server_reset_stats",
-    "bamg_server_free", "bamg_stationary", "bamg_full_residual",
+    "bamg_server_free", "bamg_stationary", "bamg_full_residual", "bamg_full_residual_noalloc",
 ]
 
 
@@ -120,6 +120,7 @@ def _load():
         "bamg_server_free": (None, [P]),
         "bamg_stationary": (I32, [P, P, I32, P]),
         "bamg_full_residual": (I32, [I32, P, D, P, P, I32, P, P]),
+        "bamg_full_residual_noalloc": (I32, [I32, P, D, P, P, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -296,14 +297,24 @@ def bamg_stationary(h, x, iters: int):
     return norms
 
 
-def bamg_full_residual(N: int, gauge, m: float, B, X, nrhs: int, relres):
-    """relres (float64 GPU tensor of nrhs) = ||b - D x|| / ||b|| per right-hand side."""
+def _relres_ptr(relres, nrhs):
     import torch
     if not (isinstance(relres, torch.Tensor) and relres.is_cuda and relres.dtype == torch.float64
             and relres.is_contiguous() and relres.numel() >= nrhs):
         raise TypeError("relres must be a contiguous float64 GPU tensor of nrhs entries")
+    return ctypes.c_void_p(relres.data_ptr())
+
+
+def bamg_full_residual(N: int, gauge, m: float, B, X, nrhs: int, relres):
+    """relres (float64 GPU tensor of nrhs) = ||b - D x|| / ||b|| per right-hand side."""
     _check(lib.bamg_full_residual(int(N), _ptr(gauge), float(m), _ptr(B), _ptr(X), int(nrhs),
-                                  ctypes.c_void_p(relres.data_ptr()), _stream()), "bamg_full_residual")
+                                  _relres_ptr(relres, nrhs), _stream()), "bamg_full_residual")
+
+
+def bamg_full_residual_noalloc(N: int, gauge, m: float, B, X, nrhs: int, relres):
+    """bamg_full_residual with the library's static scratch (allocates nothing)."""
+    _check(lib.bamg_full_residual_noalloc(int(N), _ptr(gauge), float(m), _ptr(B), _ptr(X), int(nrhs),
+                                          _relres_ptr(relres, nrhs), _stream()), "bamg_full_residual_noalloc")
 
 
 def bamg_fine_sweep_plan(N: int, nrhs: int = 1, fp32: bool = False, form: int = 0):

@@ -7,9 +7,14 @@
 // work-groups' sums in a fixed order by one more launch, so the result is
 // deterministic.  Links are read from the caller's U[mu][y][x] array or from
 // the hierarchy's even/odd packed copy.
+#include <mutex>
+#include <string>
+
+#include "../../include/bamg.h"
 #include "bamg_internal.h"
 
 namespace bamg {
+int api_fail(int code, const std::string& msg);
 
 namespace {
 
@@ -148,4 +153,60 @@ void launch_wilson_resnorm_packed(const Fine& f, const zd* B, const zd* X, int n
   hipLaunchKernelGGL(k_resnorm_final, dim3(nrhs), dim3(RT), 0, s, (const double*)partial, nb, relres);
 }
 
+// ---------------------------------------------------------------------------
+// The same residual norms with no allocation: the partial sums live in a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): the first call on a device looks up that
+// device's copy with hipGetSymbolAddress and keeps the pointer.  Every
+// partial sum is written before it is read, so nothing needs clearing; calls
+// that overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t RESNORM_SCRATCH_DOUBLES = (size_t)1 << 17;  // 1 MiB
+static __device__ __align__(256) double scratch[RESNORM_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int MAX_DEVICES = 64;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// this device's copy of `scratch`, looked up once per device (NULL on failure)
+double* scratch_of_current_device(std::string& why) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    why = "no current HIP device";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      why = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 }  // namespace bamg
+
+extern "C" int bamg_full_residual_noalloc(int32_t N, const void* gauge, double m, const void* B, const void* X,
+                                          int32_t nrhs, double* relres, void* stream) {
+  using namespace bamg;
+  if (N < 2 || !gauge || !B || !X || !relres || nrhs < 1) return api_fail(BAMG_EINVAL, "bad arguments");
+  const size_t need = (size_t)2 * resnorm_nblocks(N) * nrhs;
+  if (need > RESNORM_SCRATCH_DOUBLES)
+    return api_fail(BAMG_EINVAL, "partial sums of " + std::to_string(need) + " doubles exceed the " +
+                                     std::to_string(RESNORM_SCRATCH_DOUBLES) + " of the static scratch");
+  std::string why;
+  double* part = scratch_of_current_device(why);
+  if (!part) return api_fail(BAMG_EDEVICE, why);
+  launch_wilson_resnorm(N, (const zd*)gauge, m + 2.0, (const zd*)B, (const zd*)X, nrhs, part, relres,
+                        (hipStream_t)stream);
+  const hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return api_fail(BAMG_EDEVICE, std::string("launch: ") + hipGetErrorString(le));
+  return BAMG_OK;
+}
