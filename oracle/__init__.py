@@ -219,6 +219,30 @@ class Hierarchy:
         self.h = h
         self.n_tv = n_tv
 
+    @classmethod
+    def from_interpolation(cls, U, m, Ps, *, pre=4, post=4, cycle=0, lapack_lu=True):
+        """The oracle's hierarchy on len(Ps) + 1 levels from given interpolation
+        operators P_0 .. P_{L-2} (aggregate blocks [agg][s][row][8]): every
+        coarse operator is the oracle's Galerkin product, the smoothers its
+        colour orders.  The coarsest operator is factored by LAPACK's LU with
+        partial pivoting (scipy) when lapack_lu, else by the oracle's own LU;
+        its 1-norm condition number (LAPACK's estimate from the factors) is
+        kept as .kappa1."""
+        h = cls(U, m, n_levels=len(Ps) + 1, setup_adapt=-1, pre=pre, post=post, cycle=cycle)
+        if h.n_levels != len(Ps) + 1:
+            raise ValueError("lattice does not give len(Ps) + 1 levels")
+        for l, P in enumerate(Ps):
+            h.import_P(l, P, factor=not (lapack_lu and l == len(Ps) - 1))
+        A = h.operator(h.n_levels - 1).toarray()
+        import scipy.linalg as sl
+        lu, piv = sl.lu_factor(A, check_finite=False)
+        if lapack_lu:
+            h.set_coarsest_lu(lu, piv.astype(np.int32))
+        anorm = np.abs(A).sum(axis=0).max()
+        rcond, _ = sl.lapack.zgecon(lu, anorm, norm="1")
+        h.kappa1 = 1.0 / rcond if rcond > 0 else np.inf
+        return h
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
