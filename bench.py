@@ -56,14 +56,19 @@ def parse():
                     default="mixed_fp16+graphs+v22+bootV,mixed_fp16+graphs+v22+bootV+c32,fp64+graphs+v22+bootV,"
                             "mixed_fp16+graphs+v22,"
                             "fp64+graphs+v22,mixed_fp16+graphs+v22+bootW,mixed_fp16+graphs,fp64+graphs,mixed_fp16,"
-                            "mixed_bf16+graphs+v22,mixed_fp32+graphs+v22",
-                    help="single-RHS variants to time, <precision>[+graphs][+v22][+bootW|+bootV][+c32] (graphs: "
-                         "iterations replayed as hipGraphs; v22: V(2,2) cycle instead of V(4,4); bootW / bootV: "
-                         "bootstrap setup with the multigrid eigensolver, W or super-V cycles; c32: the mixed cycle's "
-                         "coarsest solve reads an FP32 copy of the FP64 inverse); the first one is the headline value; "
-                         "the batched solves also run on the first +c32 variant")
-    ap.add_argument("--serve", type=int, default=48, help="requests of the serving run (0: skip it)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
+                            "mixed_bf16+graphs+v22,mixed_fp32+graphs+v22,mixed_fp16+graphs+v22+bootV+W,"
+                            "mixed_fp16+graphs+v22+bootV+K,fp64+graphs+v22+bootV+K",
+                    help="single-RHS variants to time, <precision>[+graphs][+v22][+bootW|+bootV][+c32][+W|+K] "
+                         "(graphs: iterations replayed as hipGraphs; v22: V(2,2) cycle instead of V(4,4) (W(2,2), "
+                         "K(2,2) with +W, +K); bootW / bootV: bootstrap setup with the multigrid eigensolver, W or "
+                         "super-V cycles; c32: the mixed cycle's coarsest solve reads an FP32 copy of the FP64 "
+                         "inverse; W / K: W-cycle or K-cycle); the first one is the headline value; the batched "
+                         "solves also run on the first +c32 variant")
+    ap.add_argument("--serve", type=int, default=1000, help="requests per load point of the serving run (0: skip it)")
+    ap.add_argument("--serve-loads", default="0.5,0.8,1.0",
+                    help="offered loads of the serving run, as fractions of the measured capacity")
+    ap.add_argument("--serve256", type=int, default=200,
+                    help="requests of the 256^2-only served run at saturation (0: skip it)")
     ap.add_argument("--c4", type=int, default=1, help="time the 512^2 x 64 RHS batched solve (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up the headline hierarchy, time only the roofline kernel and a plain copy of "
@@ -75,9 +80,10 @@ COPY_MIB = 256
 
 
 def variant(spec):
-    """Solver parameters of a bench variant '<precision>[+graphs][+v22][+bootW|+bootV][+c32]'
+    """Solver parameters of a bench variant '<precision>[+graphs][+v22][+bootW|+bootV][+c32][+W|+K]'
     (bootW / bootV: bootstrap setup with the multigrid eigensolver, W or super-V
-    setup cycles; c32: FP32 copy of the coarsest inverse in the mixed cycle)."""
+    setup cycles; c32: FP32 copy of the coarsest inverse in the mixed cycle;
+    W / K: W-cycle or K-cycle instead of V)."""
     base, *opts = spec.split("+")
     kw = {"precision": PRECISIONS[base], "graphs": 1 if "graphs" in opts else 0}
     if "v22" in opts:
@@ -88,7 +94,11 @@ def variant(spec):
         kw.update(setup_mode=2)
     if "c32" in opts:
         kw.update(coarsest_fp32=1)
-    unknown = set(opts) - {"graphs", "v22", "bootW", "bootV", "c32"}
+    if "W" in opts:
+        kw.update(cycle=1)
+    if "K" in opts:
+        kw.update(cycle=2)
+    unknown = set(opts) - {"graphs", "v22", "bootW", "bootV", "c32", "W", "K"}
     if unknown:
         raise SystemExit(f"bench.py: unknown variant option(s) {sorted(unknown)} in {spec!r}")
     return base, kw
@@ -138,80 +148,118 @@ def time_launches(fn, reps, launches_per_call, torch):
 SERVE_FIELDS = ["s1_64_b3", "c2_128_b6", "c3_256_b10", "c4_512_b10"]
 
 
-def serving(bamg, inputs, torch, np, n_req, rate, tol, kw):
-    """Poisson arrivals of solve requests over four gauge fields (64^2 beta=3,
-    128^2 beta=6, 256^2 beta=10, 512^2 beta=10), 1-32 right-hand sides each,
-    on a threaded server with memory admission and continuous batching (the
-    headline solver parameters, 32 slots per field).  The hierarchies are made resident
-    by one warm-up request per field; then every request's right-hand sides
-    are placed in HBM and the requests are submitted at their arrival times.
-    Latency is submit -> completion as the server measures it."""
-    rng = np.random.default_rng(4242)
-    sp = bamg.bamg_server_default_params(threaded=1, slots_per_field=32)
+def _server_with_fields(bamg, inputs, torch, names, tol, kw, slots=32):
+    """A threaded server with the given fields registered and made resident by
+    one warm-up request each (setup + one solve)."""
+    sp = bamg.bamg_server_default_params(threaded=1, slots_per_field=slots)
     srv = bamg.bamg_server_create(sp)
     fids, Ns = [], []
-    t0 = time.time()
-    for name in SERVE_FIELDS:
+    for name in names:
         w = inputs.workload(name)
         U = torch.from_numpy(inputs.load_gauge(w)).to("cuda:0")
         p = bamg.bamg_default_params(N=w["N"], n_levels=w["n_levels"], seed=w["tv_seed"], **kw)
         fids.append(bamg.bamg_server_add_field(srv, U, w["m"], p))
         Ns.append(w["N"])
         del U
-    t_gauge = time.time() - t0
     t0 = time.time()
     keep = []
-    for f, N in zip(fids, Ns):  # warm-up: setup + one solve per field
+    for f, N in zip(fids, Ns):
         B = torch.from_numpy(inputs.gaussian((1, 2 * N * N), 7000 + N)).to("cuda:0")
         X = torch.zeros_like(B)
-        rid = bamg.bamg_server_submit(srv, f, B, X, 1, tol)
-        keep.append((rid, B, X))
+        keep.append((bamg.bamg_server_submit(srv, f, B, X, 1, tol), B, X))
     for rid, B, X in keep:
         bamg.bamg_server_wait(srv, rid, 1)
-    t_warm = time.time() - t0
-    warm = bamg.bamg_server_get_stats(srv)
-    bamg.bamg_server_reset_stats(srv)
-    # the request stream
-    which = rng.integers(0, len(fids), n_req)
-    nrhs = rng.integers(1, 33, n_req)
-    gaps = rng.exponential(1.0 / rate, n_req)
-    reqs = []
-    for i in range(n_req):
-        N = Ns[which[i]]
-        B = torch.from_numpy(inputs.gaussian((int(nrhs[i]), 2 * N * N), 8000 + i)).to("cuda:0")
-        reqs.append((fids[which[i]], int(nrhs[i]), B, torch.zeros_like(B)))
+    return srv, fids, Ns, time.time() - t0
+
+
+def _request_stream(bamg, torch, np, srv, fids, Ns, which, nrhs, gaps, tol, pools):
+    """Submit requests at their arrival times (gaps in s; 0: all at once), wait
+    for all; the right-hand sides come from a per-field pool of 32 Gaussian
+    vectors (request i takes the first nrhs of its field's pool), the outputs
+    are allocated before the stream starts.  Returns the server's statistics
+    with the wall time, convergence and the largest full-system residual."""
+    outs = [torch.zeros(int(k), 2 * Ns[f] ** 2, dtype=torch.complex128, device="cuda:0")
+            for f, k in zip(which, nrhs)]
     torch.cuda.synchronize()
+    bamg.bamg_server_reset_stats(srv)
     ids = []
     t_start = time.perf_counter()
     t_next = t_start
-    for i, (f, k, B, X) in enumerate(reqs):
+    for i in range(len(which)):
         t_next += gaps[i]
         dt = t_next - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        ids.append(bamg.bamg_server_submit(srv, f, B, X, k, tol))
-    iters, conv = [], True
-    per_field = {name: 0 for name in SERVE_FIELDS}
-    for (f, k, B, X), rid in zip(reqs, ids):
-        st, infos = bamg.bamg_server_wait(srv, rid, k)
+        ids.append(bamg.bamg_server_submit(srv, fids[which[i]], pools[which[i]], outs[i], int(nrhs[i]), tol))
+    conv, worst_full, iters = True, 0.0, []
+    for i, rid in enumerate(ids):
+        st, infos = bamg.bamg_server_wait(srv, rid, int(nrhs[i]))
         conv = conv and st == 0 and all(v["relres_reduced"] <= tol for v in infos)
+        worst_full = max([worst_full] + [v["relres_full"] for v in infos])
         iters.append(max(v["iters"] for v in infos))
-        per_field[SERVE_FIELDS[fids.index(f)]] += k
-    t_end = time.perf_counter()
-    st = bamg.bamg_server_get_stats(srv)
+    wall = time.perf_counter() - t_start
+    stt = bamg.bamg_server_get_stats(srv)
+    del outs
+    return {"requests": stt["completed"], "rhs": stt["rhs_completed"], "wall_s": wall,
+            "solves_per_s": stt["rhs_completed"] / wall, "requests_per_s": stt["completed"] / wall,
+            "p50_ms": stt["p50_ms"], "p99_ms": stt["p99_ms"], "mean_ms": stt["mean_ms"], "max_ms": stt["max_ms"],
+            "converged": conv, "max_relres_full": worst_full, "max_iters": int(max(iters)),
+            "evictions": stt["evictions"], "setups": stt["setups"], "rounds": stt["rounds"]}
+
+
+def serving(bamg, inputs, torch, np, n_req, loads, tol, kw, n_cal=200):
+    """Solve requests over four gauge fields (64^2 beta=3, 128^2 beta=6, 256^2
+    beta=10, 512^2 beta=10), each for one field chosen uniformly with 1-32
+    right-hand sides (uniform), on a threaded server with memory admission and
+    continuous batching (the headline solver parameters, 32 slots per field).
+    Capacity is measured first: n_cal requests submitted at once, completed
+    requests per second of the burst.  Then for each load factor f a Poisson
+    stream of n_req requests arrives at f x capacity.  Latency is submit to
+    completion per request, as the server measures it (nearest-rank
+    percentiles)."""
+    rng = np.random.default_rng(4242)
+    t0 = time.time()
+    srv, fids, Ns, t_warm = _server_with_fields(bamg, inputs, torch, SERVE_FIELDS, tol, kw)
+    pools = [torch.from_numpy(inputs.gaussian((32, 2 * N * N), 9000 + N)).to("cuda:0") for N in Ns]
+    which = rng.integers(0, len(fids), n_cal)
+    nrhs = rng.integers(1, 33, n_cal)
+    cal = _request_stream(bamg, torch, np, srv, fids, Ns, which, nrhs, np.zeros(n_cal), tol, pools)
+    cap = cal["requests_per_s"]
+    progress(f"serving capacity {cap:.1f} requests/s ({cal['solves_per_s']:.0f} solves/s)")
+    points = []
+    for f in loads:
+        which = rng.integers(0, len(fids), n_req)
+        nrhs = rng.integers(1, 33, n_req)
+        gaps = rng.exponential(1.0 / (f * cap), n_req)
+        r = _request_stream(bamg, torch, np, srv, fids, Ns, which, nrhs, gaps, tol, pools)
+        r.update({"load": f, "offered_requests_per_s": f * cap, "offered_s": float(np.sum(gaps))})
+        points.append(r)
+        progress(f"serving load {f}: p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms, {r['solves_per_s']:.0f} solves/s")
     bamg.bamg_server_free(srv)
-    n_timed, rhs_timed = st["completed"], st["rhs_completed"]
-    return {
-        "fields": {n: {"N": N_} for n, N_ in zip(SERVE_FIELDS, Ns)}, "solver": kw,
-        "slots_per_field": sp.slots_per_field, "requests": n_timed, "rhs": rhs_timed, "rhs_per_field": per_field,
-        "arrival_rate_per_s": rate, "offered_s": float(np.sum(gaps)),
-        "solves_per_s": rhs_timed / (t_end - t_start), "wall_s": t_end - t_start,
-        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
-        "latency": "submit to completion per request (server clock), nearest-rank percentiles",
-        "max_iters": int(max(iters)), "converged": conv, "setups": st["setups"], "evictions": st["evictions"],
-        "bytes_in_use": st["bytes_in_use"], "budget_bytes": st["budget_bytes"], "rounds": st["rounds"],
-        "setup_warmup_s": t_warm, "warmup_setups": warm["setups"], "gauge_gen_s": t_gauge,
-    }
+    del pools
+    torch.cuda.empty_cache()
+    return {"fields": {n: {"N": N_} for n, N_ in zip(SERVE_FIELDS, Ns)}, "solver": kw, "slots_per_field": 32,
+            "requests_per_load": n_req, "capacity": cal, "loads": points, "setup_warmup_s": t_warm,
+            "wall_s": time.time() - t0,
+            "latency": "submit to completion per request (server clock), nearest-rank percentiles"}
+
+
+def serving_256(bamg, inputs, torch, np, n_req, tol, kw):
+    """The 256^2 field alone (beta = 10, min |eig D| ~ 1e-4), mixed FP16 with
+    continuous batching: n_req requests of 1-32 right-hand sides submitted at
+    once (the served throughput at saturation), every right-hand side to the
+    same reduced residual 1e-10 as the single-RHS lines."""
+    rng = np.random.default_rng(4343)
+    srv, fids, Ns, t_warm = _server_with_fields(bamg, inputs, torch, ["c3_256_b10"], tol, kw)
+    pools = [torch.from_numpy(inputs.gaussian((32, 2 * Ns[0] ** 2), 9500)).to("cuda:0")]
+    which = np.zeros(n_req, dtype=int)
+    nrhs = rng.integers(1, 33, n_req)
+    r = _request_stream(bamg, torch, np, srv, fids, Ns, which, nrhs, np.zeros(n_req), tol, pools)
+    bamg.bamg_server_free(srv)
+    del pools
+    torch.cuda.empty_cache()
+    r.update({"field": "c3_256_b10", "solver": kw, "slots_per_field": 32, "setup_warmup_s": t_warm})
+    return r
 
 
 def c4_batched(bamg, inputs, torch, tol, kw, reps=2):
@@ -266,22 +314,26 @@ def dhat_bandwidth(bamg, inputs, torch, N, nrhs, reps):
 
 
 def sweep_bandwidth(bamg, inputs, torch, N, nrhs, reps):
-    """GB/s of one FP64 fine multicolour Kaczmarz sweep (16 colour passes, b = 0)
-    from this design's compulsory bytes per sweep: the stored slot blocks once
-    (36 complex per even site, 288 N^2) and, per right-hand side, x read and
-    written (32 N^2), (288 + 32 R) N^2 in all; b = 0 is not read.
-    Operator-only handle."""
+    """GB/s of one FP64 fine multicolour Kaczmarz sweep in the library's form for
+    the size, from the method's algorithmic bytes per sweep: the links (32 N^2)
+    and squared row norms (8 N^2) once and, per right-hand side, x read and
+    written and b read (48 N^2): (40 + 48 R) N^2, 88 N^2 for one right-hand
+    side.  design_GB/s counts this design's bytes instead: the stored slot
+    blocks (36 complex per even site, 288 N^2) and x read and written per
+    right-hand side, (288 + 32 R) N^2.  Operator-only handle."""
     U = torch.from_numpy(inputs.gauge_random(N, 77)).to("cuda:0")
     p = bamg.bamg_default_params(N=N, n_levels=1)
     h = bamg.bamg_setup(U, -0.05, p)
     x = torch.from_numpy(inputs.gaussian((nrhs, N * N), 79)).to("cuda:0")
     b = torch.zeros_like(x)
     t = time_launches(lambda: bamg.bamg_level_op(h, 0, bamg.OP_SWEEP, b, x, nrhs), reps, 1, torch)
-    bytes_ = (288.0 + 32.0 * nrhs) * N * N
+    alg = (40.0 + 48.0 * nrhs) * N * N
+    design = (288.0 + 32.0 * nrhs) * N * N
     bamg.bamg_free(h)
     del x, b, U
     torch.cuda.empty_cache()
-    return {"N": N, "nrhs": nrhs, "us_per_sweep": t * 1e6, "GB/s": bytes_ / t / 1e9, "frac": bytes_ / t / 1e9 / HBM_PEAK_GBS}
+    return {"N": N, "nrhs": nrhs, "us_per_sweep": t * 1e6, "GB/s": alg / t / 1e9, "frac": alg / t / 1e9 / HBM_PEAK_GBS,
+            "design_GB/s": design / t / 1e9, "design_frac": design / t / 1e9 / HBM_PEAK_GBS}
 
 
 BANDWIDTH_POINTS = ((256, 1, 200), (512, 64, 20), (4096, 1, 20))
@@ -354,13 +406,15 @@ def main():
         torch.cuda.synchronize()
         t_all = time.perf_counter() - t_all0
         ms = [1e3 * t for t in times]
+        cyc = "VWK"[p.cycle]
         results[prec] = {
             "solves_per_s": args.steps / t_all, "ms_per_solve": 1e3 * t_all / args.steps,
             "p10_ms": float(np.percentile(ms, 10)), "p50_ms": statistics.median(ms),
             "p90_ms": float(np.percentile(ms, 90)), "p99_ms": float(np.percentile(ms, 99)),
             "iters": infos[-1]["iters"], "relres_reduced": infos[-1]["relres_reduced"],
             "converged": all(i["relres_reduced"] <= args.tol for i in infos), "setup_s": t_setup,
-            "levels": bamg.bamg_n_levels(h), "cycle": f"V({p.pre},{p.post})", "graphs": bool(p.graphs),
+            "relres_full": infos[-1]["relres_full"],
+            "levels": bamg.bamg_n_levels(h), "cycle": f"{cyc}({p.pre},{p.post})", "graphs": bool(p.graphs),
             "setup": {0: "relax-fit passes", 1: "bootstrap W cycles", 2: "bootstrap super-V"}[p.setup_mode],
         }
         hier[prec] = h
@@ -369,7 +423,7 @@ def main():
     # error of every variant against the FP64 solve with the same cycle
     for prec in precs:
         base, kw = variant(prec)
-        key = lambda kw_: (kw_.get("pre"), kw_.get("post"), kw_.get("setup_mode"))
+        key = lambda kw_: (kw_.get("pre"), kw_.get("post"), kw_.get("setup_mode"), kw_.get("cycle", 0))
         refs = [q for q in precs if variant(q)[0] == "fp64" and key(variant(q)[1]) == key(kw)]
         if base != "fp64" and refs:
             results[prec]["rel_err_vs_fp64"] = float(np.linalg.norm(xs[prec] - xs[refs[0]]) /
@@ -439,12 +493,23 @@ def main():
         out["c4_512x64"] = c4_batched(bamg, inputs, torch, args.tol, multi_kw)
         progress(f"512^2 x 64: {out['c4_512x64']['solves_per_s']:.1f} solves/s")
 
-    # ---- serving: Poisson arrivals over four fields, continuous batching
+    # ---- serving: Poisson arrivals over four fields at 0.5 / 0.8 / 1.0 x capacity
+    multi_kw = {k: v for k, v in head_kw.items() if k != "setup_mode"}
     if args.serve > 0:
-        multi_kw = {k: v for k, v in head_kw.items() if k != "setup_mode"}
-        out["serving"] = serving(bamg, inputs, torch, np, args.serve, args.serve_rate, args.tol, multi_kw)
-        out["serving_p99_ms"] = out["serving"]["p99_ms"]
-        progress(f"serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms")
+        loads = [float(v) for v in args.serve_loads.split(",") if v.strip()]
+        out["serving"] = serving(bamg, inputs, torch, np, args.serve, loads, args.tol, multi_kw)
+        out["serving_p99_ms"] = {str(pt["load"]): pt["p99_ms"] for pt in out["serving"]["loads"]}
+    # ---- the served form at 256^2 against the FP64 single-RHS solve at the same tolerance
+    if args.serve256 > 0:
+        s256 = serving_256(bamg, inputs, torch, np, args.serve256, args.tol, multi_kw)
+        ref = next((q for q in precs if q.split("+")[0] == "fp64" and "v22" in q.split("+")
+                    and not any(o_ in q.split("+") for o_ in ("bootV", "bootW", "W", "K"))), None)
+        if ref is not None:
+            s256["fp64_single_rhs_line"] = ref
+            s256["fp64_single_rhs_solves_per_s"] = results[ref]["solves_per_s"]
+            s256["served_over_fp64_single"] = s256["solves_per_s"] / results[ref]["solves_per_s"]
+        out["serving_256"] = s256
+        progress(f"serving 256^2: {s256['solves_per_s']:.0f} solves/s")
 
     # ---- Dhat ("D_oe") bandwidth: cache-resident, batched, cache-busting
     if not args.no_dhat:
@@ -461,9 +526,16 @@ def main():
             out["mfma"] = mfma_utilisation(bamg, torch, hm)
         progress("roofline")
 
+    # ---- the stand-alone convergence rate of Sec. 4 of the timed hierarchies
+    out["rho_standalone"] = {q: convergence_rate(bamg, inputs, torch, hier[q], N) for q in precs
+                             if q == head or variant(q)[1].get("cycle")}
+    progress("stand-alone rates")
+
     # ---- CPU oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, U_np, args.tol)
+        ph = bamg.bamg_default_params(**head_kw)
+        Ps = [bamg.bamg_export_level(h, l, P=True, D=False)[0] for l in range(n_levels - 1)]
+        out["cpu_baseline"] = cpu_baseline(w, U_np, args.tol, Ps, ph.pre, ph.post)
         progress("cpu baseline")
 
     for hh in hier.values():
@@ -471,20 +543,31 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-# Algorithmic bytes of the three kernels that take the solve's time (see the
-# kernel trace), per launch:
-#  - fine colour pass: per even site of the colour, its 9 x 4 stored couplings
-#    Bst (storage = cycle type), its 2 right-hand-side entries and the 9 x 2
-#    unknowns of its row support read and written (the supports of one colour
-#    are disjoint, so nothing is counted twice within a launch);
-#  - fine sweep blocked in LDS (one launch per 16-colour sweep): per even site
-#    its 36 stored couplings, its 2 right-hand-side entries and its 2 unknowns
-#    read and written once (the compulsory bytes of a sweep);
-#  - coarse colour pass: per site of the colour, the 7 blocks of 16 x 16 of its
-#    rows (operator storage type), the 16 x 16 smoother matrix Kinv (cycle type),
-#    its 16 right-hand-side entries and the 7 x 16 unknowns of its support read
-#    and written;
-#  - coarsest product: the n x n FP64 inverse and the two vectors.
+# Bytes of the three kernels that take the solve's time, per launch.  The
+# roofline fraction uses the algorithmic (compulsory) bytes of the method:
+#  - fine sweep: 88 N^2 B per 16-colour sweep in FP64 (x read and written,
+#    b, the links, the squared row norms), 44 N^2 B in FP32; a colour pass is
+#    1/16 of it;
+#  - coarse colour pass: the operator rows of the colour's sites, 7 blocks of
+#    16 x 16 entries per site in the operator's storage type (28 KiB FP64,
+#    7 KiB FP16);
+#  - coarsest product: the entries of the inverse the product must read (its
+#    64 x 64 blocks on and above the diagonal: the inverse is gamma5-Hermitian,
+#    so they fix the rest) and the two vectors.
+# This design's own bytes are reported beside them (design_bytes_per_launch):
+#  - fine colour pass: per even site of the colour its 9 x 4 stored couplings,
+#    2 right-hand-side entries and the 9 x 2 unknowns of its support read and
+#    written; the blocked sweep: 36 stored couplings, b, x read and written once
+#    per even site;
+#  - coarse colour pass: the operator rows, the 16 x 16 smoother matrix Kinv,
+#    16 right-hand-side entries and the 7 x 16 unknowns of the support read
+#    and written.
+def fine_sweep_alg_bytes(N, s_vec):
+    """88 N^2 B (FP64) per sweep: x read + written 32 N^2, b 16 N^2, links 32 N^2,
+    row norms 8 N^2; halved for FP32 (s_vec = 8)."""
+    return 88.0 * N * N * s_vec / 16.0
+
+
 def fine_sweep_site_bytes(s_vec):
     return 36 * s_vec + 2 * s_vec + 2 * 2 * s_vec
 
@@ -498,6 +581,10 @@ def fine_sweep_blocked(N, nrhs, s_vec):
 
 def fine_site_bytes(s_vec):
     return 36 * s_vec + 2 * s_vec + 2 * 9 * 2 * s_vec
+
+
+def coarse_site_alg_bytes(s_op):
+    return 7 * 256 * s_op
 
 
 def coarse_site_bytes(s_op, s_vec):
@@ -543,11 +630,14 @@ def pmc_traffic(kind, prec):
     return 1024.0 * (e["fetch_kib"] / e["fetch_per_kib"] + e["write_kib"] / e["write_per_kib"])
 
 
-def _roof(kname, kind, prec, bytes_launch, t):
-    achieved = bytes_launch / t / 1e9
+def _roof(kname, kind, prec, alg_bytes, design_bytes, t, basis):
+    achieved = alg_bytes / t / 1e9
+    traffic = pmc_traffic(kind, prec)
     return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(kind, prec), "traffic_unit": "bytes per launch",
-            "avg_launch_us": t * 1e6, "bytes_per_launch": bytes_launch}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
+            "avg_launch_us": t * 1e6, "bytes_per_launch": alg_bytes, "bytes_basis": basis,
+            "design_bytes_per_launch": design_bytes, "design_over_algorithmic": design_bytes / alg_bytes,
+            "traffic_over_algorithmic": None if traffic is None else traffic / alg_bytes}
 
 
 def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
@@ -578,17 +668,18 @@ def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
     sv = VEC_BYTES[prec]
     xb = torch.zeros(inf["n"], dtype=dt, device="cuda:0")
     bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
+    fbasis = f"{88 * sv // 16} N^2 B per sweep (x read and written, b, links, row norms)"
     if fine_sweep_blocked(N, 1, sv):
         t = time_launches(lambda: bamg.bamg_level_op(h, 0, sweep, bb, xb, 1), 50, 1, torch)
         e = _roof(f"k_kaczmarz_fine_sweep<{tname}> (level 0, one 16-colour sweep of {inf['n'] // 2} sites per launch; "
                   f"timed per sweep call, which also copies x)", "fine_sweep", prec,
-                  inf["n"] // 2 * fine_sweep_site_bytes(sv), t)
+                  fine_sweep_alg_bytes(N, sv), inf["n"] // 2 * fine_sweep_site_bytes(sv), t, fbasis)
         out.append((e, t * sweeps))
     else:
         nsite = inf["n"] // 2 // 16  # even sites per colour
         t = time_launches(lambda: bamg.bamg_level_op(h, 0, sweep, bb, xb, 1), 50, 16, torch)
         e = _roof(f"k_kaczmarz_fine<{tname}, 1> (level 0, {nsite} sites per launch)", "fine", prec,
-                  nsite * fine_site_bytes(sv), t)
+                  fine_sweep_alg_bytes(N, sv) / 16, nsite * fine_site_bytes(sv), t, fbasis + ", 1/16 per colour pass")
         out.append((e, t * 16 * sweeps))
     L = bamg.bamg_n_levels(h)
     if L > 2:  # coarse pass, level 1
@@ -598,7 +689,9 @@ def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
         bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
         t = time_launches(lambda: bamg.bamg_level_op(h, 1, sweep, bb, xb, 1), 50, ncol, torch)
         e = _roof(f"k_kaczmarz_coarse<{tname},{sname}> (level 1, {ns // ncol} sites per launch)", "coarse",
-                  prec, ns // ncol * coarse_site_bytes(OP_BYTES[prec], sv), t)
+                  prec, ns // ncol * coarse_site_alg_bytes(OP_BYTES[prec]),
+                  ns // ncol * coarse_site_bytes(OP_BYTES[prec], sv), t,
+                  f"the operator rows of the colour's sites: 7 x 256 entries of {OP_BYTES[prec]} B per site")
         out.append((e, t * ncol * sweeps))
     if L > 1:  # coarsest product
         inf = bamg.bamg_level_info(h, L - 1)
@@ -608,20 +701,23 @@ def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
         bb = torch.ones(n, dtype=cdt, device="cuda:0")
         op = bamg.OP_COARSEST_F32 if c32 else bamg.OP_COARSEST
         t = time_launches(lambda: bamg.bamg_level_op(h, L - 1, op, bb, xb, 1), 20, 1, torch)
+        half = "the 64 x 64 blocks of the gamma5-Hermitian inverse on and above the diagonal, and x, y"
         if c32 and n % 64 == 0:
             # the FP32 copy of the packed blocks (complex64 entries), x and y complex64
+            b_ = 8.0 * (n * n / 2 + 32 * n) + 16.0 * n
             e = _roof(f"k_dense_mv_g5<cx<float>> + k_dense_mv_g5_reduce (coarsest inverse, FP32 copy of the packed "
-                      f"gamma5 half, n = {n}; timed per call)", "dense32_g5", prec, 8.0 * (n * n / 2 + 32 * n) + 16.0 * n, t)
+                      f"gamma5 half, n = {n}; timed per call)", "dense32_g5", prec, b_, b_, t, half + " (FP32)")
         elif c32:
-            e = _roof(f"k_dense_mv32 (coarsest inverse, n = {n})", "dense32", prec, 8.0 * n * n + 16.0 * n, t)
+            b_ = 8.0 * n * n + 16.0 * n
+            e = _roof(f"k_dense_mv32 (coarsest inverse, n = {n})", "dense32", prec, b_, b_, t, "the FP32 inverse, x, y")
         elif n % 64 == 0:
-            # the gamma5-Hermitian inverse's 64 x 64 blocks on and above the block
-            # diagonal (n^2 / 2 + 32 n entries) and x, y; the call is the block
-            # product and the reduction of its partial products
+            # the call is the block product and the reduction of its partial products
+            b_ = 16.0 * (n * n / 2 + 32 * n) + 32.0 * n
             e = _roof(f"k_dense_mv_g5 + k_dense_mv_g5_reduce (coarsest inverse, packed gamma5 half, n = {n}; "
-                      f"timed per call)", "dense_g5", prec, 16.0 * (n * n / 2 + 32 * n) + 32.0 * n, t)
+                      f"timed per call)", "dense_g5", prec, b_, b_, t, half)
         else:
-            e = _roof(f"k_dense_mv (coarsest inverse, n = {n})", "dense", prec, 16.0 * n * n + 32.0 * n, t)
+            b_ = 16.0 * n * n + 32.0 * n
+            e = _roof(f"k_dense_mv (coarsest inverse, n = {n})", "dense", prec, b_, b_, t, "the inverse, x, y")
         out.append((e, t))
     for e, tc in out:
         e["us_per_cycle"] = tc * 1e6
@@ -681,31 +777,73 @@ def mfma_utilisation(bamg, torch, h, R=32):
     return out
 
 
-def cpu_baseline(w, U_np, tol):
-    """The oracle (single-threaded C++ FP64) solving the same system, timed on
-    one full solve with its setup untimed.  It runs with 4 levels (coarsest
-    dimension 2048): with the GPU path's 3 levels its setup would spend ~3
-    minutes in the dense LU of the 8192-dim coarsest operator, and per solve
-    the 4-level oracle is the faster of the two (1.8 s against 2.7 s), so the
-    baseline errs in the CPU's favour."""
+def cpu_baseline(w, U_np, tol, Ps, pre, post, reps=3):
+    """The oracle (plain C++ FP64; test infrastructure, loaded only here) solving
+    the same 256^2 system with the hierarchy of the GPU's FP64 line
+    'fp64+graphs+v22+bootV': the interpolation operators of the headline setup
+    (bootstrap super-V), the oracle's own Galerkin products, smoothers and
+    V(pre,post) cycle, the 8192-dim coarsest level factored by LAPACK (setup,
+    untimed).  Timed: full solves (reduction, FGMRES(32), reconstruction) to tol.
+      single thread: `reps` solves of the benchmark's right-hand side one after
+        another, median;
+      all host cores: as many threads as cores, each solving its own
+        right-hand side at the same time (the oracle's solve is sequential
+        code; right-hand sides are independent), solves / wall time, median of
+        `reps` rounds."""
     import inputs
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
     N = w["N"]
-    b = inputs.gaussian(2 * N * N, w["rhs_seed"])
-    o = oracle.Hierarchy(U_np, w["m"], n_levels=4, seed=w["tv_seed"])
     t0 = time.perf_counter()
-    st, xo, info = o.solve(b, tol=tol)
-    t = time.perf_counter() - t0
+    o = oracle.Hierarchy.from_interpolation(U_np, w["m"], Ps, pre=pre, post=post)
+    t_setup = time.perf_counter() - t0
+    b = inputs.gaussian(2 * N * N, w["rhs_seed"])
+    single, iters = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        st, xo, info = o.solve(b, tol=tol)
+        single.append(time.perf_counter() - t0)
+        iters = info["iters"]
+    cores = len(os.sched_getaffinity(0))
+    B = [inputs.gaussian(2 * N * N, w["rhs_seed"] + 2000 + i) for i in range(cores)]
+    rates, conv = [], True
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = list(ex.map(lambda bb: o.solve(bb, tol=tol), B))
+            rates.append(cores / (time.perf_counter() - t0))
+            conv = conv and all(r_[0] == 0 for r_ in res)
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": 1.0 / t, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full solve of the same 256^2 system, oracle FP64 with 4 levels and V(4,4) "
-                      f"({info['iters']} FGMRES iterations, {t:.2f} s); oracle setup untimed", "iters": info["iters"],
-            "host_cores_available": len(os.sched_getaffinity(0)), "host_cpu": model}
+    t1 = statistics.median(single)
+    return {"value": statistics.median(rates), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} rounds of {cores} concurrent full solves (one per core, independent right-hand "
+                      f"sides) of the same 256^2 system, median; oracle FP64 with the headline setup's P, "
+                      f"3 levels, V({pre},{post}), FGMRES(32) to {tol:g}",
+            "config": {"workload": w["name"], "levels": len(Ps) + 1, "cycle": f"V({pre},{post})",
+                       "setup": "the GPU's bootstrap super-V interpolation", "precision": "fp64",
+                       "coarsest": "LAPACK LU of the oracle's Galerkin operator (setup)",
+                       "gpu_line": "precisions['fp64+graphs+v22+bootV']"},
+            "single_thread": {"value": 1.0 / t1, "unit": "solves/s", "median_s": t1, "runs_s": single,
+                              "iters": iters},
+            "all_core_rounds_solves_per_s": rates, "converged": conv, "twin_setup_s": t_setup,
+            "host_cores_available": cores, "host_cpu": model}
+
+
+def convergence_rate(bamg, inputs, torch, h, N, iters=12):
+    """The stand-alone rate of Sec. 4, rho = ||e^nu|| / ||e^{nu-1}||: the solver's
+    preconditioner used on its own, x <- x + M(0 - Dhat x) from a Gaussian start
+    (the iterate is the error)."""
+    import numpy as np
+    x = torch.from_numpy(inputs.gaussian(N * N, 4321)).to("cuda:0")
+    norms = bamg.bamg_stationary(h, x, iters)
+    r = norms[1:] / norms[:-1]
+    return {"rho_last": float(r[-1]), "rho_geomean_last5": float(np.exp(np.mean(np.log(r[-5:])))),
+            "iters": iters, "rates": [float(v) for v in r]}
 
 
 if __name__ == "__main__":
