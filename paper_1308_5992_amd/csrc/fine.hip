@@ -336,7 +336,10 @@ struct DhatRow {
   cx<T> x0, x1, e0, e1, o0, o1;  // x (both spins), Ue and Uo (both directions) of one row at this lane's column
 };
 
-template <typename T, int PF>
+// NTS: non-temporal stores of y (outputs far larger than the caches: they are
+// not re-read by this launch, and allocating them in L2 / the Infinity Cache
+// only evicts the x and link rows that the neighbouring segments still read)
+template <typename T, int PF, bool NTS>
 __global__ __launch_bounds__(256) void k_dhat_strip(FineT<T> f, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
                                                     const cx<T>* __restrict__ b, int nstrips, int H, int nseg,
                                                     int nrhs) {
@@ -432,8 +435,15 @@ __global__ __launch_bounds__(256) void k_dhat_strip(FineT<T> f, const cx<T>* __r
           }
           if (writes) {
             const size_t i = at(ty - 1);
-            yv[i] = r0v;
-            yv[i + 1] = r1v;
+            if constexpr (NTS) {
+              __builtin_nontemporal_store(r0v.x, &yv[i].x);
+              __builtin_nontemporal_store(r0v.y, &yv[i].y);
+              __builtin_nontemporal_store(r1v.x, &yv[i + 1].x);
+              __builtin_nontemporal_store(r1v.y, &yv[i + 1].y);
+            } else {
+              yv[i] = r0v;
+              yv[i + 1] = r1v;
+            }
           }
         }
         if (bv && ty < y0 + H) {  // right-hand side of the next output row, ty
@@ -452,17 +462,25 @@ template <typename T>
 void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s) {
   const int N = f.N, NH = f.NH;
   // Kernel choice by measured speed (all three give the same bits): FP64
-  // streams 16-row strip segments when they make >= 2048 waves; FP32 streams
+  // streams 16-row strip segments when they make >= 2048 waves (32- and
+  // 64-row segments were slower: fewer waves in flight); FP32 streams
   // 64-row segments for up to 4 right-hand sides when they make >= 2048
   // waves, and otherwise uses the 32 x 16 tiles, whose right-hand-side loop
-  // keeps the links in registers.
+  // keeps the links in registers.  Outputs of 128 MiB and more are stored
+  // non-temporally (4096^2: 4.67 -> 4.84 TB/s in compulsory bytes, 512^2 x 64:
+  // 3.1 -> 3.5; at 2048^2, 64 MiB, the cached stores are faster).
   if (NH >= 64) {
     const int S = (NH + STRIP - 1) / STRIP;
     const int H = sizeof(T) == 8 ? 16 : 64;
     const long items = (N % H == 0) ? (long)S * (N / H) * nrhs : 0;
     if (items >= 2048 && (sizeof(T) == 8 || nrhs <= 4)) {
-      hipLaunchKernelGGL((k_dhat_strip<T, 1>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, f, x, y, b, S, H,
-                         N / H, nrhs);
+      const bool nts = (size_t)N * N * nrhs * sizeof(cx<T>) >= ((size_t)128 << 20);
+      if (nts)
+        hipLaunchKernelGGL((k_dhat_strip<T, 1, true>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, f, x, y, b,
+                           S, H, N / H, nrhs);
+      else
+        hipLaunchKernelGGL((k_dhat_strip<T, 1, false>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, f, x, y,
+                           b, S, H, N / H, nrhs);
       return;
     }
   }
