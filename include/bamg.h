@@ -289,15 +289,22 @@ size_t bamg_footprint_bytes(const bamg_params *p);
  * reads the region [u0 + i0, u0 + i0 + Ru) x [v0 + j0, v0 + j0 + Rv) of x,
  * projects, for colour c = 0..15, the sites u0 + si0[c] + 4 p, v0 + sj0[c] + 4 q
  * (p < (first[c+1] - first[c]) / nj[c], q < nj[c]) in this order, and writes
- * its own tile.
+ * its own tile.  The pipelined form (3) marches its tile's region down v
+ * with a ring of W columns: colour c projects column sj0[c] + 4k at
+ * macro-step c + k (k < nj[c]), all rows of a macro-step at once; region
+ * column j0 + j is read at macro-step max(0, floor((j0 + j - A) / 4)) into
+ * ring slot j mod W, whose previous column (j - W) is written out first if it
+ * belongs to the tile; M macro-steps in all.
  *   form: 0 the library's choice for nrhs right-hand sides, 1 the
- *         LDS-resident form's tile, 2 the streaming form's tile;
+ *         LDS-resident form's tile, 2 the streaming form's tile, 3 the
+ *         pipelined form's tile;
  *   fp32: nonzero for FP32 arithmetic (the mixed cycle), else FP64;
- *   plan_out (host, 74 int32): Tu, Tv, ntu, ntv, i0, j0, Ru, Rv, nupd,
- *         first[17], si0[16], sj0[16], nj[16] (nupd = first[16] projections).
- * Returns the form of the plan written (1 or 2), 0 if the colour passes are
- * used (form 0) or no tile applies (the lattice is too small or N/2 is not a
- * multiple of 8), BAMG_EINVAL for bad arguments. */
+ *   plan_out (host, 77 int32): Tu, Tv, ntu, ntv, i0, j0, Ru, Rv, nupd,
+ *         first[17], si0[16], sj0[16], nj[16] (nupd = first[16] projections),
+ *         then A, M, W of form 3 (zeros for forms 1 and 2).
+ * Returns the form of the plan written (1, 2 or 3), 0 if the colour passes
+ * are used (form 0) or no tile applies (the lattice is too small or N/2 is
+ * not a multiple of 8), BAMG_EINVAL for bad arguments. */
 int bamg_fine_sweep_plan(int32_t N, int32_t nrhs, int32_t fp32, int32_t form, int32_t *plan_out);
 
 /* k test vectors from the Philox4x32-10 generator (as used by setup):

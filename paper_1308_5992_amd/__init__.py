@@ -318,10 +318,11 @@ def bamg_full_residual_noalloc(N: int, gauge, m: float, B, X, nrhs: int, relres)
 
 
 def bamg_fine_sweep_plan(N: int, nrhs: int = 1, fp32: bool = False, form: int = 0):
-    """(form, plan) of the level-0 sweep blocked in LDS (host only): form 1 or 2
-    and a dict of the tile plan, or (0, None) where the colour passes are used
-    (form 0) or no tile applies."""
-    out = np.zeros(74, dtype=np.int32)
+    """(form, plan) of the level-0 sweep blocked in LDS (host only): form 1, 2
+    or 3 and a dict of the tile plan (with the pipelined form's ring lead A,
+    macro-steps M and ring columns W, zeros for forms 1 and 2), or (0, None)
+    where the colour passes are used (form 0) or no tile applies."""
+    out = np.zeros(77, dtype=np.int32)
     got = lib.bamg_fine_sweep_plan(int(N), int(nrhs), int(bool(fp32)), int(form), out.ctypes.data)
     if got < 0:
         _check(got, "bamg_fine_sweep_plan")
@@ -333,6 +334,7 @@ def bamg_fine_sweep_plan(N: int, nrhs: int = 1, fp32: bool = False, form: int = 
     plan["si0"] = out[26:42].tolist()
     plan["sj0"] = out[42:58].tolist()
     plan["nj"] = out[58:74].tolist()
+    plan["A"], plan["M"], plan["W"] = (int(v) for v in out[74:77])
     return int(got), plan
 
 

@@ -622,9 +622,10 @@ int bamg_full_residual(int32_t N, const void* gauge, double m, const void* B, co
 }
 
 int bamg_fine_sweep_plan(int32_t N, int32_t nrhs, int32_t fp32, int32_t form, int32_t* plan_out) {
-  if (!plan_out || N < 1 || nrhs < 1 || form < 0 || form > 2) return fail(BAMG_EINVAL, "bad arguments");
+  if (!plan_out || N < 1 || nrhs < 1 || form < 0 || form > 3) return fail(BAMG_EINVAL, "bad arguments");
   FineSweepPlan p;
-  const int got = fine_sweep_plan_query(N, nrhs, fp32 != 0, form, p);
+  int sched[3];
+  const int got = fine_sweep_plan_query(N, nrhs, fp32 != 0, form, p, sched);
   if (got == 0) return 0;
   int32_t* o = plan_out;
   const int head[9] = {p.Tu, p.Tv, p.ntu, p.ntv, p.i0, p.j0, p.Ru, p.Rv, p.nupd};
@@ -633,6 +634,7 @@ int bamg_fine_sweep_plan(int32_t N, int32_t nrhs, int32_t fp32, int32_t form, in
   for (int c = 0; c < 16; ++c) *o++ = p.si0[c];
   for (int c = 0; c < 16; ++c) *o++ = p.sj0[c];
   for (int c = 0; c < 16; ++c) *o++ = p.nj[c];
+  for (int k = 0; k < 3; ++k) *o++ = sched[k];
   return got;
 }
 

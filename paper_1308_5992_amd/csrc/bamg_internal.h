@@ -157,7 +157,7 @@ template <typename T>
 bool fine_sweep_applies(const FineT<T>& f, int nrhs);
 // the plan of form 0 (the library's choice), 1 (LDS-resident) or 2
 // (streaming); returns the form written, 0 for none (host only)
-int fine_sweep_plan_query(int N, int nrhs, bool fp32, int form, FineSweepPlan& p);
+int fine_sweep_plan_query(int N, int nrhs, bool fp32, int form, FineSweepPlan& p, int sched[3]);
 template <typename T>
 void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s);
 // rc = P^H r (level 0 -> 1), and xz = 0 (level 1, same layout) if xz != NULL;

@@ -11,6 +11,9 @@
 //   +x: h = u (a - b) -> (h, -h)        -x: h = u (a + b) -> (h,  h)
 //   +y: h = u (a - i b) -> (h, i h)     -y: h = u (a + i b) -> (h, -i h)
 // with a factor 1/2 applied once per hop (exact in binary floating point).
+#include <algorithm>
+#include <vector>
+
 #include "bamg_internal.h"
 
 namespace bamg {
@@ -649,7 +652,12 @@ __device__ __forceinline__ void dhat_slot_block(const FineT<T>& f, int x, int y,
       C l1 = *p1, l2 = *p2;
       l1.y = bk1 ? -l1.y : l1.y;
       l2.y = bk2 ? -l2.y : l2.y;
-      const C u = l1 * l2;
+      // the one inexact product of a path, with its contraction fixed; the
+      // phase factors below are 0, +-1, +-2, +-i, so their products are exact
+      // and the result does not depend on how the compiler fuses them (the
+      // blocks are formed both at setup and inside the pipelined sweep, with
+      // the same bits)
+      const C u = cmul_fixed(l1, l2);
       const C a1 = hop_phase<T>(d1), a2 = hop_phase<T>(d2);
       const C s12 = a1 + a2;
       b00 = b00 + (C{1, 0} + a1 * conj(a2)) * u;
@@ -660,10 +668,10 @@ __device__ __forceinline__ void dhat_slot_block(const FineT<T>& f, int x, int y,
   }
   const T k2q = (T)(0.25 * f.kappa2);
   const T one = (n == 0) ? T(1) : T(0);
-  B[0][0] = C{one, 0} - k2q * b00;
+  B[0][0] = C{fma(-k2q, b00.x, one), -(k2q * b00.y)};
   B[0][1] = -(k2q * b01);
   B[1][0] = -(k2q * b10);
-  B[1][1] = C{one, 0} - k2q * b11;
+  B[1][1] = C{fma(-k2q, b11.x, one), -(k2q * b11.y)};
 }
 
 // The slot blocks of every even site, stored once at setup (and after the
@@ -1360,6 +1368,256 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
   }
 }
 
+// ---------------------------------------------------------------------------
+// The sweep blocked in LDS for large lattices: a pipelined march along v.
+// A work-group owns a tile of FP_TU x Tv even sites (u, v) and the same
+// dependence region as the blocked sweeps (fine_sweep_plan), but it never
+// holds the whole region: it marches down v with a ring of FP_W columns of x
+// in LDS.  In the colour order the dependence between two projections of
+// colours c' < c that share an unknown spans |dv| <= 2; colour c projects
+// column sj0[c] + 4 k at macro-step k + c, so at any macro-step the active
+// columns of the 16 colours lie 3 apart (their 3 x 3 supports are disjoint)
+// and every projection follows those it depends on: all 16 colours run
+// together, one barrier per macro-step, and the result is bitwise that of the
+// colour-by-colour sweep (the host checks the schedule and the ring; a CPU
+// replay pins it).  Every (colour, row) pair of the plan has a four-lane
+// group of its own, whose site moves by 4 in v per macro-step; it reads its
+// stored slot blocks and Gram terms one macro-step ahead.  Four lanes per projection,
+// lane q taking the slots q, q + 4 (and 8 for q = 0) and finishing the
+// 16-lane butterfly with two quad exchanges, as k_kaczmarz_fine_il does.
+// The next macro-step's columns are read while the current one projects; a
+// column whose ring slot is taken again is written out first if it belongs
+// to the tile.  xin and xout must not overlap.
+// ---------------------------------------------------------------------------
+constexpr int FP_TU = 16;               // tile extent in u
+constexpr int FP_W = 48;                // ring columns
+constexpr int FP_RU_MAX = 24;           // region extent in u the ring holds
+constexpr int FP_NT = 320;              // threads: 80 four-lane groups
+constexpr int FP_GROUPS = FP_NT / 4;
+
+struct FinePipePlan {
+  int Tu, Tv, ntu, ntv, i0, j0, Ru, Rv, M, A;
+  int si0[16], sj0[16], ni[16], nj[16], off[16];
+};
+
+// Work-group barrier for LDS only: waits for this wave's LDS accesses
+// (lgkmcnt 0) but not for its global loads, which stay in flight across it
+// (__syncthreads waits for every outstanding access, so the next macro-step's
+// loads could not overlap the current one).  The empty asm statements keep the
+// compiler from moving LDS accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt 63, expcnt 7, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// sum over the 4 lanes of a quad: partner q ^ 2, then q ^ 1 (the last two
+// steps of the 16-lane butterfly, in its pair order)
+template <typename T>
+__device__ __forceinline__ cx<T> quad_sum(cx<T> v) {
+  v.x += dpp_mov<DPP_QUAD_XOR2>(v.x);
+  v.y += dpp_mov<DPP_QUAD_XOR2>(v.y);
+  v.x += dpp_mov<DPP_QUAD_XOR1>(v.x);
+  v.y += dpp_mov<DPP_QUAD_XOR1>(v.y);
+  return v;
+}
+
+// wrap a lattice coordinate that is at most one period off
+__device__ __forceinline__ int wrap1(int a, int N) { return a < 0 ? a + N : (a >= N ? a - N : a); }
+
+template <typename T>
+__global__ __launch_bounds__(FP_NT) void k_kaczmarz_fine_pipe(FineT<T> f, FinePipePlan p, const cx<T>* __restrict__ xin,
+                                                              cx<T>* __restrict__ xout, const cx<T>* __restrict__ b) {
+  using C = cx<T>;
+  constexpr int RP = FP_W * FP_RU_MAX;  // ring positions: position = column slot * FP_RU_MAX + row
+  __shared__ C X[RP * 2];   // unknowns
+  __shared__ C BR[RP * 2];  // right-hand sides
+  const int tid = threadIdx.x;
+  const int N = f.N, NH = f.NH;
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int u0 = 1 + (tile % p.ntu) * p.Tu, v0 = 1 + (tile / p.ntu) * p.Tv;
+  const size_t n = (size_t)N * NH * 2;
+  const C* __restrict__ xr = xin + blockIdx.y * n;
+  C* __restrict__ xw = xout + blockIdx.y * n;
+  const C* __restrict__ br = b ? b + blockIdx.y * n : nullptr;
+  const int Ru = p.Ru, Rv = p.Rv;
+  // lattice coordinates of region position (ri, cj)
+  auto lxy = [&](int ri, int cj, int& xx, int& yy) {
+    const int u = u0 + p.i0 + ri, v = v0 + p.j0 + cj;
+    xx = ((u + v) % N + N) % N;
+    yy = ((u - v) % N + N) % N;
+  };
+  // columns brought in at macro-step m (m >= 1): [4m + A - j0, +4); at m = 0 every column below 4 + A - j0
+  const int col0_hi = min(Rv, 4 + p.A - p.j0);
+  // prologue: the columns of macro-step 0 (4 entries per position: 2 unknowns, 2 right-hand sides)
+  for (int e = tid; e < col0_hi * Ru * 4; e += FP_NT) {
+    const int w = e & 3, qq = e >> 2, cj = qq / Ru, ri = qq - cj * Ru;
+    int xx, yy;
+    lxy(ri, cj, xx, yy);
+    const size_t s2 = 2 * ((size_t)yy * NH + (xx >> 1));
+    const int at = (cj % FP_W) * FP_RU_MAX + ri;
+    if (w < 2) X[at * 2 + w] = xr[s2 + w];
+    else BR[at * 2 + (w - 2)] = br ? br[s2 + (w - 2)] : C{0, 0};
+  }
+  // The entries this thread brings in at every macro-step m >= 1: entry e =
+  // tid + k FP_NT of the 4-column block, column 4m + A - j0 + dc, row ri.  Its
+  // lattice coordinates move by (+4, -4) per macro-step.
+  constexpr int PF = (4 * FP_RU_MAX * 4 + FP_NT - 1) / FP_NT;
+  int ew[PF], eri[PF], edc[PF], ex[PF], ey[PF];
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int e = tid + k * FP_NT, qq = e >> 2;
+    ew[k] = e & 3;
+    edc[k] = qq / Ru;
+    eri[k] = qq - edc[k] * Ru;
+    if (edc[k] >= 4) edc[k] = 1 << 20;  // beyond the block: never loaded
+    lxy(eri[k], 4 + p.A - p.j0 + edc[k], ex[k], ey[k]);  // its position at macro-step 1
+  }
+  // The group's projection: a fixed (colour, row) pair of the plan, whose
+  // column moves by 4 per macro-step; its stored slot blocks and Gram terms
+  // are read one macro-step ahead.
+  const int gid = tid >> 2, q = tid & 3;
+  const bool q0 = q == 0;
+  int gsi = 0, gsj = 0, gnj = 0, goff = 1 << 20, gr = -1;
+  {
+    int acc = 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (gr < 0 && gid < acc + p.ni[c]) {
+        gr = gid - acc;
+        gsi = p.si0[c];
+        gsj = p.sj0[c];
+        gnj = p.nj[c];
+        goff = p.off[c];
+      }
+      acc += p.ni[c];
+    }
+  }
+  const int gri = gsi + 4 * gr - p.i0;  // the group's row in the region
+  int gx = 0, gy = 0;                   // lattice coordinates of its site at its first macro-step
+  if (gr >= 0) lxy(gri, gsj - p.j0, gx, gy);
+  struct Stored {
+    C B[3][4];
+    C nu, g10;
+  };
+  auto read_stored = [&](int xx, int yy, Stored& S) {
+    const size_t ih = (size_t)yy * NH + (xx >> 1);
+    const C* bst = f.Bst + ih * 9 * 4;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int sl = k == 0 ? q : (k == 1 ? q + 4 : (q0 ? 8 : 0));
+#pragma unroll
+      for (int w = 0; w < 4; ++w) S.B[k][w] = bst[sl * 4 + w];
+    }
+    S.nu = f.Gst[2 * ih];
+    S.g10 = f.Gst[2 * ih + 1];
+  };
+  Stored cur, nxt;
+  if (gr >= 0 && goff == 0) read_stored(gx, gy, cur);
+  __syncthreads();
+  const C c00 = cmul_fixed(C{0, 0}, C{0, 0});
+  const C zr = c00 + c00;
+  for (int m = 0; m < p.M; ++m) {
+    // the next macro-step's columns and the group's next projection data,
+    // in flight while this macro-step projects
+    const int nc0 = 4 * (m + 1) + p.A - p.j0, nc1 = (m + 1 < p.M) ? min(Rv, nc0 + 4) : nc0;
+    C pre[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      pre[k] = C{0, 0};
+      if (m > 0) {  // coordinates of macro-step m + 1
+        ex[k] = wrap1(ex[k] + 4, N);
+        ey[k] = wrap1(ey[k] - 4, N);
+      }
+      if (nc0 + edc[k] < nc1) {
+        const size_t s2 = 2 * ((size_t)ey[k] * NH + (ex[k] >> 1));
+        if (ew[k] < 2) pre[k] = xr[s2 + ew[k]];
+        else if (br) pre[k] = br[s2 + (ew[k] - 2)];
+      }
+    }
+    const int kg = m - goff;  // the group's step along its columns
+    const bool act = gr >= 0 && kg >= 0 && kg < gnj;
+    const bool act_next = gr >= 0 && kg + 1 >= 0 && kg + 1 < gnj;
+    int nx = gx, ny = gy;  // its site at macro-step m + 1
+    if (kg + 1 >= 1) {
+      nx = wrap1(gx + 4, N);
+      ny = wrap1(gy - 4, N);
+    }
+    if (act_next) read_stored(nx, ny, nxt);
+    if (act) {
+      const int cj0 = gsj + 4 * kg - p.j0;
+      const int site = (cj0 % FP_W) * FP_RU_MAX + gri;
+      C X0[3], X1[3];
+      int pos[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int sl = k == 0 ? q : (k == 1 ? q + 4 : (q0 ? 8 : 0));
+        const int ri = gri + nib(SLOT_DU1, sl) - 1, cj = cj0 + nib(SLOT_DV1, sl) - 1;
+        pos[k] = (cj % FP_W) * FP_RU_MAX + ri;
+        X0[k] = X[pos[k] * 2];
+        X1[k] = X[pos[k] * 2 + 1];
+      }
+      C w0[3], w1[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        w0[k] = cmul_fixed(cur.B[k][0], X0[k]) + cmul_fixed(cur.B[k][1], X1[k]);
+        w1[k] = cmul_fixed(cur.B[k][2], X0[k]) + cmul_fixed(cur.B[k][3], X1[k]);
+      }
+      const C r0 = quad_sum((w0[0] + (q0 ? w0[2] : zr)) + (w0[1] + zr));
+      const C r1 = quad_sum((w1[0] + (q0 ? w1[2] : zr)) + (w1[1] + zr));
+      const C b0 = BR[site * 2], b1 = BR[site * 2 + 1];
+      const C nu = cur.nu, g10 = cur.g10;
+      const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
+      const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k < 2 || q0) {
+          X[pos[k] * 2] = (X0[k] + cjmul_fixed(cur.B[k][0], a0)) + cjmul_fixed(cur.B[k][2], a1);
+          X[pos[k] * 2 + 1] = (X1[k] + cjmul_fixed(cur.B[k][1], a0)) + cjmul_fixed(cur.B[k][3], a1);
+        }
+      }
+    }
+    if (kg + 1 >= 1) {
+      gx = nx;
+      gy = ny;
+    }
+    lds_barrier();
+    // ring slots taken by the next columns: write their old column out if it
+    // belongs to the tile (every projection reading it has run), then store
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int cj = nc0 + edc[k];
+      if (cj < nc1) {
+        const int at = (cj % FP_W) * FP_RU_MAX + eri[k];
+        if (ew[k] < 2) {
+          const int old = cj - FP_W, io = eri[k] + p.i0, jo = old + p.j0;
+          if (old >= 0 && io >= 0 && io < p.Tu && jo >= 0 && jo < p.Tv) {
+            const int ox = wrap1(ex[k] - FP_W, N), oy = wrap1(ey[k] + FP_W, N);
+            xw[2 * ((size_t)oy * NH + (ox >> 1)) + ew[k]] = X[at * 2 + ew[k]];
+          }
+          X[at * 2 + ew[k]] = pre[k];
+        } else {
+          BR[at * 2 + (ew[k] - 2)] = pre[k];
+        }
+      }
+    }
+    lds_barrier();
+    if (act_next) cur = nxt;
+  }
+  // the tile's columns still in the ring
+  const int c0 = max(0, Rv - FP_W);
+  for (int e = tid; e < (Rv - c0) * Ru * 2; e += FP_NT) {
+    const int sp = e & 1, qq = e >> 1, cj = c0 + qq / Ru, ri = qq - (qq / Ru) * Ru;
+    const int i = ri + p.i0, j = cj + p.j0;
+    if (i >= 0 && i < p.Tu && j >= 0 && j < p.Tv) {
+      int xx, yy;
+      lxy(ri, cj, xx, yy);
+      xw[2 * ((size_t)yy * NH + (xx >> 1)) + sp] = X[((cj % FP_W) * FP_RU_MAX + ri) * 2 + sp];
+    }
+  }
+}
+
 // The dependence recursion for a Tu x Tv tile whose origin has u = v = 1 mod 4
 // (coordinates relative to the tile origin).  False if a projection count
 // exceeds the table or the region would meet itself across the torus.
@@ -1493,12 +1751,112 @@ bool fine_sweep_choose_s(int N, int nrhs, FineSweepPlan& best, int& best_maxcnt)
   return found;
 }
 
-// 0: no blocked sweep, 1: LDS-resident form, 2: streaming form
+// The pipelined sweep's plan for FP_TU x Tv tiles: the dependence rectangles
+// of fine_sweep_plan, colour c at macro-step offset c (the schedule the
+// kernel assumes), checked here pair by pair: every two projections whose
+// supports share an unknown must run in colour order, and no two projections
+// of one macro-step may share one.  The ring: column j is read at macro-step
+// max(0, floor((j - A) / 4)), which must come no later than its first use,
+// and its slot is taken again by column j + FP_W no earlier than the
+// macro-step after its last use.  False if no A passes or the region does not
+// fit the ring's rows.
+static bool fine_pipe_plan(int N, int Tv, FinePipePlan& q, FineSweepPlan& p) {
+  if (N % FP_TU != 0 || (N / 2) % Tv != 0 || Tv % 4 != 0) return false;
+  if (!fine_sweep_plan(N, FP_TU, Tv, p, 1 << 30)) return false;
+  if (p.Ru > FP_RU_MAX) return false;
+  q.Tu = p.Tu; q.Tv = p.Tv; q.ntu = p.ntu; q.ntv = p.ntv;
+  q.i0 = p.i0; q.j0 = p.j0; q.Ru = p.Ru; q.Rv = p.Rv;
+  q.M = 0;
+  for (int c = 0; c < 16; ++c) {
+    q.si0[c] = p.si0[c];
+    q.sj0[c] = p.sj0[c];
+    q.nj[c] = p.nj[c];
+    q.ni[c] = p.nj[c] > 0 ? (p.first[c + 1] - p.first[c]) / p.nj[c] : 0;
+    q.off[c] = c;
+    if (q.ni[c] > 0) q.M = std::max(q.M, c + q.nj[c]);
+  }
+  {  // the kernel gives each (colour, row) pair of the plan a four-lane group of its own
+    int groups = 0;
+    for (int c = 0; c < 16; ++c) groups += q.ni[c];
+    if (groups > FP_GROUPS) return false;
+  }
+  // dependences: colours c' < c, columns j' and j within 2 of each other
+  for (int c = 0; c < 16; ++c)
+    for (int cp = 0; cp < c; ++cp) {
+      if (!q.ni[c] || !q.ni[cp]) continue;
+      for (int k = 0; k < q.nj[c]; ++k)
+        for (int kp = 0; kp < q.nj[cp]; ++kp) {
+          const int dj = (q.sj0[c] + 4 * k) - (q.sj0[cp] + 4 * kp);
+          if (dj >= -2 && dj <= 2 && !(kp + q.off[cp] < k + q.off[c])) return false;
+        }
+    }
+  // first and last macro-step each region column is read or written
+  std::vector<int> first(p.Rv, 1 << 30), last(p.Rv, -1);
+  for (int c = 0; c < 16; ++c)
+    for (int k = 0; k < q.nj[c] && q.ni[c]; ++k)
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int cj = q.sj0[c] + 4 * k + dj - p.j0;
+        if (cj < 0 || cj >= p.Rv) return false;
+        first[cj] = std::min(first[cj], k + q.off[c]);
+        last[cj] = std::max(last[cj], k + q.off[c]);
+      }
+  auto floor4 = [](int a) { return a >= 0 ? a / 4 : -((-a + 3) / 4); };
+  for (int A = -64; A <= 64; ++A) {
+    bool ok = true;
+    for (int cj = 0; cj < p.Rv && ok; ++cj) {
+      const int j = cj + p.j0, sl = std::max(0, floor4(j - A));
+      if (first[cj] < (1 << 30) && sl > first[cj]) ok = false;
+      if (cj + FP_W < p.Rv) {
+        const int sl2 = std::max(0, floor4(j + FP_W - A));
+        if (sl2 <= last[cj] || sl2 < 1) ok = false;
+      }
+    }
+    if (ok) {
+      q.A = A;
+      return true;
+    }
+  }
+  return false;
+}
+
+// The pipelined sweep's tile for an N x N lattice: FP_TU in u and, along v,
+// the tile with the fewest projections per tile site among those giving at
+// least 512 work-groups (else the most work-groups).
+static bool fine_pipe_choose(int N, int nrhs, FinePipePlan& best, FineSweepPlan& best_p) {
+  bool found = false;
+  double best_red = 0;
+  long best_wg = 0;
+  for (int Tv : {32, 64, 128, 256, 512}) {
+    FinePipePlan q;
+    FineSweepPlan p;
+    if (!fine_pipe_plan(N, Tv, q, p)) continue;
+    long nproj = 0;
+    for (int c = 0; c < 16; ++c) nproj += (long)q.ni[c] * q.nj[c];
+    const long wg = (long)q.ntu * q.ntv * nrhs;
+    const double red = (double)nproj / (q.Tu * q.Tv);
+    bool better;
+    if (!found) better = true;
+    else if (wg >= 512 && best_wg >= 512) better = red < best_red;
+    else better = wg > best_wg || (wg == best_wg && red < best_red);
+    if (better) {
+      best = q;
+      best_p = p;
+      best_red = red;
+      best_wg = wg;
+      found = true;
+    }
+  }
+  return found;
+}
+
+// 0: no blocked sweep, 1: LDS-resident form, 2: streaming form, 3: pipelined
+// march along v (beyond the streaming form's sizes)
 template <typename T>
-static int fine_sweep_cached_plan(int N, int nrhs, FineSweepPlan& out, int& maxcnt) {
+static int fine_sweep_cached_plan(int N, int nrhs, FineSweepPlan& out, int& maxcnt, FinePipePlan* pipe = nullptr) {
   struct Cached {
     int N = -1, nrhs = -1, mode = 0, maxcnt = 0;
     FineSweepPlan p;
+    FinePipePlan q;
   };
   thread_local Cached cache;
   if (cache.N != N || cache.nrhs != nrhs) {
@@ -1510,9 +1868,12 @@ static int fine_sweep_cached_plan(int N, int nrhs, FineSweepPlan& out, int& maxc
       cache.mode = 1;
     else if (entries <= FSS_MAX_ENTRIES<T> && fine_sweep_choose_s<T>(N, nrhs, cache.p, cache.maxcnt))
       cache.mode = 2;
+    else if (fine_pipe_choose(N, nrhs, cache.q, cache.p))
+      cache.mode = 3;
   }
   out = cache.p;
   maxcnt = cache.maxcnt;
+  if (pipe) *pipe = cache.q;
   return cache.mode;
 }
 
@@ -1527,9 +1888,15 @@ bool fine_sweep_applies(const FineT<T>& f, int nrhs) {
 template <typename T>
 void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s) {
   FineSweepPlan p;
+  FinePipePlan q;
   int maxcnt = 0;
-  const int mode = fine_sweep_cached_plan<T>(f.N, nrhs, p, maxcnt);
+  const int mode = fine_sweep_cached_plan<T>(f.N, nrhs, p, maxcnt, &q);
   if (mode == 0) return;
+  if (mode == 3) {
+    hipLaunchKernelGGL((k_kaczmarz_fine_pipe<T>), dim3((unsigned)(q.ntu * q.ntv), (unsigned)nrhs), dim3(FP_NT), 0, s,
+                       f, q, xin, xout, b);
+    return;
+  }
   const dim3 grid((unsigned)(p.ntu * p.ntv), (unsigned)nrhs);
   if (mode == 2) {
     constexpr int UB = 36 * (int)sizeof(cx<T>) / 16, US = 2 * (int)sizeof(cx<T>) / 16;
@@ -1566,12 +1933,24 @@ void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const c
 #undef FS_ITER
 #undef FS_LAUNCH
 }
-// The plan of form (0: the library's choice, 1, 2) for the plan query of the
-// C ABI; returns the form written, 0 for none.
-int fine_sweep_plan_query(int N, int nrhs, bool fp32, int form, FineSweepPlan& p) {
+// The plan of form (0: the library's choice, 1, 2, 3) for the plan query of
+// the C ABI; returns the form written, 0 for none.  sched = {A, M, W} of the
+// pipelined form, zeros for the others.
+int fine_sweep_plan_query(int N, int nrhs, bool fp32, int form, FineSweepPlan& p, int sched[3]) {
   int maxcnt = 0;
-  if (form == 0)
-    return fp32 ? fine_sweep_cached_plan<float>(N, nrhs, p, maxcnt) : fine_sweep_cached_plan<double>(N, nrhs, p, maxcnt);
+  sched[0] = sched[1] = sched[2] = 0;
+  FinePipePlan q;
+  int got = 0;
+  if (form == 3) got = fine_pipe_choose(N, nrhs, q, p) ? 3 : 0;
+  else if (form == 0)
+    got = fp32 ? fine_sweep_cached_plan<float>(N, nrhs, p, maxcnt, &q)
+               : fine_sweep_cached_plan<double>(N, nrhs, p, maxcnt, &q);
+  if (got == 3) {
+    sched[0] = q.A;
+    sched[1] = q.M;
+    sched[2] = FP_W;
+  }
+  if (form == 0 || form == 3) return got;
   if (form == 1) return (fp32 ? fine_sweep_choose<float>(N, nrhs, p) : fine_sweep_choose<double>(N, nrhs, p)) ? 1 : 0;
   return (fp32 ? fine_sweep_choose_s<float>(N, nrhs, p, maxcnt) : fine_sweep_choose_s<double>(N, nrhs, p, maxcnt)) ? 2 : 0;
 }

@@ -163,10 +163,10 @@ def test_fine_kaczmarz_sweep(bamg, N, nrhs):
     """From 16 right-hand sides the sweeps run on right-hand-side-interleaved
     copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64).  Below
     that, from N = 64 on, one launch per sweep blocked in LDS (80: 8-wide
-    tiles in v, 96: tiles of 32 in u; 512 x 1: the streaming form); 16, 40,
-    256 x 5, 1024 and 1040 x 2 take the colour passes (1024: 32768 sites per
-    colour, 8192 work-groups renumbered per XCD; 1040: 33800 sites, a count
-    of work-groups that is not a multiple of 8)."""
+    tiles in v, 96: tiles of 32 in u; 512 x 1: the streaming form; 256 x 5
+    and 1024: the pipelined march along v); 16, 40 and 1040 x 2 take the
+    colour passes (1040: 33800 sites per colour, a count of work-groups that
+    is not a multiple of 8, and N/2 no multiple of 32)."""
     log(f"kaczmarz fine N={N}")
     U = inputs.gauge_random(N, 7)
     m = 0.02
@@ -181,13 +181,14 @@ def test_fine_kaczmarz_sweep(bamg, N, nrhs):
     assert rel(host(x), ref) < 1e-12
 
 
-@pytest.mark.parametrize("N", [40, 64, 96, 256, 512])
+@pytest.mark.parametrize("N", [40, 64, 96, 256, 512, 1024])
 @pytest.mark.parametrize("prec", [0, 3])
 def test_fine_sweep_batch_gives_the_same_bits(bamg, prec, N):
     """20 right-hand sides take the interleaved sweep; one or three of them
-    alone take the colour passes (N = 40; FP64 512^2 x 3) or a sweep blocked
-    in LDS (from N = 64; the streaming form for 256^2 x 3, 512^2 x 1 and FP32
-    512^2 x 3): the same bits (each lane adds the slot terms in
+    alone take the colour passes (N = 40) or a sweep blocked in LDS (from
+    N = 64; the streaming form for 256^2 x 3, 512^2 x 1 and FP32 512^2 x 3 and
+    1024^2 x 1, the pipelined march for FP64 512^2 x 3 and 1024^2, FP32
+    1024^2 x 3): the same bits (each lane adds the slot terms in
     the butterfly's order; the blocked sweeps project every site a tile depends
     on with the values the colour passes give it)."""
     R = 20
