@@ -599,6 +599,19 @@ def coarse_site_bytes(s_op, s_vec):
     return 7 * 256 * s_op + 256 * s_vec + 16 * s_vec + 2 * 7 * 16 * s_vec
 
 
+def coarse_pair_wg_bytes(s_op, s_vec):
+    """Bytes one work-group of the fused colour pair reads and writes: the
+    rows, Kinv and b of its three projected sites (t1, t2, s), x on the 15
+    sites of their supports, and 8 sites written."""
+    return 3 * (7 * 256 * s_op + 256 * s_vec + 16 * s_vec) + 15 * 16 * s_vec + 8 * 16 * s_vec
+
+
+def coarse_pairs_used(inf):
+    """Whether the library runs a level's single-RHS sweep as fused colour
+    pairs (coarse.hip: the 8-colouring on extents that are multiples of 8)."""
+    return inf["colours"] == 8 and inf["ex"] % 8 == 0 and inf["ey"] % 8 == 0
+
+
 VEC_BYTES = {"fp64": 16, "mixed_fp32": 8, "mixed_fp16": 8, "mixed_bf16": 8}
 OP_BYTES = {"fp64": 16, "mixed_fp32": 8, "mixed_fp16": 4, "mixed_bf16": 4}
 
@@ -690,17 +703,27 @@ def roofline(bamg, torch, h, prec, c32=0, sweeps=8):
                   fine_sweep_alg_bytes(N, sv) / 16, nsite * fine_site_bytes(sv), t, fbasis + ", 1/16 per colour pass")
         out.append((e, t * 16 * sweeps))
     L = bamg.bamg_n_levels(h)
-    if L > 2:  # coarse pass, level 1
+    if L > 2:  # coarse smoother, level 1
         inf = bamg.bamg_level_info(h, 1)
         ns, ncol = inf["ex"] * inf["ey"], inf["colours"]
         xb = torch.zeros(inf["n"], dtype=dt, device="cuda:0")
         bb = torch.ones(inf["n"], dtype=dt, device="cuda:0")
-        t = time_launches(lambda: bamg.bamg_level_op(h, 1, sweep, bb, xb, 1), 50, ncol, torch)
-        e = _roof(f"k_kaczmarz_coarse<{tname},{sname}> (level 1, {ns // ncol} sites per launch)", "coarse",
-                  prec, ns // ncol * coarse_site_alg_bytes(OP_BYTES[prec]),
-                  ns // ncol * coarse_site_bytes(OP_BYTES[prec], sv), t,
-                  f"the operator rows of the colour's sites: 7 x 256 entries of {OP_BYTES[prec]} B per site")
-        out.append((e, t * ncol * sweeps))
+        so = OP_BYTES[prec]
+        if coarse_pairs_used(inf):
+            # two colours per launch: ncol / 2 launches per sweep
+            per = ns // ncol
+            t = time_launches(lambda: bamg.bamg_level_op(h, 1, sweep, bb, xb, 1), 50, ncol // 2, torch)
+            e = _roof(f"k_kaczmarz_coarse_pair<{tname},{sname}> (level 1, colours c and c + 1, 2 x {per} sites "
+                      f"per launch)", "coarse_pair", prec, 2 * per * coarse_site_alg_bytes(so),
+                      per * coarse_pair_wg_bytes(so, sv), t,
+                      f"the operator rows of the two colours' sites: 7 x 256 entries of {so} B per site")
+            out.append((e, t * (ncol // 2) * sweeps))
+        else:
+            t = time_launches(lambda: bamg.bamg_level_op(h, 1, sweep, bb, xb, 1), 50, ncol, torch)
+            e = _roof(f"k_kaczmarz_coarse<{tname},{sname}> (level 1, {ns // ncol} sites per launch)", "coarse",
+                      prec, ns // ncol * coarse_site_alg_bytes(so), ns // ncol * coarse_site_bytes(so, sv), t,
+                      f"the operator rows of the colour's sites: 7 x 256 entries of {so} B per site")
+            out.append((e, t * ncol * sweeps))
     if L > 1:  # coarsest product
         inf = bamg.bamg_level_info(h, L - 1)
         n = inf["n"]

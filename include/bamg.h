@@ -193,12 +193,20 @@ int bamg_eo_reconstruct(bamg_hierarchy *h, const void *b, const void *xe, void *
  *         blocks of op 4 in FP32 (block product, then the reduction of its partial
  *         products), else the split-K product with the whole FP32 copy on the
  *         matrix cores and its reduction
+ *   op 13 BAMG_OP_SWEEP_COLOURS: as op 1, but as one launch per colour (Sec. 3.1
+ *         in its plain form), whatever the size: the reference for the fused
+ *         forms that op 1 runs where they apply (level 0: a sweep blocked in LDS,
+ *         streaming or pipelined; coarse levels: two colours per launch), which
+ *         give the same bits
+ *   op 14 BAMG_OP_SWEEP_COLOURS_F32: op 13 for op 11 (complex64 in and out,
+ *         mixed hierarchies; the colour passes on the vector units for any nrhs)
  * Ops 4 and 12 require in and out not to alias.
  * Level 0 is the fine reduced system (A_0 = Dhat). */
 enum { BAMG_OP_APPLY = 0, BAMG_OP_SWEEP = 1, BAMG_OP_RESTRICT = 2, BAMG_OP_PROLONG = 3,
        BAMG_OP_COARSEST = 4, BAMG_OP_CYCLE = 5, BAMG_OP_RESIDUAL = 6,
        BAMG_OP_APPLY_MIXED = 7, BAMG_OP_SWEEP_MIXED = 8, BAMG_OP_CYCLE_MIXED = 9,
-       BAMG_OP_APPLY_F32 = 10, BAMG_OP_SWEEP_F32 = 11, BAMG_OP_COARSEST_F32 = 12 };
+       BAMG_OP_APPLY_F32 = 10, BAMG_OP_SWEEP_F32 = 11, BAMG_OP_COARSEST_F32 = 12,
+       BAMG_OP_SWEEP_COLOURS = 13, BAMG_OP_SWEEP_COLOURS_F32 = 14 };
 int bamg_level_op(bamg_hierarchy *h, int32_t level, int32_t op, const void *in, void *out, int32_t nrhs);
 
 /* Pieces of the bootstrap multigrid eigensolver (Sec. 3.4, Theorem 1 of Sec. 3.5;

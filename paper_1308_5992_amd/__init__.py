@@ -23,6 +23,7 @@ BAMG_FP64, BAMG_MIXED_FP16, BAMG_MIXED_BF16, BAMG_MIXED_FP32 = 0, 1, 2, 3
 OP_APPLY, OP_SWEEP, OP_RESTRICT, OP_PROLONG, OP_COARSEST, OP_CYCLE, OP_RESIDUAL = range(7)
 OP_APPLY_MIXED, OP_SWEEP_MIXED, OP_CYCLE_MIXED = 7, 8, 9
 OP_APPLY_F32, OP_SWEEP_F32, OP_COARSEST_F32 = 10, 11, 12
+OP_SWEEP_COLOURS, OP_SWEEP_COLOURS_F32 = 13, 14
 BOOT_RITZ, BOOT_SWEEP, BOOT_EIGS, BOOT_FIT = range(4)
 
 EXPORTED = [
@@ -230,8 +231,8 @@ def bamg_eo_reconstruct(h, b, xe, x, nrhs: int = 1):
 
 
 def bamg_level_op(h, level: int, op: int, inp, out, nrhs: int = 1):
-    """Ops 10, 11 and 12 take complex64 tensors, every other op complex128."""
-    c64 = op in (OP_APPLY_F32, OP_SWEEP_F32, OP_COARSEST_F32)
+    """Ops 10, 11, 12 and 14 take complex64 tensors, every other op complex128."""
+    c64 = op in (OP_APPLY_F32, OP_SWEEP_F32, OP_COARSEST_F32, OP_SWEEP_COLOURS_F32)
     _check(lib.bamg_level_op(h, int(level), int(op), _ptr(inp, c64), _ptr(out, c64), int(nrhs)), "bamg_level_op")
 
 

@@ -137,7 +137,8 @@ size_t bamg_footprint_bytes(const bamg_params* p) {
     const size_t ns = (size_t)sh.ext[l].first * sh.ext[l].second;
     const size_t n = ns * (l == 0 ? 2 : 16);
     const bool last = l == L - 1;
-    bytes += (l == 0 ? 4 : 3) * n * cap * zm;  // x, b, r (level 0: and the second x of the blocked sweeps)
+    // x, b, r and, below the coarsest level, the second x of the blocked (level 0) or fused (coarse) sweeps
+    bytes += (last && l > 0 ? 3 : 4) * n * cap * zm;
     if (!mg) break;
     if (kvis(l)) bytes += 5 * n * cap * zm + 4 * cap * z;  // K-cycle visit vectors and coefficients
     bytes += n * (k + ne) * z;  // test vectors
@@ -182,7 +183,7 @@ size_t bamg::hierarchy_slot_extra_bytes(const bamg_params* p, int slots) {
     bytes += (size_t)kcycle_nblocks((size_t)sh.ext[1].first * sh.ext[1].second * 16) * 2 * (S - cap) * sizeof(zd);
   for (int l = 0; l < L; ++l) {
     const size_t n = (size_t)sh.ext[l].first * sh.ext[l].second * (l == 0 ? 2 : 16);
-    bytes += (l == 0 ? 4 : 3) * n * (S - cap) * zm;  // the level work vectors grow to S right-hand sides
+    bytes += (l == L - 1 && l > 0 ? 3 : 4) * n * (S - cap) * zm;  // the level work vectors grow to S right-hand sides
     if (p->cycle == BAMG_CYCLE_K && l >= 1 && l + 1 < L) bytes += (5 * n * zm + 4 * sizeof(zd)) * (S - cap);
     if (l == L - 1 && L > 1)
       bytes += (dense_mm_workspace((int)n, slots) - dense_mm_workspace((int)n, (int)cap)) * sizeof(zd);
@@ -359,6 +360,10 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         if (nrhs > h->cap) h->ensure_cap(nrhs);
         h->smooth(l, xo, xi, nrhs, 1);
         break;
+      case BAMG_OP_SWEEP_COLOURS:
+        if (h->coarsest(l) && h->L() > 1) return fail(BAMG_EINVAL, "no smoother on the coarsest level");
+        h->sweep_colours(l, xo, xi, nrhs);
+        break;
       case BAMG_OP_RESTRICT:
         if (h->coarsest(l)) return fail(BAMG_EINVAL, "no restriction from the coarsest level");
         h->restrict_(l, xi, xo, nrhs);
@@ -402,7 +407,8 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
       case BAMG_OP_SWEEP_MIXED:
       case BAMG_OP_CYCLE_MIXED:
       case BAMG_OP_APPLY_F32:
-      case BAMG_OP_SWEEP_F32: {
+      case BAMG_OP_SWEEP_F32:
+      case BAMG_OP_SWEEP_COLOURS_F32: {
         if (!h->mixed()) return fail(BAMG_EINVAL, "hierarchy is FP64");
         if (op == BAMG_OP_CYCLE_MIXED) {
           if (l != 0) return fail(BAMG_EINVAL, "the mixed cycle starts on level 0");
@@ -410,14 +416,16 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
           h->precondition_mixed(xi, xo, nrhs);
           break;
         }
-        if ((op == BAMG_OP_SWEEP_MIXED || op == BAMG_OP_SWEEP_F32) && h->coarsest(l) && h->L() > 1)
+        if ((op == BAMG_OP_SWEEP_MIXED || op == BAMG_OP_SWEEP_F32 || op == BAMG_OP_SWEEP_COLOURS_F32) &&
+            h->coarsest(l) && h->L() > 1)
           return fail(BAMG_EINVAL, "no smoother on the coarsest level");
         if (l >= 1 && h->coarsest(l)) return fail(BAMG_EINVAL, "the coarsest level has no smoother; its solve is op 12");
         if (op == BAMG_OP_APPLY_F32 && in == out) return fail(BAMG_EINVAL, "in and out must not alias");
         h->ensure_cap(nrhs);
         Level& Lv = h->lv[l];
         const size_t nn = Lv.n * nrhs;
-        const bool f32io = (op == BAMG_OP_APPLY_F32 || op == BAMG_OP_SWEEP_F32);
+        const bool f32io = (op == BAMG_OP_APPLY_F32 || op == BAMG_OP_SWEEP_F32 || op == BAMG_OP_SWEEP_COLOURS_F32);
+        const bool colours = op == BAMG_OP_SWEEP_COLOURS_F32;
         const bool is_apply = (op == BAMG_OP_APPLY_MIXED || op == BAMG_OP_APPLY_F32);
         // complex64 operands are used in place; complex128 ones go through the level's FP32 vectors
         const zf* bi = f32io ? (const zf*)in : Lv.b32;
@@ -429,14 +437,17 @@ int bamg_level_op(bamg_hierarchy* h, int32_t l, int32_t op, const void* in, void
         switch (h->p.precision) {
           case BAMG_MIXED_FP16:
             if (is_apply) h->apply32<hcx>(l, bi, xw, nullptr, nrhs);
+            else if (colours) h->sweep_colours32<hcx>(l, xw, bi, nrhs, false);
             else h->smooth32<hcx>(l, xw, bi, nrhs, 1);
             break;
           case BAMG_MIXED_BF16:
             if (is_apply) h->apply32<bcx>(l, bi, xw, nullptr, nrhs);
+            else if (colours) h->sweep_colours32<bcx>(l, xw, bi, nrhs, false);
             else h->smooth32<bcx>(l, xw, bi, nrhs, 1);
             break;
           default:
             if (is_apply) h->apply32<zf>(l, bi, xw, nullptr, nrhs);
+            else if (colours) h->sweep_colours32<zf>(l, xw, bi, nrhs, false);
             else h->smooth32<zf>(l, xw, bi, nrhs, 1);
             break;
         }

@@ -72,6 +72,20 @@ __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * 
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> cdiv_real(cx<T> a, T s) { return {a.x / s, a.y / s}; }
 
+// Complex product with its contraction fixed: each component is one fused
+// multiply-add on the exactly rounded other product, whatever the compiler
+// would otherwise fuse, so every kernel that evaluates the same product gets
+// the same bits (kernels chosen by problem size must agree).
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_fixed(cx<T> a, cx<T> b) {
+  return cx<T>{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
+}
+// conj(a) b with its contraction fixed
+template <typename T>
+__device__ __forceinline__ cx<T> cjmul_fixed(cx<T> a, cx<T> b) {
+  return cx<T>{fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x))};
+}
+
 // Work-group p of a launch goes to XCD p mod 8 (the chip's 8 XCDs, each with
 // its own L2, take work-groups in turn).  xcd_block renumbers the nb
 // work-groups so that each XCD takes one contiguous range, in order: logical
@@ -189,6 +203,13 @@ void launch_coarse_apply(const CoarseT<T, S>& c, const cx<T>* x, cx<T>* y, const
 template <typename T, typename S>
 void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
                             int nrhs, hipStream_t s);
+// colours c and c + 1 (c even) of the 8-colouring in one launch, out of place
+// (xin and xout must not overlap), bitwise the two colour passes; where
+// coarse_pair_applies
+bool coarse_pair_applies(int ex, int ey, int mode);
+template <typename T, typename S>
+void launch_kaczmarz_coarse_pair(const CoarseT<T, S>& c, int colour, int nsites, const cx<T>* xin, cx<T>* xout,
+                                 const cx<T>* b, int nrhs, hipStream_t s);
 // the same pass on the matrix cores (FP32 arithmetic, one wave per site and 16 RHS)
 template <typename S>
 void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mode, int nsites, zf* x, const zf* b,

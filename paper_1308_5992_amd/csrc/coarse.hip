@@ -116,6 +116,76 @@ __device__ __forceinline__ int coarse_colour_site(int c, int mode, int t, int ex
   return c;
 }
 
+// One thread's share of a site's projection: row i, columns 2q, 2q+1 of each
+// of the NOFF blocks of the block row, the same columns of row i of Kinv, and
+// b_i.  The three steps below are the whole projection; every kernel that
+// projects coarse sites calls them, so they all give the same bits (products
+// with their contraction fixed, sums in a fixed order).
+template <typename T>
+struct CoarseRow {
+  cx<T> Dv[NOFF][2];
+  cx<T> k0, k1, bi;
+};
+
+template <typename T, typename S>
+__device__ __forceinline__ void coarse_row_load(const CoarseT<T, S>& c, int site, int i, int q,
+                                                const cx<T>* __restrict__ b, CoarseRow<T>& w) {
+  const cx<T>* K = c.Kinv + ((size_t)site * 16 + i) * 16 + 2 * q;
+  w.k0 = K[0];
+  w.k1 = K[1];
+  w.bi = b ? b[site * 16 + i] : cx<T>{0, 0};
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    const S* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 2 * q;
+    w.Dv[o][0] = widen<T>(Dr[0]);
+    w.Dv[o][1] = widen<T>(Dr[1]);
+  }
+}
+
+// step 1: rsh[i] = b_i - (A x)_i from the thread's support values xo[o][k]
+// (column 2q + k of offset o); 8-lane row sums by DPP moves
+template <typename T>
+__device__ __forceinline__ void coarse_proj_residual(const CoarseRow<T>& w, const cx<T> (&xo)[NOFF][2], int i, int q,
+                                                     cx<T>* rsh) {
+  cx<T> acc[NOFF];
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) acc[o] = cmul_fixed(w.Dv[o][0], xo[o][0]) + cmul_fixed(w.Dv[o][1], xo[o][1]);
+  cx<T> r = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
+  r = xor_add<1>(r);
+  r = xor_add<2>(r);
+  r = xor_add<4>(r);
+  if (q == 0) rsh[i] = w.bi - r;
+}
+
+// step 2 (after a barrier): alpha_i = sum_{j <= i} Kinv[i][j] r_j, then
+// part[i][col] = conj(D[i][col]) alpha_i for the thread's columns
+template <typename T>
+__device__ __forceinline__ void coarse_proj_alpha(const CoarseRow<T>& w, const cx<T>* rsh, int i, int q,
+                                                  cx<T> (*part)[NOFF * 16 + 1]) {
+  cx<T> al = cmul_fixed(w.k0, rsh[2 * q]) + cmul_fixed(w.k1, rsh[2 * q + 1]);
+  al = xor_add<1>(al);
+  al = xor_add<2>(al);
+  al = xor_add<4>(al);
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    part[i][o * 16 + 2 * q] = cjmul_fixed(w.Dv[o][0], al);
+    part[i][o * 16 + 2 * q + 1] = cjmul_fixed(w.Dv[o][1], al);
+  }
+}
+
+// step 3 (after a barrier): the update of support column col (offset
+// col / 16, component col % 16), the sum over the 16 rows
+template <typename T>
+__device__ __forceinline__ cx<T> coarse_proj_colsum(const cx<T> (*part)[NOFF * 16 + 1], int col) {
+  cx<T> s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+  for (int rr = 0; rr < 16; rr += 2) {
+    s0 = s0 + part[rr][col];
+    s1 = s1 + part[rr + 1][col];
+  }
+  return s0 + s1;
+}
+
 template <typename T, typename S>
 __global__ __launch_bounds__(128) void k_kaczmarz_coarse(CoarseT<T, S> c, int colour, int mode, cx<T>* __restrict__ x,
                                                          const cx<T>* __restrict__ b) {
@@ -131,25 +201,17 @@ __global__ __launch_bounds__(128) void k_kaczmarz_coarse(CoarseT<T, S> c, int co
   const int ax = site % c.ex, ay = site / c.ex;
   const size_t n = (size_t)ns * 16;
   C* xv = x + blockIdx.y * n;
-  // smoother row and right-hand side: independent of everything else
-  const C* K = c.Kinv + ((size_t)site * 16 + i) * 16 + 2 * q;
-  const C k0 = K[0], k1 = K[1];
-  const C bi = b ? b[blockIdx.y * n + site * 16 + i] : C{0, 0};
+  CoarseRow<T> w;
+  coarse_row_load(c, site, i, q, b ? b + blockIdx.y * n : nullptr, w);
   int nb[NOFF];
-  C Dv[NOFF][2], xo[NOFF][2];
+  C xo[NOFF][2];
 #pragma unroll
   for (int o = 0; o < NOFF; ++o) {
     nb[o] = cwrap(ay + dyo[o], c.ey) * c.ex + cwrap(ax + dxo[o], c.ex);
-    const S* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 2 * q;
-    Dv[o][0] = widen<T>(Dr[0]);
-    Dv[o][1] = widen<T>(Dr[1]);
     const C* xp = xv + nb[o] * 16 + 2 * q;
     xo[o][0] = xp[0];
     xo[o][1] = xp[1];
   }
-  C acc[NOFF];
-#pragma unroll
-  for (int o = 0; o < NOFF; ++o) acc[o] = Dv[o][0] * xo[o][0] + Dv[o][1] * xo[o][1];
   if (i == 0) {
 #pragma unroll
     for (int o = 0; o < NOFF; ++o) {
@@ -157,38 +219,17 @@ __global__ __launch_bounds__(128) void k_kaczmarz_coarse(CoarseT<T, S> c, int co
       xsh[o * 16 + 2 * q + 1] = xo[o][1];
     }
   }
-  C r = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
-  r = xor_add<1>(r);
-  r = xor_add<2>(r);
-  r = xor_add<4>(r);
-  if (q == 0) rsh[i] = bi - r;
+  coarse_proj_residual(w, xo, i, q, rsh);
   __syncthreads();
-  // alpha_i = sum_{j <= i} Kinv[i][j] r_j
-  C al = k0 * rsh[2 * q] + k1 * rsh[2 * q + 1];
-  al = xor_add<1>(al);
-  al = xor_add<2>(al);
-  al = xor_add<4>(al);
-  // x_col += sum_i conj(D[i][col]) alpha_i; thread (i < 14, q) finishes
-  // column j = 2q + (i & 1) of offset o = i / 2 from the value it already holds
-#pragma unroll
-  for (int o = 0; o < NOFF; ++o) {
-    part[i][o * 16 + 2 * q] = cjmul(Dv[o][0], al);
-    part[i][o * 16 + 2 * q + 1] = cjmul(Dv[o][1], al);
-  }
+  coarse_proj_alpha(w, rsh, i, q, part);
   __syncthreads();
+  // thread (i < 14, q) finishes column 2q + (i & 1) of offset i / 2
   if (i < 2 * NOFF) {
     const int o = i >> 1, h = i & 1, col = o * 16 + 2 * q + h;
-    C s0 = {0, 0}, s1 = {0, 0};
-#pragma unroll
-    for (int rr = 0; rr < 16; rr += 2) {
-      s0 = s0 + part[rr][col];
-      s1 = s1 + part[rr + 1][col];
-    }
     // offsets packed as 4-bit fields (+1): (0,0) (+1,0) (-1,0) (0,+1) (0,-1) (+1,+1) (-1,-1)
     const int dx = (int)((0x0211021u >> (4 * o)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * o)) & 15u) - 1;
     const int nbo = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
-    const C xold = xsh[col];
-    xv[nbo * 16 + 2 * q + h] = xold + (s0 + s1);
+    xv[nbo * 16 + 2 * q + h] = xsh[col] + coarse_proj_colsum<T>(part, col);
   }
 }
 
@@ -196,6 +237,111 @@ template <typename T, typename S>
 void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int nsites, cx<T>* x, const cx<T>* b,
                             int nrhs, hipStream_t s) {
   hipLaunchKernelGGL((k_kaczmarz_coarse<T, S>), dim3(nsites, nrhs), dim3(128), 0, s, c, colour, mode, x, b);
+}
+
+// ---------------------------------------------------------------------------
+// Two colour passes in one launch (8-colouring, colours c and c + 1, c even).
+// With the 7-offset stencil, the support of a site s of colour c + 1 meets
+// the supports of exactly two sites of colour c, t1 = s + (-1, 0) and
+// t2 = s + (2, 1) (the colour differences of the 19 displacements between
+// overlapping supports are all distinct, and (ax - 3 ay) mod 8 falls by one
+// only for these two).  So the values on the support of s after both passes
+// follow from x on the 15 sites of the supports of t1, t2 and s alone: a
+// work-group per site s projects t1 and t2 (disjoint supports, together),
+// then s, all in LDS, with the three steps of the colour pass (the same
+// bits as two colour passes).  Out of place: every work-group reads xin and
+// writes xout, the support of s and the site s + (-1, 1), the one site of
+// the support of t1 that no colour-(c+1) support holds; these sets tile the
+// lattice, so each site is written once (a CPU test checks the claims on
+// tori from 8 x 8).  Sites t1 and t2 are projected twice, by the two
+// work-groups whose s they neighbour.  256 threads: group 0 projects t1 then
+// s, group 1 t2.
+// ---------------------------------------------------------------------------
+// the 15 sites of a work-group, displacements from s: 0-6 the support of s in
+// offset order, 7-9 the rest of the support of t1, 10-14 that of t2
+__constant__ int PR_DX[15] = {0, 1, -1, 0, 0, 1, -1, -2, -1, -2, 2, 3, 2, 2, 3};
+__constant__ int PR_DY[15] = {0, 0, 0, 1, -1, 1, -1, 0, 1, -1, 1, 1, 2, 0, 2};
+// the support of t1 (t2) in offset order, as local site indices
+constexpr int PR_T1 = 2, PR_T2 = 10;
+__device__ __forceinline__ int pair_support(int g, int o) {
+  constexpr unsigned LT1 = 0x9368702u, LT2 = 0x1EDC5BAu;  // nibble o: local index of offset o
+  return (int)(((g ? LT2 : LT1) >> (4 * o)) & 15u);
+}
+
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_kaczmarz_coarse_pair(CoarseT<T, S> c, int colour,
+                                                              const cx<T>* __restrict__ xin, cx<T>* __restrict__ xout,
+                                                              const cx<T>* __restrict__ b) {
+  using C = cx<T>;
+  __shared__ C part[2][16][NOFF * 16 + 1];
+  __shared__ C rsh[2][16];
+  __shared__ C X[15 * 16];
+  const int tid = threadIdx.x, g = tid >> 7, i = (tid >> 3) & 15, q = tid & 7;
+  const int ex = c.ex, ey = c.ey;
+  const int s = coarse_colour_site(colour + 1, 8, blockIdx.x, ex);
+  const int ax = s % ex, ay = s / ex;
+  const size_t n = (size_t)ex * ey * 16;
+  const C* xr = xin + blockIdx.y * n;
+  C* xw = xout + blockIdx.y * n;
+  const C* bv = b ? b + blockIdx.y * n : nullptr;
+  auto at = [&](int k) { return cwrap(ay + PR_DY[k], ey) * ex + cwrap(ax + PR_DX[k], ex); };
+  CoarseRow<T> wt, ws;
+  coarse_row_load(c, at(g ? PR_T2 : PR_T1), i, q, bv, wt);
+  if (g == 0) coarse_row_load(c, s, i, q, bv, ws);
+  for (int e = tid; e < 15 * 16; e += 256) X[e] = xr[at(e >> 4) * 16 + (e & 15)];
+  __syncthreads();
+  // colour c: t1 (group 0) and t2 (group 1)
+  {
+    C xo[NOFF][2];
+#pragma unroll
+    for (int o = 0; o < NOFF; ++o) {
+      const int e = pair_support(g, o) * 16 + 2 * q;
+      xo[o][0] = X[e];
+      xo[o][1] = X[e + 1];
+    }
+    coarse_proj_residual(wt, xo, i, q, rsh[g]);
+    __syncthreads();
+    coarse_proj_alpha(wt, rsh[g], i, q, part[g]);
+    __syncthreads();
+    if (i < 2 * NOFF) {
+      const int o = i >> 1, h = i & 1, col = o * 16 + 2 * q + h;
+      const int e = pair_support(g, o) * 16 + 2 * q + h;
+      X[e] = X[e] + coarse_proj_colsum<T>(part[g], col);
+    }
+    __syncthreads();
+  }
+  // colour c + 1: s (group 0; group 1 keeps the barriers)
+  {
+    C xo[NOFF][2];
+#pragma unroll
+    for (int o = 0; o < NOFF; ++o) {
+      xo[o][0] = X[o * 16 + 2 * q];
+      xo[o][1] = X[o * 16 + 2 * q + 1];
+    }
+    if (g == 0) coarse_proj_residual(ws, xo, i, q, rsh[0]);
+    __syncthreads();
+    if (g == 0) coarse_proj_alpha(ws, rsh[0], i, q, part[0]);
+    __syncthreads();
+    if (g == 0 && i < 2 * NOFF) {
+      const int o = i >> 1, h = i & 1, col = o * 16 + 2 * q + h;
+      const int e = o * 16 + 2 * q + h;
+      X[e] = X[e] + coarse_proj_colsum<T>(part[0], col);
+    }
+    __syncthreads();
+  }
+  // the support of s (local 0-6) and s + (-1, 1) (local 8)
+  if (tid < 128) {
+    const int k = tid >> 4, loc = k < 7 ? k : 8, e = tid & 15;
+    xw[at(loc) * 16 + e] = X[loc * 16 + e];
+  }
+}
+
+bool coarse_pair_applies(int ex, int ey, int mode) { return mode == 8 && ex >= 8 && ey >= 8 && ex % 8 == 0 && ey % 8 == 0; }
+
+template <typename T, typename S>
+void launch_kaczmarz_coarse_pair(const CoarseT<T, S>& c, int colour, int nsites, const cx<T>* xin, cx<T>* xout,
+                                 const cx<T>* b, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL((k_kaczmarz_coarse_pair<T, S>), dim3(nsites, nrhs), dim3(256), 0, s, c, colour, xin, xout, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -641,7 +787,9 @@ void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T
                                           hipStream_t);                                                 \
   template void launch_kaczmarz_coarse<T, S>(const CoarseT<T, S>&, int, int, int, cx<T>*, const cx<T>*, \
                                              int, hipStream_t);                                         \
-  template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);
+  template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);                  \
+  template void launch_kaczmarz_coarse_pair<T, S>(const CoarseT<T, S>&, int, int, const cx<T>*, cx<T>*, \
+                                                  const cx<T>*, int, hipStream_t);
 BAMG_COARSE_INST(double, zd)
 BAMG_COARSE_INST(float, zf)
 BAMG_COARSE_INST(float, hcx)

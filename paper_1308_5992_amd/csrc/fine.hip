@@ -25,22 +25,14 @@ __device__ __forceinline__ int hidx(int x, int y, int N, int NH) {
   return wrapn(y, N) * NH + (wrapn(x, N) >> 1);
 }
 
-// accumulate the hop in direction d (0:+x 1:-x 2:+y 3:-y) of spinor (a, b) with link u
-// (u already conjugated for backward hops) into (o0, o1), without the factor 1/2
-// Complex product with its contraction fixed: each component is one fused
-// multiply-add on the exactly rounded other product, whatever the compiler
-// would otherwise fuse, so every kernel that evaluates a hop gets the same
-// bits (the operator kernels are chosen by problem size and must agree).
-template <typename T>
-__device__ __forceinline__ cx<T> cmul_fixed(cx<T> a, cx<T> b) {
-  return cx<T>{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
-}
 // x - k a with one fused multiply-add per component
 template <typename T>
 __device__ __forceinline__ cx<T> sub_scaled(cx<T> x, T k, cx<T> a) {
   return cx<T>{fma(-k, a.x, x.x), fma(-k, a.y, x.y)};
 }
 
+// accumulate the hop in direction d (0:+x 1:-x 2:+y 3:-y) of spinor (a, b) with link u
+// (u already conjugated for backward hops) into (o0, o1), without the factor 1/2
 template <typename T>
 __device__ __forceinline__ void hop_acc(int d, cx<T> u, cx<T> a, cx<T> b, cx<T>& o0, cx<T>& o1) {
   cx<T> h;
@@ -711,11 +703,6 @@ __device__ __forceinline__ void fine_colour_site(int c, int t, int N, int& x, in
   x = 8 * k + ((2 * a - y) & 7);
 }
 
-// conj(a) b with its contraction fixed (see cmul_fixed)
-template <typename T>
-__device__ __forceinline__ cx<T> cjmul_fixed(cx<T> a, cx<T> b) {
-  return cx<T>{fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -(a.y * b.x))};
-}
 template <typename T>
 __device__ __forceinline__ T norm2_fixed(cx<T> a) {
   return fma(a.x, a.x, a.y * a.y);

@@ -107,6 +107,10 @@ struct Level {
   zd* kw = nullptr;
   zf* kw32 = nullptr;
   zd* kcoef = nullptr;
+  // second copy of x for the fused colour-pair passes (non-coarsest coarse
+  // levels), cap right-hand sides, FP64 and (mixed modes) FP32
+  zd* xs = nullptr;
+  zf* xs32 = nullptr;
   Coarse coarse() const {
     Coarse c;
     c.ex = ex; c.ey = ey; c.D = D; c.Kinv = Kinv;
@@ -247,7 +251,7 @@ struct bamg_hierarchy {
       dfree(L.D); dfree(L.Kinv); dfree(L.Ainv); dfree(L.Ap); dfree(L.Ablk); dfree(L.Apart); dfree(L.P);
       dfree(L.x); dfree(L.b); dfree(L.r); dfree(L.tv);
       dfree(L.P32); dfree(L.Dst); dfree(L.Kinv32); dfree(L.Ainv32); dfree(L.Ap32); dfree(L.x32); dfree(L.b32); dfree(L.r32);
-      dfree(L.kw); dfree(L.kw32); dfree(L.kcoef);
+      dfree(L.kw); dfree(L.kw32); dfree(L.kcoef); dfree(L.xs); dfree(L.xs32);
     }
     dfree(mmwork);
     dfree(kpart);
@@ -298,7 +302,9 @@ struct bamg_hierarchy {
       Level& Lv = lv[l];
       dfree(Lv.x); dfree(Lv.b); dfree(Lv.r);
       dfree(Lv.x32); dfree(Lv.b32); dfree(Lv.r32);
-      dfree(Lv.kw); dfree(Lv.kw32); dfree(Lv.kcoef);
+      dfree(Lv.kw); dfree(Lv.kw32); dfree(Lv.kcoef); dfree(Lv.xs); dfree(Lv.xs32);
+      Lv.xs = nullptr;
+      Lv.xs32 = nullptr;
       Lv.x32 = Lv.b32 = Lv.r32 = nullptr;
       Lv.kw = nullptr;
       Lv.kw32 = nullptr;
@@ -310,6 +316,10 @@ struct bamg_hierarchy {
         Lv.x32 = dalloc<zf>(Lv.n * nrhs);
         Lv.b32 = dalloc<zf>(Lv.n * nrhs);
         Lv.r32 = dalloc<zf>(Lv.n * nrhs);
+      }
+      if (l >= 1 && !coarsest(l)) {
+        Lv.xs = dalloc<zd>(Lv.n * nrhs);
+        if (mixed()) Lv.xs32 = dalloc<zf>(Lv.n * nrhs);
       }
       if (kvisited(l)) {
         Lv.kw = dalloc<zd>(5 * Lv.n * nrhs);
@@ -331,11 +341,31 @@ struct bamg_hierarchy {
   void sweep(int l, zd* x, const zd* b, int nrhs) {
     Level& Lv = lv[l];
     if (l == 0 && fine_sweeps(f, x, xsw, b, nrhs, 1)) return;
+    if (l >= 1 && coarse_pairs(Lv.coarse(), Lv, x, Lv.xs, b, nrhs)) return;
+    sweep_colours(l, x, b, nrhs);
+  }
+  // the sweep as one launch per colour (the reference form of the sweep)
+  void sweep_colours(int l, zd* x, const zd* b, int nrhs) {
+    Level& Lv = lv[l];
     for (int c = 0; c < Lv.ncol; ++c) {
       if (l == 0) launch_kaczmarz_fine(f, c, Lv.per_colour, x, b, nrhs, s);
       else launch_kaczmarz_coarse(Lv.coarse(), c, Lv.cmode, Lv.per_colour, x, b, nrhs, s);
     }
     check_launch();
+  }
+  // a coarse sweep as fused colour pairs, alternating between x and xs (an
+  // even number of launches, so the last writes x); false if they do not apply
+  template <typename T, typename S>
+  bool coarse_pairs(const CoarseT<T, S>& c, const Level& Lv, cx<T>* x, cx<T>* xs, const cx<T>* b, int nrhs) {
+    if (!xs || nrhs > cap || Lv.ncol != 8 || !coarse_pair_applies(Lv.ex, Lv.ey, Lv.cmode)) return false;
+    cx<T>* a = x;
+    cx<T>* o = xs;
+    for (int col = 0; col < Lv.ncol; col += 2) {
+      launch_kaczmarz_coarse_pair(c, col, Lv.per_colour, a, o, b, nrhs, s);
+      std::swap(a, o);
+    }
+    check_launch();
+    return true;
   }
   // count level-0 sweeps blocked in LDS, alternating between x and xs so that
   // the last one writes x (an odd count starts from a copy of x in xs); false
@@ -462,6 +492,13 @@ struct bamg_hierarchy {
     Level& Lv = lv[l];
     if (l == 0 && fine_sweeps(f32, x, xsw32, b, nrhs, 1)) return;
     const bool mr = force_mr || nrhs >= MR_MIN;
+    if (l >= 1 && !mr && coarse_pairs(coarse32<S>(l), Lv, x, Lv.xs32, b, nrhs)) return;
+    sweep_colours32<S>(l, x, b, nrhs, mr);
+  }
+  // one launch per colour (colour passes on the VALU unless mr)
+  template <typename S>
+  void sweep_colours32(int l, zf* x, const zf* b, int nrhs, bool mr) {
+    Level& Lv = lv[l];
     for (int c = 0; c < Lv.ncol; ++c) {
       if (l == 0) {
         launch_kaczmarz_fine(f32, c, Lv.per_colour, x, b, nrhs, s);

@@ -209,6 +209,27 @@ def test_fine_sweep_batch_gives_the_same_bits(bamg, prec, N):
         assert torch.equal(x1, X[r0:r1]), (r0, r1)
 
 
+@pytest.mark.parametrize("N,prec", [(128, 0), (256, 3), (512, 0), (1024, 0), (1024, 3), (4096, 0)])
+def test_fine_sweep_forms_give_the_colour_pass_bits(bamg, N, prec):
+    """One sweep in the library's form for the size (128^2, FP32 256^2: blocked
+    in LDS; 512^2: streaming; 1024^2 and 4096^2: pipelined) against op 13 / 14,
+    the 16 colour passes: the same bits."""
+    log(f"sweep forms vs colour passes N={N} prec={prec}")
+    U = inputs.gauge_random(N, 31)
+    h = make_h(bamg, U, 0.02, n_levels=1, precision=prec)
+    dt = torch.complex64 if prec else torch.complex128
+    op, opc = (bamg.OP_SWEEP_F32, bamg.OP_SWEEP_COLOURS_F32) if prec else (bamg.OP_SWEEP, bamg.OP_SWEEP_COLOURS)
+    x1 = torch.from_numpy(inputs.gaussian(N * N, 32)).to("cuda:0").to(dt)
+    b = torch.from_numpy(inputs.gaussian(N * N, 33)).to("cuda:0").to(dt)
+    x2 = x1.clone()
+    bamg.bamg_level_op(h, 0, op, b, x1, 1)
+    bamg.bamg_level_op(h, 0, opc, b, x2, 1)
+    assert torch.equal(x1, x2)
+    bamg.bamg_free(h)
+    del x1, x2, b
+    torch.cuda.empty_cache()
+
+
 def test_philox_test_vectors(bamg):
     N, k, seed = 32, 8, 0x1234_5678_9ABC
     out = torch.zeros(k, N * N, dtype=torch.complex128, device="cuda:0")
@@ -293,6 +314,23 @@ def test_coarse_kaczmarz_sweep(bamg, imported, nrhs):
     # block form tril(G)^-1 of the 16 sequential projections: rounding
     # differences scale with cond(tril(G)); random P keeps it moderate
     assert rel(host(x), ref) < 1e-11
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_coarse_fused_pairs_give_the_colour_pass_bits(bamg, imported, nrhs):
+    """Level 1 (8 x 16 sites, 8 colours): op 1 runs two colours per launch
+    (the fused pairs, out of place between x and a second copy), op 13 one
+    launch per colour: the same bits, over two sweeps."""
+    N, U, m, h, o = imported
+    n = bamg.bamg_level_info(h, 1)["n"]
+    x0 = inputs.gaussian((nrhs, n), 74)
+    b = dev(inputs.gaussian((nrhs, n), 75))
+    x1, x2 = dev(x0), dev(x0)
+    for _ in range(2):
+        bamg.bamg_level_op(h, 1, bamg.OP_SWEEP, b, x1, nrhs)
+        bamg.bamg_level_op(h, 1, bamg.OP_SWEEP_COLOURS, b, x2, nrhs)
+    assert torch.equal(x1, x2)
+    assert not torch.equal(x1, dev(x0))
 
 
 @pytest.mark.parametrize("nrhs", [1, 2, 3, 9, 17, 37, 70])
@@ -533,6 +571,21 @@ def test_f32_operand_ops_match_mixed_ops(bamg, imported_mixed, l, nrhs):
     xs32 = torch.from_numpy(x).to("cuda:0")
     bamg.bamg_level_op(h, l, bamg.OP_SWEEP_F32, torch.from_numpy(b).to("cuda:0"), xs32, nrhs)
     assert np.array_equal(host(xs64).astype(np.complex64), xs32.cpu().numpy())
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_mixed_coarse_fused_pairs_give_the_colour_pass_bits(bamg, imported_mixed, nrhs):
+    """FP32 sweeps on level 1 with the operator in the storage type: fused
+    pairs (op 11) against one launch per colour (op 14)."""
+    name, tol, N, U, m, h, o = imported_mixed
+    n = bamg.bamg_level_info(h, 1)["n"]
+    x1 = torch.from_numpy(inputs.gaussian((nrhs, n), 76).astype(np.complex64)).to("cuda:0")
+    b = torch.from_numpy(inputs.gaussian((nrhs, n), 77).astype(np.complex64)).to("cuda:0")
+    x2 = x1.clone()
+    for _ in range(2):
+        bamg.bamg_level_op(h, 1, bamg.OP_SWEEP_F32, b, x1, nrhs)
+        bamg.bamg_level_op(h, 1, bamg.OP_SWEEP_COLOURS_F32, b, x2, nrhs)
+    assert torch.equal(x1, x2)
 
 
 U32 = 2.0 ** -24  # unit roundoff of FP32
