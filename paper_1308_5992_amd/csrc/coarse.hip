@@ -258,9 +258,12 @@ void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int ns
 // s, group 1 t2.
 // ---------------------------------------------------------------------------
 // the 15 sites of a work-group, displacements from s: 0-6 the support of s in
-// offset order, 7-9 the rest of the support of t1, 10-14 that of t2
-__constant__ int PR_DX[15] = {0, 1, -1, 0, 0, 1, -1, -2, -1, -2, 2, 3, 2, 2, 3};
-__constant__ int PR_DY[15] = {0, 0, 0, 1, -1, 1, -1, 0, 1, -1, 1, 1, 2, 0, 2};
+// offset order, 7-9 the rest of the support of t1 ((-2, 0), (-1, 1), (-2, -1)),
+// 10-14 that of t2 ((2, 1), (3, 1), (2, 2), (2, 0), (3, 2)); nibble k holds
+// dx + 2 and dy + 1 of site k (immediates, not a table in memory: the
+// addresses of the first loads and the last stores need no load of their own)
+__device__ __forceinline__ int pair_dx(int k) { return (int)((0x544540101322132ull >> (4 * k)) & 15ull) - 2; }
+__device__ __forceinline__ int pair_dy(int k) { return (int)((0x313220210202111ull >> (4 * k)) & 15ull) - 1; }
 // the support of t1 (t2) in offset order, as local site indices
 constexpr int PR_T1 = 2, PR_T2 = 10;
 __device__ __forceinline__ int pair_support(int g, int o) {
@@ -278,13 +281,13 @@ __global__ __launch_bounds__(256) void k_kaczmarz_coarse_pair(CoarseT<T, S> c, i
   __shared__ C X[15 * 16];
   const int tid = threadIdx.x, g = tid >> 7, i = (tid >> 3) & 15, q = tid & 7;
   const int ex = c.ex, ey = c.ey;
-  const int s = coarse_colour_site(colour + 1, 8, blockIdx.x, ex);
+  const int s = coarse_colour_site(colour + 1, 8, (int)xcd_block(blockIdx.x, gridDim.x), ex);
   const int ax = s % ex, ay = s / ex;
   const size_t n = (size_t)ex * ey * 16;
   const C* xr = xin + blockIdx.y * n;
   C* xw = xout + blockIdx.y * n;
   const C* bv = b ? b + blockIdx.y * n : nullptr;
-  auto at = [&](int k) { return cwrap(ay + PR_DY[k], ey) * ex + cwrap(ax + PR_DX[k], ex); };
+  auto at = [&](int k) { return cwrap(ay + pair_dy(k), ey) * ex + cwrap(ax + pair_dx(k), ex); };
   CoarseRow<T> wt, ws;
   coarse_row_load(c, at(g ? PR_T2 : PR_T1), i, q, bv, wt);
   if (g == 0) coarse_row_load(c, s, i, q, bv, ws);

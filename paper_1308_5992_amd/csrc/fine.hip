@@ -1789,7 +1789,7 @@ static bool fine_pipe_plan(int N, int Tv, FinePipePlan& q, FineSweepPlan& p) {
       }
   auto floor4 = [](int a) { return a >= 0 ? a / 4 : -((-a + 3) / 4); };
   for (int A = -64; A <= 64; ++A) {
-    bool ok = true;
+    bool ok = 4 + A - p.j0 >= 0;  // the kernel's columns of macro-step m >= 1 are 4m + A - j0 + (0..3) >= 0
     for (int cj = 0; cj < p.Rv && ok; ++cj) {
       const int j = cj + p.j0, sl = std::max(0, floor4(j - A));
       if (first[cj] < (1 << 30) && sl > first[cj]) ok = false;
