@@ -620,15 +620,15 @@ OP_BYTES = {"fp64": 16, "mixed_fp32": 8, "mixed_fp16": 4, "mixed_bf16": 4}
 # divided by what the counter reads per KiB moved by a plain 256 MiB copy
 # kernel in the same run.  Valid only for the kernel source they were taken on
 # (sha256 of the kernel's file); any change to it makes the traffic null.
-COPY_SCALE = {"fetch_per_kib": 131091.3 / 262144.0, "write_per_kib": 262144.0 / 262144.0}
+COPY_SCALE = {"fetch_per_kib": 131090.8 / 262144.0, "write_per_kib": 262144.0 / 262144.0}
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine_sweep", "mixed_fp16"): {"src": "fine.hip",
-                                   "sha256": "700519d8cfbbc4e227dd6e109821949520989d291ad741fbf7c4fd135bfd8024",
-                                   "fetch_kib": 10153.0, "write_kib": 640.0, **COPY_SCALE},
-    ("coarse", "mixed_fp16"): {"src": "coarse.hip",
-                               "sha256": "9b18863221383c8e83eab8527f10b7b85196a3e1ffc57d35caba01889fbe3c73",
-                               "fetch_kib": 1312.5, "write_kib": 224.0, **COPY_SCALE},
+                                   "sha256": "a51828fe6252e1b041604e7d30858a4ac2a1e43ee1cdf54e1dfcb0128a3fdb30",
+                                   "fetch_kib": 10149.5, "write_kib": 640.0, **COPY_SCALE},
+    ("coarse_pair", "mixed_fp16"): {"src": "coarse.hip",
+                                    "sha256": "1af7dc7ba867ba801ea8bd5130bd51a0cafa3d004af88ac32aa1f458c8817a22",
+                                    "fetch_kib": 2673.5, "write_kib": 256.0, **COPY_SCALE},
     # the packed products and their reductions, per call (the sum of the two kernels' counters):
     # the FP64 blocks (headline) and their FP32 copy (+c32)
     ("dense_g5", "mixed_fp16"): {"src": "dense.hip",
