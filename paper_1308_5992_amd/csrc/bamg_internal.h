@@ -205,11 +205,14 @@ void launch_kaczmarz_coarse(const CoarseT<T, S>& c, int colour, int mode, int ns
                             int nrhs, hipStream_t s);
 // colours c and c + 1 (c even) of the 8-colouring in one launch, out of place
 // (xin and xout must not overlap), bitwise the two colour passes; where
-// coarse_pair_applies
+// coarse_pair_applies.  With xc != NULL the launch starts from xin + P xc
+// (P: the level's interpolation from the next level, xc: that level's x),
+// bitwise a prolongation followed by the two passes.
 bool coarse_pair_applies(int ex, int ey, int mode);
 template <typename T, typename S>
 void launch_kaczmarz_coarse_pair(const CoarseT<T, S>& c, int colour, int nsites, const cx<T>* xin, cx<T>* xout,
-                                 const cx<T>* b, int nrhs, hipStream_t s);
+                                 const cx<T>* b, int nrhs, hipStream_t s, const cx<T>* P = nullptr,
+                                 const cx<T>* xc = nullptr);
 // the same pass on the matrix cores (FP32 arithmetic, one wave per site and 16 RHS)
 template <typename S>
 void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mode, int nsites, zf* x, const zf* b,

@@ -186,6 +186,24 @@ __device__ __forceinline__ cx<T> coarse_proj_colsum(const cx<T> (*part)[NOFF * 1
   return s0 + s1;
 }
 
+// (P x_c)[site][d] for level-l site `site` (d = 8 s + j: spin s, row j of
+// the site within its 2 x 2 aggregate's 32 rows of spin s), the 8-term sum in
+// a fixed order with fixed contractions: the prolongation kernel and the fused
+// first post-smoothing launch form it the same way
+template <typename T>
+__device__ __forceinline__ cx<T> coarse_prolong_entry(int ex, const cx<T>* __restrict__ P, const cx<T>* __restrict__ xc,
+                                                      int site, int d) {
+  const int cex = ex / 2, s = d >> 3, j = d & 7;
+  const int ax = site % ex, ay = site / ex;
+  const int A = (ay >> 1) * cex + (ax >> 1), t = 2 * (ay & 1) + (ax & 1);
+  const cx<T>* Pr = P + (((size_t)A * 2 + s) * 32 + 8 * t + j) * 8;
+  const cx<T>* xcv = xc + A * 16 + 8 * s;
+  cx<T> acc = {0, 0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc = acc + cmul_fixed(Pr[k], xcv[k]);
+  return acc;
+}
+
 template <typename T, typename S>
 __global__ __launch_bounds__(128) void k_kaczmarz_coarse(CoarseT<T, S> c, int colour, int mode, cx<T>* __restrict__ x,
                                                          const cx<T>* __restrict__ b) {
@@ -274,7 +292,8 @@ __device__ __forceinline__ int pair_support(int g, int o) {
 template <typename T, typename S>
 __global__ __launch_bounds__(256) void k_kaczmarz_coarse_pair(CoarseT<T, S> c, int colour,
                                                               const cx<T>* __restrict__ xin, cx<T>* __restrict__ xout,
-                                                              const cx<T>* __restrict__ b) {
+                                                              const cx<T>* __restrict__ b, const cx<T>* __restrict__ P,
+                                                              const cx<T>* __restrict__ xc) {
   using C = cx<T>;
   __shared__ C part[2][16][NOFF * 16 + 1];
   __shared__ C rsh[2][16];
@@ -291,7 +310,15 @@ __global__ __launch_bounds__(256) void k_kaczmarz_coarse_pair(CoarseT<T, S> c, i
   CoarseRow<T> wt, ws;
   coarse_row_load(c, at(g ? PR_T2 : PR_T1), i, q, bv, wt);
   if (g == 0) coarse_row_load(c, s, i, q, bv, ws);
-  for (int e = tid; e < 15 * 16; e += 256) X[e] = xr[at(e >> 4) * 16 + (e & 15)];
+  if (xc) {  // x + P x_c: the prolongation that precedes the first post-smoothing sweep
+    const C* xcv = xc + blockIdx.y * (size_t)(ex / 2) * (ey / 2) * 16;
+    for (int e = tid; e < 15 * 16; e += 256) {
+      const int site = at(e >> 4);
+      X[e] = xr[site * 16 + (e & 15)] + coarse_prolong_entry(ex, P, xcv, site, e & 15);
+    }
+  } else {
+    for (int e = tid; e < 15 * 16; e += 256) X[e] = xr[at(e >> 4) * 16 + (e & 15)];
+  }
   __syncthreads();
   // colour c: t1 (group 0) and t2 (group 1)
   {
@@ -343,8 +370,9 @@ bool coarse_pair_applies(int ex, int ey, int mode) { return mode == 8 && ex >= 8
 
 template <typename T, typename S>
 void launch_kaczmarz_coarse_pair(const CoarseT<T, S>& c, int colour, int nsites, const cx<T>* xin, cx<T>* xout,
-                                 const cx<T>* b, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL((k_kaczmarz_coarse_pair<T, S>), dim3(nsites, nrhs), dim3(256), 0, s, c, colour, xin, xout, b);
+                                 const cx<T>* b, int nrhs, hipStream_t s, const cx<T>* P, const cx<T>* xc) {
+  hipLaunchKernelGGL((k_kaczmarz_coarse_pair<T, S>), dim3(nsites, nrhs), dim3(256), 0, s, c, colour, xin, xout, b,
+                     P, xc);
 }
 
 // ---------------------------------------------------------------------------
@@ -763,20 +791,11 @@ void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T
 template <typename T>
 __global__ void k_prolong_coarse(int ex, int ey, const cx<T>* __restrict__ P, const cx<T>* __restrict__ xc,
                                  cx<T>* __restrict__ x) {
-  using C = cx<T>;
-  const int cex = ex / 2, cey = ey / 2;
   const int tt = blockIdx.x * blockDim.x + threadIdx.x;
   const int ns = ex * ey;
   if (tt >= ns * 16) return;
-  const int site = tt >> 4, d = tt & 15, s = d >> 3, j = d & 7;
-  const int ax = site % ex, ay = site / ex;
-  const int A = (ay >> 1) * cex + (ax >> 1), t = 2 * (ay & 1) + (ax & 1);
-  const size_t n = (size_t)ns * 16, nc = (size_t)cex * cey * 16;
-  const C* Pr = P + (((size_t)A * 2 + s) * 32 + 8 * t + j) * 8;
-  const C* xcv = xc + blockIdx.y * nc + A * 16 + 8 * s;
-  C acc = {0, 0};
-  for (int k = 0; k < 8; ++k) acc = acc + Pr[k] * xcv[k];
-  x[blockIdx.y * n + tt] = x[blockIdx.y * n + tt] + acc;
+  const size_t n = (size_t)ns * 16, nc = (size_t)(ex / 2) * (ey / 2) * 16;
+  x[blockIdx.y * n + tt] = x[blockIdx.y * n + tt] + coarse_prolong_entry(ex, P, xc + blockIdx.y * nc, tt >> 4, tt & 15);
 }
 
 template <typename T>
@@ -792,7 +811,7 @@ void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T
                                              int, hipStream_t);                                         \
   template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);                  \
   template void launch_kaczmarz_coarse_pair<T, S>(const CoarseT<T, S>&, int, int, const cx<T>*, cx<T>*, \
-                                                  const cx<T>*, int, hipStream_t);
+                                                  const cx<T>*, int, hipStream_t, const cx<T>*, const cx<T>*);
 BAMG_COARSE_INST(double, zd)
 BAMG_COARSE_INST(float, zf)
 BAMG_COARSE_INST(float, hcx)

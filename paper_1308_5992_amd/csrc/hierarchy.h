@@ -355,13 +355,19 @@ struct bamg_hierarchy {
   }
   // a coarse sweep as fused colour pairs, alternating between x and xs (an
   // even number of launches, so the last writes x); false if they do not apply
+  // (P, xc given: the first launch adds the prolongation P xc to x first)
+  bool pairs_ok(const Level& Lv, const void* xs, int nrhs) const {
+    return xs && nrhs <= cap && Lv.ncol == 8 && coarse_pair_applies(Lv.ex, Lv.ey, Lv.cmode);
+  }
   template <typename T, typename S>
-  bool coarse_pairs(const CoarseT<T, S>& c, const Level& Lv, cx<T>* x, cx<T>* xs, const cx<T>* b, int nrhs) {
-    if (!xs || nrhs > cap || Lv.ncol != 8 || !coarse_pair_applies(Lv.ex, Lv.ey, Lv.cmode)) return false;
+  bool coarse_pairs(const CoarseT<T, S>& c, const Level& Lv, cx<T>* x, cx<T>* xs, const cx<T>* b, int nrhs,
+                    const cx<T>* P = nullptr, const cx<T>* xc = nullptr) {
+    if (!pairs_ok(Lv, xs, nrhs)) return false;
     cx<T>* a = x;
     cx<T>* o = xs;
     for (int col = 0; col < Lv.ncol; col += 2) {
-      launch_kaczmarz_coarse_pair(c, col, Lv.per_colour, a, o, b, nrhs, s);
+      launch_kaczmarz_coarse_pair(c, col, Lv.per_colour, a, o, b, nrhs, s, col == 0 ? P : nullptr,
+                                  col == 0 ? xc : nullptr);
       std::swap(a, o);
     }
     check_launch();
@@ -442,6 +448,12 @@ struct bamg_hierarchy {
         cycle(l + 1, C.b, C.x, nrhs);
         if (coarsest(l + 1)) break;
       }
+    }
+    if (l >= 1 && p.post >= 1 && pairs_ok(Lv, Lv.xs, nrhs)) {
+      // the prolongation inside the first post-smoothing launch
+      coarse_pairs(Lv.coarse(), Lv, x, Lv.xs, b, nrhs, (const zd*)Lv.P, (const zd*)C.x);
+      smooth(l, x, b, nrhs, p.post - 1);
+      return;
     }
     prolong(l, C.x, x, nrhs);
     smooth(l, x, b, nrhs, p.post);
@@ -556,6 +568,13 @@ struct bamg_hierarchy {
         cycle32<S>(l + 1, C.b32, C.x32, nrhs);
         if (coarsest(l + 1)) break;
       }
+    }
+    if (l >= 1 && p.post >= 1 && !(force_mr || nrhs >= MR_MIN) && pairs_ok(Lv, Lv.xs32, nrhs)) {
+      // the prolongation inside the first post-smoothing launch
+      coarse_pairs(coarse32<S>(l), Lv, x, Lv.xs32, b, nrhs, (const zf*)Lv.P32, (const zf*)C.x32);
+      smooth32<S>(l, x, b, nrhs, p.post - 1);
+      check_launch();
+      return;
     }
     if (l == 0) launch_prolong_fine(f32, Lv.P32, C.x32, x, nrhs, s);
     else launch_prolong_coarse(Lv.ex, Lv.ey, Lv.P32, C.x32, x, nrhs, s);
