@@ -213,6 +213,9 @@ template <typename T, typename S>
 void launch_kaczmarz_coarse_pair(const CoarseT<T, S>& c, int colour, int nsites, const cx<T>* xin, cx<T>* xout,
                                  const cx<T>* b, int nrhs, hipStream_t s, const cx<T>* P = nullptr,
                                  const cx<T>* xc = nullptr);
+// y = D x or b - D x on the matrix cores (FP32 arithmetic, 16 RHS per work-group)
+template <typename S>
+void launch_coarse_apply_mfma(const CoarseT<float, S>& c, const zf* x, zf* y, const zf* b, int nrhs, hipStream_t s);
 // the same pass on the matrix cores (FP32 arithmetic, one wave per site and 16 RHS)
 template <typename S>
 void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mode, int nsites, zf* x, const zf* b,

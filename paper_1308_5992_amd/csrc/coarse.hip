@@ -700,6 +700,95 @@ __global__ __launch_bounds__(256) void k_kaczmarz_coarse_mfma4(CoarseT<float, S>
   }
 }
 
+// ---------------------------------------------------------------------------
+// y = D x (or y = b - D x) for many right-hand sides on the matrix cores: one
+// work-group per site and 16 right-hand sides, the product R = A X of the
+// site's 16 x 112 block row with the 112 x 16 support block as real
+// 16x16x4 FP32 MFMA tiles split over the four waves by K (7 of the 28
+// K-steps each), the partials summed in wave order through LDS.  FP32
+// arithmetic, operator in its storage type S, like the smoother above.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_coarse_apply_mfma4(CoarseT<float, S> c, int nrhs, const zf* __restrict__ x,
+                                                            zf* __restrict__ y, const zf* __restrict__ b) {
+  constexpr int NCOL = NOFF * 16, NQ = NCOL * 16 / 256;  // 7 staged unknowns per thread
+  constexpr int KW = NCOL / 4 / 4;                       // K-steps per wave: 7
+  __shared__ float Xr[NCOL][17], Xi[NCOL][17];
+  __shared__ float Pr[4][16][17], Pi[4][16][17];  // partial products of the four waves
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lm = l & 15, lq = l >> 4;
+  const int ns = c.ex * c.ey;
+  const size_t n = (size_t)ns * 16;
+  const int site = blockIdx.x;
+  const int r0 = blockIdx.y * 16;
+  const int nr = min(16, nrhs - r0);
+  const int ax = site % c.ex, ay = site / c.ex;
+  int nb[NOFF];
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    const int dx = (int)((0x0211021u >> (4 * o)) & 15u) - 1, dy = (int)((0x0202111u >> (4 * o)) & 15u) - 1;
+    nb[o] = cwrap(ay + dy, c.ey) * c.ex + cwrap(ax + dx, c.ex);
+  }
+  // every global load first
+  zf xin[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + 256 * q, rr = e / NCOL, col = e - rr * NCOL, o = col >> 4;
+    int nbo = nb[0];
+#pragma unroll
+    for (int oo = 1; oo < NOFF; ++oo) nbo = (o == oo) ? nb[oo] : nbo;
+    xin[q] = zf{0, 0};
+    if (rr < nr) xin[q] = x[(size_t)(r0 + rr) * n + nbo * 16 + (col & 15)];
+  }
+  const S* Dsite = c.D + (size_t)site * NOFF * 256;
+  S ar[KW];  // A[lm][4 q + lq] for this wave's K-steps q = KW w + j
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    const int k = 4 * (KW * w + j) + lq;
+    ar[j] = Dsite[(k >> 4) * 256 + lm * 16 + (k & 15)];
+  }
+  const int orr = tid >> 4, oi = tid & 15;  // the output entry of this thread: right-hand side orr, row oi
+  zf bin = {0, 0};
+  if (b && orr < nr) bin = b[(size_t)(r0 + orr) * n + site * 16 + oi];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + 256 * q, rr = e / NCOL, col = e - rr * NCOL;
+    Xr[col][rr] = xin[q].x;
+    Xi[col][rr] = xin[q].y;
+  }
+  __syncthreads();
+  mf4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    const int k = 4 * (KW * w + j) + lq;
+    const zf a = widen<float>(ar[j]);
+    const float xr = Xr[k][lm], xi = Xi[k][lm];
+    cr = mfma4(a.x, xr, cr);
+    cr = mfma4(-a.y, xi, cr);
+    ci = mfma4(a.x, xi, ci);
+    ci = mfma4(a.y, xr, ci);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    Pr[w][4 * lq + e][lm] = cr[e];
+    Pi[w][4 * lq + e][lm] = ci[e];
+  }
+  __syncthreads();
+  if (orr < nr) {
+    const float rr_ = ((Pr[0][oi][orr] + Pr[1][oi][orr]) + Pr[2][oi][orr]) + Pr[3][oi][orr];
+    const float ri_ = ((Pi[0][oi][orr] + Pi[1][oi][orr]) + Pi[2][oi][orr]) + Pi[3][oi][orr];
+    y[(size_t)(r0 + orr) * n + site * 16 + oi] = b ? zf{bin.x - rr_, bin.y - ri_} : zf{rr_, ri_};
+  }
+}
+
+template <typename S>
+void launch_coarse_apply_mfma(const CoarseT<float, S>& c, const zf* x, zf* y, const zf* b, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL((k_coarse_apply_mfma4<S>), dim3(c.ex * c.ey, (nrhs + 15) / 16), dim3(256), 0, s, c, nrhs, x, y,
+                     b);
+}
+template void launch_coarse_apply_mfma<zf>(const CoarseT<float, zf>&, const zf*, zf*, const zf*, int, hipStream_t);
+template void launch_coarse_apply_mfma<hcx>(const CoarseT<float, hcx>&, const zf*, zf*, const zf*, int, hipStream_t);
+template void launch_coarse_apply_mfma<bcx>(const CoarseT<float, bcx>&, const zf*, zf*, const zf*, int, hipStream_t);
+
 template <typename S>
 void launch_kaczmarz_coarse_mfma(const CoarseT<float, S>& c, int colour, int mode, int nsites, zf* x, const zf* b,
                                  int nrhs, hipStream_t s) {

@@ -497,6 +497,7 @@ struct bamg_hierarchy {
   template <typename S>
   void apply32(int l, const zf* x, zf* y, const zf* b, int nrhs) {
     if (l == 0) launch_dhat(f32, x, y, b, nrhs, s);
+    else if (force_mr || nrhs >= MR_MIN) launch_coarse_apply_mfma(coarse32<S>(l), x, y, b, nrhs, s);
     else launch_coarse_apply(coarse32<S>(l), x, y, b, nrhs, s);
   }
   template <typename S>

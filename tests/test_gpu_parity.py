@@ -588,6 +588,27 @@ def test_mixed_coarse_fused_pairs_give_the_colour_pass_bits(bamg, imported_mixed
     assert torch.equal(x1, x2)
 
 
+def test_mixed_coarse_apply_matrix_cores_against_vector_units(bamg, imported_mixed):
+    """From 4 right-hand sides the FP32 coarse apply runs on the matrix cores
+    (16 right-hand sides per work-group); 2 at a time it runs on the vector
+    units.  Both sum the same 112 FP32 products per entry in different orders:
+    they agree to FP32 rounding."""
+    name, tol, N, U, m, h, o = imported_mixed
+    n = bamg.bamg_level_info(h, 1)["n"]
+    R = 20
+    x = torch.from_numpy(inputs.gaussian((R, n), 78).astype(np.complex64)).to("cuda:0")
+    y = torch.zeros_like(x)
+    bamg.bamg_level_op(h, 1, bamg.OP_APPLY_F32, x, y, R)
+    y2 = torch.zeros_like(x)
+    for r in range(0, R, 2):
+        yr = torch.zeros(2, n, dtype=torch.complex64, device="cuda:0")
+        bamg.bamg_level_op(h, 1, bamg.OP_APPLY_F32, x[r:r + 2].contiguous(), yr, 2)
+        y2[r:r + 2] = yr
+    d = rel(y.cpu().numpy().astype(np.complex128), y2.cpu().numpy().astype(np.complex128))
+    log(f"coarse apply MFMA vs VALU ({name}): {d:.2e}")
+    assert d < 1e-5
+
+
 U32 = 2.0 ** -24  # unit roundoff of FP32
 
 
