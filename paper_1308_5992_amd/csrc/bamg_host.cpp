@@ -13,6 +13,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "../../include/bamg.h"
@@ -664,7 +665,14 @@ int bamg_gaussian_tv(int32_t N, int32_t k, uint64_t seed, void* out, void* strea
 // right-hand side that stops early keeps zero basis vectors until the others
 // finish, so its arithmetic is that of a solve on its own.
 // Input: h->bh [R][n]; output: h->xe [R][n], infos[R].
-static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* infos) {
+// check_input: a non-finite ||bhat_r|| sends bhat through the finiteness check
+// (BAMG_EINVAL if an entry is not finite).  tail (optional): work that
+// follows the solve, enqueued with the norms of the true residual whenever
+// every right-hand side has passed its estimated-residual test, so that the
+// last host round trip covers it; *tail_done says whether it ran (it may run
+// on a pass that turns out not to be the last, and then again).
+static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* infos, bool check_input = false,
+                        const std::function<void()>& tail = nullptr, bool* tail_done = nullptr) {
   typedef std::complex<double> C;
   const size_t n = h->lv[0].n;
   const int m = h->kdim;
@@ -673,6 +681,7 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
   zd* h1 = h->hdev;
   zd* h2 = h->hdev + 64 * R;
   zd* hn2 = h->hdev + 128 * R;
+  if (tail_done) *tail_done = false;
   // ||bhat_r||
   launch_norms(h->bh, n, R, n, h->partial, hn2, s, nullptr, true);
   HIPCHK(hipMemcpyAsync(hh, hn2, R * sizeof(zd), hipMemcpyDeviceToHost, s));
@@ -680,18 +689,38 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
   std::vector<double> bnorm(R), relres(R, 1.0), beta(R);
   std::vector<int> it(R, 0), cycles(R, 0), jend(R, 0);
   std::vector<char> done(R, 0), arn(R, 0);
+  bool finite = true;
+  for (int r = 0; r < R; ++r) finite = finite && std::isfinite(hh[r].x);
+  if (check_input && !finite) {  // an entry that is not finite, or an overflowing norm
+    HIPCHK(hipMemsetAsync(h->dflag, 0, sizeof(int), s));
+    launch_check_finite(h->bh, n * R, h->dflag, s);
+    check_launch();
+    HIPCHK(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (*h->hflag) return fail(BAMG_EINVAL, "right-hand side is not finite");
+  }
   for (int r = 0; r < R; ++r) {
     bnorm[r] = std::sqrt(hh[r].x);
     if (bnorm[r] == 0.0) { done[r] = 1; relres[r] = 0.0; }
   }
   launch_fill_zero(h->xe, n * R, s);
-  launch_copy(h->bh, h->rr, n * R, s);
   std::vector<C> H((size_t)R * (m + 1) * m), g((size_t)R * (m + 1)), sn((size_t)R * m);
   std::vector<double> cs((size_t)R * m);
+  // the first pass starts from x = 0: its residual is bhat, whose norms are
+  // already on the host (the same kernel on the same vector)
+  bool first = true, settled = false;
   while (true) {
-    launch_norms(h->rr, n, R, n, h->partial, hn2, s, nullptr, true);
-    HIPCHK(hipMemcpyAsync(hh, hn2, R * sizeof(zd), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    const zd* res = first ? h->bh : h->rr;
+    if (!first) {
+      launch_norms(h->rr, n, R, n, h->partial, hn2, s, nullptr, true);
+      HIPCHK(hipMemcpyAsync(hh, hn2, R * sizeof(zd), hipMemcpyDeviceToHost, s));
+      if (tail && settled) {
+        tail();
+        if (tail_done) *tail_done = true;
+      }
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    first = false;
     bool any = false;
     for (int r = 0; r < R; ++r) {
       arn[r] = 0;
@@ -711,22 +740,31 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
       g[(size_t)r * (m + 1)] = arn[r] ? beta[r] : 0.0;
     }
     if (!any) break;
+    if (tail_done) *tail_done = false;
     HIPCHK(hipMemcpyAsync(h->scal_dev, h->scal_host, R * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_bscale(h->rr, h->V, n, R, h->scal_dev, s);
+    launch_bscale(res, h->V, n, R, h->scal_dev, s);
     int jmax = 0;
+    settled = true;
     for (int j = 0; j < m; ++j) {
       zd* vj = h->V + (size_t)j * R * n;
       zd* zj = h->Z + (size_t)j * R * n;
+      // (one right-hand side: v_j = w / |w| from the norm on the device)
       // z_j = M v_j, w = Dhat z_j, CGS2 against v_0..v_j, |w|^2, to the host
       h->run_graph(((uint64_t)R << 8) | (uint64_t)j, [&] {
         hipStream_t sc = h->s;
+        if (R == 1 && j > 0) launch_bscale_rnorm(h->w, vj, n, hn2, sc);
         h->precondition(vj, zj, R);
         h->apply(0, zj, h->w, nullptr, R);
         launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, sc);
-        launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, sc);
-        launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, sc);
-        launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, sc);
-        launch_norms(h->w, n, R, n, h->partial, hn2, sc, nullptr, true);
+        // the second projection's inner products and the norm ride on the
+        // multi-axpys before them
+        if (!launch_baxpy_dot(h->V, j + 1, h1, -1.0, h->w, n, R, j + 1, h->partial, h2, sc) ||
+            !launch_baxpy_dot(h->V, j + 1, h2, -1.0, h->w, n, R, 0, h->partial, hn2, sc)) {
+          launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, sc);
+          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, sc);
+          launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, sc);
+          launch_norms(h->w, n, R, n, h->partial, hn2, sc, nullptr, true);
+        }
         check_launch();
         HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
       });
@@ -769,14 +807,18 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
         jend[r] = j + 1;
         if (std::abs(gr[j + 1]) <= tol * bnorm[r] || it[r] >= h->p.max_iter || hn == 0.0) {
           arn[r] = 0;
+          if (!(std::abs(gr[j + 1]) <= tol * bnorm[r]) && it[r] < h->p.max_iter) settled = false;
         } else {
           h->scal_host[r] = 1.0 / hn;
           still = true;
         }
       }
       if (!still) break;
-      HIPCHK(hipMemcpyAsync(h->scal_dev, h->scal_host, R * sizeof(double), hipMemcpyHostToDevice, s));
-      launch_bscale(h->w, h->V + (size_t)(j + 1) * R * n, n, R, h->scal_dev, s);
+      if (j + 1 == m) settled = false;  // a restart follows
+      if (R > 1) {
+        HIPCHK(hipMemcpyAsync(h->scal_dev, h->scal_host, R * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_bscale(h->w, h->V + (size_t)(j + 1) * R * n, n, R, h->scal_dev, s);
+      }
     }
     // y_r = H_r^{-1} g_r (upper triangular), x_r += Z_r y_r, true residual
     for (int r = 0; r < R; ++r) {
@@ -814,22 +856,24 @@ static int solve_single(bamg_hierarchy* h, const void* B, void* X, double tol, b
   try {
     h->ensure_krylov(1, true);
     h->ensure_cap(1);
-    const size_t n = h->lv[0].n;
     launch_eo_reduce(h->f, (const zd*)B, h->bh, 1, h->s);
-    HIPCHK(hipMemsetAsync(h->dflag, 0, sizeof(int), h->s));
-    launch_check_finite(h->bh, n, h->dflag, h->s);
-    check_launch();
-    HIPCHK(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->s));
+    // x_o from x_e, and ||b - D x|| / ||b|| of the unreduced system (one
+    // apply of D and two norms), into a slot of hdev / hhost the Krylov
+    // solver does not use (past h1, h2 and |w|^2)
+    zd* rf_dev = h->hdev + 129;
+    zd* rf_host = h->hhost + 129;
+    auto tail = [&] {
+      launch_eo_reconstruct(h->f, (const zd*)B, h->xe, (zd*)X, 1, h->s);
+      launch_wilson_resnorm_packed(h->f, (const zd*)B, (const zd*)X, 1, (double*)h->partial, (double*)rf_dev, h->s);
+      check_launch();
+      HIPCHK(hipMemcpyAsync(rf_host, rf_dev, sizeof(double), hipMemcpyDeviceToHost, h->s));
+    };
+    bool tail_done = false;
+    st = fgmres_batch(h, 1, tol, info, true, tail, &tail_done);
+    if (st == BAMG_EINVAL) return st;
+    if (!tail_done) tail();
     HIPCHK(hipStreamSynchronize(h->s));
-    if (*h->hflag) return fail(BAMG_EINVAL, "right-hand side is not finite");
-    st = fgmres_batch(h, 1, tol, info);
-    launch_eo_reconstruct(h->f, (const zd*)B, h->xe, (zd*)X, 1, h->s);
-    // ||b - D x|| / ||b|| of the unreduced system (one apply of D and two norms)
-    launch_wilson_resnorm_packed(h->f, (const zd*)B, (const zd*)X, 1, (double*)h->partial, (double*)h->hdev, h->s);
-    check_launch();
-    HIPCHK(hipMemcpyAsync(h->hhost, h->hdev, sizeof(double), hipMemcpyDeviceToHost, h->s));
-    HIPCHK(hipStreamSynchronize(h->s));
-    info->relres_full = ((const double*)h->hhost)[0];
+    info->relres_full = ((const double*)rf_host)[0];
   } catch (const HipFail& e) {
     return fail(BAMG_EDEVICE, e.msg);
   }

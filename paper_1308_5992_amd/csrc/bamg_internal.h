@@ -172,8 +172,32 @@ bool fine_sweep_applies(const FineT<T>& f, int nrhs);
 // the plan of form 0 (the library's choice), 1 (LDS-resident) or 2
 // (streaming); returns the form written, 0 for none (host only)
 int fine_sweep_plan_query(int N, int nrhs, bool fp32, int form, FineSweepPlan& p, int sched[3]);
+// Work a sweep of the LDS-resident form can take over from the launches
+// around it (all fields optional):
+// - P, xc: every x value the sweep reads is x + P xc, the prolongation of
+//   launch_prolong_fine with the same bits (xin itself is not changed);
+// - xzero: x is taken as zero and xin is not read;
+// - b64, b_out: b is read as b64 (FP64) rounded to T, and written rounded to
+//   b_out on the work-group's tile (b is not read; b_out may be b);
+// - x64: the result is written in FP64 to x64 instead of to xout.
 template <typename T>
-void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s);
+struct FineFuse {
+  const cx<T>* P = nullptr;
+  const cx<T>* xc = nullptr;
+  bool xzero = false;
+  const zd* b64 = nullptr;
+  cx<T>* b_out = nullptr;
+  zd* x64 = nullptr;
+  bool any() const { return P || xzero || b64 || x64; }
+};
+// true where launch_fine_sweep takes the LDS-resident form, the one that
+// carries FineFuse work
+template <typename T>
+bool fine_sweep_fusable(const FineT<T>& f, int nrhs);
+// false (nothing launched) if fz asks for work and the size takes another form
+template <typename T>
+bool launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s,
+                       const FineFuse<T>& fz = FineFuse<T>{});
 // rc = P^H r (level 0 -> 1), and xz = 0 (level 1, same layout) if xz != NULL;
 // x += P xc (level 1 -> 0)
 template <typename T>
@@ -314,8 +338,15 @@ void launch_convert_zero(const zd* in, zf* out, zf* zero_out, size_t n, hipStrea
 // at X + (v*R + r)*n, w_r at W + r*n, coefficients at stride 64 per r
 void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s);
 void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, hipStream_t s);
+// W_r += sign sum_{v < nv} X_{v,r} h[r][v], then out[r][v] = X_{v,r}^H W_r for
+// v < nd (nd > 0) or out[r] = |W_r|^2 (nd = 0), in one pass over W_r per
+// launch pair; false (nothing launched) where a chunk is too long
+bool launch_baxpy_dot(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, int nd, zd* partial,
+                      zd* out, hipStream_t s);
 // y_r = c[r] x_r (c device, real)
 void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStream_t s);
+// one vector: y = x / sqrt(nrm2[0].x)
+void launch_bscale_rnorm(const zd* x, zd* y, size_t n, const zd* nrm2, hipStream_t s);
 // x_r += sum_q Z_{q,r} y[r*64 + q]
 void launch_blincomb(const zd* Z, int nq, const zd* y, zd* x, size_t n, int R, hipStream_t s);
 // slot-mapped forms (continuous batching): entry a of a launch uses slot slot[a]

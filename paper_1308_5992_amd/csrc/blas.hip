@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BT) void k_bdot_partial(const zd* __restrict__ X, i
   const zd* xv = X + ((size_t)v * R + r) * n;
   const zd* wv = W + (size_t)r * n;
   zd acc = {0, 0};
-  for (size_t i = lo + threadIdx.x; i < hi; i += BT) acc = acc + cjmul(xv[i], wv[i]);
+  for (size_t i = lo + threadIdx.x; i < hi; i += BT) acc = acc + cjmul_fixed(xv[i], wv[i]);
   const zd s = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[((size_t)r * nb + b) * 64 + v] = s;
 }
@@ -259,12 +259,88 @@ __global__ void k_bmultiaxpy(const zd* __restrict__ X, int nv, int R, const zd* 
   const int r = blockIdx.y;
   if (i >= n) return;
   zd acc = {0, 0};
-  for (int v = 0; v < nv; ++v) acc = acc + X[((size_t)v * R + r) * n + i] * h[(size_t)r * 64 + v];
+  for (int v = 0; v < nv; ++v) acc = acc + cmul_fixed(X[((size_t)v * R + r) * n + i], h[(size_t)r * 64 + v]);
   W[(size_t)r * n + i] = W[(size_t)r * n + i] + sign * acc;
 }
 
 void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, hipStream_t s) {
   hipLaunchKernelGGL(k_bmultiaxpy, dim3((unsigned)((n + 255) / 256), R), dim3(256), 0, s, X, nv, R, h, sign, W, n);
+}
+
+// A Gram-Schmidt step and the reduction after it in one launch: block b of
+// right-hand side r updates its chunk of w_r by the multi-axpy
+// (k_bmultiaxpy's arithmetic), then forms from the updated chunk the partial
+// inner products with X_0..X_{nd-1} (nd > 0; k_bdot_partial's block
+// decomposition, per-thread order and tree, BAX_VC vectors per tree) or the
+// partial squared norm (nd = 0; partial[b R + r], the layout of
+// k_dot_partial).  A chunk holds at most BAX_E entries per thread.
+constexpr int BAX_E = 4, BAX_VC = 8;
+__global__ __launch_bounds__(BT) void k_baxpy_dot(const zd* __restrict__ X, int nv, int R, const zd* __restrict__ h,
+                                                  double sign, zd* __restrict__ W, size_t n, int nd,
+                                                  zd* __restrict__ partial) {
+  __shared__ zd sh[BAX_VC][BT];
+  const int b = blockIdx.x, r = blockIdx.y, nb = gridDim.x, tid = threadIdx.x;
+  const size_t chunk = (n + nb - 1) / nb;
+  const size_t lo = (size_t)b * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
+  zd* wv = W + (size_t)r * n;
+  zd wl[BAX_E];
+#pragma unroll
+  for (int k = 0; k < BAX_E; ++k) {
+    const size_t i = lo + tid + (size_t)k * BT;
+    wl[k] = zd{0, 0};
+    if (i < hi) {
+      zd acc = {0, 0};
+      for (int v = 0; v < nv; ++v) acc = acc + cmul_fixed(X[((size_t)v * R + r) * n + i], h[(size_t)r * 64 + v]);
+      wl[k] = wv[i] + sign * acc;
+      wv[i] = wl[k];
+    }
+  }
+  if (nd == 0) {
+    zd acc = {0, 0};
+#pragma unroll
+    for (int k = 0; k < BAX_E; ++k)
+      if (lo + tid + (size_t)k * BT < hi) acc.x = acc.x + fma(wl[k].x, wl[k].x, wl[k].y * wl[k].y);
+    const zd s = block_sum(acc, sh[0]);
+    if (tid == 0) partial[(size_t)b * R + r] = s;
+    return;
+  }
+  for (int v0 = 0; v0 < nd; v0 += BAX_VC) {
+#pragma unroll
+    for (int q = 0; q < BAX_VC; ++q) {
+      const int v = v0 + q;
+      zd acc = {0, 0};
+      if (v < nd) {
+        const zd* xv = X + ((size_t)v * R + r) * n;
+#pragma unroll
+        for (int k = 0; k < BAX_E; ++k) {
+          const size_t i = lo + tid + (size_t)k * BT;
+          if (i < hi) acc = acc + cjmul_fixed(xv[i], wl[k]);
+        }
+      }
+      sh[q][tid] = acc;
+    }
+    __syncthreads();
+    for (int off = BT / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+#pragma unroll
+        for (int q = 0; q < BAX_VC; ++q) sh[q][tid] = sh[q][tid] + sh[q][tid + off];
+      }
+      __syncthreads();
+    }
+    if (tid < BAX_VC && v0 + tid < nd) partial[((size_t)r * nb + b) * 64 + v0 + tid] = sh[tid][0];
+    __syncthreads();
+  }
+}
+
+bool launch_baxpy_dot(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, int nd, zd* partial,
+                      zd* out, hipStream_t s) {
+  const int nb = blas_nblocks_fine(n);
+  const size_t chunk = (n + nb - 1) / nb;
+  if (chunk > (size_t)BAX_E * BT || nd < 0 || nd > 64) return false;
+  hipLaunchKernelGGL(k_baxpy_dot, dim3(nb, R), dim3(BT), 0, s, X, nv, R, h, sign, W, n, nd, partial);
+  if (nd > 0) hipLaunchKernelGGL(k_breduce, dim3(nd, R), dim3(BT), 0, s, partial, nb, out);
+  else hipLaunchKernelGGL(k_reduce_partial, dim3(R), dim3(BT), 0, s, partial, nb, R, out);
+  return true;
 }
 
 __global__ void k_bscale(const zd* __restrict__ x, zd* __restrict__ y, size_t n, const double* __restrict__ c) {
@@ -275,6 +351,17 @@ __global__ void k_bscale(const zd* __restrict__ x, zd* __restrict__ y, size_t n,
 
 void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStream_t s) {
   hipLaunchKernelGGL(k_bscale, dim3((unsigned)((n + 255) / 256), R), dim3(256), 0, s, x, y, n, c);
+}
+
+// y = x / sqrt(nrm2.x): the next Arnoldi vector from the squared norm left
+// on the device (the host's 1 / sqrt, correctly rounded both ways)
+__global__ void k_bscale_rnorm(const zd* __restrict__ x, zd* __restrict__ y, size_t n, const zd* __restrict__ nrm2) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (1.0 / sqrt(nrm2[0].x)) * x[i];
+}
+
+void launch_bscale_rnorm(const zd* x, zd* y, size_t n, const zd* nrm2, hipStream_t s) {
+  hipLaunchKernelGGL(k_bscale_rnorm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, nrm2);
 }
 
 __global__ void k_blincomb(const zd* __restrict__ Z, int nq, int R, const zd* __restrict__ y, zd* __restrict__ x,

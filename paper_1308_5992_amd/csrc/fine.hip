@@ -1005,6 +1005,24 @@ void launch_smooth_fine_il(const FineT<T>& f, int ncol, int per_colour, cx<T>* x
 // colour passes.  Projections near the region edge that no tile value depends
 // on may see stale inputs; they only write outside the tile's dependence.
 // ---------------------------------------------------------------------------
+// (P xc) at spin s of even site e (half-x index) for one right-hand side:
+// the 8 test-vector columns of the site's 4 x 4 aggregate, summed in order
+// with fixed contractions (the prolongation kernel and the sweeps that carry
+// it give the same bits)
+template <typename T>
+__device__ __forceinline__ cx<T> fine_prolong_entry(const FineT<T>& f, const cx<T>* __restrict__ P,
+                                                    const cx<T>* __restrict__ xc, int e, int s) {
+  const int cxn = f.NH / 4;
+  const int y = e / f.NH, xh = e - y * f.NH;
+  const int a = (y >> 2) * cxn + (xh >> 2), row = 4 * (y & 3) + (xh & 3);
+  const cx<T>* Pr = P + (((size_t)a * 2 + s) * 16 + row) * 8;
+  const cx<T>* xcv = xc + (size_t)a * 16 + 8 * s;
+  cx<T> acc = {0, 0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc = acc + cmul_fixed(Pr[k], xcv[k]);
+  return acc;
+}
+
 constexpr uint64_t SLOT_DU1 = 0x011202021ull, SLOT_DV1 = 0x102120021ull;  // (du, dv) + 1 of slot n
 
 constexpr int FS_NT = 512;               // threads per work-group of the blocked sweep
@@ -1049,7 +1067,8 @@ __device__ __forceinline__ FsColour<T, ITER> fs_colour(const int (&k)[ITER], boo
 
 template <typename T, int LDSB, int ITER>
 __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineSweepPlan p, const cx<T>* __restrict__ xin,
-                                                               cx<T>* __restrict__ xout, const cx<T>* __restrict__ b) {
+                                                               cx<T>* __restrict__ xout, const cx<T>* __restrict__ b,
+                                                               FineFuse<T> fz) {
   using C = cx<T>;
   constexpr int UB = 36 * (int)sizeof(C) / 16;  // 16-byte units of a site's slot blocks
   constexpr int US = 2 * (int)sizeof(C) / 16;   // 16-byte units of a site's two unknowns
@@ -1066,7 +1085,10 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
   const size_t n = (size_t)N * NH * 2;
   const C* xr = xin + blockIdx.y * n;
   C* xw = xout + blockIdx.y * n;
-  const C* br = b ? b + blockIdx.y * n : nullptr;
+  // b64: b comes from the FP64 copy (converted below), not through the loads
+  const zd* b64 = fz.b64 ? fz.b64 + blockIdx.y * n : nullptr;
+  const C* br = (b && !b64) ? b + blockIdx.y * n : nullptr;
+  const bool xzero = fz.xzero || b64;
   auto site = [&](int u, int v) {
     const int xx = (u + v + 2 * N) % N, yy = (u - v + 2 * N) % N;
     return yy * NH + (xx >> 1);
@@ -1096,7 +1118,7 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
       for (int u = 0; u < FS_BATCH; ++u) {
         const int e = e0 + u * FS_NT;
         v[u] = make_uint4(0, 0, 0, 0);
-        if (e < t4) {
+        if (e < t4 && !(xzero && e < t1)) {
           const uint4* src;
           size_t idx;
           if (e < t1) {
@@ -1126,13 +1148,28 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
       }
     }
   }
+  if (b64) {  // the projections' right-hand sides from FP64, rounded as the conversion kernels round
+    for (int e = tid; e < 2 * p.nupd; e += FS_NT) {
+      const zd v = b64[2 * (size_t)usite[e >> 1] + (e & 1)];
+      bs[e] = C{(T)v.x, (T)v.y};
+    }
+  }
   __syncthreads();
+  if (fz.P) {  // x + P xc on the region: the prolongation carried by this sweep
+    const C* xcr = fz.xc + blockIdx.y * ((size_t)(NH / 4) * (N / 4) * 16);
+    for (int e = tid; e < 2 * p.Ru * p.Rv; e += FS_NT) {
+      const int q = e >> 1, li = q / p.Rv;
+      const int st = site(u0 + p.i0 + li, v0 + p.j0 + (q - li * p.Rv));
+      X[e] = X[e] + fine_prolong_entry(f, fz.P, xcr, st, e & 1);
+    }
+    __syncthreads();
+  }
   const int g = tid >> 4, lane = tid & 15;
   const bool act = lane < 9;
   const int slot = act ? lane : 0;
   const int soff = (nib(SLOT_DU1, slot) - 1) * p.Rv + (nib(SLOT_DV1, slot) - 1);
   const C* Bl = Bs + slot * 4;  // the lane's slot block within a projection's 36 entries
-  const bool hasb = br != nullptr;
+  const bool hasb = br != nullptr || b64 != nullptr;
   // the group's projections of every colour, fixed before the first step
   int kk[16][ITER];
 #pragma unroll
@@ -1172,6 +1209,25 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
     }
     __syncthreads();
     if (c < 15) cur = nxt;
+  }
+  if (b64) {  // the tile's right-hand side, rounded, for the sweeps that follow
+    C* bo = fz.b_out + blockIdx.y * n;
+    for (int e = tid; e < p.Tu * p.Tv * 2; e += FS_NT) {
+      const int q = e >> 1, ti = q / p.Tv, tj = q - ti * p.Tv;
+      const size_t at = 2 * (size_t)site(u0 + ti, v0 + tj) + (e & 1);
+      const zd v = b64[at];
+      bo[at] = C{(T)v.x, (T)v.y};
+    }
+  }
+  if (fz.x64) {
+    zd* xo = fz.x64 + blockIdx.y * n;
+    for (int e = tid; e < p.Tu * p.Tv * 2; e += FS_NT) {
+      const int q = e >> 1, ti = q / p.Tv, tj = q - ti * p.Tv;
+      const int l = (ti - p.i0) * p.Rv + (tj - p.j0);
+      const C v = X[2 * l + (e & 1)];
+      xo[2 * (size_t)site(u0 + ti, v0 + tj) + (e & 1)] = zd{(double)v.x, (double)v.y};
+    }
+    return;
   }
   uint4* xw4 = reinterpret_cast<uint4*>(xw);
   for (int e = tid; e < p.Tu * p.Tv * US; e += FS_NT) {
@@ -1873,16 +1929,25 @@ bool fine_sweep_applies(const FineT<T>& f, int nrhs) {
 }
 
 template <typename T>
-void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s) {
+bool fine_sweep_fusable(const FineT<T>& f, int nrhs) {
+  FineSweepPlan p;
+  int maxcnt;
+  if (!f.Bst || !f.Gst || nrhs < 1 || nrhs > 65535) return false;
+  return fine_sweep_cached_plan<T>(f.N, nrhs, p, maxcnt) == 1;
+}
+
+template <typename T>
+bool launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const cx<T>* b, int nrhs, hipStream_t s,
+                       const FineFuse<T>& fz) {
   FineSweepPlan p;
   FinePipePlan q;
   int maxcnt = 0;
   const int mode = fine_sweep_cached_plan<T>(f.N, nrhs, p, maxcnt, &q);
-  if (mode == 0) return;
+  if (mode == 0 || (mode != 1 && fz.any())) return false;
   if (mode == 3) {
     hipLaunchKernelGGL((k_kaczmarz_fine_pipe<T>), dim3((unsigned)(q.ntu * q.ntv), (unsigned)nrhs), dim3(FP_NT), 0, s,
                        f, q, xin, xout, b);
-    return;
+    return true;
   }
   const dim3 grid((unsigned)(p.ntu * p.ntv), (unsigned)nrhs);
   if (mode == 2) {
@@ -1897,13 +1962,13 @@ void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const c
     else if (sb4) FSS_LAUNCH(4, 4);
     else FSS_LAUNCH(4, SBM);  // (SBM = 4 for FP64: the plan keeps its colours within 4 loads per thread)
 #undef FSS_LAUNCH
-    return;
+    return true;
   }
   const size_t lds = fine_sweep_lds<T>(p);
   maxcnt = 0;
   for (int c = 0; c < 16; ++c) maxcnt = std::max(maxcnt, p.first[c + 1] - p.first[c]);
 #define FS_LAUNCH(L, I) \
-  hipLaunchKernelGGL((k_kaczmarz_fine_sweep<T, L, I>), grid, dim3(FS_NT), 0, s, f, p, xin, xout, b)
+  hipLaunchKernelGGL((k_kaczmarz_fine_sweep<T, L, I>), grid, dim3(FS_NT), 0, s, f, p, xin, xout, b, fz)
 #define FS_ITER(L)                     \
   do {                                 \
     if (maxcnt <= FS_GROUPS)           \
@@ -1919,6 +1984,7 @@ void launch_fine_sweep(const FineT<T>& f, const cx<T>* xin, cx<T>* xout, const c
     FS_ITER(FS_LDS_LARGE);
 #undef FS_ITER
 #undef FS_LAUNCH
+  return true;
 }
 // The plan of form (0: the library's choice, 1, 2, 3) for the plan query of
 // the C ABI; returns the form written, 0 for none.  sched = {A, M, W} of the
@@ -1944,8 +2010,12 @@ int fine_sweep_plan_query(int N, int nrhs, bool fp32, int form, FineSweepPlan& p
 
 template bool fine_sweep_applies<double>(const FineT<double>&, int);
 template bool fine_sweep_applies<float>(const FineT<float>&, int);
-template void launch_fine_sweep<double>(const FineT<double>&, const zd*, zd*, const zd*, int, hipStream_t);
-template void launch_fine_sweep<float>(const FineT<float>&, const zf*, zf*, const zf*, int, hipStream_t);
+template bool fine_sweep_fusable<double>(const FineT<double>&, int);
+template bool fine_sweep_fusable<float>(const FineT<float>&, int);
+template bool launch_fine_sweep<double>(const FineT<double>&, const zd*, zd*, const zd*, int, hipStream_t,
+                                        const FineFuse<double>&);
+template bool launch_fine_sweep<float>(const FineT<float>&, const zf*, zf*, const zf*, int, hipStream_t,
+                                       const FineFuse<float>&);
 
 template void launch_smooth_fine_il<double>(const FineT<double>&, int, int, zd*, const zd*, zd*, zd*, int, int,
                                             hipStream_t);
@@ -1993,19 +2063,12 @@ void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<
 
 template <typename T>
 __global__ void k_prolong_fine(FineT<T> f, const cx<T>* __restrict__ P, const cx<T>* __restrict__ xc, cx<T>* __restrict__ x) {
-  using C = cx<T>;
   const int cxn = f.NH / 4, cyn = f.N / 4;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= f.N * f.NH * 2) return;
   const int e = t >> 1, s = t & 1;
-  const int y = e / f.NH, xh = e - y * f.NH;
-  const int a = (y >> 2) * cxn + (xh >> 2), row = 4 * (y & 3) + (xh & 3);
   const size_t n = (size_t)f.N * f.NH * 2, nc = (size_t)cxn * cyn * 16;
-  const C* Pr = P + (((size_t)a * 2 + s) * 16 + row) * 8;
-  const C* xcv = xc + blockIdx.y * nc + a * 16 + 8 * s;
-  C acc = {0, 0};
-  for (int k = 0; k < 8; ++k) acc = acc + Pr[k] * xcv[k];
-  x[blockIdx.y * n + t] = x[blockIdx.y * n + t] + acc;
+  x[blockIdx.y * n + t] = x[blockIdx.y * n + t] + fine_prolong_entry(f, P, xc + blockIdx.y * nc, e, s);
 }
 
 template <typename T>

@@ -375,33 +375,59 @@ struct bamg_hierarchy {
   }
   // count level-0 sweeps blocked in LDS, alternating between x and xs so that
   // the last one writes x (an odd count starts from a copy of x in xs); false
-  // if they do not apply
+  // if they do not apply.  fz: work carried by the sweeps (FineFuse), the
+  // prolongation and the inputs (zero x, FP64 b) by the first, the FP64
+  // output by the last (which then writes fz.x64 instead of x); only where
+  // fine_fuse_ok
   template <typename T>
-  bool fine_sweeps(const FineT<T>& ff, cx<T>* x, cx<T>* xs, const cx<T>* b, int nrhs, int count) {
+  bool fine_sweeps(const FineT<T>& ff, cx<T>* x, cx<T>* xs, const cx<T>* b, int nrhs, int count,
+                   const FineFuse<T>& fz = FineFuse<T>{}) {
     if (!xs || nrhs > cap || count < 1 || !fine_sweep_applies(ff, nrhs)) return false;
+    if (fz.any() && !fine_sweep_fusable(ff, nrhs)) return false;
+    const bool xzero = fz.xzero || fz.b64;
     cx<T>* a = x;
     cx<T>* o = xs;
     if (count & 1) {
-      launch_copy(reinterpret_cast<const zd*>(x), reinterpret_cast<zd*>(xs), lv[0].n * nrhs * sizeof(cx<T>) / sizeof(zd), s);
+      if (!xzero)
+        launch_copy(reinterpret_cast<const zd*>(x), reinterpret_cast<zd*>(xs),
+                    lv[0].n * nrhs * sizeof(cx<T>) / sizeof(zd), s);
       std::swap(a, o);
     }
     for (int i = 0; i < count; ++i) {
-      launch_fine_sweep(ff, a, o, b, nrhs, s);
+      FineFuse<T> g;
+      if (i == 0) {
+        g.P = fz.P;
+        g.xc = fz.xc;
+        g.xzero = fz.xzero;
+        g.b64 = fz.b64;
+        g.b_out = fz.b_out;
+      }
+      if (i == count - 1) g.x64 = fz.x64;
+      if (!launch_fine_sweep(ff, a, o, b, nrhs, s, g)) throw HipFail("fine sweep: no blocked form for fused work");
       std::swap(a, o);
     }
     check_launch();
     return true;
   }
+  // the level-0 sweeps of smooth / smooth32 at nrhs take the LDS-resident
+  // blocked form, which carries FineFuse work
+  template <typename T>
+  bool fine_fuse_ok(const FineT<T>& ff, const cx<T>* xs, const cx<T>* xi, int nrhs) const {
+    if (nrhs >= IL_MIN && xi && nrhs <= cap) return false;
+    return xs && nrhs <= cap && fine_sweep_applies(ff, nrhs) && fine_sweep_fusable(ff, nrhs);
+  }
   // count sweeps on level l; on level 0 from IL_MIN right-hand sides through
   // the interleaved copies, below that blocked in LDS where a tile plan
   // applies (the same bits as count calls of sweep)
-  void smooth(int l, zd* x, const zd* b, int nrhs, int count) {
-    if (l == 0 && nrhs >= IL_MIN && xil && nrhs <= cap) {
+  // (fz: work the level-0 sweeps carry, only where fine_fuse_ok and count >= 1)
+  void smooth(int l, zd* x, const zd* b, int nrhs, int count, const FineFuse<double>& fz = FineFuse<double>{}) {
+    if (!fz.any() && l == 0 && nrhs >= IL_MIN && xil && nrhs <= cap) {
       launch_smooth_fine_il(f, lv[0].ncol, lv[0].per_colour, x, b, xil, bil, nrhs, count, s);
       check_launch();
       return;
     }
-    if (l == 0 && fine_sweeps(f, x, xsw, b, nrhs, count)) return;
+    if (l == 0 && fine_sweeps(f, x, xsw, b, nrhs, count, fz)) return;
+    if (fz.any()) throw HipFail("fine sweeps: fused work where the blocked form does not apply");
     for (int i = 0; i < count; ++i) sweep(l, x, b, nrhs);
   }
   // rc = P^H r; xz (level l+1, may be NULL) = 0 in the same launch
@@ -426,9 +452,12 @@ struct bamg_hierarchy {
   // multigrid cycle on level l for A_l x = b, x holds the initial guess
   // (pre-smoothing, residual, restriction, coarse correction, prolongation,
   // post-smoothing; Sec. 1 two-grid scheme applied recursively, Sec. 4)
-  void cycle(int l, const zd* b, zd* x, int nrhs) {
+  // xzero (level 0, where fine_zero_ok): x is zero on entry and is not read
+  void cycle(int l, const zd* b, zd* x, int nrhs, bool xzero = false) {
+    FineFuse<double> fz0;
+    fz0.xzero = xzero;
     if (L() == 1) {  // one level: the cycle reduces to its smoothing sweeps
-      smooth(0, x, b, nrhs, p.pre + p.post);
+      smooth(0, x, b, nrhs, p.pre + p.post, fz0);
       return;
     }
     if (coarsest(l)) {
@@ -437,7 +466,7 @@ struct bamg_hierarchy {
     }
     Level& Lv = lv[l];
     Level& C = lv[l + 1];
-    smooth(l, x, b, nrhs, p.pre);
+    smooth(l, x, b, nrhs, p.pre, fz0);
     apply(l, x, Lv.r, b, nrhs);  // r = b - A x
     restrict_(l, Lv.r, C.b, nrhs, coarsest(l + 1) ? nullptr : C.x);  // and the coarse initial guess x = 0
     if (kvisited(l + 1)) {
@@ -455,8 +484,20 @@ struct bamg_hierarchy {
       smooth(l, x, b, nrhs, p.post - 1);
       return;
     }
+    if (l == 0 && p.post >= 1 && fine_fuse_ok(f, xsw, xil, nrhs)) {
+      // the prolongation inside the first post-smoothing sweep
+      FineFuse<double> fz;
+      fz.P = Lv.P;
+      fz.xc = C.x;
+      smooth(0, x, b, nrhs, p.post, fz);
+      return;
+    }
     prolong(l, C.x, x, nrhs);
     smooth(l, x, b, nrhs, p.post);
+  }
+  // the FP64 cycle can start from a zero x it does not read
+  bool fine_zero_ok(int nrhs) const {
+    return fine_fuse_ok(f, xsw, xil, nrhs) && (L() == 1 ? p.pre + p.post : p.pre) >= 1;
   }
 
   // K-cycle coarse visit of level c: two steps of flexible GCR on A_c x = r0
@@ -522,18 +563,26 @@ struct bamg_hierarchy {
     }
   }
   template <typename S>
-  void smooth32(int l, zf* x, const zf* b, int nrhs, int count) {
-    if (l == 0 && nrhs >= IL_MIN && xil32 && nrhs <= cap) {
+  void smooth32(int l, zf* x, const zf* b, int nrhs, int count, const FineFuse<float>& fz = FineFuse<float>{}) {
+    if (!fz.any() && l == 0 && nrhs >= IL_MIN && xil32 && nrhs <= cap) {
       launch_smooth_fine_il(f32, lv[0].ncol, lv[0].per_colour, x, b, xil32, bil32, nrhs, count, s);
       return;
     }
-    if (l == 0 && fine_sweeps(f32, x, xsw32, b, nrhs, count)) return;
+    if (l == 0 && fine_sweeps(f32, x, xsw32, b, nrhs, count, fz)) return;
+    if (fz.any()) throw HipFail("fine sweeps: fused work where the blocked form does not apply");
     for (int i = 0; i < count; ++i) sweep32<S>(l, x, b, nrhs);
   }
+  // in64, out64 (level 0, where fine_io_ok): x is zero on entry, b is in64
+  // rounded to FP32 (the first sweep writes it to b), and the last sweep
+  // writes the result to out64 in FP64 instead of to x
   template <typename S>
-  void cycle32(int l, const zf* b, zf* x, int nrhs) {
+  void cycle32(int l, const zf* b, zf* x, int nrhs, const zd* in64 = nullptr, zd* out64 = nullptr) {
+    FineFuse<float> fin;
+    fin.b64 = in64;
+    fin.b_out = in64 ? lv[0].b32 : nullptr;
     if (L() == 1) {
-      smooth32<S>(0, x, b, nrhs, p.pre + p.post);
+      fin.x64 = out64;
+      smooth32<S>(0, x, b, nrhs, p.pre + p.post, fin);
       check_launch();
       return;
     }
@@ -554,7 +603,7 @@ struct bamg_hierarchy {
     }
     Level& Lv = lv[l];
     Level& C = lv[l + 1];
-    smooth32<S>(l, x, b, nrhs, p.pre);
+    smooth32<S>(l, x, b, nrhs, p.pre, fin);
     apply32<S>(l, x, Lv.r32, b, nrhs);
     // the restriction also zeroes the coarse initial guess, which the coarsest
     // solve does not need (it writes all of x)
@@ -577,10 +626,27 @@ struct bamg_hierarchy {
       check_launch();
       return;
     }
+    if (l == 0 && p.post >= 1 && fine_fuse_ok(f32, xsw32, xil32, nrhs)) {
+      // the prolongation inside the first post-smoothing sweep, the FP64
+      // output (if asked) from the last
+      FineFuse<float> fz;
+      fz.P = Lv.P32;
+      fz.xc = C.x32;
+      fz.x64 = out64;
+      smooth32<S>(0, x, b, nrhs, p.post, fz);
+      check_launch();
+      return;
+    }
+    if (out64) throw HipFail("mixed cycle: FP64 output where the blocked sweep does not apply");
     if (l == 0) launch_prolong_fine(f32, Lv.P32, C.x32, x, nrhs, s);
     else launch_prolong_coarse(Lv.ex, Lv.ey, Lv.P32, C.x32, x, nrhs, s);
     smooth32<S>(l, x, b, nrhs, p.post);
     check_launch();
+  }
+  // the mixed cycle can take its input and give its output in FP64 through
+  // the level-0 sweeps
+  bool fine_io_ok(int nrhs) const {
+    return fine_fuse_ok(f32, xsw32, xil32, nrhs) && (L() == 1 ? p.pre + p.post >= 1 : (p.pre >= 1 && p.post >= 1));
   }
   // the K-cycle visit of kvisit with FP32 vectors (FP64 sums and coefficients)
   template <typename S>
@@ -605,15 +671,20 @@ struct bamg_hierarchy {
     check_launch();
   }
   // z = M v for nrhs FP64 level-0 vectors through the FP32 cycle
+  // (where the level-0 sweeps are blocked in LDS, the conversions ride in
+  // the first and last sweeps)
   void precondition_mixed(const zd* v, zd* z, int nrhs) {
     Level& L0 = lv[0];
-    launch_convert_zero(v, L0.b32, L0.x32, L0.n * nrhs, s);
+    const bool io = fine_io_ok(nrhs);
+    if (!io) launch_convert_zero(v, L0.b32, L0.x32, L0.n * nrhs, s);
+    const zd* in64 = io ? v : nullptr;
+    zd* out64 = io ? z : nullptr;
     switch (p.precision) {
-      case BAMG_MIXED_FP16: cycle32<hcx>(0, L0.b32, L0.x32, nrhs); break;
-      case BAMG_MIXED_BF16: cycle32<bcx>(0, L0.b32, L0.x32, nrhs); break;
-      default: cycle32<zf>(0, L0.b32, L0.x32, nrhs); break;
+      case BAMG_MIXED_FP16: cycle32<hcx>(0, L0.b32, L0.x32, nrhs, in64, out64); break;
+      case BAMG_MIXED_BF16: cycle32<bcx>(0, L0.b32, L0.x32, nrhs, in64, out64); break;
+      default: cycle32<zf>(0, L0.b32, L0.x32, nrhs, in64, out64); break;
     }
-    launch_convert(L0.x32, z, L0.n * nrhs, s);
+    if (!io) launch_convert(L0.x32, z, L0.n * nrhs, s);
     check_launch();
   }
   // z = M v in the hierarchy's precision
@@ -621,8 +692,9 @@ struct bamg_hierarchy {
     if (mixed()) {
       precondition_mixed(v, z, nrhs);
     } else {
-      launch_fill_zero(z, lv[0].n * nrhs, s);
-      cycle(0, v, z, nrhs);
+      const bool zero = fine_zero_ok(nrhs);
+      if (!zero) launch_fill_zero(z, lv[0].n * nrhs, s);
+      cycle(0, v, z, nrhs, zero);
     }
   }
   template <typename S>
