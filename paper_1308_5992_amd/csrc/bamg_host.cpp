@@ -754,19 +754,25 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
         hipStream_t sc = h->s;
         if (R == 1 && j > 0) launch_bscale_rnorm(h->w, vj, n, hn2, sc);
         h->precondition(vj, zj, R);
-        h->apply(0, zj, h->w, nullptr, R);
-        launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, sc);
-        // the second projection's inner products and the norm ride on the
-        // multi-axpys before them
-        if (!launch_baxpy_dot(h->V, j + 1, h1, -1.0, h->w, n, R, j + 1, h->partial, h2, sc) ||
-            !launch_baxpy_dot(h->V, j + 1, h2, -1.0, h->w, n, R, 0, h->partial, hn2, sc)) {
+        if (baxpy_dot_applies(n)) {
+          // the second projection's inner products and the norm ride on the
+          // multi-axpys before them; the reductions also write their results
+          // to the pinned host copy themselves (no copy after them)
+          h->apply(0, zj, h->w, nullptr, R);
+          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, sc, hh);
+          launch_baxpy_dot(h->V, j + 1, h1, -1.0, h->w, n, R, j + 1, h->partial, h2, sc, hh + 64 * R);
+          launch_baxpy_dot(h->V, j + 1, h2, -1.0, h->w, n, R, 0, h->partial, hn2, sc, hh + 128 * R);
+          check_launch();
+        } else {
+          h->apply(0, zj, h->w, nullptr, R);
+          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, sc);
           launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, sc);
           launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, sc);
           launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, sc);
           launch_norms(h->w, n, R, n, h->partial, hn2, sc, nullptr, true);
+          check_launch();
+          HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
         }
-        check_launch();
-        HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
       });
       HIPCHK(hipStreamSynchronize(s));
       jmax = j + 1;

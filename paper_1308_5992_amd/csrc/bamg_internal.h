@@ -205,6 +205,12 @@ void launch_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* r, cx<
                           cx<T>* xz = nullptr);
 template <typename T>
 void launch_prolong_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s);
+// rc = P^H (b - Dhat x) in one launch, the bits of launch_dhat then
+// launch_restrict_fine (r itself is not stored), and xz = 0 if not null;
+// false (nothing launched) where the lattice does not take its tiles
+template <typename T>
+bool launch_residual_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* x, const cx<T>* b, cx<T>* rc,
+                                   int nrhs, hipStream_t s, cx<T>* xz = nullptr);
 // D_1 = P^H Dhat P in 7-offset blocks
 void launch_galerkin_fine(const Fine& f, const zd* P, zd* D1, hipStream_t s);
 // gather test vectors into aggregate blocks and fit P (level 0)
@@ -336,13 +342,17 @@ void launch_convert(const Tin* in, Tout* out, size_t n, hipStream_t s);
 void launch_convert_zero(const zd* in, zf* out, zf* zero_out, size_t n, hipStream_t s);
 // batched forms over R right-hand sides: basis vector v of right-hand side r
 // at X + (v*R + r)*n, w_r at W + r*n, coefficients at stride 64 per r
-void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s);
+// (host_out, if not null: pinned host memory laid out as out that receives a
+// copy of the results from the reduction kernel itself)
+void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s,
+                      zd* host_out = nullptr);
 void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, hipStream_t s);
 // W_r += sign sum_{v < nv} X_{v,r} h[r][v], then out[r][v] = X_{v,r}^H W_r for
 // v < nd (nd > 0) or out[r] = |W_r|^2 (nd = 0), in one pass over W_r per
 // launch pair; false (nothing launched) where a chunk is too long
 bool launch_baxpy_dot(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, int nd, zd* partial,
-                      zd* out, hipStream_t s);
+                      zd* out, hipStream_t s, zd* host_out = nullptr);
+bool baxpy_dot_applies(size_t n);
 // y_r = c[r] x_r (c device, real)
 void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStream_t s);
 // one vector: y = x / sqrt(nrm2[0].x)

@@ -57,28 +57,32 @@ __global__ __launch_bounds__(BT) void k_dot_partial(const zd* __restrict__ X, si
   if (threadIdx.x == 0) partial[(size_t)b * nv + v] = s;
 }
 
+// (host_out, if not null: pinned host memory that receives a copy of out)
 __global__ __launch_bounds__(BT) void k_reduce_partial(const zd* __restrict__ partial, int nb, int nv,
-                                                       zd* __restrict__ out) {
+                                                       zd* __restrict__ out, zd* __restrict__ host_out) {
   __shared__ zd sh[BT];
   const int v = blockIdx.x;
   zd acc = {0, 0};
   for (int b = threadIdx.x; b < nb; b += BT) acc = acc + partial[(size_t)b * nv + v];
   const zd s = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[v] = s;
+  if (threadIdx.x == 0) {
+    out[v] = s;
+    if (host_out) host_out[v] = s;
+  }
 }
 
 void launch_multidot(const zd* X, size_t ldx, int nv, const zd* w, size_t n, zd* partial, zd* out,
                      hipStream_t s) {
   const int nb = blas_nblocks(n);
   hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, w, n, partial, (const int*)nullptr);
-  hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out, (zd*)nullptr);
 }
 
 void launch_norms(const zd* X, size_t ldx, int nv, size_t n, zd* partial, zd* out, hipStream_t s, const int* map,
                   bool fine) {
   const int nb = fine ? blas_nblocks_fine(n) : blas_nblocks(n);
   hipLaunchKernelGGL(k_dot_partial, dim3(nb, nv), dim3(BT), 0, s, X, ldx, nv, (const zd*)nullptr, n, partial, map);
-  hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out);
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(BT), 0, s, partial, nb, nv, out, (zd*)nullptr);
 }
 
 // w[i] += sign * sum_v X_v[i] h[v]
@@ -238,19 +242,24 @@ __global__ __launch_bounds__(BT) void k_bdot_partial(const zd* __restrict__ X, i
   if (threadIdx.x == 0) partial[((size_t)r * nb + b) * 64 + v] = s;
 }
 
-__global__ __launch_bounds__(BT) void k_breduce(const zd* __restrict__ partial, int nb, zd* __restrict__ out) {
+__global__ __launch_bounds__(BT) void k_breduce(const zd* __restrict__ partial, int nb, zd* __restrict__ out,
+                                                zd* __restrict__ host_out) {
   __shared__ zd sh[BT];
   const int v = blockIdx.x, r = blockIdx.y;
   zd acc = {0, 0};
   for (int b = threadIdx.x; b < nb; b += BT) acc = acc + partial[((size_t)r * nb + b) * 64 + v];
   const zd s = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[(size_t)r * 64 + v] = s;
+  if (threadIdx.x == 0) {
+    out[(size_t)r * 64 + v] = s;
+    if (host_out) host_out[(size_t)r * 64 + v] = s;
+  }
 }
 
-void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s) {
+void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* partial, zd* out, hipStream_t s,
+                      zd* host_out) {
   const int nb = blas_nblocks_fine(n);
   hipLaunchKernelGGL(k_bdot_partial, dim3(nb, nv, R), dim3(BT), 0, s, X, R, W, n, partial);
-  hipLaunchKernelGGL(k_breduce, dim3(nv, R), dim3(BT), 0, s, partial, nb, out);
+  hipLaunchKernelGGL(k_breduce, dim3(nv, R), dim3(BT), 0, s, partial, nb, out, host_out);
 }
 
 __global__ void k_bmultiaxpy(const zd* __restrict__ X, int nv, int R, const zd* __restrict__ h, double sign,
@@ -267,18 +276,59 @@ void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, siz
   hipLaunchKernelGGL(k_bmultiaxpy, dim3((unsigned)((n + 255) / 256), R), dim3(256), 0, s, X, nv, R, h, sign, W, n);
 }
 
+// The partial inner products of one chunk [lo, hi) of a right-hand side's
+// w with X_0..X_{nd-1} (X_v at X + (v R + r) n), for work-groups of PD_BT
+// threads: thread t holds w at lo + t + k PD_BT in wl[k], accumulates
+// conj(X_v) w over its entries in order from zero, and the work-group sums
+// the threads by the halving tree (t + off into t, off = PD_BT / 2 ... 1),
+// PD_VC vectors per tree; partial[(r nb + b) 64 + v]: the order of
+// k_bdot_partial.
+constexpr int PD_BT = 256, PD_VC = 8;
+template <int E>
+__device__ __forceinline__ void block_partial_dots(const zd* __restrict__ X, int R, int r, size_t n, size_t lo,
+                                                   size_t hi, const zd (&wl)[E], int nd, zd (*sh)[PD_BT],
+                                                   zd* __restrict__ partial, int nb, int b) {
+  const int tid = threadIdx.x;
+  for (int v0 = 0; v0 < nd; v0 += PD_VC) {
+#pragma unroll
+    for (int q = 0; q < PD_VC; ++q) {
+      const int v = v0 + q;
+      zd acc = {0, 0};
+      if (v < nd) {
+        const zd* xv = X + ((size_t)v * R + r) * n;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const size_t i = lo + tid + (size_t)k * PD_BT;
+          if (i < hi) acc = acc + cjmul_fixed(xv[i], wl[k]);
+        }
+      }
+      sh[q][tid] = acc;
+    }
+    __syncthreads();
+    for (int off = PD_BT / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+#pragma unroll
+        for (int q = 0; q < PD_VC; ++q) sh[q][tid] = sh[q][tid] + sh[q][tid + off];
+      }
+      __syncthreads();
+    }
+    if (tid < PD_VC && v0 + tid < nd) partial[((size_t)r * nb + b) * 64 + v0 + tid] = sh[tid][0];
+    __syncthreads();
+  }
+}
+
 // A Gram-Schmidt step and the reduction after it in one launch: block b of
 // right-hand side r updates its chunk of w_r by the multi-axpy
 // (k_bmultiaxpy's arithmetic), then forms from the updated chunk the partial
 // inner products with X_0..X_{nd-1} (nd > 0; k_bdot_partial's block
-// decomposition, per-thread order and tree, BAX_VC vectors per tree) or the
+// decomposition, per-thread order and tree; block_partial_dots) or the
 // partial squared norm (nd = 0; partial[b R + r], the layout of
 // k_dot_partial).  A chunk holds at most BAX_E entries per thread.
-constexpr int BAX_E = 4, BAX_VC = 8;
+constexpr int BAX_E = 4;
 __global__ __launch_bounds__(BT) void k_baxpy_dot(const zd* __restrict__ X, int nv, int R, const zd* __restrict__ h,
                                                   double sign, zd* __restrict__ W, size_t n, int nd,
                                                   zd* __restrict__ partial) {
-  __shared__ zd sh[BAX_VC][BT];
+  __shared__ zd sh[PD_VC][PD_BT];
   const int b = blockIdx.x, r = blockIdx.y, nb = gridDim.x, tid = threadIdx.x;
   const size_t chunk = (n + nb - 1) / nb;
   const size_t lo = (size_t)b * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
@@ -304,42 +354,21 @@ __global__ __launch_bounds__(BT) void k_baxpy_dot(const zd* __restrict__ X, int 
     if (tid == 0) partial[(size_t)b * R + r] = s;
     return;
   }
-  for (int v0 = 0; v0 < nd; v0 += BAX_VC) {
-#pragma unroll
-    for (int q = 0; q < BAX_VC; ++q) {
-      const int v = v0 + q;
-      zd acc = {0, 0};
-      if (v < nd) {
-        const zd* xv = X + ((size_t)v * R + r) * n;
-#pragma unroll
-        for (int k = 0; k < BAX_E; ++k) {
-          const size_t i = lo + tid + (size_t)k * BT;
-          if (i < hi) acc = acc + cjmul_fixed(xv[i], wl[k]);
-        }
-      }
-      sh[q][tid] = acc;
-    }
-    __syncthreads();
-    for (int off = BT / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-#pragma unroll
-        for (int q = 0; q < BAX_VC; ++q) sh[q][tid] = sh[q][tid] + sh[q][tid + off];
-      }
-      __syncthreads();
-    }
-    if (tid < BAX_VC && v0 + tid < nd) partial[((size_t)r * nb + b) * 64 + v0 + tid] = sh[tid][0];
-    __syncthreads();
-  }
+  block_partial_dots<BAX_E>(X, R, r, n, lo, hi, wl, nd, sh, partial, nb, b);
+}
+
+bool baxpy_dot_applies(size_t n) {
+  const int nb = blas_nblocks_fine(n);
+  return (n + nb - 1) / nb <= (size_t)BAX_E * BT;
 }
 
 bool launch_baxpy_dot(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, int nd, zd* partial,
-                      zd* out, hipStream_t s) {
+                      zd* out, hipStream_t s, zd* host_out) {
   const int nb = blas_nblocks_fine(n);
-  const size_t chunk = (n + nb - 1) / nb;
-  if (chunk > (size_t)BAX_E * BT || nd < 0 || nd > 64) return false;
+  if (!baxpy_dot_applies(n) || nd < 0 || nd > 64) return false;
   hipLaunchKernelGGL(k_baxpy_dot, dim3(nb, R), dim3(BT), 0, s, X, nv, R, h, sign, W, n, nd, partial);
-  if (nd > 0) hipLaunchKernelGGL(k_breduce, dim3(nd, R), dim3(BT), 0, s, partial, nb, out);
-  else hipLaunchKernelGGL(k_reduce_partial, dim3(R), dim3(BT), 0, s, partial, nb, R, out);
+  if (nd > 0) hipLaunchKernelGGL(k_breduce, dim3(nd, R), dim3(BT), 0, s, partial, nb, out, host_out);
+  else hipLaunchKernelGGL(k_reduce_partial, dim3(R), dim3(BT), 0, s, partial, nb, R, out, host_out);
   return true;
 }
 

@@ -143,16 +143,17 @@ void launch_eo_reconstruct(const Fine& f, const zd* b, const zd* xe, zd* x, int 
 // halo into LDS; stage 2 applies H_eo from LDS.  x and the links are read
 // once from HBM per tile (halo re-reads hit L2).
 // ---------------------------------------------------------------------------
+// The two stages of k_dhat for one TX x TY tile of even sites at (x0, y0)
+// (half-x, y), one site per thread: H_oe x on the odd sites of the tile and
+// its one-site halo into LDS (t0, t1: (TY + 2)(TX + 2) entries each), then
+// H_eo of that at the thread's site e: (a0, a1) = (H_eo H_oe x)_e without the
+// factor kappa^2/4.  The caller finishes y_e = x_e - kappa^2/4 (a0, a1).
 template <typename T, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_dhat(FineT<T> f, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
-                                                 const cx<T>* __restrict__ b) {
+__device__ __forceinline__ void dhat_tile_hops(const FineT<T>& f, const cx<T>* __restrict__ xv, cx<T>* t0, cx<T>* t1,
+                                               int x0, int y0, cx<T>& a0, cx<T>& a1, int& e) {
   using C = cx<T>;
   constexpr int W = TX + 2, NREG = (TY + 2) * (TX + 2), NT = TX * TY;
-  __shared__ C t0[NREG], t1[NREG];
   const int N = f.N, NH = f.NH;
-  const size_t n = (size_t)N * NH * 2;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const C* __restrict__ xv = x + blockIdx.z * n;
   const C* __restrict__ Ue = f.Ue;
   const C* __restrict__ Uo = f.Uo;
   const int tid = threadIdx.x;
@@ -163,26 +164,40 @@ __global__ __launch_bounds__(TX* TY) void k_dhat(FineT<T> f, const cx<T>* __rest
     int w = yy * NH + xhh;
     int jpx = hidx(lx + 1, yy, N, NH), jmx = hidx(lx - 1, yy, N, NH);
     int jpy = hidx(lx, yy + 1, N, NH), jmy = hidx(lx, yy - 1, N, NH);
-    C a0 = {0, 0}, a1 = {0, 0};
-    hop_acc(0, Uo[2 * w], xv[2 * jpx], xv[2 * jpx + 1], a0, a1);
-    hop_acc(1, conj(Ue[2 * jmx]), xv[2 * jmx], xv[2 * jmx + 1], a0, a1);
-    hop_acc(2, Uo[2 * w + 1], xv[2 * jpy], xv[2 * jpy + 1], a0, a1);
-    hop_acc(3, conj(Ue[2 * jmy + 1]), xv[2 * jmy], xv[2 * jmy + 1], a0, a1);
-    t0[q] = a0;
-    t1[q] = a1;
+    C b0 = {0, 0}, b1 = {0, 0};
+    hop_acc(0, Uo[2 * w], xv[2 * jpx], xv[2 * jpx + 1], b0, b1);
+    hop_acc(1, conj(Ue[2 * jmx]), xv[2 * jmx], xv[2 * jmx + 1], b0, b1);
+    hop_acc(2, Uo[2 * w + 1], xv[2 * jpy], xv[2 * jpy + 1], b0, b1);
+    hop_acc(3, conj(Ue[2 * jmy + 1]), xv[2 * jmy], xv[2 * jmy + 1], b0, b1);
+    t0[q] = b0;
+    t1[q] = b1;
   }
   __syncthreads();
   const int ly = tid / TX, lxh = tid - ly * TX;
   const int yy = y0 + ly, xhh = x0 + lxh, p = yy & 1;
-  const int e = yy * NH + xhh;
+  e = yy * NH + xhh;
   const int qpx = (ly + 1) * W + lxh + 1 + p, qmx = (ly + 1) * W + lxh + p;
   const int qpy = (ly + 2) * W + lxh + 1, qmy = ly * W + lxh + 1;
   const int omx = yy * NH + wrapn(xhh + p - 1, NH), omy = wrapn(yy - 1, N) * NH + xhh;
-  C a0 = {0, 0}, a1 = {0, 0};
+  a0 = C{0, 0};
+  a1 = C{0, 0};
   hop_acc(0, Ue[2 * e], t0[qpx], t1[qpx], a0, a1);
   hop_acc(1, conj(Uo[2 * omx]), t0[qmx], t1[qmx], a0, a1);
   hop_acc(2, Ue[2 * e + 1], t0[qpy], t1[qpy], a0, a1);
   hop_acc(3, conj(Uo[2 * omy + 1]), t0[qmy], t1[qmy], a0, a1);
+}
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_dhat(FineT<T> f, const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                 const cx<T>* __restrict__ b) {
+  using C = cx<T>;
+  constexpr int NREG = (TY + 2) * (TX + 2);
+  __shared__ C t0[NREG], t1[NREG];
+  const size_t n = (size_t)f.N * f.NH * 2;
+  const C* __restrict__ xv = x + blockIdx.z * n;
+  C a0, a1;
+  int e;
+  dhat_tile_hops<T, TX, TY>(f, xv, t0, t1, blockIdx.x * TX, blockIdx.y * TY, a0, a1, e);
   const T k2q = (T)(0.25 * f.kappa2);
   C r0 = sub_scaled(xv[2 * e], k2q, a0), r1 = sub_scaled(xv[2 * e + 1], k2q, a1);
   C* yv = y + blockIdx.z * n;
@@ -193,6 +208,48 @@ __global__ __launch_bounds__(TX* TY) void k_dhat(FineT<T> f, const cx<T>* __rest
   }
   yv[2 * e] = r0;
   yv[2 * e + 1] = r1;
+}
+
+// The residual r = b - Dhat x and its restriction r_c = P^H r in one
+// launch, for the tiles of k_dhat with TX = 64, TY = 4: a tile then holds 16
+// whole 4 x 4 aggregates (one aggregate row), whose 256 restricted entries
+// (2 spins x 8 columns each) are formed from the tile's residual in LDS with
+// the arithmetic of k_restrict_fine.  r itself is not stored.  xz (if not
+// null) = 0 on the same entries (the coarse level's initial guess).
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_restrict_fine(FineT<T> f, const cx<T>* __restrict__ P,
+                                                               const cx<T>* __restrict__ x, const cx<T>* __restrict__ b,
+                                                               cx<T>* __restrict__ rc, cx<T>* __restrict__ xz) {
+  using C = cx<T>;
+  constexpr int TX = 64, TY = 4, NREG = (TY + 2) * (TX + 2);
+  __shared__ C t0[NREG], t1[NREG];
+  __shared__ C rs[TY * TX * 2];  // the tile's residual, [row][half-x][spin]
+  const size_t n = (size_t)f.N * f.NH * 2;
+  const C* __restrict__ xv = x + blockIdx.z * n;
+  const C* __restrict__ bv = b + blockIdx.z * n;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  C a0, a1;
+  int e;
+  dhat_tile_hops<T, TX, TY>(f, xv, t0, t1, x0, y0, a0, a1, e);
+  const T k2q = (T)(0.25 * f.kappa2);
+  const C r0 = sub_scaled(xv[2 * e], k2q, a0), r1 = sub_scaled(xv[2 * e + 1], k2q, a1);
+  const int tid = threadIdx.x;
+  rs[2 * tid] = bv[2 * e] - r0;
+  rs[2 * tid + 1] = bv[2 * e + 1] - r1;
+  __syncthreads();
+  const int cxn = f.NH / 4, cyn = f.N / 4;
+  const int al = tid >> 4, d = tid & 15, s = d >> 3, k = d & 7;
+  const int a = (y0 / 4) * cxn + x0 / 4 + al;
+  const C* Pa = P + ((size_t)a * 2 + s) * 16 * 8;
+  C acc = {0, 0};
+#pragma unroll
+  for (int row = 0; row < 16; ++row) {
+    const int ly = row >> 2, lx = row & 3;
+    acc = acc + cjmul_fixed(Pa[row * 8 + k], rs[2 * (ly * TX + 4 * al + lx) + s]);
+  }
+  const size_t nc = (size_t)cxn * cyn * 16;
+  rc[blockIdx.z * nc + (size_t)a * 16 + d] = acc;
+  if (xz) xz[blockIdx.z * nc + (size_t)a * 16 + d] = C{0, 0};
 }
 
 // The same operator for lattices with many tiles: 32 x 16 even sites per
@@ -453,6 +510,19 @@ __global__ __launch_bounds__(256) void k_dhat_strip(FineT<T> f, const cx<T>* __r
   }
 }
 
+// the streamed strips (0), the 32 x 16 tiles with the right-hand-side loop
+// (1) or the small tiles (2) for launch_dhat
+static int dhat_form(int N, int NH, int nrhs, size_t tsize) {
+  if (NH >= 64) {
+    const int S = (NH + STRIP - 1) / STRIP;
+    const int H = tsize == 8 ? 16 : 64;
+    const long items = (N % H == 0) ? (long)S * (N / H) * nrhs : 0;
+    if (items >= 2048 && (tsize == 8 || nrhs <= 4)) return 0;
+  }
+  if (NH % 32 == 0 && N % 16 == 0 && (NH / 32) * (N / 16) >= 256) return 1;
+  return 2;
+}
+
 template <typename T>
 void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, int nrhs, hipStream_t s) {
   const int N = f.N, NH = f.NH;
@@ -502,6 +572,20 @@ void launch_dhat(const FineT<T>& f, const cx<T>* x, cx<T>* y, const cx<T>* b, in
 }
 template void launch_dhat<double>(const FineT<double>&, const zd*, zd*, const zd*, int, hipStream_t);
 template void launch_dhat<float>(const FineT<float>&, const zf*, zf*, const zf*, int, hipStream_t);
+
+template <typename T>
+bool launch_residual_restrict_fine(const FineT<T>& f, const cx<T>* P, const cx<T>* x, const cx<T>* b, cx<T>* rc,
+                                   int nrhs, hipStream_t s, cx<T>* xz) {
+  // only where launch_dhat takes the small tiles (the other forms are faster
+  // on larger lattices)
+  if (f.NH % 64 != 0 || f.N % 4 != 0 || !b || nrhs < 1 || dhat_form(f.N, f.NH, nrhs, sizeof(T)) != 2) return false;
+  hipLaunchKernelGGL(k_residual_restrict_fine<T>, dim3(f.NH / 64, f.N / 4, nrhs), dim3(256), 0, s, f, P, x, b, rc, xz);
+  return true;
+}
+template bool launch_residual_restrict_fine<double>(const FineT<double>&, const zd*, const zd*, const zd*, zd*, int,
+                                                    hipStream_t, zd*);
+template bool launch_residual_restrict_fine<float>(const FineT<float>&, const zf*, const zf*, const zf*, zf*, int,
+                                                   hipStream_t, zf*);
 
 // ---------------------------------------------------------------------------
 // Rows of Dhat at even site (xh, y): e[n][s][t] = Dhat[(i,s), (j_n,t)] for the
@@ -2048,7 +2132,7 @@ __global__ void k_restrict_fine(FineT<T> f, const cx<T>* __restrict__ P, const c
   for (int row = 0; row < 16; ++row) {
     int ly = row >> 2, lx = row & 3;
     int e = (4 * Ay + ly) * f.NH + 4 * Ax + lx;
-    acc = acc + cjmul(Pa[row * 8 + k], rv[2 * e + s]);
+    acc = acc + cjmul_fixed(Pa[row * 8 + k], rv[2 * e + s]);
   }
   rc[blockIdx.y * nc + t] = acc;
   if (xz) xz[blockIdx.y * nc + t] = C{0, 0};  // the coarse level's zero initial guess

@@ -230,7 +230,8 @@ struct bamg_hierarchy {
       kcap = cap2;
       partial = dalloc<zd>((size_t)blas_nblocks_fine(n0) * 64 * kcap);  // the finer of the two block counts
       hdev = dalloc<zd>((size_t)3 * 64 * kcap);
-      HIPCHK(hipHostMalloc((void**)&hhost, (size_t)3 * 64 * kcap * sizeof(zd)));
+      // coherent: the Gram-Schmidt reductions write their results here directly
+      HIPCHK(hipHostMalloc((void**)&hhost, (size_t)3 * 64 * kcap * sizeof(zd), hipHostMallocCoherent));
       scal_dev = dalloc<double>(kcap);
       HIPCHK(hipHostMalloc((void**)&scal_host, (size_t)kcap * sizeof(double)));
       ycoef_dev = dalloc<zd>((size_t)64 * kcap);
@@ -467,8 +468,11 @@ struct bamg_hierarchy {
     Level& Lv = lv[l];
     Level& C = lv[l + 1];
     smooth(l, x, b, nrhs, p.pre, fz0);
-    apply(l, x, Lv.r, b, nrhs);  // r = b - A x
-    restrict_(l, Lv.r, C.b, nrhs, coarsest(l + 1) ? nullptr : C.x);  // and the coarse initial guess x = 0
+    zd* xz = coarsest(l + 1) ? nullptr : C.x;  // the coarse initial guess x = 0
+    if (!(l == 0 && launch_residual_restrict_fine(f, (const zd*)Lv.P, (const zd*)x, b, C.b, nrhs, s, xz))) {
+      apply(l, x, Lv.r, b, nrhs);  // r = b - A x
+      restrict_(l, Lv.r, C.b, nrhs, xz);
+    }
     if (kvisited(l + 1)) {
       kvisit(l + 1, C.b, C.x, nrhs);
     } else {
@@ -604,12 +608,15 @@ struct bamg_hierarchy {
     Level& Lv = lv[l];
     Level& C = lv[l + 1];
     smooth32<S>(l, x, b, nrhs, p.pre, fin);
-    apply32<S>(l, x, Lv.r32, b, nrhs);
     // the restriction also zeroes the coarse initial guess, which the coarsest
-    // solve does not need (it writes all of x)
+    // solve does not need (it writes all of x); on level 0 the residual and
+    // its restriction run in one launch where the lattice takes its tiles
     zf* xz = coarsest(l + 1) ? nullptr : C.x32;
-    if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
-    else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
+    if (!(l == 0 && launch_residual_restrict_fine(f32, (const zf*)Lv.P32, (const zf*)x, b, C.b32, nrhs, s, xz))) {
+      apply32<S>(l, x, Lv.r32, b, nrhs);
+      if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
+      else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
+    }
     if (kvisited(l + 1)) {
       kvisit32<S>(l + 1, C.b32, C.x32, nrhs);
     } else {
