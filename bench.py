@@ -624,11 +624,11 @@ COPY_SCALE = {"fetch_per_kib": 131090.8 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine_sweep", "mixed_fp16"): {"src": "fine.hip",
-                                   "sha256": "a51828fe6252e1b041604e7d30858a4ac2a1e43ee1cdf54e1dfcb0128a3fdb30",
-                                   "fetch_kib": 10149.5, "write_kib": 640.0, **COPY_SCALE},
+                                   "sha256": "736a8199b0549f0d3da4bfc8f0147eea340dc2f233d4f5989902e7d0f07fdc25",
+                                   "fetch_kib": 10166.0, "write_kib": 640.0, **COPY_SCALE},
     ("coarse_pair", "mixed_fp16"): {"src": "coarse.hip",
-                                    "sha256": "1af7dc7ba867ba801ea8bd5130bd51a0cafa3d004af88ac32aa1f458c8817a22",
-                                    "fetch_kib": 2673.5, "write_kib": 256.0, **COPY_SCALE},
+                                    "sha256": "59bf7771e29161171bd1d170ed84b6a1e52241bc3f59f553e96cf435e8734d60",
+                                    "fetch_kib": 2675.0, "write_kib": 256.0, **COPY_SCALE},
     # the packed products and their reductions, per call (the sum of the two kernels' counters):
     # the FP64 blocks (headline) and their FP32 copy (+c32)
     ("dense_g5", "mixed_fp16"): {"src": "dense.hip",
