@@ -1113,9 +1113,22 @@ constexpr int FS_NT = 512;               // threads per work-group of the blocke
 constexpr int FS_GROUPS = FS_NT / 16;    // 16-lane groups, one projection each per step
 constexpr int FS_BATCH = 16;             // 16-byte loads in flight per thread while filling LDS
 
+// Work-group barrier for LDS only: waits for this wave's LDS accesses
+// (lgkmcnt 0) but not for its global loads, which stay in flight across it
+// (__syncthreads waits for every outstanding access, so the next macro-step's
+// loads could not overlap the current one).  The empty asm statements keep the
+// compiler from moving LDS accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt 63, expcnt 7, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // the projections one 16-lane group makes in one colour (at most ITER), read
-// from LDS before they are needed: slot blocks, right-hand side, and the
-// position of the lane's support entry in the region (k < 0: none)
+// from global memory (L2) fs_ahead colours before they are needed: slot
+// blocks, right-hand side, stored Gram terms, and the position of the lane's
+// support entry in the region (k < 0: none)
 template <typename T, int ITER>
 struct FsColour {
   cx<T> B[ITER][4];
@@ -1123,28 +1136,46 @@ struct FsColour {
   cx<T> nu[ITER], g10[ITER];  // the row pair's stored Gram terms
   int e[ITER];
 };
+// colours read ahead: three, or one where four sets would not fit the
+// registers of the FP64 form with two projections per group
+template <typename T, int ITER>
+constexpr int fs_ahead() {
+  return (sizeof(T) == 8 && ITER == 2) ? 1 : 3;
+}
 
 template <typename T, int ITER>
-__device__ __forceinline__ FsColour<T, ITER> fs_colour(const int (&k)[ITER], bool act, int soff, const cx<T>* Bl,
-                                                       const cx<T>* bs, const cx<T>* gs, const int* uloc, bool hasb) {
-  // reads without branches (an absent projection reads entry 0 and drops
-  // it), so that they stay in flight while the current step computes
+__device__ __forceinline__ FsColour<T, ITER> fs_colour(const FineT<T>& f, const int (&k)[ITER], bool act, int slot,
+                                                       int soff, const int* usite, const int* uloc,
+                                                       const cx<T>* br, const zd* b64) {
+  // reads without branches on the data (an absent projection reads
+  // projection 0 and drops it), so that they stay in flight while the
+  // current colours compute
   FsColour<T, ITER> r;
   const cx<T> z = {0, 0};
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int kq = k[it] >= 0 ? k[it] : 0;
+    const size_t site = (size_t)usite[kq];
     r.e[it] = uloc[kq] + soff;
+    const cx<T>* Bp = f.Bst + (site * 9 + slot) * 4;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      const cx<T> v = Bl[kq * 36 + w];
+      const cx<T> v = Bp[w];
       r.B[it][w] = act ? v : z;
     }
-    const cx<T> v0 = bs[2 * kq], v1 = bs[2 * kq + 1];
-    r.b[it][0] = hasb ? v0 : z;
-    r.b[it][1] = hasb ? v1 : z;
-    r.nu[it] = gs[2 * kq];
-    r.g10[it] = gs[2 * kq + 1];
+    if (b64) {  // rounded as the conversion kernels round
+      const zd v0 = b64[2 * site], v1 = b64[2 * site + 1];
+      r.b[it][0] = cx<T>{(T)v0.x, (T)v0.y};
+      r.b[it][1] = cx<T>{(T)v1.x, (T)v1.y};
+    } else if (br) {
+      r.b[it][0] = br[2 * site];
+      r.b[it][1] = br[2 * site + 1];
+    } else {
+      r.b[it][0] = z;
+      r.b[it][1] = z;
+    }
+    r.nu[it] = f.Gst[2 * site];
+    r.g10[it] = f.Gst[2 * site + 1];
   }
   return r;
 }
@@ -1154,22 +1185,18 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
                                                                cx<T>* __restrict__ xout, const cx<T>* __restrict__ b,
                                                                FineFuse<T> fz) {
   using C = cx<T>;
-  constexpr int UB = 36 * (int)sizeof(C) / 16;  // 16-byte units of a site's slot blocks
   constexpr int US = 2 * (int)sizeof(C) / 16;   // 16-byte units of a site's two unknowns
   __shared__ uint4 sm[LDSB / 16];
   C* X = reinterpret_cast<C*>(sm);      // region of x, [Ru][Rv][2]
-  C* Bs = X + 2 * p.Ru * p.Rv;          // slot blocks of the projections, [nupd][36]
-  C* bs = Bs + 36 * p.nupd;             // their right-hand sides, [nupd][2]
-  C* gs = bs + 2 * p.nupd;              // their stored Gram terms, [nupd][2]
-  int* usite = reinterpret_cast<int*>(gs + 2 * p.nupd);  // their even-site index
-  int* uloc = usite + p.nupd;                            // their position in the region
+  int* usite = reinterpret_cast<int*>(X + 2 * p.Ru * p.Rv);  // the projections' even-site index
+  int* uloc = usite + p.nupd;                                // their position in the region
   const int tid = threadIdx.x;
   const int N = f.N, NH = f.NH;
   const int u0 = 1 + (int)(blockIdx.x % p.ntu) * p.Tu, v0 = 1 + (int)(blockIdx.x / p.ntu) * p.Tv;
   const size_t n = (size_t)N * NH * 2;
   const C* xr = xin + blockIdx.y * n;
   C* xw = xout + blockIdx.y * n;
-  // b64: b comes from the FP64 copy (converted below), not through the loads
+  // b64: b comes from the FP64 copy, rounded
   const zd* b64 = fz.b64 ? fz.b64 + blockIdx.y * n : nullptr;
   const C* br = (b && !b64) ? b + blockIdx.y * n : nullptr;
   const bool xzero = fz.xzero || b64;
@@ -1185,58 +1212,29 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
     usite[q] = site(u0 + i, v0 + j);
     uloc[q] = (i - p.i0) * p.Rv + (j - p.j0);
   }
-  __syncthreads();
-  // One round of loads fills the region of x, the slot blocks, the
-  // right-hand sides (if any) and the Gram terms, which lie in this order in
-  // LDS (16-byte units; without right-hand sides their place stays empty).
-  {
-    const int t1 = p.Ru * p.Rv * US, t2 = t1 + p.nupd * UB, t3 = t2 + (br ? p.nupd * US : 0);
-    const int t4 = t3 + p.nupd * US, gshift = br ? 0 : p.nupd * US;
+  // one round of loads fills the region of x (16-byte units)
+  if (!xzero) {
+    const int t1 = p.Ru * p.Rv * US;
     const uint4* x4 = reinterpret_cast<const uint4*>(xr);
-    const uint4* B4 = reinterpret_cast<const uint4*>(f.Bst);
-    const uint4* b4 = reinterpret_cast<const uint4*>(br);
-    const uint4* G4 = reinterpret_cast<const uint4*>(f.Gst);
-    for (int e0 = tid; e0 < t4; e0 += FS_NT * FS_BATCH) {
+    for (int e0 = tid; e0 < t1; e0 += FS_NT * FS_BATCH) {
       uint4 v[FS_BATCH];
 #pragma unroll
       for (int u = 0; u < FS_BATCH; ++u) {
         const int e = e0 + u * FS_NT;
         v[u] = make_uint4(0, 0, 0, 0);
-        if (e < t4 && !(xzero && e < t1)) {
-          const uint4* src;
-          size_t idx;
-          if (e < t1) {
-            const int q = e / US, li = q / p.Rv;
-            src = x4;
-            idx = (size_t)site(u0 + p.i0 + li, v0 + p.j0 + (q - li * p.Rv)) * US + (e - q * US);
-          } else if (e < t2) {
-            const int q = (e - t1) / UB;
-            src = B4;
-            idx = (size_t)usite[q] * UB + (e - t1 - q * UB);
-          } else if (e < t3) {
-            const int q = (e - t2) / US;
-            src = b4;
-            idx = (size_t)usite[q] * US + (e - t2 - q * US);
-          } else {
-            const int q = (e - t3) / US;
-            src = G4;
-            idx = (size_t)usite[q] * US + (e - t3 - q * US);
-          }
-          v[u] = src[idx];
+        if (e < t1) {
+          const int q = e / US, li = q / p.Rv;
+          v[u] = x4[(size_t)site(u0 + p.i0 + li, v0 + p.j0 + (q - li * p.Rv)) * US + (e - q * US)];
         }
       }
 #pragma unroll
       for (int u = 0; u < FS_BATCH; ++u) {
         const int e = e0 + u * FS_NT;
-        if (e < t4) sm[e < t3 ? e : e + gshift] = v[u];
+        if (e < t1) sm[e] = v[u];
       }
     }
-  }
-  if (b64) {  // the projections' right-hand sides from FP64, rounded as the conversion kernels round
-    for (int e = tid; e < 2 * p.nupd; e += FS_NT) {
-      const zd v = b64[2 * (size_t)usite[e >> 1] + (e & 1)];
-      bs[e] = C{(T)v.x, (T)v.y};
-    }
+  } else {
+    for (int e = tid; e < 2 * p.Ru * p.Rv; e += FS_NT) X[e] = C{0, 0};
   }
   __syncthreads();
   if (fz.P) {  // x + P xc on the region: the prolongation carried by this sweep
@@ -1252,8 +1250,6 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
   const bool act = lane < 9;
   const int slot = act ? lane : 0;
   const int soff = (nib(SLOT_DU1, slot) - 1) * p.Rv + (nib(SLOT_DV1, slot) - 1);
-  const C* Bl = Bs + slot * 4;  // the lane's slot block within a projection's 36 entries
-  const bool hasb = br != nullptr || b64 != nullptr;
   // the group's projections of every colour, fixed before the first step
   int kk[16][ITER];
 #pragma unroll
@@ -1263,9 +1259,14 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
       const int k = p.first[c] + g + it * FS_GROUPS;
       kk[c][it] = k < p.first[c + 1] ? k : -1;
     }
-  FsColour<T, ITER> cur = fs_colour<T, ITER>(kk[0], act, soff, Bl, bs, gs, uloc, hasb);
+  // colour c's data in ring[c % (AH + 1)], read AH colours ahead
+  constexpr int AH = fs_ahead<T, ITER>();
+  FsColour<T, ITER> ring[AH + 1];
+#pragma unroll
+  for (int c = 0; c < AH; ++c) ring[c] = fs_colour<T, ITER>(f, kk[c], act, slot, soff, usite, uloc, br, b64);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
+    const FsColour<T, ITER>& cur = ring[c % (AH + 1)];
     C x0[ITER], x1[ITER];
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {  // the unknowns first: their reads head the LDS queue
@@ -1273,8 +1274,8 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
       x0[it] = act ? v0 : C{0, 0};
       x1[it] = act ? v1 : C{0, 0};
     }
-    FsColour<T, ITER> nxt;
-    if (c < 15) nxt = fs_colour<T, ITER>(kk[c < 15 ? c + 1 : c], act, soff, Bl, bs, gs, uloc, hasb);
+    if (c + AH < 16)
+      ring[(c + AH) % (AH + 1)] = fs_colour<T, ITER>(f, kk[c + AH < 16 ? c + AH : c], act, slot, soff, usite, uloc, br, b64);
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       if (kk[c][it] < 0) continue;  // whole 16-lane groups
@@ -1291,8 +1292,8 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
         X[2 * e + 1] = (x1[it] + cjmul_fixed(B[1], a0)) + cjmul_fixed(B[3], a1);
       }
     }
-    __syncthreads();
-    if (c < 15) cur = nxt;
+    // LDS only: the colours' reads from global memory stay in flight
+    lds_barrier();
   }
   if (b64) {  // the tile's right-hand side, rounded, for the sweeps that follow
     C* bo = fz.b_out + blockIdx.y * n;
@@ -1526,18 +1527,6 @@ struct FinePipePlan {
   int Tu, Tv, ntu, ntv, i0, j0, Ru, Rv, M, A;
   int si0[16], sj0[16], ni[16], nj[16], off[16];
 };
-
-// Work-group barrier for LDS only: waits for this wave's LDS accesses
-// (lgkmcnt 0) but not for its global loads, which stay in flight across it
-// (__syncthreads waits for every outstanding access, so the next macro-step's
-// loads could not overlap the current one).  The empty asm statements keep the
-// compiler from moving LDS accesses across the barrier.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt 63, expcnt 7, lgkmcnt 0
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
 
 // sum over the 4 lanes of a quad: partner q ^ 2, then q ^ 1 (the last two
 // steps of the 16-lane butterfly, in its pair order)
