@@ -669,6 +669,26 @@ __device__ void dhat_rows(const Fine& f, int xh, int y, zd e[9][2][2], int jn[9]
 //   alpha_1 = (b_1 - d_1 x - G10 alpha_0) / nu_1,
 // so one group reduction of (d_0 x, d_1 x, nu_0, nu_1, G10) suffices.
 // ---------------------------------------------------------------------------
+// The coefficients of a site's two sequential row projections:
+// alpha_0 = e_0 / nu_0 and alpha_1 = (e_1 - G10 alpha_0) / nu_1 (e_i the row
+// residuals).  In FP32 as products with 1 / nu: the reciprocals depend only on
+// the stored norms, so they leave the residual's dependency chain (the FP32
+// sweep at 256^2: 17.7 -> 16.3 us); in FP64 as quotients (the reciprocals
+// measured slower there).  Every form of the fine sweep forms them here and
+// so agrees bitwise; a zero norm gives a zero coefficient.
+template <typename T>
+__device__ __forceinline__ void kz_coefs(cx<T> nu, cx<T> g10, cx<T> e0, cx<T> e1, cx<T>& a0, cx<T>& a1) {
+  if constexpr (sizeof(T) == 4) {
+    const T i0 = nu.x > 0 ? T(1) / nu.x : T(0), i1 = nu.y > 0 ? T(1) / nu.y : T(0);
+    a0 = nu.x > 0 ? cx<T>{e0.x * i0, e0.y * i0} : cx<T>{0, 0};
+    const cx<T> f1 = e1 - cmul_fixed(g10, a0);
+    a1 = nu.y > 0 ? cx<T>{f1.x * i1, f1.y * i1} : cx<T>{0, 0};
+  } else {
+    a0 = nu.x > 0 ? cdiv_real(e0, nu.x) : cx<T>{0, 0};
+    a1 = nu.y > 0 ? cdiv_real(e1 - cmul_fixed(g10, a0), nu.y) : cx<T>{0, 0};
+  }
+}
+
 // Per-slot tables packed in 4-bit fields so that a lane-dependent lookup is
 // pure register arithmetic: displacement + 2 of slot n, and d + 1 of the
 // first / second hop of the (up to two) two-hop paths reaching slot n.
@@ -903,8 +923,8 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine(FineT<T> f, int colour, in
     }
     const C r0 = grp16_sum(cmul_fixed(Bk[0][0], x0[k]) + cmul_fixed(Bk[0][1], x1[k]));
     const C r1 = grp16_sum(cmul_fixed(Bk[1][0], x0[k]) + cmul_fixed(Bk[1][1], x1[k]));
-    const C a0 = nu.x > 0 ? cdiv_real(b0[k] - r0, nu.x) : C{0, 0};
-    const C a1 = nu.y > 0 ? cdiv_real((b1[k] - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+    C a0, a1;
+    kz_coefs(nu, g10, b0[k] - r0, b1[k] - r1, a0, a1);
     if (act) {
       x[r * n + 2 * jn] = (x0[k] + cjmul_fixed(Bk[0][0], a0)) + cjmul_fixed(Bk[1][0], a1);
       x[r * n + 2 * jn + 1] = (x1[k] + cjmul_fixed(Bk[0][1], a0)) + cjmul_fixed(Bk[1][1], a1);
@@ -1004,8 +1024,8 @@ __global__ __launch_bounds__(64) void k_kaczmarz_fine_il(FineT<T> f, int colour,
     b0 = bi[((size_t)i * 2) * R + r];
     b1 = bi[((size_t)i * 2 + 1) * R + r];
   }
-  const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
-  const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+  C a0, a1;
+  kz_coefs(nu, g10, b0 - r0, b1 - r1, a0, a1);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (k == 2 && !q0) break;
@@ -1285,8 +1305,8 @@ __global__ __launch_bounds__(FS_NT) void k_kaczmarz_fine_sweep(FineT<T> f, FineS
       const C nu = cur.nu[it], g10 = cur.g10[it];
       const C r0 = grp16_sum(cmul_fixed(B[0], x0[it]) + cmul_fixed(B[1], x1[it]));
       const C r1 = grp16_sum(cmul_fixed(B[2], x0[it]) + cmul_fixed(B[3], x1[it]));
-      const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
-      const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+      C a0, a1;
+      kz_coefs(nu, g10, b0 - r0, b1 - r1, a0, a1);
       if (act) {
         X[2 * e] = (x0[it] + cjmul_fixed(B[0], a0)) + cjmul_fixed(B[2], a1);
         X[2 * e + 1] = (x1[it] + cjmul_fixed(B[1], a0)) + cjmul_fixed(B[3], a1);
@@ -1475,8 +1495,8 @@ __global__ __launch_bounds__(FSS_NT) void k_kaczmarz_fine_sweep_s(FineT<T> f, Fi
       const C nu = gC[2 * kl], g10 = gC[2 * kl + 1];
       const C r0 = grp16_sum(cmul_fixed(B[0], x0) + cmul_fixed(B[1], x1));
       const C r1 = grp16_sum(cmul_fixed(B[2], x0) + cmul_fixed(B[3], x1));
-      const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
-      const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+      C a0, a1;
+      kz_coefs(nu, g10, b0 - r0, b1 - r1, a0, a1);
       if (act) {
         X[2 * e] = (x0 + cjmul_fixed(B[0], a0)) + cjmul_fixed(B[2], a1);
         X[2 * e + 1] = (x1 + cjmul_fixed(B[1], a0)) + cjmul_fixed(B[3], a1);
@@ -1684,8 +1704,8 @@ __global__ __launch_bounds__(FP_NT) void k_kaczmarz_fine_pipe(FineT<T> f, FinePi
       const C r1 = quad_sum((w1[0] + (q0 ? w1[2] : zr)) + (w1[1] + zr));
       const C b0 = BR[site * 2], b1 = BR[site * 2 + 1];
       const C nu = cur.nu, g10 = cur.g10;
-      const C a0 = nu.x > 0 ? cdiv_real(b0 - r0, nu.x) : C{0, 0};
-      const C a1 = nu.y > 0 ? cdiv_real((b1 - r1) - cmul_fixed(g10, a0), nu.y) : C{0, 0};
+      C a0, a1;
+      kz_coefs(nu, g10, b0 - r0, b1 - r1, a0, a1);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         if (k < 2 || q0) {
