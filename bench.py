@@ -624,7 +624,7 @@ COPY_SCALE = {"fetch_per_kib": 131090.8 / 262144.0, "write_per_kib": 262144.0 / 
 PMC_PROFILE = "profiles/roofline_kernels_c3_256_mixed_fp16_pmc.md"
 PMC_TRAFFIC = {
     ("fine_sweep", "mixed_fp16"): {"src": "fine.hip",
-                                   "sha256": "b09782cdd35f800c5089450a78962c3b684c9aeb563d90d9a27f6938e2cea3b7",
+                                   "sha256": "607b1a3a175d23870f457411a1aba9f6b8c81191c9bbe5eb94820270b6cc3a23",
                                    "fetch_kib": 10143.5, "write_kib": 640.0, **COPY_SCALE},
     ("coarse_pair", "mixed_fp16"): {"src": "coarse.hip",
                                     "sha256": "59bf7771e29161171bd1d170ed84b6a1e52241bc3f59f553e96cf435e8734d60",

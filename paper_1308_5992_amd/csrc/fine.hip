@@ -1098,9 +1098,10 @@ void launch_smooth_fine_il(const FineT<T>& f, int ncol, int per_colour, cx<T>* x
 // (rectangles, on the host) and gives, per colour, the sites a work-group must
 // project and, at the start, the region it must read (the tile plus 2 sites
 // on each side in u and 14 in v for tiles starting at u = v = 1 mod 4).  A
-// work-group copies that region of x, the slot blocks and the right-hand
-// sides of all its projections into LDS, runs the 16 colours with a barrier
-// between them and writes its tile.  The sweep reads xin and writes xout:
+// work-group copies that region of x into LDS, reads the slot blocks,
+// right-hand sides and Gram terms of its projections into registers a few
+// colours ahead, runs the 16 colours with a barrier between them and writes
+// its tile.  The sweep reads xin and writes xout:
 // other work-groups read a tile's old values as their halo, so the two must
 // not overlap.  Each projection needed for the tile
 // sees the values the colour-by-colour sweep gives it, and is evaluated with
