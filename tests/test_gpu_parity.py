@@ -685,6 +685,34 @@ def test_mixed_solve_reaches_fp64_accuracy(bamg, prec, c32):
     assert full < 2e-10 and dx < 1e-9
 
 
+def test_work_carried_by_the_fine_sweeps_gives_the_same_bits(bamg):
+    """One right-hand side takes the fine sweep blocked in LDS, which carries
+    the mixed preconditioner's input conversion and zero start, the
+    prolongation into the first post-smoothing sweep and the FP64 output of
+    the last (FP32 at 320^2; the FP64 cycle at 256^2 carries the
+    prolongation); two right-hand sides take the streaming sweep and the
+    separate conversion, prolongation and conversion launches.  Every other
+    kernel of the cycle is the same for both (fused colour pairs on level 1,
+    colour passes below, the packed coarsest product), and right-hand sides
+    are independent, so the preconditioner (op 9) and the FP64 cycle (op 5)
+    give each right-hand side the same bits either way."""
+    for prec, op, N, L in ((1, bamg.OP_CYCLE_MIXED, 320, 4), (0, bamg.OP_CYCLE, 256, 3)):
+        fp32 = prec != 0
+        assert bamg.bamg_fine_sweep_plan(N, 1, fp32=fp32)[0] == 1 and bamg.bamg_fine_sweep_plan(N, 2, fp32=fp32)[0] == 2
+        U = inputs.gauge_metropolis(N, 3.0, 20, 11)
+        B = dev(inputs.gaussian((2, N * N), 98))
+        h = make_h(bamg, U, -0.05, n_levels=L, setup_sweeps=1, setup_adapt=0, precision=prec)
+        assert bamg.bamg_n_levels(h) == L
+        X2 = torch.zeros_like(B)
+        bamg.bamg_level_op(h, 0, op, B, X2, 2)
+        for r in range(2):
+            x1 = torch.zeros(1, N * N, dtype=torch.complex128, device="cuda:0")
+            bamg.bamg_level_op(h, 0, op, B[r:r + 1].contiguous(), x1, 1)
+            assert torch.equal(x1[0], X2[r]), (prec, r)
+        assert bool(torch.isfinite(X2).all()) and float(X2.abs().max()) > 0
+        bamg.bamg_free(h)
+
+
 @pytest.mark.parametrize("prec,c32", [("fp16", 0), ("bf16", 0), ("fp16", 1)])
 def test_mixed_batch_results_do_not_depend_on_the_batch(bamg, prec, c32):
     w = inputs.workload("c1_32_b3")
