@@ -118,6 +118,13 @@ typedef struct {
                            FP64 inverse (FP64 in and out).  1: it reads FP32 copies of that inverse
                            (rounded to nearest), FP32 in and out: half the bytes of the coarsest read,
                            relative rounding 2^-24 per entry */
+  int32_t lookahead;    /* bamg_solve only (one right-hand side; the batched solves are not affected).
+                           1 (default): while the estimated residual exceeds 1000 tol, FGMRES iteration
+                           j + 1 (its cycle, Dhat, Gram-Schmidt) is queued on the stream before the host
+                           has read iteration j's norms, so that the host's convergence test overlaps
+                           the device's work; if the test stops the solve, the queued iteration ran for
+                           nothing (never used).  0: off.  2: at every iteration (a check that the
+                           results do not depend on it).  Results are bitwise the same in all three. */
 } bamg_params;
 
 typedef struct {

@@ -46,6 +46,7 @@ class bamg_params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("init_tv_host", ctypes.c_void_p), ("stream", ctypes.c_void_p),
         ("graphs", ctypes.c_int32), ("setup_mode", ctypes.c_int32), ("n_ev", ctypes.c_int32),
         ("boot_nu1", ctypes.c_int32), ("boot_nu2", ctypes.c_int32), ("coarsest_fp32", ctypes.c_int32),
+        ("lookahead", ctypes.c_int32),
     ]
 
 

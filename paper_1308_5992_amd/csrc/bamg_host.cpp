@@ -79,6 +79,7 @@ bool valid_params(const bamg_params* p, std::string& why) {
   if (p->setup_mode && (p->boot_nu1 < 0 || p->boot_nu2 < 0)) { why = "negative bootstrap sweep count"; return false; }
   if (p->coarsest_fp32 != 0 && p->coarsest_fp32 != 1) { why = "coarsest_fp32 must be 0 or 1"; return false; }
   if (p->coarsest_fp32 && p->precision == BAMG_FP64) { why = "coarsest_fp32 needs a mixed precision"; return false; }
+  if (p->lookahead < 0 || p->lookahead > 2) { why = "lookahead must be 0, 1 or 2"; return false; }
   return true;
 }
 
@@ -115,6 +116,7 @@ int bamg_default_params(bamg_params* p) {
   p->boot_nu1 = 10;
   p->boot_nu2 = 5;
   p->coarsest_fp32 = 0;
+  p->lookahead = 1;
   return BAMG_OK;
 }
 
@@ -745,36 +747,55 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
     launch_bscale(res, h->V, n, R, h->scal_dev, s);
     int jmax = 0;
     settled = true;
-    for (int j = 0; j < m; ++j) {
+    // iteration j: z_j = M v_j, w = Dhat z_j, CGS2 against v_0..v_j, |w|^2,
+    // the results to the host (one right-hand side: first v_j = w / |w| from
+    // the norm on the device, and the results of odd j in the second set)
+    auto iterate = [&](int j) {
       zd* vj = h->V + (size_t)j * R * n;
       zd* zj = h->Z + (size_t)j * R * n;
-      // (one right-hand side: v_j = w / |w| from the norm on the device)
-      // z_j = M v_j, w = Dhat z_j, CGS2 against v_0..v_j, |w|^2, to the host
+      const size_t o = (R == 1 && (j & 1)) ? HSET1 : 0, op = (R == 1 && !(j & 1)) ? HSET1 : 0;
       h->run_graph(((uint64_t)R << 8) | (uint64_t)j, [&] {
         hipStream_t sc = h->s;
-        if (R == 1 && j > 0) launch_bscale_rnorm(h->w, vj, n, hn2, sc);
+        if (R == 1 && j > 0) launch_bscale_rnorm(h->w, vj, n, hn2 + op, sc);
         h->precondition(vj, zj, R);
         if (baxpy_dot_applies(n)) {
           // the second projection's inner products and the norm ride on the
           // multi-axpys before them; the reductions also write their results
           // to the pinned host copy themselves (no copy after them)
           h->apply(0, zj, h->w, nullptr, R);
-          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, sc, hh);
-          launch_baxpy_dot(h->V, j + 1, h1, -1.0, h->w, n, R, j + 1, h->partial, h2, sc, hh + 64 * R);
-          launch_baxpy_dot(h->V, j + 1, h2, -1.0, h->w, n, R, 0, h->partial, hn2, sc, hh + 128 * R);
+          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1 + o, sc, hh + o);
+          launch_baxpy_dot(h->V, j + 1, h1 + o, -1.0, h->w, n, R, j + 1, h->partial, h2 + o, sc, hh + o + 64 * R);
+          launch_baxpy_dot(h->V, j + 1, h2 + o, -1.0, h->w, n, R, 0, h->partial, hn2 + o, sc, hh + o + 128 * R);
           check_launch();
         } else {
           h->apply(0, zj, h->w, nullptr, R);
-          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1, sc);
-          launch_bmultiaxpy(h->V, j + 1, h1, -1.0, h->w, n, R, sc);
-          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2, sc);
-          launch_bmultiaxpy(h->V, j + 1, h2, -1.0, h->w, n, R, sc);
-          launch_norms(h->w, n, R, n, h->partial, hn2, sc, nullptr, true);
+          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1 + o, sc);
+          launch_bmultiaxpy(h->V, j + 1, h1 + o, -1.0, h->w, n, R, sc);
+          launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2 + o, sc);
+          launch_bmultiaxpy(h->V, j + 1, h2 + o, -1.0, h->w, n, R, sc);
+          launch_norms(h->w, n, R, n, h->partial, hn2 + o, sc, nullptr, true);
           check_launch();
-          HIPCHK(hipMemcpyAsync(hh, h->hdev, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
+          HIPCHK(hipMemcpyAsync(hh + o, h->hdev + o, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
         }
       });
-      HIPCHK(hipStreamSynchronize(s));
+    };
+    bool queued = false;  // iteration j already on the stream (look-ahead)
+    for (int j = 0; j < m; ++j) {
+      if (!queued) iterate(j);
+      // look-ahead (one right-hand side): queue iteration j + 1 before
+      // reading j's results when j is unlikely to end the solve; it only
+      // needs what j leaves on the device
+      queued = R == 1 && h->p.lookahead && j + 1 < m && it[0] + 1 < h->p.max_iter &&
+               (h->p.lookahead == 2 || std::abs(g[j]) > 1000.0 * tol * bnorm[0]);
+      if (queued) {
+        if (!h->ev_iter) HIPCHK(hipEventCreateWithFlags(&h->ev_iter, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(h->ev_iter, s));
+        iterate(j + 1);
+        HIPCHK(hipEventSynchronize(h->ev_iter));
+      } else {
+        HIPCHK(hipStreamSynchronize(s));
+      }
+      const zd* hj = hh + ((R == 1 && (j & 1)) ? HSET1 : 0);
       jmax = j + 1;
       bool still = false;
       for (int r = 0; r < R; ++r) {
@@ -785,8 +806,8 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
         C* snr = &sn[(size_t)r * m];
         double* csr = &cs[(size_t)r * m];
         for (int q = 0; q <= j; ++q)
-          Hr[(size_t)q * m + j] = C(hh[r * 64 + q].x, hh[r * 64 + q].y) + C(hh[64 * R + r * 64 + q].x, hh[64 * R + r * 64 + q].y);
-        const double hn = std::sqrt(hh[128 * R + r].x);
+          Hr[(size_t)q * m + j] = C(hj[r * 64 + q].x, hj[r * 64 + q].y) + C(hj[64 * R + r * 64 + q].x, hj[64 * R + r * 64 + q].y);
+        const double hn = std::sqrt(hj[128 * R + r].x);
         if (!std::isfinite(hn)) throw HipFail("non-finite Arnoldi vector");
         for (int q = 0; q < j; ++q) {
           const C a = Hr[(size_t)q * m + j], bq = Hr[(size_t)(q + 1) * m + j];

@@ -383,10 +383,13 @@ void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStre
 }
 
 // y = x / sqrt(nrm2.x): the next Arnoldi vector from the squared norm left
-// on the device (the host's 1 / sqrt, correctly rounded both ways)
+// on the device (the host's 1 / sqrt, correctly rounded both ways); a zero
+// norm (an exhausted Krylov space, where the host stops and any iteration
+// queued ahead goes unused) gives y = 0 rather than NaN
 __global__ void k_bscale_rnorm(const zd* __restrict__ x, zd* __restrict__ y, size_t n, const zd* __restrict__ nrm2) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (1.0 / sqrt(nrm2[0].x)) * x[i];
+  const double q = nrm2[0].x;
+  if (i < n) y[i] = q > 0 ? (1.0 / sqrt(q)) * x[i] : zd{0, 0};
 }
 
 void launch_bscale_rnorm(const zd* x, zd* y, size_t n, const zd* nrm2, hipStream_t s) {

@@ -59,6 +59,9 @@ constexpr int MR_MIN = 4;
 // from this many right-hand sides the level-0 smoothing sweeps run on
 // right-hand-side-interleaved copies of x and b (launch_smooth_fine_il)
 constexpr int IL_MIN = 16;
+// offset (entries) of the second set of single-RHS reduction results in
+// hdev / hhost: past the first set's [3][64] and the solve's own slots after it
+constexpr size_t HSET1 = 192;
 
 // ---- multicolour orderings (Sec. 3.1 leaves the colouring open) -------------
 // fine even site (x, y): 4 * (((x+y)/2) mod 4) + (((x-y)/2) mod 4); 16 colours
@@ -148,8 +151,12 @@ struct bamg_hierarchy {
   // Krylov workspace for kcap right-hand sides (basis layout [j][r][n])
   int kdim = 0, kcap = 0;
   zd *V = nullptr, *Z = nullptr, *w = nullptr, *bh = nullptr, *xe = nullptr, *rr = nullptr;
-  zd *partial = nullptr, *hdev = nullptr;  // reduction partials; [3][kcap][64] results
+  // reduction partials; results [3][kcap][64], then for a single right-hand
+  // side a second set of [3][64] (FGMRES iterations of odd index, so that one
+  // iteration can run while the host reads the results of the one before)
+  zd *partial = nullptr, *hdev = nullptr;
   zd* hhost = nullptr;                     // pinned mirror of hdev
+  hipEvent_t ev_iter = nullptr;            // end of an FGMRES iteration (look-ahead)
   double *scal_dev = nullptr, *scal_host = nullptr;  // per right-hand side scale factors
   zd *ycoef_dev = nullptr, *ycoef_host = nullptr;    // per right-hand side update coefficients
   zd* tvsave = nullptr; // level-0 test vectors after the last setup pass
@@ -229,9 +236,9 @@ struct bamg_hierarchy {
       free_krylov();
       kcap = cap2;
       partial = dalloc<zd>((size_t)blas_nblocks_fine(n0) * 64 * kcap);  // the finer of the two block counts
-      hdev = dalloc<zd>((size_t)3 * 64 * kcap);
+      hdev = dalloc<zd>((size_t)3 * 64 * kcap + HSET1);
       // coherent: the Gram-Schmidt reductions write their results here directly
-      HIPCHK(hipHostMalloc((void**)&hhost, (size_t)3 * 64 * kcap * sizeof(zd), hipHostMallocCoherent));
+      HIPCHK(hipHostMalloc((void**)&hhost, ((size_t)3 * 64 * kcap + HSET1) * sizeof(zd), hipHostMallocCoherent));
       scal_dev = dalloc<double>(kcap);
       HIPCHK(hipHostMalloc((void**)&scal_host, (size_t)kcap * sizeof(double)));
       ycoef_dev = dalloc<zd>((size_t)64 * kcap);
@@ -267,6 +274,7 @@ struct bamg_hierarchy {
     if (eigH) (void)hipHostFree(eigH);
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ev_iter) (void)hipEventDestroy(ev_iter);
   }
 
   int L() const { return (int)lv.size(); }

@@ -53,3 +53,9 @@ def test_host_only_entry_points():
     f16c = b.bamg_footprint_bytes(b.bamg_default_params(N=256, precision=1, coarsest_fp32=1))
     assert f16c - f16 == 8 * n ** 2 + 8 * (n ** 2 // 2 + 32 * n)
     assert b.bamg_footprint_bytes(b.bamg_default_params(N=256, coarsest_fp32=1)) == 0
+    # look-ahead of the single-RHS FGMRES: on by default, 0 / 1 / 2 valid, other values rejected
+    assert p.lookahead == 1
+    for la in (0, 2):
+        assert b.bamg_footprint_bytes(b.bamg_default_params(N=256, lookahead=la)) == fb
+    assert b.bamg_footprint_bytes(b.bamg_default_params(N=256, lookahead=3)) == 0
+    assert b.bamg_footprint_bytes(b.bamg_default_params(N=256, lookahead=-1)) == 0

@@ -768,3 +768,70 @@ def test_graph_replay_equals_eager(bamg, prec):
             float(junk)
             bamg.bamg_solve_batch(hg, dev(B[:R]), Xg, R, 1e-10)
             assert np.array_equal(host(Xe), host(Xg)), (rep, R)
+
+
+SOLVE_INFO_KEYS = ("iters", "restarts", "relres_reduced", "relres_full", "rho_est")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lookahead_gives_the_same_bits(bamg, prec):
+    """Look-ahead of the single-RHS FGMRES: iteration j + 1 is queued before
+    the host reads iteration j's norms (its results in the second set of host
+    slots).  Off (0), while the estimated residual exceeds 1000 tol (1, the
+    default) and at every iteration (2, which also leaves a queued iteration
+    unused at the end of every pass) give bitwise the same x, status and
+    counts, eager and as graphs: at 1e-10, at a loose tolerance, with a
+    restart every 3 iterations, and stopped by the iteration cap."""
+    w = inputs.workload("c1_32_b3")
+    U = inputs.load_gauge(w)
+    N = w["N"]
+    B = inputs.gaussian((2, 2 * N * N), 71)
+    for graphs in (0, 1):
+        for restart, max_iter, tols in ((32, 1000, (1e-10, 1e-3)), (3, 1000, (1e-10,)), (32, 4, (1e-14,))):
+            log(f"lookahead prec={prec} graphs={graphs} restart={restart} max_iter={max_iter}")
+            kw = dict(n_levels=w["n_levels"], seed=w["tv_seed"], precision=prec, graphs=graphs,
+                      restart=restart, max_iter=max_iter)
+            hs = [make_h(bamg, U, w["m"], lookahead=la, **kw) for la in (0, 1, 2)]
+            for tol in tols:
+                for r in range(2):
+                    b = dev(B[r])
+                    res = []
+                    for h in hs:
+                        x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
+                        st, info = bamg.bamg_solve(h, b, x, tol)
+                        res.append((st, tuple(info[k] for k in SOLVE_INFO_KEYS), host(x)))
+                    st0, info0, x0 = res[0]
+                    assert st0 == (1 if max_iter == 4 else 0), (st0, info0)
+                    assert info0[0] == min(max_iter, info0[0]) and info0[0] >= 1
+                    if restart == 3:
+                        assert info0[1] >= 1
+                    for la, (st, info, x) in zip((1, 2), res[1:]):
+                        assert st == st0 and info == info0, (la, tol, r, info, info0)
+                        assert np.array_equal(x, x0), (la, tol, r)
+            for h in hs:
+                bamg.bamg_free(h)
+
+
+def test_lookahead_headline_shape(bamg):
+    """The single-RHS solve in the shape of the headline (256^2, 3 levels,
+    mixed FP16, V(2,2), graphs), with and without look-ahead, twice each: the
+    same bits."""
+    N = 256
+    U = inputs.gauge_metropolis(N, 3.0, 20, 11)
+    B = inputs.gaussian((1, 2 * N * N), 72)
+    kw = dict(n_levels=3, setup_sweeps=4, setup_adapt=0, precision=1, pre=2, post=2, graphs=1)
+    hs = [make_h(bamg, U, -0.05, lookahead=la, **kw) for la in (0, 1)]
+    b = dev(B[0])
+    res = []
+    for h in hs:
+        for rep in range(2):
+            x = torch.zeros(2 * N * N, dtype=torch.complex128, device="cuda:0")
+            st, info = bamg.bamg_solve(h, b, x, 1e-10)
+            res.append((st, tuple(info[k] for k in SOLVE_INFO_KEYS), host(x)))
+    st0, info0, x0 = res[0]
+    assert st0 == 0 and info0[0] >= 3, info0
+    for i, (st, info, x) in enumerate(res[1:]):
+        assert st == st0 and info == info0, (i, info, info0)
+        assert np.array_equal(x, x0), i
+    for h in hs:
+        bamg.bamg_free(h)
