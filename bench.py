@@ -627,8 +627,8 @@ PMC_TRAFFIC = {
                                    "sha256": "607b1a3a175d23870f457411a1aba9f6b8c81191c9bbe5eb94820270b6cc3a23",
                                    "fetch_kib": 10143.5, "write_kib": 640.0, **COPY_SCALE},
     ("coarse_pair", "mixed_fp16"): {"src": "coarse.hip",
-                                    "sha256": "59bf7771e29161171bd1d170ed84b6a1e52241bc3f59f553e96cf435e8734d60",
-                                    "fetch_kib": 2675.0, "write_kib": 256.0, **COPY_SCALE},
+                                    "sha256": "96d0a0fe00f0a847a6e54296a083d2a1be0b60e0980cf61e2274cbd1c38e7990",
+                                    "fetch_kib": 2679.0, "write_kib": 256.0, **COPY_SCALE},
     # the packed products and their reductions, per call (the sum of the two kernels' counters):
     # the FP64 blocks (headline) and their FP32 copy (+c32)
     ("dense_g5", "mixed_fp16"): {"src": "dense.hip",

@@ -259,6 +259,12 @@ void launch_restrict_coarse(int ex, int ey, const cx<T>* P, const cx<T>* r, cx<T
                             cx<T>* xz = nullptr);
 template <typename T>
 void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T>* x, int nrhs, hipStream_t s);
+// rc = P^H (b - D x) from level l (c, ex x ey) to l+1 in one launch, xz as
+// for launch_restrict_coarse: the same bits as launch_coarse_apply followed by
+// launch_restrict_coarse; false (nothing launched) without b or for odd extents
+template <typename T, typename S>
+bool launch_residual_restrict_coarse(const CoarseT<T, S>& c, const cx<T>* P, const cx<T>* x, const cx<T>* b,
+                                     cx<T>* rc, int nrhs, hipStream_t s, cx<T>* xz = nullptr);
 void launch_galerkin_coarse(const Coarse& c, const zd* P, zd* Dc, hipStream_t s);
 void launch_fit_coarse(const Coarse& c, const zd* V, int k, zd* P, hipStream_t s);
 // expand the block stencil into a dense n x n matrix (coarsest level)

@@ -54,6 +54,29 @@ __device__ __forceinline__ cx<T> xor_add(cx<T> v) {
 // ---------------------------------------------------------------------------
 // y = D x  (or y = b - D x)
 // ---------------------------------------------------------------------------
+// A wave's share of (D x)_site: lane 4 i + q loads row i, columns 4q..4q+3 of
+// each of the 7 blocks (and the neighbour sites), then row_dot sums them
+// against x in a fixed order and over the quad.  k_coarse_apply and the fused
+// residual-restriction kernel call both, so they give the same bits.
+template <typename T, typename S>
+__device__ __forceinline__ void coarse_apply_load(const CoarseT<T, S>& c, int site, int i, int q, cx<T> (&Dv)[NOFF][4],
+                                                  int (&nb)[NOFF]) {
+  for (int o = 0; o < NOFF; ++o) {
+    nb[o] = neighbour_site(site, o, c.ex, c.ey);
+    const S* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 4 * q;
+    for (int jj = 0; jj < 4; ++jj) Dv[o][jj] = widen<T>(Dr[jj]);
+  }
+}
+template <typename T>
+__device__ __forceinline__ cx<T> coarse_apply_row(const cx<T> (&Dv)[NOFF][4], const int (&nb)[NOFF], int q,
+                                                  const cx<T>* __restrict__ xv) {
+  cx<T> acc = {0, 0};
+  for (int o = 0; o < NOFF; ++o)
+    for (int jj = 0; jj < 4; ++jj) acc = acc + Dv[o][jj] * xv[nb[o] * 16 + 4 * q + jj];
+  acc = xor_add<1>(acc);
+  return xor_add<2>(acc);
+}
+
 template <typename T, typename S>
 __global__ __launch_bounds__(256) void k_coarse_apply(CoarseT<T, S> c, const cx<T>* __restrict__ x,
                                                       cx<T>* __restrict__ y, const cx<T>* __restrict__ b, int nrhs) {
@@ -65,19 +88,10 @@ __global__ __launch_bounds__(256) void k_coarse_apply(CoarseT<T, S> c, const cx<
   const int i = lane >> 2, q = lane & 3;
   int nb[NOFF];
   C Dv[NOFF][4];
-  for (int o = 0; o < NOFF; ++o) {
-    nb[o] = neighbour_site(site, o, c.ex, c.ey);
-    const S* Dr = c.D + (((size_t)site * NOFF + o) * 16 + i) * 16 + 4 * q;
-    for (int jj = 0; jj < 4; ++jj) Dv[o][jj] = widen<T>(Dr[jj]);
-  }
+  coarse_apply_load(c, site, i, q, Dv, nb);
   const size_t n = (size_t)ns * 16;
   for (int r = 0; r < nrhs; ++r) {
-    const C* xv = x + r * n;
-    C acc = {0, 0};
-    for (int o = 0; o < NOFF; ++o)
-      for (int jj = 0; jj < 4; ++jj) acc = acc + Dv[o][jj] * xv[nb[o] * 16 + 4 * q + jj];
-    acc = xor_add<1>(acc);
-    acc = xor_add<2>(acc);
+    C acc = coarse_apply_row(Dv, nb, q, x + r * n);
     if (q == 0) {
       if (b) acc = b[r * n + site * 16 + i] - acc;
       y[r * n + site * 16 + i] = acc;
@@ -849,6 +863,19 @@ void launch_kaczmarz_prep(const CoarseT<T, S>& c, cx<T>* Kinv, hipStream_t s) {
 // 2x2 aggregation: coarse site A = AY*(ex/2) + AX holds the sites
 // (2AX + (t&1), 2AY + (t>>1)), local t; P rows 8t + (d mod 8) for spin d/8.
 // ---------------------------------------------------------------------------
+// (P^H r)[A][d] for coarse dof d = 8 s + k of aggregate A, from rrow(t, e) =
+// r[e] of the aggregate's site t; the sum in a fixed order (the restriction
+// kernel and the fused residual-restriction kernel form it the same way)
+template <typename T, typename F>
+__device__ __forceinline__ cx<T> coarse_restrict_entry(const cx<T>* __restrict__ P, int A, int d, F rrow) {
+  const int s = d >> 3, k = d & 7;
+  const cx<T>* Pa = P + ((size_t)A * 2 + s) * 32 * 8;
+  cx<T> acc = {0, 0};
+  for (int t = 0; t < 4; ++t)
+    for (int j = 0; j < 8; ++j) acc = acc + cjmul(Pa[(8 * t + j) * 8 + k], rrow(t, 8 * s + j));
+  return acc;
+}
+
 template <typename T>
 __global__ void k_restrict_coarse(int ex, int ey, const cx<T>* __restrict__ P, const cx<T>* __restrict__ r,
                                   cx<T>* __restrict__ rc, cx<T>* __restrict__ xz) {
@@ -856,18 +883,53 @@ __global__ void k_restrict_coarse(int ex, int ey, const cx<T>* __restrict__ P, c
   const int cex = ex / 2, cey = ey / 2;
   const int tt = blockIdx.x * blockDim.x + threadIdx.x;
   if (tt >= cex * cey * 16) return;
-  const int A = tt >> 4, d = tt & 15, s = d >> 3, k = d & 7;
+  const int A = tt >> 4, d = tt & 15;
   const int AX = A % cex, AY = A / cex;
   const size_t n = (size_t)ex * ey * 16, nc = (size_t)cex * cey * 16;
   const C* rv = r + blockIdx.y * n;
-  const C* Pa = P + ((size_t)A * 2 + s) * 32 * 8;
-  C acc = {0, 0};
-  for (int t = 0; t < 4; ++t) {
-    const int site = (2 * AY + (t >> 1)) * ex + 2 * AX + (t & 1);
-    for (int j = 0; j < 8; ++j) acc = acc + cjmul(Pa[(8 * t + j) * 8 + k], rv[site * 16 + 8 * s + j]);
-  }
-  rc[blockIdx.y * nc + tt] = acc;
+  rc[blockIdx.y * nc + tt] = coarse_restrict_entry(P, A, d, [&](int t, int e) {
+    return rv[((2 * AY + (t >> 1)) * ex + 2 * AX + (t & 1)) * 16 + e];
+  });
   if (xz) xz[blockIdx.y * nc + tt] = C{0, 0};  // the coarser level's zero initial guess
+}
+
+// r = b - D x on a coarse level and r_c = P^H r on the next, in one launch: a
+// work-group per aggregate A of the next level, wave t forming the residual
+// rows of A's site t as k_coarse_apply does (into LDS), then thread d < 16
+// the restricted entry d as k_restrict_coarse does: the same bits as the two
+// launches, without r in memory.  xz (the next level, may be null) = 0.
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_residual_restrict_coarse(CoarseT<T, S> c, const cx<T>* __restrict__ P,
+                                                                  const cx<T>* __restrict__ x,
+                                                                  const cx<T>* __restrict__ b,
+                                                                  cx<T>* __restrict__ rc, cx<T>* __restrict__ xz) {
+  using C = cx<T>;
+  __shared__ C rs[4][16];
+  const int ex = c.ex, cex = ex / 2, cey = c.ey / 2;
+  const int A = blockIdx.x, AX = A % cex, AY = A / cex;
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane >> 2, q = lane & 3;
+  const int site = (2 * AY + (t >> 1)) * ex + 2 * AX + (t & 1);
+  const size_t n = (size_t)ex * c.ey * 16, nc = (size_t)cex * cey * 16;
+  int nb[NOFF];
+  C Dv[NOFF][4];
+  coarse_apply_load(c, site, i, q, Dv, nb);
+  const C acc = coarse_apply_row(Dv, nb, q, x + blockIdx.y * n);
+  if (q == 0) rs[t][i] = b[blockIdx.y * n + site * 16 + i] - acc;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int d = threadIdx.x;
+    rc[blockIdx.y * nc + (size_t)A * 16 + d] = coarse_restrict_entry(P, A, d, [&](int tt, int e) { return rs[tt][e]; });
+    if (xz) xz[blockIdx.y * nc + (size_t)A * 16 + d] = C{0, 0};
+  }
+}
+
+template <typename T, typename S>
+bool launch_residual_restrict_coarse(const CoarseT<T, S>& c, const cx<T>* P, const cx<T>* x, const cx<T>* b,
+                                     cx<T>* rc, int nrhs, hipStream_t s, cx<T>* xz) {
+  if (!b || nrhs < 1 || c.ex % 2 || c.ey % 2) return false;
+  hipLaunchKernelGGL((k_residual_restrict_coarse<T, S>), dim3((c.ex / 2) * (c.ey / 2), nrhs), dim3(256), 0, s, c, P,
+                     x, b, rc, xz);
+  return true;
 }
 
 template <typename T>
@@ -900,7 +962,9 @@ void launch_prolong_coarse(int ex, int ey, const cx<T>* P, const cx<T>* xc, cx<T
                                              int, hipStream_t);                                         \
   template void launch_kaczmarz_prep<T, S>(const CoarseT<T, S>&, cx<T>*, hipStream_t);                  \
   template void launch_kaczmarz_coarse_pair<T, S>(const CoarseT<T, S>&, int, int, const cx<T>*, cx<T>*, \
-                                                  const cx<T>*, int, hipStream_t, const cx<T>*, const cx<T>*);
+                                                  const cx<T>*, int, hipStream_t, const cx<T>*, const cx<T>*); \
+  template bool launch_residual_restrict_coarse<T, S>(const CoarseT<T, S>&, const cx<T>*, const cx<T>*,  \
+                                                      const cx<T>*, cx<T>*, int, hipStream_t, cx<T>*);
 BAMG_COARSE_INST(double, zd)
 BAMG_COARSE_INST(float, zf)
 BAMG_COARSE_INST(float, hcx)

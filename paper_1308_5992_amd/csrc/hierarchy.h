@@ -477,8 +477,13 @@ struct bamg_hierarchy {
     Level& C = lv[l + 1];
     smooth(l, x, b, nrhs, p.pre, fz0);
     zd* xz = coarsest(l + 1) ? nullptr : C.x;  // the coarse initial guess x = 0
-    if (!(l == 0 && launch_residual_restrict_fine(f, (const zd*)Lv.P, (const zd*)x, b, C.b, nrhs, s, xz))) {
-      apply(l, x, Lv.r, b, nrhs);  // r = b - A x
+    // r = b - A x and its restriction, in one launch on level 0 where the
+    // lattice takes its tiles and on coarse levels for one right-hand side
+    const bool fused = l == 0 ? launch_residual_restrict_fine(f, (const zd*)Lv.P, (const zd*)x, b, C.b, nrhs, s, xz)
+                              : nrhs == 1 && launch_residual_restrict_coarse(Lv.coarse(), (const zd*)Lv.P,
+                                                                             (const zd*)x, b, C.b, nrhs, s, xz);
+    if (!fused) {
+      apply(l, x, Lv.r, b, nrhs);
       restrict_(l, Lv.r, C.b, nrhs, xz);
     }
     if (kvisited(l + 1)) {
@@ -617,10 +622,16 @@ struct bamg_hierarchy {
     Level& C = lv[l + 1];
     smooth32<S>(l, x, b, nrhs, p.pre, fin);
     // the restriction also zeroes the coarse initial guess, which the coarsest
-    // solve does not need (it writes all of x); on level 0 the residual and
-    // its restriction run in one launch where the lattice takes its tiles
+    // solve does not need (it writes all of x); the residual and its
+    // restriction run in one launch on level 0 where the lattice takes its
+    // tiles, and on coarse levels for one right-hand side (the vector form)
     zf* xz = coarsest(l + 1) ? nullptr : C.x32;
-    if (!(l == 0 && launch_residual_restrict_fine(f32, (const zf*)Lv.P32, (const zf*)x, b, C.b32, nrhs, s, xz))) {
+    const bool fused =
+        l == 0 ? launch_residual_restrict_fine(f32, (const zf*)Lv.P32, (const zf*)x, b, C.b32, nrhs, s, xz)
+               : nrhs == 1 && !force_mr &&
+                     launch_residual_restrict_coarse(coarse32<S>(l), (const zf*)Lv.P32, (const zf*)x, b, C.b32, nrhs,
+                                                     s, xz);
+    if (!fused) {
       apply32<S>(l, x, Lv.r32, b, nrhs);
       if (l == 0) launch_restrict_fine(f32, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);
       else launch_restrict_coarse(Lv.ex, Lv.ey, Lv.P32, Lv.r32, C.b32, nrhs, s, xz);

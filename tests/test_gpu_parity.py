@@ -690,8 +690,10 @@ def test_work_carried_by_the_fine_sweeps_gives_the_same_bits(bamg):
     the mixed preconditioner's input conversion and zero start, the
     prolongation into the first post-smoothing sweep and the FP64 output of
     the last (FP32 at 320^2; the FP64 cycle at 256^2 carries the
-    prolongation); two right-hand sides take the streaming sweep and the
-    separate conversion, prolongation and conversion launches.  Every other
+    prolongation), and every coarse level that is not the coarsest forms its
+    residual and the restriction in one launch; two right-hand sides take
+    the streaming sweep, the separate conversion, prolongation and conversion
+    launches and the separate coarse residual and restriction.  Every other
     kernel of the cycle is the same for both (fused colour pairs on level 1,
     colour passes below, the packed coarsest product), and right-hand sides
     are independent, so the preconditioner (op 9) and the FP64 cycle (op 5)
