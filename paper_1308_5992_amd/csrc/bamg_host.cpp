@@ -748,24 +748,31 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
     int jmax = 0;
     settled = true;
     // iteration j: z_j = M v_j, w = Dhat z_j, CGS2 against v_0..v_j, |w|^2,
-    // the results to the host (one right-hand side: first v_j = w / |w| from
-    // the norm on the device, and the results of odd j in the second set)
+    // the results to the host (one right-hand side: the results of odd j in
+    // the second set, and v_{j+1} = w / |w| formed on the device from the
+    // norm at the end, used or not)
     auto iterate = [&](int j) {
       zd* vj = h->V + (size_t)j * R * n;
       zd* zj = h->Z + (size_t)j * R * n;
-      const size_t o = (R == 1 && (j & 1)) ? HSET1 : 0, op = (R == 1 && !(j & 1)) ? HSET1 : 0;
+      zd* vnext = h->V + (size_t)(j + 1) * R * n;  // (the basis holds m + 1 vectors)
+      const size_t o = (R == 1 && (j & 1)) ? HSET1 : 0;
       h->run_graph(((uint64_t)R << 8) | (uint64_t)j, [&] {
         hipStream_t sc = h->s;
-        if (R == 1 && j > 0) launch_bscale_rnorm(h->w, vj, n, hn2 + op, sc);
         h->precondition(vj, zj, R);
         if (baxpy_dot_applies(n)) {
           // the second projection's inner products and the norm ride on the
           // multi-axpys before them; the reductions also write their results
-          // to the pinned host copy themselves (no copy after them)
+          // to the pinned host copy themselves (no copy after them); one
+          // right-hand side: the norm's reduction also scales w into v_{j+1}
           h->apply(0, zj, h->w, nullptr, R);
           launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h1 + o, sc, hh + o);
           launch_baxpy_dot(h->V, j + 1, h1 + o, -1.0, h->w, n, R, j + 1, h->partial, h2 + o, sc, hh + o + 64 * R);
-          launch_baxpy_dot(h->V, j + 1, h2 + o, -1.0, h->w, n, R, 0, h->partial, hn2 + o, sc, hh + o + 128 * R);
+          if (R == 1) {
+            launch_baxpy_dot(h->V, j + 1, h2 + o, -1.0, h->w, n, R, 0, h->partial, nullptr, sc);
+            launch_norm_scale(h->partial, h->w, vnext, n, hn2 + o, hh + o + 128, sc);
+          } else {
+            launch_baxpy_dot(h->V, j + 1, h2 + o, -1.0, h->w, n, R, 0, h->partial, hn2 + o, sc, hh + o + 128 * R);
+          }
           check_launch();
         } else {
           h->apply(0, zj, h->w, nullptr, R);
@@ -774,6 +781,7 @@ static int fgmres_batch(bamg_hierarchy* h, int R, double tol, bamg_solve_info* i
           launch_bmultidot(h->V, j + 1, h->w, n, R, h->partial, h2 + o, sc);
           launch_bmultiaxpy(h->V, j + 1, h2 + o, -1.0, h->w, n, R, sc);
           launch_norms(h->w, n, R, n, h->partial, hn2 + o, sc, nullptr, true);
+          if (R == 1) launch_bscale_rnorm(h->w, vnext, n, hn2 + o, sc);
           check_launch();
           HIPCHK(hipMemcpyAsync(hh + o, h->hdev + o, (size_t)(128 * R + R) * sizeof(zd), hipMemcpyDeviceToHost, sc));
         }

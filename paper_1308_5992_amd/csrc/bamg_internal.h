@@ -355,7 +355,8 @@ void launch_bmultidot(const zd* X, int nv, const zd* W, size_t n, int R, zd* par
 void launch_bmultiaxpy(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, hipStream_t s);
 // W_r += sign sum_{v < nv} X_{v,r} h[r][v], then out[r][v] = X_{v,r}^H W_r for
 // v < nd (nd > 0) or out[r] = |W_r|^2 (nd = 0), in one pass over W_r per
-// launch pair; false (nothing launched) where a chunk is too long
+// launch pair (nd = 0 and out null: only the block partials of |W_r|^2, for
+// launch_norm_scale); false (nothing launched) where a chunk is too long
 bool launch_baxpy_dot(const zd* X, int nv, const zd* h, double sign, zd* W, size_t n, int R, int nd, zd* partial,
                       zd* out, hipStream_t s, zd* host_out = nullptr);
 bool baxpy_dot_applies(size_t n);
@@ -363,6 +364,10 @@ bool baxpy_dot_applies(size_t n);
 void launch_bscale(const zd* x, zd* y, size_t n, int R, const double* c, hipStream_t s);
 // one vector: y = x / sqrt(nrm2[0].x)
 void launch_bscale_rnorm(const zd* x, zd* y, size_t n, const zd* nrm2, hipStream_t s);
+// one vector: out[0] (and host_out) = |w|^2 from the block partials that
+// launch_baxpy_dot with nd = 0 and out = nullptr leaves, and y = w / |w|, in
+// one launch (the bits of the reduction and launch_bscale_rnorm)
+void launch_norm_scale(const zd* partial, const zd* w, zd* y, size_t n, zd* out, zd* host_out, hipStream_t s);
 // x_r += sum_q Z_{q,r} y[r*64 + q]
 void launch_blincomb(const zd* Z, int nq, const zd* y, zd* x, size_t n, int R, hipStream_t s);
 // slot-mapped forms (continuous batching): entry a of a launch uses slot slot[a]

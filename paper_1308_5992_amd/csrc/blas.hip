@@ -368,7 +368,7 @@ bool launch_baxpy_dot(const zd* X, int nv, const zd* h, double sign, zd* W, size
   if (!baxpy_dot_applies(n) || nd < 0 || nd > 64) return false;
   hipLaunchKernelGGL(k_baxpy_dot, dim3(nb, R), dim3(BT), 0, s, X, nv, R, h, sign, W, n, nd, partial);
   if (nd > 0) hipLaunchKernelGGL(k_breduce, dim3(nd, R), dim3(BT), 0, s, partial, nb, out, host_out);
-  else hipLaunchKernelGGL(k_reduce_partial, dim3(R), dim3(BT), 0, s, partial, nb, R, out, host_out);
+  else if (out) hipLaunchKernelGGL(k_reduce_partial, dim3(R), dim3(BT), 0, s, partial, nb, R, out, host_out);
   return true;
 }
 
@@ -390,6 +390,37 @@ __global__ void k_bscale_rnorm(const zd* __restrict__ x, zd* __restrict__ y, siz
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double q = nrm2[0].x;
   if (i < n) y[i] = q > 0 ? (1.0 / sqrt(q)) * x[i] : zd{0, 0};
+}
+
+// One right-hand side: |w|^2 summed from the nb block partials in every
+// work-group with k_reduce_partial's per-thread order and tree (block 0
+// writes it to out and host_out), then y = w / |w| over the work-group's
+// chunk with k_bscale_rnorm's arithmetic: the norm and the next Arnoldi
+// vector in one launch, the same bits as the two
+constexpr int NS_E = 4;
+__global__ __launch_bounds__(BT) void k_norm_scale(const zd* __restrict__ partial, int nb, const zd* __restrict__ w,
+                                                   zd* __restrict__ y, size_t n, zd* __restrict__ out,
+                                                   zd* __restrict__ host_out) {
+  __shared__ zd sh[BT];
+  zd acc = {0, 0};
+  for (int b = threadIdx.x; b < nb; b += BT) acc = acc + partial[b];
+  const zd nrm = block_sum(acc, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out[0] = nrm;
+    if (host_out) host_out[0] = nrm;
+  }
+  const double q = nrm.x;
+#pragma unroll
+  for (int k = 0; k < NS_E; ++k) {
+    const size_t i = ((size_t)blockIdx.x * NS_E + k) * BT + threadIdx.x;
+    if (i < n) y[i] = q > 0 ? (1.0 / sqrt(q)) * w[i] : zd{0, 0};
+  }
+}
+
+void launch_norm_scale(const zd* partial, const zd* w, zd* y, size_t n, zd* out, zd* host_out, hipStream_t s) {
+  const size_t per = (size_t)NS_E * BT;
+  hipLaunchKernelGGL(k_norm_scale, dim3((unsigned)((n + per - 1) / per)), dim3(BT), 0, s, partial,
+                     blas_nblocks_fine(n), w, y, n, out, host_out);
 }
 
 void launch_bscale_rnorm(const zd* x, zd* y, size_t n, const zd* nrm2, hipStream_t s) {
