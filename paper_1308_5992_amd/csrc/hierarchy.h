@@ -57,8 +57,10 @@ inline int floor_mod(int a, int n) { return ((a % n) + n) % n; }
 // right-hand sides from which the smoothers use their multi-RHS kernels
 constexpr int MR_MIN = 4;
 // from this many right-hand sides the level-0 smoothing sweeps run on
-// right-hand-side-interleaved copies of x and b (launch_smooth_fine_il)
+// right-hand-side-interleaved copies of x and b (launch_smooth_fine_il),
+// below IL_BLOCKED only where the streaming blocked sweep does not apply
 constexpr int IL_MIN = 16;
+constexpr int IL_BLOCKED = 32;
 // offset (entries) of the second set of single-RHS reduction results in
 // hdev / hhost: past the first set's [3][64] and the solve's own slots after it
 constexpr size_t HSET1 = 192;
@@ -418,19 +420,31 @@ struct bamg_hierarchy {
     check_launch();
     return true;
   }
+  // the level-0 sweeps at nrhs run on the interleaved copies: from IL_MIN
+  // right-hand sides, but below IL_BLOCKED not where the sweep streamed
+  // through LDS (form 2) applies (256^2 x 16 FP32 batches: 9.84 against
+  // 10.41 ms; from 32 the interleaved passes win); both give the same bits
+  template <typename T>
+  bool use_il(const FineT<T>& ff, const cx<T>* xs, const cx<T>* xi, int nrhs) const {
+    if (nrhs < IL_MIN || !xi || nrhs > cap) return false;
+    if (nrhs >= IL_BLOCKED || !xs || !fine_sweep_applies(ff, nrhs)) return true;
+    FineSweepPlan pl;
+    int sched[3];
+    return fine_sweep_plan_query(ff.N, nrhs, sizeof(T) == 4, 0, pl, sched) != 2;
+  }
   // the level-0 sweeps of smooth / smooth32 at nrhs take the LDS-resident
   // blocked form, which carries FineFuse work
   template <typename T>
   bool fine_fuse_ok(const FineT<T>& ff, const cx<T>* xs, const cx<T>* xi, int nrhs) const {
-    if (nrhs >= IL_MIN && xi && nrhs <= cap) return false;
+    if (use_il(ff, xs, xi, nrhs)) return false;
     return xs && nrhs <= cap && fine_sweep_applies(ff, nrhs) && fine_sweep_fusable(ff, nrhs);
   }
-  // count sweeps on level l; on level 0 from IL_MIN right-hand sides through
-  // the interleaved copies, below that blocked in LDS where a tile plan
-  // applies (the same bits as count calls of sweep)
+  // count sweeps on level l; on level 0 through the interleaved copies where
+  // use_il, otherwise blocked in LDS where a tile plan applies (the same bits
+  // as count calls of sweep)
   // (fz: work the level-0 sweeps carry, only where fine_fuse_ok and count >= 1)
   void smooth(int l, zd* x, const zd* b, int nrhs, int count, const FineFuse<double>& fz = FineFuse<double>{}) {
-    if (!fz.any() && l == 0 && nrhs >= IL_MIN && xil && nrhs <= cap) {
+    if (!fz.any() && l == 0 && use_il(f, xsw, xil, nrhs)) {
       launch_smooth_fine_il(f, lv[0].ncol, lv[0].per_colour, x, b, xil, bil, nrhs, count, s);
       check_launch();
       return;
@@ -581,7 +595,7 @@ struct bamg_hierarchy {
   }
   template <typename S>
   void smooth32(int l, zf* x, const zf* b, int nrhs, int count, const FineFuse<float>& fz = FineFuse<float>{}) {
-    if (!fz.any() && l == 0 && nrhs >= IL_MIN && xil32 && nrhs <= cap) {
+    if (!fz.any() && l == 0 && use_il(f32, xsw32, xil32, nrhs)) {
       launch_smooth_fine_il(f32, lv[0].ncol, lv[0].per_colour, x, b, xil32, bil32, nrhs, count, s);
       return;
     }

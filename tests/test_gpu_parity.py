@@ -160,9 +160,10 @@ def test_eo_reduce_reconstruct(bamg, N, nrhs):
 @pytest.mark.parametrize("N,nrhs", [(16, 1), (40, 2), (64, 1), (40, 5), (40, 16), (64, 17), (64, 40), (40, 70),
                                     (80, 3), (96, 2), (128, 1), (512, 1), (256, 5), (1024, 1), (1040, 2)])
 def test_fine_kaczmarz_sweep(bamg, N, nrhs):
-    """From 16 right-hand sides the sweeps run on right-hand-side-interleaved
-    copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64).  Below
-    that, from N = 64 on, one launch per sweep blocked in LDS (80: 8-wide
+    """From 32 right-hand sides the sweeps run on right-hand-side-interleaved
+    copies (16, 32 or 64 lanes per site; 70 takes two chunks of 64), from 16
+    where no sweep blocked in LDS applies (40 x 16).  Otherwise, from N = 64
+    on, one launch per sweep blocked in LDS (64 x 17: the streaming form; 80: 8-wide
     tiles in v, 96: tiles of 32 in u; 512 x 1: the streaming form; 256 x 5
     and 1024: the pipelined march along v); 16, 40 and 1040 x 2 take the
     colour passes (1040: 33800 sites per colour, a count of work-groups that
@@ -184,14 +185,15 @@ def test_fine_kaczmarz_sweep(bamg, N, nrhs):
 @pytest.mark.parametrize("N", [40, 64, 96, 256, 512, 1024])
 @pytest.mark.parametrize("prec", [0, 3])
 def test_fine_sweep_batch_gives_the_same_bits(bamg, prec, N):
-    """20 right-hand sides take the interleaved sweep; one or three of them
-    alone take the colour passes (N = 40) or a sweep blocked in LDS (from
+    """32 right-hand sides take the interleaved sweep (below 32 it gives way to
+    a sweep blocked in LDS where one applies); one or three of them alone take
+    the colour passes (N = 40) or a sweep blocked in LDS (from
     N = 64; the streaming form for 256^2 x 3, 512^2 x 1 and FP32 512^2 x 3 and
     1024^2 x 1, the pipelined march for FP64 512^2 x 3 and 1024^2, FP32
     1024^2 x 3): the same bits (each lane adds the slot terms in
     the butterfly's order; the blocked sweeps project every site a tile depends
     on with the values the colour passes give it)."""
-    R = 20
+    R = 32
     log(f"sweep bits N={N} prec={prec}")
     U = inputs.gauge_random(N, 27)
     h = make_h(bamg, U, 0.02, n_levels=1, precision=prec)
@@ -202,7 +204,7 @@ def test_fine_sweep_batch_gives_the_same_bits(bamg, prec, N):
     X1 = X.clone()
     for _ in range(2):
         bamg.bamg_level_op(h, 0, op, B, X, R)
-    for r0, r1 in ((0, 1), (7, 10), (19, 20)):
+    for r0, r1 in ((0, 1), (7, 10), (31, 32)):
         x1 = X1[r0:r1].contiguous()
         for _ in range(2):
             bamg.bamg_level_op(h, 0, op, B[r0:r1].contiguous(), x1, r1 - r0)
