@@ -627,7 +627,7 @@ PMC_TRAFFIC = {
                                    "sha256": "607b1a3a175d23870f457411a1aba9f6b8c81191c9bbe5eb94820270b6cc3a23",
                                    "fetch_kib": 10143.5, "write_kib": 640.0, **COPY_SCALE},
     ("coarse_pair", "mixed_fp16"): {"src": "coarse.hip",
-                                    "sha256": "96d0a0fe00f0a847a6e54296a083d2a1be0b60e0980cf61e2274cbd1c38e7990",
+                                    "sha256": "2b1b26e11d8d45d10fb43512862560425d957eaf5981e90d62072440ad9955a4",
                                     "fetch_kib": 2679.0, "write_kib": 256.0, **COPY_SCALE},
     # the packed products and their reductions, per call (the sum of the two kernels' counters):
     # the FP64 blocks (headline) and their FP32 copy (+c32)

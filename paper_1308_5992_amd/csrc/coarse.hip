@@ -55,9 +55,9 @@ __device__ __forceinline__ cx<T> xor_add(cx<T> v) {
 // y = D x  (or y = b - D x)
 // ---------------------------------------------------------------------------
 // A wave's share of (D x)_site: lane 4 i + q loads row i, columns 4q..4q+3 of
-// each of the 7 blocks (and the neighbour sites), then row_dot sums them
-// against x in a fixed order and over the quad.  k_coarse_apply and the fused
-// residual-restriction kernel call both, so they give the same bits.
+// each of the 7 blocks (and the neighbour sites), then coarse_apply_row sums
+// them against x in a fixed order and over the quad.  k_coarse_apply and the
+// fused residual-restriction kernel call both, so they give the same bits.
 template <typename T, typename S>
 __device__ __forceinline__ void coarse_apply_load(const CoarseT<T, S>& c, int site, int i, int q, cx<T> (&Dv)[NOFF][4],
                                                   int (&nb)[NOFF]) {
